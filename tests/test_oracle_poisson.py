@@ -1,0 +1,138 @@
+"""Oracle pins: operator, multigrid, mixed precision, right side and update.
+
+Pins: dense direct solve of the bordered system on 16^2 and 8^3 at density
+ratio 1000; diagonalisation (FFT) for constant coefficients; a discrete
+manufactured solution; second-order convergence for a continuous one;
+symmetry of A; divergence-free corrected velocity (the projection property).
+"""
+import numpy as np
+import pytest
+
+from oracle import poisson
+from paper_1807_10504_amd import workloads as W
+
+
+def _drop_beta(shape, ratio=1000.0):
+    dim = len(shape)
+    n = shape[0]
+    g = np.indices(shape)
+    r2 = sum(((g[a] + 0.5) / n - 0.5) ** 2 for a in range(dim))
+    H = (r2 < 0.3 ** 2).astype(float)
+    return poisson.face_beta(poisson.density(H, 1.0, 1.0 / ratio))
+
+
+@pytest.mark.parametrize("shape", [(16, 16), (8, 8, 8)])
+def test_multigrid_matches_dense_direct(shape):
+    beta = _drop_beta(shape)
+    h = 1.0 / shape[0]
+    b = W.random_cells(tuple(reversed(shape)), len(shape), 1.0, seed=21)
+    b -= b.mean()
+    pd = poisson.direct_solve(b, beta, h)
+    pm, cyc, hist = poisson.mg_solve(b, beta, h, rtol=1e-13)
+    assert hist[-1] <= 1e-13
+    assert np.max(np.abs(pm - pd)) <= 1e-10 * np.max(np.abs(pd))
+    assert abs(pm.mean()) < 1e-14 * np.max(np.abs(pd))
+
+
+@pytest.mark.parametrize("shape", [(32, 32), (16, 16, 16)])
+def test_constant_coefficient_fft(shape):
+    dim = len(shape)
+    h = 1.0 / shape[0]
+    beta = [np.full(shape, 0.7) for _ in range(dim)]
+    b = W.random_cells(tuple(reversed(shape)), dim, 1.0, seed=5)
+    b -= b.mean()
+    pf = poisson.fft_solve(b, 0.7, h)
+    pm, _, _ = poisson.mg_solve(b, beta, h, rtol=1e-13)
+    assert np.max(np.abs(pm - pf)) <= 1e-10 * np.max(np.abs(pf))
+
+
+def test_discrete_manufactured_solution_ratio_1000():
+    shape = (64, 64)
+    h = 1.0 / 64
+    beta = _drop_beta(shape)
+    pex = W.random_cells(shape, 2, 1.0, seed=8)
+    pex -= pex.mean()
+    b = poisson.apply_A(pex, beta, h)
+    p, cyc, hist = poisson.mg_solve(b, beta, h, rtol=1e-13)
+    assert np.linalg.norm(p - pex) <= 1e-9 * np.linalg.norm(pex)
+
+
+def test_continuous_manufactured_second_order():
+    errs = []
+    for n in (16, 32, 64):
+        h = 1.0 / n
+        x = (np.arange(n) + 0.5) * h
+        X, Y = np.meshgrid(x, x, indexing="xy")
+        xf = np.arange(n) * h
+        # beta(x, y) = 2 + sin(2 pi x) sampled on faces
+        bx = 2.0 + np.sin(2 * np.pi * xf)[None, :] * np.ones((n, 1))
+        by = 2.0 + np.sin(2 * np.pi * X)
+        pex = np.cos(2 * np.pi * X) * np.sin(2 * np.pi * Y)
+        # div(beta grad p) with beta = 2 + sin(2 pi x)
+        px = -2 * np.pi * np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y)
+        pxx = -4 * np.pi ** 2 * pex
+        pyy = -4 * np.pi ** 2 * pex
+        beta_c = 2.0 + np.sin(2 * np.pi * X)
+        f = beta_c * (pxx + pyy) + 2 * np.pi * np.cos(2 * np.pi * X) * px
+        f -= f.mean()
+        p, _, _ = poisson.mg_solve(f, [bx, by], h, rtol=1e-12)
+        errs.append(np.max(np.abs(p - (pex - pex.mean()))))
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (4, 4, 4)])
+def test_operator_symmetric_and_null_space(shape):
+    beta = _drop_beta(shape)
+    h = 1.0 / shape[0]
+    A = poisson.dense_matrix(beta, h)
+    assert np.max(np.abs(A - A.T)) <= 1e-12 * np.max(np.abs(A))
+    assert np.max(np.abs(A @ np.ones(A.shape[0]))) <= 1e-12 * np.max(np.abs(A))
+
+
+def test_restriction_prolongation_transfer_constants():
+    e = np.full((4, 4, 4), 3.0)
+    assert np.max(np.abs(poisson.prolong(e) - 3.0)) == 0.0
+    r = W.random_cells((8, 8, 8), 3, 1.0, seed=1)
+    assert abs(poisson.restrict(r).sum() * 8 - r.sum()) < 1e-12
+    # linear in x along one axis: interior fine values follow the line exactly
+    x = np.arange(8, dtype=float)
+    e1 = np.tile(x, (8, 1))
+    f = poisson.prolong(e1)
+    xf = (np.arange(16) + 0.5) / 2 - 0.5
+    assert np.max(np.abs(f[3, 1:15] - xf[1:15])) < 1e-14
+
+
+def test_coarsen_beta_means_fine_faces():
+    b = [W.random_cells((8, 8), 2, 1.0, seed=s) for s in (1, 2)]
+    c = poisson.coarsen_beta(b)
+    assert abs(c[0][1, 2] - 0.5 * (b[0][2, 4] + b[0][3, 4])) < 1e-15
+    assert abs(c[1][1, 2] - 0.5 * (b[1][2, 4] + b[1][2, 5])) < 1e-15
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (16, 16, 16)])
+def test_mixed_precision_reaches_fp64_tolerance(shape):
+    beta = _drop_beta(shape)
+    h = 1.0 / shape[0]
+    b = W.random_cells(tuple(reversed(shape)), len(shape), 1.0, seed=31)
+    b -= b.mean()
+    p64, c64, h64 = poisson.mg_solve(b, beta, h, rtol=1e-10)
+    p32, c32, h32 = poisson.mg_solve_mixed(b, beta, h, rtol=1e-10)
+    assert h32[-1] <= 1e-10
+    assert c32 <= c64 + 2
+    pt, _, _ = poisson.mg_solve(b, beta, h, rtol=1e-14, max_cycles=200)
+    assert np.linalg.norm(p32 - pt) <= 1e-7 * np.linalg.norm(pt)
+
+
+def test_projection_makes_velocity_divergence_free():
+    shape = (32, 32)
+    h = 1.0 / 32
+    beta = _drop_beta(shape)
+    us = W.random_faces((32, 32), 2, 1.0, seed=3)
+    F = W.random_faces((32, 32), 2, 5.0, seed=4)
+    dt = 1e-3
+    b = poisson.rhs(us, F, beta, dt, h)
+    assert abs(b.sum()) < 1e-9 * np.abs(b).sum()
+    p, _, _ = poisson.mg_solve(b, beta, h, rtol=1e-13)
+    u = poisson.velocity_update(us, F, beta, p, dt, h)
+    div = poisson.divergence(u, h)
+    assert np.max(np.abs(div)) <= 1e-9 * np.max(np.abs(poisson.divergence(us, h)))
