@@ -1,0 +1,267 @@
+/*
+ * ibproj.h -- C ABI of the MI355X immersed-boundary projection step.
+ *
+ * Method: Ong & Miura, "New Immersed Boundary Method with Irrotational
+ * Discrete Delta Vector for Droplet Simulations with Large Density Ratio"
+ * (arXiv 1807.10504). One projection step interpolates the MAC velocity to
+ * the interface markers (Section 2.2, eq jump_condu), spreads the marker
+ * surface tension to the grid with the irrotational delta vector grad_h H
+ * (Section 3.2, eqs delta_hea_xy, new_hea, new_hea2) or the conventional
+ * delta function (Section 3.1, eq delta_vec), builds the density from the
+ * indicator (eq indicator), solves div(beta grad p) = div(u_star / dt + beta F)
+ * (eq ps with the force in the projection, eq ns2_new) by geometric
+ * multigrid, and corrects the velocity (eq ns2_new).
+ *
+ * Conventions shared by every entry point
+ *  - Grid: uniform spacing h, periodic box of n[0] x n[1] (x n[2]) cells.
+ *    Cell arrays are SoA, x fastest: index c = (k*n[1] + j)*n[0] + i.
+ *    The velocity/force component along axis d is stored at the face on the
+ *    low side of the cell along d (u[c] at x = i*h), one array per
+ *    component, same length as a cell array.
+ *  - Floating point is IEEE binary64 unless a name says otherwise.
+ *  - "device" pointers are HIP device memory owned by the caller; the
+ *    library never frees caller memory. "host" pointers are ordinary host
+ *    memory, read or written before the call returns.
+ *  - stream: a hipStream_t passed as void* (NULL = the null stream). All
+ *    device work is enqueued on it. Calls that must read a device scalar
+ *    (residual norms, error flags, the 2D marker round trip) synchronise
+ *    that stream before returning; such calls are marked "syncs".
+ *  - Return value: IB_OK (0) or a negative error code below. On error the
+ *    outputs are unspecified unless stated; ib_last_error() returns a
+ *    message for the calling thread. No exception crosses this ABI.
+ *  - Handles (ib_ctx, mg_handle) own their device workspace, allocated in
+ *    the create/setup call and freed in destroy. A handle may be used from
+ *    one host thread at a time; calls on one handle must not overlap.
+ */
+#ifndef IBPROJ_H
+#define IBPROJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IB_OK        0
+#define IB_EINVAL   -1  /* bad argument: null pointer, size, mode, grid not coarsenable */
+#define IB_EHIP     -2  /* a HIP runtime call failed */
+#define IB_ENOMEM   -3  /* device allocation failed */
+#define IB_ENOTCONV -4  /* multigrid hit max_cycles; p holds the last iterate, stats filled */
+#define IB_EGEOM    -5  /* geometry: marker or offset surface outside the box interior,
+                           a band face with no element in reach, or the B-spline normal
+                           matrix not positive definite (Schoenberg-Whitney violated) */
+#define IB_ENAN     -6  /* NaN/Inf residual */
+
+enum { IB_SPREAD_IRROT = 0, IB_SPREAD_DELTA = 1 };
+enum { MG_FP64 = 0, MG_MIXED = 1 };
+enum { WS_ZERO = 0, WS_PREV = 1 };
+
+typedef struct {
+    int dim;      /* 2 or 3 */
+    int n[3];     /* cells per axis; n[2] ignored when dim == 2 */
+    double h;     /* uniform spacing */
+} ib_grid;
+
+/* An interface: closed counter-clockwise polyline (2D) or closed triangle
+ * mesh with outward counter-clockwise triangles (3D). */
+typedef struct {
+    int n_markers;
+    const double* X;       /* device, n_markers*dim, interleaved (x, y[, z]) */
+    int n_elems;           /* 3D: triangle count; 2D: 0 (elements are k -> k+1 mod n) */
+    const int32_t* elems;  /* device, n_elems*3 vertex indices (3D); NULL in 2D */
+    const double* nrm;     /* device, n_markers*dim unit normals toward the drop
+                              (3D: required, they define the offset surfaces;
+                              2D: may be NULL, then the left perpendicular of the
+                              chord X_{k+1} - X_{k-1} is used) */
+    const double* fs;      /* device, n_markers: surface tension times curvature */
+    const double* ds;      /* device, n_markers: arc length (2D) / area (3D) */
+} ib_surface;
+
+typedef struct ib_ctx ib_ctx;
+typedef struct mg_handle mg_handle;
+
+/* ---------------------------------------------------------------------------
+ * Context: workspace for binning, spreading and the step. max_markers and
+ * max_elems bound every later surface. Cells per axis must be even and the
+ * total below 2^31. Allocates device memory (about 40 bytes per cell plus
+ * 24 bytes per face per axis).  Errors: IB_EINVAL, IB_ENOMEM, IB_EHIP. */
+int  ib_create(const ib_grid* g, int max_markers, int max_elems, ib_ctx** out);
+void ib_destroy(ib_ctx* ctx);
+
+/* a1 -- marker binning (deterministic counting sort into 4^dim-cell tiles).
+ * tile_of_marker: device int32[n_markers] tile key of each marker;
+ * order:          device int32[n_markers] marker indices sorted by tile,
+ *                 ascending marker index within a tile (stable);
+ * tile_start:     device int32[n_tiles + 1], n_tiles = prod(n[d] / 4),
+ *                 markers of tile t are order[tile_start[t] .. tile_start[t+1]).
+ * Marker positions are wrapped into the periodic box. Any output may be NULL
+ * (the context keeps its own copy for ib_spread). */
+int ib_bin_markers(ib_ctx* ctx, const ib_surface* s, int32_t* tile_of_marker,
+                   int32_t* order, int32_t* tile_start, void* stream);
+
+/* a2 -- interpolation, eq jump_condu:
+ * U[s*dim + d] = sum over faces f of orientation d of u_d(f) phi(dx/h)...,
+ * phi(q) = (1 + cos(pi q/2))/4 for |q| < 2 (eq cherby in grid units), with
+ * minimum-image periodic offsets. u: dim device face arrays; U: device
+ * n_markers*dim. Errors: IB_EINVAL. */
+int ib_interp(ib_ctx* ctx, const double* const u[3], const ib_surface* s, double* U,
+              void* stream);
+
+/* a4 + a5 -- spreading.
+ * IB_SPREAD_IRROT: H (device cell array, required) is the discrete Heaviside
+ *   built from the interface offset by -1.5h, -0.5h, 0.5h, 1.5h (mitred in
+ *   2D, along nrm in 3D) with region values H(q) = 1/2 + q/4 +
+ *   sin(pi q/2)/(2 pi) at q = -2..2 (Section 3.2); F_d = f (H_c - H_{c-e_d})/h
+ *   with f = fs at the foot point on the nearest element (linear/barycentric).
+ *   The offset surfaces must stay strictly inside the box (no wrap): else
+ *   IB_EGEOM (syncs).
+ * IB_SPREAD_DELTA: F_d(x_f) = sum_s fs_s ds_s n_s,d delta_h(x_f - X_s)
+ *   (eq delta_vec); H may be NULL (then not computed) or is filled as above.
+ * F: dim device face arrays, fully overwritten. Deterministic: repeated calls
+ * give bitwise identical results. */
+int ib_spread(ib_ctx* ctx, const ib_surface* s, int mode, double* const F[3], double* H,
+              void* stream);
+
+/* a6 -- density and face coefficient (eq indicator with I = H):
+ * rho_c = rho_out + (rho_in - rho_out) H_c, beta_d[c] = 2/(rho_c + rho_{c-e_d}).
+ * H device cell array; beta: dim device face arrays. */
+int ib_coefficients(ib_ctx* ctx, const double* H, double rho_in, double rho_out,
+                    double* const beta[3], void* stream);
+
+/* a7 -- right side (eqs ps, ns2_new):
+ * b_c = (1/h) sum_d [w_d(c+e_d) - w_d(c)], w = u_star / dt + beta F, mean removed. */
+int ib_rhs(ib_ctx* ctx, const double* const u_star[3], const double* const F[3],
+           const double* const beta[3], double dt, double* b, void* stream);
+
+/* a11 -- velocity update (eq ns2_new): u_d = u*_d + dt beta_d (F_d - (p_c - p_{c-e_d})/h).
+ * u_new may alias u_star. */
+int ib_update(ib_ctx* ctx, const double* const u_star[3], const double* const F[3],
+              const double* const beta[3], const double* p, double dt,
+              double* const u_new[3], void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Multigrid for A p = b, (A p)_c = (1/h^2) sum_faces beta_f (p_nb - p_c),
+ * periodic, zero-mean solution (Section 2.1: centred second order, solved by
+ * multigrid). Cell-centred V(nu1, nu2) cycles: red-black Gauss-Seidel (red =
+ * index sum even, first), restriction = mean of the 2^dim children,
+ * prolongation = cell-centred (bi/tri)linear, coarse face coefficient = mean
+ * of the fine faces on it, coarsest n_coarsest^dim grid solved exactly with
+ * the zero-mean constraint, mean removed after every cycle.
+ * MG_MIXED: float32 V-cycles on the float64 defect r = b - A p (float64
+ * residual, update and coarsest solve), same stopping test. */
+typedef struct {
+    int precision;   /* MG_FP64 or MG_MIXED */
+    int nu1, nu2;    /* smoothing sweeps before / after the coarse correction (2, 2) */
+    int n_coarsest;  /* cells per axis on the coarsest grid (4); n[d] = n_coarsest * 2^L */
+} mg_opts;
+
+typedef struct {
+    int cycles;              /* V-cycles (outer iterations in MG_MIXED) performed */
+    double rel_res0;         /* ||b - A p0|| / ||b|| of the initial guess */
+    double rel_res;          /* final ||b - A p|| / ||b|| */
+    double res_hist[128];    /* rel_res after each cycle (first 128) */
+} mg_stats;
+
+/* Allocates the hierarchy. Errors: IB_EINVAL (grid not n_coarsest * 2^L), IB_ENOMEM. */
+int  mg_setup(const ib_grid* g, const mg_opts* o, mg_handle** out);
+/* beta: dim device face arrays of the finest level. The handle keeps these
+ * pointers (no copy) until the next call: they must stay valid and unchanged
+ * while mg_solve runs. Coarsens the coefficients and factorises the coarsest
+ * grid. */
+int  mg_update_coeffs(mg_handle* m, const double* const beta[3], void* stream);
+/* b: device cell array (zero mean); p: device cell array, in: initial guess,
+ * out: zero-mean solution. Stops when ||b - A p||_2 / ||b||_2 <= rtol or after
+ * max_cycles (IB_ENOTCONV); fixed_cycles > 0 instead runs exactly that many
+ * cycles (no test). stats may be NULL. Syncs once per cycle (one scalar).
+ * b = 0 returns p = 0. Errors: IB_EINVAL, IB_ENOTCONV, IB_ENAN. */
+int  mg_solve(mg_handle* m, const double* b, double* p, double rtol, int max_cycles,
+              int fixed_cycles, mg_stats* stats, void* stream);
+void mg_destroy(mg_handle* m);
+
+/* ---------------------------------------------------------------------------
+ * One projection step (a1..a11). */
+typedef struct {
+    double rho_in, rho_out;  /* drop and ambient densities */
+    double sigma;            /* surface tension coefficient (2D relocation) */
+    double dt;
+    double rtol;             /* multigrid stopping tolerance */
+    int max_cycles;
+    int fixed_cycles;        /* > 0: exactly this many cycles (parity runs) */
+    int spread_mode;         /* IB_SPREAD_IRROT or IB_SPREAD_DELTA */
+    int warm_start;          /* WS_ZERO or WS_PREV (p_prev as initial guess) */
+} ib_params;
+
+typedef struct {
+    const double* u_star[3]; /* device face arrays */
+    const double* p_prev;    /* device cell array (WS_PREV) or NULL */
+    ib_surface surf;         /* 3D: the static surface (all fields required).
+                                2D: only n_markers is read; markers come from X_host. */
+    double* X_host;          /* 2D: host n_markers*2, in: markers at step n, out: advanced
+                                by dt U and relocated on the least-squares B-spline.
+                                3D: NULL. */
+} ib_state;
+
+typedef struct {
+    double* p;               /* device cell array (required) */
+    double* u[3];            /* device face arrays (required; may alias u_star) */
+    double* U;               /* device n_markers*dim marker velocities (required) */
+    double* H;               /* device cell array or NULL */
+    double* F[3];            /* device face arrays or NULL */
+    double* fs_host;         /* 2D: host n_markers sigma*kappa after relocation, or NULL */
+    mg_stats stats;
+} ib_outputs;
+
+/* Runs interp -> (2D: D2H U, host advance + B-spline relocation, H2D) ->
+ * spread -> coefficients -> rhs -> mg_solve -> update on `stream`. The mg
+ * handle must be set up for the same grid. Syncs (per multigrid cycle and, in
+ * 2D, for the marker round trip). Errors: any of the above. */
+int project_step(ib_ctx* ctx, mg_handle* m, const ib_params* prm, ib_state* st,
+                 ib_outputs* out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * a3 -- host FP64 least-squares B-spline relocation (Section 4), 2D closed
+ * curve of n markers. X, U: host n*2. Advances X* = X + dt U, fits a
+ * periodic cubic B-spline (knot spacing L/round(L/1.5h), at least 7 spans)
+ * to the chord-length parametrised markers by least squares, places n new
+ * markers at constant arc spacing starting at the first marker's parameter,
+ * and returns fs = sigma kappa (eq ten_f with tangents half-way between
+ * markers, eq b_tan), ds (the spacing) and unit inward normals. Outputs are
+ * host arrays: X_out n*2, fs_out n, ds_out n, nrm_out n*2 (nrm_out may be
+ * NULL). Arithmetic is binary64 with a fixed operation order (no contraction),
+ * so results are reproducible bit for bit. Errors: IB_EINVAL, IB_EGEOM. */
+int ib_relocate_bspline(int n, const double* X, const double* U, double dt, double h,
+                        double sigma, double* X_out, double* fs_out, double* ds_out,
+                        double* nrm_out);
+
+/* 3D surface geometry (the paper stops at curves; this is the library's
+ * extension for static closed meshes): cotangent-formula curvature force
+ * F_v = -sigma d(area)/dX_v, vertex area A_v = sum(adjacent areas)/3, unit
+ * angle-weighted normal toward the drop; fs = F_v . n_v / A_v, ds = A_v.
+ * All host arrays: X nv*3, tris nt*3; outputs fs nv, ds nv, nrm nv*3. */
+int ib_surface_geometry_3d(int nv, const double* X, int nt, const int32_t* tris, double sigma,
+                           double* fs_out, double* ds_out, double* nrm_out);
+
+/* ---------------------------------------------------------------------------
+ * a12 -- diagnostics (Section 5): Delta P = mean(p | H >= 1-1e-12) -
+ * mean(p | H <= 1e-12) (eq sd_pres_diff); TKE = sum of squared face
+ * velocities times h^dim (eq tke); grid force sum; max |index-form curl| of F
+ * (Section 3.2); max |F|. Any of p/H, u, F may be NULL (its fields are then 0).
+ * Syncs. */
+typedef struct {
+    double dP;
+    double tke;
+    double force_sum[3];
+    double curl_max;
+    double f_max;
+} ib_diag;
+
+int ib_diagnostics(ib_ctx* ctx, const double* p, const double* H, const double* const u[3],
+                   const double* const F[3], ib_diag* out, void* stream);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* ib_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IBPROJ_H */

@@ -1,0 +1,145 @@
+// Shared internals of the ibproj library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/ibproj.h"
+
+namespace ib {
+
+// ---------------------------------------------------------------------------
+// error reporting
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define IB_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::ib::fail(IB_EHIP, std::string(#call " failed: ") +                \
+                                           hipGetErrorString(e_));                     \
+    } while (0)
+
+#define IB_CHECK(cond, code, msg)                                                      \
+    do {                                                                               \
+        if (!(cond)) return ::ib::fail((code), (msg));                                 \
+    } while (0)
+
+#define IB_TRY(call)                                                                   \
+    do {                                                                               \
+        int r_ = (call);                                                               \
+        if (r_ != IB_OK) return r_;                                                    \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// grid geometry passed to kernels by value
+struct Dims {
+    int nx, ny, nz;   // nz = 1 in 2D
+    int dim;
+    double h;
+    __host__ __device__ long cells() const { return (long)nx * ny * nz; }
+};
+
+inline Dims make_dims(const ib_grid& g) {
+    Dims d;
+    d.dim = g.dim;
+    d.nx = g.n[0];
+    d.ny = g.n[1];
+    d.nz = g.dim == 3 ? g.n[2] : 1;
+    d.h = g.h;
+    return d;
+}
+
+constexpr int kBlock = 256;
+inline unsigned grid_for(long n, int block = kBlock) {
+    return (unsigned)((n + block - 1) / block);
+}
+
+__host__ __device__ inline int wrap(int i, int n) {
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// fixed tree sum over one block (blockDim.x a power of two, sh of blockDim.x)
+__device__ inline double block_reduce_sum(double v, double* sh) {
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// fixed-point scale of the deterministic integer accumulation of Heaviside
+// contributions: 1.0 (a full cell) maps to 2^56
+constexpr double kFixScale = 72057594037927936.0;        // 2^56
+constexpr double kFixInv = 1.0 / 72057594037927936.0;
+
+// tile edge (cells) of the marker bins
+constexpr int kTile = 4;
+
+// ---------------------------------------------------------------------------
+// context
+struct Ctx {
+    ib_grid g;
+    Dims d;
+    int max_markers, max_elems;
+    // binning
+    int n_tiles, tnx, tny, tnz;
+    int32_t* bin_key = nullptr;      // per marker tile key
+    int32_t* bin_idx = nullptr;      // 0..n-1
+    int32_t* bin_key_sorted = nullptr;
+    int32_t* bin_order = nullptr;    // sorted marker indices
+    int32_t* tile_start = nullptr;   // n_tiles + 1
+    void* sort_tmp = nullptr;
+    size_t sort_tmp_bytes = 0;
+    // Heaviside accumulators (int64, zeroed after every use)
+    long long* accA = nullptr;
+    long long* accS = nullptr;
+    // nearest-element keys per face (all ones after every use)
+    unsigned long long* best = nullptr;  // dim * cells
+    // offset vertices (4 surfaces)
+    double* offv = nullptr;              // 4 * max_markers * dim
+    // device marker buffers for 2D steps
+    double* mX = nullptr;
+    double* mfs = nullptr;
+    double* mds = nullptr;
+    double* mnrm = nullptr;
+    // step intermediates
+    double* H = nullptr;
+    double* F[3] = {nullptr, nullptr, nullptr};
+    double* beta[3] = {nullptr, nullptr, nullptr};
+    double* b = nullptr;
+    // flags / scalars
+    int* flags = nullptr;                // [0] geometry error, [1] band face without element
+    double* red = nullptr;               // reduction scratch
+    int red_len = 0;
+    double* host_red = nullptr;          // pinned host scalars
+};
+
+// launchers implemented in the .hip files
+int launch_bin_markers(Ctx* c, const ib_surface* s, hipStream_t st);
+int launch_interp(Ctx* c, const double* const u[3], const ib_surface* s, double* U, hipStream_t st);
+int launch_spread_delta(Ctx* c, const ib_surface* s, double* const F[3], hipStream_t st);
+int launch_heaviside(Ctx* c, const ib_surface* s, double* H, hipStream_t st);
+int launch_irrot_force(Ctx* c, const ib_surface* s, const double* H, double* const F[3], hipStream_t st);
+int launch_coefficients(Ctx* c, const double* H, double rin, double rout, double* const beta[3], hipStream_t st);
+int launch_rhs(Ctx* c, const double* const us[3], const double* const F[3], const double* const beta[3],
+               double dt, double* b, hipStream_t st);
+int launch_update(Ctx* c, const double* const us[3], const double* const F[3], const double* const beta[3],
+                  const double* p, double dt, double* const un[3], hipStream_t st);
+int launch_diagnostics(Ctx* c, const double* p, const double* H, const double* const u[3],
+                       const double* const F[3], ib_diag* out, hipStream_t st);
+int read_flags(Ctx* c, int* host_flags, hipStream_t st);
+
+// deterministic reduction helpers (fixed tree: block partials then one block)
+int device_sum(const double* partials_in, int n, double* out_dev, hipStream_t st);
+
+}  // namespace ib

@@ -1,0 +1,705 @@
+// Geometric multigrid for the projection Poisson problem (Section 2.1: the
+// centred second-order Laplacian of eq ps, solved by multigrid).
+//
+// (A p)_c = (1/h^2) sum_faces beta_f (p_nb - p_c), periodic, zero-mean p.
+// Cell-centred V(nu1, nu2): red-black Gauss-Seidel (red = i+j+k even first),
+// restriction = mean of the 2^dim children of the fine residual, cell-centred
+// (bi/tri)linear prolongation (3/4, 1/4 per axis), coarse face coefficient =
+// mean of the 2^(dim-1) fine faces on the coarse face, coarsest grid solved
+// with the inverse of the bordered matrix [[A, 1], [1^T, 0]] (zero-mean
+// constraint), mean of p removed after every cycle.
+//
+// Mixed precision: the V-cycle in float32 (float32 coefficients cast from the
+// float64 hierarchy) acting on fl32(b - A p), with the defect, the update
+// p += e and the coarsest solve in float64.
+//
+// Memory layout: every level stores p, b and one coefficient array per axis
+// (left faces) as SoA with x fastest. Kernels are plain one-thread-per-cell
+// stencils; the stopping test reads one scalar per cycle.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace ib {
+
+template <typename T>
+struct LevelT {
+    T* p = nullptr;
+    T* b = nullptr;
+    T* beta[3] = {nullptr, nullptr, nullptr};
+};
+
+struct Level {
+    Dims d;
+    LevelT<double> f64;
+    LevelT<float> f32;
+    bool own_pb = true;
+};
+
+}  // namespace ib
+
+struct mg_handle {
+    ib_grid g;
+    mg_opts o;
+    std::vector<ib::Level> lv;
+    // coarsest dense solve
+    int nc = 0;                 // coarsest cells
+    double* cmat = nullptr;     // (nc+1)^2 bordered matrix
+    double* cinv = nullptr;     // its inverse
+    double* cwork = nullptr;    // coarsest rhs/solution in float64 (mixed)
+    // reductions
+    double* red = nullptr;      // block partials + scalars
+    double* host = nullptr;     // pinned scalars
+    // float64 buffers for the mixed defect loop are the caller's p and b
+    bool coeffs_ready = false;
+};
+
+namespace ib {
+
+constexpr int kRed = 1024;
+
+// ---------------------------------------------------------------------------
+// index helpers
+struct Nb {
+    long c, xm, xp, ym, yp, zm, zp;
+};
+
+__device__ __forceinline__ Nb neighbours(const Dims& d, int i, int j, int k, int dim) {
+    Nb n;
+    n.c = ((long)k * d.ny + j) * d.nx + i;
+    n.xm = i == 0 ? n.c + d.nx - 1 : n.c - 1;
+    n.xp = i == d.nx - 1 ? n.c - (d.nx - 1) : n.c + 1;
+    n.ym = j == 0 ? n.c + (long)(d.ny - 1) * d.nx : n.c - d.nx;
+    n.yp = j == d.ny - 1 ? n.c - (long)(d.ny - 1) * d.nx : n.c + d.nx;
+    if (dim == 3) {
+        long pl = (long)d.nx * d.ny;
+        n.zm = k == 0 ? n.c + (long)(d.nz - 1) * pl : n.c - pl;
+        n.zp = k == d.nz - 1 ? n.c - (long)(d.nz - 1) * pl : n.c + pl;
+    } else {
+        n.zm = n.zp = n.c;
+    }
+    return n;
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ T apply_row(const T* __restrict__ p, const T* __restrict__ b0,
+                                       const T* __restrict__ b1, const T* __restrict__ b2,
+                                       const Nb& n) {
+    // sum_d br (p_r - p) - bl (p - p_l), without the 1/h^2
+    T pc = p[n.c];
+    T s = b0[n.xp] * (p[n.xp] - pc) - b0[n.c] * (pc - p[n.xm]);
+    s += b1[n.yp] * (p[n.yp] - pc) - b1[n.c] * (pc - p[n.ym]);
+    if (DIM == 3) s += b2[n.zp] * (p[n.zp] - pc) - b2[n.c] * (pc - p[n.zm]);
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// smoother: one colour of red-black Gauss-Seidel, one thread per cell of the colour
+template <typename T, int DIM>
+__global__ void k_rbgs(T* __restrict__ p, const T* __restrict__ b, const T* __restrict__ b0,
+                       const T* __restrict__ b1, const T* __restrict__ b2, Dims d, T h2, int color) {
+    long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int hx = d.nx >> 1;
+    long half = d.cells() >> 1;
+    if (t >= half) return;
+    int i2 = (int)(t % hx);
+    long r = t / hx;
+    int j = (int)(r % d.ny);
+    int k = (int)(r / d.ny);
+    int i = 2 * i2 + ((j + k + color) & 1);
+    Nb n = neighbours(d, i, j, k, DIM);
+    T br = b0[n.xp], bl = b0[n.c];
+    T num = br * p[n.xp] + bl * p[n.xm];
+    T diag = br + bl;
+    br = b1[n.yp];
+    bl = b1[n.c];
+    num += br * p[n.yp] + bl * p[n.ym];
+    diag += br + bl;
+    if (DIM == 3) {
+        br = b2[n.zp];
+        bl = b2[n.c];
+        num += br * p[n.zp] + bl * p[n.zm];
+        diag += br + bl;
+    }
+    p[n.c] = (num - h2 * b[n.c]) / diag;
+}
+
+// residual of the fine level restricted to the coarse right side
+template <typename T, int DIM>
+__global__ void k_residual_restrict(const T* __restrict__ p, const T* __restrict__ b,
+                                    const T* __restrict__ b0, const T* __restrict__ b1,
+                                    const T* __restrict__ b2, Dims f, T inv_h2,
+                                    T* __restrict__ bc) {
+    long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int cx = f.nx >> 1, cy = f.ny >> 1, cz = DIM == 3 ? (f.nz >> 1) : 1;
+    long ncells = (long)cx * cy * cz;
+    if (t >= ncells) return;
+    int I = (int)(t % cx);
+    long r = t / cx;
+    int J = (int)(r % cy);
+    int K = (int)(r / cy);
+    T acc = 0;
+    for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                Nb n = neighbours(f, 2 * I + dx, 2 * J + dy, DIM == 3 ? 2 * K + dz : 0, DIM);
+                acc += b[n.c] - apply_row<T, DIM>(p, b0, b1, b2, n) * inv_h2;
+            }
+    bc[t] = acc * (DIM == 3 ? T(0.125) : T(0.25));
+}
+
+// p_fine += P e_coarse (cell-centred linear, 3/4 and 1/4 per axis)
+template <typename T, int DIM>
+__global__ void k_prolong_add(T* __restrict__ p, const T* __restrict__ e, Dims f) {
+    long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= f.cells()) return;
+    int i = (int)(c % f.nx);
+    long r = c / f.nx;
+    int j = (int)(r % f.ny);
+    int k = (int)(r / f.ny);
+    int cx = f.nx >> 1, cy = f.ny >> 1, cz = DIM == 3 ? (f.nz >> 1) : 1;
+    int I = i >> 1, J = j >> 1, K = k >> 1;
+    int I2 = (i & 1) ? (I + 1 == cx ? 0 : I + 1) : (I == 0 ? cx - 1 : I - 1);
+    int J2 = (j & 1) ? (J + 1 == cy ? 0 : J + 1) : (J == 0 ? cy - 1 : J - 1);
+    const T a = T(0.75), q = T(0.25);
+    T v;
+    if (DIM == 2) {
+        T r0 = a * e[(long)J * cx + I] + q * e[(long)J * cx + I2];
+        T r1 = a * e[(long)J2 * cx + I] + q * e[(long)J2 * cx + I2];
+        v = a * r0 + q * r1;
+    } else {
+        int K2 = (k & 1) ? (K + 1 == cz ? 0 : K + 1) : (K == 0 ? cz - 1 : K - 1);
+        long pl = (long)cx * cy;
+        const T* e0 = e + (long)K * pl;
+        const T* e1 = e + (long)K2 * pl;
+        T r00 = a * e0[(long)J * cx + I] + q * e0[(long)J * cx + I2];
+        T r01 = a * e0[(long)J2 * cx + I] + q * e0[(long)J2 * cx + I2];
+        T r10 = a * e1[(long)J * cx + I] + q * e1[(long)J * cx + I2];
+        T r11 = a * e1[(long)J2 * cx + I] + q * e1[(long)J2 * cx + I2];
+        v = a * (a * r00 + q * r01) + q * (a * r10 + q * r11);
+    }
+    p[c] += v;
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ x, long n, T v) {
+    long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) x[c] = v;
+}
+
+__global__ void k_cast_f32(const double* __restrict__ x, float* __restrict__ y, long n) {
+    long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) y[c] = (float)x[c];
+}
+
+// coarse face coefficient = mean of the fine faces on it
+template <int DIM>
+__global__ void k_coarsen_beta(const double* __restrict__ f0, const double* __restrict__ f1,
+                               const double* __restrict__ f2, Dims f, double* __restrict__ c0,
+                               double* __restrict__ c1, double* __restrict__ c2) {
+    long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int cx = f.nx >> 1, cy = f.ny >> 1, cz = DIM == 3 ? (f.nz >> 1) : 1;
+    long ncells = (long)cx * cy * cz;
+    if (t >= ncells) return;
+    int I = (int)(t % cx);
+    long r = t / cx;
+    int J = (int)(r % cy);
+    int K = (int)(r / cy);
+    long fpl = (long)f.nx * f.ny;
+    auto at = [&](int i, int j, int k) { return (long)k * fpl + (long)j * f.nx + i; };
+    if (DIM == 2) {
+        c0[t] = 0.5 * (f0[at(2 * I, 2 * J, 0)] + f0[at(2 * I, 2 * J + 1, 0)]);
+        c1[t] = 0.5 * (f1[at(2 * I, 2 * J, 0)] + f1[at(2 * I + 1, 2 * J, 0)]);
+    } else {
+        c0[t] = 0.25 * ((f0[at(2 * I, 2 * J, 2 * K)] + f0[at(2 * I, 2 * J + 1, 2 * K)]) +
+                        (f0[at(2 * I, 2 * J, 2 * K + 1)] + f0[at(2 * I, 2 * J + 1, 2 * K + 1)]));
+        c1[t] = 0.25 * ((f1[at(2 * I, 2 * J, 2 * K)] + f1[at(2 * I + 1, 2 * J, 2 * K)]) +
+                        (f1[at(2 * I, 2 * J, 2 * K + 1)] + f1[at(2 * I + 1, 2 * J, 2 * K + 1)]));
+        c2[t] = 0.25 * ((f2[at(2 * I, 2 * J, 2 * K)] + f2[at(2 * I + 1, 2 * J, 2 * K)]) +
+                        (f2[at(2 * I, 2 * J + 1, 2 * K)] + f2[at(2 * I + 1, 2 * J + 1, 2 * K)]));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// coarsest level: bordered matrix, Gauss-Jordan inverse, apply
+template <int DIM>
+__global__ void k_build_coarse(const double* __restrict__ b0, const double* __restrict__ b1,
+                               const double* __restrict__ b2, Dims d, double* __restrict__ M) {
+    int nc = (int)d.cells();
+    int m = nc + 1;
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > nc) return;
+    for (int c = 0; c < m; ++c) M[(long)r * m + c] = 0.0;
+    if (r == nc) {
+        for (int c = 0; c < nc; ++c) M[(long)r * m + c] = 1.0;
+        return;
+    }
+    int i = r % d.nx, j = (r / d.nx) % d.ny, k = r / (d.nx * d.ny);
+    Nb n = neighbours(d, i, j, k, DIM);
+    double inv = 1.0 / (d.h * d.h);
+    auto add = [&](long col, double v) { M[(long)r * m + col] += v * inv; };
+    add(n.xp, b0[n.xp]); add(n.c, -b0[n.xp]);
+    add(n.xm, b0[n.c]);  add(n.c, -b0[n.c]);
+    add(n.yp, b1[n.yp]); add(n.c, -b1[n.yp]);
+    add(n.ym, b1[n.c]);  add(n.c, -b1[n.c]);
+    if (DIM == 3) {
+        add(n.zp, b2[n.zp]); add(n.c, -b2[n.zp]);
+        add(n.zm, b2[n.c]);  add(n.c, -b2[n.c]);
+    }
+    M[(long)r * m + nc] = 1.0;
+}
+
+// one workgroup; augmented [M | I] in LDS, partial pivoting
+constexpr int kMaxCoarse = 65;
+
+__global__ void k_gauss_jordan(const double* __restrict__ M, int m, double* __restrict__ Minv,
+                               int* __restrict__ flag) {
+    __shared__ double a[kMaxCoarse][2 * kMaxCoarse + 1];
+    __shared__ int piv;
+    int t = threadIdx.x;
+    for (int q = t; q < m * m; q += blockDim.x) {
+        int r = q / m, c = q % m;
+        a[r][c] = M[q];
+        a[r][m + c] = (r == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int col = 0; col < m; ++col) {
+        if (t == 0) {
+            int best = col;
+            double bv = fabs(a[col][col]);
+            for (int r = col + 1; r < m; ++r)
+                if (fabs(a[r][col]) > bv) { bv = fabs(a[r][col]); best = r; }
+            piv = best;
+            if (bv == 0.0) *flag = 1;
+        }
+        __syncthreads();
+        int pr = piv;
+        if (pr != col)
+            for (int c = t; c < 2 * m; c += blockDim.x) {
+                double tmp = a[col][c];
+                a[col][c] = a[pr][c];
+                a[pr][c] = tmp;
+            }
+        __syncthreads();
+        double inv = 1.0 / a[col][col];
+        __syncthreads();
+        for (int c = t; c < 2 * m; c += blockDim.x) a[col][c] *= inv;
+        __syncthreads();
+        for (int q = t; q < m * 2 * m; q += blockDim.x) {
+            int r = q / (2 * m), c = q % (2 * m);
+            if (r != col && c != col) a[r][c] -= a[r][col] * a[col][c];
+        }
+        __syncthreads();
+        for (int r = t; r < m; r += blockDim.x)
+            if (r != col) a[r][col] = 0.0;
+        __syncthreads();
+    }
+    for (int q = t; q < m * m; q += blockDim.x) Minv[q] = a[q / m][m + q % m];
+}
+
+// x = (Minv [b; 0])[0..nc), input/output in T
+template <typename T>
+__global__ void k_coarse_apply(const double* __restrict__ Minv, int nc, const T* __restrict__ b,
+                               T* __restrict__ x) {
+    __shared__ double sb[kMaxCoarse];
+    int t = threadIdx.x;
+    for (int q = t; q < nc; q += blockDim.x) sb[q] = (double)b[q];
+    __syncthreads();
+    int m = nc + 1;
+    for (int r = t; r < nc; r += blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < nc; ++c) s += Minv[(long)r * m + c] * sb[c];
+        x[r] = (T)s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// norms: partial sums of r^2 (and of p) per block
+template <int DIM>
+__global__ void k_resid_norm(const double* __restrict__ p, const double* __restrict__ b,
+                             const double* __restrict__ b0, const double* __restrict__ b1,
+                             const double* __restrict__ b2, Dims d, double inv_h2,
+                             double* __restrict__ partial_r2, double* __restrict__ partial_b2) {
+    __shared__ double sh[kBlock];
+    double ar = 0.0, ab = 0.0;
+    long N = d.cells();
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long)gridDim.x * blockDim.x) {
+        int i = (int)(c % d.nx);
+        long r = c / d.nx;
+        int j = (int)(r % d.ny);
+        int k = (int)(r / d.ny);
+        Nb n = neighbours(d, i, j, k, DIM);
+        double bv = b[c];
+        double rv = bv - apply_row<double, DIM>(p, b0, b1, b2, n) * inv_h2;
+        ar += rv * rv;
+        ab += bv * bv;
+    }
+    double s = block_reduce_sum(ar, sh);
+    if (threadIdx.x == 0) partial_r2[blockIdx.x] = s;
+    if (partial_b2) {
+        s = block_reduce_sum(ab, sh);
+        if (threadIdx.x == 0) partial_b2[blockIdx.x] = s;
+    }
+}
+
+// mixed precision: r32 = fl32(b - A p) with partial sums of r^2 and b^2
+template <int DIM>
+__global__ void k_defect_f32(const double* __restrict__ p, const double* __restrict__ b,
+                             const double* __restrict__ b0, const double* __restrict__ b1,
+                             const double* __restrict__ b2, Dims d, double inv_h2,
+                             float* __restrict__ r32, double* __restrict__ partial_r2,
+                             double* __restrict__ partial_b2) {
+    __shared__ double sh[kBlock];
+    double ar = 0.0, ab = 0.0;
+    long N = d.cells();
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long)gridDim.x * blockDim.x) {
+        int i = (int)(c % d.nx);
+        long r = c / d.nx;
+        int j = (int)(r % d.ny);
+        int k = (int)(r / d.ny);
+        Nb n = neighbours(d, i, j, k, DIM);
+        double bv = b[c];
+        double rv = bv - apply_row<double, DIM>(p, b0, b1, b2, n) * inv_h2;
+        r32[c] = (float)rv;
+        ar += rv * rv;
+        ab += bv * bv;
+    }
+    double s = block_reduce_sum(ar, sh);
+    if (threadIdx.x == 0) partial_r2[blockIdx.x] = s;
+    if (partial_b2) {
+        s = block_reduce_sum(ab, sh);
+        if (threadIdx.x == 0) partial_b2[blockIdx.x] = s;
+    }
+}
+
+// p += e (float32 correction) with partial sums of the new p
+__global__ void k_correct_f32(double* __restrict__ p, const float* __restrict__ e, long N,
+                              double* __restrict__ partial) {
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long)gridDim.x * blockDim.x) {
+        double v = p[c] + (double)e[c];
+        p[c] = v;
+        acc += v;
+    }
+    double s = block_reduce_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void k_sum_cells(const double* __restrict__ p, long N, double* __restrict__ partial) {
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long)gridDim.x * blockDim.x)
+        acc += p[c];
+    double s = block_reduce_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void k_sub_scalar_mean(double* __restrict__ p, long N, const double* __restrict__ sum) {
+    long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < N) p[c] -= *sum / (double)N;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+template <typename T> LevelT<T>& lvl(Level& L);
+template <> LevelT<double>& lvl<double>(Level& L) { return L.f64; }
+template <> LevelT<float>& lvl<float>(Level& L) { return L.f32; }
+
+template <typename T>
+static void launch_rbgs(Level& L, int color, hipStream_t st) {
+    LevelT<T>& A = lvl<T>(L);
+    T h2 = (T)(L.d.h * L.d.h);
+    long half = L.d.cells() / 2;
+    if (L.d.dim == 2)
+        hipLaunchKernelGGL((k_rbgs<T, 2>), dim3(grid_for(half)), dim3(kBlock), 0, st, A.p, A.b,
+                           A.beta[0], A.beta[1], A.beta[1], L.d, h2, color);
+    else
+        hipLaunchKernelGGL((k_rbgs<T, 3>), dim3(grid_for(half)), dim3(kBlock), 0, st, A.p, A.b,
+                           A.beta[0], A.beta[1], A.beta[2], L.d, h2, color);
+}
+
+template <typename T>
+static void vcycle(mg_handle* m, int l, hipStream_t st) {
+    Level& L = m->lv[l];
+    LevelT<T>& A = lvl<T>(L);
+    int last = (int)m->lv.size() - 1;
+    if (l == last) {
+        hipLaunchKernelGGL((k_coarse_apply<T>), dim3(1), dim3(64), 0, st, m->cinv, m->nc, A.b, A.p);
+        return;
+    }
+    Level& C = m->lv[l + 1];
+    LevelT<T>& B = lvl<T>(C);
+    for (int s = 0; s < m->o.nu1; ++s) {
+        launch_rbgs<T>(L, 0, st);
+        launch_rbgs<T>(L, 1, st);
+    }
+    T inv_h2 = (T)(1.0 / (L.d.h * L.d.h));
+    long nc = C.d.cells();
+    if (L.d.dim == 2)
+        hipLaunchKernelGGL((k_residual_restrict<T, 2>), dim3(grid_for(nc)), dim3(kBlock), 0, st,
+                           A.p, A.b, A.beta[0], A.beta[1], A.beta[1], L.d, inv_h2, B.b);
+    else
+        hipLaunchKernelGGL((k_residual_restrict<T, 3>), dim3(grid_for(nc)), dim3(kBlock), 0, st,
+                           A.p, A.b, A.beta[0], A.beta[1], A.beta[2], L.d, inv_h2, B.b);
+    if (l + 1 != last)
+        hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(nc)), dim3(kBlock), 0, st, B.p, nc, (T)0);
+    vcycle<T>(m, l + 1, st);
+    if (L.d.dim == 2)
+        hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(grid_for(L.d.cells())), dim3(kBlock), 0, st,
+                           A.p, B.p, L.d);
+    else
+        hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(grid_for(L.d.cells())), dim3(kBlock), 0, st,
+                           A.p, B.p, L.d);
+    for (int s = 0; s < m->o.nu2; ++s) {
+        launch_rbgs<T>(L, 0, st);
+        launch_rbgs<T>(L, 1, st);
+    }
+}
+
+static int red_blocks(long N) { return (int)std::min<long>(kRed, (long)grid_for(N)); }
+
+// ||b - A p||^2 (and ||b||^2 when want_b) into m->host[0], m->host[1]; syncs
+static int fp64_norms(mg_handle* m, bool want_b, hipStream_t st) {
+    Level& L = m->lv[0];
+    long N = L.d.cells();
+    int nb = red_blocks(N);
+    double inv_h2 = 1.0 / (L.d.h * L.d.h);
+    double* pr = m->red;
+    double* pb = want_b ? m->red + kRed : nullptr;
+    if (L.d.dim == 2)
+        hipLaunchKernelGGL((k_resid_norm<2>), dim3(nb), dim3(kBlock), 0, st, L.f64.p, L.f64.b,
+                           L.f64.beta[0], L.f64.beta[1], L.f64.beta[1], L.d, inv_h2, pr, pb);
+    else
+        hipLaunchKernelGGL((k_resid_norm<3>), dim3(nb), dim3(kBlock), 0, st, L.f64.p, L.f64.b,
+                           L.f64.beta[0], L.f64.beta[1], L.f64.beta[2], L.d, inv_h2, pr, pb);
+    IB_TRY(device_sum(pr, nb, m->red + 3 * kRed, st));
+    if (want_b) IB_TRY(device_sum(pb, nb, m->red + 3 * kRed + 1, st));
+    IB_HIP(hipMemcpyAsync(m->host, m->red + 3 * kRed, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+    IB_HIP(hipStreamSynchronize(st));
+    return IB_OK;
+}
+
+static int mixed_defect(mg_handle* m, bool want_b, hipStream_t st) {
+    Level& L = m->lv[0];
+    long N = L.d.cells();
+    int nb = red_blocks(N);
+    double inv_h2 = 1.0 / (L.d.h * L.d.h);
+    double* pr = m->red;
+    double* pb = want_b ? m->red + kRed : nullptr;
+    if (L.d.dim == 2)
+        hipLaunchKernelGGL((k_defect_f32<2>), dim3(nb), dim3(kBlock), 0, st, L.f64.p, L.f64.b,
+                           L.f64.beta[0], L.f64.beta[1], L.f64.beta[1], L.d, inv_h2, L.f32.b, pr, pb);
+    else
+        hipLaunchKernelGGL((k_defect_f32<3>), dim3(nb), dim3(kBlock), 0, st, L.f64.p, L.f64.b,
+                           L.f64.beta[0], L.f64.beta[1], L.f64.beta[2], L.d, inv_h2, L.f32.b, pr, pb);
+    IB_TRY(device_sum(pr, nb, m->red + 3 * kRed, st));
+    if (want_b) IB_TRY(device_sum(pb, nb, m->red + 3 * kRed + 1, st));
+    IB_HIP(hipMemcpyAsync(m->host, m->red + 3 * kRed, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+    IB_HIP(hipStreamSynchronize(st));
+    return IB_OK;
+}
+
+static int remove_mean(mg_handle* m, bool sums_ready, hipStream_t st) {
+    Level& L = m->lv[0];
+    long N = L.d.cells();
+    int nb = red_blocks(N);
+    if (!sums_ready)
+        hipLaunchKernelGGL(k_sum_cells, dim3(nb), dim3(kBlock), 0, st, L.f64.p, N, m->red + 2 * kRed);
+    IB_TRY(device_sum(m->red + 2 * kRed, nb, m->red + 3 * kRed + 2, st));
+    hipLaunchKernelGGL(k_sub_scalar_mean, dim3(grid_for(N)), dim3(kBlock), 0, st, L.f64.p, N,
+                       m->red + 3 * kRed + 2);
+    IB_HIP(hipGetLastError());
+    return IB_OK;
+}
+
+}  // namespace ib
+
+using namespace ib;
+
+extern "C" int mg_setup(const ib_grid* g, const mg_opts* o, mg_handle** out) {
+    IB_CHECK(g && o && out, IB_EINVAL, "mg_setup: null argument");
+    IB_CHECK(g->dim == 2 || g->dim == 3, IB_EINVAL, "mg_setup: dim must be 2 or 3");
+    IB_CHECK(o->precision == MG_FP64 || o->precision == MG_MIXED, IB_EINVAL, "mg_setup: precision");
+    IB_CHECK(o->nu1 >= 0 && o->nu2 >= 0 && o->nu1 + o->nu2 > 0, IB_EINVAL, "mg_setup: sweeps");
+    IB_CHECK(o->n_coarsest >= 2, IB_EINVAL, "mg_setup: n_coarsest");
+    IB_CHECK(g->h > 0, IB_EINVAL, "mg_setup: h");
+    int nmin = g->n[0];
+    for (int e = 0; e < g->dim; ++e) {
+        IB_CHECK(g->n[e] >= 2, IB_EINVAL, "mg_setup: grid size");
+        nmin = std::min(nmin, g->n[e]);
+    }
+    int L = 0;
+    while ((nmin >> L) > o->n_coarsest) ++L;
+    IB_CHECK((nmin >> L) == o->n_coarsest && ((nmin >> L) << L) == nmin, IB_EINVAL,
+             "mg_setup: the smallest axis must be n_coarsest * 2^L");
+    long ncoarse = 1;
+    for (int e = 0; e < g->dim; ++e) {
+        IB_CHECK(((g->n[e] >> L) << L) == g->n[e], IB_EINVAL,
+                 "mg_setup: every axis must be divisible by 2^levels");
+        ncoarse *= (g->n[e] >> L);
+    }
+    IB_CHECK(ncoarse + 1 <= kMaxCoarse, IB_EINVAL, "mg_setup: coarsest grid larger than 64 cells");
+    mg_handle* m = new mg_handle();
+    m->g = *g;
+    m->o = *o;
+    m->nc = (int)ncoarse;
+    bool mixed = o->precision == MG_MIXED;
+    auto cleanup = [&](int code, const char* msg) {
+        mg_destroy(m);
+        return fail(code, msg);
+    };
+    for (int l = 0; l <= L; ++l) {
+        Level lv;
+        lv.d = make_dims(*g);
+        lv.d.nx = g->n[0] >> l;
+        lv.d.ny = g->n[1] >> l;
+        lv.d.nz = g->dim == 3 ? (g->n[2] >> l) : 1;
+        lv.d.h = g->h * (double)(1 << l);
+        long N = lv.d.cells();
+        lv.own_pb = l > 0;
+        if (l > 0) {
+            if (hipMalloc(&lv.f64.p, N * sizeof(double)) != hipSuccess ||
+                hipMalloc(&lv.f64.b, N * sizeof(double)) != hipSuccess)
+                return cleanup(IB_ENOMEM, "mg_setup: out of device memory");
+            for (int e = 0; e < g->dim; ++e)
+                if (hipMalloc(&lv.f64.beta[e], N * sizeof(double)) != hipSuccess)
+                    return cleanup(IB_ENOMEM, "mg_setup: out of device memory");
+        }
+        if (mixed) {
+            if (hipMalloc(&lv.f32.p, N * sizeof(float)) != hipSuccess ||
+                hipMalloc(&lv.f32.b, N * sizeof(float)) != hipSuccess)
+                return cleanup(IB_ENOMEM, "mg_setup: out of device memory");
+            for (int e = 0; e < g->dim; ++e)
+                if (hipMalloc(&lv.f32.beta[e], N * sizeof(float)) != hipSuccess)
+                    return cleanup(IB_ENOMEM, "mg_setup: out of device memory");
+        }
+        m->lv.push_back(lv);
+    }
+    int m1 = m->nc + 1;
+    if (hipMalloc(&m->cmat, sizeof(double) * m1 * m1) != hipSuccess ||
+        hipMalloc(&m->cinv, sizeof(double) * m1 * m1) != hipSuccess ||
+        hipMalloc(&m->red, sizeof(double) * (3 * kRed + 8)) != hipSuccess ||
+        hipHostMalloc(&m->host, sizeof(double) * 8) != hipSuccess)
+        return cleanup(IB_ENOMEM, "mg_setup: out of memory");
+    *out = m;
+    return IB_OK;
+}
+
+extern "C" void mg_destroy(mg_handle* m) {
+    if (!m) return;
+    for (auto& lv : m->lv) {
+        if (lv.own_pb) {
+            hipFree(lv.f64.p);
+            hipFree(lv.f64.b);
+            for (int e = 0; e < 3; ++e) hipFree(lv.f64.beta[e]);
+        }
+        hipFree(lv.f32.p);
+        hipFree(lv.f32.b);
+        for (int e = 0; e < 3; ++e) hipFree(lv.f32.beta[e]);
+    }
+    hipFree(m->cmat);
+    hipFree(m->cinv);
+    hipFree(m->red);
+    if (m->host) hipHostFree(m->host);
+    delete m;
+}
+
+extern "C" int mg_update_coeffs(mg_handle* m, const double* const beta[3], void* stream) {
+    IB_CHECK(m && beta, IB_EINVAL, "mg_update_coeffs: null argument");
+    hipStream_t st = (hipStream_t)stream;
+    int dim = m->g.dim;
+    for (int e = 0; e < dim; ++e) {
+        IB_CHECK(beta[e], IB_EINVAL, "mg_update_coeffs: null coefficient array");
+        m->lv[0].f64.beta[e] = const_cast<double*>(beta[e]);
+    }
+    for (size_t l = 1; l < m->lv.size(); ++l) {
+        Level& F = m->lv[l - 1];
+        Level& C = m->lv[l];
+        long nc = C.d.cells();
+        if (dim == 2)
+            hipLaunchKernelGGL(k_coarsen_beta<2>, dim3(grid_for(nc)), dim3(kBlock), 0, st,
+                               F.f64.beta[0], F.f64.beta[1], F.f64.beta[1], F.d, C.f64.beta[0],
+                               C.f64.beta[1], C.f64.beta[1]);
+        else
+            hipLaunchKernelGGL(k_coarsen_beta<3>, dim3(grid_for(nc)), dim3(kBlock), 0, st,
+                               F.f64.beta[0], F.f64.beta[1], F.f64.beta[2], F.d, C.f64.beta[0],
+                               C.f64.beta[1], C.f64.beta[2]);
+    }
+    if (m->o.precision == MG_MIXED)
+        for (auto& L : m->lv)
+            for (int e = 0; e < dim; ++e)
+                hipLaunchKernelGGL(k_cast_f32, dim3(grid_for(L.d.cells())), dim3(kBlock), 0, st,
+                                   L.f64.beta[e], L.f32.beta[e], L.d.cells());
+    Level& Cl = m->lv.back();
+    if (dim == 2)
+        hipLaunchKernelGGL(k_build_coarse<2>, dim3(1), dim3(128), 0, st, Cl.f64.beta[0],
+                           Cl.f64.beta[1], Cl.f64.beta[1], Cl.d, m->cmat);
+    else
+        hipLaunchKernelGGL(k_build_coarse<3>, dim3(1), dim3(128), 0, st, Cl.f64.beta[0],
+                           Cl.f64.beta[1], Cl.f64.beta[2], Cl.d, m->cmat);
+    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(256), 0, st, m->cmat, m->nc + 1, m->cinv,
+                       (int*)(m->red + 3 * kRed + 4));
+    IB_HIP(hipGetLastError());
+    m->coeffs_ready = true;
+    return IB_OK;
+}
+
+extern "C" int mg_solve(mg_handle* m, const double* b, double* p, double rtol, int max_cycles,
+                        int fixed_cycles, mg_stats* stats, void* stream) {
+    IB_CHECK(m && b && p, IB_EINVAL, "mg_solve: null argument");
+    IB_CHECK(m->coeffs_ready, IB_EINVAL, "mg_solve: call mg_update_coeffs first");
+    IB_CHECK(max_cycles >= 0 && fixed_cycles >= 0, IB_EINVAL, "mg_solve: cycle counts");
+    hipStream_t st = (hipStream_t)stream;
+    Level& L0 = m->lv[0];
+    L0.f64.p = p;
+    L0.f64.b = const_cast<double*>(b);
+    long N = L0.d.cells();
+    bool mixed = m->o.precision == MG_MIXED;
+    mg_stats loc;
+    mg_stats* S = stats ? stats : &loc;
+    S->cycles = 0;
+    if (mixed) IB_TRY(mixed_defect(m, true, st));
+    else IB_TRY(fp64_norms(m, true, st));
+    double bnorm = std::sqrt(m->host[1]);
+    if (!(bnorm > 0.0)) {
+        hipLaunchKernelGGL((k_fill<double>), dim3(grid_for(N)), dim3(kBlock), 0, st, p, N, 0.0);
+        S->rel_res0 = S->rel_res = 0.0;
+        IB_HIP(hipGetLastError());
+        return bnorm == 0.0 ? IB_OK : fail(IB_ENAN, "mg_solve: right side is not finite");
+    }
+    double rel = std::sqrt(m->host[0]) / bnorm;
+    S->rel_res0 = rel;
+    S->rel_res = rel;
+    int cycles = 0;
+    while (true) {
+        if (!std::isfinite(rel)) return fail(IB_ENAN, "mg_solve: residual is not finite");
+        if (fixed_cycles > 0 ? cycles >= fixed_cycles : rel <= rtol) break;
+        if (fixed_cycles == 0 && cycles >= max_cycles) {
+            S->cycles = cycles;
+            return fail(IB_ENOTCONV, "mg_solve: no convergence within max_cycles");
+        }
+        if (mixed) {
+            hipLaunchKernelGGL((k_fill<float>), dim3(grid_for(N)), dim3(kBlock), 0, st, L0.f32.p, N, 0.0f);
+            vcycle<float>(m, 0, st);
+            int nb = red_blocks(N);
+            hipLaunchKernelGGL(k_correct_f32, dim3(nb), dim3(kBlock), 0, st, p, L0.f32.p, N,
+                               m->red + 2 * kRed);
+            IB_TRY(remove_mean(m, true, st));
+            IB_TRY(mixed_defect(m, false, st));
+        } else {
+            vcycle<double>(m, 0, st);
+            IB_TRY(remove_mean(m, false, st));
+            IB_TRY(fp64_norms(m, false, st));
+        }
+        rel = std::sqrt(m->host[0]) / bnorm;
+        if (cycles < 128) S->res_hist[cycles] = rel;
+        ++cycles;
+        S->cycles = cycles;
+        S->rel_res = rel;
+    }
+    IB_HIP(hipGetLastError());
+    return IB_OK;
+}

@@ -1,0 +1,394 @@
+"""ctypes binding of ``libibproj.so`` (the C ABI in ``include/ibproj.h``).
+
+Argument marshalling only: device arrays are float64/int32 torch tensors on
+the current HIP device (contiguous), host arrays are numpy float64/int32, and
+every call is enqueued on ``torch.cuda.current_stream()``. All arithmetic
+runs in the library. Loading fails loudly when the library is missing: there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libibproj.so")
+
+IB_OK, IB_EINVAL, IB_EHIP, IB_ENOMEM, IB_ENOTCONV, IB_EGEOM, IB_ENAN = 0, -1, -2, -3, -4, -5, -6
+IB_SPREAD_IRROT, IB_SPREAD_DELTA = 0, 1
+MG_FP64, MG_MIXED = 0, 1
+WS_ZERO, WS_PREV = 0, 1
+
+EXPORTS = ("ib_create", "ib_destroy", "ib_bin_markers", "ib_interp", "ib_spread",
+           "ib_coefficients", "ib_rhs", "ib_update", "mg_setup", "mg_update_coeffs", "mg_solve",
+           "mg_destroy", "project_step", "ib_relocate_bspline", "ib_surface_geometry_3d",
+           "ib_diagnostics", "ib_last_error")
+
+
+class IbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double)]
+
+
+class Surface(C.Structure):
+    _fields_ = [("n_markers", C.c_int), ("X", C.c_void_p), ("n_elems", C.c_int),
+                ("elems", C.c_void_p), ("nrm", C.c_void_p), ("fs", C.c_void_p), ("ds", C.c_void_p)]
+
+
+class MgOpts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int), ("n_coarsest", C.c_int)]
+
+
+class MgStats(C.Structure):
+    _fields_ = [("cycles", C.c_int), ("rel_res0", C.c_double), ("rel_res", C.c_double),
+                ("res_hist", C.c_double * 128)]
+
+    def as_dict(self):
+        return dict(cycles=self.cycles, rel_res0=self.rel_res0, rel_res=self.rel_res,
+                    hist=list(self.res_hist[: min(self.cycles, 128)]))
+
+
+class Params(C.Structure):
+    _fields_ = [("rho_in", C.c_double), ("rho_out", C.c_double), ("sigma", C.c_double),
+                ("dt", C.c_double), ("rtol", C.c_double), ("max_cycles", C.c_int),
+                ("fixed_cycles", C.c_int), ("spread_mode", C.c_int), ("warm_start", C.c_int)]
+
+
+class State(C.Structure):
+    _fields_ = [("u_star", C.c_void_p * 3), ("p_prev", C.c_void_p), ("surf", Surface),
+                ("X_host", C.c_void_p)]
+
+
+class Outputs(C.Structure):
+    _fields_ = [("p", C.c_void_p), ("u", C.c_void_p * 3), ("U", C.c_void_p), ("H", C.c_void_p),
+                ("F", C.c_void_p * 3), ("fs_host", C.c_void_p), ("stats", MgStats)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("dP", C.c_double), ("tke", C.c_double), ("force_sum", C.c_double * 3),
+                ("curl_max", C.c_double), ("f_max", C.c_double)]
+
+    def as_dict(self):
+        return dict(dP=self.dP, tke=self.tke, force_sum=list(self.force_sum),
+                    curl_max=self.curl_max, f_max=self.f_max)
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (no GPU call is made here)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library not built: {path} (run python -m paper_1807_10504_amd.build)")
+    lib = C.CDLL(path)
+    vp, i32, f64 = C.c_void_p, C.c_int, C.c_double
+    P = C.POINTER
+    sig = {
+        "ib_create": (i32, [P(Grid), i32, i32, P(vp)]),
+        "ib_destroy": (None, [vp]),
+        "ib_bin_markers": (i32, [vp, P(Surface), vp, vp, vp, vp]),
+        "ib_interp": (i32, [vp, vp * 3, P(Surface), vp, vp]),
+        "ib_spread": (i32, [vp, P(Surface), i32, vp * 3, vp, vp]),
+        "ib_coefficients": (i32, [vp, vp, f64, f64, vp * 3, vp]),
+        "ib_rhs": (i32, [vp, vp * 3, vp * 3, vp * 3, f64, vp, vp]),
+        "ib_update": (i32, [vp, vp * 3, vp * 3, vp * 3, vp, f64, vp * 3, vp]),
+        "mg_setup": (i32, [P(Grid), P(MgOpts), P(vp)]),
+        "mg_update_coeffs": (i32, [vp, vp * 3, vp]),
+        "mg_solve": (i32, [vp, vp, vp, f64, i32, i32, P(MgStats), vp]),
+        "mg_destroy": (None, [vp]),
+        "project_step": (i32, [vp, vp, P(Params), P(State), P(Outputs), vp]),
+        "ib_relocate_bspline": (i32, [i32, vp, vp, f64, f64, f64, vp, vp, vp, vp]),
+        "ib_surface_geometry_3d": (i32, [i32, vp, i32, vp, f64, vp, vp, vp]),
+        "ib_diagnostics": (i32, [vp, vp, vp, vp * 3, vp * 3, P(Diag), vp]),
+        "ib_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != IB_OK:
+        msg = _lib.ib_last_error().decode()
+        raise IbError(rc, msg)
+
+
+# ----------------------------------------------------------------------------
+# marshalling helpers
+def _dptr(t, dtype=None):
+    import torch
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected dtype {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+def _hptr(a, dtype=np.float64):
+    if a is None:
+        return None
+    if not (isinstance(a, np.ndarray) and a.dtype == dtype and a.flags["C_CONTIGUOUS"]):
+        raise ValueError(f"expected a C-contiguous numpy {np.dtype(dtype)} array")
+    return a.ctypes.data
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _vec3(ts, dtype):
+    import torch
+    arr = (C.c_void_p * 3)()
+    for e, t in enumerate(ts):
+        arr[e] = _dptr(t, dtype)
+    return arr
+
+
+def make_grid(dim, n, h) -> Grid:
+    g = Grid()
+    g.dim = dim
+    for e in range(3):
+        g.n[e] = int(n[e]) if e < len(n) else 1
+    g.h = float(h)
+    return g
+
+
+def make_surface(X, elems=None, nrm=None, fs=None, ds=None) -> Surface:
+    import torch
+    s = Surface()
+    s.n_markers = int(X.shape[0])
+    s.X = _dptr(X, torch.float64)
+    s.n_elems = 0 if elems is None else int(elems.shape[0])
+    s.elems = _dptr(elems, torch.int32)
+    s.nrm = _dptr(nrm, torch.float64)
+    s.fs = _dptr(fs, torch.float64)
+    s.ds = _dptr(ds, torch.float64)
+    return s
+
+
+# ----------------------------------------------------------------------------
+class Context:
+    """Workspace for binning, spreading and projection steps on one grid."""
+
+    def __init__(self, dim, n, h, max_markers, max_elems=0):
+        import torch
+        self.lib = load()
+        self.dim, self.n, self.h = dim, tuple(n[:dim]), float(h)
+        self.grid = make_grid(dim, n, h)
+        self.ptr = C.c_void_p()
+        _check(self.lib.ib_create(C.byref(self.grid), int(max_markers), int(max_elems),
+                                  C.byref(self.ptr)))
+        self.shape = tuple(reversed(self.n))
+
+    def close(self):
+        if self.ptr:
+            self.lib.ib_destroy(self.ptr)
+            self.ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_tiles(self):
+        t = 1
+        for e in range(self.dim):
+            t *= self.n[e] // 4
+        return t
+
+    def bin_markers(self, surf: Surface):
+        import torch
+        n = surf.n_markers
+        key = torch.empty(n, dtype=torch.int32, device="cuda")
+        order = torch.empty(n, dtype=torch.int32, device="cuda")
+        start = torch.empty(self.n_tiles + 1, dtype=torch.int32, device="cuda")
+        _check(self.lib.ib_bin_markers(self.ptr, C.byref(surf), key.data_ptr(), order.data_ptr(),
+                                       start.data_ptr(), _stream()))
+        return key, order, start
+
+    def interp(self, u, surf: Surface, U=None):
+        import torch
+        if U is None:
+            U = torch.empty((surf.n_markers, self.dim), dtype=torch.float64, device="cuda")
+        _check(self.lib.ib_interp(self.ptr, _vec3(u, torch.float64), C.byref(surf),
+                                  _dptr(U, torch.float64), _stream()))
+        return U
+
+    def spread(self, surf: Surface, mode=IB_SPREAD_IRROT, F=None, H=None, want_H=True):
+        import torch
+        if F is None:
+            F = [torch.empty(self.shape, dtype=torch.float64, device="cuda") for _ in range(self.dim)]
+        if H is None and (want_H or mode == IB_SPREAD_IRROT):
+            H = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+        _check(self.lib.ib_spread(self.ptr, C.byref(surf), mode, _vec3(F, torch.float64),
+                                  _dptr(H, torch.float64), _stream()))
+        return F, H
+
+    def coefficients(self, H, rho_in, rho_out, beta=None):
+        import torch
+        if beta is None:
+            beta = [torch.empty(self.shape, dtype=torch.float64, device="cuda") for _ in range(self.dim)]
+        _check(self.lib.ib_coefficients(self.ptr, _dptr(H, torch.float64), rho_in, rho_out,
+                                        _vec3(beta, torch.float64), _stream()))
+        return beta
+
+    def rhs(self, u_star, F, beta, dt, b=None):
+        import torch
+        if b is None:
+            b = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+        _check(self.lib.ib_rhs(self.ptr, _vec3(u_star, torch.float64), _vec3(F, torch.float64),
+                               _vec3(beta, torch.float64), dt, _dptr(b, torch.float64), _stream()))
+        return b
+
+    def update(self, u_star, F, beta, p, dt, u_new=None):
+        import torch
+        if u_new is None:
+            u_new = [torch.empty(self.shape, dtype=torch.float64, device="cuda") for _ in range(self.dim)]
+        _check(self.lib.ib_update(self.ptr, _vec3(u_star, torch.float64), _vec3(F, torch.float64),
+                                  _vec3(beta, torch.float64), _dptr(p, torch.float64), dt,
+                                  _vec3(u_new, torch.float64), _stream()))
+        return u_new
+
+    def diagnostics(self, p=None, H=None, u=None, F=None):
+        import torch
+        d = Diag()
+        _check(self.lib.ib_diagnostics(self.ptr, _dptr(p, torch.float64), _dptr(H, torch.float64),
+                                       _vec3(u, torch.float64) if u is not None else None,
+                                       _vec3(F, torch.float64) if F is not None else None,
+                                       C.byref(d), _stream()))
+        return d.as_dict()
+
+    def project_step(self, mg: "Multigrid", params: dict, u_star, p_prev=None, surf=None,
+                     X_host=None, n_markers=None, out=None):
+        """One projection step. 2D: X_host (numpy, N x 2) is advanced and relocated in
+        place; 3D: surf is the static surface. Returns the outputs dict."""
+        import torch
+        prm = Params()
+        prm.rho_in = params["rho_in"]
+        prm.rho_out = params["rho_out"]
+        prm.sigma = params.get("sigma", 1.0)
+        prm.dt = params["dt"]
+        prm.rtol = params.get("rtol", 1e-10)
+        prm.max_cycles = params.get("max_cycles", 100)
+        prm.fixed_cycles = params.get("fixed_cycles", 0)
+        prm.spread_mode = params.get("spread_mode", IB_SPREAD_IRROT)
+        prm.warm_start = params.get("warm_start", WS_PREV if p_prev is not None else WS_ZERO)
+        st = State()
+        st.u_star = _vec3(u_star, torch.float64)
+        st.p_prev = _dptr(p_prev, torch.float64)
+        if self.dim == 2:
+            st.surf = Surface()
+            st.surf.n_markers = int(X_host.shape[0])
+            st.X_host = _hptr(X_host)
+            nm = int(X_host.shape[0])
+        else:
+            st.surf = surf
+            st.X_host = None
+            nm = surf.n_markers
+        if out is None:
+            out = {}
+        o = Outputs()
+        shape = self.shape
+        dev = "cuda"
+        out.setdefault("p", torch.empty(shape, dtype=torch.float64, device=dev))
+        out.setdefault("u", [torch.empty(shape, dtype=torch.float64, device=dev) for _ in range(self.dim)])
+        out.setdefault("U", torch.empty((nm, self.dim), dtype=torch.float64, device=dev))
+        o.p = _dptr(out["p"], torch.float64)
+        o.u = _vec3(out["u"], torch.float64)
+        o.U = _dptr(out["U"], torch.float64)
+        o.H = _dptr(out.get("H"), torch.float64)
+        o.F = _vec3(out["F"], torch.float64) if out.get("F") is not None else (C.c_void_p * 3)()
+        fs_host = out.get("fs_host")
+        o.fs_host = _hptr(fs_host) if fs_host is not None else None
+        rc = self.lib.project_step(self.ptr, mg.ptr, C.byref(prm), C.byref(st), C.byref(o), _stream())
+        out["stats"] = o.stats.as_dict()
+        if rc == IB_ENOTCONV and params.get("allow_notconv", False):
+            return out
+        _check(rc)
+        return out
+
+
+class Multigrid:
+    def __init__(self, dim, n, h, precision=MG_FP64, nu1=2, nu2=2, n_coarsest=4):
+        self.lib = load()
+        self.grid = make_grid(dim, n, h)
+        o = MgOpts()
+        o.precision, o.nu1, o.nu2, o.n_coarsest = precision, nu1, nu2, n_coarsest
+        self.opts = o
+        self.dim = dim
+        self.ptr = C.c_void_p()
+        _check(self.lib.mg_setup(C.byref(self.grid), C.byref(o), C.byref(self.ptr)))
+
+    def close(self):
+        if self.ptr:
+            self.lib.mg_destroy(self.ptr)
+            self.ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update_coeffs(self, beta):
+        import torch
+        self._beta = list(beta)  # keep the arrays alive while the handle refers to them
+        _check(self.lib.mg_update_coeffs(self.ptr, _vec3(beta, torch.float64), _stream()))
+
+    def solve(self, b, p, rtol=1e-10, max_cycles=100, fixed_cycles=0, allow_notconv=False):
+        import torch
+        st = MgStats()
+        rc = self.lib.mg_solve(self.ptr, _dptr(b, torch.float64), _dptr(p, torch.float64), rtol,
+                               max_cycles, fixed_cycles, C.byref(st), _stream())
+        if not (rc == IB_ENOTCONV and allow_notconv):
+            _check(rc)
+        return st.as_dict()
+
+
+# ----------------------------------------------------------------------------
+# host FP64 interface geometry
+def relocate_bspline(X, U, dt, h, sigma):
+    lib = load()
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    n = X.shape[0]
+    Xo = np.empty_like(X)
+    fs = np.empty(n)
+    ds = np.empty(n)
+    nrm = np.empty_like(X)
+    _check(lib.ib_relocate_bspline(n, _hptr(X), _hptr(U), dt, h, sigma, _hptr(Xo), _hptr(fs),
+                                   _hptr(ds), _hptr(nrm)))
+    return Xo, fs, ds, nrm
+
+
+def surface_geometry_3d(V, T, sigma):
+    lib = load()
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.int32)
+    nv = V.shape[0]
+    fs = np.empty(nv)
+    ds = np.empty(nv)
+    nrm = np.empty_like(V)
+    _check(lib.ib_surface_geometry_3d(nv, _hptr(V), T.shape[0], _hptr(T, np.int32), sigma,
+                                      _hptr(fs), _hptr(ds), _hptr(nrm)))
+    return fs, ds, nrm

@@ -1,0 +1,88 @@
+"""The C ABI library without a GPU: it loads, exports every declared entry
+point, rejects bad arguments before touching the device, and its host FP64
+geometry (B-spline relocation, sphere-mesh curvature) matches the oracle --
+bit for bit for the relocation, to rounding for the mesh geometry."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import bspline, surface3d
+from paper_1807_10504_amd import ibproj
+from paper_1807_10504_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "ibproj.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = set(re.findall(r"\b([a-z_0-9]+)\s*\(", txt))
+    return {n for n in names if n.startswith(("ib_", "mg_", "project_"))}
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ibproj.load()
+    decl = _declared()
+    assert len(decl) >= 17
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert set(ibproj.EXPORTS) == decl
+
+
+def test_invalid_arguments_rejected_without_device():
+    import ctypes as C
+    lib = ibproj.load()
+    g = ibproj.make_grid(5, (16, 16, 16), 1 / 16)
+    out = C.c_void_p()
+    assert lib.ib_create(C.byref(g), 100, 0, C.byref(out)) == ibproj.IB_EINVAL
+    assert b"dim" in lib.ib_last_error()
+    g = ibproj.make_grid(2, (24, 20, 1), 1 / 16)
+    o = ibproj.MgOpts(0, 2, 2, 4)
+    assert lib.mg_setup(C.byref(g), C.byref(o), C.byref(out)) == ibproj.IB_EINVAL
+    g = ibproj.make_grid(2, (64, 64, 1), 1 / 64)
+    o = ibproj.MgOpts(7, 2, 2, 4)
+    assert lib.mg_setup(C.byref(g), C.byref(o), C.byref(out)) == ibproj.IB_EINVAL
+
+
+@pytest.mark.parametrize("case", ["c1_static", "c1_moving", "c2_jitter", "interpol_cir", "mode2"])
+def test_bspline_relocation_bit_exact(case):
+    if case == "c1_static":
+        X, h, dt = W.circle_markers(128, 0.25), 1 / 64, 1e-4
+        U = np.zeros_like(X)
+    elif case == "c1_moving":
+        X, h, dt = W.circle_markers(128, 0.25), 1 / 64, 1e-3
+        U = np.random.default_rng(5).standard_normal(X.shape) * 0.3
+    elif case == "c2_jitter":
+        X, h, dt = W.jittered_circle(1024, 0.2, 1e-3, seed=2), 1 / 512, 2e-5
+        U = np.zeros_like(X)
+    elif case == "interpol_cir":
+        X, h, dt = W.perturbed_circle(126, 1e-3), 1 / 32, 0.0
+        U = np.zeros_like(X)
+    else:
+        X, h, dt = W.mode_shape(256, 0.2, 0.1), 1 / 128, 1e-4
+        U = np.random.default_rng(7).standard_normal(X.shape)
+    Xo, fs, ds, nrm = ibproj.relocate_bspline(X, U, dt, h, 1.0)
+    Xr, fr, dr, nr = bspline.relocate([tuple(x) for x in X], [tuple(u) for u in U], dt, h, 1.0)
+    assert np.array_equal(Xo, np.array(Xr))
+    assert np.array_equal(fs, np.array(fr))
+    assert np.array_equal(ds, np.array(dr))
+    assert np.array_equal(nrm, np.array(nr))
+
+
+def test_bspline_relocation_reports_schoenberg_whitney():
+    X = W.circle_markers(20, 0.3)
+    with pytest.raises(ibproj.IbError) as e:
+        ibproj.relocate_bspline(X, np.zeros_like(X), 0.0, 1 / 256, 1.0)
+    assert e.value.code == ibproj.IB_EGEOM
+
+
+@pytest.mark.parametrize("level", [2, 4])
+def test_surface_geometry_3d_matches_oracle(level):
+    V, T = W.sphere_mesh(level, 0.25, seed=3)
+    fs, ds, nrm = ibproj.surface_geometry_3d(V, T, 1.0)
+    fo, Ao, no, _ = surface3d.surface_geometry(V, T, 1.0)
+    assert np.max(np.abs(fs - fo)) <= 1e-12 * np.max(np.abs(fo))
+    assert np.max(np.abs(ds - Ao)) <= 1e-14 * np.max(Ao)
+    assert np.max(np.abs(nrm - no)) <= 1e-13

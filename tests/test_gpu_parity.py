@@ -1,0 +1,398 @@
+"""GPU parity: every step of the projection through the C ABI against the CPU
+oracle, on the same seeded inputs, at sizes that span several tiles and the
+periodic seam. Tolerances (FP64 everywhere):
+
+* binning: bit-exact (integer work);
+* interpolation, conventional spread, Heaviside, face force, coefficients,
+  right side, update: agreement to a few ulps of the field scale (1e-13
+  relative) -- the two sides only differ in summation order and contraction;
+* multigrid at an equal number of cycles of the mirrored algorithm: p within
+  1e-11 relative L2 (observed ~1e-14); converged solves within what the
+  stopping test allows;
+* whole projection step: p and u within 1e-11 relative L2, u normalised by
+  max(||u||, dt ||beta F||) because a static drop leaves u near zero.
+"""
+import numpy as np
+import pytest
+
+from oracle import binning, diag, force, heaviside, poisson, step, surface3d, transfer
+from paper_1807_10504_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def dev(a, dtype=None):
+    a = np.ascontiguousarray(a)
+    t = torch.from_numpy(a)
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def ib():
+    from paper_1807_10504_amd import ibproj
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    ibproj.load()
+    return ibproj
+
+
+def _surface2d(ib, X, fs=None, ds=None):
+    Xd = dev(X)
+    fsd = dev(fs) if fs is not None else None
+    dsd = dev(ds) if ds is not None else None
+    keep = [Xd, fsd, dsd]
+    return ib.make_surface(Xd, fs=fsd, ds=dsd), keep
+
+
+def _surface3d(ib, V, T, sigma=1.0):
+    fs, ds, nrm = ib.surface_geometry_3d(V, T, sigma)
+    Vd, Td, fsd, dsd, nd = dev(V), dev(T.astype(np.int32)), dev(fs), dev(ds), dev(nrm)
+    return ib.make_surface(Vd, elems=Td, nrm=nd, fs=fsd, ds=dsd), [Vd, Td, fsd, dsd, nd], fs, ds, nrm
+
+
+# ----------------------------------------------------------------------------
+# a1 binning
+@pytest.mark.parametrize("dim", [2, 3])
+def test_binning_bit_exact(ib, dim):
+    n = (64, 64) if dim == 2 else (32, 32, 32)
+    h = 1.0 / n[0]
+    rng = np.random.default_rng(17)
+    X = rng.uniform(0.0, 1.0, size=(3000, dim))
+    X[:50] = X[:50] * 0.01 + 0.995  # crowd one tile at the seam
+    X[50:60, 0] = 1.0 - 1e-17        # rounds into the last cell
+    ctx = ib.Context(dim, n, h, max_markers=4000)
+    surf, keep = ib.make_surface(dev(X)), None
+    Xd = dev(X)
+    surf = ib.make_surface(Xd)
+    key, order, start = ctx.bin_markers(surf)
+    k0, o0, s0 = binning.bin_markers(X, n, h)
+    assert np.array_equal(host(key), k0)
+    assert np.array_equal(host(order), o0)
+    assert np.array_equal(host(start), s0)
+
+
+# ----------------------------------------------------------------------------
+# a2 interpolation
+@pytest.mark.parametrize("dim", [2, 3])
+def test_interp_parity(ib, dim):
+    n = (64, 64) if dim == 2 else (32, 48, 32)
+    h = 1.0 / n[0]
+    rng = np.random.default_rng(23)
+    L = np.array(n[:dim]) * h
+    X = rng.uniform(0.0, 1.0, size=(777, dim)) * L
+    X[0, 0] = 1e-3
+    X[1, 1] = L[1] - 2e-3
+    u = W.random_faces(n, dim, 1.0, seed=29)
+    ctx = ib.Context(dim, n, h, max_markers=1000)
+    Xd = dev(X)
+    U = host(ctx.interp([dev(c) for c in u], ib.make_surface(Xd)))
+    Uo = transfer.interp(u, X, h)
+    assert np.max(np.abs(U - Uo)) <= 1e-14 * np.max(np.abs(u[0])) * 8
+
+
+# ----------------------------------------------------------------------------
+# a5 conventional spreading
+def test_spread_delta_parity_2d(ib):
+    wl = W.static_drop_2d_64()
+    X = wl.X
+    N = len(X)
+    rng = np.random.default_rng(3)
+    fs = 4.0 + 0.1 * rng.standard_normal(N)
+    ds = np.full(N, 2 * np.pi * 0.25 / N)
+    ctx = ib.Context(2, wl.n, wl.h, max_markers=N)
+    surf, keep = _surface2d(ib, X, fs, ds)
+    F, H = ctx.spread(surf, ib.IB_SPREAD_DELTA, want_H=False)
+    Fo = transfer.spread_delta(transfer.marker_forces(fs, ds, transfer.marker_normals_2d(X)), X, wl.n, wl.h)
+    for d in range(2):
+        assert np.max(np.abs(host(F[d]) - Fo[d])) <= 1e-13 * np.max(np.abs(Fo[d]))
+
+
+def test_spread_delta_parity_3d(ib):
+    V, T = W.sphere_mesh(2, 0.25, seed=3)
+    n = (32, 32, 32)
+    h = 1.0 / 32
+    ctx = ib.Context(3, n, h, max_markers=len(V), max_elems=len(T))
+    surf, keep, fs, ds, nrm = _surface3d(ib, V, T)
+    F, _ = ctx.spread(surf, ib.IB_SPREAD_DELTA, want_H=False)
+    fo, Ao, no, _ = surface3d.surface_geometry(V, T, 1.0)
+    Fo = transfer.spread_delta(transfer.marker_forces(fo, Ao, no), V, n, h)
+    for d in range(3):
+        assert np.max(np.abs(host(F[d]) - Fo[d])) <= 1e-12 * np.max(np.abs(Fo[d]))
+
+
+# ----------------------------------------------------------------------------
+# a4 Heaviside and a5 irrotational force
+@pytest.mark.parametrize("which", ["c1", "c2"])
+def test_heaviside_and_force_parity_2d(ib, which):
+    wl = W.static_drop_2d_64() if which == "c1" else W.static_drop_2d_512()
+    X, fs, ds, nrm = ib.relocate_bspline(wl.X, np.zeros_like(wl.X), 0.0, wl.h, 1.0)
+    ctx = ib.Context(2, wl.n, wl.h, max_markers=len(X))
+    surf, keep = _surface2d(ib, X, fs, ds)
+    F, H = ctx.spread(surf, ib.IB_SPREAD_IRROT)
+    Ho = heaviside.heaviside_2d(X, wl.n, wl.h)
+    Hg = host(H)
+    assert np.max(np.abs(Hg - Ho)) <= 1e-13
+    Fo = force.irrotational_force(Ho, X, fs, wl.h)
+    fmax = max(np.abs(f).max() for f in Fo)
+    for d in range(2):
+        assert np.max(np.abs(host(F[d]) - Fo[d])) <= 1e-12 * fmax
+    # same faces carry force on both sides
+    for d in range(2):
+        assert np.array_equal(host(F[d]) != 0.0, Fo[d] != 0.0)
+
+
+def test_heaviside_and_force_parity_3d(ib):
+    V, T = W.sphere_mesh(3, 0.25, seed=3)
+    n = (32, 32, 32)
+    h = 1.0 / 32
+    ctx = ib.Context(3, n, h, max_markers=len(V), max_elems=len(T))
+    surf, keep, fs, ds, nrm = _surface3d(ib, V, T)
+    F, H = ctx.spread(surf, ib.IB_SPREAD_IRROT)
+    fo, Ao, no, _ = surface3d.surface_geometry(V, T, 1.0)
+    Ho = heaviside.heaviside_3d(V, T, n, h, nrm=no)
+    assert np.max(np.abs(host(H) - Ho)) <= 1e-13
+    Fo = force.irrotational_force(Ho, V, fo, h, T)
+    fmax = max(np.abs(f).max() for f in Fo)
+    for d in range(3):
+        assert np.max(np.abs(host(F[d]) - Fo[d])) <= 1e-11 * fmax
+
+
+def test_spread_is_deterministic(ib):
+    V, T = W.sphere_mesh(3, 0.25, seed=3)
+    n = (32, 32, 32)
+    ctx = ib.Context(3, n, 1 / 32, max_markers=len(V), max_elems=len(T))
+    surf, keep, *_ = _surface3d(ib, V, T)
+    F1, H1 = ctx.spread(surf, ib.IB_SPREAD_IRROT)
+    F2, H2 = ctx.spread(surf, ib.IB_SPREAD_IRROT)
+    assert torch.equal(H1, H2)
+    for d in range(3):
+        assert torch.equal(F1[d], F2[d])
+    G1, _ = ctx.spread(surf, ib.IB_SPREAD_DELTA, want_H=False)
+    G2, _ = ctx.spread(surf, ib.IB_SPREAD_DELTA, want_H=False)
+    for d in range(3):
+        assert torch.equal(G1[d], G2[d])
+
+
+def test_curl_free_and_total_force_on_gpu(ib):
+    """Section 3.2 identity on the GPU output: constant f gives an index-form
+    curl of zero to rounding; the grid total of F vanishes."""
+    n, h = (64, 64), 1 / 64
+    X = W.circle_markers(200, 0.2)
+    N = len(X)
+    ctx = ib.Context(2, n, h, max_markers=N)
+    surf, keep = _surface2d(ib, X, np.ones(N), np.full(N, 2 * np.pi * 0.2 / N))
+    F, H = ctx.spread(surf, ib.IB_SPREAD_IRROT)
+    d = ctx.diagnostics(F=F)
+    assert d["curl_max"] <= 1e-12 * d["f_max"]
+    assert max(abs(x) for x in d["force_sum"][:2]) <= 1e-12 * d["f_max"]
+    Fc, _ = ctx.spread(surf, ib.IB_SPREAD_DELTA, want_H=False)
+    dc = ctx.diagnostics(F=Fc)
+    assert dc["curl_max"] > 1e-3 * dc["f_max"]
+
+
+# ----------------------------------------------------------------------------
+# a6 coefficients, a7 right side, a11 update
+@pytest.mark.parametrize("dim", [2, 3])
+def test_coefficients_rhs_update_parity(ib, dim):
+    n = (64, 64) if dim == 2 else (32, 32, 32)
+    h = 1.0 / n[0]
+    shape = tuple(reversed(n))
+    rng = np.random.default_rng(41)
+    H = np.clip(rng.uniform(-0.2, 1.2, size=shape), 0.0, 1.0)
+    us = W.random_faces(n, dim, 1.0, seed=42)
+    F = W.random_faces(n, dim, 10.0, seed=43)
+    p = W.random_cells(n, dim, 1.0, seed=44)
+    dt = 1e-4
+    ctx = ib.Context(dim, n, h, max_markers=16)
+    beta = ctx.coefficients(dev(H), 1.0, 1e-3)
+    bo = poisson.face_beta(poisson.density(H, 1.0, 1e-3))
+    for d in range(dim):
+        assert np.max(np.abs(host(beta[d]) - bo[d])) <= 1e-15 * np.max(bo[d])
+    b = ctx.rhs([dev(c) for c in us], [dev(c) for c in F], [dev(c) for c in bo], dt)
+    b_o = poisson.rhs(us, F, bo, dt, h)
+    assert rel_l2(host(b), b_o) <= 1e-14
+    un = ctx.update([dev(c) for c in us], [dev(c) for c in F], [dev(c) for c in bo], dev(p), dt)
+    uo = poisson.velocity_update(us, F, bo, p, dt, h)
+    for d in range(dim):
+        assert rel_l2(host(un[d]), uo[d]) <= 1e-15 * 10
+
+
+# ----------------------------------------------------------------------------
+# a8, a9 multigrid
+def _drop_beta(shape, ratio=1000.0):
+    dim = len(shape)
+    g = np.indices(shape)
+    r2 = sum(((g[a] + 0.5) / shape[a] - 0.5) ** 2 for a in range(dim))
+    H = (r2 < 0.3 ** 2).astype(float)
+    return poisson.face_beta(poisson.density(H, 1.0, 1.0 / ratio))
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (32, 32, 32), (64, 128)])
+def test_mg_fixed_cycles_parity(ib, shape):
+    dim = len(shape)
+    n = tuple(reversed(shape))
+    h = 1.0 / 64 if dim == 2 else 1.0 / 32
+    beta = _drop_beta(shape)
+    b = W.random_cells(n, dim, 1.0, seed=51)
+    b -= b.mean()
+    mg = ib.Multigrid(dim, n, h)
+    bd = [dev(x) for x in beta]
+    mg.update_coeffs(bd)
+    p = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    st = mg.solve(dev(b), p, fixed_cycles=6)
+    po, cyc, hist = poisson.mg_solve(b, beta, h, fixed_cycles=6)
+    assert st["cycles"] == 6
+    assert rel_l2(host(p), po) <= 1e-11
+    assert abs(st["rel_res"] - hist[-1]) <= 1e-6 * hist[-1]
+
+
+def test_mg_converged_vs_dense(ib):
+    shape = (16, 16)
+    beta = _drop_beta(shape)
+    b = W.random_cells((16, 16), 2, 1.0, seed=52)
+    b -= b.mean()
+    mg = ib.Multigrid(2, (16, 16), 1 / 16)
+    mg.update_coeffs([dev(x) for x in beta])
+    p = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    st = mg.solve(dev(b), p, rtol=1e-13)
+    pd = poisson.direct_solve(b, beta, 1 / 16)
+    assert st["rel_res"] <= 1e-13
+    assert np.max(np.abs(host(p) - pd)) <= 1e-10 * np.max(np.abs(pd))
+
+
+@pytest.mark.parametrize("shape", [(128, 128), (32, 32, 32)])
+def test_mg_mixed_converges_and_error_vs_fp64(ib, shape):
+    dim = len(shape)
+    n = tuple(reversed(shape))
+    h = 1.0 / shape[0]
+    beta = _drop_beta(shape)
+    b = W.random_cells(n, dim, 1.0, seed=53)
+    b -= b.mean()
+    mg = ib.Multigrid(dim, n, h, precision=ib.MG_MIXED)
+    mg.update_coeffs([dev(x) for x in beta])
+    p = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    st = mg.solve(dev(b), p, rtol=1e-10)
+    assert st["rel_res"] <= 1e-10
+    pt, _, _ = poisson.mg_solve(b, beta, h, rtol=1e-14, max_cycles=200)
+    err = rel_l2(host(p), pt)
+    # the 1e-10 residual bound leaves an error of order cond * 1e-10 in p
+    assert err <= 1e-7
+    print(f"mixed {shape}: cycles={st['cycles']} rel_res={st['rel_res']:.2e} err_vs_fp64_oracle={err:.2e}")
+
+
+def test_mg_not_converged_reports(ib):
+    shape = (64, 64)
+    beta = _drop_beta(shape)
+    b = W.random_cells((64, 64), 2, 1.0, seed=54)
+    b -= b.mean()
+    mg = ib.Multigrid(2, (64, 64), 1 / 64)
+    mg.update_coeffs([dev(x) for x in beta])
+    p = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(ib.IbError) as e:
+        mg.solve(dev(b), p, rtol=1e-10, max_cycles=1)
+    assert e.value.code == ib.IB_ENOTCONV
+
+
+# ----------------------------------------------------------------------------
+# the whole step
+def _u_tol(u_o, F_o, beta_o, dt):
+    s = np.sqrt(sum(np.sum(c * c) for c in u_o))
+    f = np.sqrt(sum(np.sum((dt * beta_o[d] * F_o[d]) ** 2) for d in range(len(u_o))))
+    return max(s, f)
+
+
+@pytest.mark.parametrize("mode", ["irrot", "delta"])
+def test_project_step_2d_c1_parity(ib, mode):
+    """64^2 static drop, 128 markers, rho ratio 1000: 10 chained steps on each side."""
+    wl = W.static_drop_2d_64()
+    dim, n, h = 2, wl.n, wl.h
+    shape = tuple(reversed(n))
+    ctx = ib.Context(dim, n, h, max_markers=len(wl.X))
+    mg = ib.Multigrid(dim, n, h)
+    Xg = wl.X.copy()
+    Xo = wl.X.copy()
+    ug = [torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(dim)]
+    uo = [np.zeros(shape) for _ in range(dim)]
+    pg, po = None, None
+    params = dict(rho_in=wl.rho_in, rho_out=wl.rho_out, sigma=wl.sigma, dt=wl.dt, rtol=1e-10,
+                  spread_mode=ib.IB_SPREAD_IRROT if mode == "irrot" else ib.IB_SPREAD_DELTA)
+    for s in range(wl.steps):
+        out = dict(F=[torch.empty(shape, dtype=torch.float64, device="cuda") for _ in range(dim)],
+                   H=torch.empty(shape, dtype=torch.float64, device="cuda"))
+        out = ctx.project_step(mg, params, ug, p_prev=pg, X_host=Xg, out=out)
+        cyc = out["stats"]["cycles"]
+        ro = step.project_step(dim, n, h, wl.rho_in, wl.rho_out, wl.sigma, wl.dt, uo, Xo, p_prev=po,
+                               mode=mode, fixed_cycles=cyc)
+        assert ro["hist"][-1] <= 1e-10 * 1.5
+        assert np.max(np.abs(Xg - ro["X"])) <= 1e-14
+        assert rel_l2(host(out["p"]), ro["p"]) <= 1e-11
+        tol = _u_tol(ro["u"], ro["F"], ro["beta"], wl.dt)
+        du = np.sqrt(sum(np.sum((host(out["u"][d]) - ro["u"][d]) ** 2) for d in range(dim)))
+        assert du <= 1e-11 * tol
+        ug, pg = out["u"], out["p"]
+        uo, po, Xo = ro["u"], ro["p"], ro["X"]
+    if mode == "irrot":
+        d = ctx.diagnostics(p=pg, H=out["H"], u=ug, F=out["F"])
+        assert abs(d["dP"] - 4.0) < 4e-3 * 4
+        assert abs(d["dP"] - diag.pressure_jump(po, ro["H"])) <= 1e-9
+
+
+def test_project_step_3d_parity(ib):
+    V, T = W.sphere_mesh(3, 0.25, seed=3)
+    dim, n, h = 3, (32, 32, 32), 1.0 / 32
+    shape = tuple(reversed(n))
+    ctx = ib.Context(dim, n, h, max_markers=len(V), max_elems=len(T))
+    mg = ib.Multigrid(dim, n, h)
+    surf, keep, fs, ds, nrm = _surface3d(ib, V, T)
+    fo, Ao, no, _ = surface3d.surface_geometry(V, T, 1.0)
+    ug = [torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(dim)]
+    uo = [np.zeros(shape) for _ in range(dim)]
+    pg, po = None, None
+    params = dict(rho_in=1.0, rho_out=1e-3, sigma=1.0, dt=5e-5, rtol=1e-10)
+    for s in range(2):
+        out = dict(H=torch.empty(shape, dtype=torch.float64, device="cuda"))
+        out = ctx.project_step(mg, params, ug, p_prev=pg, surf=surf, out=out)
+        cyc = out["stats"]["cycles"]
+        ro = step.project_step(dim, n, h, 1.0, 1e-3, 1.0, 5e-5, uo, V, tris=T, p_prev=po,
+                               fixed_cycles=cyc, surface=(V, fo, Ao, no))
+        assert rel_l2(host(out["p"]), ro["p"]) <= 1e-11
+        tol = _u_tol(ro["u"], ro["F"], ro["beta"], 5e-5)
+        du = np.sqrt(sum(np.sum((host(out["u"][d]) - ro["u"][d]) ** 2) for d in range(dim)))
+        assert du <= 1e-11 * tol
+        assert np.max(np.abs(host(out["U"]) - ro["U"])) <= 1e-14 + 1e-12 * np.max(np.abs(ro["U"]))
+        ug, pg, uo, po = out["u"], out["p"], ro["u"], ro["p"]
+    d = ctx.diagnostics(p=pg, H=out["H"])
+    assert abs(d["dP"] - 8.0) < 0.02 * 8
+
+
+def test_geometry_errors(ib):
+    n, h = (64, 64), 1 / 64
+    X = W.circle_markers(64, 0.45)   # offsets reach the box faces
+    N = len(X)
+    ctx = ib.Context(2, n, h, max_markers=N)
+    surf, keep = _surface2d(ib, X, np.ones(N), np.ones(N))
+    with pytest.raises(ib.IbError) as e:
+        ctx.spread(surf, ib.IB_SPREAD_IRROT)
+    assert e.value.code == ib.IB_EGEOM
+    V, T = W.sphere_mesh(1, 0.25, seed=3)
+    T = T.copy()
+    T[3, 1] = len(V) + 5
+    ctx3 = ib.Context(3, (32, 32, 32), 1 / 32, max_markers=len(V), max_elems=len(T))
+    fs = np.ones(len(V))
+    nrm = (np.array([0.5, 0.5, 0.5]) - V) / 0.25
+    Vd, Td, fd, nd = dev(V), dev(T.astype(np.int32)), dev(fs), dev(nrm)
+    s3 = ib.make_surface(Vd, elems=Td, nrm=nd, fs=fd, ds=fd)
+    with pytest.raises(ib.IbError) as e:
+        ctx3.spread(s3, ib.IB_SPREAD_IRROT)
+    assert e.value.code == ib.IB_EINVAL
