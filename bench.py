@@ -1,0 +1,251 @@
+"""Projection-step throughput on one MI355X.
+
+Workload (the headline configuration): static spherical drop in a 256^3
+periodic unit box, sphere R = 0.25 from a level-6 icosphere (40,962 markers,
+81,920 triangles) under a seeded rotation, density ratio 1000, sigma = 1,
+dt = 5e-5, multigrid to ||r||/||b|| <= 1e-10. A step is one full pass of the
+hot path through the C ABI (project_step): interpolation, spreading with the
+irrotational delta vector (offset-polyhedron Heaviside + face force),
+coefficients, right side, multigrid solve warm-started from the previous
+pressure, velocity update; the next step starts from the updated velocity.
+
+Every step solves from p = 0 ("cold"): a static drop warm-started from the
+previous pressure already meets the 1e-10 test after the first step, so a
+warm-started step would measure no multigrid at all. The warm-started
+variant is reported beside it.
+
+Variants: plain FP64 multigrid (the JSON `value`), float32 V-cycles inside
+FP64 defect correction (same stopping test), each cold and warm.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "projection steps/s @256³, ρ ratio 1000, resid≤1e-10; FP64 vs mixed+NN"
+HBM_PEAK_GBS = 8000.0
+# one red-black sweep reads p, b and three face coefficients and writes p:
+# 6 x 8 bytes per cell (float64); one launch updates one colour = half a sweep
+SWEEP_BYTES_F64 = 48.0
+SWEEP_BYTES_F32 = 24.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_variant(ib, torch, wl, geo, precision, steps, warmup, profile, warm=False):
+    n, h = wl.n, wl.h
+    shape = tuple(reversed(n))
+    V, T = wl.X, wl.tris
+    fs, ds, nrm = geo
+    Vd = torch.from_numpy(V).cuda()
+    Td = torch.from_numpy(T.astype(np.int32)).cuda()
+    fsd, dsd, nd = (torch.from_numpy(a).cuda() for a in (fs, ds, nrm))
+    surf = ib.make_surface(Vd, elems=Td, nrm=nd, fs=fsd, ds=dsd)
+    ctx = ib.Context(3, n, h, max_markers=len(V), max_elems=len(T))
+    mg = ib.Multigrid(3, n, h, precision=precision)
+    params = dict(rho_in=wl.rho_in, rho_out=wl.rho_out, sigma=wl.sigma, dt=wl.dt, rtol=1e-10,
+                  max_cycles=100, warm_start=ib.WS_PREV if warm else ib.WS_ZERO)
+    u = [torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+    bufs = [dict(p=torch.empty(shape, dtype=torch.float64, device="cuda"),
+                 u=[torch.empty(shape, dtype=torch.float64, device="cuda") for _ in range(3)],
+                 U=torch.empty((len(V), 3), dtype=torch.float64, device="cuda"))
+            for _ in range(2)]
+    p_prev = None
+    cycles = []
+    res = []
+    first = None
+
+    def one(k):
+        nonlocal u, p_prev
+        out = bufs[k % 2]
+        out = ctx.project_step(mg, params, u, p_prev=p_prev, surf=surf, out=out)
+        u, p_prev = out["u"], out["p"]
+        return out["stats"]
+
+    for k in range(warmup):
+        st = one(k)
+        if first is None:
+            first = st
+    torch.cuda.synchronize()
+    if profile:
+        ib.profile_reset()
+        ib.profile_enable(True)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        st = one(warmup + k)
+        cycles.append(st["cycles"])
+        res.append(st["rel_res"])
+        if (k + 1) % max(1, steps // 4) == 0:
+            log(f"  step {k + 1}/{steps}: cycles={st['cycles']} rel_res={st['rel_res']:.2e}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = None
+    if profile:
+        ib.profile_enable(False)
+        prof = ib.profile_read()
+    d = ctx.diagnostics(p=p_prev, u=u)
+    ctx.close()
+    mg.close()
+    return dict(seconds=t1 - t0, steps=steps, cycles=cycles, rel_res=res, first=first, prof=prof,
+                dP=d["dP"], tke=d["tke"])
+
+
+def cpu_baseline(wl, cycles_per_step):
+    """The oracle on a bounded sample of the same 256^3 step, extrapolated to one step."""
+    from oracle import heaviside, poisson
+    n, h = wl.n, wl.h
+    shape = tuple(reversed(n))
+    rng = np.random.default_rng(1)
+    t = {}
+    # multigrid: one FP64 V-cycle at full size
+    H = np.zeros(shape)
+    g = np.indices(shape, sparse=True)
+    r2 = sum(((g[a] + 0.5) * h - 0.5) ** 2 for a in range(3))
+    H[r2 < 0.25 ** 2] = 1.0
+    beta = poisson.face_beta(poisson.density(H, wl.rho_in, wl.rho_out))
+    b = rng.standard_normal(shape)
+    b -= b.mean()
+    t0 = time.perf_counter()
+    hier = poisson.Hierarchy(beta, h)
+    t["setup"] = time.perf_counter() - t0
+    p = np.zeros(shape)
+    t0 = time.perf_counter()
+    p = poisson.vcycle(hier, 0, p, b)
+    t["vcycle"] = time.perf_counter() - t0
+    # coefficients, right side, update at full size
+    F = [np.zeros(shape) for _ in range(3)]
+    u = [np.zeros(shape) for _ in range(3)]
+    t0 = time.perf_counter()
+    beta = poisson.face_beta(poisson.density(H, wl.rho_in, wl.rho_out))
+    b = poisson.rhs(u, F, beta, wl.dt, h)
+    poisson.velocity_update(u, F, beta, p, wl.dt, h)
+    t["grid_ops"] = time.perf_counter() - t0
+    # Heaviside on a sample of columns, scaled by the number of columns the
+    # surface projects onto
+    V, T = wl.X, wl.tris
+    nrm = heaviside.vertex_normals(V, T)  # static surface: computed once, not timed
+    cols = []
+    for k in range(24):
+        i = int(rng.integers(int(0.25 / h) + 2, int(0.75 / h) - 2))
+        j = int(rng.integers(int(0.25 / h) + 2, int(0.75 / h) - 2))
+        cols.append((i, j))
+    t0 = time.perf_counter()
+    heaviside.heaviside_3d(V, T, n, h, nrm=nrm, columns=cols)
+    tH = time.perf_counter() - t0
+    ncols = math.pi * (0.25 + 2 * h) ** 2 / h ** 2
+    t["heaviside"] = tH / len(cols) * ncols
+    per_step = t["grid_ops"] + t["heaviside"] + cycles_per_step * t["vcycle"]
+    sample = (f"256^3 oracle: one FP64 V-cycle ({t['vcycle']:.1f} s) x {cycles_per_step:.1f} cycles/step, "
+              f"coefficients+rhs+update ({t['grid_ops']:.1f} s), Heaviside on {len(cols)} columns scaled to "
+              f"{ncols:.0f} columns ({t['heaviside']:.0f} s); nearest-element face force not included")
+    return dict(value=1.0 / per_step, unit="steps/s", cores=1, kind="oracle", sample=sample,
+                seconds_per_step=per_step, breakdown={k: round(v, 2) for k, v in t.items()})
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--level", type=int, default=6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-warm", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MB (PMC byte-counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is described, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1807_10504_amd import ibproj as ib
+    from paper_1807_10504_amd import workloads as W
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    ib.load()
+    wl = W.static_drop_3d(args.size, args.level, seed=3)
+    log(f"workload {wl.name}: {len(wl.X)} markers, {len(wl.tris)} triangles")
+    geo = ib.surface_geometry_3d(wl.X, wl.tris, wl.sigma)
+    if args.copy_mb:
+        a = torch.ones(args.copy_mb * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        del a, c
+
+    def summary(r, ref=None):
+        sps = r["steps"] / r["seconds"]
+        out = dict(steps_per_s=round(sps, 3), ms_per_step=round(1e3 * r["seconds"] / r["steps"], 3),
+                   mean_cycles=float(np.mean(r["cycles"])), max_rel_res=float(np.max(r["rel_res"])),
+                   dP=r["dP"])
+        if ref is not None:
+            out["speedup_vs_fp64_cold"] = round(sps / ref, 3)
+        return out
+
+    log("== FP64 multigrid, cold start every step")
+    r64 = run_variant(ib, torch, wl, geo, ib.MG_FP64, args.steps, args.warmup, profile=True)
+    sps64 = r64["steps"] / r64["seconds"]
+    variants = {"fp64_cold": summary(r64)}
+    if not args.no_mixed:
+        log("== mixed FP32/FP64 multigrid, cold start every step")
+        rmx = run_variant(ib, torch, wl, geo, ib.MG_MIXED, args.steps, args.warmup, profile=True)
+        variants["mixed_cold"] = summary(rmx, sps64)
+        variants["mixed_cold"]["kernels"] = {k: dict(launches=v[0], avg_us=round(1e3 * v[1] / v[0], 2))
+                                             for k, v in rmx["prof"].items() if v[0]}
+    if not args.no_warm:
+        log("== FP64 multigrid, warm start from the previous pressure")
+        rw = run_variant(ib, torch, wl, geo, ib.MG_FP64, args.steps, args.warmup, profile=False,
+                         warm=True)
+        variants["fp64_warm"] = summary(rw, sps64)
+    # roofline of the dominant kernel: the finest-level FP64 smoother, either
+    # one full single-pass sweep or one colour pass (half a sweep)
+    N = float(np.prod(wl.n))
+    if r64["prof"]["sweep64"][0]:
+        nl, ms = r64["prof"]["sweep64"]
+        bytes_per_launch = SWEEP_BYTES_F64 * N
+        kname = "k_rbgs_fused<double> (finest level, one full red-black sweep)"
+    else:
+        nl, ms = r64["prof"]["smooth64"]
+        bytes_per_launch = 0.5 * SWEEP_BYTES_F64 * N
+        kname = "k_rbgs<double,3> (finest level, one colour)"
+    avg_s = ms / 1e3 / max(nl, 1)
+    achieved = bytes_per_launch / avg_s / 1e9
+    prof_summary = {k: dict(launches=v[0], avg_us=round(1e3 * v[1] / v[0], 2))
+                    for k, v in r64["prof"].items() if v[0]}
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                kernel=kname,
+                bytes_per_launch=bytes_per_launch, avg_launch_us=round(avg_s * 1e6, 2))
+    line = dict(metric=METRIC, value=round(sps64, 3), unit="steps/s", n_gpus=1, steps=args.steps,
+                warmup=args.warmup, ms_per_step=round(1e3 * r64["seconds"] / r64["steps"], 3),
+                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+                data="synthetic",
+                config=dict(workload=f"static_drop_3d_{args.size}: {args.size}^3 periodic box, sphere R=0.25 "
+                                     f"(level-{args.level} icosphere, {len(wl.X)} markers, {len(wl.tris)} "
+                                     f"triangles, seeded rotation 3), rho ratio 1000, sigma=1, dt=5e-5, "
+                                     f"irrotational spreading, FP64 multigrid V(2,2) from p=0 to 1e-10 every step",
+                            grid=list(wl.n), markers=len(wl.X), triangles=len(wl.tris)),
+                variants=variants, roofline=roof, kernels_fp64=prof_summary)
+    if not args.no_cpu_baseline:
+        log("== CPU oracle baseline (bounded sample)")
+        line["cpu_baseline"] = cpu_baseline(wl, variants["fp64_cold"]["mean_cycles"])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

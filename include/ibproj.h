@@ -258,6 +258,27 @@ typedef struct {
 int ib_diagnostics(ib_ctx* ctx, const double* p, const double* H, const double* const u[3],
                    const double* const F[3], ib_diag* out, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Kernel timing for measurement (not part of the method). When enabled, the
+ * multigrid records a pair of HIP events on the solve stream around every
+ * launch of a finest-level kernel and reads them at its next stream
+ * synchronisation; the totals accumulate until reset. Kinds:
+ *   IB_PROF_SMOOTH64 / IB_PROF_SMOOTH32 -- one colour of red-black Gauss-Seidel
+ *     (levels smoothed colour by colour)
+ *   IB_PROF_SWEEP64 / IB_PROF_SWEEP32 -- one full red-black sweep in a single
+ *     pass (3D levels of at least 128^3 cells)
+ *   IB_PROF_RESTRICT64 / IB_PROF_RESTRICT32 -- residual + restriction
+ *   IB_PROF_PROLONG64 / IB_PROF_PROLONG32 -- prolongation + correction
+ *   IB_PROF_RESID -- float64 residual norm / defect
+ * ib_profile_read returns the launch count and the summed duration (ms).
+ * Process-wide; not thread safe. */
+enum { IB_PROF_SMOOTH64 = 0, IB_PROF_SMOOTH32, IB_PROF_RESTRICT64, IB_PROF_RESTRICT32,
+       IB_PROF_PROLONG64, IB_PROF_PROLONG32, IB_PROF_RESID, IB_PROF_SWEEP64,
+       IB_PROF_SWEEP32, IB_PROF_KINDS };
+void ib_profile_enable(int on);
+void ib_profile_reset(void);
+int  ib_profile_read(int kind, long long* launches, double* total_ms);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char* ib_last_error(void);
 

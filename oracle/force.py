@@ -12,8 +12,15 @@ the face centre to the nearest interface segment (2D) or triangle (3D), with
 sigma*kappa interpolated linearly (2D) or barycentrically (3D) from the end
 markers / vertices; exact distance ties go to the lower element index.
 f is only evaluated on faces where the Heaviside difference is nonzero.
+In exact arithmetic H is exactly 0 or 1 away from the interface; the overlap
+sums leave rounding noise of order 1e-16 there, so a face counts as an
+interface face when |H_c - H_{c-e_d}| > DH_EPS = 1e-13 and carries F = 0
+otherwise (well above the noise, and a legitimate difference that small
+would change F by less than 1e-13 of its scale).
 """
 import numpy as np
+
+DH_EPS = 1e-13
 
 
 def _face_centres(dim, d, idx, h):
@@ -84,7 +91,7 @@ def irrotational_force(H, X, fs, h, tris=None):
         ax = dim - 1 - d
         dH = H - np.roll(H, 1, axis=ax)
         Fd = np.zeros_like(H)
-        idx = np.nonzero(dH != 0.0)
+        idx = np.nonzero(np.abs(dH) > DH_EPS)
         pts = _face_centres(dim, d, idx, h)
         for m in range(len(pts)):
             if dim == 2:
@@ -99,7 +106,7 @@ def irrotational_force(H, X, fs, h, tris=None):
 def face_force_at(H_lo, H_hi, pt, X, fs, h, tris=None):
     """F at one face from the two adjacent cell values (for sampled checks)."""
     dH = H_hi - H_lo
-    if dH == 0.0:
+    if abs(dH) <= DH_EPS:
         return 0.0
     f = nearest_on_polyline(pt, X, fs) if tris is None else nearest_on_mesh(pt, X, tris, fs)
     return f * dH / h

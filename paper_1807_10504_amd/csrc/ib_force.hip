@@ -11,6 +11,10 @@
 // the quantised squared distance (2^-36 h^2 steps) and the element index, so
 // the winner does not depend on execution order. The face pass reads the
 // winner, evaluates f in FP64 and resets the key.
+//
+// Away from the interface H is 0 or 1 up to the rounding of the overlap sums
+// (~1e-16); a face is an interface face when |dH| > kDhEps = 1e-13, and
+// carries F = 0 otherwise.
 #include "common.h"
 
 namespace ib {
@@ -19,6 +23,7 @@ constexpr int kElemBits = 23;
 constexpr unsigned long long kElemMask = (1ull << kElemBits) - 1;
 constexpr double kDistScale = 68719476736.0;  // 2^36
 constexpr double kReach = 3.0;                // search radius in h
+constexpr double kDhEps = 1e-13;
 
 __device__ __forceinline__ long cell_index(const Dims& d, int i, int j, int k) {
     return ((long)k * d.ny + j) * d.nx + i;
@@ -118,7 +123,7 @@ __global__ void k_nearest_2d(const double* __restrict__ X, int n, const double* 
             long c = (long)j * d.nx + i;
             long cm = comp == 0 ? (long)j * d.nx + (i == 0 ? d.nx - 1 : i - 1)
                                 : (long)(j == 0 ? d.ny - 1 : j - 1) * d.nx + i;
-            if (H[c] == H[cm]) continue;
+            if (fabs(H[c] - H[cm]) <= kDhEps) continue;
             double tt;
             double d2 = seg_closest((i + offx) * h, (j + offy) * h, ax, ay, bx, by, &tt);
             if (d2 >= R2) continue;
@@ -161,7 +166,7 @@ __global__ void k_nearest_3d(const double* __restrict__ X, int nv, const int32_t
                 long cc = cell_index(d, i, j, k);
                 int ic = comp == 0 ? i : (comp == 1 ? j : k);
                 long cm = ic == 0 ? cc + (long)(nn[comp] - 1) * stride : cc - stride;
-                if (H[cc] == H[cm]) continue;
+                if (fabs(H[cc] - H[cm]) <= kDhEps) continue;
                 double p[3] = {(i + (comp == 0 ? 0.0 : 0.5)) * h, (j + (comp == 1 ? 0.0 : 0.5)) * h,
                                (k + (comp == 2 ? 0.0 : 0.5)) * h};
                 double w[3];
@@ -189,7 +194,7 @@ __global__ void k_irrot_force(const double* __restrict__ X, const int32_t* __res
     long cm = ic == 0 ? c + (long)(nn - 1) * stride : c - stride;
     double dH = H[c] - H[cm];
     double out = 0.0;
-    if (dH != 0.0) {
+    if (fabs(dH) > kDhEps) {
         unsigned long long* B = best + (long)comp * d.cells();
         unsigned long long key = B[c];
         if (key == ~0ull) {

@@ -7,7 +7,8 @@
 // (bi/tri)linear prolongation (3/4, 1/4 per axis), coarse face coefficient =
 // mean of the 2^(dim-1) fine faces on the coarse face, coarsest grid solved
 // with the inverse of the bordered matrix [[A, 1], [1^T, 0]] (zero-mean
-// constraint), mean of p removed after every cycle.
+// constraint; solved through an SPD shift of the constant mode, see the
+// coarsest-level kernels), mean of p removed after every cycle.
 //
 // Mixed precision: the V-cycle in float32 (float32 coefficients cast from the
 // float64 hierarchy) acting on fl32(b - A p), with the defect, the update
@@ -29,6 +30,7 @@ struct LevelT {
     T* p = nullptr;
     T* b = nullptr;
     T* beta[3] = {nullptr, nullptr, nullptr};
+    T* alt = nullptr;   // second p buffer for the single-pass smoother
 };
 
 struct Level {
@@ -36,6 +38,8 @@ struct Level {
     LevelT<double> f64;
     LevelT<float> f32;
     bool own_pb = true;
+    bool fused = false;  // single-pass smoother applies
+    int tz = 0;          // its z-range per workgroup
 };
 
 }  // namespace ib
@@ -59,6 +63,63 @@ struct mg_handle {
 namespace ib {
 
 constexpr int kRed = 1024;
+
+// ---------------------------------------------------------------------------
+// optional event timing of finest-level launches
+struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    struct Pending {
+        hipEvent_t a, b;
+        int kind;
+    };
+    std::vector<Pending> pending;
+    long long count[IB_PROF_KINDS] = {0};
+    double ms[IB_PROF_KINDS] = {0};
+};
+static Prof g_prof;
+
+static hipEvent_t prof_event() {
+    if (!g_prof.pool.empty()) {
+        hipEvent_t e = g_prof.pool.back();
+        g_prof.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct ProfScope {
+    hipEvent_t a = nullptr, b = nullptr;
+    int kind;
+    hipStream_t st;
+    ProfScope(int k, hipStream_t s, bool finest) : kind(k), st(s) {
+        if (!g_prof.on || !finest) return;
+        a = prof_event();
+        b = prof_event();
+        if (a && b) (void)hipEventRecord(a, st);
+    }
+    ~ProfScope() {
+        if (!a || !b) return;
+        (void)hipEventRecord(b, st);
+        g_prof.pending.push_back({a, b, kind});
+    }
+};
+
+// called after a stream synchronisation
+static void prof_drain() {
+    for (auto& p : g_prof.pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            g_prof.count[p.kind] += 1;
+            g_prof.ms[p.kind] += ms;
+        }
+        g_prof.pool.push_back(p.a);
+        g_prof.pool.push_back(p.b);
+    }
+    g_prof.pending.clear();
+}
 
 // ---------------------------------------------------------------------------
 // index helpers
@@ -124,6 +185,169 @@ __global__ void k_rbgs(T* __restrict__ p, const T* __restrict__ b, const T* __re
         diag += br + bl;
     }
     p[n.c] = (num - h2 * b[n.c]) / diag;
+}
+
+// One full red-black sweep in a single pass (3D levels with nx % 32 == 0,
+// ny % 8 == 0). A workgroup owns a 32 x 8 column tile and a z-range [z0, z1)
+// and marches upward; at plane step k it updates the red cells of plane k
+// on the tile plus a one-cell ring, then the black cells of plane k - 1 on
+// the tile, then writes plane k - 1. Red values on the ring are recomputed
+// (the neighbour tile computes the same numbers from the same inputs), and p
+// is double-buffered (read pin, write pout), so workgroups never read what
+// another one writes during the sweep. It performs the same arithmetic as
+// the two-colour sweep: red reads only old black values, black reads only
+// new red values. Each array is read from memory about once per sweep (halos come
+// from L2: consecutive workgroups of one XCD get neighbouring tiles).
+constexpr int kFTX = 32, kFTY = 8;
+constexpr int kFRX = kFTX + 4, kFRY = kFTY + 4, kFRN = kFRX * kFRY;
+constexpr int kFLoads = (kFRN + kBlock - 1) / kBlock;
+
+// barrier for LDS traffic only: global loads issued before it stay in flight
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin, T* __restrict__ pout,
+                                                       const T* __restrict__ bb, const T* __restrict__ bx,
+                                                       const T* __restrict__ by, const T* __restrict__ bz,
+                                                       Dims d, T h2, int TZ, int ntx, int nty, int nzc) {
+    __shared__ T P[4][kFRN];
+    __shared__ T BX[2][kFRN];
+    __shared__ T BY[2][kFRN];
+    __shared__ T BZ[4][kFRN];
+    __shared__ T B[2][kFRN];
+    const int nw = ntx * nty * nzc;
+    const int bid = blockIdx.x;
+    // blocks are dealt round-robin to the 8 XCDs: give each XCD a contiguous
+    // range of tiles so that halo rows are shared in its L2
+    const int w = (nw % 8 == 0) ? (bid % 8) * (nw / 8) + bid / 8 : bid;
+    const int tx = w % ntx;
+    const int r0 = w / ntx;
+    const int ty = r0 % nty;
+    const int zc = r0 / nty;
+    const int i0 = tx * kFTX - 2, j0 = ty * kFTY - 2;
+    const int z0 = zc * TZ, z1 = z0 + TZ;
+    const long plane = (long)d.nx * d.ny;
+    const int t = threadIdx.x;
+    long goff[kFLoads];
+#pragma unroll
+    for (int s = 0; s < kFLoads; ++s) {
+        int q = t + s * kBlock;
+        goff[s] = -1;
+        if (q < kFRN) {
+            int x = q % kFRX, y = q / kFRX;
+            goff[s] = (long)wrap(j0 + y, d.ny) * d.nx + wrap(i0 + x, d.nx);
+        }
+    }
+    auto pl = [&](int k) { return (long)wrap(k, d.nz) * plane; };
+    auto load = [&](T* dst, const T* src, int k) {
+        long base = pl(k);
+#pragma unroll
+        for (int s = 0; s < kFLoads; ++s)
+            if (goff[s] >= 0) dst[t + s * kBlock] = src[base + goff[s]];
+    };
+    // registers holding the planes of the next step: p(k+1), beta_x/y(k), b(k), beta_z(k+1)
+    T rp[kFLoads], rx[kFLoads], ry[kFLoads], rb[kFLoads], rz[kFLoads];
+    auto fetch = [&](int k) {
+        long bp = pl(k + 1), bk = pl(k);
+#pragma unroll
+        for (int s = 0; s < kFLoads; ++s)
+            if (goff[s] >= 0) {
+                rp[s] = pin[bp + goff[s]];
+                rz[s] = bz[bp + goff[s]];
+                rx[s] = bx[bk + goff[s]];
+                ry[s] = by[bk + goff[s]];
+                rb[s] = bb[bk + goff[s]];
+            }
+    };
+    auto commit = [&](int k) {
+#pragma unroll
+        for (int s = 0; s < kFLoads; ++s)
+            if (goff[s] >= 0) {
+                int q = t + s * kBlock;
+                P[(k + 1) & 3][q] = rp[s];
+                BZ[(k + 1) & 3][q] = rz[s];
+                BX[k & 1][q] = rx[s];
+                BY[k & 1][q] = ry[s];
+                B[k & 1][q] = rb[s];
+            }
+    };
+    load(P[(z0 - 2) & 3], pin, z0 - 2);
+    load(P[(z0 - 1) & 3], pin, z0 - 1);
+    load(BZ[(z0 - 1) & 3], bz, z0 - 1);
+    fetch(z0 - 1);
+    const int rw = kFRX - 2, rh = kFRY - 2;
+    for (int k = z0 - 1; k <= z1; ++k) {
+        commit(k);
+        if (k < z1) fetch(k + 1);  // in flight during this step
+        lds_barrier();
+        // red cells of plane k on the tile and its one-cell ring
+        {
+            T* Pc = P[k & 3];
+            const T* Pd = P[(k - 1) & 3];
+            const T* Pu = P[(k + 1) & 3];
+            const T* X = BX[k & 1];
+            const T* Y = BY[k & 1];
+            const T* Zl = BZ[k & 3];
+            const T* Zr = BZ[(k + 1) & 3];
+            const T* Bc = B[k & 1];
+            for (int q = t; q < rw * rh; q += kBlock) {
+                int x = 1 + q % rw, y = 1 + q / rw;
+                if (((i0 + x) + (j0 + y) + k) & 1) continue;
+                int c = y * kFRX + x;
+                T br = X[c + 1], bl = X[c];
+                T num = br * Pc[c + 1] + bl * Pc[c - 1];
+                T diag = br + bl;
+                br = Y[c + kFRX];
+                bl = Y[c];
+                num += br * Pc[c + kFRX] + bl * Pc[c - kFRX];
+                diag += br + bl;
+                br = Zr[c];
+                bl = Zl[c];
+                num += br * Pu[c] + bl * Pd[c];
+                diag += br + bl;
+                Pc[c] = (num - h2 * Bc[c]) / diag;
+            }
+        }
+        lds_barrier();
+        const int kb = k - 1;
+        if (kb >= z0 && kb < z1) {
+            // black cells of plane k - 1 on the tile
+            T* Pc = P[kb & 3];
+            const T* Pd = P[(kb - 1) & 3];
+            const T* Pu = P[(kb + 1) & 3];
+            const T* X = BX[kb & 1];
+            const T* Y = BY[kb & 1];
+            const T* Zl = BZ[kb & 3];
+            const T* Zr = BZ[(kb + 1) & 3];
+            const T* Bc = B[kb & 1];
+            for (int q = t; q < kFTX * kFTY; q += kBlock) {
+                int x = 2 + q % kFTX, y = 2 + q / kFTX;
+                if ((((i0 + x) + (j0 + y) + kb) & 1) == 0) continue;
+                int c = y * kFRX + x;
+                T br = X[c + 1], bl = X[c];
+                T num = br * Pc[c + 1] + bl * Pc[c - 1];
+                T diag = br + bl;
+                br = Y[c + kFRX];
+                bl = Y[c];
+                num += br * Pc[c + kFRX] + bl * Pc[c - kFRX];
+                diag += br + bl;
+                br = Zr[c];
+                bl = Zl[c];
+                num += br * Pu[c] + bl * Pd[c];
+                diag += br + bl;
+                Pc[c] = (num - h2 * Bc[c]) / diag;
+            }
+            lds_barrier();
+            long base = pl(kb) + (long)(j0 + 2) * d.nx + (i0 + 2);
+            for (int q = t; q < kFTX * kFTY; q += kBlock) {
+                int x = q % kFTX, y = q / kFTX;
+                pout[base + (long)y * d.nx + x] = Pc[(y + 2) * kFRX + x + 2];
+            }
+        }
+        lds_barrier();
+    }
 }
 
 // residual of the fine level restricted to the coarse right side
@@ -223,83 +447,76 @@ __global__ void k_coarsen_beta(const double* __restrict__ f0, const double* __re
 }
 
 // ---------------------------------------------------------------------------
-// coarsest level: bordered matrix, Gauss-Jordan inverse, apply
+// coarsest level: exact zero-mean solve.
+// A is symmetric negative semidefinite with the constants as its null space,
+// so M = -A + c 1 1^T (c > 0) is symmetric positive definite, and for a
+// right side with zero sum the unique solution of (A - c 1 1^T) x = b has
+// sum(x) = 0 and A x = b: it is the zero-mean solution of the singular
+// system. M is inverted once per coefficient update (Gauss-Jordan without
+// pivoting, stable for SPD matrices) and each cycle applies x = -M^{-1} b.
+// c = trace(-A) / nc^2 gives the constant mode an eigenvalue equal to the
+// mean eigenvalue of -A.
+constexpr int kMaxCoarse = 64;
+
 template <int DIM>
 __global__ void k_build_coarse(const double* __restrict__ b0, const double* __restrict__ b1,
                                const double* __restrict__ b2, Dims d, double* __restrict__ M) {
+    __shared__ double diag[kMaxCoarse];
     int nc = (int)d.cells();
-    int m = nc + 1;
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r > nc) return;
-    for (int c = 0; c < m; ++c) M[(long)r * m + c] = 0.0;
-    if (r == nc) {
-        for (int c = 0; c < nc; ++c) M[(long)r * m + c] = 1.0;
-        return;
-    }
-    int i = r % d.nx, j = (r / d.nx) % d.ny, k = r / (d.nx * d.ny);
-    Nb n = neighbours(d, i, j, k, DIM);
+    int r = threadIdx.x;
     double inv = 1.0 / (d.h * d.h);
-    auto add = [&](long col, double v) { M[(long)r * m + col] += v * inv; };
-    add(n.xp, b0[n.xp]); add(n.c, -b0[n.xp]);
-    add(n.xm, b0[n.c]);  add(n.c, -b0[n.c]);
-    add(n.yp, b1[n.yp]); add(n.c, -b1[n.yp]);
-    add(n.ym, b1[n.c]);  add(n.c, -b1[n.c]);
-    if (DIM == 3) {
-        add(n.zp, b2[n.zp]); add(n.c, -b2[n.zp]);
-        add(n.zm, b2[n.c]);  add(n.c, -b2[n.c]);
-    }
-    M[(long)r * m + nc] = 1.0;
-}
-
-// one workgroup; augmented [M | I] in LDS, partial pivoting
-constexpr int kMaxCoarse = 65;
-
-__global__ void k_gauss_jordan(const double* __restrict__ M, int m, double* __restrict__ Minv,
-                               int* __restrict__ flag) {
-    __shared__ double a[kMaxCoarse][2 * kMaxCoarse + 1];
-    __shared__ int piv;
-    int t = threadIdx.x;
-    for (int q = t; q < m * m; q += blockDim.x) {
-        int r = q / m, c = q % m;
-        a[r][c] = M[q];
-        a[r][m + c] = (r == c) ? 1.0 : 0.0;
+    if (r < nc) {
+        for (int c = 0; c < nc; ++c) M[(long)r * nc + c] = 0.0;
+        int i = r % d.nx, j = (r / d.nx) % d.ny, k = r / (d.nx * d.ny);
+        Nb n = neighbours(d, i, j, k, DIM);
+        // rows of -A
+        auto add = [&](long col, double v) { M[(long)r * nc + col] += v * inv; };
+        add(n.xp, -b0[n.xp]); add(n.c, b0[n.xp]);
+        add(n.xm, -b0[n.c]);  add(n.c, b0[n.c]);
+        add(n.yp, -b1[n.yp]); add(n.c, b1[n.yp]);
+        add(n.ym, -b1[n.c]);  add(n.c, b1[n.c]);
+        if (DIM == 3) {
+            add(n.zp, -b2[n.zp]); add(n.c, b2[n.zp]);
+            add(n.zm, -b2[n.c]);  add(n.c, b2[n.c]);
+        }
+        diag[r] = M[(long)r * nc + r];
     }
     __syncthreads();
-    for (int col = 0; col < m; ++col) {
-        if (t == 0) {
-            int best = col;
-            double bv = fabs(a[col][col]);
-            for (int r = col + 1; r < m; ++r)
-                if (fabs(a[r][col]) > bv) { bv = fabs(a[r][col]); best = r; }
-            piv = best;
-            if (bv == 0.0) *flag = 1;
-        }
-        __syncthreads();
-        int pr = piv;
-        if (pr != col)
-            for (int c = t; c < 2 * m; c += blockDim.x) {
-                double tmp = a[col][c];
-                a[col][c] = a[pr][c];
-                a[pr][c] = tmp;
-            }
-        __syncthreads();
-        double inv = 1.0 / a[col][col];
-        __syncthreads();
-        for (int c = t; c < 2 * m; c += blockDim.x) a[col][c] *= inv;
-        __syncthreads();
-        for (int q = t; q < m * 2 * m; q += blockDim.x) {
-            int r = q / (2 * m), c = q % (2 * m);
-            if (r != col && c != col) a[r][c] -= a[r][col] * a[col][c];
-        }
-        __syncthreads();
-        for (int r = t; r < m; r += blockDim.x)
-            if (r != col) a[r][col] = 0.0;
-        __syncthreads();
+    if (r < nc) {
+        double tr = 0.0;
+        for (int q = 0; q < nc; ++q) tr += diag[q];
+        double c = tr / ((double)nc * (double)nc);
+        for (int q = 0; q < nc; ++q) M[(long)r * nc + q] += c;
     }
-    for (int q = t; q < m * m; q += blockDim.x) Minv[q] = a[q / m][m + q % m];
 }
 
-// x = (Minv [b; 0])[0..nc), input/output in T
+// one workgroup, in-place inverse in LDS
+__global__ void k_spd_inverse(const double* __restrict__ M, int m, double* __restrict__ Minv) {
+    __shared__ double a[kMaxCoarse][kMaxCoarse + 1];
+    __shared__ double f[kMaxCoarse];
+    int t = threadIdx.x, nt = blockDim.x;
+    for (int q = t; q < m * m; q += nt) a[q / m][q % m] = M[q];
+    __syncthreads();
+    for (int k = 0; k < m; ++k) {
+        double piv = a[k][k];
+        __syncthreads();
+        for (int j = t; j < m; j += nt) a[k][j] = (j == k ? 1.0 : a[k][j]) / piv;
+        for (int i = t; i < m; i += nt)
+            if (i != k) {
+                f[i] = a[i][k];
+                a[i][k] = 0.0;
+            }
+        __syncthreads();
+        for (int q = t; q < m * m; q += nt) {
+            int i = q / m, j = q % m;
+            if (i != k) a[i][j] -= f[i] * a[k][j];
+        }
+        __syncthreads();
+    }
+    for (int q = t; q < m * m; q += nt) Minv[q] = -a[q / m][q % m];
+}
+
+// x = (-M^{-1}) b on the coarsest level, input/output in T
 template <typename T>
 __global__ void k_coarse_apply(const double* __restrict__ Minv, int nc, const T* __restrict__ b,
                                T* __restrict__ x) {
@@ -307,10 +524,9 @@ __global__ void k_coarse_apply(const double* __restrict__ Minv, int nc, const T*
     int t = threadIdx.x;
     for (int q = t; q < nc; q += blockDim.x) sb[q] = (double)b[q];
     __syncthreads();
-    int m = nc + 1;
     for (int r = t; r < nc; r += blockDim.x) {
         double s = 0.0;
-        for (int c = 0; c < nc; ++c) s += Minv[(long)r * m + c] * sb[c];
+        for (int c = 0; c < nc; ++c) s += Minv[(long)r * nc + c] * sb[c];
         x[r] = (T)s;
     }
 }
@@ -409,7 +625,8 @@ template <> LevelT<double>& lvl<double>(Level& L) { return L.f64; }
 template <> LevelT<float>& lvl<float>(Level& L) { return L.f32; }
 
 template <typename T>
-static void launch_rbgs(Level& L, int color, hipStream_t st) {
+static void launch_rbgs(Level& L, int color, hipStream_t st, bool finest) {
+    ProfScope ps(sizeof(T) == 8 ? IB_PROF_SMOOTH64 : IB_PROF_SMOOTH32, st, finest);
     LevelT<T>& A = lvl<T>(L);
     T h2 = (T)(L.d.h * L.d.h);
     long half = L.d.cells() / 2;
@@ -419,6 +636,36 @@ static void launch_rbgs(Level& L, int color, hipStream_t st) {
     else
         hipLaunchKernelGGL((k_rbgs<T, 3>), dim3(grid_for(half)), dim3(kBlock), 0, st, A.p, A.b,
                            A.beta[0], A.beta[1], A.beta[2], L.d, h2, color);
+}
+
+template <typename T>
+static void launch_fused(Level& L, T* pin, T* pout, hipStream_t st, bool finest) {
+    ProfScope ps(sizeof(T) == 8 ? IB_PROF_SWEEP64 : IB_PROF_SWEEP32, st, finest);
+    LevelT<T>& A = lvl<T>(L);
+    T h2 = (T)(L.d.h * L.d.h);
+    int ntx = L.d.nx / kFTX, nty = L.d.ny / kFTY, nzc = L.d.nz / L.tz;
+    hipLaunchKernelGGL((k_rbgs_fused<T>), dim3(ntx * nty * nzc), dim3(kBlock), 0, st, pin, pout, A.b,
+                       A.beta[0], A.beta[1], A.beta[2], L.d, h2, L.tz, ntx, nty, nzc);
+}
+
+// nu red-black sweeps on level L; returns the buffer holding the result
+template <typename T>
+static T* smooth(Level& L, T* cur, int nu, hipStream_t st, bool finest) {
+    LevelT<T>& A = lvl<T>(L);
+    for (int s = 0; s < nu; ++s) {
+        if (L.fused) {
+            T* other = cur == A.p ? A.alt : A.p;
+            launch_fused<T>(L, cur, other, st, finest);
+            cur = other;
+        } else {
+            T* save = A.p;
+            A.p = cur;
+            launch_rbgs<T>(L, 0, st, finest);
+            launch_rbgs<T>(L, 1, st, finest);
+            A.p = save;
+        }
+    }
+    return cur;
 }
 
 template <typename T>
@@ -432,31 +679,34 @@ static void vcycle(mg_handle* m, int l, hipStream_t st) {
     }
     Level& C = m->lv[l + 1];
     LevelT<T>& B = lvl<T>(C);
-    for (int s = 0; s < m->o.nu1; ++s) {
-        launch_rbgs<T>(L, 0, st);
-        launch_rbgs<T>(L, 1, st);
-    }
+    bool fin = l == 0;
+    T* cur = smooth<T>(L, A.p, m->o.nu1, st, fin);
     T inv_h2 = (T)(1.0 / (L.d.h * L.d.h));
     long nc = C.d.cells();
-    if (L.d.dim == 2)
-        hipLaunchKernelGGL((k_residual_restrict<T, 2>), dim3(grid_for(nc)), dim3(kBlock), 0, st,
-                           A.p, A.b, A.beta[0], A.beta[1], A.beta[1], L.d, inv_h2, B.b);
-    else
-        hipLaunchKernelGGL((k_residual_restrict<T, 3>), dim3(grid_for(nc)), dim3(kBlock), 0, st,
-                           A.p, A.b, A.beta[0], A.beta[1], A.beta[2], L.d, inv_h2, B.b);
+    {
+        ProfScope ps(sizeof(T) == 8 ? IB_PROF_RESTRICT64 : IB_PROF_RESTRICT32, st, fin);
+        if (L.d.dim == 2)
+            hipLaunchKernelGGL((k_residual_restrict<T, 2>), dim3(grid_for(nc)), dim3(kBlock), 0, st,
+                               cur, A.b, A.beta[0], A.beta[1], A.beta[1], L.d, inv_h2, B.b);
+        else
+            hipLaunchKernelGGL((k_residual_restrict<T, 3>), dim3(grid_for(nc)), dim3(kBlock), 0, st,
+                               cur, A.b, A.beta[0], A.beta[1], A.beta[2], L.d, inv_h2, B.b);
+    }
     if (l + 1 != last)
         hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(nc)), dim3(kBlock), 0, st, B.p, nc, (T)0);
     vcycle<T>(m, l + 1, st);
-    if (L.d.dim == 2)
-        hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(grid_for(L.d.cells())), dim3(kBlock), 0, st,
-                           A.p, B.p, L.d);
-    else
-        hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(grid_for(L.d.cells())), dim3(kBlock), 0, st,
-                           A.p, B.p, L.d);
-    for (int s = 0; s < m->o.nu2; ++s) {
-        launch_rbgs<T>(L, 0, st);
-        launch_rbgs<T>(L, 1, st);
+    {
+        ProfScope ps(sizeof(T) == 8 ? IB_PROF_PROLONG64 : IB_PROF_PROLONG32, st, fin);
+        if (L.d.dim == 2)
+            hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(grid_for(L.d.cells())), dim3(kBlock), 0,
+                               st, cur, B.p, L.d);
+        else
+            hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(grid_for(L.d.cells())), dim3(kBlock), 0,
+                               st, cur, B.p, L.d);
     }
+    cur = smooth<T>(L, cur, m->o.nu2, st, fin);
+    if (cur != A.p)
+        (void)hipMemcpyAsync(A.p, cur, sizeof(T) * L.d.cells(), hipMemcpyDeviceToDevice, st);
 }
 
 static int red_blocks(long N) { return (int)std::min<long>(kRed, (long)grid_for(N)); }
@@ -469,16 +719,20 @@ static int fp64_norms(mg_handle* m, bool want_b, hipStream_t st) {
     double inv_h2 = 1.0 / (L.d.h * L.d.h);
     double* pr = m->red;
     double* pb = want_b ? m->red + kRed : nullptr;
+    {
+    ProfScope ps(IB_PROF_RESID, st, true);
     if (L.d.dim == 2)
         hipLaunchKernelGGL((k_resid_norm<2>), dim3(nb), dim3(kBlock), 0, st, L.f64.p, L.f64.b,
                            L.f64.beta[0], L.f64.beta[1], L.f64.beta[1], L.d, inv_h2, pr, pb);
     else
         hipLaunchKernelGGL((k_resid_norm<3>), dim3(nb), dim3(kBlock), 0, st, L.f64.p, L.f64.b,
                            L.f64.beta[0], L.f64.beta[1], L.f64.beta[2], L.d, inv_h2, pr, pb);
+    }
     IB_TRY(device_sum(pr, nb, m->red + 3 * kRed, st));
     if (want_b) IB_TRY(device_sum(pb, nb, m->red + 3 * kRed + 1, st));
     IB_HIP(hipMemcpyAsync(m->host, m->red + 3 * kRed, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
     IB_HIP(hipStreamSynchronize(st));
+    prof_drain();
     return IB_OK;
 }
 
@@ -489,16 +743,20 @@ static int mixed_defect(mg_handle* m, bool want_b, hipStream_t st) {
     double inv_h2 = 1.0 / (L.d.h * L.d.h);
     double* pr = m->red;
     double* pb = want_b ? m->red + kRed : nullptr;
+    {
+    ProfScope ps(IB_PROF_RESID, st, true);
     if (L.d.dim == 2)
         hipLaunchKernelGGL((k_defect_f32<2>), dim3(nb), dim3(kBlock), 0, st, L.f64.p, L.f64.b,
                            L.f64.beta[0], L.f64.beta[1], L.f64.beta[1], L.d, inv_h2, L.f32.b, pr, pb);
     else
         hipLaunchKernelGGL((k_defect_f32<3>), dim3(nb), dim3(kBlock), 0, st, L.f64.p, L.f64.b,
                            L.f64.beta[0], L.f64.beta[1], L.f64.beta[2], L.d, inv_h2, L.f32.b, pr, pb);
+    }
     IB_TRY(device_sum(pr, nb, m->red + 3 * kRed, st));
     if (want_b) IB_TRY(device_sum(pb, nb, m->red + 3 * kRed + 1, st));
     IB_HIP(hipMemcpyAsync(m->host, m->red + 3 * kRed, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
     IB_HIP(hipStreamSynchronize(st));
+    prof_drain();
     return IB_OK;
 }
 
@@ -518,6 +776,23 @@ static int remove_mean(mg_handle* m, bool sums_ready, hipStream_t st) {
 }  // namespace ib
 
 using namespace ib;
+
+extern "C" void ib_profile_enable(int on) { g_prof.on = on != 0; }
+
+extern "C" void ib_profile_reset(void) {
+    for (int k = 0; k < IB_PROF_KINDS; ++k) {
+        g_prof.count[k] = 0;
+        g_prof.ms[k] = 0.0;
+    }
+}
+
+extern "C" int ib_profile_read(int kind, long long* launches, double* total_ms) {
+    IB_CHECK(kind >= 0 && kind < IB_PROF_KINDS && launches && total_ms, IB_EINVAL,
+             "ib_profile_read: bad argument");
+    *launches = g_prof.count[kind];
+    *total_ms = g_prof.ms[kind];
+    return IB_OK;
+}
 
 extern "C" int mg_setup(const ib_grid* g, const mg_opts* o, mg_handle** out) {
     IB_CHECK(g && o && out, IB_EINVAL, "mg_setup: null argument");
@@ -541,7 +816,7 @@ extern "C" int mg_setup(const ib_grid* g, const mg_opts* o, mg_handle** out) {
                  "mg_setup: every axis must be divisible by 2^levels");
         ncoarse *= (g->n[e] >> L);
     }
-    IB_CHECK(ncoarse + 1 <= kMaxCoarse, IB_EINVAL, "mg_setup: coarsest grid larger than 64 cells");
+    IB_CHECK(ncoarse <= kMaxCoarse, IB_EINVAL, "mg_setup: coarsest grid larger than 64 cells");
     mg_handle* m = new mg_handle();
     m->g = *g;
     m->o = *o;
@@ -560,6 +835,14 @@ extern "C" int mg_setup(const ib_grid* g, const mg_opts* o, mg_handle** out) {
         lv.d.h = g->h * (double)(1 << l);
         long N = lv.d.cells();
         lv.own_pb = l > 0;
+        if (g->dim == 3 && lv.d.nx % kFTX == 0 && lv.d.ny % kFTY == 0 && lv.d.nz >= 32 &&
+            N >= 128L * 128 * 128) {
+            lv.fused = true;
+            long tiles = (long)(lv.d.nx / kFTX) * (lv.d.ny / kFTY);
+            int tz = lv.d.nz;
+            while (tz > 16 && tiles * (lv.d.nz / tz) < 1024) tz /= 2;
+            lv.tz = tz;
+        }
         if (l > 0) {
             if (hipMalloc(&lv.f64.p, N * sizeof(double)) != hipSuccess ||
                 hipMalloc(&lv.f64.b, N * sizeof(double)) != hipSuccess)
@@ -568,6 +851,10 @@ extern "C" int mg_setup(const ib_grid* g, const mg_opts* o, mg_handle** out) {
                 if (hipMalloc(&lv.f64.beta[e], N * sizeof(double)) != hipSuccess)
                     return cleanup(IB_ENOMEM, "mg_setup: out of device memory");
         }
+        if (lv.fused && hipMalloc(&lv.f64.alt, N * sizeof(double)) != hipSuccess)
+            return cleanup(IB_ENOMEM, "mg_setup: out of device memory");
+        if (lv.fused && mixed && hipMalloc(&lv.f32.alt, N * sizeof(float)) != hipSuccess)
+            return cleanup(IB_ENOMEM, "mg_setup: out of device memory");
         if (mixed) {
             if (hipMalloc(&lv.f32.p, N * sizeof(float)) != hipSuccess ||
                 hipMalloc(&lv.f32.b, N * sizeof(float)) != hipSuccess)
@@ -578,7 +865,7 @@ extern "C" int mg_setup(const ib_grid* g, const mg_opts* o, mg_handle** out) {
         }
         m->lv.push_back(lv);
     }
-    int m1 = m->nc + 1;
+    int m1 = m->nc;
     if (hipMalloc(&m->cmat, sizeof(double) * m1 * m1) != hipSuccess ||
         hipMalloc(&m->cinv, sizeof(double) * m1 * m1) != hipSuccess ||
         hipMalloc(&m->red, sizeof(double) * (3 * kRed + 8)) != hipSuccess ||
@@ -596,6 +883,8 @@ extern "C" void mg_destroy(mg_handle* m) {
             hipFree(lv.f64.b);
             for (int e = 0; e < 3; ++e) hipFree(lv.f64.beta[e]);
         }
+        hipFree(lv.f64.alt);
+        hipFree(lv.f32.alt);
         hipFree(lv.f32.p);
         hipFree(lv.f32.b);
         for (int e = 0; e < 3; ++e) hipFree(lv.f32.beta[e]);
@@ -635,13 +924,12 @@ extern "C" int mg_update_coeffs(mg_handle* m, const double* const beta[3], void*
                                    L.f64.beta[e], L.f32.beta[e], L.d.cells());
     Level& Cl = m->lv.back();
     if (dim == 2)
-        hipLaunchKernelGGL(k_build_coarse<2>, dim3(1), dim3(128), 0, st, Cl.f64.beta[0],
+        hipLaunchKernelGGL(k_build_coarse<2>, dim3(1), dim3(kMaxCoarse), 0, st, Cl.f64.beta[0],
                            Cl.f64.beta[1], Cl.f64.beta[1], Cl.d, m->cmat);
     else
-        hipLaunchKernelGGL(k_build_coarse<3>, dim3(1), dim3(128), 0, st, Cl.f64.beta[0],
+        hipLaunchKernelGGL(k_build_coarse<3>, dim3(1), dim3(kMaxCoarse), 0, st, Cl.f64.beta[0],
                            Cl.f64.beta[1], Cl.f64.beta[2], Cl.d, m->cmat);
-    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(256), 0, st, m->cmat, m->nc + 1, m->cinv,
-                       (int*)(m->red + 3 * kRed + 4));
+    hipLaunchKernelGGL(k_spd_inverse, dim3(1), dim3(1024), 0, st, m->cmat, m->nc, m->cinv);
     IB_HIP(hipGetLastError());
     m->coeffs_ready = true;
     return IB_OK;

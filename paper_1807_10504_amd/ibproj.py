@@ -24,7 +24,11 @@ WS_ZERO, WS_PREV = 0, 1
 EXPORTS = ("ib_create", "ib_destroy", "ib_bin_markers", "ib_interp", "ib_spread",
            "ib_coefficients", "ib_rhs", "ib_update", "mg_setup", "mg_update_coeffs", "mg_solve",
            "mg_destroy", "project_step", "ib_relocate_bspline", "ib_surface_geometry_3d",
-           "ib_diagnostics", "ib_last_error")
+           "ib_diagnostics", "ib_profile_enable", "ib_profile_reset", "ib_profile_read",
+           "ib_last_error")
+
+PROF_KINDS = ("smooth64", "smooth32", "restrict64", "restrict32", "prolong64", "prolong32", "resid",
+              "sweep64", "sweep32")
 
 
 class IbError(RuntimeError):
@@ -109,7 +113,10 @@ def load(path: str = LIB_PATH):
         "project_step": (i32, [vp, vp, P(Params), P(State), P(Outputs), vp]),
         "ib_relocate_bspline": (i32, [i32, vp, vp, f64, f64, f64, vp, vp, vp, vp]),
         "ib_surface_geometry_3d": (i32, [i32, vp, i32, vp, f64, vp, vp, vp]),
-        "ib_diagnostics": (i32, [vp, vp, vp, vp * 3, vp * 3, P(Diag), vp]),
+        "ib_diagnostics": (i32, [vp, vp, vp, vp, vp, P(Diag), vp]),
+        "ib_profile_enable": (None, [i32]),
+        "ib_profile_reset": (None, []),
+        "ib_profile_read": (i32, [i32, P(C.c_longlong), P(f64)]),
         "ib_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -272,9 +279,11 @@ class Context:
     def diagnostics(self, p=None, H=None, u=None, F=None):
         import torch
         d = Diag()
+        ua = _vec3(u, torch.float64) if u is not None else None
+        Fa = _vec3(F, torch.float64) if F is not None else None
         _check(self.lib.ib_diagnostics(self.ptr, _dptr(p, torch.float64), _dptr(H, torch.float64),
-                                       _vec3(u, torch.float64) if u is not None else None,
-                                       _vec3(F, torch.float64) if F is not None else None,
+                                       C.addressof(ua) if ua is not None else None,
+                                       C.addressof(Fa) if Fa is not None else None,
                                        C.byref(d), _stream()))
         return d.as_dict()
 
@@ -363,6 +372,28 @@ class Multigrid:
         if not (rc == IB_ENOTCONV and allow_notconv):
             _check(rc)
         return st.as_dict()
+
+
+# ----------------------------------------------------------------------------
+# kernel timing
+def profile_enable(on=True):
+    load().ib_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    load().ib_profile_reset()
+
+
+def profile_read():
+    """{kind: (launches, total_ms)} for the finest-level multigrid kernels."""
+    lib = load()
+    out = {}
+    for k, name in enumerate(PROF_KINDS):
+        n = C.c_longlong()
+        ms = C.c_double()
+        _check(lib.ib_profile_read(k, C.byref(n), C.byref(ms)))
+        out[name] = (int(n.value), float(ms.value))
+    return out
 
 
 # ----------------------------------------------------------------------------
