@@ -54,7 +54,7 @@ extern "C" {
 
 enum { IB_SPREAD_IRROT = 0, IB_SPREAD_DELTA = 1 };
 enum { MG_FP64 = 0, MG_MIXED = 1 };
-enum { WS_ZERO = 0, WS_PREV = 1 };
+enum { WS_ZERO = 0, WS_PREV = 1, WS_NN = 2 };
 
 typedef struct {
     int dim;      /* 2 or 3 */
@@ -79,6 +79,7 @@ typedef struct {
 
 typedef struct ib_ctx ib_ctx;
 typedef struct mg_handle mg_handle;
+typedef struct ib_nn ib_nn;
 
 /* ---------------------------------------------------------------------------
  * Context: workspace for binning, spreading and the step. max_markers and
@@ -177,6 +178,9 @@ int  mg_update_coeffs(mg_handle* m, const double* const beta[3], void* stream);
 int  mg_solve(mg_handle* m, const double* b, double* p, double rtol, int max_cycles,
               int fixed_cycles, mg_stats* stats, void* stream);
 void mg_destroy(mg_handle* m);
+/* ||b - A p||_2 / ||b||_2 on the finest level with the coefficients of the last
+ * mg_update_coeffs (0 when b = 0). Syncs. */
+int  mg_residual_norm(mg_handle* m, const double* b, const double* p, double* rel, void* stream);
 
 /* ---------------------------------------------------------------------------
  * One projection step (a1..a11). */
@@ -188,7 +192,9 @@ typedef struct {
     int max_cycles;
     int fixed_cycles;        /* > 0: exactly this many cycles (parity runs) */
     int spread_mode;         /* IB_SPREAD_IRROT or IB_SPREAD_DELTA */
-    int warm_start;          /* WS_ZERO or WS_PREV (p_prev as initial guess) */
+    int warm_start;          /* WS_ZERO, WS_PREV (p_prev as initial guess) or WS_NN
+                                (network guess from (b, 1/rho, p_prev), used only when
+                                its residual is below that of p_prev; else p_prev) */
 } ib_params;
 
 typedef struct {
@@ -199,6 +205,7 @@ typedef struct {
     double* X_host;          /* 2D: host n_markers*2, in: markers at step n, out: advanced
                                 by dt U and relocated on the least-squares B-spline.
                                 3D: NULL. */
+    ib_nn* nn;               /* WS_NN: the network (2D), else NULL */
 } ib_state;
 
 typedef struct {
@@ -208,7 +215,11 @@ typedef struct {
     double* H;               /* device cell array or NULL */
     double* F[3];            /* device face arrays or NULL */
     double* fs_host;         /* 2D: host n_markers sigma*kappa after relocation, or NULL */
+    double* b;               /* device cell array: copy of the right side, or NULL */
     mg_stats stats;
+    int guess_accepted;      /* WS_NN: 1 when the network guess was used */
+    double guess_rel_res;    /* WS_NN: ||b - A p_nn|| / ||b|| */
+    double prev_rel_res;     /* WS_NN: ||b - A p_prev|| / ||b|| */
 } ib_outputs;
 
 /* Runs interp -> (2D: D2H U, host advance + B-spline relocation, H2D) ->
@@ -278,6 +289,37 @@ enum { IB_PROF_SMOOTH64 = 0, IB_PROF_SMOOTH32, IB_PROF_RESTRICT64, IB_PROF_RESTR
 void ib_profile_enable(int on);
 void ib_profile_reset(void);
 int  ib_profile_read(int kind, long long* launches, double* total_ms);
+
+/* ---------------------------------------------------------------------------
+ * a10 -- learned warm start (project addition, 2D). A 6-layer 3x3
+ * convolutional network (circular padding, channels 3 -> 32 x5 -> 1, ReLU
+ * between) in bfloat16 on the matrix cores with float32 accumulation maps
+ * x = (b h^2 / s_b, (1/rho) / max(1/rho), p_prev / s_p) (s = RMS) to y, and the
+ * guess is p0 = p_prev + s_p y; trained with Adam on the mean squared error to
+ * t = (p - p_prev) / s_p, p being the multigrid solution. n[0] must be a
+ * multiple of 64. Parameters cross the ABI as host float32, per layer
+ * W[co][ci][ky][kx] (unpadded channel counts) then b[co]; count from
+ * ib_nn_param_count(). The network starts with all parameters zero. */
+int  ib_nn_param_count(void);
+int  ib_nn_create(const ib_grid* g, ib_nn** out);
+void ib_nn_destroy(ib_nn* nn);
+int  ib_nn_set_params(ib_nn* nn, const float* params, int count);
+int  ib_nn_get_params(ib_nn* nn, float* params, int count);
+/* p0 (device cells) from b, H (device cells; rho from H as in ib_coefficients),
+ * p_prev (device cells or NULL = 0). */
+int  ib_nn_predict(ib_nn* nn, const double* b, const double* H, const double* p_prev,
+                   double rho_in, double rho_out, double* p0, void* stream);
+/* Gradient of the loss for one sample (no update): host float32 in the
+ * parameter layout (may be NULL), loss returned. Syncs. */
+int  ib_nn_gradients(ib_nn* nn, const double* b, const double* H, const double* p_prev,
+                     const double* p, double rho_in, double rho_out, float* grads,
+                     int count, double* loss, void* stream);
+/* One Adam step (lr; beta 0.9, 0.999; eps 1e-8) on the mean gradient of
+ * `count` samples (arrays of device pointers, host arrays of length count;
+ * p_prev may be NULL). Returns the mean loss. Syncs per sample. */
+int  ib_nn_train_step(ib_nn* nn, int count, const double* const* b, const double* const* H,
+                      const double* const* p_prev, const double* const* p, double rho_in,
+                      double rho_out, float lr, double* loss, void* stream);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char* ib_last_error(void);

@@ -287,7 +287,27 @@ extern "C" int project_step(ib_ctx* c, mg_handle* m, const ib_params* prm, ib_st
     IB_TRY(launch_rhs(c, stt->u_star, Fc, bc, prm->dt, c->b, st));
     // a9, a10: warm start and solve
     long N = c->d.cells();
-    if (prm->warm_start == WS_PREV && stt->p_prev) {
+    if (out->b) IB_HIP(hipMemcpyAsync(out->b, c->b, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    out->guess_accepted = 0;
+    out->guess_rel_res = out->prev_rel_res = 0.0;
+    if (prm->warm_start == WS_NN) {
+        IB_CHECK(stt->nn && dim == 2, IB_EINVAL, "project_step: WS_NN needs a 2D network");
+        IB_CHECK(stt->p_prev != out->p, IB_EINVAL, "project_step: WS_NN needs p_prev distinct from p");
+        IB_TRY(ib_nn_predict(stt->nn, c->b, H, stt->p_prev, prm->rho_in, prm->rho_out, out->p, st));
+        IB_TRY(mg_residual_norm(m, c->b, out->p, &out->guess_rel_res, st));
+        if (stt->p_prev) {
+            IB_TRY(mg_residual_norm(m, c->b, stt->p_prev, &out->prev_rel_res, st));
+        } else {
+            out->prev_rel_res = 1.0;  // zero guess
+        }
+        if (out->guess_rel_res < out->prev_rel_res) {
+            out->guess_accepted = 1;
+        } else if (stt->p_prev) {
+            IB_HIP(hipMemcpyAsync(out->p, stt->p_prev, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+        } else {
+            IB_HIP(hipMemsetAsync(out->p, 0, sizeof(double) * N, st));
+        }
+    } else if (prm->warm_start == WS_PREV && stt->p_prev) {
         if (stt->p_prev != out->p)
             IB_HIP(hipMemcpyAsync(out->p, stt->p_prev, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
     } else {

@@ -935,6 +935,24 @@ extern "C" int mg_update_coeffs(mg_handle* m, const double* const beta[3], void*
     return IB_OK;
 }
 
+extern "C" int mg_residual_norm(mg_handle* m, const double* b, const double* p, double* rel,
+                                void* stream) {
+    IB_CHECK(m && b && p && rel, IB_EINVAL, "mg_residual_norm: null argument");
+    IB_CHECK(m->coeffs_ready, IB_EINVAL, "mg_residual_norm: call mg_update_coeffs first");
+    Level& L0 = m->lv[0];
+    double* sp = L0.f64.p;
+    double* sb = L0.f64.b;
+    L0.f64.p = const_cast<double*>(p);
+    L0.f64.b = const_cast<double*>(b);
+    int rc = fp64_norms(m, true, (hipStream_t)stream);
+    L0.f64.p = sp;
+    L0.f64.b = sb;
+    IB_TRY(rc);
+    double bn = std::sqrt(m->host[1]);
+    *rel = bn > 0.0 ? std::sqrt(m->host[0]) / bn : 0.0;
+    return IB_OK;
+}
+
 extern "C" int mg_solve(mg_handle* m, const double* b, double* p, double rtol, int max_cycles,
                         int fixed_cycles, mg_stats* stats, void* stream) {
     IB_CHECK(m && b && p, IB_EINVAL, "mg_solve: null argument");

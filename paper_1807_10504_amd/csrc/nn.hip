@@ -1,0 +1,561 @@
+// Learned warm start for the pressure solve (project addition; the paper
+// uses multigrid alone). A 6-layer 3x3 convolutional network (circular
+// padding, channels 3 -> 32 x 5 -> 1, ReLU between) maps the normalised
+// right side, inverse density and previous pressure to a pressure
+// correction; multigrid starts from p0 = p_prev + s_p * y and stays the judge.
+//
+// Precision: bfloat16 weights, activations and gradients in memory, float32
+// accumulation on the matrix cores (v_mfma_f32_16x16x32_bf16), float32
+// master weights and Adam moments, float64 at the solver boundary.
+//
+// Layout: activations NHWC with 32 channels (the 3 input channels and the 1
+// output channel are zero-padded to 32), bfloat16 stored as 16-bit patterns.
+// Weights per layer: Wl[co][tap][ci] (tap = 3 ky + kx multiplies the input at
+// (y + ky - 1, x + kx - 1)) and the flipped transpose Wt[ci][8 - tap][co]
+// used by the input gradient, which is then the same convolution kernel.
+//
+// A convolution is an implicit GEMM: a wave owns 16 pixels of one row and
+// all 32 output channels; for each tap it multiplies a 16 x 32 (pixel x
+// channel) slab of the shifted input by the 32 x 16 weight block of each half
+// of the output channels (two MFMA per tap). The weight gradient is a GEMM
+// over pixels: a workgroup stages 64 pixels of the gradient and the three
+// input rows they touch in LDS and accumulates 36 (tap, co-block, ci-block)
+// 16 x 16 tiles; per-workgroup partials are summed in a fixed order.
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace ib {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16;
+
+constexpr int kC = 32;          // padded channel count
+constexpr int kTaps = 9;
+constexpr int kWSize = kC * kTaps * kC;  // weights per layer
+constexpr int kPSize = kWSize + kC;      // + bias
+constexpr int kLayers = 6;
+constexpr int kGradBlocks = 256;
+static const int kChan[7] = {3, 32, 32, 32, 32, 32, 1};
+
+__device__ __forceinline__ u16 f2bf(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (u16)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(u16 h) { return __uint_as_float(((unsigned)h) << 16); }
+
+// ---------------------------------------------------------------------------
+// input normalisation: partial sums of (b h^2)^2 and p_prev^2, max of 1/rho
+__global__ void k_nn_stats(const double* __restrict__ b, const double* __restrict__ H,
+                           const double* __restrict__ pp, long N, double h2, double rin,
+                           double rout, double* __restrict__ part) {
+    __shared__ double sh[kBlock];
+    double sb = 0.0, sp = 0.0, mr = 0.0;
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long)gridDim.x * blockDim.x) {
+        double bh = b[c] * h2;
+        sb += bh * bh;
+        double p = pp ? pp[c] : 0.0;
+        sp += p * p;
+        mr = fmax(mr, 1.0 / (rout + (rin - rout) * H[c]));
+    }
+    double r = block_reduce_sum(sb, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = r;
+    r = block_reduce_sum(sp, sh);
+    if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = r;
+    sh[threadIdx.x] = mr;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[2 * gridDim.x + blockIdx.x] = sh[0];
+}
+
+// scale[0] = s_b, scale[1] = s_p, scale[2] = s_r (each 1 when zero)
+__global__ void k_nn_scales(const double* __restrict__ part, int nb, long N, double* __restrict__ scale) {
+    __shared__ double sh[kBlock];
+    double a = 0.0, b = 0.0, m = 0.0;
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+        a += part[q];
+        b += part[nb + q];
+        m = fmax(m, part[2 * nb + q]);
+    }
+    double sa = block_reduce_sum(a, sh);
+    double sb = block_reduce_sum(b, sh);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double rb = sqrt(sa / (double)N), rp = sqrt(sb / (double)N);
+        scale[0] = rb > 0.0 ? rb : 1.0;
+        scale[1] = rp > 0.0 ? rp : 1.0;
+        scale[2] = sh[0] > 0.0 ? sh[0] : 1.0;
+    }
+}
+
+__global__ void k_nn_input(const double* __restrict__ b, const double* __restrict__ H,
+                           const double* __restrict__ pp, long N, double h2, double rin, double rout,
+                           const double* __restrict__ scale, u16* __restrict__ X) {
+    long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    float v0 = (float)(b[c] * h2 / scale[0]);
+    float v1 = (float)((1.0 / (rout + (rin - rout) * H[c])) / scale[2]);
+    float v2 = (float)((pp ? pp[c] : 0.0) / scale[1]);
+    u16* o = X + c * kC;
+    o[0] = f2bf(v0);
+    o[1] = f2bf(v1);
+    o[2] = f2bf(v2);
+    for (int q = 3; q < kC; ++q) o[q] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// convolution on the matrix cores
+// MODE 0: + bias, ReLU, bfloat16 out; MODE 1: + bias, float32 out of channel 0;
+// MODE 2: bfloat16 out times (act > 0) (input gradient through the ReLU below)
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_nn_conv(const u16* __restrict__ X, const u16* __restrict__ Wl,
+                                                    const float* __restrict__ bias,
+                                                    const u16* __restrict__ act, u16* __restrict__ Y,
+                                                    float* __restrict__ Yf, int H, int W) {
+    __shared__ u16 tile[4][16][kC];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int y = blockIdx.y;
+    const int x0 = blockIdx.x * 64 + wave * 16;
+    const int m = lane & 15, kg = lane >> 4;
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < kTaps; ++tap) {
+        const int ky = tap / 3, kx = tap - 3 * ky;
+        const int yy = wrap(y + ky - 1, H), xx = wrap(x0 + m + kx - 1, W);
+        bf16x8 a = *reinterpret_cast<const bf16x8*>(X + ((long)yy * W + xx) * kC + kg * 8);
+        bf16x8 b0 = *reinterpret_cast<const bf16x8*>(Wl + ((m)*kTaps + tap) * kC + kg * 8);
+        bf16x8 b1 = *reinterpret_cast<const bf16x8*>(Wl + ((16 + m) * kTaps + tap) * kC + kg * 8);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, acc1, 0, 0, 0);
+    }
+    // accumulator element i of lane (m, kg): pixel 4 kg + i, channel m (acc0) / 16 + m (acc1)
+    if (MODE == 1) {
+        if (m == 0) {
+            float b0v = bias[0];
+            for (int i = 0; i < 4; ++i) Yf[(long)y * W + x0 + 4 * kg + i] = acc0[i] + b0v;
+        }
+        return;
+    }
+    for (int i = 0; i < 4; ++i) {
+        int px = 4 * kg + i;
+        float v0 = acc0[i], v1 = acc1[i];
+        if (MODE == 0) {
+            v0 = fmaxf(v0 + bias[m], 0.f);
+            v1 = fmaxf(v1 + bias[16 + m], 0.f);
+            tile[wave][px][m] = f2bf(v0);
+            tile[wave][px][16 + m] = f2bf(v1);
+        } else {
+            const u16* ar = act + ((long)y * W + x0 + px) * kC;
+            u16 h0 = f2bf(v0), h1 = f2bf(v1);
+            tile[wave][px][m] = bf2f(ar[m]) > 0.f ? h0 : (u16)0;
+            tile[wave][px][16 + m] = bf2f(ar[16 + m]) > 0.f ? h1 : (u16)0;
+        }
+    }
+    __syncthreads();
+    // lane l stores 8 channels of pixel l / 4
+    const int px = lane >> 2, ch = (lane & 3) * 8;
+    uint4 v = *reinterpret_cast<const uint4*>(&tile[wave][px][ch]);
+    *reinterpret_cast<uint4*>(Y + ((long)y * W + x0 + px) * kC + ch) = v;
+}
+
+// ---------------------------------------------------------------------------
+// loss: y (float32), target t = (p - p_prev) / s_p; gradient (2/N)(y - t) into
+// channel 0 of G (bfloat16), per-block partial sums of (y - t)^2
+__global__ void k_nn_loss(const float* __restrict__ y, const double* __restrict__ p,
+                          const double* __restrict__ pp, const double* __restrict__ scale, long N,
+                          u16* __restrict__ G, double* __restrict__ part) {
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    const double inv_sp = 1.0 / scale[1];
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long)gridDim.x * blockDim.x) {
+        double t = (p[c] - (pp ? pp[c] : 0.0)) * inv_sp;
+        double d = (double)y[c] - t;
+        acc += d * d;
+        u16* o = G + c * kC;
+        o[0] = f2bf((float)(2.0 * d / (double)N));
+        for (int q = 1; q < kC; ++q) o[q] = 0;
+    }
+    double r = block_reduce_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient: dW[co][tap][ci] = sum_p G[p][co] X[p + off(tap)][ci], db[co] = sum_p G[p][co]
+__global__ __launch_bounds__(kBlock) void k_nn_wgrad(const u16* __restrict__ G, const u16* __restrict__ X,
+                                                     int H, int W, float* __restrict__ part) {
+    __shared__ u16 g_s[64][kC];
+    __shared__ u16 x_s[3][66][kC];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m = lane & 15, kg = lane >> 4;
+    const int segs_per_row = W / 64;
+    const long nseg = (long)H * segs_per_row;
+    f32x4 acc[9];
+    for (int q = 0; q < 9; ++q) acc[q] = {0.f, 0.f, 0.f, 0.f};
+    float dbias = 0.f;
+    for (long sgi = blockIdx.x; sgi < nseg; sgi += gridDim.x) {
+        const int y = (int)(sgi / segs_per_row), xs = (int)(sgi % segs_per_row) * 64;
+        // stage 64 gradient pixels and the 3 x 66 input pixels they touch
+        for (int q = threadIdx.x; q < 64 * 4; q += kBlock) {
+            int px = q >> 2, part8 = (q & 3) * 8;
+            *reinterpret_cast<uint4*>(&g_s[px][part8]) =
+                *reinterpret_cast<const uint4*>(G + ((long)y * W + xs + px) * kC + part8);
+        }
+        for (int q = threadIdx.x; q < 3 * 66 * 4; q += kBlock) {
+            int r = q / (66 * 4), rem = q % (66 * 4);
+            int px = rem >> 2, part8 = (rem & 3) * 8;
+            int yy = wrap(y + r - 1, H), xx = wrap(xs + px - 1, W);
+            *reinterpret_cast<uint4*>(&x_s[r][px][part8]) =
+                *reinterpret_cast<const uint4*>(X + ((long)yy * W + xx) * kC + part8);
+        }
+        __syncthreads();
+        if (threadIdx.x < kC) {
+            float s = 0.f;
+            for (int px = 0; px < 64; ++px) s += bf2f(g_s[px][threadIdx.x]);
+            dbias += s;
+        }
+        // tiles t = wave + 4 j, j = 0..8: tap = t / 4, co block = (t / 2) & 1, ci block = t & 1
+        for (int j = 0; j < 9; ++j) {
+            const int t = wave + 4 * j;
+            const int tap = t >> 2, cb = (t >> 1) & 1, nb = t & 1;
+            const int ky = tap / 3, kx = tap - 3 * ky;
+            for (int kk = 0; kk < 2; ++kk) {
+                bf16x8 a, b;
+                const int p0 = kk * 32 + kg * 8;
+                for (int e = 0; e < 8; ++e) {
+                    u16 ga = g_s[p0 + e][cb * 16 + m];
+                    u16 xb = x_s[ky][p0 + e + kx][nb * 16 + m];
+                    a[e] = __builtin_bit_cast(__bf16, ga);
+                    b[e] = __builtin_bit_cast(__bf16, xb);
+                }
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    float* out = part + (long)blockIdx.x * kPSize;
+    for (int j = 0; j < 9; ++j) {
+        const int t = wave + 4 * j;
+        const int tap = t >> 2, cb = (t >> 1) & 1, nb = t & 1;
+        for (int i = 0; i < 4; ++i) {
+            int co = cb * 16 + 4 * kg + i, ci = nb * 16 + m;
+            out[(co * kTaps + tap) * kC + ci] = acc[j][i];
+        }
+    }
+    if (threadIdx.x < kC) out[kWSize + threadIdx.x] = dbias;
+}
+
+// grad[q] += sum over blocks of part[b][q], in block order
+__global__ void k_nn_grad_reduce(const float* __restrict__ part, int nb, float* __restrict__ grad) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= kPSize) return;
+    float s = 0.f;
+    for (int b = 0; b < nb; ++b) s += part[(long)b * kPSize + q];
+    grad[q] += s;
+}
+
+// Adam on the float32 master parameters of one layer; refresh the bfloat16
+// copies (Wl and the flipped transpose Wt) and the float32 bias
+__global__ void k_nn_adam(float* __restrict__ master, float* __restrict__ mom, float* __restrict__ vel,
+                          float* __restrict__ grad, float scale, float lr, float c1, float c2,
+                          u16* __restrict__ Wl, u16* __restrict__ Wt, float* __restrict__ bias) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= kPSize) return;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    float g = grad[q] * scale;
+    float mq = b1 * mom[q] + (1.f - b1) * g;
+    float vq = b2 * vel[q] + (1.f - b2) * g * g;
+    mom[q] = mq;
+    vel[q] = vq;
+    float mh = mq / c1, vh = vq / c2;
+    float w = master[q] - lr * mh / (sqrtf(vh) + eps);
+    master[q] = w;
+    grad[q] = 0.f;
+    if (q < kWSize) {
+        int co = q / (kTaps * kC), rem = q % (kTaps * kC), tap = rem / kC, ci = rem % kC;
+        u16 h = f2bf(w);
+        Wl[q] = h;
+        Wt[(ci * kTaps + (kTaps - 1 - tap)) * kC + co] = h;
+    } else {
+        bias[q - kWSize] = w;
+    }
+}
+
+// refresh the bfloat16 copies from the master parameters
+__global__ void k_nn_publish(const float* __restrict__ master, u16* __restrict__ Wl,
+                             u16* __restrict__ Wt, float* __restrict__ bias) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= kPSize) return;
+    float w = master[q];
+    if (q < kWSize) {
+        int co = q / (kTaps * kC), rem = q % (kTaps * kC), tap = rem / kC, ci = rem % kC;
+        u16 h = f2bf(w);
+        Wl[q] = h;
+        Wt[(ci * kTaps + (kTaps - 1 - tap)) * kC + co] = h;
+    } else {
+        bias[q - kWSize] = w;
+    }
+}
+
+// p0 = p_prev + s_p * y
+__global__ void k_nn_guess(const float* __restrict__ y, const double* __restrict__ pp,
+                           const double* __restrict__ scale, long N, double* __restrict__ p0) {
+    long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    p0[c] = (pp ? pp[c] : 0.0) + scale[1] * (double)y[c];
+}
+
+}  // namespace ib
+
+using namespace ib;
+
+struct ib_nn {
+    int H = 0, W = 0;
+    double h = 0.0;
+    long N = 0;
+    u16* act[kLayers] = {};   // layer inputs (act[0] = normalised input)
+    float* yf = nullptr;      // network output
+    u16* g[2] = {};           // gradient ping-pong
+    u16* Wl = nullptr;        // kLayers * kWSize
+    u16* Wt = nullptr;
+    float* bias = nullptr;    // kLayers * kC
+    float* master = nullptr;  // kLayers * kPSize
+    float* mom = nullptr;
+    float* vel = nullptr;
+    float* grad = nullptr;
+    float* part = nullptr;    // kGradBlocks * kPSize
+    double* red = nullptr;    // reductions
+    double* scale = nullptr;  // s_b, s_p, s_r
+    double* host = nullptr;   // pinned
+    int step = 0;
+};
+
+static int nn_forward(ib_nn* n, const double* b, const double* H, const double* pp, double rin,
+                      double rout, hipStream_t st) {
+    const int nb = 1024;
+    double h2 = n->h * n->h;
+    hipLaunchKernelGGL(k_nn_stats, dim3(nb), dim3(kBlock), 0, st, b, H, pp, n->N, h2, rin, rout, n->red);
+    hipLaunchKernelGGL(k_nn_scales, dim3(1), dim3(kBlock), 0, st, n->red, nb, n->N, n->scale);
+    hipLaunchKernelGGL(k_nn_input, dim3(grid_for(n->N)), dim3(kBlock), 0, st, b, H, pp, n->N, h2, rin,
+                       rout, n->scale, n->act[0]);
+    dim3 grid(n->W / 64, n->H);
+    for (int l = 0; l < kLayers; ++l) {
+        const u16* Wl = n->Wl + (long)l * kWSize;
+        const float* bias = n->bias + l * kC;
+        if (l < kLayers - 1)
+            hipLaunchKernelGGL(k_nn_conv<0>, grid, dim3(kBlock), 0, st, n->act[l], Wl, bias, nullptr,
+                               n->act[l + 1], nullptr, n->H, n->W);
+        else
+            hipLaunchKernelGGL(k_nn_conv<1>, grid, dim3(kBlock), 0, st, n->act[l], Wl, bias, nullptr,
+                               nullptr, n->yf, n->H, n->W);
+    }
+    IB_HIP(hipGetLastError());
+    return IB_OK;
+}
+
+// forward + backward of one sample, gradients added to n->grad; loss partials
+// summed into *loss (syncs)
+static int nn_backward(ib_nn* n, const double* b, const double* H, const double* pp, const double* p,
+                       double rin, double rout, double* loss, hipStream_t st) {
+    IB_TRY(nn_forward(n, b, H, pp, rin, rout, st));
+    const int nb = 1024;
+    hipLaunchKernelGGL(k_nn_loss, dim3(nb), dim3(kBlock), 0, st, n->yf, p, pp, n->scale, n->N, n->g[0],
+                       n->red);
+    IB_TRY(device_sum(n->red, nb, n->red + 4 * 1024, st));
+    dim3 grid(n->W / 64, n->H);
+    int cur = 0;
+    for (int l = kLayers - 1; l >= 0; --l) {
+        // n->g[cur] holds layer l's pre-activation gradient (bfloat16)
+        hipLaunchKernelGGL(k_nn_wgrad, dim3(kGradBlocks), dim3(kBlock), 0, st, n->g[cur], n->act[l], n->H,
+                           n->W, n->part);
+        hipLaunchKernelGGL(k_nn_grad_reduce, dim3(grid_for(kPSize)), dim3(kBlock), 0, st, n->part,
+                           kGradBlocks, n->grad + (long)l * kPSize);
+        if (l > 0)
+            hipLaunchKernelGGL(k_nn_conv<2>, grid, dim3(kBlock), 0, st, n->g[cur],
+                               n->Wt + (long)l * kWSize, nullptr, n->act[l], n->g[1 - cur], nullptr,
+                               n->H, n->W);
+        cur = 1 - cur;
+    }
+    IB_HIP(hipGetLastError());
+    IB_HIP(hipMemcpyAsync(n->host, n->red + 4 * 1024, sizeof(double), hipMemcpyDeviceToHost, st));
+    IB_HIP(hipStreamSynchronize(st));
+    *loss = n->host[0] / (double)n->N;
+    return IB_OK;
+}
+
+static void nn_free(ib_nn* n) {
+    if (!n) return;
+    for (int l = 0; l < kLayers; ++l) (void)hipFree(n->act[l]);
+    void* ptrs[] = {n->yf, n->g[0], n->g[1], n->Wl, n->Wt, n->bias, n->master, n->mom,
+                    n->vel, n->grad, n->part, n->red, n->scale};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (n->host) (void)hipHostFree(n->host);
+    delete n;
+}
+
+extern "C" int ib_nn_param_count(void) {
+    int t = 0;
+    for (int l = 0; l < kLayers; ++l) t += kChan[l + 1] * kChan[l] * 9 + kChan[l + 1];
+    return t;
+}
+
+extern "C" int ib_nn_create(const ib_grid* g, ib_nn** out) {
+    IB_CHECK(g && out, IB_EINVAL, "ib_nn_create: null argument");
+    IB_CHECK(g->dim == 2, IB_EINVAL, "ib_nn_create: the network is two-dimensional");
+    IB_CHECK(g->n[0] % 64 == 0 && g->n[0] >= 64 && g->n[1] >= 1, IB_EINVAL,
+             "ib_nn_create: n[0] must be a multiple of 64");
+    ib_nn* n = new ib_nn();
+    n->W = g->n[0];
+    n->H = g->n[1];
+    n->h = g->h;
+    n->N = (long)n->W * n->H;
+    bool ok = true;
+    auto alloc = [&](void** p, size_t bytes) {
+        if (ok && hipMalloc(p, bytes) != hipSuccess) ok = false;
+    };
+    for (int l = 0; l < kLayers; ++l) alloc((void**)&n->act[l], n->N * kC * sizeof(u16));
+    alloc((void**)&n->yf, n->N * sizeof(float));
+    alloc((void**)&n->g[0], n->N * kC * sizeof(u16));
+    alloc((void**)&n->g[1], n->N * kC * sizeof(u16));
+    alloc((void**)&n->Wl, kLayers * kWSize * sizeof(u16));
+    alloc((void**)&n->Wt, kLayers * kWSize * sizeof(u16));
+    alloc((void**)&n->bias, kLayers * kC * sizeof(float));
+    alloc((void**)&n->master, kLayers * kPSize * sizeof(float));
+    alloc((void**)&n->mom, kLayers * kPSize * sizeof(float));
+    alloc((void**)&n->vel, kLayers * kPSize * sizeof(float));
+    alloc((void**)&n->grad, kLayers * kPSize * sizeof(float));
+    alloc((void**)&n->part, (size_t)kGradBlocks * kPSize * sizeof(float));
+    alloc((void**)&n->red, 8 * 1024 * sizeof(double));
+    alloc((void**)&n->scale, 4 * sizeof(double));
+    if (ok && hipHostMalloc((void**)&n->host, 8 * sizeof(double)) != hipSuccess) ok = false;
+    if (!ok) {
+        nn_free(n);
+        return fail(IB_ENOMEM, "ib_nn_create: out of memory");
+    }
+    size_t pb = kLayers * kPSize * sizeof(float);
+    if (hipMemset(n->master, 0, pb) != hipSuccess || hipMemset(n->mom, 0, pb) != hipSuccess ||
+        hipMemset(n->vel, 0, pb) != hipSuccess || hipMemset(n->grad, 0, pb) != hipSuccess ||
+        hipMemset(n->Wl, 0, kLayers * kWSize * sizeof(u16)) != hipSuccess ||
+        hipMemset(n->Wt, 0, kLayers * kWSize * sizeof(u16)) != hipSuccess ||
+        hipMemset(n->bias, 0, kLayers * kC * sizeof(float)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        nn_free(n);
+        return fail(IB_EHIP, "ib_nn_create: initialisation failed");
+    }
+    *out = n;
+    return IB_OK;
+}
+
+extern "C" void ib_nn_destroy(ib_nn* n) { nn_free(n); }
+
+// params: host float32, per layer W[co][ci][ky][kx] (unpadded channel counts) then b[co]
+extern "C" int ib_nn_set_params(ib_nn* n, const float* params, int count) {
+    IB_CHECK(n && params, IB_EINVAL, "ib_nn_set_params: null argument");
+    IB_CHECK(count == ib_nn_param_count(), IB_EINVAL, "ib_nn_set_params: wrong parameter count");
+    std::vector<float> pad((size_t)kLayers * kPSize, 0.f);
+    const float* src = params;
+    for (int l = 0; l < kLayers; ++l) {
+        int ci_n = kChan[l], co_n = kChan[l + 1];
+        float* dst = pad.data() + (size_t)l * kPSize;
+        for (int co = 0; co < co_n; ++co)
+            for (int ci = 0; ci < ci_n; ++ci)
+                for (int tap = 0; tap < kTaps; ++tap) dst[(co * kTaps + tap) * kC + ci] = *src++;
+        for (int co = 0; co < co_n; ++co) dst[kWSize + co] = *src++;
+    }
+    IB_HIP(hipMemcpy(n->master, pad.data(), pad.size() * sizeof(float), hipMemcpyHostToDevice));
+    for (int l = 0; l < kLayers; ++l)
+        hipLaunchKernelGGL(k_nn_publish, dim3(grid_for(kPSize)), dim3(kBlock), 0, 0,
+                           n->master + (long)l * kPSize, n->Wl + (long)l * kWSize,
+                           n->Wt + (long)l * kWSize, n->bias + l * kC);
+    IB_HIP(hipMemset(n->mom, 0, kLayers * kPSize * sizeof(float)));
+    IB_HIP(hipMemset(n->vel, 0, kLayers * kPSize * sizeof(float)));
+    IB_HIP(hipDeviceSynchronize());
+    n->step = 0;
+    return IB_OK;
+}
+
+static int unpad(const std::vector<float>& pad, float* params) {
+    float* dst = params;
+    for (int l = 0; l < kLayers; ++l) {
+        int ci_n = kChan[l], co_n = kChan[l + 1];
+        const float* src = pad.data() + (size_t)l * kPSize;
+        for (int co = 0; co < co_n; ++co)
+            for (int ci = 0; ci < ci_n; ++ci)
+                for (int tap = 0; tap < kTaps; ++tap) *dst++ = src[(co * kTaps + tap) * kC + ci];
+        for (int co = 0; co < co_n; ++co) *dst++ = src[kWSize + co];
+    }
+    return IB_OK;
+}
+
+extern "C" int ib_nn_get_params(ib_nn* n, float* params, int count) {
+    IB_CHECK(n && params, IB_EINVAL, "ib_nn_get_params: null argument");
+    IB_CHECK(count == ib_nn_param_count(), IB_EINVAL, "ib_nn_get_params: wrong parameter count");
+    std::vector<float> pad((size_t)kLayers * kPSize);
+    IB_HIP(hipDeviceSynchronize());
+    IB_HIP(hipMemcpy(pad.data(), n->master, pad.size() * sizeof(float), hipMemcpyDeviceToHost));
+    return unpad(pad, params);
+}
+
+extern "C" int ib_nn_predict(ib_nn* n, const double* b, const double* H, const double* p_prev,
+                             double rho_in, double rho_out, double* p0, void* stream) {
+    IB_CHECK(n && b && H && p0, IB_EINVAL, "ib_nn_predict: null argument");
+    hipStream_t st = (hipStream_t)stream;
+    IB_TRY(nn_forward(n, b, H, p_prev, rho_in, rho_out, st));
+    hipLaunchKernelGGL(k_nn_guess, dim3(grid_for(n->N)), dim3(kBlock), 0, st, n->yf, p_prev, n->scale,
+                       n->N, p0);
+    IB_HIP(hipGetLastError());
+    return IB_OK;
+}
+
+extern "C" int ib_nn_gradients(ib_nn* n, const double* b, const double* H, const double* p_prev,
+                               const double* p, double rho_in, double rho_out, float* grads_host,
+                               int count, double* loss, void* stream) {
+    IB_CHECK(n && b && H && p && loss, IB_EINVAL, "ib_nn_gradients: null argument");
+    IB_CHECK(!grads_host || count == ib_nn_param_count(), IB_EINVAL, "ib_nn_gradients: count");
+    hipStream_t st = (hipStream_t)stream;
+    IB_HIP(hipMemsetAsync(n->grad, 0, kLayers * kPSize * sizeof(float), st));
+    IB_TRY(nn_backward(n, b, H, p_prev, p, rho_in, rho_out, loss, st));
+    if (grads_host) {
+        std::vector<float> pad((size_t)kLayers * kPSize);
+        IB_HIP(hipMemcpyAsync(pad.data(), n->grad, pad.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+        IB_HIP(hipStreamSynchronize(st));
+        unpad(pad, grads_host);
+    }
+    IB_HIP(hipMemsetAsync(n->grad, 0, kLayers * kPSize * sizeof(float), st));
+    return IB_OK;
+}
+
+extern "C" int ib_nn_train_step(ib_nn* n, int count, const double* const* b, const double* const* H,
+                                const double* const* p_prev, const double* const* p, double rho_in,
+                                double rho_out, float lr, double* loss, void* stream) {
+    IB_CHECK(n && b && H && p && loss && count > 0, IB_EINVAL, "ib_nn_train_step: bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    double tot = 0.0;
+    for (int s = 0; s < count; ++s) {
+        double l = 0.0;
+        IB_TRY(nn_backward(n, b[s], H[s], p_prev ? p_prev[s] : nullptr, p[s], rho_in, rho_out, &l, st));
+        tot += l;
+    }
+    n->step += 1;
+    float c1 = 1.f - powf(0.9f, (float)n->step), c2 = 1.f - powf(0.999f, (float)n->step);
+    for (int l = 0; l < kLayers; ++l)
+        hipLaunchKernelGGL(k_nn_adam, dim3(grid_for(kPSize)), dim3(kBlock), 0, st,
+                           n->master + (long)l * kPSize, n->mom + (long)l * kPSize,
+                           n->vel + (long)l * kPSize, n->grad + (long)l * kPSize, 1.f / (float)count,
+                           lr, c1, c2, n->Wl + (long)l * kWSize, n->Wt + (long)l * kWSize,
+                           n->bias + l * kC);
+    IB_HIP(hipGetLastError());
+    *loss = tot / count;
+    return IB_OK;
+}

@@ -19,11 +19,14 @@ LIB_PATH = os.path.join(_HERE, "libibproj.so")
 IB_OK, IB_EINVAL, IB_EHIP, IB_ENOMEM, IB_ENOTCONV, IB_EGEOM, IB_ENAN = 0, -1, -2, -3, -4, -5, -6
 IB_SPREAD_IRROT, IB_SPREAD_DELTA = 0, 1
 MG_FP64, MG_MIXED = 0, 1
-WS_ZERO, WS_PREV = 0, 1
+WS_ZERO, WS_PREV, WS_NN = 0, 1, 2
 
 EXPORTS = ("ib_create", "ib_destroy", "ib_bin_markers", "ib_interp", "ib_spread",
            "ib_coefficients", "ib_rhs", "ib_update", "mg_setup", "mg_update_coeffs", "mg_solve",
-           "mg_destroy", "project_step", "ib_relocate_bspline", "ib_surface_geometry_3d",
+           "mg_destroy", "mg_residual_norm", "project_step", "ib_relocate_bspline",
+           "ib_surface_geometry_3d", "ib_nn_param_count", "ib_nn_create", "ib_nn_destroy",
+           "ib_nn_set_params", "ib_nn_get_params", "ib_nn_predict", "ib_nn_gradients",
+           "ib_nn_train_step",
            "ib_diagnostics", "ib_profile_enable", "ib_profile_reset", "ib_profile_read",
            "ib_last_error")
 
@@ -67,12 +70,14 @@ class Params(C.Structure):
 
 class State(C.Structure):
     _fields_ = [("u_star", C.c_void_p * 3), ("p_prev", C.c_void_p), ("surf", Surface),
-                ("X_host", C.c_void_p)]
+                ("X_host", C.c_void_p), ("nn", C.c_void_p)]
 
 
 class Outputs(C.Structure):
     _fields_ = [("p", C.c_void_p), ("u", C.c_void_p * 3), ("U", C.c_void_p), ("H", C.c_void_p),
-                ("F", C.c_void_p * 3), ("fs_host", C.c_void_p), ("stats", MgStats)]
+                ("F", C.c_void_p * 3), ("fs_host", C.c_void_p), ("b", C.c_void_p),
+                ("stats", MgStats), ("guess_accepted", C.c_int), ("guess_rel_res", C.c_double),
+                ("prev_rel_res", C.c_double)]
 
 
 class Diag(C.Structure):
@@ -110,6 +115,15 @@ def load(path: str = LIB_PATH):
         "mg_update_coeffs": (i32, [vp, vp * 3, vp]),
         "mg_solve": (i32, [vp, vp, vp, f64, i32, i32, P(MgStats), vp]),
         "mg_destroy": (None, [vp]),
+        "mg_residual_norm": (i32, [vp, vp, vp, P(f64), vp]),
+        "ib_nn_param_count": (i32, []),
+        "ib_nn_create": (i32, [P(Grid), P(vp)]),
+        "ib_nn_destroy": (None, [vp]),
+        "ib_nn_set_params": (i32, [vp, vp, i32]),
+        "ib_nn_get_params": (i32, [vp, vp, i32]),
+        "ib_nn_predict": (i32, [vp, vp, vp, vp, f64, f64, vp, vp]),
+        "ib_nn_gradients": (i32, [vp, vp, vp, vp, vp, f64, f64, vp, i32, P(f64), vp]),
+        "ib_nn_train_step": (i32, [vp, i32, vp, vp, vp, vp, f64, f64, C.c_float, P(f64), vp]),
         "project_step": (i32, [vp, vp, P(Params), P(State), P(Outputs), vp]),
         "ib_relocate_bspline": (i32, [i32, vp, vp, f64, f64, f64, vp, vp, vp, vp]),
         "ib_surface_geometry_3d": (i32, [i32, vp, i32, vp, f64, vp, vp, vp]),
@@ -288,7 +302,7 @@ class Context:
         return d.as_dict()
 
     def project_step(self, mg: "Multigrid", params: dict, u_star, p_prev=None, surf=None,
-                     X_host=None, n_markers=None, out=None):
+                     X_host=None, n_markers=None, out=None, nn: "Network" = None):
         """One projection step. 2D: X_host (numpy, N x 2) is advanced and relocated in
         place; 3D: surf is the static surface. Returns the outputs dict."""
         import torch
@@ -314,6 +328,7 @@ class Context:
             st.surf = surf
             st.X_host = None
             nm = surf.n_markers
+        st.nn = nn.ptr if nn is not None else None
         if out is None:
             out = {}
         o = Outputs()
@@ -329,8 +344,11 @@ class Context:
         o.F = _vec3(out["F"], torch.float64) if out.get("F") is not None else (C.c_void_p * 3)()
         fs_host = out.get("fs_host")
         o.fs_host = _hptr(fs_host) if fs_host is not None else None
+        o.b = _dptr(out.get("b"), torch.float64)
         rc = self.lib.project_step(self.ptr, mg.ptr, C.byref(prm), C.byref(st), C.byref(o), _stream())
         out["stats"] = o.stats.as_dict()
+        out["guess"] = dict(accepted=o.guess_accepted, rel_res=o.guess_rel_res,
+                            prev_rel_res=o.prev_rel_res)
         if rc == IB_ENOTCONV and params.get("allow_notconv", False):
             return out
         _check(rc)
@@ -364,6 +382,13 @@ class Multigrid:
         self._beta = list(beta)  # keep the arrays alive while the handle refers to them
         _check(self.lib.mg_update_coeffs(self.ptr, _vec3(beta, torch.float64), _stream()))
 
+    def residual_norm(self, b, p):
+        import torch
+        r = C.c_double()
+        _check(self.lib.mg_residual_norm(self.ptr, _dptr(b, torch.float64), _dptr(p, torch.float64),
+                                         C.byref(r), _stream()))
+        return r.value
+
     def solve(self, b, p, rtol=1e-10, max_cycles=100, fixed_cycles=0, allow_notconv=False):
         import torch
         st = MgStats()
@@ -372,6 +397,87 @@ class Multigrid:
         if not (rc == IB_ENOTCONV and allow_notconv):
             _check(rc)
         return st.as_dict()
+
+
+# ----------------------------------------------------------------------------
+class Network:
+    """The learned warm start (2D): bfloat16 convolutional network on the matrix cores."""
+
+    def __init__(self, n, h):
+        self.lib = load()
+        self.grid = make_grid(2, n, h)
+        self.ptr = C.c_void_p()
+        _check(self.lib.ib_nn_create(C.byref(self.grid), C.byref(self.ptr)))
+        self.count = self.lib.ib_nn_param_count()
+
+    def close(self):
+        if self.ptr:
+            self.lib.ib_nn_destroy(self.ptr)
+            self.ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        _check(self.lib.ib_nn_set_params(self.ptr, flat.ctypes.data, flat.size))
+
+    def get_params(self):
+        out = np.empty(self.count, dtype=np.float32)
+        _check(self.lib.ib_nn_get_params(self.ptr, out.ctypes.data, out.size))
+        return out
+
+    def predict(self, b, H, p_prev, rho_in, rho_out, p0=None):
+        import torch
+        if p0 is None:
+            p0 = torch.empty_like(b)
+        _check(self.lib.ib_nn_predict(self.ptr, _dptr(b, torch.float64), _dptr(H, torch.float64),
+                                      _dptr(p_prev, torch.float64), rho_in, rho_out,
+                                      _dptr(p0, torch.float64), _stream()))
+        return p0
+
+    def gradients(self, b, H, p_prev, p, rho_in, rho_out):
+        import torch
+        g = np.empty(self.count, dtype=np.float32)
+        loss = C.c_double()
+        _check(self.lib.ib_nn_gradients(self.ptr, _dptr(b, torch.float64), _dptr(H, torch.float64),
+                                        _dptr(p_prev, torch.float64), _dptr(p, torch.float64), rho_in,
+                                        rho_out, g.ctypes.data, g.size, C.byref(loss), _stream()))
+        return loss.value, g
+
+    def train_step(self, samples, rho_in, rho_out, lr):
+        """samples: list of (b, H, p_prev, p) device tensors. Returns the mean loss."""
+        import torch
+        n = len(samples)
+        arr = [(C.c_void_p * n)() for _ in range(4)]
+        for i, smp in enumerate(samples):
+            for j in range(4):
+                arr[j][i] = _dptr(smp[j], torch.float64)
+        loss = C.c_double()
+        _check(self.lib.ib_nn_train_step(self.ptr, n, arr[0], arr[1], arr[2], arr[3], rho_in, rho_out,
+                                         C.c_float(lr), C.byref(loss), _stream()))
+        return loss.value
+
+
+def flatten_params(params):
+    """Oracle parameter list [[W, b], ...] -> the ABI's flat float32 layout."""
+    return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in params]).astype(np.float32)
+
+
+def unflatten_params(flat, channels=(3, 32, 32, 32, 32, 32, 1)):
+    out, o = [], 0
+    for l in range(6):
+        ci, co = channels[l], channels[l + 1]
+        nW = co * ci * 9
+        W = flat[o:o + nW].reshape(co, ci, 3, 3).astype(np.float64)
+        o += nW
+        b = flat[o:o + co].astype(np.float64)
+        o += co
+        out.append([W, b])
+    return out
 
 
 # ----------------------------------------------------------------------------
