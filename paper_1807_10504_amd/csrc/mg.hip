@@ -8,7 +8,9 @@
 // mean of the 2^(dim-1) fine faces on the coarse face, coarsest grid solved
 // with the inverse of the bordered matrix [[A, 1], [1^T, 0]] (zero-mean
 // constraint; solved through an SPD shift of the constant mode, see the
-// coarsest-level kernels), mean of p removed after every cycle.
+// coarsest-level kernels), mean of p removed (once, after the last cycle: the
+// cycle commutes with adding a constant, so iterates differ from a per-cycle
+// removal by a constant only).
 //
 // Mixed precision: the V-cycle in float32 (float32 coefficients cast from the
 // float64 hierarchy) acting on fl32(b - A p), with the defect, the update
@@ -62,7 +64,7 @@ struct mg_handle {
 
 namespace ib {
 
-constexpr int kRed = 1024;
+constexpr int kRed = 8192;
 
 // ---------------------------------------------------------------------------
 // optional event timing of finest-level launches
@@ -374,37 +376,63 @@ __global__ void k_residual_restrict(const T* __restrict__ p, const T* __restrict
     bc[t] = acc * (DIM == 3 ? T(0.125) : T(0.25));
 }
 
+// Same restriction for 3D levels with nx % 64 == 0: one thread per fine cell
+// (block = 64 x 2 x 2 fine cells = 32 coarse cells), the residual of each fine
+// cell computed once; the two x-children meet by a lane exchange, the y and
+// z pairs through LDS, summed in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_residual_restrict64(const T* __restrict__ p,
+                                                                const T* __restrict__ b,
+                                                                const T* __restrict__ b0,
+                                                                const T* __restrict__ b1,
+                                                                const T* __restrict__ b2, Dims f,
+                                                                T inv_h2, T* __restrict__ bc) {
+    __shared__ T part[4][32];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
+    const int j = blockIdx.y * 2 + (wave & 1);
+    const int k = blockIdx.z * 2 + (wave >> 1);
+    Nb n = neighbours(f, i, j, k, 3);
+    T r = b[n.c] - apply_row<T, 3>(p, b0, b1, b2, n) * inv_h2;
+    T rx = r + __shfl_xor(r, 1);
+    if ((lane & 1) == 0) part[wave][lane >> 1] = rx;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        const int I = blockIdx.x * 32 + threadIdx.x;
+        const int cx = f.nx >> 1, cy = f.ny >> 1;
+        T v = (part[0][threadIdx.x] + part[1][threadIdx.x]) + (part[2][threadIdx.x] + part[3][threadIdx.x]);
+        bc[((long)blockIdx.z * cy + blockIdx.y) * cx + I] = v * T(0.125);
+    }
+}
+
 // p_fine += P e_coarse (cell-centred linear, 3/4 and 1/4 per axis)
 template <typename T, int DIM>
 __global__ void k_prolong_add(T* __restrict__ p, const T* __restrict__ e, Dims f) {
-    long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= f.cells()) return;
-    int i = (int)(c % f.nx);
-    long r = c / f.nx;
-    int j = (int)(r % f.ny);
-    int k = (int)(r / f.ny);
-    int cx = f.nx >> 1, cy = f.ny >> 1, cz = DIM == 3 ? (f.nz >> 1) : 1;
-    int I = i >> 1, J = j >> 1, K = k >> 1;
-    int I2 = (i & 1) ? (I + 1 == cx ? 0 : I + 1) : (I == 0 ? cx - 1 : I - 1);
-    int J2 = (j & 1) ? (J + 1 == cy ? 0 : J + 1) : (J == 0 ? cy - 1 : J - 1);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= f.nx) return;
+    const int j = blockIdx.y, k = blockIdx.z;
+    const int cx = f.nx >> 1, cy = f.ny >> 1, cz = DIM == 3 ? (f.nz >> 1) : 1;
+    const int I = i >> 1, J = j >> 1, K = k >> 1;
+    const int I2 = (i & 1) ? (I + 1 == cx ? 0 : I + 1) : (I == 0 ? cx - 1 : I - 1);
+    const int J2 = (j & 1) ? (J + 1 == cy ? 0 : J + 1) : (J == 0 ? cy - 1 : J - 1);
     const T a = T(0.75), q = T(0.25);
     T v;
     if (DIM == 2) {
-        T r0 = a * e[(long)J * cx + I] + q * e[(long)J * cx + I2];
-        T r1 = a * e[(long)J2 * cx + I] + q * e[(long)J2 * cx + I2];
+        T r0 = a * e[J * cx + I] + q * e[J * cx + I2];
+        T r1 = a * e[J2 * cx + I] + q * e[J2 * cx + I2];
         v = a * r0 + q * r1;
     } else {
-        int K2 = (k & 1) ? (K + 1 == cz ? 0 : K + 1) : (K == 0 ? cz - 1 : K - 1);
-        long pl = (long)cx * cy;
-        const T* e0 = e + (long)K * pl;
-        const T* e1 = e + (long)K2 * pl;
-        T r00 = a * e0[(long)J * cx + I] + q * e0[(long)J * cx + I2];
-        T r01 = a * e0[(long)J2 * cx + I] + q * e0[(long)J2 * cx + I2];
-        T r10 = a * e1[(long)J * cx + I] + q * e1[(long)J * cx + I2];
-        T r11 = a * e1[(long)J2 * cx + I] + q * e1[(long)J2 * cx + I2];
+        const int K2 = (k & 1) ? (K + 1 == cz ? 0 : K + 1) : (K == 0 ? cz - 1 : K - 1);
+        const int pl = cx * cy;
+        const T* e0 = e + K * pl;
+        const T* e1 = e + K2 * pl;
+        T r00 = a * e0[J * cx + I] + q * e0[J * cx + I2];
+        T r01 = a * e0[J2 * cx + I] + q * e0[J2 * cx + I2];
+        T r10 = a * e1[J * cx + I] + q * e1[J * cx + I2];
+        T r11 = a * e1[J2 * cx + I] + q * e1[J2 * cx + I2];
         v = a * (a * r00 + q * r01) + q * (a * r10 + q * r11);
     }
-    p[c] += v;
+    p[((long)k * f.ny + j) * f.nx + i] += v;
 }
 
 template <typename T>
@@ -540,12 +568,12 @@ __global__ void k_resid_norm(const double* __restrict__ p, const double* __restr
                              double* __restrict__ partial_r2, double* __restrict__ partial_b2) {
     __shared__ double sh[kBlock];
     double ar = 0.0, ab = 0.0;
-    long N = d.cells();
-    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long)gridDim.x * blockDim.x) {
-        int i = (int)(c % d.nx);
-        long r = c / d.nx;
-        int j = (int)(r % d.ny);
-        int k = (int)(r / d.ny);
+    const int N = (int)d.cells(), nx = d.nx, ny = d.ny;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < N; c += gridDim.x * blockDim.x) {
+        int i = c % nx;
+        int r = c / nx;
+        int j = r % ny;
+        int k = r / ny;
         Nb n = neighbours(d, i, j, k, DIM);
         double bv = b[c];
         double rv = bv - apply_row<double, DIM>(p, b0, b1, b2, n) * inv_h2;
@@ -569,12 +597,12 @@ __global__ void k_defect_f32(const double* __restrict__ p, const double* __restr
                              double* __restrict__ partial_b2) {
     __shared__ double sh[kBlock];
     double ar = 0.0, ab = 0.0;
-    long N = d.cells();
-    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long)gridDim.x * blockDim.x) {
-        int i = (int)(c % d.nx);
-        long r = c / d.nx;
-        int j = (int)(r % d.ny);
-        int k = (int)(r / d.ny);
+    const int N = (int)d.cells(), nx = d.nx, ny = d.ny;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < N; c += gridDim.x * blockDim.x) {
+        int i = c % nx;
+        int r = c / nx;
+        int j = r % ny;
+        int k = r / ny;
         Nb n = neighbours(d, i, j, k, DIM);
         double bv = b[c];
         double rv = bv - apply_row<double, DIM>(p, b0, b1, b2, n) * inv_h2;
@@ -688,6 +716,10 @@ static void vcycle(mg_handle* m, int l, hipStream_t st) {
         if (L.d.dim == 2)
             hipLaunchKernelGGL((k_residual_restrict<T, 2>), dim3(grid_for(nc)), dim3(kBlock), 0, st,
                                cur, A.b, A.beta[0], A.beta[1], A.beta[1], L.d, inv_h2, B.b);
+        else if (L.d.nx % 64 == 0)
+            hipLaunchKernelGGL((k_residual_restrict64<T>), dim3(L.d.nx / 64, L.d.ny / 2, L.d.nz / 2),
+                               dim3(kBlock), 0, st, cur, A.b, A.beta[0], A.beta[1], A.beta[2], L.d,
+                               inv_h2, B.b);
         else
             hipLaunchKernelGGL((k_residual_restrict<T, 3>), dim3(grid_for(nc)), dim3(kBlock), 0, st,
                                cur, A.b, A.beta[0], A.beta[1], A.beta[2], L.d, inv_h2, B.b);
@@ -697,12 +729,12 @@ static void vcycle(mg_handle* m, int l, hipStream_t st) {
     vcycle<T>(m, l + 1, st);
     {
         ProfScope ps(sizeof(T) == 8 ? IB_PROF_PROLONG64 : IB_PROF_PROLONG32, st, fin);
+        int bx = std::min(L.d.nx, kBlock);
+        dim3 pg((L.d.nx + bx - 1) / bx, L.d.ny, L.d.nz);
         if (L.d.dim == 2)
-            hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(grid_for(L.d.cells())), dim3(kBlock), 0,
-                               st, cur, B.p, L.d);
+            hipLaunchKernelGGL((k_prolong_add<T, 2>), pg, dim3(bx), 0, st, cur, B.p, L.d);
         else
-            hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(grid_for(L.d.cells())), dim3(kBlock), 0,
-                               st, cur, B.p, L.d);
+            hipLaunchKernelGGL((k_prolong_add<T, 3>), pg, dim3(bx), 0, st, cur, B.p, L.d);
     }
     cur = smooth<T>(L, cur, m->o.nu2, st, fin);
     if (cur != A.p)
@@ -985,19 +1017,20 @@ extern "C" int mg_solve(mg_handle* m, const double* b, double* p, double rtol, i
         if (fixed_cycles > 0 ? cycles >= fixed_cycles : rel <= rtol) break;
         if (fixed_cycles == 0 && cycles >= max_cycles) {
             S->cycles = cycles;
+            IB_TRY(remove_mean(m, false, st));
             return fail(IB_ENOTCONV, "mg_solve: no convergence within max_cycles");
         }
+        // A annihilates constants and every step of a cycle commutes with adding
+        // one, so the mean is removed once, after the last cycle
         if (mixed) {
             hipLaunchKernelGGL((k_fill<float>), dim3(grid_for(N)), dim3(kBlock), 0, st, L0.f32.p, N, 0.0f);
             vcycle<float>(m, 0, st);
             int nb = red_blocks(N);
             hipLaunchKernelGGL(k_correct_f32, dim3(nb), dim3(kBlock), 0, st, p, L0.f32.p, N,
                                m->red + 2 * kRed);
-            IB_TRY(remove_mean(m, true, st));
             IB_TRY(mixed_defect(m, false, st));
         } else {
             vcycle<double>(m, 0, st);
-            IB_TRY(remove_mean(m, false, st));
             IB_TRY(fp64_norms(m, false, st));
         }
         rel = std::sqrt(m->host[0]) / bnorm;
@@ -1006,6 +1039,7 @@ extern "C" int mg_solve(mg_handle* m, const double* b, double* p, double rtol, i
         S->cycles = cycles;
         S->rel_res = rel;
     }
+    if (cycles > 0) IB_TRY(remove_mean(m, false, st));
     IB_HIP(hipGetLastError());
     return IB_OK;
 }

@@ -202,6 +202,8 @@ def make_surface(X, elems=None, nrm=None, fs=None, ds=None) -> Surface:
     s.nrm = _dptr(nrm, torch.float64)
     s.fs = _dptr(fs, torch.float64)
     s.ds = _dptr(ds, torch.float64)
+    # the structure holds raw device pointers: keep the tensors alive with it
+    s._keep = (X, elems, nrm, fs, ds)
     return s
 
 

@@ -1,0 +1,183 @@
+"""Parity at the benchmark's full size: 256^3 periodic box, sphere R = 0.25 from
+a level-6 icosphere (40,962 markers, 81,920 triangles), density ratio 1000,
+one cold projection step in the same launch configuration bench.py times.
+
+The oracle cannot run the whole step at this size in seconds, so it is checked
+on sampled outputs it can compute one by one, and through properties that hold
+at any size:
+  * H on sampled columns (full height) and the irrotational face force on
+    every face of those columns (<= 1e-13 / 1e-11 of max |F|);
+  * the right side at sampled cells (before its mean, which is ~1e-16 of it);
+  * interpolation of a seeded random velocity at sampled markers;
+  * p: ||b - A p|| / ||b|| <= 1e-10 with an independent NumPy operator on the
+    library's coefficients, and zero mean;
+  * the updated velocity at sampled faces from the oracle formula;
+  * the Laplace jump close to 2 sigma / R.
+"""
+import numpy as np
+import pytest
+
+from oracle import force, heaviside, poisson, transfer
+from paper_1807_10504_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def run():
+    from paper_1807_10504_amd import ibproj as ib
+    assert torch.cuda.is_available()
+    wl = W.static_drop_3d(256, 6, seed=3)
+    n, h = wl.n, wl.h
+    shape = tuple(reversed(n))
+    fs, ds, nrm = ib.surface_geometry_3d(wl.X, wl.tris, wl.sigma)
+    Vd = torch.from_numpy(wl.X).cuda()
+    Td = torch.from_numpy(wl.tris.astype(np.int32)).cuda()
+    surf = ib.make_surface(Vd, elems=Td, nrm=torch.from_numpy(nrm).cuda(),
+                           fs=torch.from_numpy(fs).cuda(), ds=torch.from_numpy(ds).cuda())
+    keep = [Vd, Td]
+    ctx = ib.Context(3, n, h, max_markers=len(wl.X), max_elems=len(wl.tris))
+    mg = ib.Multigrid(3, n, h)
+    u0 = [torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+    out = dict(H=torch.empty(shape, dtype=torch.float64, device="cuda"),
+               F=[torch.empty(shape, dtype=torch.float64, device="cuda") for _ in range(3)],
+               b=torch.empty(shape, dtype=torch.float64, device="cuda"))
+    params = dict(rho_in=wl.rho_in, rho_out=wl.rho_out, sigma=wl.sigma, dt=wl.dt, rtol=1e-10,
+                  warm_start=ib.WS_ZERO)
+    out = ctx.project_step(mg, params, u0, surf=surf, out=out)
+    beta = ctx.coefficients(out["H"], wl.rho_in, wl.rho_out)
+    d = ctx.diagnostics(p=out["p"], H=out["H"])
+    torch.cuda.synchronize()
+    res = dict(wl=wl, ib=ib, ctx=ctx, surf=surf, keep=keep, stats=out["stats"], diag=d,
+               H=out["H"].cpu().numpy(), F=[f.cpu().numpy() for f in out["F"]],
+               b=out["b"].cpu().numpy(), p=out["p"].cpu().numpy(),
+               u=[c.cpu().numpy() for c in out["u"]], beta=[x.cpu().numpy() for x in beta])
+    res["nrm_o"] = heaviside.vertex_normals(wl.X, wl.tris)
+    from oracle import surface3d
+    res["fs_o"] = surface3d.surface_geometry(wl.X, wl.tris, wl.sigma)[0]
+    return res
+
+
+def _cols(run):
+    h = run["wl"].h
+    c = int(0.5 / h)
+    r = int(0.25 / h)
+    # through the centre, near the rim, across the equator, plus neighbours
+    base = [(c, c), (c + r - 2, c + 3), (c - 7, c + r - 4), (c + 11, c - 13)]
+    cols = set()
+    for (i, j) in base:
+        for (di, dj) in ((0, 0), (-1, 0), (0, -1), (1, 0), (0, 1)):
+            cols.add((i + di, j + dj))
+    return sorted(cols), base
+
+
+@pytest.fixture(scope="module")
+def oracle_cols(run):
+    cols, base = _cols(run)
+    wl = run["wl"]
+    Ho = heaviside.heaviside_3d(wl.X, wl.tris, wl.n, wl.h, nrm=run["nrm_o"], columns=cols)
+    return Ho, base
+
+
+def test_solve_converged_and_jump(run):
+    st = run["stats"]
+    assert st["rel_res"] <= 1e-10
+    assert abs(run["diag"]["dP"] - 8.0) < 0.02 * 8.0
+
+
+def test_heaviside_columns(run, oracle_cols):
+    Ho, base = oracle_cols
+    for (i, j), col in Ho.items():
+        assert np.max(np.abs(run["H"][:, j, i] - col)) <= 1e-13, (i, j)
+
+
+def test_face_force_on_sampled_columns(run, oracle_cols):
+    Ho, base = oracle_cols
+    wl = run["wl"]
+    h = wl.h
+    F = run["F"]
+    fmax = max(np.abs(f).max() for f in F)
+    checked = 0
+    for (i, j) in base:
+        for k in range(wl.n[2]):
+            # z-face (i, j, k): cells (i, j, k-1) and (i, j, k)
+            faces = [(2, Ho[(i, j)][k - 1], Ho[(i, j)][k], ((i + 0.5) * h, (j + 0.5) * h, k * h)),
+                     (0, Ho[(i - 1, j)][k], Ho[(i, j)][k], (i * h, (j + 0.5) * h, (k + 0.5) * h)),
+                     (1, Ho[(i, j - 1)][k], Ho[(i, j)][k], ((i + 0.5) * h, j * h, (k + 0.5) * h))]
+            for (dd, lo, hi, pt) in faces:
+                ref = force.face_force_at(lo, hi, np.array(pt), wl.X, run["fs_o"], h, tris=wl.tris)
+                assert abs(F[dd][k, j, i] - ref) <= 1e-11 * fmax, (dd, i, j, k)
+                checked += ref != 0.0
+    assert checked > 20
+
+
+def test_rhs_sampled_cells(run, oracle_cols):
+    Ho, base = oracle_cols
+    wl = run["wl"]
+    h = wl.h
+    b = run["b"]
+    bmax = np.abs(b).max()
+
+    def rho(Hv):
+        return wl.rho_out + (wl.rho_in - wl.rho_out) * Hv
+
+    for (i, j) in base:
+        col = Ho[(i, j)]
+        for k in range(wl.n[2]):
+            # b = (1/h) sum_d [beta F](c + e_d) - [beta F](c)   (u* = 0)
+            terms = []
+            for (dd, cell_lo, cell_hi) in (
+                    (0, Ho[(i - 1, j)][k], col[k]), (0, col[k], Ho[(i + 1, j)][k]),
+                    (1, Ho[(i, j - 1)][k], col[k]), (1, col[k], Ho[(i, j + 1)][k]),
+                    (2, col[k - 1], col[k]), (2, col[k], col[(k + 1) % wl.n[2]])):
+                terms.append((dd, cell_lo, cell_hi))
+            val = 0.0
+            for side, (dd, lo, hi) in enumerate(terms):
+                if dd == 0:
+                    x = (i + side % 2) * h
+                    pt = (x, (j + 0.5) * h, (k + 0.5) * h)
+                elif dd == 1:
+                    y = (j + side % 2) * h
+                    pt = ((i + 0.5) * h, y, (k + 0.5) * h)
+                else:
+                    z = (k + side % 2) * h
+                    pt = ((i + 0.5) * h, (j + 0.5) * h, z)
+                Ff = force.face_force_at(lo, hi, np.array(pt), wl.X, run["fs_o"], h, tris=wl.tris)
+                bf = 2.0 / (rho(lo) + rho(hi))
+                val += (1 if side % 2 else -1) * bf * Ff
+            val /= h
+            if val != 0.0 or b[k, j, i] != 0.0:
+                assert abs(b[k, j, i] - val) <= 1e-11 * bmax, (i, j, k)
+
+
+def test_pressure_residual_property(run):
+    wl = run["wl"]
+    p, b, beta = run["p"], run["b"], run["beta"]
+    r = b - poisson.apply_A(p, beta, wl.h)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
+    assert abs(p.mean()) <= 1e-12 * np.abs(p).max()
+
+
+def test_velocity_update_sampled_faces(run):
+    wl = run["wl"]
+    h, dt = wl.h, wl.dt
+    p, F, beta, u = run["p"], run["F"], run["beta"], run["u"]
+    rng = np.random.default_rng(9)
+    scale = dt * max(np.abs(beta[d] * F[d]).max() for d in range(3))
+    for _ in range(2000):
+        k, j, i = (int(x) for x in rng.integers(0, 256, size=3))
+        for dd in range(3):
+            km, jm, im = k - (dd == 2), j - (dd == 1), i - (dd == 0)
+            ref = dt * beta[dd][k, j, i] * (F[dd][k, j, i] - (p[k, j, i] - p[km, jm, im]) / h)
+            assert abs(u[dd][k, j, i] - ref) <= 1e-12 * scale
+
+
+def test_interp_full_size_sampled_markers(run):
+    ib, ctx, wl = run["ib"], run["ctx"], run["wl"]
+    u = W.random_faces(wl.n, 3, 1.0, seed=77)
+    ud = [torch.from_numpy(c).cuda() for c in u]
+    U = ctx.interp(ud, run["surf"]).cpu().numpy()
+    sel = np.random.default_rng(3).choice(len(wl.X), size=500, replace=False)
+    Uo = transfer.interp(u, wl.X[sel], wl.h)
+    assert np.max(np.abs(U[sel] - Uo)) <= 1e-13
