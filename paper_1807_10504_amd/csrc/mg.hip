@@ -201,13 +201,24 @@ __global__ void k_rbgs(T* __restrict__ p, const T* __restrict__ b, const T* __re
 // new red values. Each array is read from memory about once per sweep (halos come
 // from L2: consecutive workgroups of one XCD get neighbouring tiles).
 constexpr int kFTX = 32, kFTY = 8;
-constexpr int kFRX = kFTX + 4, kFRY = kFTY + 4, kFRN = kFRX * kFRY;
+constexpr int kFRX = kFTX + 4, kFRY = kFTY + 4, kFRN = kFRX * kFRY;   // p: tile + 2-cell halo
+// coefficient planes are staged on the smaller regions the updates read:
+// beta_x on x in [1, RX), y in [1, RY-1); beta_y on x in [1, RX-1), y in [1, RY);
+// beta_z and b on the one-cell ring x in [1, RX-1), y in [1, RY-1)
+constexpr int kFXW = kFRX - 1, kFXN = kFXW * (kFRY - 2);
+constexpr int kFYW = kFRX - 2, kFYN = kFYW * (kFRY - 1);
+constexpr int kFZW = kFRX - 2, kFZN = kFZW * (kFRY - 2);
 constexpr int kFLoads = (kFRN + kBlock - 1) / kBlock;
+constexpr int kFXLoads = (kFXN + kBlock - 1) / kBlock;
+constexpr int kFYLoads = (kFYN + kBlock - 1) / kBlock;
+constexpr int kFZLoads = (kFZN + kBlock - 1) / kBlock;
 
 // barrier for LDS traffic only: global loads issued before it stay in flight
 __device__ __forceinline__ void lds_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
+
+__device__ __forceinline__ int mod3(int k) { return ((k % 3) + 3) % 3; }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin, T* __restrict__ pout,
@@ -215,10 +226,10 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
                                                        const T* __restrict__ by, const T* __restrict__ bz,
                                                        Dims d, T h2, int TZ, int ntx, int nty, int nzc) {
     __shared__ T P[4][kFRN];
-    __shared__ T BX[2][kFRN];
-    __shared__ T BY[2][kFRN];
-    __shared__ T BZ[4][kFRN];
-    __shared__ T B[2][kFRN];
+    __shared__ T BX[2][kFXN];
+    __shared__ T BY[2][kFYN];
+    __shared__ T BZ[3][kFZN];
+    __shared__ T B[2][kFZN];
     const int nw = ntx * nty * nzc;
     const int bid = blockIdx.x;
     // blocks are dealt round-robin to the 8 XCDs: give each XCD a contiguous
@@ -232,116 +243,124 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
     const int z0 = zc * TZ, z1 = z0 + TZ;
     const long plane = (long)d.nx * d.ny;
     const int t = threadIdx.x;
-    long goff[kFLoads];
+    auto gofs = [&](int x, int y) { return wrap(j0 + y, d.ny) * d.nx + wrap(i0 + x, d.nx); };
+    int gp[kFLoads], gx[kFXLoads], gy[kFYLoads], gz[kFZLoads];
 #pragma unroll
     for (int s = 0; s < kFLoads; ++s) {
         int q = t + s * kBlock;
-        goff[s] = -1;
-        if (q < kFRN) {
-            int x = q % kFRX, y = q / kFRX;
-            goff[s] = (long)wrap(j0 + y, d.ny) * d.nx + wrap(i0 + x, d.nx);
-        }
+        gp[s] = q < kFRN ? gofs(q % kFRX, q / kFRX) : -1;
+    }
+#pragma unroll
+    for (int s = 0; s < kFXLoads; ++s) {
+        int q = t + s * kBlock;
+        gx[s] = q < kFXN ? gofs(1 + q % kFXW, 1 + q / kFXW) : -1;
+    }
+#pragma unroll
+    for (int s = 0; s < kFYLoads; ++s) {
+        int q = t + s * kBlock;
+        gy[s] = q < kFYN ? gofs(1 + q % kFYW, 1 + q / kFYW) : -1;
+    }
+#pragma unroll
+    for (int s = 0; s < kFZLoads; ++s) {
+        int q = t + s * kBlock;
+        gz[s] = q < kFZN ? gofs(1 + q % kFZW, 1 + q / kFZW) : -1;
     }
     auto pl = [&](int k) { return (long)wrap(k, d.nz) * plane; };
-    auto load = [&](T* dst, const T* src, int k) {
-        long base = pl(k);
-#pragma unroll
-        for (int s = 0; s < kFLoads; ++s)
-            if (goff[s] >= 0) dst[t + s * kBlock] = src[base + goff[s]];
-    };
     // registers holding the planes of the next step: p(k+1), beta_x/y(k), b(k), beta_z(k+1)
-    T rp[kFLoads], rx[kFLoads], ry[kFLoads], rb[kFLoads], rz[kFLoads];
+    T rp[kFLoads], rx[kFXLoads], ry[kFYLoads], rb[kFZLoads], rz[kFZLoads];
     auto fetch = [&](int k) {
         long bp = pl(k + 1), bk = pl(k);
 #pragma unroll
         for (int s = 0; s < kFLoads; ++s)
-            if (goff[s] >= 0) {
-                rp[s] = pin[bp + goff[s]];
-                rz[s] = bz[bp + goff[s]];
-                rx[s] = bx[bk + goff[s]];
-                ry[s] = by[bk + goff[s]];
-                rb[s] = bb[bk + goff[s]];
+            if (gp[s] >= 0) rp[s] = pin[bp + gp[s]];
+#pragma unroll
+        for (int s = 0; s < kFXLoads; ++s)
+            if (gx[s] >= 0) rx[s] = bx[bk + gx[s]];
+#pragma unroll
+        for (int s = 0; s < kFYLoads; ++s)
+            if (gy[s] >= 0) ry[s] = by[bk + gy[s]];
+#pragma unroll
+        for (int s = 0; s < kFZLoads; ++s)
+            if (gz[s] >= 0) {
+                rb[s] = bb[bk + gz[s]];
+                rz[s] = bz[bp + gz[s]];
             }
     };
     auto commit = [&](int k) {
 #pragma unroll
         for (int s = 0; s < kFLoads; ++s)
-            if (goff[s] >= 0) {
-                int q = t + s * kBlock;
-                P[(k + 1) & 3][q] = rp[s];
-                BZ[(k + 1) & 3][q] = rz[s];
-                BX[k & 1][q] = rx[s];
-                BY[k & 1][q] = ry[s];
-                B[k & 1][q] = rb[s];
+            if (gp[s] >= 0) P[(k + 1) & 3][t + s * kBlock] = rp[s];
+#pragma unroll
+        for (int s = 0; s < kFXLoads; ++s)
+            if (gx[s] >= 0) BX[k & 1][t + s * kBlock] = rx[s];
+#pragma unroll
+        for (int s = 0; s < kFYLoads; ++s)
+            if (gy[s] >= 0) BY[k & 1][t + s * kBlock] = ry[s];
+#pragma unroll
+        for (int s = 0; s < kFZLoads; ++s)
+            if (gz[s] >= 0) {
+                B[k & 1][t + s * kBlock] = rb[s];
+                BZ[mod3(k + 1)][t + s * kBlock] = rz[s];
             }
     };
-    load(P[(z0 - 2) & 3], pin, z0 - 2);
-    load(P[(z0 - 1) & 3], pin, z0 - 1);
-    load(BZ[(z0 - 1) & 3], bz, z0 - 1);
+    {
+        long a = pl(z0 - 2), a1 = pl(z0 - 1);
+#pragma unroll
+        for (int s = 0; s < kFLoads; ++s)
+            if (gp[s] >= 0) {
+                P[(z0 - 2) & 3][t + s * kBlock] = pin[a + gp[s]];
+                P[(z0 - 1) & 3][t + s * kBlock] = pin[a1 + gp[s]];
+            }
+#pragma unroll
+        for (int s = 0; s < kFZLoads; ++s)
+            if (gz[s] >= 0) BZ[mod3(z0 - 1)][t + s * kBlock] = bz[a1 + gz[s]];
+    }
     fetch(z0 - 1);
+    // one cell update at region position (x, y) of plane kk
+    auto update = [&](int x, int y, int kk) {
+        const int c = y * kFRX + x;
+        const int ix = (y - 1) * kFXW + (x - 1);
+        const int iz = (y - 1) * kFZW + (x - 1);
+        T* Pc = P[kk & 3];
+        const T* Pd = P[(kk - 1) & 3];
+        const T* Pu = P[(kk + 1) & 3];
+        const T* X = BX[kk & 1];
+        const T* Y = BY[kk & 1];
+        T br = X[ix + 1], bl = X[ix];
+        T num = br * Pc[c + 1] + bl * Pc[c - 1];
+        T diag = br + bl;
+        br = Y[iz + kFYW];
+        bl = Y[iz];
+        num += br * Pc[c + kFRX] + bl * Pc[c - kFRX];
+        diag += br + bl;
+        br = BZ[mod3(kk + 1)][iz];
+        bl = BZ[mod3(kk)][iz];
+        num += br * Pu[c] + bl * Pd[c];
+        diag += br + bl;
+        Pc[c] = (num - h2 * B[kk & 1][iz]) / diag;
+    };
     const int rw = kFRX - 2, rh = kFRY - 2;
     for (int k = z0 - 1; k <= z1; ++k) {
         commit(k);
         if (k < z1) fetch(k + 1);  // in flight during this step
         lds_barrier();
         // red cells of plane k on the tile and its one-cell ring
-        {
-            T* Pc = P[k & 3];
-            const T* Pd = P[(k - 1) & 3];
-            const T* Pu = P[(k + 1) & 3];
-            const T* X = BX[k & 1];
-            const T* Y = BY[k & 1];
-            const T* Zl = BZ[k & 3];
-            const T* Zr = BZ[(k + 1) & 3];
-            const T* Bc = B[k & 1];
-            for (int q = t; q < rw * rh; q += kBlock) {
-                int x = 1 + q % rw, y = 1 + q / rw;
-                if (((i0 + x) + (j0 + y) + k) & 1) continue;
-                int c = y * kFRX + x;
-                T br = X[c + 1], bl = X[c];
-                T num = br * Pc[c + 1] + bl * Pc[c - 1];
-                T diag = br + bl;
-                br = Y[c + kFRX];
-                bl = Y[c];
-                num += br * Pc[c + kFRX] + bl * Pc[c - kFRX];
-                diag += br + bl;
-                br = Zr[c];
-                bl = Zl[c];
-                num += br * Pu[c] + bl * Pd[c];
-                diag += br + bl;
-                Pc[c] = (num - h2 * Bc[c]) / diag;
-            }
+        for (int q = t; q < rw * rh; q += kBlock) {
+            int x = 1 + q % rw, y = 1 + q / rw;
+            if (((i0 + x) + (j0 + y) + k) & 1) continue;
+            update(x, y, k);
         }
         lds_barrier();
         const int kb = k - 1;
         if (kb >= z0 && kb < z1) {
             // black cells of plane k - 1 on the tile
-            T* Pc = P[kb & 3];
-            const T* Pd = P[(kb - 1) & 3];
-            const T* Pu = P[(kb + 1) & 3];
-            const T* X = BX[kb & 1];
-            const T* Y = BY[kb & 1];
-            const T* Zl = BZ[kb & 3];
-            const T* Zr = BZ[(kb + 1) & 3];
-            const T* Bc = B[kb & 1];
             for (int q = t; q < kFTX * kFTY; q += kBlock) {
                 int x = 2 + q % kFTX, y = 2 + q / kFTX;
                 if ((((i0 + x) + (j0 + y) + kb) & 1) == 0) continue;
-                int c = y * kFRX + x;
-                T br = X[c + 1], bl = X[c];
-                T num = br * Pc[c + 1] + bl * Pc[c - 1];
-                T diag = br + bl;
-                br = Y[c + kFRX];
-                bl = Y[c];
-                num += br * Pc[c + kFRX] + bl * Pc[c - kFRX];
-                diag += br + bl;
-                br = Zr[c];
-                bl = Zl[c];
-                num += br * Pu[c] + bl * Pd[c];
-                diag += br + bl;
-                Pc[c] = (num - h2 * Bc[c]) / diag;
+                update(x, y, kb);
             }
             lds_barrier();
+            const T* Pc = P[kb & 3];
             long base = pl(kb) + (long)(j0 + 2) * d.nx + (i0 + 2);
             for (int q = t; q < kFTX * kFTY; q += kBlock) {
                 int x = q % kFTX, y = q / kFTX;
