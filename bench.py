@@ -101,6 +101,100 @@ def run_variant(ib, torch, wl, geo, precision, steps, warmup, profile, warm=Fals
                 dP=d["dP"], tke=d["tke"])
 
 
+def bench_2d_c2(ib, torch, steps=200):
+    """512^2 jittered static drop, warm-started steps: FP64 vs mixed multigrid."""
+    from paper_1807_10504_amd import workloads as W
+    wl = W.static_drop_2d_512()
+    shape = tuple(reversed(wl.n))
+    out = {}
+    for name, prec in (("fp64", ib.MG_FP64), ("mixed", ib.MG_MIXED)):
+        ctx = ib.Context(2, wl.n, wl.h, max_markers=len(wl.X))
+        mg = ib.Multigrid(2, wl.n, wl.h, precision=prec)
+        X = wl.X.copy()
+        u = [torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(2)]
+        p_prev = None
+        prm = dict(rho_in=wl.rho_in, rho_out=wl.rho_out, sigma=wl.sigma, dt=wl.dt, rtol=1e-10)
+        cyc = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            o = ctx.project_step(mg, prm, u, p_prev=p_prev, X_host=X)
+            u, p_prev = o["u"], o["p"]
+            cyc.append(o["stats"]["cycles"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        d = ctx.diagnostics(p=p_prev, u=u)
+        out[name] = dict(steps_per_s=round(steps / dt, 2), mean_cycles=float(np.mean(cyc)),
+                         tke=d["tke"], p=p_prev.cpu().numpy())
+    diff = float(np.linalg.norm(out["mixed"].pop("p") - out["fp64"]["p"]) / np.linalg.norm(out["fp64"]["p"]))
+    out["fp64"].pop("p")
+    out["mixed_vs_fp64_p_rel_l2_after_steps"] = diff
+    out["workload"] = (f"static_drop_2d_512: 512^2, R=0.2, 1024 markers with 1e-3 R seeded jitter, rho ratio "
+                       f"1000, dt=2e-5, {steps} steps warm-started from p_prev, B-spline relocation each step")
+    return out
+
+
+def bench_2d_c4_nn(ib, torch, n=512, steps=48, train_iters=300):
+    """Learned warm start: oscillating drop (mode 2, amplitude 0.1), projection-only
+    dynamics; the network is trained on pairs the multigrid generates and judged
+    on held-out steps against a zero start (cold) and against p_prev (warm)."""
+    from paper_1807_10504_amd import workloads as W
+    h = 1.0 / n
+    shape = (n, n)
+    X = W.mode_shape(1024, 0.2, 0.1)
+    ctx = ib.Context(2, (n, n), h, max_markers=len(X))
+    mg = ib.Multigrid(2, (n, n), h)
+    u = [torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(2)]
+    prm = dict(rho_in=1.0, rho_out=1e-3, sigma=1.0, dt=2e-5, rtol=1e-10, warm_start=ib.WS_PREV)
+    p_prev, samples = None, []
+    t0 = time.perf_counter()
+    for s in range(steps):
+        o = dict(b=torch.empty(shape, dtype=torch.float64, device="cuda"),
+                 H=torch.empty(shape, dtype=torch.float64, device="cuda"))
+        pp = p_prev.clone() if p_prev is not None else torch.zeros(shape, dtype=torch.float64, device="cuda")
+        o = ctx.project_step(mg, prm, u, p_prev=p_prev, X_host=X, out=o)
+        samples.append((o["b"], o["H"], pp, o["p"].clone()))
+        u, p_prev = o["u"], o["p"]
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    train, held = samples[4:steps - 8], samples[steps - 8:]
+    net = ib.Network((n, n), h)
+    net.set_params(W.network_init(1))
+    rng = np.random.default_rng(1)
+    t0 = time.perf_counter()
+    losses = []
+    for it in range(train_iters):
+        idx = rng.choice(len(train), size=4, replace=False)
+        losses.append(net.train_step([(train[i][0], train[i][1], None, train[i][3]) for i in idx],
+                                     1.0, 1e-3, 2e-3))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    cyc_nn, cyc_zero, t_nn, t_zero = [], [], 0.0, 0.0
+    for (b, H, pp, p) in held:
+        beta = ctx.coefficients(H, 1.0, 1e-3)
+        mg.update_coeffs(beta)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = net.predict(b, H, None, 1.0, 1e-3)
+        s1 = mg.solve(b, g, rtol=1e-10)
+        torch.cuda.synchronize()
+        t_nn += time.perf_counter() - t0
+        z = torch.zeros_like(p)
+        t0 = time.perf_counter()
+        s2 = mg.solve(b, z, rtol=1e-10)
+        torch.cuda.synchronize()
+        t_zero += time.perf_counter() - t0
+        cyc_nn.append(s1["cycles"])
+        cyc_zero.append(s2["cycles"])
+    return dict(workload=f"oscillating drop 2D {n}^2, r=R(1+0.1cos2theta), R=0.2, 1024 markers, rho ratio 1000, "
+                         f"dt=2e-5, {steps} projection steps -> {len(train)} training pairs, {len(held)} held out",
+                pairs_s=round(t_pairs, 2), train_s=round(t_train, 2),
+                loss_first=float(np.mean(losses[:5])), loss_last=float(np.mean(losses[-20:])),
+                cold_cycles_zero=float(np.mean(cyc_zero)), cold_cycles_nn=float(np.mean(cyc_nn)),
+                cold_solve_ms_zero=round(1e3 * t_zero / len(held), 3),
+                cold_solve_ms_nn_incl_inference=round(1e3 * t_nn / len(held), 3))
+
+
 def cpu_baseline(wl, cycles_per_step):
     """The oracle on a bounded sample of the same 256^3 step, extrapolated to one step."""
     from oracle import heaviside, poisson
@@ -145,10 +239,24 @@ def cpu_baseline(wl, cycles_per_step):
     tH = time.perf_counter() - t0
     ncols = math.pi * (0.25 + 2 * h) ** 2 / h ** 2
     t["heaviside"] = tH / len(cols) * ncols
-    per_step = t["grid_ops"] + t["heaviside"] + cycles_per_step * t["vcycle"]
+    # face force: nearest-element search for sampled faces next to the surface,
+    # scaled by the faces of a shell of +-2.9h (where H differences live)
+    from oracle import force, surface3d
+    fs_o = surface3d.surface_geometry(V, T, wl.sigma)[0]
+    dirs = rng.standard_normal((40, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    pts = 0.5 + (0.25 + rng.uniform(-2.5, 2.5, size=(40, 1)) * h) * dirs
+    t0 = time.perf_counter()
+    for q in pts:
+        force.nearest_on_mesh(q, V, T, fs_o)
+    tF = time.perf_counter() - t0
+    nfaces = 3 * 4 * math.pi * 0.25 ** 2 * 5.8 * h / h ** 3
+    t["face_force"] = tF / len(pts) * nfaces
+    per_step = t["grid_ops"] + t["heaviside"] + t["face_force"] + cycles_per_step * t["vcycle"]
     sample = (f"256^3 oracle: one FP64 V-cycle ({t['vcycle']:.1f} s) x {cycles_per_step:.1f} cycles/step, "
               f"coefficients+rhs+update ({t['grid_ops']:.1f} s), Heaviside on {len(cols)} columns scaled to "
-              f"{ncols:.0f} columns ({t['heaviside']:.0f} s); nearest-element face force not included")
+              f"{ncols:.0f} columns ({t['heaviside']:.0f} s), nearest-element face value on 40 faces scaled "
+              f"to {nfaces:.0f} band faces ({t['face_force']:.0f} s)")
     return dict(value=1.0 / per_step, unit="steps/s", cores=1, kind="oracle", sample=sample,
                 seconds_per_step=per_step, breakdown={k: round(v, 2) for k, v in t.items()})
 
@@ -163,6 +271,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-warm", action="store_true")
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2D workloads (C2, learned warm start)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MB (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -241,6 +350,11 @@ def main():
                                      f"irrotational spreading, FP64 multigrid V(2,2) from p=0 to 1e-10 every step",
                             grid=list(wl.n), markers=len(wl.X), triangles=len(wl.tris)),
                 variants=variants, roofline=roof, kernels_fp64=prof_summary)
+    if not args.no_2d:
+        log("== 2D 512^2 jittered drop: FP64 vs mixed, 200 steps")
+        line["c2_2d"] = bench_2d_c2(ib, torch)
+        log("== 2D 512^2 learned warm start")
+        line["nn_2d"] = bench_2d_c4_nn(ib, torch)
     if not args.no_cpu_baseline:
         log("== CPU oracle baseline (bounded sample)")
         line["cpu_baseline"] = cpu_baseline(wl, variants["fp64_cold"]["mean_cycles"])

@@ -160,7 +160,8 @@ typedef struct {
     int cycles;              /* V-cycles (outer iterations in MG_MIXED) performed */
     double rel_res0;         /* ||b - A p0|| / ||b|| of the initial guess */
     double rel_res;          /* final ||b - A p|| / ||b|| */
-    double res_hist[128];    /* rel_res after each cycle (first 128) */
+    double res_hist[128];    /* rel_res after each cycle (first 128); -1 for cycles run
+                                without a check (the solver skips norms it can predict) */
 } mg_stats;
 
 /* Allocates the hierarchy. Errors: IB_EINVAL (grid not n_coarsest * 2^L), IB_ENOMEM. */

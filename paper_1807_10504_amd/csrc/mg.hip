@@ -787,7 +787,7 @@ static int fp64_norms(mg_handle* m, bool want_b, hipStream_t st) {
     return IB_OK;
 }
 
-static int mixed_defect(mg_handle* m, bool want_b, hipStream_t st) {
+static int mixed_defect(mg_handle* m, bool want_b, hipStream_t st, bool sync = true) {
     Level& L = m->lv[0];
     long N = L.d.cells();
     int nb = red_blocks(N);
@@ -803,6 +803,7 @@ static int mixed_defect(mg_handle* m, bool want_b, hipStream_t st) {
         hipLaunchKernelGGL((k_defect_f32<3>), dim3(nb), dim3(kBlock), 0, st, L.f64.p, L.f64.b,
                            L.f64.beta[0], L.f64.beta[1], L.f64.beta[2], L.d, inv_h2, L.f32.b, pr, pb);
     }
+    if (!sync) return IB_OK;
     IB_TRY(device_sum(pr, nb, m->red + 3 * kRed, st));
     if (want_b) IB_TRY(device_sum(pb, nb, m->red + 3 * kRed + 1, st));
     IB_HIP(hipMemcpyAsync(m->host, m->red + 3 * kRed, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
@@ -1031,6 +1032,12 @@ extern "C" int mg_solve(mg_handle* m, const double* b, double* p, double rtol, i
     S->rel_res0 = rel;
     S->rel_res = rel;
     int cycles = 0;
+    // residual checks: after two measured contraction factors the solver
+    // predicts how many cycles remain and skips the norm (and its host sync)
+    // until two cycles before the predicted end; it always checks before
+    // stopping, so the stopping test is unchanged
+    int skip = 0, last_check = 0, checks = 0;
+    double rel_check = rel;
     while (true) {
         if (!std::isfinite(rel)) return fail(IB_ENAN, "mg_solve: residual is not finite");
         if (fixed_cycles > 0 ? cycles >= fixed_cycles : rel <= rtol) break;
@@ -1039,6 +1046,7 @@ extern "C" int mg_solve(mg_handle* m, const double* b, double* p, double rtol, i
             IB_TRY(remove_mean(m, false, st));
             return fail(IB_ENOTCONV, "mg_solve: no convergence within max_cycles");
         }
+        const bool check = fixed_cycles > 0 || skip == 0 || cycles + 1 >= max_cycles;
         // A annihilates constants and every step of a cycle commutes with adding
         // one, so the mean is removed once, after the last cycle
         if (mixed) {
@@ -1047,16 +1055,31 @@ extern "C" int mg_solve(mg_handle* m, const double* b, double* p, double rtol, i
             int nb = red_blocks(N);
             hipLaunchKernelGGL(k_correct_f32, dim3(nb), dim3(kBlock), 0, st, p, L0.f32.p, N,
                                m->red + 2 * kRed);
-            IB_TRY(mixed_defect(m, false, st));
+            IB_TRY(mixed_defect(m, false, st, check));
         } else {
             vcycle<double>(m, 0, st);
-            IB_TRY(fp64_norms(m, false, st));
+            if (check) IB_TRY(fp64_norms(m, false, st));
         }
-        rel = std::sqrt(m->host[0]) / bnorm;
-        if (cycles < 128) S->res_hist[cycles] = rel;
         ++cycles;
         S->cycles = cycles;
+        if (!check) {
+            --skip;
+            if (cycles <= 128) S->res_hist[cycles - 1] = -1.0;
+            continue;
+        }
+        rel = std::sqrt(m->host[0]) / bnorm;
+        if (cycles <= 128) S->res_hist[cycles - 1] = rel;
         S->rel_res = rel;
+        ++checks;
+        if (fixed_cycles == 0 && checks >= 3 && rel > rtol && rel < rel_check) {
+            double rho = std::pow(rel / rel_check, 1.0 / (double)(cycles - last_check));
+            if (rho < 0.9) {
+                int need = (int)std::ceil(std::log(rtol / rel) / std::log(rho));
+                skip = std::max(0, need - 2);
+            }
+        }
+        rel_check = rel;
+        last_check = cycles;
     }
     if (cycles > 0) IB_TRY(remove_mean(m, false, st));
     IB_HIP(hipGetLastError());

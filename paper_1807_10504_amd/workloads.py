@@ -145,6 +145,20 @@ def random_cells(n, dim: int, scale: float, seed: int):
     return scale * rng.standard_normal(tuple(reversed(n[:dim])))
 
 
+def network_init(seed: int, channels=(3, 32, 32, 32, 32, 32, 1)) -> np.ndarray:
+    """Seeded He-normal initial weights of the warm-start network, flat float32
+    in the library's parameter layout (per layer W[co][ci][ky][kx] then b[co];
+    the last layer is scaled down so that the first guesses stay near p_prev)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for l in range(6):
+        ci, co = channels[l], channels[l + 1]
+        std = np.sqrt(2.0 / (ci * 9)) if l < 5 else 0.1 * np.sqrt(1.0 / (ci * 9))
+        parts.append((rng.standard_normal(co * ci * 9) * std).astype(np.float32))
+        parts.append(np.zeros(co, dtype=np.float32))
+    return np.concatenate(parts)
+
+
 # ----------------------------------------------------------------------------
 # Named workloads
 # ----------------------------------------------------------------------------
