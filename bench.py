@@ -34,8 +34,11 @@ import numpy as np  # noqa: E402
 METRIC = "projection steps/s @256³, ρ ratio 1000, resid≤1e-10; FP64 vs mixed+NN"
 HBM_PEAK_GBS = 8000.0
 # one red-black sweep reads p, b and three face coefficients and writes p:
-# 6 x 8 bytes per cell (float64); one launch updates one colour = half a sweep
+# 6 x 8 bytes per cell (float64); one launch updates one colour = half a sweep.
+# The sweep that forms the coefficients from cell densities reads p, b, rho
+# and writes p: 4 x 8 bytes per cell.
 SWEEP_BYTES_F64 = 48.0
+SWEEP_BYTES_F64_RHO = 32.0
 SWEEP_BYTES_F32 = 24.0
 
 
@@ -290,10 +293,11 @@ def main():
     log(f"workload {wl.name}: {len(wl.X)} markers, {len(wl.tris)} triangles")
     geo = ib.surface_geometry_3d(wl.X, wl.tris, wl.sigma)
     if args.copy_mb:
+        # an elementwise kernel (not a DMA blit): reads 8 B and writes 8 B per element
         a = torch.ones(args.copy_mb * (1 << 20) // 8, dtype=torch.float64, device="cuda")
         c = torch.empty_like(a)
         for _ in range(3):
-            c.copy_(a)
+            torch.mul(a, 2.0, out=c)
         torch.cuda.synchronize()
         del a, c
 
@@ -324,7 +328,11 @@ def main():
     # roofline of the dominant kernel: the finest-level FP64 smoother, either
     # one full single-pass sweep or one colour pass (half a sweep)
     N = float(np.prod(wl.n))
-    if r64["prof"]["sweep64"][0]:
+    if r64["prof"]["sweep64_rho"][0]:
+        nl, ms = r64["prof"]["sweep64_rho"]
+        bytes_per_launch = SWEEP_BYTES_F64_RHO * N
+        kname = "k_rbgs_fused_rho (finest level, one full red-black sweep, coefficients from rho)"
+    elif r64["prof"]["sweep64"][0]:
         nl, ms = r64["prof"]["sweep64"]
         bytes_per_launch = SWEEP_BYTES_F64 * N
         kname = "k_rbgs_fused<double> (finest level, one full red-black sweep)"

@@ -129,6 +129,13 @@ int ib_spread(ib_ctx* ctx, const ib_surface* s, int mode, double* const F[3], do
 int ib_coefficients(ib_ctx* ctx, const double* H, double rho_in, double rho_out,
                     double* const beta[3], void* stream);
 
+/* a6 -- the cell densities alone, rho_c = rho_out + (rho_in - rho_out) H_c
+ * (eq indicator with I = H), rounded as in ib_coefficients (a separate
+ * multiply and add), so that 2/(rho_c + rho_{c-e_d}) is bitwise beta_d[c].
+ * H, rho: device cell arrays. */
+int ib_density(ib_ctx* ctx, const double* H, double rho_in, double rho_out, double* rho,
+               void* stream);
+
 /* a7 -- right side (eqs ps, ns2_new):
  * b_c = (1/h) sum_d [w_d(c+e_d) - w_d(c)], w = u_star / dt + beta F, mean removed. */
 int ib_rhs(ib_ctx* ctx, const double* const u_star[3], const double* const F[3],
@@ -147,7 +154,8 @@ int ib_update(ib_ctx* ctx, const double* const u_star[3], const double* const F[
  * index sum even, first), restriction = mean of the 2^dim children,
  * prolongation = cell-centred (bi/tri)linear, coarse face coefficient = mean
  * of the fine faces on it, coarsest n_coarsest^dim grid solved exactly with
- * the zero-mean constraint, mean removed after every cycle.
+ * the zero-mean constraint, mean removed once after the last cycle (a cycle
+ * commutes with adding a constant).
  * MG_MIXED: float32 V-cycles on the float64 defect r = b - A p (float64
  * residual, update and coarsest solve), same stopping test. */
 typedef struct {
@@ -171,6 +179,16 @@ int  mg_setup(const ib_grid* g, const mg_opts* o, mg_handle** out);
  * while mg_solve runs. Coarsens the coefficients and factorises the coarsest
  * grid. */
 int  mg_update_coeffs(mg_handle* m, const double* const beta[3], void* stream);
+/* The same from cell densities (device cell array, from ib_density): the
+ * finest face coefficient is beta_d[c] = 2/(rho_c + rho_{c-e_d}) (eq
+ * indicator, the face density being the mean of its two cells), bitwise the
+ * mg_update_coeffs hierarchy for the beta of ib_coefficients. The handle keeps
+ * the pointer (no copy) until the next update. On 3D grids with x a multiple
+ * of 64, y of 8, at least 128^3 cells and one coarse level, the finest-level
+ * kernels form the coefficients from rho where they use them (one array read
+ * instead of three); on other grids the face arrays are formed once into
+ * storage of the handle (IB_ENOMEM if that allocation fails). */
+int  mg_update_density(mg_handle* m, const double* rho, void* stream);
 /* b: device cell array (zero mean); p: device cell array, in: initial guess,
  * out: zero-mean solution. Stops when ||b - A p||_2 / ||b||_2 <= rtol or after
  * max_cycles (IB_ENOTCONV); fixed_cycles > 0 instead runs exactly that many
@@ -278,7 +296,9 @@ int ib_diagnostics(ib_ctx* ctx, const double* p, const double* H, const double* 
  *   IB_PROF_SMOOTH64 / IB_PROF_SMOOTH32 -- one colour of red-black Gauss-Seidel
  *     (levels smoothed colour by colour)
  *   IB_PROF_SWEEP64 / IB_PROF_SWEEP32 -- one full red-black sweep in a single
- *     pass (3D levels of at least 128^3 cells)
+ *     pass (3D levels of at least 128^3 cells), stored face coefficients
+ *   IB_PROF_SWEEP64_RHO -- the same float64 sweep forming the coefficients
+ *     from cell densities (mg_update_density)
  *   IB_PROF_RESTRICT64 / IB_PROF_RESTRICT32 -- residual + restriction
  *   IB_PROF_PROLONG64 / IB_PROF_PROLONG32 -- prolongation + correction
  *   IB_PROF_RESID -- float64 residual norm / defect
@@ -286,7 +306,7 @@ int ib_diagnostics(ib_ctx* ctx, const double* p, const double* H, const double* 
  * Process-wide; not thread safe. */
 enum { IB_PROF_SMOOTH64 = 0, IB_PROF_SMOOTH32, IB_PROF_RESTRICT64, IB_PROF_RESTRICT32,
        IB_PROF_PROLONG64, IB_PROF_PROLONG32, IB_PROF_RESID, IB_PROF_SWEEP64,
-       IB_PROF_SWEEP32, IB_PROF_KINDS };
+       IB_PROF_SWEEP32, IB_PROF_SWEEP64_RHO, IB_PROF_KINDS };
 void ib_profile_enable(int on);
 void ib_profile_reset(void);
 int  ib_profile_read(int kind, long long* launches, double* total_ms);

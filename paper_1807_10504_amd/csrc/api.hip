@@ -55,7 +55,7 @@ static int free_ctx(ib_ctx* c) {
     void* ptrs[] = {c->bin_key, c->bin_idx, c->bin_key_sorted, c->bin_order, c->tile_start,
                     c->sort_tmp, c->accA, c->accS, c->best, c->offv, c->mX, c->mfs, c->mds,
                     c->mnrm, c->H, c->F[0], c->F[1], c->F[2], c->beta[0], c->beta[1],
-                    c->beta[2], c->b, c->flags, c->red};
+                    c->beta[2], c->rho, c->b, c->flags, c->red};
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (c->host_red) hipHostFree(c->host_red);
@@ -122,6 +122,7 @@ extern "C" int ib_create(const ib_grid* g, int max_markers, int max_elems, ib_ct
         alloc((void**)&c->F[e], cells * sizeof(double));
         alloc((void**)&c->beta[e], cells * sizeof(double));
     }
+    alloc((void**)&c->rho, cells * sizeof(double));
     alloc((void**)&c->b, cells * sizeof(double));
     alloc((void**)&c->flags, 4 * sizeof(int));
     c->red_len = 4096;
@@ -202,7 +203,14 @@ extern "C" int ib_coefficients(ib_ctx* c, const double* H, double rin, double ro
                                double* const beta[3], void* stream) {
     IB_CHECK(c && H && beta, IB_EINVAL, "ib_coefficients: null argument");
     IB_CHECK(rin > 0 && rout > 0, IB_EINVAL, "ib_coefficients: densities must be positive");
-    return launch_coefficients(c, H, rin, rout, beta, (hipStream_t)stream);
+    return launch_coefficients(c, H, rin, rout, beta, nullptr, (hipStream_t)stream);
+}
+
+extern "C" int ib_density(ib_ctx* c, const double* H, double rin, double rout, double* rho,
+                          void* stream) {
+    IB_CHECK(c && H && rho, IB_EINVAL, "ib_density: null argument");
+    IB_CHECK(rin > 0 && rout > 0, IB_EINVAL, "ib_density: densities must be positive");
+    return launch_coefficients(c, H, rin, rout, nullptr, rho, (hipStream_t)stream);
 }
 
 extern "C" int ib_rhs(ib_ctx* c, const double* const us[3], const double* const F[3],
@@ -279,8 +287,9 @@ extern "C" int project_step(ib_ctx* c, mg_handle* m, const ib_params* prm, ib_st
              "project_step: spread mode");
     IB_TRY(spread_impl(c, &s, prm->spread_mode, F, H, st));
     // a6: coefficients, a8: hierarchy
-    IB_TRY(launch_coefficients(c, H, prm->rho_in, prm->rho_out, c->beta, st));
-    IB_TRY(mg_update_coeffs(m, c->beta, st));
+    IB_TRY(launch_coefficients(c, H, prm->rho_in, prm->rho_out, c->beta, c->rho, st));
+    if (mg_takes_density(m)) IB_TRY(mg_update_density(m, c->rho, st));
+    else IB_TRY(mg_update_coeffs(m, c->beta, st));
     // a7: right side
     const double* Fc[3] = {F[0], F[1], F[2]};
     const double* bc[3] = {c->beta[0], c->beta[1], c->beta[2]};

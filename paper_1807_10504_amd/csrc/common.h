@@ -63,6 +63,11 @@ __host__ __device__ inline int wrap(int i, int n) {
     return r < 0 ? r + n : r;
 }
 
+// the same for -n <= i < 2n, without a division
+__host__ __device__ inline int wrap_near(int i, int n) {
+    return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
 // fixed tree sum over one block (blockDim.x a power of two, sh of blockDim.x)
 __device__ inline double block_reduce_sum(double v, double* sh) {
     int t = threadIdx.x;
@@ -116,6 +121,7 @@ struct Ctx {
     double* H = nullptr;
     double* F[3] = {nullptr, nullptr, nullptr};
     double* beta[3] = {nullptr, nullptr, nullptr};
+    double* rho = nullptr;
     double* b = nullptr;
     // flags / scalars
     int* flags = nullptr;                // [0] geometry error, [1] band face without element
@@ -130,7 +136,9 @@ int launch_interp(Ctx* c, const double* const u[3], const ib_surface* s, double*
 int launch_spread_delta(Ctx* c, const ib_surface* s, double* const F[3], hipStream_t st);
 int launch_heaviside(Ctx* c, const ib_surface* s, double* H, hipStream_t st);
 int launch_irrot_force(Ctx* c, const ib_surface* s, const double* H, double* const F[3], hipStream_t st);
-int launch_coefficients(Ctx* c, const double* H, double rin, double rout, double* const beta[3], hipStream_t st);
+// beta (dim face arrays) and rho (cell densities) may each be null
+int launch_coefficients(Ctx* c, const double* H, double rin, double rout, double* const beta[3],
+                        double* rho, hipStream_t st);
 int launch_rhs(Ctx* c, const double* const us[3], const double* const F[3], const double* const beta[3],
                double dt, double* b, hipStream_t st);
 int launch_update(Ctx* c, const double* const us[3], const double* const F[3], const double* const beta[3],
@@ -143,3 +151,6 @@ int read_flags(Ctx* c, int* host_flags, hipStream_t st);
 int device_sum(const double* partials_in, int n, double* out_dev, hipStream_t st);
 
 }  // namespace ib
+
+// 1 when the multigrid's finest level reads cell densities directly (mg.hip)
+int mg_takes_density(const mg_handle* m);

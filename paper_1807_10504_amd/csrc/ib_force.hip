@@ -249,10 +249,17 @@ int launch_irrot_force(Ctx* c, const ib_surface* s, const double* H, double* con
 
 // ---------------------------------------------------------------------------
 // a6 coefficients
+// rho = rho_out + (rho_in - rho_out) H, multiply and add rounded separately
+// (no fused multiply-add), as the formula reads
+__device__ __forceinline__ double cell_density(double rout, double drho, double H) {
+#pragma clang fp contract(off)
+    return rout + drho * H;
+}
+
 template <int DIM>
 __global__ void k_coefficients(const double* __restrict__ H, Dims d, double rin, double rout,
                                double* __restrict__ b0, double* __restrict__ b1,
-                               double* __restrict__ b2) {
+                               double* __restrict__ b2, double* __restrict__ rho) {
     long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.cells()) return;
     int i = (int)(c % d.nx);
@@ -260,26 +267,31 @@ __global__ void k_coefficients(const double* __restrict__ H, Dims d, double rin,
     int j = (int)(r % d.ny);
     int k = (int)(r / d.ny);
     double drho = rin - rout;
-    double rc = rout + drho * H[c];
+    double rc = cell_density(rout, drho, H[c]);
+    if (rho) rho[c] = rc;
+    if (!b0) return;
     long cx = i == 0 ? c + d.nx - 1 : c - 1;
     long cy = j == 0 ? c + (long)(d.ny - 1) * d.nx : c - d.nx;
-    b0[c] = 2.0 / (rc + (rout + drho * H[cx]));
-    b1[c] = 2.0 / (rc + (rout + drho * H[cy]));
+    b0[c] = 2.0 / (rc + cell_density(rout, drho, H[cx]));
+    b1[c] = 2.0 / (rc + cell_density(rout, drho, H[cy]));
     if (DIM == 3) {
         long pl = (long)d.nx * d.ny;
         long cz = k == 0 ? c + (long)(d.nz - 1) * pl : c - pl;
-        b2[c] = 2.0 / (rc + (rout + drho * H[cz]));
+        b2[c] = 2.0 / (rc + cell_density(rout, drho, H[cz]));
     }
 }
 
 int launch_coefficients(Ctx* c, const double* H, double rin, double rout, double* const beta[3],
-                        hipStream_t st) {
+                        double* rho, hipStream_t st) {
+    double* b0 = beta ? beta[0] : nullptr;
+    double* b1 = beta ? beta[1] : nullptr;
+    double* b2 = beta ? beta[c->d.dim == 3 ? 2 : 1] : nullptr;
     if (c->d.dim == 2)
         hipLaunchKernelGGL(k_coefficients<2>, dim3(grid_for(c->d.cells())), dim3(kBlock), 0, st, H,
-                           c->d, rin, rout, beta[0], beta[1], beta[1]);
+                           c->d, rin, rout, b0, b1, b1, rho);
     else
         hipLaunchKernelGGL(k_coefficients<3>, dim3(grid_for(c->d.cells())), dim3(kBlock), 0, st, H,
-                           c->d, rin, rout, beta[0], beta[1], beta[2]);
+                           c->d, rin, rout, b0, b1, b2, rho);
     IB_HIP(hipGetLastError());
     return IB_OK;
 }

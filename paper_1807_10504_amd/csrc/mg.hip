@@ -17,10 +17,13 @@
 // p += e and the coarsest solve in float64.
 //
 // Memory layout: every level stores p, b and one coefficient array per axis
-// (left faces) as SoA with x fastest. Kernels are plain one-thread-per-cell
-// stencils; the stopping test reads one scalar per cycle.
+// (left faces) as SoA with x fastest; a finest level given by cell densities
+// (mg_update_density) keeps only rho and its float64 kernels form each face
+// coefficient where they use it. The smoother of large 3D levels is a
+// single-pass tiled sweep; the others are one-thread-per-cell stencils.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -42,6 +45,9 @@ struct Level {
     bool own_pb = true;
     bool fused = false;  // single-pass smoother applies
     int tz = 0;          // its z-range per workgroup
+    // finest level only: cell densities from which the float64 kernels form
+    // the face coefficients themselves (f64.beta is then unused)
+    const double* rho = nullptr;
 };
 
 }  // namespace ib
@@ -60,6 +66,9 @@ struct mg_handle {
     double* host = nullptr;     // pinned scalars
     // float64 buffers for the mixed defect loop are the caller's p and b
     bool coeffs_ready = false;
+    // finest face arrays formed from densities on grids whose kernels cannot
+    // read the densities directly
+    double* beta0[3] = {nullptr, nullptr, nullptr};
 };
 
 namespace ib {
@@ -146,16 +155,75 @@ __device__ __forceinline__ Nb neighbours(const Dims& d, int i, int j, int k, int
     return n;
 }
 
-template <typename T, int DIM>
-__device__ __forceinline__ T apply_row(const T* __restrict__ p, const T* __restrict__ b0,
-                                       const T* __restrict__ b1, const T* __restrict__ b2,
-                                       const Nb& n) {
-    // sum_d br (p_r - p) - bl (p - p_l), without the 1/h^2
-    T pc = p[n.c];
-    T s = b0[n.xp] * (p[n.xp] - pc) - b0[n.c] * (pc - p[n.xm]);
-    s += b1[n.yp] * (p[n.yp] - pc) - b1[n.c] * (pc - p[n.ym]);
-    if (DIM == 3) s += b2[n.zp] * (p[n.zp] - pc) - b2[n.c] * (pc - p[n.zm]);
+// Face coefficients of a level, read through one of two sources:
+// stored per axis (the face on the low side of each cell) ...
+template <typename T>
+struct CoefArrays {
+    const T* __restrict__ b0;
+    const T* __restrict__ b1;
+    const T* __restrict__ b2;
+    __device__ T xl(const Nb& n) const { return b0[n.c]; }
+    __device__ T xr(const Nb& n) const { return b0[n.xp]; }
+    __device__ T yl(const Nb& n) const { return b1[n.c]; }
+    __device__ T yr(const Nb& n) const { return b1[n.yp]; }
+    __device__ T zl(const Nb& n) const { return b2[n.c]; }
+    __device__ T zr(const Nb& n) const { return b2[n.zp]; }
+};
+
+// ... or formed from the cell densities, beta = 2 / (rho_hi + rho_lo) (the
+// inverse of the mean density of the two cells; eq indicator with I = H).
+// The operands and the division are those of the coefficient kernel, so the
+// values are bitwise the stored ones.
+struct CoefRho {
+    const double* __restrict__ rho;
+    __device__ double f(long hi, long lo) const { return 2.0 / (rho[hi] + rho[lo]); }
+    __device__ double xl(const Nb& n) const { return f(n.c, n.xm); }
+    __device__ double xr(const Nb& n) const { return f(n.xp, n.c); }
+    __device__ double yl(const Nb& n) const { return f(n.c, n.ym); }
+    __device__ double yr(const Nb& n) const { return f(n.yp, n.c); }
+    __device__ double zl(const Nb& n) const { return f(n.c, n.zm); }
+    __device__ double zr(const Nb& n) const { return f(n.zp, n.c); }
+};
+
+// densities: where all neighbours share the cell's density, every face is
+// 2 / (rho + rho) = 1 / rho exactly, and one division serves the six faces
+template <int DIM>
+__device__ __forceinline__ double apply_row_rho(const double* __restrict__ p, const CoefRho& co,
+                                                const Nb& n) {
+    const double* __restrict__ r = co.rho;
+    const double rc = r[n.c];
+    const double rxp = r[n.xp], rxm = r[n.xm], ryp = r[n.yp], rym = r[n.ym];
+    const double rzp = DIM == 3 ? r[n.zp] : rc, rzm = DIM == 3 ? r[n.zm] : rc;
+    double bxp, bxm, byp, bym, bzp, bzm;
+    if (rxp == rc && rxm == rc && ryp == rc && rym == rc && rzp == rc && rzm == rc) {
+        bxp = bxm = byp = bym = bzp = bzm = 1.0 / rc;
+    } else {
+        bxp = 2.0 / (rxp + rc);
+        bxm = 2.0 / (rc + rxm);
+        byp = 2.0 / (ryp + rc);
+        bym = 2.0 / (rc + rym);
+        bzp = 2.0 / (rzp + rc);
+        bzm = 2.0 / (rc + rzm);
+    }
+    const double pc = p[n.c];
+    double s = bxp * (p[n.xp] - pc) - bxm * (pc - p[n.xm]);
+    s += byp * (p[n.yp] - pc) - bym * (pc - p[n.ym]);
+    if (DIM == 3) s += bzp * (p[n.zp] - pc) - bzm * (pc - p[n.zm]);
     return s;
+}
+
+template <typename T, int DIM, class K>
+__device__ __forceinline__ T apply_row(const T* __restrict__ p, const K& co, const Nb& n) {
+    if constexpr (std::is_same<K, CoefRho>::value) {
+        return apply_row_rho<DIM>(p, co, n);
+    } else {
+        // sum_d br (p_r - p) - bl (p - p_l), without the 1/h^2
+        T pc = p[n.c];
+        T s = co.xr(n) * (p[n.xp] - pc) - co.xl(n) * (pc - p[n.xm]);
+        s += co.yr(n) * (p[n.yp] - pc) - co.yl(n) * (pc - p[n.ym]);
+        if (DIM == 3) s += co.zr(n) * (p[n.zp] - pc) - co.zl(n) * (pc - p[n.zm]);
+        return s;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -190,16 +258,19 @@ __global__ void k_rbgs(T* __restrict__ p, const T* __restrict__ b, const T* __re
 }
 
 // One full red-black sweep in a single pass (3D levels with nx % 32 == 0,
-// ny % 8 == 0). A workgroup owns a 32 x 8 column tile and a z-range [z0, z1)
-// and marches upward; at plane step k it updates the red cells of plane k
-// on the tile plus a one-cell ring, then the black cells of plane k - 1 on
-// the tile, then writes plane k - 1. Red values on the ring are recomputed
-// (the neighbour tile computes the same numbers from the same inputs), and p
-// is double-buffered (read pin, write pout), so workgroups never read what
-// another one writes during the sweep. It performs the same arithmetic as
-// the two-colour sweep: red reads only old black values, black reads only
-// new red values. Each array is read from memory about once per sweep (halos come
-// from L2: consecutive workgroups of one XCD get neighbouring tiles).
+// ny % 8 == 0, nz even). A workgroup owns a 32 x 8 column tile and an even
+// z-range [z0, z1) and marches upward; at plane step k it updates the red
+// cells of plane k on the tile plus a one-cell ring, then the black cells of
+// plane k - 1 on the tile, then writes plane k - 1. Red values on the ring are
+// recomputed (the neighbour tile computes the same numbers from the same
+// inputs), and p is double-buffered (read pin, write pout), so workgroups
+// never read what another one writes during the sweep. It performs the same
+// arithmetic as the two-colour sweep: red reads only old black values, black
+// reads only new red values. Lanes are dealt cells of the colour being
+// updated only. The planes of a step are loaded into registers two steps
+// ahead (two alternating stages) and staged in LDS at the step. Halo rows
+// and columns are re-read by the neighbouring tiles; consecutive workgroups
+// of one XCD get neighbouring tiles so that part of those reads hit its L2.
 constexpr int kFTX = 32, kFTY = 8;
 constexpr int kFRX = kFTX + 4, kFRY = kFTY + 4, kFRN = kFRX * kFRY;   // p: tile + 2-cell halo
 // coefficient planes are staged on the smaller regions the updates read:
@@ -208,6 +279,10 @@ constexpr int kFRX = kFTX + 4, kFRY = kFTY + 4, kFRN = kFRX * kFRY;   // p: tile
 constexpr int kFXW = kFRX - 1, kFXN = kFXW * (kFRY - 2);
 constexpr int kFYW = kFRX - 2, kFYN = kFYW * (kFRY - 1);
 constexpr int kFZW = kFRX - 2, kFZN = kFZW * (kFRY - 2);
+// red updates cover the one-cell ring region (kFRX - 2) x (kFRY - 2), black
+// updates the tile; each row holds half its cells of either colour
+constexpr int kFRedRow = (kFRX - 2) / 2, kFRedN = kFRedRow * (kFRY - 2);
+constexpr int kFBlackRow = kFTX / 2, kFBlackN = kFBlackRow * kFTY;
 constexpr int kFLoads = (kFRN + kBlock - 1) / kBlock;
 constexpr int kFXLoads = (kFXN + kBlock - 1) / kBlock;
 constexpr int kFYLoads = (kFYN + kBlock - 1) / kBlock;
@@ -243,79 +318,91 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
     const int z0 = zc * TZ, z1 = z0 + TZ;
     const long plane = (long)d.nx * d.ny;
     const int t = threadIdx.x;
-    auto gofs = [&](int x, int y) { return wrap(j0 + y, d.ny) * d.nx + wrap(i0 + x, d.nx); };
+    // tile origins are at least -2 and regions end within one period
+    auto gofs = [&](int x, int y) { return wrap_near(j0 + y, d.ny) * d.nx + wrap_near(i0 + x, d.nx); };
+    // every lane issues every load (slots past a region re-read its first
+    // cell and are not stored): unconditional loads give exact wait counts
     int gp[kFLoads], gx[kFXLoads], gy[kFYLoads], gz[kFZLoads];
+    bool vp[kFLoads], vx[kFXLoads], vy[kFYLoads], vz[kFZLoads];
 #pragma unroll
     for (int s = 0; s < kFLoads; ++s) {
         int q = t + s * kBlock;
-        gp[s] = q < kFRN ? gofs(q % kFRX, q / kFRX) : -1;
+        vp[s] = q < kFRN;
+        gp[s] = vp[s] ? gofs(q % kFRX, q / kFRX) : gofs(0, 0);
     }
 #pragma unroll
     for (int s = 0; s < kFXLoads; ++s) {
         int q = t + s * kBlock;
-        gx[s] = q < kFXN ? gofs(1 + q % kFXW, 1 + q / kFXW) : -1;
+        vx[s] = q < kFXN;
+        gx[s] = vx[s] ? gofs(1 + q % kFXW, 1 + q / kFXW) : gofs(1, 1);
     }
 #pragma unroll
     for (int s = 0; s < kFYLoads; ++s) {
         int q = t + s * kBlock;
-        gy[s] = q < kFYN ? gofs(1 + q % kFYW, 1 + q / kFYW) : -1;
+        vy[s] = q < kFYN;
+        gy[s] = vy[s] ? gofs(1 + q % kFYW, 1 + q / kFYW) : gofs(1, 1);
     }
 #pragma unroll
     for (int s = 0; s < kFZLoads; ++s) {
         int q = t + s * kBlock;
-        gz[s] = q < kFZN ? gofs(1 + q % kFZW, 1 + q / kFZW) : -1;
+        vz[s] = q < kFZN;
+        gz[s] = vz[s] ? gofs(1 + q % kFZW, 1 + q / kFZW) : gofs(1, 1);
     }
-    auto pl = [&](int k) { return (long)wrap(k, d.nz) * plane; };
-    // registers holding the planes of the next step: p(k+1), beta_x/y(k), b(k), beta_z(k+1)
-    T rp[kFLoads], rx[kFXLoads], ry[kFYLoads], rb[kFZLoads], rz[kFZLoads];
-    auto fetch = [&](int k) {
+    // planes z0 - 2 .. z1 + 2 lie within one period of the box
+    auto pl = [&](int k) { return (long)wrap_near(k, d.nz) * plane; };
+    // two register stages, alternating, each holding the planes of one step:
+    // p(k+1), beta_x/y(k), b(k), beta_z(k+1), loaded two steps ahead
+    struct Stage {
+        T p[kFLoads], x[kFXLoads], y[kFYLoads], b[kFZLoads], z[kFZLoads];
+    };
+    Stage SA, SB;
+    auto fetch = [&](Stage& S, int k) {
         long bp = pl(k + 1), bk = pl(k);
 #pragma unroll
-        for (int s = 0; s < kFLoads; ++s)
-            if (gp[s] >= 0) rp[s] = pin[bp + gp[s]];
+        for (int s = 0; s < kFLoads; ++s) S.p[s] = pin[bp + gp[s]];
 #pragma unroll
-        for (int s = 0; s < kFXLoads; ++s)
-            if (gx[s] >= 0) rx[s] = bx[bk + gx[s]];
+        for (int s = 0; s < kFXLoads; ++s) S.x[s] = bx[bk + gx[s]];
 #pragma unroll
-        for (int s = 0; s < kFYLoads; ++s)
-            if (gy[s] >= 0) ry[s] = by[bk + gy[s]];
+        for (int s = 0; s < kFYLoads; ++s) S.y[s] = by[bk + gy[s]];
 #pragma unroll
-        for (int s = 0; s < kFZLoads; ++s)
-            if (gz[s] >= 0) {
-                rb[s] = bb[bk + gz[s]];
-                rz[s] = bz[bp + gz[s]];
-            }
+        for (int s = 0; s < kFZLoads; ++s) {
+            S.b[s] = bb[bk + gz[s]];
+            S.z[s] = bz[bp + gz[s]];
+        }
     };
-    auto commit = [&](int k) {
+    auto commit = [&](const Stage& S, int k) {
 #pragma unroll
         for (int s = 0; s < kFLoads; ++s)
-            if (gp[s] >= 0) P[(k + 1) & 3][t + s * kBlock] = rp[s];
+            if (s * kBlock + kBlock <= kFRN || vp[s]) P[(k + 1) & 3][t + s * kBlock] = S.p[s];
 #pragma unroll
         for (int s = 0; s < kFXLoads; ++s)
-            if (gx[s] >= 0) BX[k & 1][t + s * kBlock] = rx[s];
+            if (s * kBlock + kBlock <= kFXN || vx[s]) BX[k & 1][t + s * kBlock] = S.x[s];
 #pragma unroll
         for (int s = 0; s < kFYLoads; ++s)
-            if (gy[s] >= 0) BY[k & 1][t + s * kBlock] = ry[s];
+            if (s * kBlock + kBlock <= kFYN || vy[s]) BY[k & 1][t + s * kBlock] = S.y[s];
 #pragma unroll
         for (int s = 0; s < kFZLoads; ++s)
-            if (gz[s] >= 0) {
-                B[k & 1][t + s * kBlock] = rb[s];
-                BZ[mod3(k + 1)][t + s * kBlock] = rz[s];
+            if (s * kBlock + kBlock <= kFZN || vz[s]) {
+                B[k & 1][t + s * kBlock] = S.b[s];
+                BZ[mod3(k + 1)][t + s * kBlock] = S.z[s];
             }
     };
     {
         long a = pl(z0 - 2), a1 = pl(z0 - 1);
 #pragma unroll
         for (int s = 0; s < kFLoads; ++s)
-            if (gp[s] >= 0) {
+            if (vp[s]) {
                 P[(z0 - 2) & 3][t + s * kBlock] = pin[a + gp[s]];
                 P[(z0 - 1) & 3][t + s * kBlock] = pin[a1 + gp[s]];
             }
 #pragma unroll
         for (int s = 0; s < kFZLoads; ++s)
-            if (gz[s] >= 0) BZ[mod3(z0 - 1)][t + s * kBlock] = bz[a1 + gz[s]];
+            if (vz[s]) BZ[mod3(z0 - 1)][t + s * kBlock] = bz[a1 + gz[s]];
     }
-    fetch(z0 - 1);
+    fetch(SA, z0 - 1);
+    // keep stage A's loads ahead of stage B's (the wait counts assume that order)
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(SB, z0);
     // one cell update at region position (x, y) of plane kk
     auto update = [&](int x, int y, int kk) {
         const int c = y * kFRX + x;
@@ -339,25 +426,25 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
         diag += br + bl;
         Pc[c] = (num - h2 * B[kk & 1][iz]) / diag;
     };
-    const int rw = kFRX - 2, rh = kFRY - 2;
-    for (int k = z0 - 1; k <= z1; ++k) {
-        commit(k);
-        if (k < z1) fetch(k + 1);  // in flight during this step
+    auto step = [&](Stage& S, int k) {
+        commit(S, k);
+        // in flight for two steps; past the range it re-reads plane z1 (not
+        // committed), which keeps the loads unconditional
+        fetch(S, k + 2 <= z1 ? k + 2 : z1);
         lds_barrier();
-        // red cells of plane k on the tile and its one-cell ring
-        for (int q = t; q < rw * rh; q += kBlock) {
-            int x = 1 + q % rw, y = 1 + q / rw;
-            if (((i0 + x) + (j0 + y) + k) & 1) continue;
-            update(x, y, k);
+        // red cells of plane k on the tile and its one-cell ring (only
+        // those: every lane has a cell of the colour)
+        for (int q = t; q < kFRedN; q += kBlock) {
+            int y = 1 + q / kFRedRow;
+            update(1 + ((i0 + 1 + j0 + y + k) & 1) + 2 * (q % kFRedRow), y, k);
         }
         lds_barrier();
         const int kb = k - 1;
         if (kb >= z0 && kb < z1) {
             // black cells of plane k - 1 on the tile
-            for (int q = t; q < kFTX * kFTY; q += kBlock) {
-                int x = 2 + q % kFTX, y = 2 + q / kFTX;
-                if ((((i0 + x) + (j0 + y) + kb) & 1) == 0) continue;
-                update(x, y, kb);
+            for (int q = t; q < kFBlackN; q += kBlock) {
+                int y = 2 + q / kFBlackRow;
+                update(2 + ((i0 + 3 + j0 + y + kb) & 1) + 2 * (q % kFBlackRow), y, kb);
             }
             lds_barrier();
             const T* Pc = P[kb & 3];
@@ -368,15 +455,173 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
             }
         }
         lds_barrier();
+    };
+    // steps z0 - 1 .. z1 in pairs (stage A, stage B); TZ is even
+    for (int k = z0 - 1; k <= z1; k += 2) {
+        step(SA, k);
+        step(SB, k + 1);
+    }
+}
+
+// The same single-pass sweep on a finest level given by cell densities: the
+// workgroup stages p and rho on the tile plus the two-cell halo and b on the
+// one-cell ring, and forms each face coefficient 2 / (rho_hi + rho_lo) where
+// it is used. That is 32 bytes of memory traffic per cell (p read and
+// written, b, rho) instead of 48 with three stored face arrays; the update is
+// the one above, operand for operand, so the results are bitwise those of
+// the stored-face sweep.
+__global__ __launch_bounds__(kBlock) void k_rbgs_fused_rho(const double* __restrict__ pin,
+                                                           double* __restrict__ pout,
+                                                           const double* __restrict__ bb,
+                                                           const double* __restrict__ rho, Dims d,
+                                                           double h2, int TZ, int ntx, int nty,
+                                                           int nzc) {
+    __shared__ double P[4][kFRN];
+    __shared__ double R[4][kFRN];
+    __shared__ double B[2][kFZN];
+    const int nw = ntx * nty * nzc;
+    const int bid = blockIdx.x;
+    const int w = (nw % 8 == 0) ? (bid % 8) * (nw / 8) + bid / 8 : bid;
+    const int tx = w % ntx;
+    const int r0 = w / ntx;
+    const int ty = r0 % nty;
+    const int zc = r0 / nty;
+    const int i0 = tx * kFTX - 2, j0 = ty * kFTY - 2;
+    const int z0 = zc * TZ, z1 = z0 + TZ;
+    const long plane = (long)d.nx * d.ny;
+    const int t = threadIdx.x;
+    // tile origins are at least -2 and regions end within one period
+    auto gofs = [&](int x, int y) { return wrap_near(j0 + y, d.ny) * d.nx + wrap_near(i0 + x, d.nx); };
+    // every lane issues every load (slots past a region re-read its first
+    // cell and are not stored), so the loads are unconditional and the
+    // compiler's wait counts are exact: a commit waits for its own plane only,
+    // not for the loads and stores issued after it
+    int gp[kFLoads], gz[kFZLoads];
+    bool vp[kFLoads], vz[kFZLoads];
+#pragma unroll
+    for (int s = 0; s < kFLoads; ++s) {
+        int q = t + s * kBlock;
+        vp[s] = q < kFRN;
+        gp[s] = vp[s] ? gofs(q % kFRX, q / kFRX) : gofs(0, 0);
+    }
+#pragma unroll
+    for (int s = 0; s < kFZLoads; ++s) {
+        int q = t + s * kBlock;
+        vz[s] = q < kFZN;
+        gz[s] = vz[s] ? gofs(1 + q % kFZW, 1 + q / kFZW) : gofs(1, 1);
+    }
+    // planes z0 - 2 .. z1 + 2 lie within one period of the box
+    auto pl = [&](int k) { return (long)wrap_near(k, d.nz) * plane; };
+    // two register stages, alternating: the planes of step k, p(k+1), rho(k+1)
+    // and b(k), are loaded two steps ahead
+    struct Stage {
+        double p[kFLoads], r[kFLoads], b[kFZLoads];
+    };
+    Stage SA, SB;
+    auto fetch = [&](Stage& S, int k) {
+        long bp = pl(k + 1), bk = pl(k);
+#pragma unroll
+        for (int s = 0; s < kFLoads; ++s) {
+            S.p[s] = pin[bp + gp[s]];
+            S.r[s] = rho[bp + gp[s]];
+        }
+#pragma unroll
+        for (int s = 0; s < kFZLoads; ++s) S.b[s] = bb[bk + gz[s]];
+    };
+    auto commit = [&](const Stage& S, int k) {
+#pragma unroll
+        for (int s = 0; s < kFLoads; ++s)
+            if (s * kBlock + kBlock <= kFRN || vp[s]) {
+                P[(k + 1) & 3][t + s * kBlock] = S.p[s];
+                R[(k + 1) & 3][t + s * kBlock] = S.r[s];
+            }
+#pragma unroll
+        for (int s = 0; s < kFZLoads; ++s)
+            if (s * kBlock + kBlock <= kFZN || vz[s]) B[k & 1][t + s * kBlock] = S.b[s];
+    };
+    {
+        long a = pl(z0 - 2), a1 = pl(z0 - 1);
+#pragma unroll
+        for (int s = 0; s < kFLoads; ++s)
+            if (vp[s]) {
+                P[(z0 - 2) & 3][t + s * kBlock] = pin[a + gp[s]];
+                P[(z0 - 1) & 3][t + s * kBlock] = pin[a1 + gp[s]];
+                R[(z0 - 2) & 3][t + s * kBlock] = rho[a + gp[s]];
+                R[(z0 - 1) & 3][t + s * kBlock] = rho[a1 + gp[s]];
+            }
+    }
+    fetch(SA, z0 - 1);
+    // keep stage A's loads ahead of stage B's (the wait counts assume that order)
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(SB, z0);
+    auto update = [&](int x, int y, int kk) {
+        const int c = y * kFRX + x;
+        const int iz = (y - 1) * kFZW + (x - 1);
+        double* Pc = P[kk & 3];
+        const double* Pd = P[(kk - 1) & 3];
+        const double* Pu = P[(kk + 1) & 3];
+        const double* Rc = R[kk & 3];
+        const double rc = Rc[c];
+        const double rxp = Rc[c + 1], rxm = Rc[c - 1], ryp = Rc[c + kFRX], rym = Rc[c - kFRX];
+        const double rzp = R[(kk + 1) & 3][c], rzm = R[(kk - 1) & 3][c];
+        double bxp, bxm, byp, bym, bzp, bzm;
+        if (rxp == rc && rxm == rc && ryp == rc && rym == rc && rzp == rc && rzm == rc) {
+            // away from the interface: 2 / (rc + rc) is exactly 1 / rc, one division
+            bxp = bxm = byp = bym = bzp = bzm = 1.0 / rc;
+        } else {
+            bxp = 2.0 / (rxp + rc);
+            bxm = 2.0 / (rc + rxm);
+            byp = 2.0 / (ryp + rc);
+            bym = 2.0 / (rc + rym);
+            bzp = 2.0 / (rzp + rc);
+            bzm = 2.0 / (rc + rzm);
+        }
+        double num = bxp * Pc[c + 1] + bxm * Pc[c - 1];
+        double diag = bxp + bxm;
+        num += byp * Pc[c + kFRX] + bym * Pc[c - kFRX];
+        diag += byp + bym;
+        num += bzp * Pu[c] + bzm * Pd[c];
+        diag += bzp + bzm;
+        Pc[c] = (num - h2 * B[kk & 1][iz]) / diag;
+    };
+    auto step = [&](Stage& S, int k) {
+        commit(S, k);
+        // in flight for two steps; past the range it re-reads plane z1 (not
+        // committed), which keeps the loads unconditional
+        fetch(S, k + 2 <= z1 ? k + 2 : z1);
+        lds_barrier();
+        for (int q = t; q < kFRedN; q += kBlock) {
+            int y = 1 + q / kFRedRow;
+            update(1 + ((i0 + 1 + j0 + y + k) & 1) + 2 * (q % kFRedRow), y, k);
+        }
+        lds_barrier();
+        const int kb = k - 1;
+        if (kb >= z0 && kb < z1) {
+            for (int q = t; q < kFBlackN; q += kBlock) {
+                int y = 2 + q / kFBlackRow;
+                update(2 + ((i0 + 3 + j0 + y + kb) & 1) + 2 * (q % kFBlackRow), y, kb);
+            }
+            lds_barrier();
+            const double* Pc = P[kb & 3];
+            long base = pl(kb) + (long)(j0 + 2) * d.nx + (i0 + 2);
+            for (int q = t; q < kFTX * kFTY; q += kBlock) {
+                int x = q % kFTX, y = q / kFTX;
+                pout[base + (long)y * d.nx + x] = Pc[(y + 2) * kFRX + x + 2];
+            }
+        }
+        lds_barrier();
+    };
+    // steps z0 - 1 .. z1 in pairs (stage A, stage B); TZ is even
+    for (int k = z0 - 1; k <= z1; k += 2) {
+        step(SA, k);
+        step(SB, k + 1);
     }
 }
 
 // residual of the fine level restricted to the coarse right side
 template <typename T, int DIM>
 __global__ void k_residual_restrict(const T* __restrict__ p, const T* __restrict__ b,
-                                    const T* __restrict__ b0, const T* __restrict__ b1,
-                                    const T* __restrict__ b2, Dims f, T inv_h2,
-                                    T* __restrict__ bc) {
+                                    CoefArrays<T> co, Dims f, T inv_h2, T* __restrict__ bc) {
     long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     int cx = f.nx >> 1, cy = f.ny >> 1, cz = DIM == 3 ? (f.nz >> 1) : 1;
     long ncells = (long)cx * cy * cz;
@@ -390,7 +635,7 @@ __global__ void k_residual_restrict(const T* __restrict__ p, const T* __restrict
         for (int dy = 0; dy < 2; ++dy)
             for (int dx = 0; dx < 2; ++dx) {
                 Nb n = neighbours(f, 2 * I + dx, 2 * J + dy, DIM == 3 ? 2 * K + dz : 0, DIM);
-                acc += b[n.c] - apply_row<T, DIM>(p, b0, b1, b2, n) * inv_h2;
+                acc += b[n.c] - apply_row<T, DIM>(p, co, n) * inv_h2;
             }
     bc[t] = acc * (DIM == 3 ? T(0.125) : T(0.25));
 }
@@ -399,20 +644,18 @@ __global__ void k_residual_restrict(const T* __restrict__ p, const T* __restrict
 // (block = 64 x 2 x 2 fine cells = 32 coarse cells), the residual of each fine
 // cell computed once; the two x-children meet by a lane exchange, the y and
 // z pairs through LDS, summed in a fixed order.
-template <typename T>
+template <typename T, class K>
 __global__ __launch_bounds__(kBlock) void k_residual_restrict64(const T* __restrict__ p,
-                                                                const T* __restrict__ b,
-                                                                const T* __restrict__ b0,
-                                                                const T* __restrict__ b1,
-                                                                const T* __restrict__ b2, Dims f,
-                                                                T inv_h2, T* __restrict__ bc) {
+                                                                const T* __restrict__ b, K co,
+                                                                Dims f, T inv_h2,
+                                                                T* __restrict__ bc) {
     __shared__ T part[4][32];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = blockIdx.x * 64 + lane;
     const int j = blockIdx.y * 2 + (wave & 1);
     const int k = blockIdx.z * 2 + (wave >> 1);
     Nb n = neighbours(f, i, j, k, 3);
-    T r = b[n.c] - apply_row<T, 3>(p, b0, b1, b2, n) * inv_h2;
+    T r = b[n.c] - apply_row<T, 3>(p, co, n) * inv_h2;
     T rx = r + __shfl_xor(r, 1);
     if ((lane & 1) == 0) part[wave][lane >> 1] = rx;
     __syncthreads();
@@ -466,10 +709,9 @@ __global__ void k_cast_f32(const double* __restrict__ x, float* __restrict__ y, 
 }
 
 // coarse face coefficient = mean of the fine faces on it
-template <int DIM>
-__global__ void k_coarsen_beta(const double* __restrict__ f0, const double* __restrict__ f1,
-                               const double* __restrict__ f2, Dims f, double* __restrict__ c0,
-                               double* __restrict__ c1, double* __restrict__ c2) {
+template <int DIM, class K>
+__global__ void k_coarsen_beta(K co, Dims f, double* __restrict__ c0, double* __restrict__ c1,
+                               double* __restrict__ c2) {
     long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     int cx = f.nx >> 1, cy = f.ny >> 1, cz = DIM == 3 ? (f.nz >> 1) : 1;
     long ncells = (long)cx * cy * cz;
@@ -477,20 +719,37 @@ __global__ void k_coarsen_beta(const double* __restrict__ f0, const double* __re
     int I = (int)(t % cx);
     long r = t / cx;
     int J = (int)(r % cy);
-    int K = (int)(r / cy);
-    long fpl = (long)f.nx * f.ny;
-    auto at = [&](int i, int j, int k) { return (long)k * fpl + (long)j * f.nx + i; };
+    int K3 = (int)(r / cy);
+    auto nb = [&](int i, int j, int k) { return neighbours(f, i, j, k, DIM); };
     if (DIM == 2) {
-        c0[t] = 0.5 * (f0[at(2 * I, 2 * J, 0)] + f0[at(2 * I, 2 * J + 1, 0)]);
-        c1[t] = 0.5 * (f1[at(2 * I, 2 * J, 0)] + f1[at(2 * I + 1, 2 * J, 0)]);
+        c0[t] = 0.5 * (co.xl(nb(2 * I, 2 * J, 0)) + co.xl(nb(2 * I, 2 * J + 1, 0)));
+        c1[t] = 0.5 * (co.yl(nb(2 * I, 2 * J, 0)) + co.yl(nb(2 * I + 1, 2 * J, 0)));
     } else {
-        c0[t] = 0.25 * ((f0[at(2 * I, 2 * J, 2 * K)] + f0[at(2 * I, 2 * J + 1, 2 * K)]) +
-                        (f0[at(2 * I, 2 * J, 2 * K + 1)] + f0[at(2 * I, 2 * J + 1, 2 * K + 1)]));
-        c1[t] = 0.25 * ((f1[at(2 * I, 2 * J, 2 * K)] + f1[at(2 * I + 1, 2 * J, 2 * K)]) +
-                        (f1[at(2 * I, 2 * J, 2 * K + 1)] + f1[at(2 * I + 1, 2 * J, 2 * K + 1)]));
-        c2[t] = 0.25 * ((f2[at(2 * I, 2 * J, 2 * K)] + f2[at(2 * I + 1, 2 * J, 2 * K)]) +
-                        (f2[at(2 * I, 2 * J + 1, 2 * K)] + f2[at(2 * I + 1, 2 * J + 1, 2 * K)]));
+        const int i = 2 * I, j = 2 * J, k = 2 * K3;
+        c0[t] = 0.25 * ((co.xl(nb(i, j, k)) + co.xl(nb(i, j + 1, k))) +
+                        (co.xl(nb(i, j, k + 1)) + co.xl(nb(i, j + 1, k + 1))));
+        c1[t] = 0.25 * ((co.yl(nb(i, j, k)) + co.yl(nb(i + 1, j, k))) +
+                        (co.yl(nb(i, j, k + 1)) + co.yl(nb(i + 1, j, k + 1))));
+        c2[t] = 0.25 * ((co.zl(nb(i, j, k)) + co.zl(nb(i + 1, j, k))) +
+                        (co.zl(nb(i, j + 1, k)) + co.zl(nb(i + 1, j + 1, k))));
     }
+}
+
+// the face arrays of a level from its cell densities (float32 for the mixed
+// V-cycle, float64 where the kernels read stored faces)
+template <int DIM, typename TO>
+__global__ void k_beta_from_rho(CoefRho co, Dims d, TO* __restrict__ b0, TO* __restrict__ b1,
+                                TO* __restrict__ b2) {
+    long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.cells()) return;
+    int i = (int)(c % d.nx);
+    long r = c / d.nx;
+    int j = (int)(r % d.ny);
+    int k = (int)(r / d.ny);
+    Nb n = neighbours(d, i, j, k, DIM);
+    b0[c] = (TO)co.xl(n);
+    b1[c] = (TO)co.yl(n);
+    if (DIM == 3) b2[c] = (TO)co.zl(n);
 }
 
 // ---------------------------------------------------------------------------
@@ -580,11 +839,10 @@ __global__ void k_coarse_apply(const double* __restrict__ Minv, int nc, const T*
 
 // ---------------------------------------------------------------------------
 // norms: partial sums of r^2 (and of p) per block
-template <int DIM>
-__global__ void k_resid_norm(const double* __restrict__ p, const double* __restrict__ b,
-                             const double* __restrict__ b0, const double* __restrict__ b1,
-                             const double* __restrict__ b2, Dims d, double inv_h2,
-                             double* __restrict__ partial_r2, double* __restrict__ partial_b2) {
+template <int DIM, class K>
+__global__ void k_resid_norm(const double* __restrict__ p, const double* __restrict__ b, K co,
+                             Dims d, double inv_h2, double* __restrict__ partial_r2,
+                             double* __restrict__ partial_b2) {
     __shared__ double sh[kBlock];
     double ar = 0.0, ab = 0.0;
     const int N = (int)d.cells(), nx = d.nx, ny = d.ny;
@@ -595,7 +853,7 @@ __global__ void k_resid_norm(const double* __restrict__ p, const double* __restr
         int k = r / ny;
         Nb n = neighbours(d, i, j, k, DIM);
         double bv = b[c];
-        double rv = bv - apply_row<double, DIM>(p, b0, b1, b2, n) * inv_h2;
+        double rv = bv - apply_row<double, DIM>(p, co, n) * inv_h2;
         ar += rv * rv;
         ab += bv * bv;
     }
@@ -608,12 +866,10 @@ __global__ void k_resid_norm(const double* __restrict__ p, const double* __restr
 }
 
 // mixed precision: r32 = fl32(b - A p) with partial sums of r^2 and b^2
-template <int DIM>
-__global__ void k_defect_f32(const double* __restrict__ p, const double* __restrict__ b,
-                             const double* __restrict__ b0, const double* __restrict__ b1,
-                             const double* __restrict__ b2, Dims d, double inv_h2,
-                             float* __restrict__ r32, double* __restrict__ partial_r2,
-                             double* __restrict__ partial_b2) {
+template <int DIM, class K>
+__global__ void k_defect_f32(const double* __restrict__ p, const double* __restrict__ b, K co,
+                             Dims d, double inv_h2, float* __restrict__ r32,
+                             double* __restrict__ partial_r2, double* __restrict__ partial_b2) {
     __shared__ double sh[kBlock];
     double ar = 0.0, ab = 0.0;
     const int N = (int)d.cells(), nx = d.nx, ny = d.ny;
@@ -624,7 +880,7 @@ __global__ void k_defect_f32(const double* __restrict__ p, const double* __restr
         int k = r / ny;
         Nb n = neighbours(d, i, j, k, DIM);
         double bv = b[c];
-        double rv = bv - apply_row<double, DIM>(p, b0, b1, b2, n) * inv_h2;
+        double rv = bv - apply_row<double, DIM>(p, co, n) * inv_h2;
         r32[c] = (float)rv;
         ar += rv * rv;
         ab += bv * bv;
@@ -687,10 +943,18 @@ static void launch_rbgs(Level& L, int color, hipStream_t st, bool finest) {
 
 template <typename T>
 static void launch_fused(Level& L, T* pin, T* pout, hipStream_t st, bool finest) {
-    ProfScope ps(sizeof(T) == 8 ? IB_PROF_SWEEP64 : IB_PROF_SWEEP32, st, finest);
+    ProfScope ps(sizeof(T) == 8 ? (L.rho ? IB_PROF_SWEEP64_RHO : IB_PROF_SWEEP64) : IB_PROF_SWEEP32,
+                 st, finest);
     LevelT<T>& A = lvl<T>(L);
     T h2 = (T)(L.d.h * L.d.h);
     int ntx = L.d.nx / kFTX, nty = L.d.ny / kFTY, nzc = L.d.nz / L.tz;
+    if constexpr (sizeof(T) == 8) {
+        if (L.rho) {
+            hipLaunchKernelGGL(k_rbgs_fused_rho, dim3(ntx * nty * nzc), dim3(kBlock), 0, st, pin, pout,
+                               A.b, L.rho, L.d, h2, L.tz, ntx, nty, nzc);
+            return;
+        }
+    }
     hipLaunchKernelGGL((k_rbgs_fused<T>), dim3(ntx * nty * nzc), dim3(kBlock), 0, st, pin, pout, A.b,
                        A.beta[0], A.beta[1], A.beta[2], L.d, h2, L.tz, ntx, nty, nzc);
 }
@@ -732,16 +996,26 @@ static void vcycle(mg_handle* m, int l, hipStream_t st) {
     long nc = C.d.cells();
     {
         ProfScope ps(sizeof(T) == 8 ? IB_PROF_RESTRICT64 : IB_PROF_RESTRICT32, st, fin);
-        if (L.d.dim == 2)
+        const CoefArrays<T> co{A.beta[0], A.beta[1], L.d.dim == 3 ? A.beta[2] : A.beta[1]};
+        const dim3 g64(L.d.nx / 64, L.d.ny / 2, L.d.nz / 2);
+        bool done = false;
+        if constexpr (sizeof(T) == 8) {
+            if (L.rho) {  // set only where nx % 64 == 0 in 3D
+                hipLaunchKernelGGL((k_residual_restrict64<double, CoefRho>), g64, dim3(kBlock), 0, st,
+                                   cur, A.b, CoefRho{L.rho}, L.d, inv_h2, B.b);
+                done = true;
+            }
+        }
+        if (done) {
+        } else if (L.d.dim == 2)
             hipLaunchKernelGGL((k_residual_restrict<T, 2>), dim3(grid_for(nc)), dim3(kBlock), 0, st,
-                               cur, A.b, A.beta[0], A.beta[1], A.beta[1], L.d, inv_h2, B.b);
+                               cur, A.b, co, L.d, inv_h2, B.b);
         else if (L.d.nx % 64 == 0)
-            hipLaunchKernelGGL((k_residual_restrict64<T>), dim3(L.d.nx / 64, L.d.ny / 2, L.d.nz / 2),
-                               dim3(kBlock), 0, st, cur, A.b, A.beta[0], A.beta[1], A.beta[2], L.d,
-                               inv_h2, B.b);
+            hipLaunchKernelGGL((k_residual_restrict64<T, CoefArrays<T>>), g64, dim3(kBlock), 0, st,
+                               cur, A.b, co, L.d, inv_h2, B.b);
         else
             hipLaunchKernelGGL((k_residual_restrict<T, 3>), dim3(grid_for(nc)), dim3(kBlock), 0, st,
-                               cur, A.b, A.beta[0], A.beta[1], A.beta[2], L.d, inv_h2, B.b);
+                               cur, A.b, co, L.d, inv_h2, B.b);
     }
     if (l + 1 != last)
         hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(nc)), dim3(kBlock), 0, st, B.p, nc, (T)0);
@@ -772,12 +1046,17 @@ static int fp64_norms(mg_handle* m, bool want_b, hipStream_t st) {
     double* pb = want_b ? m->red + kRed : nullptr;
     {
     ProfScope ps(IB_PROF_RESID, st, true);
-    if (L.d.dim == 2)
-        hipLaunchKernelGGL((k_resid_norm<2>), dim3(nb), dim3(kBlock), 0, st, L.f64.p, L.f64.b,
-                           L.f64.beta[0], L.f64.beta[1], L.f64.beta[1], L.d, inv_h2, pr, pb);
+    const CoefArrays<double> co{L.f64.beta[0], L.f64.beta[1],
+                                L.d.dim == 3 ? L.f64.beta[2] : L.f64.beta[1]};
+    if (L.rho)
+        hipLaunchKernelGGL((k_resid_norm<3, CoefRho>), dim3(nb), dim3(kBlock), 0, st, L.f64.p,
+                           L.f64.b, CoefRho{L.rho}, L.d, inv_h2, pr, pb);
+    else if (L.d.dim == 2)
+        hipLaunchKernelGGL((k_resid_norm<2, CoefArrays<double>>), dim3(nb), dim3(kBlock), 0, st,
+                           L.f64.p, L.f64.b, co, L.d, inv_h2, pr, pb);
     else
-        hipLaunchKernelGGL((k_resid_norm<3>), dim3(nb), dim3(kBlock), 0, st, L.f64.p, L.f64.b,
-                           L.f64.beta[0], L.f64.beta[1], L.f64.beta[2], L.d, inv_h2, pr, pb);
+        hipLaunchKernelGGL((k_resid_norm<3, CoefArrays<double>>), dim3(nb), dim3(kBlock), 0, st,
+                           L.f64.p, L.f64.b, co, L.d, inv_h2, pr, pb);
     }
     IB_TRY(device_sum(pr, nb, m->red + 3 * kRed, st));
     if (want_b) IB_TRY(device_sum(pb, nb, m->red + 3 * kRed + 1, st));
@@ -796,12 +1075,17 @@ static int mixed_defect(mg_handle* m, bool want_b, hipStream_t st, bool sync = t
     double* pb = want_b ? m->red + kRed : nullptr;
     {
     ProfScope ps(IB_PROF_RESID, st, true);
-    if (L.d.dim == 2)
-        hipLaunchKernelGGL((k_defect_f32<2>), dim3(nb), dim3(kBlock), 0, st, L.f64.p, L.f64.b,
-                           L.f64.beta[0], L.f64.beta[1], L.f64.beta[1], L.d, inv_h2, L.f32.b, pr, pb);
+    const CoefArrays<double> co{L.f64.beta[0], L.f64.beta[1],
+                                L.d.dim == 3 ? L.f64.beta[2] : L.f64.beta[1]};
+    if (L.rho)
+        hipLaunchKernelGGL((k_defect_f32<3, CoefRho>), dim3(nb), dim3(kBlock), 0, st, L.f64.p,
+                           L.f64.b, CoefRho{L.rho}, L.d, inv_h2, L.f32.b, pr, pb);
+    else if (L.d.dim == 2)
+        hipLaunchKernelGGL((k_defect_f32<2, CoefArrays<double>>), dim3(nb), dim3(kBlock), 0, st,
+                           L.f64.p, L.f64.b, co, L.d, inv_h2, L.f32.b, pr, pb);
     else
-        hipLaunchKernelGGL((k_defect_f32<3>), dim3(nb), dim3(kBlock), 0, st, L.f64.p, L.f64.b,
-                           L.f64.beta[0], L.f64.beta[1], L.f64.beta[2], L.d, inv_h2, L.f32.b, pr, pb);
+        hipLaunchKernelGGL((k_defect_f32<3, CoefArrays<double>>), dim3(nb), dim3(kBlock), 0, st,
+                           L.f64.p, L.f64.b, co, L.d, inv_h2, L.f32.b, pr, pb);
     }
     if (!sync) return IB_OK;
     IB_TRY(device_sum(pr, nb, m->red + 3 * kRed, st));
@@ -888,11 +1172,13 @@ extern "C" int mg_setup(const ib_grid* g, const mg_opts* o, mg_handle** out) {
         long N = lv.d.cells();
         lv.own_pb = l > 0;
         if (g->dim == 3 && lv.d.nx % kFTX == 0 && lv.d.ny % kFTY == 0 && lv.d.nz >= 32 &&
-            N >= 128L * 128 * 128) {
+            lv.d.nz % 2 == 0 && N >= 128L * 128 * 128) {
+            // z-range per workgroup: an even divisor of nz (the sweep runs its
+            // steps in pairs), halved while the grid has under 1024 workgroups
             lv.fused = true;
             long tiles = (long)(lv.d.nx / kFTX) * (lv.d.ny / kFTY);
             int tz = lv.d.nz;
-            while (tz > 16 && tiles * (lv.d.nz / tz) < 1024) tz /= 2;
+            while (tz % 4 == 0 && tz > 16 && tiles * (lv.d.nz / tz) < 1024) tz /= 2;
             lv.tz = tz;
         }
         if (l > 0) {
@@ -941,6 +1227,7 @@ extern "C" void mg_destroy(mg_handle* m) {
         hipFree(lv.f32.b);
         for (int e = 0; e < 3; ++e) hipFree(lv.f32.beta[e]);
     }
+    for (int e = 0; e < 3; ++e) hipFree(m->beta0[e]);
     hipFree(m->cmat);
     hipFree(m->cinv);
     hipFree(m->red);
@@ -948,32 +1235,40 @@ extern "C" void mg_destroy(mg_handle* m) {
     delete m;
 }
 
-extern "C" int mg_update_coeffs(mg_handle* m, const double* const beta[3], void* stream) {
-    IB_CHECK(m && beta, IB_EINVAL, "mg_update_coeffs: null argument");
-    hipStream_t st = (hipStream_t)stream;
+// finest level from stored faces (beta) or from cell densities (rho)
+static int update_hierarchy(mg_handle* m, const double* const beta[3], const double* rho,
+                            hipStream_t st) {
     int dim = m->g.dim;
-    for (int e = 0; e < dim; ++e) {
-        IB_CHECK(beta[e], IB_EINVAL, "mg_update_coeffs: null coefficient array");
-        m->lv[0].f64.beta[e] = const_cast<double*>(beta[e]);
-    }
+    Level& L0 = m->lv[0];
+    L0.rho = rho;
+    for (int e = 0; e < 3; ++e) L0.f64.beta[e] = (!rho && e < dim) ? const_cast<double*>(beta[e]) : nullptr;
     for (size_t l = 1; l < m->lv.size(); ++l) {
         Level& F = m->lv[l - 1];
         Level& C = m->lv[l];
         long nc = C.d.cells();
-        if (dim == 2)
-            hipLaunchKernelGGL(k_coarsen_beta<2>, dim3(grid_for(nc)), dim3(kBlock), 0, st,
-                               F.f64.beta[0], F.f64.beta[1], F.f64.beta[1], F.d, C.f64.beta[0],
-                               C.f64.beta[1], C.f64.beta[1]);
+        const CoefArrays<double> co{F.f64.beta[0], F.f64.beta[1], dim == 3 ? F.f64.beta[2] : F.f64.beta[1]};
+        if (F.rho)
+            hipLaunchKernelGGL((k_coarsen_beta<3, CoefRho>), dim3(grid_for(nc)), dim3(kBlock), 0, st,
+                               CoefRho{F.rho}, F.d, C.f64.beta[0], C.f64.beta[1], C.f64.beta[2]);
+        else if (dim == 2)
+            hipLaunchKernelGGL((k_coarsen_beta<2, CoefArrays<double>>), dim3(grid_for(nc)), dim3(kBlock),
+                               0, st, co, F.d, C.f64.beta[0], C.f64.beta[1], C.f64.beta[1]);
         else
-            hipLaunchKernelGGL(k_coarsen_beta<3>, dim3(grid_for(nc)), dim3(kBlock), 0, st,
-                               F.f64.beta[0], F.f64.beta[1], F.f64.beta[2], F.d, C.f64.beta[0],
-                               C.f64.beta[1], C.f64.beta[2]);
+            hipLaunchKernelGGL((k_coarsen_beta<3, CoefArrays<double>>), dim3(grid_for(nc)), dim3(kBlock),
+                               0, st, co, F.d, C.f64.beta[0], C.f64.beta[1], C.f64.beta[2]);
     }
     if (m->o.precision == MG_MIXED)
-        for (auto& L : m->lv)
+        for (auto& L : m->lv) {
+            if (L.rho) {
+                hipLaunchKernelGGL((k_beta_from_rho<3, float>), dim3(grid_for(L.d.cells())), dim3(kBlock),
+                                   0, st, CoefRho{L.rho}, L.d, L.f32.beta[0], L.f32.beta[1],
+                                   L.f32.beta[2]);
+                continue;
+            }
             for (int e = 0; e < dim; ++e)
                 hipLaunchKernelGGL(k_cast_f32, dim3(grid_for(L.d.cells())), dim3(kBlock), 0, st,
                                    L.f64.beta[e], L.f32.beta[e], L.d.cells());
+        }
     Level& Cl = m->lv.back();
     if (dim == 2)
         hipLaunchKernelGGL(k_build_coarse<2>, dim3(1), dim3(kMaxCoarse), 0, st, Cl.f64.beta[0],
@@ -987,10 +1282,47 @@ extern "C" int mg_update_coeffs(mg_handle* m, const double* const beta[3], void*
     return IB_OK;
 }
 
+// the finest-level kernels read densities directly on 3D grids with the
+// single-pass smoother, the 64-wide restriction and at least one coarse level
+static bool density_direct(const mg_handle* m) {
+    const Level& L0 = m->lv[0];
+    return m->g.dim == 3 && L0.fused && L0.d.nx % 64 == 0 && m->lv.size() >= 2;
+}
+
+int mg_takes_density(const mg_handle* m) { return m && density_direct(m) ? 1 : 0; }
+
+extern "C" int mg_update_coeffs(mg_handle* m, const double* const beta[3], void* stream) {
+    IB_CHECK(m && beta, IB_EINVAL, "mg_update_coeffs: null argument");
+    for (int e = 0; e < m->g.dim; ++e)
+        IB_CHECK(beta[e], IB_EINVAL, "mg_update_coeffs: null coefficient array");
+    return update_hierarchy(m, beta, nullptr, (hipStream_t)stream);
+}
+
+extern "C" int mg_update_density(mg_handle* m, const double* rho, void* stream) {
+    IB_CHECK(m && rho, IB_EINVAL, "mg_update_density: null argument");
+    hipStream_t st = (hipStream_t)stream;
+    if (density_direct(m)) return update_hierarchy(m, nullptr, rho, st);
+    // other grids: form the finest face arrays once, into storage of the handle
+    Level& L0 = m->lv[0];
+    long N = L0.d.cells();
+    int dim = m->g.dim;
+    for (int e = 0; e < dim; ++e)
+        if (!m->beta0[e] && hipMalloc(&m->beta0[e], N * sizeof(double)) != hipSuccess)
+            return fail(IB_ENOMEM, "mg_update_density: out of device memory");
+    if (dim == 2)
+        hipLaunchKernelGGL((k_beta_from_rho<2, double>), dim3(grid_for(N)), dim3(kBlock), 0, st,
+                           CoefRho{rho}, L0.d, m->beta0[0], m->beta0[1], m->beta0[1]);
+    else
+        hipLaunchKernelGGL((k_beta_from_rho<3, double>), dim3(grid_for(N)), dim3(kBlock), 0, st,
+                           CoefRho{rho}, L0.d, m->beta0[0], m->beta0[1], m->beta0[2]);
+    const double* b[3] = {m->beta0[0], m->beta0[1], m->beta0[2]};
+    return update_hierarchy(m, b, nullptr, st);
+}
+
 extern "C" int mg_residual_norm(mg_handle* m, const double* b, const double* p, double* rel,
                                 void* stream) {
     IB_CHECK(m && b && p && rel, IB_EINVAL, "mg_residual_norm: null argument");
-    IB_CHECK(m->coeffs_ready, IB_EINVAL, "mg_residual_norm: call mg_update_coeffs first");
+    IB_CHECK(m->coeffs_ready, IB_EINVAL, "mg_residual_norm: no coefficients yet (mg_update_coeffs or mg_update_density)");
     Level& L0 = m->lv[0];
     double* sp = L0.f64.p;
     double* sb = L0.f64.b;
@@ -1008,7 +1340,7 @@ extern "C" int mg_residual_norm(mg_handle* m, const double* b, const double* p, 
 extern "C" int mg_solve(mg_handle* m, const double* b, double* p, double rtol, int max_cycles,
                         int fixed_cycles, mg_stats* stats, void* stream) {
     IB_CHECK(m && b && p, IB_EINVAL, "mg_solve: null argument");
-    IB_CHECK(m->coeffs_ready, IB_EINVAL, "mg_solve: call mg_update_coeffs first");
+    IB_CHECK(m->coeffs_ready, IB_EINVAL, "mg_solve: no coefficients yet (mg_update_coeffs or mg_update_density)");
     IB_CHECK(max_cycles >= 0 && fixed_cycles >= 0, IB_EINVAL, "mg_solve: cycle counts");
     hipStream_t st = (hipStream_t)stream;
     Level& L0 = m->lv[0];

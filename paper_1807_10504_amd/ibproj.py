@@ -22,7 +22,8 @@ MG_FP64, MG_MIXED = 0, 1
 WS_ZERO, WS_PREV, WS_NN = 0, 1, 2
 
 EXPORTS = ("ib_create", "ib_destroy", "ib_bin_markers", "ib_interp", "ib_spread",
-           "ib_coefficients", "ib_rhs", "ib_update", "mg_setup", "mg_update_coeffs", "mg_solve",
+           "ib_coefficients", "ib_density", "ib_rhs", "ib_update", "mg_setup", "mg_update_coeffs",
+           "mg_update_density", "mg_solve",
            "mg_destroy", "mg_residual_norm", "project_step", "ib_relocate_bspline",
            "ib_surface_geometry_3d", "ib_nn_param_count", "ib_nn_create", "ib_nn_destroy",
            "ib_nn_set_params", "ib_nn_get_params", "ib_nn_predict", "ib_nn_gradients",
@@ -31,7 +32,7 @@ EXPORTS = ("ib_create", "ib_destroy", "ib_bin_markers", "ib_interp", "ib_spread"
            "ib_last_error")
 
 PROF_KINDS = ("smooth64", "smooth32", "restrict64", "restrict32", "prolong64", "prolong32", "resid",
-              "sweep64", "sweep32")
+              "sweep64", "sweep32", "sweep64_rho")
 
 
 class IbError(RuntimeError):
@@ -109,10 +110,12 @@ def load(path: str = LIB_PATH):
         "ib_interp": (i32, [vp, vp * 3, P(Surface), vp, vp]),
         "ib_spread": (i32, [vp, P(Surface), i32, vp * 3, vp, vp]),
         "ib_coefficients": (i32, [vp, vp, f64, f64, vp * 3, vp]),
+        "ib_density": (i32, [vp, vp, f64, f64, vp, vp]),
         "ib_rhs": (i32, [vp, vp * 3, vp * 3, vp * 3, f64, vp, vp]),
         "ib_update": (i32, [vp, vp * 3, vp * 3, vp * 3, vp, f64, vp * 3, vp]),
         "mg_setup": (i32, [P(Grid), P(MgOpts), P(vp)]),
         "mg_update_coeffs": (i32, [vp, vp * 3, vp]),
+        "mg_update_density": (i32, [vp, vp, vp]),
         "mg_solve": (i32, [vp, vp, vp, f64, i32, i32, P(MgStats), vp]),
         "mg_destroy": (None, [vp]),
         "mg_residual_norm": (i32, [vp, vp, vp, P(f64), vp]),
@@ -275,6 +278,14 @@ class Context:
                                         _vec3(beta, torch.float64), _stream()))
         return beta
 
+    def density(self, H, rho_in, rho_out, rho=None):
+        import torch
+        if rho is None:
+            rho = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+        _check(self.lib.ib_density(self.ptr, _dptr(H, torch.float64), rho_in, rho_out,
+                                   _dptr(rho, torch.float64), _stream()))
+        return rho
+
     def rhs(self, u_star, F, beta, dt, b=None):
         import torch
         if b is None:
@@ -383,6 +394,11 @@ class Multigrid:
         import torch
         self._beta = list(beta)  # keep the arrays alive while the handle refers to them
         _check(self.lib.mg_update_coeffs(self.ptr, _vec3(beta, torch.float64), _stream()))
+
+    def update_density(self, rho):
+        import torch
+        self._beta = [rho]  # keep the array alive while the handle refers to it
+        _check(self.lib.mg_update_density(self.ptr, _dptr(rho, torch.float64), _stream()))
 
     def residual_norm(self, b, p):
         import torch
