@@ -45,6 +45,7 @@ struct Level {
     bool own_pb = true;
     bool fused = false;  // single-pass smoother applies
     int tz = 0;          // its z-range per workgroup
+    int rtz = 0;         // z-range of the density sweep (nx % 64 == 0)
     // finest level only: cell densities from which the float64 kernels form
     // the face coefficients themselves (f64.beta is then unused)
     const double* rho = nullptr;
@@ -408,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
         const int c = y * kFRX + x;
         const int ix = (y - 1) * kFXW + (x - 1);
         const int iz = (y - 1) * kFZW + (x - 1);
-        T* Pc = P[kk & 3];
+        const T* Pc = P[kk & 3];
         const T* Pd = P[(kk - 1) & 3];
         const T* Pu = P[(kk + 1) & 3];
         const T* X = BX[kk & 1];
@@ -424,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
         bl = BZ[mod3(kk)][iz];
         num += br * Pu[c] + bl * Pd[c];
         diag += br + bl;
-        Pc[c] = (num - h2 * B[kk & 1][iz]) / diag;
+        return (num - h2 * B[kk & 1][iz]) / diag;
     };
     auto step = [&](Stage& S, int k) {
         commit(S, k);
@@ -436,24 +437,28 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
         // those: every lane has a cell of the colour)
         for (int q = t; q < kFRedN; q += kBlock) {
             int y = 1 + q / kFRedRow;
-            update(1 + ((i0 + 1 + j0 + y + k) & 1) + 2 * (q % kFRedRow), y, k);
+            int x = 1 + ((i0 + 1 + j0 + y + k) & 1) + 2 * (q % kFRedRow);
+            P[k & 3][y * kFRX + x] = update(x, y, k);
         }
         lds_barrier();
         const int kb = k - 1;
         if (kb >= z0 && kb < z1) {
-            // black cells of plane k - 1 on the tile
+            // black cells of plane k - 1 on the tile; plane k - 1 is then
+            // final: each lane writes its black cell and the red cell beside
+            // it (computed a step earlier), and no one reads black values of
+            // this plane from LDS again
+            const long base = pl(kb) + (long)(j0 + 2) * d.nx + (i0 + 2);
             for (int q = t; q < kFBlackN; q += kBlock) {
-                int y = 2 + q / kFBlackRow;
-                update(2 + ((i0 + 3 + j0 + y + kb) & 1) + 2 * (q % kFBlackRow), y, kb);
-            }
-            lds_barrier();
-            const T* Pc = P[kb & 3];
-            long base = pl(kb) + (long)(j0 + 2) * d.nx + (i0 + 2);
-            for (int q = t; q < kFTX * kFTY; q += kBlock) {
-                int x = q % kFTX, y = q / kFTX;
-                pout[base + (long)y * d.nx + x] = Pc[(y + 2) * kFRX + x + 2];
+                int y = 2 + q / kFBlackRow, m = q % kFBlackRow;
+                int par = (i0 + 3 + j0 + y + kb) & 1;
+                T v = update(2 + par + 2 * m, y, kb);
+                T r = P[kb & 3][y * kFRX + 3 - par + 2 * m];
+                T* o = pout + base + (long)(y - 2) * d.nx + 2 * m;
+                o[par] = v;
+                o[1 - par] = r;
             }
         }
+        // the next commit overwrites the plane below k - 1
         lds_barrier();
     };
     // steps z0 - 1 .. z1 in pairs (stage A, stage B); TZ is even
@@ -470,15 +475,22 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
 // written, b, rho) instead of 48 with three stored face arrays; the update is
 // the one above, operand for operand, so the results are bitwise those of
 // the stored-face sweep.
-__global__ __launch_bounds__(kBlock) void k_rbgs_fused_rho(const double* __restrict__ pin,
-                                                           double* __restrict__ pout,
-                                                           const double* __restrict__ bb,
-                                                           const double* __restrict__ rho, Dims d,
-                                                           double h2, int TZ, int ntx, int nty,
-                                                           int nzc) {
-    __shared__ double P[4][kFRN];
-    __shared__ double R[4][kFRN];
-    __shared__ double B[2][kFZN];
+template <int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const double* __restrict__ pin,
+                                                       double* __restrict__ pout,
+                                                       const double* __restrict__ bb,
+                                                       const double* __restrict__ rho, Dims d,
+                                                       double h2, int TZ, int ntx, int nty,
+                                                       int nzc) {
+    // region of p and rho: the tile and a two-cell halo; b: the one-cell ring
+    constexpr int RX = TX + 4, RY = TY + 4, RN = RX * RY;
+    constexpr int ZW = RX - 2, ZN = ZW * (RY - 2);
+    constexpr int NL = (RN + NT - 1) / NT, NZL = (ZN + NT - 1) / NT;
+    constexpr int RedRow = (RX - 2) / 2, RedN = RedRow * (RY - 2);
+    constexpr int BlackRow = TX / 2, BlackN = BlackRow * TY;
+    __shared__ double P[4][RN];
+    __shared__ double R[4][RN];
+    __shared__ double B[2][ZN];
     const int nw = ntx * nty * nzc;
     const int bid = blockIdx.x;
     const int w = (nw % 8 == 0) ? (bid % 8) * (nw / 8) + bid / 8 : bid;
@@ -486,7 +498,7 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused_rho(const double* __restr
     const int r0 = w / ntx;
     const int ty = r0 % nty;
     const int zc = r0 / nty;
-    const int i0 = tx * kFTX - 2, j0 = ty * kFTY - 2;
+    const int i0 = tx * TX - 2, j0 = ty * TY - 2;
     const int z0 = zc * TZ, z1 = z0 + TZ;
     const long plane = (long)d.nx * d.ny;
     const int t = threadIdx.x;
@@ -496,58 +508,58 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused_rho(const double* __restr
     // cell and are not stored), so the loads are unconditional and the
     // compiler's wait counts are exact: a commit waits for its own plane only,
     // not for the loads and stores issued after it
-    int gp[kFLoads], gz[kFZLoads];
-    bool vp[kFLoads], vz[kFZLoads];
+    int gp[NL], gz[NZL];
+    bool vp[NL], vz[NZL];
 #pragma unroll
-    for (int s = 0; s < kFLoads; ++s) {
-        int q = t + s * kBlock;
-        vp[s] = q < kFRN;
-        gp[s] = vp[s] ? gofs(q % kFRX, q / kFRX) : gofs(0, 0);
+    for (int s = 0; s < NL; ++s) {
+        int q = t + s * NT;
+        vp[s] = q < RN;
+        gp[s] = vp[s] ? gofs(q % RX, q / RX) : gofs(0, 0);
     }
 #pragma unroll
-    for (int s = 0; s < kFZLoads; ++s) {
-        int q = t + s * kBlock;
-        vz[s] = q < kFZN;
-        gz[s] = vz[s] ? gofs(1 + q % kFZW, 1 + q / kFZW) : gofs(1, 1);
+    for (int s = 0; s < NZL; ++s) {
+        int q = t + s * NT;
+        vz[s] = q < ZN;
+        gz[s] = vz[s] ? gofs(1 + q % ZW, 1 + q / ZW) : gofs(1, 1);
     }
     // planes z0 - 2 .. z1 + 2 lie within one period of the box
     auto pl = [&](int k) { return (long)wrap_near(k, d.nz) * plane; };
     // two register stages, alternating: the planes of step k, p(k+1), rho(k+1)
     // and b(k), are loaded two steps ahead
     struct Stage {
-        double p[kFLoads], r[kFLoads], b[kFZLoads];
+        double p[NL], r[NL], b[NZL];
     };
     Stage SA, SB;
     auto fetch = [&](Stage& S, int k) {
         long bp = pl(k + 1), bk = pl(k);
 #pragma unroll
-        for (int s = 0; s < kFLoads; ++s) {
+        for (int s = 0; s < NL; ++s) {
             S.p[s] = pin[bp + gp[s]];
             S.r[s] = rho[bp + gp[s]];
         }
 #pragma unroll
-        for (int s = 0; s < kFZLoads; ++s) S.b[s] = bb[bk + gz[s]];
+        for (int s = 0; s < NZL; ++s) S.b[s] = bb[bk + gz[s]];
     };
     auto commit = [&](const Stage& S, int k) {
 #pragma unroll
-        for (int s = 0; s < kFLoads; ++s)
-            if (s * kBlock + kBlock <= kFRN || vp[s]) {
-                P[(k + 1) & 3][t + s * kBlock] = S.p[s];
-                R[(k + 1) & 3][t + s * kBlock] = S.r[s];
+        for (int s = 0; s < NL; ++s)
+            if (s * NT + NT <= RN || vp[s]) {
+                P[(k + 1) & 3][t + s * NT] = S.p[s];
+                R[(k + 1) & 3][t + s * NT] = S.r[s];
             }
 #pragma unroll
-        for (int s = 0; s < kFZLoads; ++s)
-            if (s * kBlock + kBlock <= kFZN || vz[s]) B[k & 1][t + s * kBlock] = S.b[s];
+        for (int s = 0; s < NZL; ++s)
+            if (s * NT + NT <= ZN || vz[s]) B[k & 1][t + s * NT] = S.b[s];
     };
     {
         long a = pl(z0 - 2), a1 = pl(z0 - 1);
 #pragma unroll
-        for (int s = 0; s < kFLoads; ++s)
+        for (int s = 0; s < NL; ++s)
             if (vp[s]) {
-                P[(z0 - 2) & 3][t + s * kBlock] = pin[a + gp[s]];
-                P[(z0 - 1) & 3][t + s * kBlock] = pin[a1 + gp[s]];
-                R[(z0 - 2) & 3][t + s * kBlock] = rho[a + gp[s]];
-                R[(z0 - 1) & 3][t + s * kBlock] = rho[a1 + gp[s]];
+                P[(z0 - 2) & 3][t + s * NT] = pin[a + gp[s]];
+                P[(z0 - 1) & 3][t + s * NT] = pin[a1 + gp[s]];
+                R[(z0 - 2) & 3][t + s * NT] = rho[a + gp[s]];
+                R[(z0 - 1) & 3][t + s * NT] = rho[a1 + gp[s]];
             }
     }
     fetch(SA, z0 - 1);
@@ -555,14 +567,14 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused_rho(const double* __restr
     __builtin_amdgcn_sched_barrier(0);
     fetch(SB, z0);
     auto update = [&](int x, int y, int kk) {
-        const int c = y * kFRX + x;
-        const int iz = (y - 1) * kFZW + (x - 1);
-        double* Pc = P[kk & 3];
+        const int c = y * RX + x;
+        const int iz = (y - 1) * ZW + (x - 1);
+        const double* Pc = P[kk & 3];
         const double* Pd = P[(kk - 1) & 3];
         const double* Pu = P[(kk + 1) & 3];
         const double* Rc = R[kk & 3];
         const double rc = Rc[c];
-        const double rxp = Rc[c + 1], rxm = Rc[c - 1], ryp = Rc[c + kFRX], rym = Rc[c - kFRX];
+        const double rxp = Rc[c + 1], rxm = Rc[c - 1], ryp = Rc[c + RX], rym = Rc[c - RX];
         const double rzp = R[(kk + 1) & 3][c], rzm = R[(kk - 1) & 3][c];
         double bxp, bxm, byp, bym, bzp, bzm;
         if (rxp == rc && rxm == rc && ryp == rc && rym == rc && rzp == rc && rzm == rc) {
@@ -578,11 +590,11 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused_rho(const double* __restr
         }
         double num = bxp * Pc[c + 1] + bxm * Pc[c - 1];
         double diag = bxp + bxm;
-        num += byp * Pc[c + kFRX] + bym * Pc[c - kFRX];
+        num += byp * Pc[c + RX] + bym * Pc[c - RX];
         diag += byp + bym;
         num += bzp * Pu[c] + bzm * Pd[c];
         diag += bzp + bzm;
-        Pc[c] = (num - h2 * B[kk & 1][iz]) / diag;
+        return (num - h2 * B[kk & 1][iz]) / diag;
     };
     auto step = [&](Stage& S, int k) {
         commit(S, k);
@@ -590,23 +602,23 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused_rho(const double* __restr
         // committed), which keeps the loads unconditional
         fetch(S, k + 2 <= z1 ? k + 2 : z1);
         lds_barrier();
-        for (int q = t; q < kFRedN; q += kBlock) {
-            int y = 1 + q / kFRedRow;
-            update(1 + ((i0 + 1 + j0 + y + k) & 1) + 2 * (q % kFRedRow), y, k);
+        for (int q = t; q < RedN; q += NT) {
+            int y = 1 + q / RedRow;
+            int x = 1 + ((i0 + 1 + j0 + y + k) & 1) + 2 * (q % RedRow);
+            P[k & 3][y * RX + x] = update(x, y, k);
         }
         lds_barrier();
         const int kb = k - 1;
         if (kb >= z0 && kb < z1) {
-            for (int q = t; q < kFBlackN; q += kBlock) {
-                int y = 2 + q / kFBlackRow;
-                update(2 + ((i0 + 3 + j0 + y + kb) & 1) + 2 * (q % kFBlackRow), y, kb);
-            }
-            lds_barrier();
-            const double* Pc = P[kb & 3];
-            long base = pl(kb) + (long)(j0 + 2) * d.nx + (i0 + 2);
-            for (int q = t; q < kFTX * kFTY; q += kBlock) {
-                int x = q % kFTX, y = q / kFTX;
-                pout[base + (long)y * d.nx + x] = Pc[(y + 2) * kFRX + x + 2];
+            const long base = pl(kb) + (long)(j0 + 2) * d.nx + (i0 + 2);
+            for (int q = t; q < BlackN; q += NT) {
+                int y = 2 + q / BlackRow, m = q % BlackRow;
+                int par = (i0 + 3 + j0 + y + kb) & 1;
+                double v = update(2 + par + 2 * m, y, kb);
+                double r = P[kb & 3][y * RX + 3 - par + 2 * m];
+                double* o = pout + base + (long)(y - 2) * d.nx + 2 * m;
+                o[par] = v;
+                o[1 - par] = r;
             }
         }
         lds_barrier();
@@ -923,6 +935,9 @@ __global__ void k_sub_scalar_mean(double* __restrict__ p, long N, const double* 
 
 // ---------------------------------------------------------------------------
 // host side
+// tile of the density sweep: 64 x 8 cells, 512 threads (2 workgroups per CU)
+constexpr int kRTX = 64, kRTY = 8, kRNT = 512;
+
 template <typename T> LevelT<T>& lvl(Level& L);
 template <> LevelT<double>& lvl<double>(Level& L) { return L.f64; }
 template <> LevelT<float>& lvl<float>(Level& L) { return L.f32; }
@@ -950,8 +965,9 @@ static void launch_fused(Level& L, T* pin, T* pout, hipStream_t st, bool finest)
     int ntx = L.d.nx / kFTX, nty = L.d.ny / kFTY, nzc = L.d.nz / L.tz;
     if constexpr (sizeof(T) == 8) {
         if (L.rho) {
-            hipLaunchKernelGGL(k_rbgs_fused_rho, dim3(ntx * nty * nzc), dim3(kBlock), 0, st, pin, pout,
-                               A.b, L.rho, L.d, h2, L.tz, ntx, nty, nzc);
+            const int rx = L.d.nx / kRTX, ry = L.d.ny / kRTY, rz = L.d.nz / L.rtz;
+            hipLaunchKernelGGL((k_rbgs_fused_rho<kRTX, kRTY, kRNT>), dim3(rx * ry * rz), dim3(kRNT), 0, st,
+                               pin, pout, A.b, L.rho, L.d, h2, L.rtz, rx, ry, rz);
             return;
         }
     }
@@ -1180,6 +1196,14 @@ extern "C" int mg_setup(const ib_grid* g, const mg_opts* o, mg_handle** out) {
             int tz = lv.d.nz;
             while (tz % 4 == 0 && tz > 16 && tiles * (lv.d.nz / tz) < 1024) tz /= 2;
             lv.tz = tz;
+            if (lv.d.nx % kRTX == 0) {
+                long rtiles = (long)(lv.d.nx / kRTX) * (lv.d.ny / kRTY);
+                int rtz = lv.d.nz;
+                // 1024 workgroups on 256^3 (z-range 32): two rounds of the 512
+                // resident ones keep the z-marches short and the XCDs balanced
+                while (rtz % 4 == 0 && rtz > 16 && rtiles * (lv.d.nz / rtz) < 1024) rtz /= 2;
+                lv.rtz = rtz;
+            }
         }
         if (l > 0) {
             if (hipMalloc(&lv.f64.p, N * sizeof(double)) != hipSuccess ||
@@ -1286,7 +1310,7 @@ static int update_hierarchy(mg_handle* m, const double* const beta[3], const dou
 // single-pass smoother, the 64-wide restriction and at least one coarse level
 static bool density_direct(const mg_handle* m) {
     const Level& L0 = m->lv[0];
-    return m->g.dim == 3 && L0.fused && L0.d.nx % 64 == 0 && m->lv.size() >= 2;
+    return m->g.dim == 3 && L0.fused && L0.rtz > 0 && L0.d.nx % 64 == 0 && m->lv.size() >= 2;
 }
 
 int mg_takes_density(const mg_handle* m) { return m && density_direct(m) ? 1 : 0; }
