@@ -24,6 +24,13 @@ cycle, stop when ||b - A p||_2 / ||b||_2 <= rtol.
 Mixed precision: the same V-cycle in float32 (float32 coefficients, float32
 right side and correction, coarsest level in float64) inside a float64
 defect-correction loop r = b - A p (float64), p += V32(fl32(r)).
+
+Krylov variant (an extension; the paper only names multigrid): flexible
+conjugate gradients (the Polak-Ribiere form of the direction update, which
+tolerates a preconditioner that is not exactly symmetric) preconditioned by
+one V-cycle from a zero guess. The V-cycle here is not symmetric (mean
+restriction with linear prolongation; red-then-black in both smoothing
+passes), hence the flexible form. Stops on the recursively updated residual.
 """
 import numpy as np
 
@@ -284,3 +291,66 @@ def mg_solve_mixed(b, beta, h, p0=None, rtol=1e-10, max_cycles=100, nu1=2, nu2=2
         cycles += 1
         hist.append(rel_residual(p, b, beta, h))
     return p, cycles, hist
+
+
+# ----------------------------------------------------------------------------
+# Flexible conjugate gradients preconditioned by multigrid
+# ----------------------------------------------------------------------------
+def fcg(apply, precond, b, x0=None, rtol=1e-10, max_iter=100, fixed_iters=None):
+    """Flexible CG for an SPD (or, as here, positive semidefinite with b in
+    its range) operator. Returns (x, iterations, history of ||r|| / ||b||),
+    r updated recursively:
+
+        r = b - A x, z = M(r), d = z, rz = (r, z)
+        repeat: q = A d, alpha = rz / (d, q), x += alpha d, r -= alpha q,
+                z = M(r), beta = (r_new - r_old, z) / rz = -alpha (q, z) / rz,
+                rz = (r, z), d = z + beta d
+    """
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - apply(x)
+    bn = np.linalg.norm(b)
+    hist = [np.linalg.norm(r) / bn]
+    it = 0
+
+    def done():
+        if fixed_iters is not None:
+            return it >= fixed_iters
+        return hist[-1] <= rtol or it >= max_iter
+
+    if done():
+        return x, it, hist
+    z = precond(r)
+    d = z.copy()
+    rz = np.vdot(r, z)
+    while True:
+        q = apply(d)
+        alpha = rz / np.vdot(d, q)
+        x += alpha * d
+        r -= alpha * q
+        it += 1
+        hist.append(np.linalg.norm(r) / bn)
+        if done():
+            break
+        z = precond(r)
+        beta = -alpha * np.vdot(q, z) / rz
+        rz = np.vdot(r, z)
+        d = z + beta * d
+    return x, it, hist
+
+
+def mg_pcg(b, beta, h, p0=None, rtol=1e-10, max_iter=100, nu1=2, nu2=2, n_coarsest=4,
+           fixed_iters=None, mixed=False):
+    """FCG with one V(nu1, nu2) cycle from zero as preconditioner (float32
+    V-cycle on fl32(r) when mixed); mean of p removed at the end."""
+    hier = Hierarchy(beta, h, n_coarsest, dtype=np.float32 if mixed else np.float64)
+
+    def precond(r):
+        if mixed:
+            r32 = r.astype(np.float32)
+            return vcycle(hier, 0, np.zeros_like(r32), r32, nu1, nu2).astype(np.float64)
+        return vcycle(hier, 0, np.zeros_like(r), r, nu1, nu2)
+
+    p, it, hist = fcg(lambda v: apply_A(v, beta, h), precond, b, p0, rtol, max_iter, fixed_iters)
+    p -= p.mean()
+    return p, it, hist
+

@@ -4,6 +4,9 @@ Pins: dense direct solve of the bordered system on 16^2 and 8^3 at density
 ratio 1000; diagonalisation (FFT) for constant coefficients; a discrete
 manufactured solution; second-order convergence for a continuous one;
 symmetry of A; divergence-free corrected velocity (the projection property).
+Flexible CG: finite termination with the identity preconditioner (plain CG),
+one iteration with the exact inverse, the dense direct solve and FFT solve
+when converged, and fewer V-cycles than plain multigrid on a drop.
 """
 import numpy as np
 import pytest
@@ -136,3 +139,73 @@ def test_projection_makes_velocity_divergence_free():
     u = poisson.velocity_update(us, F, beta, p, dt, h)
     div = poisson.divergence(u, h)
     assert np.max(np.abs(div)) <= 1e-9 * np.max(np.abs(poisson.divergence(us, h)))
+
+
+# ----------------------------------------------------------------------------
+# flexible CG preconditioned by multigrid
+def test_fcg_finite_termination_identity_preconditioner():
+    """With M = I the method is plain CG: on an SPD matrix with m distinct
+    eigenvalues it reaches the solution in at most m iterations (exact
+    arithmetic; here to ~1e-12). A wrong alpha or beta breaks this."""
+    rng = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(rng.standard_normal((12, 12)))
+    lam = np.repeat([1.0, 2.0, 5.0, 11.0, 30.0], [3, 3, 2, 2, 2])
+    A = (Q * lam) @ Q.T
+    b = rng.standard_normal(12)
+    x, it, hist = poisson.fcg(lambda v: A @ v, lambda r: r.copy(), b, rtol=1e-12, max_iter=50)
+    assert it <= 5
+    assert np.linalg.norm(A @ x - b) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_fcg_exact_preconditioner_one_iteration():
+    rng = np.random.default_rng(4)
+    M = rng.standard_normal((10, 10))
+    A = M @ M.T + 10 * np.eye(10)
+    Ainv = np.linalg.inv(A)
+    b = rng.standard_normal(10)
+    x, it, hist = poisson.fcg(lambda v: A @ v, lambda r: Ainv @ r, b, rtol=1e-12)
+    assert it == 1
+    assert np.linalg.norm(x - Ainv @ b) <= 1e-12 * np.linalg.norm(Ainv @ b)
+
+
+@pytest.mark.parametrize("shape", [(16, 16), (8, 8, 8)])
+def test_mg_pcg_matches_dense_direct(shape):
+    beta = _drop_beta(shape)
+    h = 1.0 / shape[0]
+    b = W.random_cells(tuple(reversed(shape)), len(shape), 1.0, seed=22)
+    b -= b.mean()
+    pd = poisson.direct_solve(b, beta, h)
+    p, it, hist = poisson.mg_pcg(b, beta, h, rtol=1e-13)
+    assert hist[-1] <= 1e-13
+    assert np.max(np.abs(p - pd)) <= 1e-10 * np.max(np.abs(pd))
+    # the recursive residual tracks the true one
+    true = np.linalg.norm(b - poisson.apply_A(p, beta, h)) / np.linalg.norm(b)
+    assert true <= 1e-12
+
+
+def test_mg_pcg_constant_coefficient_fft():
+    shape = (16, 16, 16)
+    h = 1.0 / 16
+    beta = [np.full(shape, 0.7) for _ in range(3)]
+    b = W.random_cells(shape, 3, 1.0, seed=6)
+    b -= b.mean()
+    p, _, _ = poisson.mg_pcg(b, beta, h, rtol=1e-13)
+    pf = poisson.fft_solve(b, 0.7, h)
+    assert np.max(np.abs(p - pf)) <= 1e-10 * np.max(np.abs(pf))
+
+
+def test_mg_pcg_fewer_iterations_than_vcycles_and_mixed():
+    """Drop at density ratio 1000 on 32^3: the Krylov wrapper needs fewer
+    V-cycles than plain multigrid for the same stopping test, and the mixed
+    (float32 preconditioner) variant converges to the same answer."""
+    shape = (32, 32, 32)
+    beta = _drop_beta(shape)
+    h = 1.0 / 32
+    b = W.random_cells(shape, 3, 1.0, seed=23)
+    b -= b.mean()
+    pm, cyc, _ = poisson.mg_solve(b, beta, h, rtol=1e-10)
+    p, it, hist = poisson.mg_pcg(b, beta, h, rtol=1e-10)
+    p32, it32, _ = poisson.mg_pcg(b, beta, h, rtol=1e-10, mixed=True)
+    assert it < cyc
+    assert np.linalg.norm(p - pm) <= 1e-8 * np.linalg.norm(pm)
+    assert np.linalg.norm(p32 - p) <= 1e-8 * np.linalg.norm(p)
