@@ -46,7 +46,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_variant(ib, torch, wl, geo, precision, steps, warmup, profile, warm=False):
+def run_variant(ib, torch, wl, geo, precision, steps, warmup, profile, warm=False, krylov=0):
     n, h = wl.n, wl.h
     shape = tuple(reversed(n))
     V, T = wl.X, wl.tris
@@ -56,7 +56,7 @@ def run_variant(ib, torch, wl, geo, precision, steps, warmup, profile, warm=Fals
     fsd, dsd, nd = (torch.from_numpy(a).cuda() for a in (fs, ds, nrm))
     surf = ib.make_surface(Vd, elems=Td, nrm=nd, fs=fsd, ds=dsd)
     ctx = ib.Context(3, n, h, max_markers=len(V), max_elems=len(T))
-    mg = ib.Multigrid(3, n, h, precision=precision)
+    mg = ib.Multigrid(3, n, h, precision=precision, krylov=krylov)
     params = dict(rho_in=wl.rho_in, rho_out=wl.rho_out, sigma=wl.sigma, dt=wl.dt, rtol=1e-10,
                   max_cycles=100, warm_start=ib.WS_PREV if warm else ib.WS_ZERO)
     u = [torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(3)]
@@ -198,7 +198,7 @@ def bench_2d_c4_nn(ib, torch, n=512, steps=48, train_iters=300):
                 cold_solve_ms_nn_incl_inference=round(1e3 * t_nn / len(held), 3))
 
 
-def cpu_baseline(wl, cycles_per_step):
+def cpu_baseline(wl, cycles_per_step, krylov):
     """The oracle on a bounded sample of the same 256^3 step, extrapolated to one step."""
     from oracle import heaviside, poisson
     n, h = wl.n, wl.h
@@ -220,6 +220,21 @@ def cpu_baseline(wl, cycles_per_step):
     t0 = time.perf_counter()
     p = poisson.vcycle(hier, 0, p, b)
     t["vcycle"] = time.perf_counter() - t0
+    if krylov:
+        # the rest of one flexible-CG iteration of the oracle: q = A d, the
+        # three inner products and the three vector updates
+        d, r = p.copy(), b.copy()
+        t0 = time.perf_counter()
+        q = poisson.apply_A(d, beta, h)
+        alpha = np.vdot(r, p) / np.vdot(d, q)
+        p += alpha * d
+        r -= alpha * q
+        np.linalg.norm(r)
+        bq = np.vdot(q, p)
+        np.vdot(r, p)
+        d = p + bq * d
+        t["cg_vectors"] = time.perf_counter() - t0
+        t["vcycle"] += t["cg_vectors"]
     # coefficients, right side, update at full size
     F = [np.zeros(shape) for _ in range(3)]
     u = [np.zeros(shape) for _ in range(3)]
@@ -256,7 +271,8 @@ def cpu_baseline(wl, cycles_per_step):
     nfaces = 3 * 4 * math.pi * 0.25 ** 2 * 5.8 * h / h ** 3
     t["face_force"] = tF / len(pts) * nfaces
     per_step = t["grid_ops"] + t["heaviside"] + t["face_force"] + cycles_per_step * t["vcycle"]
-    sample = (f"256^3 oracle: one FP64 V-cycle ({t['vcycle']:.1f} s) x {cycles_per_step:.1f} cycles/step, "
+    what = "flexible-CG iteration (V-cycle + vector work)" if krylov else "V-cycle"
+    sample = (f"256^3 oracle: one FP64 {what} ({t['vcycle']:.1f} s) x {cycles_per_step:.1f} per step, "
               f"coefficients+rhs+update ({t['grid_ops']:.1f} s), Heaviside on {len(cols)} columns scaled to "
               f"{ncols:.0f} columns ({t['heaviside']:.0f} s), nearest-element face value on 40 faces scaled "
               f"to {nfaces:.0f} band faces ({t['face_force']:.0f} s)")
@@ -272,6 +288,8 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--level", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--solver", choices=("fcg", "vcycle"), default="fcg",
+                    help="headline FP64 solver: flexible CG preconditioned by V(2,2), or V(2,2) cycles")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D workloads (C2, learned warm start)")
@@ -310,21 +328,34 @@ def main():
             out["speedup_vs_fp64_cold"] = round(sps / ref, 3)
         return out
 
-    log("== FP64 multigrid, cold start every step")
-    r64 = run_variant(ib, torch, wl, geo, ib.MG_FP64, args.steps, args.warmup, profile=True)
+    # the headline solver: FP64 flexible CG preconditioned by one V(2,2) cycle
+    # (--solver vcycle: plain V(2,2) cycles); the other one is reported beside it
+    head_k = 1 if args.solver == "fcg" else 0
+    names = {1: "fcg", 0: "vcycle"}
+    log(f"== FP64 {names[head_k]}, cold start every step (headline)")
+    r64 = run_variant(ib, torch, wl, geo, ib.MG_FP64, args.steps, args.warmup, profile=True,
+                      krylov=head_k)
     sps64 = r64["steps"] / r64["seconds"]
-    variants = {"fp64_cold": summary(r64)}
+    variants = {f"fp64_cold_{names[head_k]}": summary(r64)}
+    log(f"== FP64 {names[1 - head_k]}, cold start every step")
+    ro = run_variant(ib, torch, wl, geo, ib.MG_FP64, args.steps, args.warmup, profile=False,
+                     krylov=1 - head_k)
+    variants[f"fp64_cold_{names[1 - head_k]}"] = summary(ro, sps64)
     if not args.no_mixed:
-        log("== mixed FP32/FP64 multigrid, cold start every step")
-        rmx = run_variant(ib, torch, wl, geo, ib.MG_MIXED, args.steps, args.warmup, profile=True)
-        variants["mixed_cold"] = summary(rmx, sps64)
-        variants["mixed_cold"]["kernels"] = {k: dict(launches=v[0], avg_us=round(1e3 * v[1] / v[0], 2))
-                                             for k, v in rmx["prof"].items() if v[0]}
+        for kry in (head_k, 1 - head_k):
+            log(f"== mixed FP32/FP64 {names[kry]}, cold start every step")
+            rmx = run_variant(ib, torch, wl, geo, ib.MG_MIXED, args.steps, args.warmup,
+                              profile=kry == head_k, krylov=kry)
+            variants[f"mixed_cold_{names[kry]}"] = summary(rmx, sps64)
+            if kry == head_k:
+                variants[f"mixed_cold_{names[kry]}"]["kernels"] = {
+                    k: dict(launches=v[0], avg_us=round(1e3 * v[1] / v[0], 2))
+                    for k, v in rmx["prof"].items() if v[0]}
     if not args.no_warm:
-        log("== FP64 multigrid, warm start from the previous pressure")
+        log(f"== FP64 {names[head_k]}, warm start from the previous pressure")
         rw = run_variant(ib, torch, wl, geo, ib.MG_FP64, args.steps, args.warmup, profile=False,
-                         warm=True)
-        variants["fp64_warm"] = summary(rw, sps64)
+                         warm=True, krylov=head_k)
+        variants[f"fp64_warm_{names[head_k]}"] = summary(rw, sps64)
     # roofline of the dominant kernel: the finest-level FP64 smoother, either
     # one full single-pass sweep or one colour pass (half a sweep)
     N = float(np.prod(wl.n))
@@ -355,7 +386,9 @@ def main():
                 config=dict(workload=f"static_drop_3d_{args.size}: {args.size}^3 periodic box, sphere R=0.25 "
                                      f"(level-{args.level} icosphere, {len(wl.X)} markers, {len(wl.tris)} "
                                      f"triangles, seeded rotation 3), rho ratio 1000, sigma=1, dt=5e-5, "
-                                     f"irrotational spreading, FP64 multigrid V(2,2) from p=0 to 1e-10 every step",
+                                     f"irrotational spreading, FP64 pressure solve from p=0 to 1e-10 every step by "
+                                     + ("flexible CG preconditioned by one V(2,2) cycle" if head_k else
+                                        "V(2,2) multigrid cycles"),
                             grid=list(wl.n), markers=len(wl.X), triangles=len(wl.tris)),
                 variants=variants, roofline=roof, kernels_fp64=prof_summary)
     if not args.no_2d:
@@ -365,7 +398,8 @@ def main():
         line["nn_2d"] = bench_2d_c4_nn(ib, torch)
     if not args.no_cpu_baseline:
         log("== CPU oracle baseline (bounded sample)")
-        line["cpu_baseline"] = cpu_baseline(wl, variants["fp64_cold"]["mean_cycles"])
+        line["cpu_baseline"] = cpu_baseline(wl, variants[f"fp64_cold_{names[head_k]}"]["mean_cycles"],
+                                            head_k)
     print(json.dumps(line), flush=True)
 
 

@@ -157,17 +157,27 @@ int ib_update(ib_ctx* ctx, const double* const u_star[3], const double* const F[
  * the zero-mean constraint, mean removed once after the last cycle (a cycle
  * commutes with adding a constant).
  * MG_MIXED: float32 V-cycles on the float64 defect r = b - A p (float64
- * residual, update and coarsest solve), same stopping test. */
+ * residual, update and coarsest solve), same stopping test.
+ * krylov = 1 (an extension; the paper names multigrid only): flexible
+ * conjugate gradients in float64 preconditioned by one V-cycle from a zero
+ * guess (float32 V-cycle under MG_MIXED),
+ *   r = b - A p, z = V(r), d = z;  each iteration q = A d, alpha = (r,z)/(d,q),
+ *   p += alpha d, r -= alpha q, z = V(r), beta = -alpha (q,z)/(r,z)_old,
+ *   d = z + beta d;
+ * the stopping test reads the recursively updated r. Four more float64 cell
+ * arrays. Deterministic: every sum has a fixed order. */
 typedef struct {
     int precision;   /* MG_FP64 or MG_MIXED */
     int nu1, nu2;    /* smoothing sweeps before / after the coarse correction (2, 2) */
     int n_coarsest;  /* cells per axis on the coarsest grid (4); n[d] = n_coarsest * 2^L */
+    int krylov;      /* 0: V-cycles; 1: flexible CG preconditioned by one V-cycle */
 } mg_opts;
 
 typedef struct {
-    int cycles;              /* V-cycles (outer iterations in MG_MIXED) performed */
+    int cycles;              /* V-cycles (outer iterations in MG_MIXED; CG iterations, one
+                                V-cycle each, with krylov) performed */
     double rel_res0;         /* ||b - A p0|| / ||b|| of the initial guess */
-    double rel_res;          /* final ||b - A p|| / ||b|| */
+    double rel_res;          /* final ||b - A p|| / ||b|| (recursive residual with krylov) */
     double res_hist[128];    /* rel_res after each cycle (first 128); -1 for cycles run
                                 without a check (the solver skips norms it can predict) */
 } mg_stats;

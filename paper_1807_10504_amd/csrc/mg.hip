@@ -70,6 +70,13 @@ struct mg_handle {
     // finest face arrays formed from densities on grids whose kernels cannot
     // read the densities directly
     double* beta0[3] = {nullptr, nullptr, nullptr};
+    // flexible CG (krylov): residual r, preconditioned residual z (float64
+    // V-cycle), direction d, q = A d; device scalars
+    double* kr = nullptr;
+    double* kz = nullptr;
+    double* kd = nullptr;
+    double* kq = nullptr;
+    double* ks = nullptr;
 };
 
 namespace ib {
@@ -934,6 +941,114 @@ __global__ void k_sub_scalar_mean(double* __restrict__ p, long N, const double* 
 }
 
 // ---------------------------------------------------------------------------
+// flexible CG. Scalars live on the device (ks) and each kernel forms alpha
+// and beta from them, so an iteration needs no host round trip.
+enum { KS_RZ0 = 0, KS_RZ1 = 1, KS_DQ = 2, KS_QZ = 3, KS_RR = 4, KS_BB = 5 };
+
+// r = b - A x with partial sums of r^2 and b^2
+template <int DIM, class K>
+__global__ void k_residual_vec(const double* __restrict__ x, const double* __restrict__ b, K co,
+                               Dims d, double inv_h2, double* __restrict__ r,
+                               double* __restrict__ partial_r2, double* __restrict__ partial_b2) {
+    __shared__ double sh[kBlock];
+    double ar = 0.0, ab = 0.0;
+    const int N = (int)d.cells(), nx = d.nx, ny = d.ny;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < N; c += gridDim.x * blockDim.x) {
+        int i = c % nx;
+        int rr = c / nx;
+        int j = rr % ny;
+        int k = rr / ny;
+        Nb n = neighbours(d, i, j, k, DIM);
+        double bv = b[c];
+        double rv = bv - apply_row<double, DIM>(x, co, n) * inv_h2;
+        r[c] = rv;
+        ar += rv * rv;
+        ab += bv * bv;
+    }
+    double s = block_reduce_sum(ar, sh);
+    if (threadIdx.x == 0) partial_r2[blockIdx.x] = s;
+    s = block_reduce_sum(ab, sh);
+    if (threadIdx.x == 0) partial_b2[blockIdx.x] = s;
+}
+
+// q = A d with partial sums of d q
+template <int DIM, class K>
+__global__ void k_apply_dot(const double* __restrict__ dv, K co, Dims d, double inv_h2,
+                            double* __restrict__ q, double* __restrict__ partial) {
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    const int N = (int)d.cells(), nx = d.nx, ny = d.ny;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < N; c += gridDim.x * blockDim.x) {
+        int i = c % nx;
+        int rr = c / nx;
+        int j = rr % ny;
+        int k = rr / ny;
+        Nb n = neighbours(d, i, j, k, DIM);
+        double qv = apply_row<double, DIM>(dv, co, n) * inv_h2;
+        q[c] = qv;
+        acc += dv[c] * qv;
+    }
+    double s = block_reduce_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// alpha = (r,z) / (d,q); x += alpha d; r -= alpha q; partial sums of r^2
+__global__ void k_pcg_xr(double* __restrict__ x, double* __restrict__ r,
+                         const double* __restrict__ dv, const double* __restrict__ q, long N,
+                         const double* __restrict__ ks, int rz_slot,
+                         double* __restrict__ partial) {
+    __shared__ double sh[kBlock];
+    const double alpha = ks[rz_slot] / ks[KS_DQ];
+    double acc = 0.0;
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long)gridDim.x * blockDim.x) {
+        x[c] += alpha * dv[c];
+        double rv = r[c] - alpha * q[c];
+        r[c] = rv;
+        acc += rv * rv;
+    }
+    double s = block_reduce_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// partial sums of r z and (when q is given) q z; z is the float64 V-cycle
+// output or the float32 one
+template <typename TZ>
+__global__ void k_pcg_dots(const double* __restrict__ r, const double* __restrict__ q,
+                           const TZ* __restrict__ z, long N, double* __restrict__ partial_rz,
+                           double* __restrict__ partial_qz) {
+    __shared__ double sh[kBlock];
+    double a = 0.0, b = 0.0;
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long)gridDim.x * blockDim.x) {
+        double zv = (double)z[c];
+        a += r[c] * zv;
+        if (q) b += q[c] * zv;
+    }
+    double s = block_reduce_sum(a, sh);
+    if (threadIdx.x == 0) partial_rz[blockIdx.x] = s;
+    if (q) {
+        s = block_reduce_sum(b, sh);
+        if (threadIdx.x == 0) partial_qz[blockIdx.x] = s;
+    }
+}
+
+// d = z + beta d, beta = -alpha (q,z) / (r,z)_old with alpha = (r,z)_old / (d,q);
+// on the first iteration d = z
+template <typename TZ>
+__global__ void k_pcg_dir(double* __restrict__ dv, const TZ* __restrict__ z, long N,
+                          const double* __restrict__ ks, int rz_old_slot, int first) {
+    long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    if (first) {
+        dv[c] = (double)z[c];
+        return;
+    }
+    const double rz = ks[rz_old_slot];
+    const double alpha = rz / ks[KS_DQ];
+    const double beta = -alpha * ks[KS_QZ] / rz;
+    dv[c] = (double)z[c] + beta * dv[c];
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // tile of the density sweep: 64 x 8 cells, 512 threads (2 workgroups per CU)
 constexpr int kRTX = 64, kRTY = 8, kRNT = 512;
@@ -1152,6 +1267,7 @@ extern "C" int mg_setup(const ib_grid* g, const mg_opts* o, mg_handle** out) {
     IB_CHECK(o->precision == MG_FP64 || o->precision == MG_MIXED, IB_EINVAL, "mg_setup: precision");
     IB_CHECK(o->nu1 >= 0 && o->nu2 >= 0 && o->nu1 + o->nu2 > 0, IB_EINVAL, "mg_setup: sweeps");
     IB_CHECK(o->n_coarsest >= 2, IB_EINVAL, "mg_setup: n_coarsest");
+    IB_CHECK(o->krylov == 0 || o->krylov == 1, IB_EINVAL, "mg_setup: krylov must be 0 or 1");
     IB_CHECK(g->h > 0, IB_EINVAL, "mg_setup: h");
     int nmin = g->n[0];
     for (int e = 0; e < g->dim; ++e) {
@@ -1233,6 +1349,15 @@ extern "C" int mg_setup(const ib_grid* g, const mg_opts* o, mg_handle** out) {
         hipMalloc(&m->red, sizeof(double) * (3 * kRed + 8)) != hipSuccess ||
         hipHostMalloc(&m->host, sizeof(double) * 8) != hipSuccess)
         return cleanup(IB_ENOMEM, "mg_setup: out of memory");
+    if (o->krylov) {
+        const long N = m->lv[0].d.cells();
+        if (hipMalloc(&m->kr, N * sizeof(double)) != hipSuccess ||
+            hipMalloc(&m->kd, N * sizeof(double)) != hipSuccess ||
+            hipMalloc(&m->kq, N * sizeof(double)) != hipSuccess ||
+            (!mixed && hipMalloc(&m->kz, N * sizeof(double)) != hipSuccess) ||
+            hipMalloc(&m->ks, 16 * sizeof(double)) != hipSuccess)
+            return cleanup(IB_ENOMEM, "mg_setup: out of device memory");
+    }
     *out = m;
     return IB_OK;
 }
@@ -1252,6 +1377,11 @@ extern "C" void mg_destroy(mg_handle* m) {
         for (int e = 0; e < 3; ++e) hipFree(lv.f32.beta[e]);
     }
     for (int e = 0; e < 3; ++e) hipFree(m->beta0[e]);
+    hipFree(m->kr);
+    hipFree(m->kz);
+    hipFree(m->kd);
+    hipFree(m->kq);
+    hipFree(m->ks);
     hipFree(m->cmat);
     hipFree(m->cinv);
     hipFree(m->red);
@@ -1361,6 +1491,149 @@ extern "C" int mg_residual_norm(mg_handle* m, const double* b, const double* p, 
     return IB_OK;
 }
 
+// flexible CG preconditioned by one V-cycle (float64, or a float32 V-cycle
+// under MG_MIXED); same stopping logic and residual-check skipping as the
+// plain cycles, on the recursive residual
+static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, int max_it,
+                        int fixed, mg_stats* S, hipStream_t st) {
+    Level& L0 = m->lv[0];
+    const long N = L0.d.cells();
+    const int nb = red_blocks(N);
+    const int dim = L0.d.dim;
+    const double inv_h2 = 1.0 / (L0.d.h * L0.d.h);
+    const bool mixed = m->o.precision == MG_MIXED;
+    double* pa = m->red;
+    double* pb = m->red + kRed;
+    const CoefArrays<double> co{L0.f64.beta[0], L0.f64.beta[1],
+                                dim == 3 ? L0.f64.beta[2] : L0.f64.beta[1]};
+    const dim3 g1(grid_for(N)), gr(nb), blk(kBlock);
+    {
+        ProfScope ps(IB_PROF_RESID, st, true);
+        if (L0.rho)
+            hipLaunchKernelGGL((k_residual_vec<3, CoefRho>), gr, blk, 0, st, x, b, CoefRho{L0.rho}, L0.d,
+                               inv_h2, m->kr, pa, pb);
+        else if (dim == 2)
+            hipLaunchKernelGGL((k_residual_vec<2, CoefArrays<double>>), gr, blk, 0, st, x, b, co, L0.d,
+                               inv_h2, m->kr, pa, pb);
+        else
+            hipLaunchKernelGGL((k_residual_vec<3, CoefArrays<double>>), gr, blk, 0, st, x, b, co, L0.d,
+                               inv_h2, m->kr, pa, pb);
+    }
+    IB_TRY(device_sum(pa, nb, m->ks + KS_RR, st));
+    IB_TRY(device_sum(pb, nb, m->ks + KS_BB, st));
+    IB_HIP(hipMemcpyAsync(m->host, m->ks + KS_RR, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    IB_HIP(hipStreamSynchronize(st));
+    prof_drain();
+    const double bnorm = std::sqrt(m->host[1]);
+    if (!(bnorm > 0.0)) {
+        hipLaunchKernelGGL((k_fill<double>), g1, blk, 0, st, x, N, 0.0);
+        S->rel_res0 = S->rel_res = 0.0;
+        IB_HIP(hipGetLastError());
+        return bnorm == 0.0 ? IB_OK : fail(IB_ENAN, "mg_solve: right side is not finite");
+    }
+    double rel = std::sqrt(m->host[0]) / bnorm;
+    S->rel_res0 = S->rel_res = rel;
+    // z = V(r) from zero
+    auto precond = [&]() {
+        if (mixed) {
+            hipLaunchKernelGGL(k_cast_f32, g1, blk, 0, st, m->kr, L0.f32.b, N);
+            hipLaunchKernelGGL((k_fill<float>), g1, blk, 0, st, L0.f32.p, N, 0.0f);
+            vcycle<float>(m, 0, st);
+        } else {
+            L0.f64.b = m->kr;
+            L0.f64.p = m->kz;
+            hipLaunchKernelGGL((k_fill<double>), g1, blk, 0, st, m->kz, N, 0.0);
+            vcycle<double>(m, 0, st);
+        }
+    };
+    // the preconditioner points the finest level at (r, z); the mean
+    // removal works on the level's p, which must be the solution again
+    auto restore = [&]() {
+        L0.f64.p = x;
+        L0.f64.b = const_cast<double*>(b);
+    };
+    auto dots = [&](const double* q, int rz_slot) {
+        if (mixed)
+            hipLaunchKernelGGL((k_pcg_dots<float>), gr, blk, 0, st, m->kr, q, L0.f32.p, N, pa, pb);
+        else
+            hipLaunchKernelGGL((k_pcg_dots<double>), gr, blk, 0, st, m->kr, q, m->kz, N, pa, pb);
+        int rc = device_sum(pa, nb, m->ks + rz_slot, st);
+        if (rc == IB_OK && q) rc = device_sum(pb, nb, m->ks + KS_QZ, st);
+        return rc;
+    };
+    auto direction = [&](int rz_old_slot, int first) {
+        if (mixed)
+            hipLaunchKernelGGL((k_pcg_dir<float>), g1, blk, 0, st, m->kd, L0.f32.p, N, m->ks,
+                               rz_old_slot, first);
+        else
+            hipLaunchKernelGGL((k_pcg_dir<double>), g1, blk, 0, st, m->kd, m->kz, N, m->ks,
+                               rz_old_slot, first);
+    };
+    int it = 0, slot = KS_RZ0;
+    int skip = 0, last_check = 0, checks = 0;
+    double rel_check = rel;
+    while (true) {
+        if (!std::isfinite(rel)) return fail(IB_ENAN, "mg_solve: residual is not finite");
+        if (fixed > 0 ? it >= fixed : rel <= rtol) break;
+        if (fixed == 0 && it >= max_it) {
+            S->cycles = it;
+            restore();
+            IB_TRY(remove_mean(m, false, st));
+            return fail(IB_ENOTCONV, "mg_solve: no convergence within max_cycles");
+        }
+        const bool check = fixed > 0 || skip == 0 || it + 1 >= max_it;
+        precond();
+        if (it == 0) {
+            IB_TRY(dots(nullptr, slot));
+            direction(slot, 1);
+        } else {
+            const int next = slot == KS_RZ0 ? KS_RZ1 : KS_RZ0;
+            IB_TRY(dots(m->kq, next));
+            direction(slot, 0);
+            slot = next;
+        }
+        if (L0.rho)
+            hipLaunchKernelGGL((k_apply_dot<3, CoefRho>), gr, blk, 0, st, m->kd, CoefRho{L0.rho}, L0.d,
+                               inv_h2, m->kq, pa);
+        else if (dim == 2)
+            hipLaunchKernelGGL((k_apply_dot<2, CoefArrays<double>>), gr, blk, 0, st, m->kd, co, L0.d,
+                               inv_h2, m->kq, pa);
+        else
+            hipLaunchKernelGGL((k_apply_dot<3, CoefArrays<double>>), gr, blk, 0, st, m->kd, co, L0.d,
+                               inv_h2, m->kq, pa);
+        IB_TRY(device_sum(pa, nb, m->ks + KS_DQ, st));
+        hipLaunchKernelGGL(k_pcg_xr, gr, blk, 0, st, x, m->kr, m->kd, m->kq, N, m->ks, slot, pa);
+        IB_TRY(device_sum(pa, nb, m->ks + KS_RR, st));
+        ++it;
+        S->cycles = it;
+        if (!check) {
+            --skip;
+            if (it <= 128) S->res_hist[it - 1] = -1.0;
+            continue;
+        }
+        IB_HIP(hipMemcpyAsync(m->host, m->ks + KS_RR, sizeof(double), hipMemcpyDeviceToHost, st));
+        IB_HIP(hipStreamSynchronize(st));
+        prof_drain();
+        rel = std::sqrt(m->host[0]) / bnorm;
+        if (it <= 128) S->res_hist[it - 1] = rel;
+        S->rel_res = rel;
+        ++checks;
+        if (fixed == 0 && checks >= 3 && rel > rtol && rel < rel_check) {
+            double rho = std::pow(rel / rel_check, 1.0 / (double)(it - last_check));
+            if (rho < 0.9) {
+                int need = (int)std::ceil(std::log(rtol / rel) / std::log(rho));
+                skip = std::max(0, need - 2);
+            }
+        }
+        rel_check = rel;
+        last_check = it;
+    }
+    restore();
+    if (it > 0) IB_TRY(remove_mean(m, false, st));
+    IB_HIP(hipGetLastError());
+    return IB_OK;
+}
+
 extern "C" int mg_solve(mg_handle* m, const double* b, double* p, double rtol, int max_cycles,
                         int fixed_cycles, mg_stats* stats, void* stream) {
     IB_CHECK(m && b && p, IB_EINVAL, "mg_solve: null argument");
@@ -1375,6 +1648,7 @@ extern "C" int mg_solve(mg_handle* m, const double* b, double* p, double rtol, i
     mg_stats loc;
     mg_stats* S = stats ? stats : &loc;
     S->cycles = 0;
+    if (m->o.krylov) return solve_krylov(m, b, p, rtol, max_cycles, fixed_cycles, S, st);
     if (mixed) IB_TRY(mixed_defect(m, true, st));
     else IB_TRY(fp64_norms(m, true, st));
     double bnorm = std::sqrt(m->host[1]);
