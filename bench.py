@@ -40,6 +40,11 @@ HBM_PEAK_GBS = 8000.0
 SWEEP_BYTES_F64 = 48.0
 SWEEP_BYTES_F64_RHO = 32.0
 SWEEP_BYTES_F32 = 24.0
+# HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc runs
+# (FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000, the factors an elementwise copy of
+# known size reads), recorded with the kernel they were taken on; any other
+# kernel reports null
+TRAFFIC = {"k_rbgs_fused_rho<64,8,512>": (637.9e6, "profiles/rbgs_fused_rho_256cube_hbm_counters.txt")}
 
 
 def log(msg):
@@ -362,23 +367,25 @@ def main():
     if r64["prof"]["sweep64_rho"][0]:
         nl, ms = r64["prof"]["sweep64_rho"]
         bytes_per_launch = SWEEP_BYTES_F64_RHO * N
-        kname = "k_rbgs_fused_rho (finest level, one full red-black sweep, coefficients from rho)"
+        kname = "k_rbgs_fused_rho<64,8,512>"
     elif r64["prof"]["sweep64"][0]:
         nl, ms = r64["prof"]["sweep64"]
         bytes_per_launch = SWEEP_BYTES_F64 * N
-        kname = "k_rbgs_fused<double> (finest level, one full red-black sweep)"
+        kname = "k_rbgs_fused<double>"
     else:
         nl, ms = r64["prof"]["smooth64"]
         bytes_per_launch = 0.5 * SWEEP_BYTES_F64 * N
-        kname = "k_rbgs<double,3> (finest level, one colour)"
+        kname = "k_rbgs<double,3>"
     avg_s = ms / 1e3 / max(nl, 1)
     achieved = bytes_per_launch / avg_s / 1e9
     prof_summary = {k: dict(launches=v[0], avg_us=round(1e3 * v[1] / v[0], 2))
                     for k, v in r64["prof"].items() if v[0]}
+    traffic, source = TRAFFIC.get(kname, (None, None))
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                kernel=kname,
-                bytes_per_launch=bytes_per_launch, avg_launch_us=round(avg_s * 1e6, 2))
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                kernel=kname + " (finest-level single-pass red-black sweep)",
+                bytes_per_launch=bytes_per_launch, avg_launch_us=round(avg_s * 1e6, 2),
+                traffic_source=source)
     line = dict(metric=METRIC, value=round(sps64, 3), unit="steps/s", n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=round(1e3 * r64["seconds"] / r64["steps"], 3),
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
