@@ -7,7 +7,7 @@ of the previous pressure; multigrid then starts from
     p0 = p_prev + s_p * y,
 and remains the judge of the final answer.
 
-Definition (2D):
+Definition (2D; the 3D network is the same with 3x3x3 taps):
   * inputs, normalised per sample: x0 = b h^2 / s_b, x1 = (1/rho) / max(1/rho),
     x2 = p_prev / s_p, with s_b, s_p the root-mean-square values of b h^2 and
     p_prev (1 when zero);
@@ -23,9 +23,12 @@ Definition (2D):
   * optimiser: Adam (beta1 0.9, beta2 0.999, eps 1e-8) on float32 master
     weights.
 
-Arrays: activations (C, H, W) with W = x fastest; weights (Cout, Cin, 3, 3)
-where tap (ky, kx) multiplies the input at (y + ky - 1, x + kx - 1).
+Arrays: activations (C, H, W) or (C, D, H, W) with x fastest; weights
+(Cout, Cin, 3, 3) or (Cout, Cin, 3, 3, 3) where tap (kz,) ky, kx multiplies the
+input at ((z + kz - 1,) y + ky - 1, x + kx - 1).
 """
+import itertools
+
 import numpy as np
 
 CHANNELS = (3, 32, 32, 32, 32, 32, 1)
@@ -39,46 +42,59 @@ def bf16(x):
     return r.view(np.float32).astype(np.float64)
 
 
-def init_params(seed=0):
-    """He-normal weights (float32 master copy), zero biases."""
+def taps(dim):
+    """Tap index tuples (t_0, ..., t_{dim-1}) in {0, 1, 2}^dim, last axis fastest;
+    tap t multiplies the input at offset t - 1 along each axis."""
+    return list(itertools.product(range(3), repeat=dim))
+
+
+def init_params(seed=0, dim=2):
+    """He-normal weights (float32 master copy), zero biases; W has shape
+    (Cout, Cin, 3[, 3], 3)."""
     rng = np.random.default_rng(seed)
     params = []
     for l in range(6):
         ci, co = CHANNELS[l], CHANNELS[l + 1]
-        std = np.sqrt(2.0 / (ci * 9)) if l < 5 else 0.1 * np.sqrt(1.0 / (ci * 9))
-        W = (rng.standard_normal((co, ci, 3, 3)) * std).astype(np.float32).astype(np.float64)
+        fan = ci * 3 ** dim
+        std = np.sqrt(2.0 / fan) if l < 5 else 0.1 * np.sqrt(1.0 / fan)
+        W = (rng.standard_normal((co, ci) + (3,) * dim) * std).astype(np.float32).astype(np.float64)
         params.append([W, np.zeros(co)])
     return params
 
 
+def _shift(x, t, sign):
+    """x moved so that out[..., i] = x[..., i + sign (t - 1)] (periodic) on the spatial axes."""
+    for a, ta in enumerate(t):
+        x = np.roll(x, -sign * (ta - 1), axis=x.ndim - len(t) + a)
+    return x
+
+
 def conv(x, W, b):
-    """out[o, y, x] = b[o] + sum_{i, ky, kx} W[o, i, ky, kx] x[i, y+ky-1, x+kx-1] (periodic)."""
-    C, H, Wd = x.shape
-    out = np.zeros((W.shape[0], H, Wd))
-    for ky in range(3):
-        for kx in range(3):
-            xs = np.roll(np.roll(x, -(ky - 1), axis=1), -(kx - 1), axis=2)
-            out += np.einsum("oi,ihw->ohw", W[:, :, ky, kx], xs)
-    return out + b[:, None, None]
+    """out[o, i] = b[o] + sum_{c, t} W[o, c, t] x[c, i + t - 1] (periodic), i a 2D or 3D index."""
+    dim = x.ndim - 1
+    out = np.zeros((W.shape[0],) + x.shape[1:])
+    for t in taps(dim):
+        out += np.einsum("oc,c...->o...", W[(slice(None), slice(None)) + t], _shift(x, t, 1))
+    return out + b.reshape((-1,) + (1,) * dim)
 
 
 def conv_grad_input(g, W):
     """Adjoint of conv in x."""
+    dim = g.ndim - 1
     out = np.zeros((W.shape[1],) + g.shape[1:])
-    for ky in range(3):
-        for kx in range(3):
-            t = np.einsum("oi,ohw->ihw", W[:, :, ky, kx], g)
-            out += np.roll(np.roll(t, ky - 1, axis=1), kx - 1, axis=2)
+    for t in taps(dim):
+        v = np.einsum("oc,o...->c...", W[(slice(None), slice(None)) + t], g)
+        out += _shift(v, t, -1)
     return out
 
 
 def conv_grad_weight(g, x):
-    dW = np.zeros((g.shape[0], x.shape[0], 3, 3))
-    for ky in range(3):
-        for kx in range(3):
-            xs = np.roll(np.roll(x, -(ky - 1), axis=1), -(kx - 1), axis=2)
-            dW[:, :, ky, kx] = np.einsum("ohw,ihw->oi", g, xs)
-    return dW, g.sum(axis=(1, 2))
+    dim = x.ndim - 1
+    dW = np.zeros((g.shape[0], x.shape[0]) + (3,) * dim)
+    axes = tuple(range(1, dim + 1))
+    for t in taps(dim):
+        dW[(slice(None), slice(None)) + t] = np.tensordot(g, _shift(x, t, 1), axes=(axes, axes))
+    return dW, g.sum(axis=axes)
 
 
 def normalise(b, inv_rho, p_prev, h):
@@ -91,7 +107,7 @@ def normalise(b, inv_rho, p_prev, h):
 
 
 def forward(params, x, use_bf16=True):
-    """Returns (y, cache) with y of shape (H, W)."""
+    """Returns (y, cache) with y of the spatial shape of x."""
     q = bf16 if use_bf16 else (lambda a: a)
     acts = [q(x)]
     for l, (W, b) in enumerate(params):

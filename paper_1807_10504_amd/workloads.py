@@ -145,16 +145,16 @@ def random_cells(n, dim: int, scale: float, seed: int):
     return scale * rng.standard_normal(tuple(reversed(n[:dim])))
 
 
-def network_init(seed: int, channels=(3, 32, 32, 32, 32, 32, 1)) -> np.ndarray:
-    """Seeded He-normal initial weights of the warm-start network, flat float32
-    in the library's parameter layout (per layer W[co][ci][ky][kx] then b[co];
-    the last layer is scaled down so that the first guesses stay near p_prev)."""
+def network_init(seed: int, dim: int = 2, channels=(3, 32, 32, 32, 32, 32, 1)) -> np.ndarray:
+    """He-normal initial weights (zero biases) of the warm-start network in the
+    ABI's flat float32 layout: per layer W[co][ci][taps] then b[co], taps 3^dim."""
     rng = np.random.default_rng(seed)
     parts = []
+    taps = 3 ** dim
     for l in range(6):
         ci, co = channels[l], channels[l + 1]
-        std = np.sqrt(2.0 / (ci * 9)) if l < 5 else 0.1 * np.sqrt(1.0 / (ci * 9))
-        parts.append((rng.standard_normal(co * ci * 9) * std).astype(np.float32))
+        std = np.sqrt(2.0 / (ci * taps)) if l < 5 else 0.1 * np.sqrt(1.0 / (ci * taps))
+        parts.append((rng.standard_normal(co * ci * taps) * std).astype(np.float32))
         parts.append(np.zeros(co, dtype=np.float32))
     return np.concatenate(parts)
 
