@@ -234,7 +234,7 @@ typedef struct {
     double* X_host;          /* 2D: host n_markers*2, in: markers at step n, out: advanced
                                 by dt U and relocated on the least-squares B-spline.
                                 3D: NULL. */
-    ib_nn* nn;               /* WS_NN: the network (2D), else NULL */
+    ib_nn* nn;               /* WS_NN: the network (of the grid's dimension), else NULL */
 } ib_state;
 
 typedef struct {
@@ -322,16 +322,17 @@ void ib_profile_reset(void);
 int  ib_profile_read(int kind, long long* launches, double* total_ms);
 
 /* ---------------------------------------------------------------------------
- * a10 -- learned warm start (project addition, 2D). A 6-layer 3x3
- * convolutional network (circular padding, channels 3 -> 32 x5 -> 1, ReLU
- * between) in bfloat16 on the matrix cores with float32 accumulation maps
- * x = (b h^2 / s_b, (1/rho) / max(1/rho), p_prev / s_p) (s = RMS) to y, and the
- * guess is p0 = p_prev + s_p y; trained with Adam on the mean squared error to
- * t = (p - p_prev) / s_p, p being the multigrid solution. n[0] must be a
- * multiple of 64. Parameters cross the ABI as host float32, per layer
- * W[co][ci][ky][kx] (unpadded channel counts) then b[co]; count from
- * ib_nn_param_count(). The network starts with all parameters zero. */
-int  ib_nn_param_count(void);
+ * a10 -- learned warm start (project addition). A 6-layer convolutional
+ * network with 3x3 (2D) or 3x3x3 (3D) taps (circular padding, channels
+ * 3 -> 32 x5 -> 1, ReLU between) in bfloat16 on the matrix cores with float32
+ * accumulation maps x = (b h^2 / s_b, (1/rho) / max(1/rho), p_prev / s_p)
+ * (s = RMS) to y, and the guess is p0 = p_prev + s_p y; trained with Adam on
+ * the mean squared error to t = (p - p_prev) / s_p, p being the multigrid
+ * solution. n[0] must be a multiple of 64. Parameters cross the ABI as host
+ * float32, per layer W[co][ci][(kz)][ky][kx] (unpadded channel counts) then
+ * b[co]; count from ib_nn_param_count(dim) (0 for another dim). The network
+ * starts with all parameters zero. */
+int  ib_nn_param_count(int dim);
 int  ib_nn_create(const ib_grid* g, ib_nn** out);
 void ib_nn_destroy(ib_nn* nn);
 int  ib_nn_set_params(ib_nn* nn, const float* params, int count);

@@ -300,7 +300,7 @@ extern "C" int project_step(ib_ctx* c, mg_handle* m, const ib_params* prm, ib_st
     out->guess_accepted = 0;
     out->guess_rel_res = out->prev_rel_res = 0.0;
     if (prm->warm_start == WS_NN) {
-        IB_CHECK(stt->nn && dim == 2, IB_EINVAL, "project_step: WS_NN needs a 2D network");
+        IB_CHECK(stt->nn, IB_EINVAL, "project_step: WS_NN needs a network");
         IB_CHECK(stt->p_prev != out->p, IB_EINVAL, "project_step: WS_NN needs p_prev distinct from p");
         IB_TRY(ib_nn_predict(stt->nn, c->b, H, stt->p_prev, prm->rho_in, prm->rho_out, out->p, st));
         IB_TRY(mg_residual_norm(m, c->b, out->p, &out->guess_rel_res, st));

@@ -1,25 +1,27 @@
 // Learned warm start for the pressure solve (project addition; the paper
-// uses multigrid alone). A 6-layer 3x3 convolutional network (circular
-// padding, channels 3 -> 32 x 5 -> 1, ReLU between) maps the normalised
-// right side, inverse density and previous pressure to a pressure
-// correction; multigrid starts from p0 = p_prev + s_p * y and stays the judge.
+// uses multigrid alone). A 6-layer convolutional network with 3x3 (2D) or
+// 3x3x3 (3D) taps (circular padding, channels 3 -> 32 x 5 -> 1, ReLU between)
+// maps the normalised right side, inverse density and previous pressure to a
+// pressure correction; multigrid starts from p0 = p_prev + s_p * y and stays
+// the judge.
 //
 // Precision: bfloat16 weights, activations and gradients in memory, float32
 // accumulation on the matrix cores (v_mfma_f32_16x16x32_bf16), float32
 // master weights and Adam moments, float64 at the solver boundary.
 //
-// Layout: activations NHWC with 32 channels (the 3 input channels and the 1
-// output channel are zero-padded to 32), bfloat16 stored as 16-bit patterns.
-// Weights per layer: Wl[co][tap][ci] (tap = 3 ky + kx multiplies the input at
-// (y + ky - 1, x + kx - 1)) and the flipped transpose Wt[ci][8 - tap][co]
-// used by the input gradient, which is then the same convolution kernel.
+// Layout: activations NDHWC / NHWC with 32 channels (the 3 input channels and
+// the 1 output channel are zero-padded to 32), bfloat16 stored as 16-bit
+// patterns. Weights per layer: Wl[co][tap][ci] (tap = 9 kz + 3 ky + kx
+// multiplies the input at (z + kz - 1, y + ky - 1, x + kx - 1); 2D: tap =
+// 3 ky + kx) and the flipped transpose Wt[ci][taps - 1 - tap][co] used by the
+// input gradient, which is then the same convolution kernel.
 //
 // A convolution is an implicit GEMM: a wave owns 16 pixels of one row and
 // all 32 output channels; for each tap it multiplies a 16 x 32 (pixel x
 // channel) slab of the shifted input by the 32 x 16 weight block of each half
 // of the output channels (two MFMA per tap). The weight gradient is a GEMM
-// over pixels: a workgroup stages 64 pixels of the gradient and the three
-// input rows they touch in LDS and accumulates 36 (tap, co-block, ci-block)
+// over pixels: a workgroup stages 64 pixels of the gradient and the input
+// rows they touch in LDS and accumulates the (tap, co-block, ci-block)
 // 16 x 16 tiles; per-workgroup partials are summed in a fixed order.
 #include <cmath>
 #include <vector>
@@ -33,10 +35,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16;
 
 constexpr int kC = 32;          // padded channel count
-constexpr int kTaps = 9;
-constexpr int kWSize = kC * kTaps * kC;  // weights per layer
-constexpr int kPSize = kWSize + kC;      // + bias
 constexpr int kLayers = 6;
+// taps per convolution: 3^dim; weights per layer kC x taps x kC, + bias
+__host__ __device__ constexpr int wsize(int taps) { return kC * taps * kC; }
+__host__ __device__ constexpr int psize(int taps) { return wsize(taps) + kC; }
 constexpr int kGradBlocks = 256;
 static const int kChan[7] = {3, 32, 32, 32, 32, 32, 1};
 
@@ -118,24 +120,29 @@ __global__ void k_nn_input(const double* __restrict__ b, const double* __restric
 // convolution on the matrix cores
 // MODE 0: + bias, ReLU, bfloat16 out; MODE 1: + bias, float32 out of channel 0;
 // MODE 2: bfloat16 out times (act > 0) (input gradient through the ReLU below)
-template <int MODE>
+template <int MODE, int DIM>
 __global__ __launch_bounds__(kBlock) void k_nn_conv(const u16* __restrict__ X, const u16* __restrict__ Wl,
                                                     const float* __restrict__ bias,
                                                     const u16* __restrict__ act, u16* __restrict__ Y,
-                                                    float* __restrict__ Yf, int H, int W) {
+                                                    float* __restrict__ Yf, int D, int H, int W) {
+    constexpr int TAPS = DIM == 3 ? 27 : 9;
     __shared__ u16 tile[4][16][kC];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int y = blockIdx.y;
+    const int y = blockIdx.y, z = blockIdx.z;
     const int x0 = blockIdx.x * 64 + wave * 16;
     const int m = lane & 15, kg = lane >> 4;
+    // first pixel of this wave's 16 (row y of plane z)
+    const long row0 = ((long)z * H + y) * W + x0;
     f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int tap = 0; tap < kTaps; ++tap) {
-        const int ky = tap / 3, kx = tap - 3 * ky;
-        const int yy = wrap(y + ky - 1, H), xx = wrap(x0 + m + kx - 1, W);
-        bf16x8 a = *reinterpret_cast<const bf16x8*>(X + ((long)yy * W + xx) * kC + kg * 8);
-        bf16x8 b0 = *reinterpret_cast<const bf16x8*>(Wl + ((m)*kTaps + tap) * kC + kg * 8);
-        bf16x8 b1 = *reinterpret_cast<const bf16x8*>(Wl + ((16 + m) * kTaps + tap) * kC + kg * 8);
+    for (int tap = 0; tap < TAPS; ++tap) {
+        // tap = 9 kz + 3 ky + kx (kz = 1 in 2D): offsets k - 1 along each axis
+        const int kz = DIM == 3 ? tap / 9 : 1, ky = (tap % 9) / 3, kx = tap % 3;
+        const int zz = DIM == 3 ? wrap_near(z + kz - 1, D) : 0;
+        const int yy = wrap_near(y + ky - 1, H), xx = wrap_near(x0 + m + kx - 1, W);
+        bf16x8 a = *reinterpret_cast<const bf16x8*>(X + (((long)zz * H + yy) * W + xx) * kC + kg * 8);
+        bf16x8 b0 = *reinterpret_cast<const bf16x8*>(Wl + ((m)*TAPS + tap) * kC + kg * 8);
+        bf16x8 b1 = *reinterpret_cast<const bf16x8*>(Wl + ((16 + m) * TAPS + tap) * kC + kg * 8);
         acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, acc1, 0, 0, 0);
     }
@@ -143,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_conv(const u16* __restrict__ X, c
     if (MODE == 1) {
         if (m == 0) {
             float b0v = bias[0];
-            for (int i = 0; i < 4; ++i) Yf[(long)y * W + x0 + 4 * kg + i] = acc0[i] + b0v;
+            for (int i = 0; i < 4; ++i) Yf[row0 + 4 * kg + i] = acc0[i] + b0v;
         }
         return;
     }
@@ -156,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_conv(const u16* __restrict__ X, c
             tile[wave][px][m] = f2bf(v0);
             tile[wave][px][16 + m] = f2bf(v1);
         } else {
-            const u16* ar = act + ((long)y * W + x0 + px) * kC;
+            const u16* ar = act + (row0 + px) * kC;
             u16 h0 = f2bf(v0), h1 = f2bf(v1);
             tile[wave][px][m] = bf2f(ar[m]) > 0.f ? h0 : (u16)0;
             tile[wave][px][16 + m] = bf2f(ar[16 + m]) > 0.f ? h1 : (u16)0;
@@ -166,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_conv(const u16* __restrict__ X, c
     // lane l stores 8 channels of pixel l / 4
     const int px = lane >> 2, ch = (lane & 3) * 8;
     uint4 v = *reinterpret_cast<const uint4*>(&tile[wave][px][ch]);
-    *reinterpret_cast<uint4*>(Y + ((long)y * W + x0 + px) * kC + ch) = v;
+    *reinterpret_cast<uint4*>(Y + (row0 + px) * kC + ch) = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -191,32 +198,41 @@ __global__ void k_nn_loss(const float* __restrict__ y, const double* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// weight gradient: dW[co][tap][ci] = sum_p G[p][co] X[p + off(tap)][ci], db[co] = sum_p G[p][co]
-__global__ __launch_bounds__(kBlock) void k_nn_wgrad(const u16* __restrict__ G, const u16* __restrict__ X,
-                                                     int H, int W, float* __restrict__ part) {
+// weight gradient: dW[co][tap][ci] = sum_p G[p][co] X[p + off(tap)][ci], db[co] = sum_p G[p][co].
+// A workgroup stages 64 gradient pixels of one row and the 3 (2D) or 9 (3D)
+// input rows of 66 pixels they touch; its 4 (2D) or 12 (3D) waves own 9 of
+// the 4 x taps (tap, co-block, ci-block) 16 x 16 tiles each.
+template <int DIM>
+__global__ __launch_bounds__(DIM == 3 ? 768 : 256) void k_nn_wgrad(const u16* __restrict__ G,
+                                                                   const u16* __restrict__ X, int D,
+                                                                   int H, int W, float* __restrict__ part) {
+    constexpr int TAPS = DIM == 3 ? 27 : 9, ROWS = DIM == 3 ? 9 : 3;
+    constexpr int NT = DIM == 3 ? 768 : 256, NWV = NT / 64;
     __shared__ u16 g_s[64][kC];
-    __shared__ u16 x_s[3][66][kC];
+    __shared__ u16 x_s[ROWS][66][kC];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = lane & 15, kg = lane >> 4;
     const int segs_per_row = W / 64;
-    const long nseg = (long)H * segs_per_row;
+    const long nseg = (long)D * H * segs_per_row;
     f32x4 acc[9];
     for (int q = 0; q < 9; ++q) acc[q] = {0.f, 0.f, 0.f, 0.f};
     float dbias = 0.f;
     for (long sgi = blockIdx.x; sgi < nseg; sgi += gridDim.x) {
-        const int y = (int)(sgi / segs_per_row), xs = (int)(sgi % segs_per_row) * 64;
-        // stage 64 gradient pixels and the 3 x 66 input pixels they touch
-        for (int q = threadIdx.x; q < 64 * 4; q += kBlock) {
+        const long row = sgi / segs_per_row;
+        const int y = (int)(row % H), z = (int)(row / H), xs = (int)(sgi % segs_per_row) * 64;
+        // stage 64 gradient pixels and the ROWS x 66 input pixels they touch
+        for (int q = threadIdx.x; q < 64 * 4; q += NT) {
             int px = q >> 2, part8 = (q & 3) * 8;
             *reinterpret_cast<uint4*>(&g_s[px][part8]) =
-                *reinterpret_cast<const uint4*>(G + ((long)y * W + xs + px) * kC + part8);
+                *reinterpret_cast<const uint4*>(G + ((row * W) + xs + px) * kC + part8);
         }
-        for (int q = threadIdx.x; q < 3 * 66 * 4; q += kBlock) {
+        for (int q = threadIdx.x; q < ROWS * 66 * 4; q += NT) {
             int r = q / (66 * 4), rem = q % (66 * 4);
             int px = rem >> 2, part8 = (rem & 3) * 8;
-            int yy = wrap(y + r - 1, H), xx = wrap(xs + px - 1, W);
+            int zz = DIM == 3 ? wrap_near(z + r / 3 - 1, D) : 0;
+            int yy = wrap_near(y + r % 3 - 1, H), xx = wrap_near(xs + px - 1, W);
             *reinterpret_cast<uint4*>(&x_s[r][px][part8]) =
-                *reinterpret_cast<const uint4*>(X + ((long)yy * W + xx) * kC + part8);
+                *reinterpret_cast<const uint4*>(X + (((long)zz * H + yy) * W + xx) * kC + part8);
         }
         __syncthreads();
         if (threadIdx.x < kC) {
@@ -224,17 +240,17 @@ __global__ __launch_bounds__(kBlock) void k_nn_wgrad(const u16* __restrict__ G, 
             for (int px = 0; px < 64; ++px) s += bf2f(g_s[px][threadIdx.x]);
             dbias += s;
         }
-        // tiles t = wave + 4 j, j = 0..8: tap = t / 4, co block = (t / 2) & 1, ci block = t & 1
+        // tiles t = wave + NWV j, j = 0..8: tap = t / 4, co block = (t / 2) & 1, ci block = t & 1
         for (int j = 0; j < 9; ++j) {
-            const int t = wave + 4 * j;
+            const int t = wave + NWV * j;
             const int tap = t >> 2, cb = (t >> 1) & 1, nb = t & 1;
-            const int ky = tap / 3, kx = tap - 3 * ky;
+            const int r = tap / 3, kx = tap % 3;  // input row (3 kz + ky) and x offset
             for (int kk = 0; kk < 2; ++kk) {
                 bf16x8 a, b;
                 const int p0 = kk * 32 + kg * 8;
                 for (int e = 0; e < 8; ++e) {
                     u16 ga = g_s[p0 + e][cb * 16 + m];
-                    u16 xb = x_s[ky][p0 + e + kx][nb * 16 + m];
+                    u16 xb = x_s[r][p0 + e + kx][nb * 16 + m];
                     a[e] = __builtin_bit_cast(__bf16, ga);
                     b[e] = __builtin_bit_cast(__bf16, xb);
                 }
@@ -243,24 +259,24 @@ __global__ __launch_bounds__(kBlock) void k_nn_wgrad(const u16* __restrict__ G, 
         }
         __syncthreads();
     }
-    float* out = part + (long)blockIdx.x * kPSize;
+    float* out = part + (long)blockIdx.x * psize(TAPS);
     for (int j = 0; j < 9; ++j) {
-        const int t = wave + 4 * j;
+        const int t = wave + NWV * j;
         const int tap = t >> 2, cb = (t >> 1) & 1, nb = t & 1;
         for (int i = 0; i < 4; ++i) {
             int co = cb * 16 + 4 * kg + i, ci = nb * 16 + m;
-            out[(co * kTaps + tap) * kC + ci] = acc[j][i];
+            out[(co * TAPS + tap) * kC + ci] = acc[j][i];
         }
     }
-    if (threadIdx.x < kC) out[kWSize + threadIdx.x] = dbias;
+    if (threadIdx.x < kC) out[wsize(TAPS) + threadIdx.x] = dbias;
 }
 
 // grad[q] += sum over blocks of part[b][q], in block order
-__global__ void k_nn_grad_reduce(const float* __restrict__ part, int nb, float* __restrict__ grad) {
+__global__ void k_nn_grad_reduce(const float* __restrict__ part, int nb, int psz, float* __restrict__ grad) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= kPSize) return;
+    if (q >= psz) return;
     float s = 0.f;
-    for (int b = 0; b < nb; ++b) s += part[(long)b * kPSize + q];
+    for (int b = 0; b < nb; ++b) s += part[(long)b * psz + q];
     grad[q] += s;
 }
 
@@ -268,9 +284,10 @@ __global__ void k_nn_grad_reduce(const float* __restrict__ part, int nb, float* 
 // copies (Wl and the flipped transpose Wt) and the float32 bias
 __global__ void k_nn_adam(float* __restrict__ master, float* __restrict__ mom, float* __restrict__ vel,
                           float* __restrict__ grad, float scale, float lr, float c1, float c2,
-                          u16* __restrict__ Wl, u16* __restrict__ Wt, float* __restrict__ bias) {
+                          u16* __restrict__ Wl, u16* __restrict__ Wt, float* __restrict__ bias,
+                          int taps) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= kPSize) return;
+    if (q >= psize(taps)) return;
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     float g = grad[q] * scale;
     float mq = b1 * mom[q] + (1.f - b1) * g;
@@ -281,29 +298,29 @@ __global__ void k_nn_adam(float* __restrict__ master, float* __restrict__ mom, f
     float w = master[q] - lr * mh / (sqrtf(vh) + eps);
     master[q] = w;
     grad[q] = 0.f;
-    if (q < kWSize) {
-        int co = q / (kTaps * kC), rem = q % (kTaps * kC), tap = rem / kC, ci = rem % kC;
+    if (q < wsize(taps)) {
+        int co = q / (taps * kC), rem = q % (taps * kC), tap = rem / kC, ci = rem % kC;
         u16 h = f2bf(w);
         Wl[q] = h;
-        Wt[(ci * kTaps + (kTaps - 1 - tap)) * kC + co] = h;
+        Wt[(ci * taps + (taps - 1 - tap)) * kC + co] = h;
     } else {
-        bias[q - kWSize] = w;
+        bias[q - wsize(taps)] = w;
     }
 }
 
 // refresh the bfloat16 copies from the master parameters
 __global__ void k_nn_publish(const float* __restrict__ master, u16* __restrict__ Wl,
-                             u16* __restrict__ Wt, float* __restrict__ bias) {
+                             u16* __restrict__ Wt, float* __restrict__ bias, int taps) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= kPSize) return;
+    if (q >= psize(taps)) return;
     float w = master[q];
-    if (q < kWSize) {
-        int co = q / (kTaps * kC), rem = q % (kTaps * kC), tap = rem / kC, ci = rem % kC;
+    if (q < wsize(taps)) {
+        int co = q / (taps * kC), rem = q % (taps * kC), tap = rem / kC, ci = rem % kC;
         u16 h = f2bf(w);
         Wl[q] = h;
-        Wt[(ci * kTaps + (kTaps - 1 - tap)) * kC + co] = h;
+        Wt[(ci * taps + (taps - 1 - tap)) * kC + co] = h;
     } else {
-        bias[q - kWSize] = w;
+        bias[q - wsize(taps)] = w;
     }
 }
 
@@ -320,20 +337,21 @@ __global__ void k_nn_guess(const float* __restrict__ y, const double* __restrict
 using namespace ib;
 
 struct ib_nn {
-    int H = 0, W = 0;
+    int dim = 2, taps = 9;
+    int D = 1, H = 0, W = 0;
     double h = 0.0;
     long N = 0;
     u16* act[kLayers] = {};   // layer inputs (act[0] = normalised input)
     float* yf = nullptr;      // network output
     u16* g[2] = {};           // gradient ping-pong
-    u16* Wl = nullptr;        // kLayers * kWSize
+    u16* Wl = nullptr;        // kLayers * wsize(taps)
     u16* Wt = nullptr;
     float* bias = nullptr;    // kLayers * kC
-    float* master = nullptr;  // kLayers * kPSize
+    float* master = nullptr;  // kLayers * psize(taps)
     float* mom = nullptr;
     float* vel = nullptr;
     float* grad = nullptr;
-    float* part = nullptr;    // kGradBlocks * kPSize
+    float* part = nullptr;    // kGradBlocks * psize(taps)
     double* red = nullptr;    // reductions
     double* scale = nullptr;  // s_b, s_p, s_r
     double* host = nullptr;   // pinned
@@ -348,16 +366,29 @@ static int nn_forward(ib_nn* n, const double* b, const double* H, const double* 
     hipLaunchKernelGGL(k_nn_scales, dim3(1), dim3(kBlock), 0, st, n->red, nb, n->N, n->scale);
     hipLaunchKernelGGL(k_nn_input, dim3(grid_for(n->N)), dim3(kBlock), 0, st, b, H, pp, n->N, h2, rin,
                        rout, n->scale, n->act[0]);
-    dim3 grid(n->W / 64, n->H);
+    dim3 grid(n->W / 64, n->H, n->D);
+    const long ws = wsize(n->taps);
     for (int l = 0; l < kLayers; ++l) {
-        const u16* Wl = n->Wl + (long)l * kWSize;
+        const u16* Wl = n->Wl + (long)l * ws;
         const float* bias = n->bias + l * kC;
-        if (l < kLayers - 1)
-            hipLaunchKernelGGL(k_nn_conv<0>, grid, dim3(kBlock), 0, st, n->act[l], Wl, bias, nullptr,
-                               n->act[l + 1], nullptr, n->H, n->W);
-        else
-            hipLaunchKernelGGL(k_nn_conv<1>, grid, dim3(kBlock), 0, st, n->act[l], Wl, bias, nullptr,
-                               nullptr, n->yf, n->H, n->W);
+        const bool last = l == kLayers - 1;
+        u16* Y = last ? nullptr : n->act[l + 1];
+        float* Yf = last ? n->yf : nullptr;
+        if (n->dim == 3) {
+            if (last)
+                hipLaunchKernelGGL((k_nn_conv<1, 3>), grid, dim3(kBlock), 0, st, n->act[l], Wl, bias,
+                                   nullptr, Y, Yf, n->D, n->H, n->W);
+            else
+                hipLaunchKernelGGL((k_nn_conv<0, 3>), grid, dim3(kBlock), 0, st, n->act[l], Wl, bias,
+                                   nullptr, Y, Yf, n->D, n->H, n->W);
+        } else {
+            if (last)
+                hipLaunchKernelGGL((k_nn_conv<1, 2>), grid, dim3(kBlock), 0, st, n->act[l], Wl, bias,
+                                   nullptr, Y, Yf, n->D, n->H, n->W);
+            else
+                hipLaunchKernelGGL((k_nn_conv<0, 2>), grid, dim3(kBlock), 0, st, n->act[l], Wl, bias,
+                                   nullptr, Y, Yf, n->D, n->H, n->W);
+        }
     }
     IB_HIP(hipGetLastError());
     return IB_OK;
@@ -372,18 +403,30 @@ static int nn_backward(ib_nn* n, const double* b, const double* H, const double*
     hipLaunchKernelGGL(k_nn_loss, dim3(nb), dim3(kBlock), 0, st, n->yf, p, pp, n->scale, n->N, n->g[0],
                        n->red);
     IB_TRY(device_sum(n->red, nb, n->red + 4 * 1024, st));
-    dim3 grid(n->W / 64, n->H);
+    dim3 grid(n->W / 64, n->H, n->D);
+    const int ps = psize(n->taps);
+    const long ws = wsize(n->taps);
     int cur = 0;
     for (int l = kLayers - 1; l >= 0; --l) {
         // n->g[cur] holds layer l's pre-activation gradient (bfloat16)
-        hipLaunchKernelGGL(k_nn_wgrad, dim3(kGradBlocks), dim3(kBlock), 0, st, n->g[cur], n->act[l], n->H,
-                           n->W, n->part);
-        hipLaunchKernelGGL(k_nn_grad_reduce, dim3(grid_for(kPSize)), dim3(kBlock), 0, st, n->part,
-                           kGradBlocks, n->grad + (long)l * kPSize);
-        if (l > 0)
-            hipLaunchKernelGGL(k_nn_conv<2>, grid, dim3(kBlock), 0, st, n->g[cur],
-                               n->Wt + (long)l * kWSize, nullptr, n->act[l], n->g[1 - cur], nullptr,
-                               n->H, n->W);
+        if (n->dim == 3)
+            hipLaunchKernelGGL((k_nn_wgrad<3>), dim3(kGradBlocks), dim3(768), 0, st, n->g[cur], n->act[l],
+                               n->D, n->H, n->W, n->part);
+        else
+            hipLaunchKernelGGL((k_nn_wgrad<2>), dim3(kGradBlocks), dim3(256), 0, st, n->g[cur], n->act[l],
+                               n->D, n->H, n->W, n->part);
+        hipLaunchKernelGGL(k_nn_grad_reduce, dim3(grid_for(ps)), dim3(kBlock), 0, st, n->part,
+                           kGradBlocks, ps, n->grad + (long)l * ps);
+        if (l > 0) {
+            if (n->dim == 3)
+                hipLaunchKernelGGL((k_nn_conv<2, 3>), grid, dim3(kBlock), 0, st, n->g[cur],
+                                   n->Wt + (long)l * ws, nullptr, n->act[l], n->g[1 - cur], nullptr,
+                                   n->D, n->H, n->W);
+            else
+                hipLaunchKernelGGL((k_nn_conv<2, 2>), grid, dim3(kBlock), 0, st, n->g[cur],
+                                   n->Wt + (long)l * ws, nullptr, n->act[l], n->g[1 - cur], nullptr,
+                                   n->D, n->H, n->W);
+        }
         cur = 1 - cur;
     }
     IB_HIP(hipGetLastError());
@@ -404,22 +447,27 @@ static void nn_free(ib_nn* n) {
     delete n;
 }
 
-extern "C" int ib_nn_param_count(void) {
+extern "C" int ib_nn_param_count(int dim) {
+    if (dim != 2 && dim != 3) return 0;
+    const int taps = dim == 3 ? 27 : 9;
     int t = 0;
-    for (int l = 0; l < kLayers; ++l) t += kChan[l + 1] * kChan[l] * 9 + kChan[l + 1];
+    for (int l = 0; l < kLayers; ++l) t += kChan[l + 1] * kChan[l] * taps + kChan[l + 1];
     return t;
 }
 
 extern "C" int ib_nn_create(const ib_grid* g, ib_nn** out) {
     IB_CHECK(g && out, IB_EINVAL, "ib_nn_create: null argument");
-    IB_CHECK(g->dim == 2, IB_EINVAL, "ib_nn_create: the network is two-dimensional");
-    IB_CHECK(g->n[0] % 64 == 0 && g->n[0] >= 64 && g->n[1] >= 1, IB_EINVAL,
-             "ib_nn_create: n[0] must be a multiple of 64");
+    IB_CHECK(g->dim == 2 || g->dim == 3, IB_EINVAL, "ib_nn_create: dim must be 2 or 3");
+    IB_CHECK(g->n[0] % 64 == 0 && g->n[0] >= 64 && g->n[1] >= 1 && (g->dim == 2 || g->n[2] >= 1),
+             IB_EINVAL, "ib_nn_create: n[0] must be a multiple of 64");
     ib_nn* n = new ib_nn();
+    n->dim = g->dim;
+    n->taps = g->dim == 3 ? 27 : 9;
     n->W = g->n[0];
     n->H = g->n[1];
+    n->D = g->dim == 3 ? g->n[2] : 1;
     n->h = g->h;
-    n->N = (long)n->W * n->H;
+    n->N = (long)n->W * n->H * n->D;
     bool ok = true;
     auto alloc = [&](void** p, size_t bytes) {
         if (ok && hipMalloc(p, bytes) != hipSuccess) ok = false;
@@ -428,14 +476,15 @@ extern "C" int ib_nn_create(const ib_grid* g, ib_nn** out) {
     alloc((void**)&n->yf, n->N * sizeof(float));
     alloc((void**)&n->g[0], n->N * kC * sizeof(u16));
     alloc((void**)&n->g[1], n->N * kC * sizeof(u16));
-    alloc((void**)&n->Wl, kLayers * kWSize * sizeof(u16));
-    alloc((void**)&n->Wt, kLayers * kWSize * sizeof(u16));
+    const size_t WS = wsize(n->taps), PS = psize(n->taps);
+    alloc((void**)&n->Wl, kLayers * WS * sizeof(u16));
+    alloc((void**)&n->Wt, kLayers * WS * sizeof(u16));
     alloc((void**)&n->bias, kLayers * kC * sizeof(float));
-    alloc((void**)&n->master, kLayers * kPSize * sizeof(float));
-    alloc((void**)&n->mom, kLayers * kPSize * sizeof(float));
-    alloc((void**)&n->vel, kLayers * kPSize * sizeof(float));
-    alloc((void**)&n->grad, kLayers * kPSize * sizeof(float));
-    alloc((void**)&n->part, (size_t)kGradBlocks * kPSize * sizeof(float));
+    alloc((void**)&n->master, kLayers * PS * sizeof(float));
+    alloc((void**)&n->mom, kLayers * PS * sizeof(float));
+    alloc((void**)&n->vel, kLayers * PS * sizeof(float));
+    alloc((void**)&n->grad, kLayers * PS * sizeof(float));
+    alloc((void**)&n->part, (size_t)kGradBlocks * PS * sizeof(float));
     alloc((void**)&n->red, 8 * 1024 * sizeof(double));
     alloc((void**)&n->scale, 4 * sizeof(double));
     if (ok && hipHostMalloc((void**)&n->host, 8 * sizeof(double)) != hipSuccess) ok = false;
@@ -443,11 +492,11 @@ extern "C" int ib_nn_create(const ib_grid* g, ib_nn** out) {
         nn_free(n);
         return fail(IB_ENOMEM, "ib_nn_create: out of memory");
     }
-    size_t pb = kLayers * kPSize * sizeof(float);
+    size_t pb = kLayers * PS * sizeof(float);
     if (hipMemset(n->master, 0, pb) != hipSuccess || hipMemset(n->mom, 0, pb) != hipSuccess ||
         hipMemset(n->vel, 0, pb) != hipSuccess || hipMemset(n->grad, 0, pb) != hipSuccess ||
-        hipMemset(n->Wl, 0, kLayers * kWSize * sizeof(u16)) != hipSuccess ||
-        hipMemset(n->Wt, 0, kLayers * kWSize * sizeof(u16)) != hipSuccess ||
+        hipMemset(n->Wl, 0, kLayers * WS * sizeof(u16)) != hipSuccess ||
+        hipMemset(n->Wt, 0, kLayers * WS * sizeof(u16)) != hipSuccess ||
         hipMemset(n->bias, 0, kLayers * kC * sizeof(float)) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         nn_free(n);
@@ -459,52 +508,54 @@ extern "C" int ib_nn_create(const ib_grid* g, ib_nn** out) {
 
 extern "C" void ib_nn_destroy(ib_nn* n) { nn_free(n); }
 
-// params: host float32, per layer W[co][ci][ky][kx] (unpadded channel counts) then b[co]
+// params: host float32, per layer W[co][ci][(kz)][ky][kx] (unpadded channel counts) then b[co]
 extern "C" int ib_nn_set_params(ib_nn* n, const float* params, int count) {
     IB_CHECK(n && params, IB_EINVAL, "ib_nn_set_params: null argument");
-    IB_CHECK(count == ib_nn_param_count(), IB_EINVAL, "ib_nn_set_params: wrong parameter count");
-    std::vector<float> pad((size_t)kLayers * kPSize, 0.f);
+    IB_CHECK(count == ib_nn_param_count(n->dim), IB_EINVAL, "ib_nn_set_params: wrong parameter count");
+    const int taps = n->taps, PS = psize(taps), WS = wsize(taps);
+    std::vector<float> pad((size_t)kLayers * PS, 0.f);
     const float* src = params;
     for (int l = 0; l < kLayers; ++l) {
         int ci_n = kChan[l], co_n = kChan[l + 1];
-        float* dst = pad.data() + (size_t)l * kPSize;
+        float* dst = pad.data() + (size_t)l * PS;
         for (int co = 0; co < co_n; ++co)
             for (int ci = 0; ci < ci_n; ++ci)
-                for (int tap = 0; tap < kTaps; ++tap) dst[(co * kTaps + tap) * kC + ci] = *src++;
-        for (int co = 0; co < co_n; ++co) dst[kWSize + co] = *src++;
+                for (int tap = 0; tap < taps; ++tap) dst[(co * taps + tap) * kC + ci] = *src++;
+        for (int co = 0; co < co_n; ++co) dst[WS + co] = *src++;
     }
     IB_HIP(hipMemcpy(n->master, pad.data(), pad.size() * sizeof(float), hipMemcpyHostToDevice));
     for (int l = 0; l < kLayers; ++l)
-        hipLaunchKernelGGL(k_nn_publish, dim3(grid_for(kPSize)), dim3(kBlock), 0, 0,
-                           n->master + (long)l * kPSize, n->Wl + (long)l * kWSize,
-                           n->Wt + (long)l * kWSize, n->bias + l * kC);
-    IB_HIP(hipMemset(n->mom, 0, kLayers * kPSize * sizeof(float)));
-    IB_HIP(hipMemset(n->vel, 0, kLayers * kPSize * sizeof(float)));
+        hipLaunchKernelGGL(k_nn_publish, dim3(grid_for(PS)), dim3(kBlock), 0, 0,
+                           n->master + (long)l * PS, n->Wl + (long)l * WS, n->Wt + (long)l * WS,
+                           n->bias + l * kC, taps);
+    IB_HIP(hipMemset(n->mom, 0, kLayers * PS * sizeof(float)));
+    IB_HIP(hipMemset(n->vel, 0, kLayers * PS * sizeof(float)));
     IB_HIP(hipDeviceSynchronize());
     n->step = 0;
     return IB_OK;
 }
 
-static int unpad(const std::vector<float>& pad, float* params) {
+static int unpad(const std::vector<float>& pad, int taps, float* params) {
+    const int PS = psize(taps), WS = wsize(taps);
     float* dst = params;
     for (int l = 0; l < kLayers; ++l) {
         int ci_n = kChan[l], co_n = kChan[l + 1];
-        const float* src = pad.data() + (size_t)l * kPSize;
+        const float* src = pad.data() + (size_t)l * PS;
         for (int co = 0; co < co_n; ++co)
             for (int ci = 0; ci < ci_n; ++ci)
-                for (int tap = 0; tap < kTaps; ++tap) *dst++ = src[(co * kTaps + tap) * kC + ci];
-        for (int co = 0; co < co_n; ++co) *dst++ = src[kWSize + co];
+                for (int tap = 0; tap < taps; ++tap) *dst++ = src[(co * taps + tap) * kC + ci];
+        for (int co = 0; co < co_n; ++co) *dst++ = src[WS + co];
     }
     return IB_OK;
 }
 
 extern "C" int ib_nn_get_params(ib_nn* n, float* params, int count) {
     IB_CHECK(n && params, IB_EINVAL, "ib_nn_get_params: null argument");
-    IB_CHECK(count == ib_nn_param_count(), IB_EINVAL, "ib_nn_get_params: wrong parameter count");
-    std::vector<float> pad((size_t)kLayers * kPSize);
+    IB_CHECK(count == ib_nn_param_count(n->dim), IB_EINVAL, "ib_nn_get_params: wrong parameter count");
+    std::vector<float> pad((size_t)kLayers * psize(n->taps));
     IB_HIP(hipDeviceSynchronize());
     IB_HIP(hipMemcpy(pad.data(), n->master, pad.size() * sizeof(float), hipMemcpyDeviceToHost));
-    return unpad(pad, params);
+    return unpad(pad, n->taps, params);
 }
 
 extern "C" int ib_nn_predict(ib_nn* n, const double* b, const double* H, const double* p_prev,
@@ -522,17 +573,18 @@ extern "C" int ib_nn_gradients(ib_nn* n, const double* b, const double* H, const
                                const double* p, double rho_in, double rho_out, float* grads_host,
                                int count, double* loss, void* stream) {
     IB_CHECK(n && b && H && p && loss, IB_EINVAL, "ib_nn_gradients: null argument");
-    IB_CHECK(!grads_host || count == ib_nn_param_count(), IB_EINVAL, "ib_nn_gradients: count");
+    IB_CHECK(!grads_host || count == ib_nn_param_count(n->dim), IB_EINVAL, "ib_nn_gradients: count");
     hipStream_t st = (hipStream_t)stream;
-    IB_HIP(hipMemsetAsync(n->grad, 0, kLayers * kPSize * sizeof(float), st));
+    const size_t pbytes = (size_t)kLayers * psize(n->taps) * sizeof(float);
+    IB_HIP(hipMemsetAsync(n->grad, 0, pbytes, st));
     IB_TRY(nn_backward(n, b, H, p_prev, p, rho_in, rho_out, loss, st));
     if (grads_host) {
-        std::vector<float> pad((size_t)kLayers * kPSize);
-        IB_HIP(hipMemcpyAsync(pad.data(), n->grad, pad.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+        std::vector<float> pad((size_t)kLayers * psize(n->taps));
+        IB_HIP(hipMemcpyAsync(pad.data(), n->grad, pbytes, hipMemcpyDeviceToHost, st));
         IB_HIP(hipStreamSynchronize(st));
-        unpad(pad, grads_host);
+        unpad(pad, n->taps, grads_host);
     }
-    IB_HIP(hipMemsetAsync(n->grad, 0, kLayers * kPSize * sizeof(float), st));
+    IB_HIP(hipMemsetAsync(n->grad, 0, pbytes, st));
     return IB_OK;
 }
 
@@ -549,12 +601,12 @@ extern "C" int ib_nn_train_step(ib_nn* n, int count, const double* const* b, con
     }
     n->step += 1;
     float c1 = 1.f - powf(0.9f, (float)n->step), c2 = 1.f - powf(0.999f, (float)n->step);
+    const int PS = psize(n->taps), WS = wsize(n->taps);
     for (int l = 0; l < kLayers; ++l)
-        hipLaunchKernelGGL(k_nn_adam, dim3(grid_for(kPSize)), dim3(kBlock), 0, st,
-                           n->master + (long)l * kPSize, n->mom + (long)l * kPSize,
-                           n->vel + (long)l * kPSize, n->grad + (long)l * kPSize, 1.f / (float)count,
-                           lr, c1, c2, n->Wl + (long)l * kWSize, n->Wt + (long)l * kWSize,
-                           n->bias + l * kC);
+        hipLaunchKernelGGL(k_nn_adam, dim3(grid_for(PS)), dim3(kBlock), 0, st, n->master + (long)l * PS,
+                           n->mom + (long)l * PS, n->vel + (long)l * PS, n->grad + (long)l * PS,
+                           1.f / (float)count, lr, c1, c2, n->Wl + (long)l * WS, n->Wt + (long)l * WS,
+                           n->bias + l * kC, n->taps);
     IB_HIP(hipGetLastError());
     *loss = tot / count;
     return IB_OK;

@@ -120,7 +120,7 @@ def load(path: str = LIB_PATH):
         "mg_solve": (i32, [vp, vp, vp, f64, i32, i32, P(MgStats), vp]),
         "mg_destroy": (None, [vp]),
         "mg_residual_norm": (i32, [vp, vp, vp, P(f64), vp]),
-        "ib_nn_param_count": (i32, []),
+        "ib_nn_param_count": (i32, [i32]),
         "ib_nn_create": (i32, [P(Grid), P(vp)]),
         "ib_nn_destroy": (None, [vp]),
         "ib_nn_set_params": (i32, [vp, vp, i32]),
@@ -421,14 +421,16 @@ class Multigrid:
 
 # ----------------------------------------------------------------------------
 class Network:
-    """The learned warm start (2D): bfloat16 convolutional network on the matrix cores."""
+    """The learned warm start: bfloat16 convolutional network on the matrix cores
+    (2D with n = (nx, ny), 3D with n = (nx, ny, nz))."""
 
     def __init__(self, n, h):
         self.lib = load()
-        self.grid = make_grid(2, n, h)
+        self.dim = len(n)
+        self.grid = make_grid(self.dim, n, h)
         self.ptr = C.c_void_p()
         _check(self.lib.ib_nn_create(C.byref(self.grid), C.byref(self.ptr)))
-        self.count = self.lib.ib_nn_param_count()
+        self.count = self.lib.ib_nn_param_count(self.dim)
 
     def close(self):
         if self.ptr:
@@ -487,12 +489,12 @@ def flatten_params(params):
     return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in params]).astype(np.float32)
 
 
-def unflatten_params(flat, channels=(3, 32, 32, 32, 32, 32, 1)):
+def unflatten_params(flat, channels=(3, 32, 32, 32, 32, 32, 1), dim=2):
     out, o = [], 0
     for l in range(6):
         ci, co = channels[l], channels[l + 1]
-        nW = co * ci * 9
-        W = flat[o:o + nW].reshape(co, ci, 3, 3).astype(np.float64)
+        nW = co * ci * 3 ** dim
+        W = flat[o:o + nW].reshape((co, ci) + (3,) * dim).astype(np.float64)
         o += nW
         b = flat[o:o + co].astype(np.float64)
         o += co

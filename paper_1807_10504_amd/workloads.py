@@ -130,6 +130,23 @@ def sphere_mesh(level: int, R: float, centre=(0.5, 0.5, 0.5), seed: int | None =
     return np.ascontiguousarray(V), np.ascontiguousarray(T)
 
 
+def perturbed_sphere_mesh(level: int, R: float, amp: float, seed: int, centre=(0.5, 0.5, 0.5)):
+    """Icosphere of mean radius R whose vertex radii carry a seeded smooth
+    perturbation: r(v) = R (1 + amp * sum_k c_k P(v . a_k)), a_k three seeded
+    unit axes, c_k ~ U(-1, 1), P(s) = (3 s^2 - 1) / 2 (an axisymmetric l = 2
+    mode about each axis); with amp = 0 it is the sphere of sphere_mesh(seed)."""
+    rng = np.random.default_rng(seed)
+    V, T = icosphere(level)
+    V = V @ seeded_rotation(seed).T
+    axes = rng.standard_normal((3, 3))
+    axes /= np.linalg.norm(axes, axis=1, keepdims=True)
+    c = rng.uniform(-1.0, 1.0, size=3)
+    s = V @ axes.T
+    r = R * (1.0 + amp * ((3.0 * s * s - 1.0) * 0.5) @ c)
+    V = np.asarray(centre, dtype=np.float64) + r[:, None] * V
+    return np.ascontiguousarray(V), np.ascontiguousarray(T)
+
+
 # ----------------------------------------------------------------------------
 # Fields
 # ----------------------------------------------------------------------------
