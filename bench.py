@@ -51,7 +51,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_variant(ib, torch, wl, geo, precision, steps, warmup, profile, warm=False, krylov=0):
+def run_variant(ib, torch, wl, geo, precision, steps, warmup, profile, warm=False, krylov=0, nn=None):
     n, h = wl.n, wl.h
     shape = tuple(reversed(n))
     V, T = wl.X, wl.tris
@@ -64,6 +64,9 @@ def run_variant(ib, torch, wl, geo, precision, steps, warmup, profile, warm=Fals
     mg = ib.Multigrid(3, n, h, precision=precision, krylov=krylov)
     params = dict(rho_in=wl.rho_in, rho_out=wl.rho_out, sigma=wl.sigma, dt=wl.dt, rtol=1e-10,
                   max_cycles=100, warm_start=ib.WS_PREV if warm else ib.WS_ZERO)
+    if nn is not None:
+        # cold start from the network's guess (from b and 1/rho alone)
+        params["warm_start"] = ib.WS_NN
     u = [torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(3)]
     bufs = [dict(p=torch.empty(shape, dtype=torch.float64, device="cuda"),
                  u=[torch.empty(shape, dtype=torch.float64, device="cuda") for _ in range(3)],
@@ -74,11 +77,16 @@ def run_variant(ib, torch, wl, geo, precision, steps, warmup, profile, warm=Fals
     res = []
     first = None
 
+    accepted = []
+
     def one(k):
         nonlocal u, p_prev
         out = bufs[k % 2]
-        out = ctx.project_step(mg, params, u, p_prev=p_prev, surf=surf, out=out)
+        out = ctx.project_step(mg, params, u, p_prev=None if nn is not None else p_prev, surf=surf,
+                               out=out, nn=nn)
         u, p_prev = out["u"], out["p"]
+        if nn is not None:
+            accepted.append(out["guess"]["accepted"])
         return out["stats"]
 
     for k in range(warmup):
@@ -106,7 +114,78 @@ def run_variant(ib, torch, wl, geo, precision, steps, warmup, profile, warm=Fals
     ctx.close()
     mg.close()
     return dict(seconds=t1 - t0, steps=steps, cycles=cycles, rel_res=res, first=first, prof=prof,
-                dP=d["dP"], tke=d["tke"])
+                dP=d["dP"], tke=d["tke"], accepted=accepted)
+
+
+def bench_3d_nn(ib, torch, wl, geo, steps, warmup, sps64, pairs=24, train_iters=60):
+    """Learned warm start at the full 3D size: the 3D network is trained on cold FP64
+    solutions of perturbed spheres (random radius 0.2-0.3, l = 2 modes of amplitude
+    0.15; not the benchmark sphere) and then gives the cold-start guess of the
+    benchmark step, judged by flexible CG in FP64 and mixed precision."""
+    from paper_1807_10504_amd import workloads as W
+    n, h = wl.n, wl.h
+    shape = tuple(reversed(n))
+    V0, T0 = wl.X, wl.tris
+    ctx = ib.Context(3, n, h, max_markers=len(V0), max_elems=len(T0))
+    mg = ib.Multigrid(3, n, h, krylov=1)
+    prm = dict(rho_in=wl.rho_in, rho_out=wl.rho_out, sigma=wl.sigma, dt=wl.dt, rtol=1e-10,
+               warm_start=ib.WS_ZERO)
+    t0 = time.perf_counter()
+    samples = []
+    for s in range(pairs):
+        seed = 1000 + s
+        R = 0.2 + 0.1 * np.random.default_rng(seed).uniform()
+        V, T = W.perturbed_sphere_mesh(6, R, 0.15, seed)
+        fs, ds, nrm = ib.surface_geometry_3d(V, T, wl.sigma)
+        keep = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (V, T.astype(np.int32), nrm, fs, ds)]
+        surf = ib.make_surface(keep[0], elems=keep[1], nrm=keep[2], fs=keep[3], ds=keep[4])
+        u0 = [torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+        o = dict(b=torch.empty(shape, dtype=torch.float64, device="cuda"),
+                 H=torch.empty(shape, dtype=torch.float64, device="cuda"))
+        o = ctx.project_step(mg, prm, u0, surf=surf, out=o)
+        samples.append((o["b"], o["H"], None, o["p"].clone()))
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    ctx.close()
+    mg.close()
+    net = ib.Network(n, h)
+    net.set_params(W.network_init(1, dim=3))
+    rng = np.random.default_rng(3)
+    losses = []
+    t0 = time.perf_counter()
+    for it in range(train_iters):
+        idx = rng.choice(pairs, size=4, replace=False)
+        losses.append(net.train_step([samples[i] for i in idx], wl.rho_in, wl.rho_out, 2e-3))
+        if (it + 1) % max(1, train_iters // 4) == 0:
+            log(f"  training {it + 1}/{train_iters}: loss {losses[-1]:.3e}")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    b, H = samples[0][0], samples[0][1]
+    g = net.predict(b, H, None, wl.rho_in, wl.rho_out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        net.predict(b, H, None, wl.rho_in, wl.rho_out, p0=g)
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t0) / 5
+    del samples, b, H, g
+    out = dict(workload=f"{pairs} perturbed spheres at {n[0]}^3 (level-6 meshes, R 0.2-0.3, l=2 modes of "
+                        f"amplitude 0.15) -> training pairs from cold FP64 solves; judged on the benchmark "
+                        f"sphere (not in the training set)",
+               pairs_s=round(t_pairs, 2), train_iters=train_iters, train_s=round(t_train, 2),
+               loss_first=float(np.mean(losses[:5])), loss_last=float(np.mean(losses[-10:])),
+               inference_ms=round(1e3 * t_inf, 3))
+    for name, prec in (("fp64", ib.MG_FP64), ("mixed", ib.MG_MIXED)):
+        log(f"== {name} flexible CG from the 3D network's guess, cold every step")
+        r = run_variant(ib, torch, wl, geo, prec, steps, warmup, profile=False, krylov=1, nn=net)
+        sps = r["steps"] / r["seconds"]
+        out[f"{name}_cold_fcg_nn"] = dict(
+            steps_per_s=round(sps, 3), ms_per_step=round(1e3 * r["seconds"] / r["steps"], 3),
+            mean_cycles=float(np.mean(r["cycles"])), max_rel_res=float(np.max(r["rel_res"])),
+            guess_accepted=float(np.mean(r["accepted"])) if r["accepted"] else 0.0,
+            speedup_vs_fp64_cold=round(sps / sps64, 3))
+    net.close()
+    return out
 
 
 def bench_2d_c2(ib, torch, steps=200):
@@ -298,6 +377,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D workloads (C2, learned warm start)")
+    ap.add_argument("--no-nn3d", action="store_true", help="skip the 3D learned warm start")
+    ap.add_argument("--nn3d-iters", type=int, default=60, help="training iterations of the 3D network")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MB (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -398,6 +479,10 @@ def main():
                                         "V(2,2) multigrid cycles"),
                             grid=list(wl.n), markers=len(wl.X), triangles=len(wl.tris)),
                 variants=variants, roofline=roof, kernels_fp64=prof_summary)
+    if not args.no_nn3d:
+        log(f"== 3D learned warm start at {args.size}^3")
+        line["nn_3d"] = bench_3d_nn(ib, torch, wl, geo, args.steps, args.warmup, sps64,
+                                    train_iters=args.nn3d_iters)
     if not args.no_2d:
         log("== 2D 512^2 jittered drop: FP64 vs mixed, 200 steps")
         line["c2_2d"] = bench_2d_c2(ib, torch)

@@ -222,8 +222,9 @@ typedef struct {
     int fixed_cycles;        /* > 0: exactly this many cycles (parity runs) */
     int spread_mode;         /* IB_SPREAD_IRROT or IB_SPREAD_DELTA */
     int warm_start;          /* WS_ZERO, WS_PREV (p_prev as initial guess) or WS_NN
-                                (network guess from (b, 1/rho, p_prev), used only when
-                                its residual is below that of p_prev; else p_prev) */
+                                (network guess from (b, 1/rho, p_prev), used when it is
+                                finite and its residual is at most 100 times that of
+                                p_prev (of 0 when p_prev is NULL); else p_prev or 0) */
 } ib_params;
 
 typedef struct {
