@@ -75,6 +75,7 @@ struct mg_handle {
     double* kr = nullptr;
     double* kz = nullptr;
     double* kd = nullptr;
+    double* kd2 = nullptr;  // second direction buffer of the fused density-path update
     double* kq = nullptr;
     double* ks = nullptr;
 };
@@ -1048,6 +1049,146 @@ __global__ void k_pcg_dir(double* __restrict__ dv, const TZ* __restrict__ z, lon
     dv[c] = (double)z[c] + beta * dv[c];
 }
 
+// One flexible-CG direction update fused with the product and its inner
+// product, on a finest level given by densities (3D): dnew = z + beta d
+// (dnew = z on the first iteration), q = A dnew, partial sums of dnew q per
+// workgroup. d and dnew are distinct buffers: neighbouring workgroups read the
+// old direction in their halos while this one writes the new one. Same
+// z-march as the sweep: a workgroup owns a CG_TX x CG_TY tile and a z-range,
+// stages the new d and rho of each plane on the tile plus a one-cell ring in
+// LDS (three-plane rings), and loads the planes two steps ahead. The
+// arithmetic of each q is that of apply_row_rho, operand for operand.
+constexpr int CG_TX = 64, CG_TY = 8, CG_NT = 512;
+constexpr int CG_RX = CG_TX + 2, CG_RY = CG_TY + 2, CG_RN = CG_RX * CG_RY;
+constexpr int CG_NL = (CG_RN + CG_NT - 1) / CG_NT;
+
+template <typename TZ>
+__global__ __launch_bounds__(CG_NT) void k_cg_dir_apply_rho(const TZ* __restrict__ z,
+                                                            const double* __restrict__ d,
+                                                            double* __restrict__ dnew,
+                                                            const double* __restrict__ rho,
+                                                            double* __restrict__ q, Dims dm,
+                                                            double inv_h2, const double* __restrict__ ks,
+                                                            int rz_old_slot, int first, int TZr,
+                                                            int ntx, int nty, int nzc,
+                                                            double* __restrict__ partial) {
+    __shared__ double DN[3][CG_RN];
+    __shared__ double RR[3][CG_RN];
+    __shared__ double red[CG_NT / 64];
+    const int nw = ntx * nty * nzc;
+    const int bid = blockIdx.x;
+    const int w = (nw % 8 == 0) ? (bid % 8) * (nw / 8) + bid / 8 : bid;
+    const int tx = w % ntx;
+    const int r0 = w / ntx;
+    const int ty = r0 % nty;
+    const int zc = r0 / nty;
+    const int i0 = tx * CG_TX - 1, j0 = ty * CG_TY - 1;
+    const int z0 = zc * TZr, z1 = z0 + TZr;
+    const long plane = (long)dm.nx * dm.ny;
+    const int t = threadIdx.x;
+    // beta of the direction update from the device scalars
+    double beta = 0.0;
+    if (!first) {
+        const double rz = ks[rz_old_slot];
+        const double alpha = rz / ks[KS_DQ];
+        beta = -alpha * ks[KS_QZ] / rz;
+    }
+    auto gofs = [&](int x, int y) {
+        return (long)wrap_near(j0 + y, dm.ny) * dm.nx + wrap_near(i0 + x, dm.nx);
+    };
+    long gp[CG_NL];
+    bool vp[CG_NL];
+#pragma unroll
+    for (int s = 0; s < CG_NL; ++s) {
+        int qq = t + s * CG_NT;
+        vp[s] = qq < CG_RN;
+        gp[s] = vp[s] ? gofs(qq % CG_RX, qq / CG_RX) : gofs(0, 0);
+    }
+    auto pl = [&](int k) { return (long)wrap_near(k, dm.nz) * plane; };
+    struct Stage {
+        double dn[CG_NL], r[CG_NL];
+    };
+    Stage SA, SB;
+    // planes are loaded as the new direction d + ... and rho
+    auto fetch = [&](Stage& S, int k) {
+        const long b = pl(k);
+#pragma unroll
+        for (int s = 0; s < CG_NL; ++s) {
+            const double zv = (double)z[b + gp[s]];
+            S.dn[s] = first ? zv : zv + beta * d[b + gp[s]];
+            S.r[s] = rho[b + gp[s]];
+        }
+    };
+    auto commit = [&](const Stage& S, int k) {
+#pragma unroll
+        for (int s = 0; s < CG_NL; ++s)
+            if (s * CG_NT + CG_NT <= CG_RN || vp[s]) {
+                DN[(k + 3) % 3][t + s * CG_NT] = S.dn[s];
+                RR[(k + 3) % 3][t + s * CG_NT] = S.r[s];
+            }
+    };
+    // planes z0 - 1 and z0 staged before the march; the march step k computes
+    // plane k and stages plane k + 1
+    {
+        Stage S0;
+        fetch(S0, z0 - 1);
+        commit(S0, z0 - 1);
+        fetch(S0, z0);
+        commit(S0, z0);
+    }
+    fetch(SA, z0 + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(SB, z0 + 2);
+    const int lx = t % CG_TX, ly = t / CG_TX;  // one cell of the tile per thread
+    const int c = (ly + 1) * CG_RX + lx + 1;
+    double acc = 0.0;
+    auto step = [&](Stage& S, int k) {
+        commit(S, k + 1);
+        fetch(S, k + 3 <= z1 ? k + 3 : z1);
+        lds_barrier();
+        const double* Dc = DN[(k + 3) % 3];
+        const double* Rc = RR[(k + 3) % 3];
+        const double pc = Dc[c], rc = Rc[c];
+        const double rxp = Rc[c + 1], rxm = Rc[c - 1], ryp = Rc[c + CG_RX], rym = Rc[c - CG_RX];
+        const double rzp = RR[(k + 4) % 3][c], rzm = RR[(k + 2) % 3][c];
+        double bxp, bxm, byp, bym, bzp, bzm;
+        if (rxp == rc && rxm == rc && ryp == rc && rym == rc && rzp == rc && rzm == rc) {
+            bxp = bxm = byp = bym = bzp = bzm = 1.0 / rc;
+        } else {
+            bxp = 2.0 / (rxp + rc);
+            bxm = 2.0 / (rc + rxm);
+            byp = 2.0 / (ryp + rc);
+            bym = 2.0 / (rc + rym);
+            bzp = 2.0 / (rzp + rc);
+            bzm = 2.0 / (rc + rzm);
+        }
+        double sv = bxp * (Dc[c + 1] - pc) - bxm * (pc - Dc[c - 1]);
+        sv += byp * (Dc[c + CG_RX] - pc) - bym * (pc - Dc[c - CG_RX]);
+        sv += bzp * (DN[(k + 4) % 3][c] - pc) - bzm * (pc - DN[(k + 2) % 3][c]);
+        const double qv = sv * inv_h2;
+        const long o = pl(k) + (long)(j0 + 1 + ly) * dm.nx + (i0 + 1 + lx);
+        dnew[o] = pc;
+        q[o] = qv;
+        acc += pc * qv;
+        // the next commit overwrites plane k - 1's slot
+        lds_barrier();
+    };
+    // steps z0 .. z1 - 1 in pairs; TZr is even
+    for (int k = z0; k < z1; k += 2) {
+        step(SA, k);
+        step(SB, k + 1);
+    }
+    // fixed-order workgroup sum
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((t & 63) == 0) red[t >> 6] = acc;
+    __syncthreads();
+    if (t == 0) {
+        double sacc = 0.0;
+        for (int i = 0; i < CG_NT / 64; ++i) sacc += red[i];
+        partial[bid] = sacc;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // tile of the density sweep: 64 x 8 cells, 512 threads (2 workgroups per CU)
@@ -1353,6 +1494,7 @@ extern "C" int mg_setup(const ib_grid* g, const mg_opts* o, mg_handle** out) {
         const long N = m->lv[0].d.cells();
         if (hipMalloc(&m->kr, N * sizeof(double)) != hipSuccess ||
             hipMalloc(&m->kd, N * sizeof(double)) != hipSuccess ||
+            hipMalloc(&m->kd2, N * sizeof(double)) != hipSuccess ||
             hipMalloc(&m->kq, N * sizeof(double)) != hipSuccess ||
             (!mixed && hipMalloc(&m->kz, N * sizeof(double)) != hipSuccess) ||
             hipMalloc(&m->ks, 16 * sizeof(double)) != hipSuccess)
@@ -1380,6 +1522,7 @@ extern "C" void mg_destroy(mg_handle* m) {
     hipFree(m->kr);
     hipFree(m->kz);
     hipFree(m->kd);
+    hipFree(m->kd2);
     hipFree(m->kq);
     hipFree(m->ks);
     hipFree(m->cmat);
@@ -1569,6 +1712,13 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
             hipLaunchKernelGGL((k_pcg_dir<double>), g1, blk, 0, st, m->kd, m->kz, N, m->ks,
                                rz_old_slot, first);
     };
+    // the fused tiled update on the density path (64 x 8 tiles, the sweep's z-range)
+    const bool fused = L0.rho != nullptr && L0.d.nx % CG_TX == 0 && L0.d.ny % CG_TY == 0 &&
+                       L0.rtz > 0 && L0.rtz % 2 == 0;
+    const int cg_tx = L0.d.nx / CG_TX, cg_ty = L0.d.ny / CG_TY;
+    const int cg_tz = fused ? L0.d.nz / L0.rtz : 0;
+    const int cg_wgs = cg_tx * cg_ty * cg_tz;
+    IB_CHECK(!fused || cg_wgs <= kRed, IB_EINVAL, "mg_solve: too many workgroups for the partial sums");
     int it = 0, slot = KS_RZ0;
     int skip = 0, last_check = 0, checks = 0;
     double rel_check = rel;
@@ -1583,25 +1733,39 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
         }
         const bool check = fixed > 0 || skip == 0 || it + 1 >= max_it;
         precond();
+        const int rz_old = slot;
         if (it == 0) {
             IB_TRY(dots(nullptr, slot));
-            direction(slot, 1);
         } else {
             const int next = slot == KS_RZ0 ? KS_RZ1 : KS_RZ0;
             IB_TRY(dots(m->kq, next));
-            direction(slot, 0);
             slot = next;
         }
-        if (L0.rho)
-            hipLaunchKernelGGL((k_apply_dot<3, CoefRho>), gr, blk, 0, st, m->kd, CoefRho{L0.rho}, L0.d,
-                               inv_h2, m->kq, pa);
-        else if (dim == 2)
-            hipLaunchKernelGGL((k_apply_dot<2, CoefArrays<double>>), gr, blk, 0, st, m->kd, co, L0.d,
-                               inv_h2, m->kq, pa);
-        else
-            hipLaunchKernelGGL((k_apply_dot<3, CoefArrays<double>>), gr, blk, 0, st, m->kd, co, L0.d,
-                               inv_h2, m->kq, pa);
-        IB_TRY(device_sum(pa, nb, m->ks + KS_DQ, st));
+        if (fused) {
+            // d = z + beta d, q = A d and (d, q) in one tiled pass
+            if (mixed)
+                hipLaunchKernelGGL((k_cg_dir_apply_rho<float>), dim3(cg_wgs), dim3(CG_NT), 0, st,
+                                   L0.f32.p, m->kd, m->kd2, L0.rho, m->kq, L0.d, inv_h2, m->ks, rz_old,
+                                   it == 0 ? 1 : 0, L0.rtz, cg_tx, cg_ty, cg_tz, pa);
+            else
+                hipLaunchKernelGGL((k_cg_dir_apply_rho<double>), dim3(cg_wgs), dim3(CG_NT), 0, st,
+                                   m->kz, m->kd, m->kd2, L0.rho, m->kq, L0.d, inv_h2, m->ks, rz_old,
+                                   it == 0 ? 1 : 0, L0.rtz, cg_tx, cg_ty, cg_tz, pa);
+            std::swap(m->kd, m->kd2);
+            IB_TRY(device_sum(pa, cg_wgs, m->ks + KS_DQ, st));
+        } else {
+            direction(rz_old, it == 0 ? 1 : 0);
+            if (L0.rho)
+                hipLaunchKernelGGL((k_apply_dot<3, CoefRho>), gr, blk, 0, st, m->kd, CoefRho{L0.rho},
+                                   L0.d, inv_h2, m->kq, pa);
+            else if (dim == 2)
+                hipLaunchKernelGGL((k_apply_dot<2, CoefArrays<double>>), gr, blk, 0, st, m->kd, co, L0.d,
+                                   inv_h2, m->kq, pa);
+            else
+                hipLaunchKernelGGL((k_apply_dot<3, CoefArrays<double>>), gr, blk, 0, st, m->kd, co, L0.d,
+                                   inv_h2, m->kq, pa);
+            IB_TRY(device_sum(pa, nb, m->ks + KS_DQ, st));
+        }
         hipLaunchKernelGGL(k_pcg_xr, gr, blk, 0, st, x, m->kr, m->kd, m->kq, N, m->ks, slot, pa);
         IB_TRY(device_sum(pa, nb, m->ks + KS_RR, st));
         ++it;
