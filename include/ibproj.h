@@ -171,6 +171,9 @@ typedef struct {
     int nu1, nu2;    /* smoothing sweeps before / after the coarse correction (2, 2) */
     int n_coarsest;  /* cells per axis on the coarsest grid (4); n[d] = n_coarsest * 2^L */
     int krylov;      /* 0: V-cycles; 1: flexible CG preconditioned by one V-cycle */
+    int split_coarse; /* 0: the levels of at most 32768 cells (generic restriction) run as
+                         one persistent workgroup per cycle; 1: one launch per phase
+                         (same results bit for bit; for comparison) */
 } mg_opts;
 
 typedef struct {

@@ -78,6 +78,8 @@ struct mg_handle {
     double* kd2 = nullptr;  // second direction buffer of the fused density-path update
     double* kq = nullptr;
     double* ks = nullptr;
+    // first level run by the persistent coarse kernel (-1: none)
+    int persist = -1;
 };
 
 namespace ib {
@@ -858,6 +860,164 @@ __global__ void k_coarse_apply(const double* __restrict__ Minv, int nc, const T*
 }
 
 // ---------------------------------------------------------------------------
+// The small coarse levels in one persistent workgroup: the sub-V-cycle from
+// level `first` (at most kPersistCells cells) down to the coarsest and back,
+// with a workgroup barrier between dependent phases instead of a launch per
+// phase. Per cell it performs the arithmetic of the separate kernels
+// (k_rbgs, k_residual_restrict, k_prolong_add, k_coarse_apply) in the same
+// order, so results are bitwise those of the launch-per-phase cycle.
+constexpr int kPersistMaxLevels = 8;
+constexpr long kPersistCells = 4096;
+constexpr int kPersistThreads = 1024;
+
+template <typename T>
+struct PersistLevels {
+    int n;  // levels first .. coarsest
+    int nu1, nu2;
+    int nc;  // coarsest cells
+    const double* minv;
+    Dims d[kPersistMaxLevels];
+    T* p[kPersistMaxLevels];
+    T* b[kPersistMaxLevels];
+    const T* b0[kPersistMaxLevels];
+    const T* b1[kPersistMaxLevels];
+    const T* b2[kPersistMaxLevels];
+};
+
+template <typename T, int DIM>
+__device__ void pv_rbgs(const PersistLevels<T>& L, int l, int color) {
+    const Dims d = L.d[l];
+    T* __restrict__ p = L.p[l];
+    const T* __restrict__ b = L.b[l];
+    const T* __restrict__ b0 = L.b0[l];
+    const T* __restrict__ b1 = L.b1[l];
+    const T* __restrict__ b2 = L.b2[l];
+    const T h2 = (T)(d.h * d.h);
+    const int hx = d.nx >> 1;
+    const long half = d.cells() >> 1;
+    for (long t = threadIdx.x; t < half; t += blockDim.x) {
+        int i2 = (int)(t % hx);
+        long r = t / hx;
+        int j = (int)(r % d.ny);
+        int k = (int)(r / d.ny);
+        int i = 2 * i2 + ((j + k + color) & 1);
+        Nb n = neighbours(d, i, j, k, DIM);
+        T br = b0[n.xp], bl = b0[n.c];
+        T num = br * p[n.xp] + bl * p[n.xm];
+        T diag = br + bl;
+        br = b1[n.yp];
+        bl = b1[n.c];
+        num += br * p[n.yp] + bl * p[n.ym];
+        diag += br + bl;
+        if (DIM == 3) {
+            br = b2[n.zp];
+            bl = b2[n.c];
+            num += br * p[n.zp] + bl * p[n.zm];
+            diag += br + bl;
+        }
+        p[n.c] = (num - h2 * b[n.c]) / diag;
+    }
+}
+
+template <typename T, int DIM>
+__device__ void pv_restrict(const PersistLevels<T>& L, int l) {
+    const Dims f = L.d[l];
+    const CoefArrays<T> co{L.b0[l], L.b1[l], L.b2[l]};
+    const T inv_h2 = (T)(1.0 / (f.h * f.h));
+    const T* __restrict__ p = L.p[l];
+    const T* __restrict__ b = L.b[l];
+    T* __restrict__ bc = L.b[l + 1];
+    T* __restrict__ pc = L.p[l + 1];
+    const bool fill = l + 1 != L.n - 1;
+    int cx = f.nx >> 1, cy = f.ny >> 1, cz = DIM == 3 ? (f.nz >> 1) : 1;
+    long ncells = (long)cx * cy * cz;
+    for (long t = threadIdx.x; t < ncells; t += blockDim.x) {
+        int I = (int)(t % cx);
+        long r = t / cx;
+        int J = (int)(r % cy);
+        int K = (int)(r / cy);
+        T acc = 0;
+        for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx) {
+                    Nb n = neighbours(f, 2 * I + dx, 2 * J + dy, DIM == 3 ? 2 * K + dz : 0, DIM);
+                    acc += b[n.c] - apply_row<T, DIM>(p, co, n) * inv_h2;
+                }
+        bc[t] = acc * (DIM == 3 ? T(0.125) : T(0.25));
+        if (fill) pc[t] = (T)0;
+    }
+}
+
+template <typename T, int DIM>
+__device__ void pv_prolong(const PersistLevels<T>& L, int l) {
+    const Dims f = L.d[l];
+    T* __restrict__ p = L.p[l];
+    const T* __restrict__ e = L.p[l + 1];
+    const int cx = f.nx >> 1, cy = f.ny >> 1, cz = DIM == 3 ? (f.nz >> 1) : 1;
+    const T a = T(0.75), q = T(0.25);
+    for (long t = threadIdx.x; t < f.cells(); t += blockDim.x) {
+        const int i = (int)(t % f.nx);
+        const long r = t / f.nx;
+        const int j = (int)(r % f.ny), k = (int)(r / f.ny);
+        const int I = i >> 1, J = j >> 1, K = k >> 1;
+        const int I2 = (i & 1) ? (I + 1 == cx ? 0 : I + 1) : (I == 0 ? cx - 1 : I - 1);
+        const int J2 = (j & 1) ? (J + 1 == cy ? 0 : J + 1) : (J == 0 ? cy - 1 : J - 1);
+        T v;
+        if (DIM == 2) {
+            T r0 = a * e[J * cx + I] + q * e[J * cx + I2];
+            T r1 = a * e[J2 * cx + I] + q * e[J2 * cx + I2];
+            v = a * r0 + q * r1;
+        } else {
+            const int K2 = (k & 1) ? (K + 1 == cz ? 0 : K + 1) : (K == 0 ? cz - 1 : K - 1);
+            const int pl = cx * cy;
+            const T* e0 = e + K * pl;
+            const T* e1 = e + K2 * pl;
+            T r00 = a * e0[J * cx + I] + q * e0[J * cx + I2];
+            T r01 = a * e0[J2 * cx + I] + q * e0[J2 * cx + I2];
+            T r10 = a * e1[J * cx + I] + q * e1[J * cx + I2];
+            T r11 = a * e1[J2 * cx + I] + q * e1[J2 * cx + I2];
+            v = a * (a * r00 + q * r01) + q * (a * r10 + q * r11);
+        }
+        p[t] += v;
+    }
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kPersistThreads) void k_coarse_vcycle(PersistLevels<T> L) {
+    __shared__ double sb[kMaxCoarse];
+    const int last = L.n - 1;
+    for (int l = 0; l < last; ++l) {
+        for (int s = 0; s < L.nu1; ++s) {
+            pv_rbgs<T, DIM>(L, l, 0);
+            __syncthreads();
+            pv_rbgs<T, DIM>(L, l, 1);
+            __syncthreads();
+        }
+        pv_restrict<T, DIM>(L, l);
+        __syncthreads();
+    }
+    // coarsest: x = (-M^{-1}) b, float64 sums
+    for (int q = threadIdx.x; q < L.nc; q += blockDim.x) sb[q] = (double)L.b[last][q];
+    __syncthreads();
+    for (int r = threadIdx.x; r < L.nc; r += blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < L.nc; ++c) s += L.minv[(long)r * L.nc + c] * sb[c];
+        L.p[last][r] = (T)s;
+    }
+    __syncthreads();
+    for (int l = last - 1; l >= 0; --l) {
+        pv_prolong<T, DIM>(L, l);
+        __syncthreads();
+        for (int s = 0; s < L.nu2; ++s) {
+            pv_rbgs<T, DIM>(L, l, 0);
+            __syncthreads();
+            pv_rbgs<T, DIM>(L, l, 1);
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // norms: partial sums of r^2 (and of p) per block
 template <int DIM, class K>
 __global__ void k_resid_norm(const double* __restrict__ p, const double* __restrict__ b, K co,
@@ -1256,6 +1416,30 @@ static void vcycle(mg_handle* m, int l, hipStream_t st) {
     Level& L = m->lv[l];
     LevelT<T>& A = lvl<T>(L);
     int last = (int)m->lv.size() - 1;
+    if (l == m->persist) {
+        // this level and all below in one workgroup
+        PersistLevels<T> P;
+        P.n = last - l + 1;
+        P.nu1 = m->o.nu1;
+        P.nu2 = m->o.nu2;
+        P.nc = m->nc;
+        P.minv = m->cinv;
+        for (int i = 0; i < P.n; ++i) {
+            Level& Li = m->lv[l + i];
+            LevelT<T>& Ai = lvl<T>(Li);
+            P.d[i] = Li.d;
+            P.p[i] = Ai.p;
+            P.b[i] = Ai.b;
+            P.b0[i] = Ai.beta[0];
+            P.b1[i] = Ai.beta[1];
+            P.b2[i] = Li.d.dim == 3 ? Ai.beta[2] : Ai.beta[1];
+        }
+        if (L.d.dim == 3)
+            hipLaunchKernelGGL((k_coarse_vcycle<T, 3>), dim3(1), dim3(kPersistThreads), 0, st, P);
+        else
+            hipLaunchKernelGGL((k_coarse_vcycle<T, 2>), dim3(1), dim3(kPersistThreads), 0, st, P);
+        return;
+    }
     if (l == last) {
         hipLaunchKernelGGL((k_coarse_apply<T>), dim3(1), dim3(64), 0, st, m->cinv, m->nc, A.b, A.p);
         return;
@@ -1409,6 +1593,7 @@ extern "C" int mg_setup(const ib_grid* g, const mg_opts* o, mg_handle** out) {
     IB_CHECK(o->nu1 >= 0 && o->nu2 >= 0 && o->nu1 + o->nu2 > 0, IB_EINVAL, "mg_setup: sweeps");
     IB_CHECK(o->n_coarsest >= 2, IB_EINVAL, "mg_setup: n_coarsest");
     IB_CHECK(o->krylov == 0 || o->krylov == 1, IB_EINVAL, "mg_setup: krylov must be 0 or 1");
+    IB_CHECK(o->split_coarse == 0 || o->split_coarse == 1, IB_EINVAL, "mg_setup: split_coarse must be 0 or 1");
     IB_CHECK(g->h > 0, IB_EINVAL, "mg_setup: h");
     int nmin = g->n[0];
     for (int e = 0; e < g->dim; ++e) {
@@ -1483,6 +1668,20 @@ extern "C" int mg_setup(const ib_grid* g, const mg_opts* o, mg_handle** out) {
                     return cleanup(IB_ENOMEM, "mg_setup: out of device memory");
         }
         m->lv.push_back(lv);
+    }
+    // the persistent coarse kernel takes the first level of at most
+    // kPersistCells cells (with at least one level below it) whose
+    // restriction is the generic one (2D, or x not a multiple of 64)
+    if (!o->split_coarse) {
+        const int nl = (int)m->lv.size();
+        for (int l = 1; l < nl - 1; ++l) {
+            const Level& lv = m->lv[l];
+            if (lv.d.cells() <= kPersistCells && !lv.fused && (g->dim == 2 || lv.d.nx % 64 != 0) &&
+                nl - l <= kPersistMaxLevels) {
+                m->persist = l;
+                break;
+            }
+        }
     }
     int m1 = m->nc;
     if (hipMalloc(&m->cmat, sizeof(double) * m1 * m1) != hipSuccess ||

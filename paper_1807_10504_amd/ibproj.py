@@ -52,7 +52,7 @@ class Surface(C.Structure):
 
 class MgOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int), ("n_coarsest", C.c_int),
-                ("krylov", C.c_int)]
+                ("krylov", C.c_int), ("split_coarse", C.c_int)]
 
 
 class MgStats(C.Structure):
@@ -370,12 +370,14 @@ class Context:
 
 
 class Multigrid:
-    def __init__(self, dim, n, h, precision=MG_FP64, nu1=2, nu2=2, n_coarsest=4, krylov=0):
+    def __init__(self, dim, n, h, precision=MG_FP64, nu1=2, nu2=2, n_coarsest=4, krylov=0,
+                 split_coarse=0):
         self.lib = load()
         self.grid = make_grid(dim, n, h)
         o = MgOpts()
         o.precision, o.nu1, o.nu2, o.n_coarsest = precision, nu1, nu2, n_coarsest
         o.krylov = krylov
+        o.split_coarse = split_coarse
         self.opts = o
         self.dim = dim
         self.ptr = C.c_void_p()
