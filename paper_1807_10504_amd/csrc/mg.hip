@@ -306,7 +306,7 @@ __device__ __forceinline__ void lds_barrier() {
 
 __device__ __forceinline__ int mod3(int k) { return ((k % 3) + 3) % 3; }
 
-template <typename T>
+template <typename T, bool ZERO>
 __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin, T* __restrict__ pout,
                                                        const T* __restrict__ bb, const T* __restrict__ bx,
                                                        const T* __restrict__ by, const T* __restrict__ bz,
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
     auto fetch = [&](Stage& S, int k) {
         long bp = pl(k + 1), bk = pl(k);
 #pragma unroll
-        for (int s = 0; s < kFLoads; ++s) S.p[s] = pin[bp + gp[s]];
+        for (int s = 0; s < kFLoads; ++s) S.p[s] = ZERO ? T(0) : pin[bp + gp[s]];
 #pragma unroll
         for (int s = 0; s < kFXLoads; ++s) S.x[s] = bx[bk + gx[s]];
 #pragma unroll
@@ -403,8 +403,8 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
 #pragma unroll
         for (int s = 0; s < kFLoads; ++s)
             if (vp[s]) {
-                P[(z0 - 2) & 3][t + s * kBlock] = pin[a + gp[s]];
-                P[(z0 - 1) & 3][t + s * kBlock] = pin[a1 + gp[s]];
+                P[(z0 - 2) & 3][t + s * kBlock] = ZERO ? T(0) : pin[a + gp[s]];
+                P[(z0 - 1) & 3][t + s * kBlock] = ZERO ? T(0) : pin[a1 + gp[s]];
             }
 #pragma unroll
         for (int s = 0; s < kFZLoads; ++s)
@@ -485,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
 // written, b, rho) instead of 48 with three stored face arrays; the update is
 // the one above, operand for operand, so the results are bitwise those of
 // the stored-face sweep.
-template <int TX, int TY, int NT>
+template <int TX, int TY, int NT, bool ZERO>
 __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const double* __restrict__ pin,
                                                        double* __restrict__ pout,
                                                        const double* __restrict__ bb,
@@ -544,7 +544,7 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const double* __restrict_
         long bp = pl(k + 1), bk = pl(k);
 #pragma unroll
         for (int s = 0; s < NL; ++s) {
-            S.p[s] = pin[bp + gp[s]];
+            S.p[s] = ZERO ? 0.0 : pin[bp + gp[s]];
             S.r[s] = rho[bp + gp[s]];
         }
 #pragma unroll
@@ -566,8 +566,8 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const double* __restrict_
 #pragma unroll
         for (int s = 0; s < NL; ++s)
             if (vp[s]) {
-                P[(z0 - 2) & 3][t + s * NT] = pin[a + gp[s]];
-                P[(z0 - 1) & 3][t + s * NT] = pin[a1 + gp[s]];
+                P[(z0 - 2) & 3][t + s * NT] = ZERO ? 0.0 : pin[a + gp[s]];
+                P[(z0 - 1) & 3][t + s * NT] = ZERO ? 0.0 : pin[a1 + gp[s]];
                 R[(z0 - 2) & 3][t + s * NT] = rho[a + gp[s]];
                 R[(z0 - 1) & 3][t + s * NT] = rho[a1 + gp[s]];
             }
@@ -1372,9 +1372,12 @@ static void launch_rbgs(Level& L, int color, hipStream_t st, bool finest) {
                            A.beta[0], A.beta[1], A.beta[2], L.d, h2, color);
 }
 
+// zero: the sweep starts from p = 0 (pin is not read)
 template <typename T>
-static void launch_fused(Level& L, T* pin, T* pout, hipStream_t st, bool finest) {
-    ProfScope ps(sizeof(T) == 8 ? (L.rho ? IB_PROF_SWEEP64_RHO : IB_PROF_SWEEP64) : IB_PROF_SWEEP32,
+static void launch_fused(Level& L, T* pin, T* pout, hipStream_t st, bool finest, bool zero) {
+    // sweeps from p = 0 read less and are timed under their own kind
+    ProfScope ps(zero ? IB_PROF_SWEEP_ZERO
+                      : (sizeof(T) == 8 ? (L.rho ? IB_PROF_SWEEP64_RHO : IB_PROF_SWEEP64) : IB_PROF_SWEEP32),
                  st, finest);
     LevelT<T>& A = lvl<T>(L);
     T h2 = (T)(L.d.h * L.d.h);
@@ -1382,23 +1385,33 @@ static void launch_fused(Level& L, T* pin, T* pout, hipStream_t st, bool finest)
     if constexpr (sizeof(T) == 8) {
         if (L.rho) {
             const int rx = L.d.nx / kRTX, ry = L.d.ny / kRTY, rz = L.d.nz / L.rtz;
-            hipLaunchKernelGGL((k_rbgs_fused_rho<kRTX, kRTY, kRNT>), dim3(rx * ry * rz), dim3(kRNT), 0, st,
-                               pin, pout, A.b, L.rho, L.d, h2, L.rtz, rx, ry, rz);
+            if (zero)
+                hipLaunchKernelGGL((k_rbgs_fused_rho<kRTX, kRTY, kRNT, true>), dim3(rx * ry * rz), dim3(kRNT),
+                                   0, st, pin, pout, A.b, L.rho, L.d, h2, L.rtz, rx, ry, rz);
+            else
+                hipLaunchKernelGGL((k_rbgs_fused_rho<kRTX, kRTY, kRNT, false>), dim3(rx * ry * rz), dim3(kRNT),
+                                   0, st, pin, pout, A.b, L.rho, L.d, h2, L.rtz, rx, ry, rz);
             return;
         }
     }
-    hipLaunchKernelGGL((k_rbgs_fused<T>), dim3(ntx * nty * nzc), dim3(kBlock), 0, st, pin, pout, A.b,
-                       A.beta[0], A.beta[1], A.beta[2], L.d, h2, L.tz, ntx, nty, nzc);
+    if (zero)
+        hipLaunchKernelGGL((k_rbgs_fused<T, true>), dim3(ntx * nty * nzc), dim3(kBlock), 0, st, pin, pout,
+                           A.b, A.beta[0], A.beta[1], A.beta[2], L.d, h2, L.tz, ntx, nty, nzc);
+    else
+        hipLaunchKernelGGL((k_rbgs_fused<T, false>), dim3(ntx * nty * nzc), dim3(kBlock), 0, st, pin, pout,
+                           A.b, A.beta[0], A.beta[1], A.beta[2], L.d, h2, L.tz, ntx, nty, nzc);
 }
 
-// nu red-black sweeps on level L; returns the buffer holding the result
+// nu red-black sweeps on level L; returns the buffer holding the result.
+// zero_first: the level starts from p = 0, which a single-pass first sweep
+// takes without reading (the caller then need not fill p)
 template <typename T>
-static T* smooth(Level& L, T* cur, int nu, hipStream_t st, bool finest) {
+static T* smooth(Level& L, T* cur, int nu, hipStream_t st, bool finest, bool zero_first) {
     LevelT<T>& A = lvl<T>(L);
     for (int s = 0; s < nu; ++s) {
         if (L.fused) {
             T* other = cur == A.p ? A.alt : A.p;
-            launch_fused<T>(L, cur, other, st, finest);
+            launch_fused<T>(L, cur, other, st, finest, zero_first && s == 0);
             cur = other;
         } else {
             T* save = A.p;
@@ -1411,8 +1424,10 @@ static T* smooth(Level& L, T* cur, int nu, hipStream_t st, bool finest) {
     return cur;
 }
 
+// zero_start: level l starts from p = 0; on levels with the single-pass
+// smoother p is then neither filled nor read, elsewhere the caller filled it
 template <typename T>
-static void vcycle(mg_handle* m, int l, hipStream_t st) {
+static void vcycle(mg_handle* m, int l, hipStream_t st, bool zero_start) {
     Level& L = m->lv[l];
     LevelT<T>& A = lvl<T>(L);
     int last = (int)m->lv.size() - 1;
@@ -1447,7 +1462,7 @@ static void vcycle(mg_handle* m, int l, hipStream_t st) {
     Level& C = m->lv[l + 1];
     LevelT<T>& B = lvl<T>(C);
     bool fin = l == 0;
-    T* cur = smooth<T>(L, A.p, m->o.nu1, st, fin);
+    T* cur = smooth<T>(L, A.p, m->o.nu1, st, fin, zero_start);
     T inv_h2 = (T)(1.0 / (L.d.h * L.d.h));
     long nc = C.d.cells();
     {
@@ -1473,9 +1488,9 @@ static void vcycle(mg_handle* m, int l, hipStream_t st) {
             hipLaunchKernelGGL((k_residual_restrict<T, 3>), dim3(grid_for(nc)), dim3(kBlock), 0, st,
                                cur, A.b, co, L.d, inv_h2, B.b);
     }
-    if (l + 1 != last)
+    if (l + 1 != last && !C.fused)
         hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(nc)), dim3(kBlock), 0, st, B.p, nc, (T)0);
-    vcycle<T>(m, l + 1, st);
+    vcycle<T>(m, l + 1, st, true);
     {
         ProfScope ps(sizeof(T) == 8 ? IB_PROF_PROLONG64 : IB_PROF_PROLONG32, st, fin);
         int bx = std::min(L.d.nx, kBlock);
@@ -1485,7 +1500,7 @@ static void vcycle(mg_handle* m, int l, hipStream_t st) {
         else
             hipLaunchKernelGGL((k_prolong_add<T, 3>), pg, dim3(bx), 0, st, cur, B.p, L.d);
     }
-    cur = smooth<T>(L, cur, m->o.nu2, st, fin);
+    cur = smooth<T>(L, cur, m->o.nu2, st, fin, false);
     if (cur != A.p)
         (void)hipMemcpyAsync(A.p, cur, sizeof(T) * L.d.cells(), hipMemcpyDeviceToDevice, st);
 }
@@ -1879,13 +1894,13 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
     auto precond = [&]() {
         if (mixed) {
             hipLaunchKernelGGL(k_cast_f32, g1, blk, 0, st, m->kr, L0.f32.b, N);
-            hipLaunchKernelGGL((k_fill<float>), g1, blk, 0, st, L0.f32.p, N, 0.0f);
-            vcycle<float>(m, 0, st);
+            if (!L0.fused) hipLaunchKernelGGL((k_fill<float>), g1, blk, 0, st, L0.f32.p, N, 0.0f);
+            vcycle<float>(m, 0, st, true);
         } else {
             L0.f64.b = m->kr;
             L0.f64.p = m->kz;
-            hipLaunchKernelGGL((k_fill<double>), g1, blk, 0, st, m->kz, N, 0.0);
-            vcycle<double>(m, 0, st);
+            if (!L0.fused) hipLaunchKernelGGL((k_fill<double>), g1, blk, 0, st, m->kz, N, 0.0);
+            vcycle<double>(m, 0, st, true);
         }
     };
     // the preconditioner points the finest level at (r, z); the mean
@@ -2043,14 +2058,15 @@ extern "C" int mg_solve(mg_handle* m, const double* b, double* p, double rtol, i
         // A annihilates constants and every step of a cycle commutes with adding
         // one, so the mean is removed once, after the last cycle
         if (mixed) {
-            hipLaunchKernelGGL((k_fill<float>), dim3(grid_for(N)), dim3(kBlock), 0, st, L0.f32.p, N, 0.0f);
-            vcycle<float>(m, 0, st);
+            if (!L0.fused)
+                hipLaunchKernelGGL((k_fill<float>), dim3(grid_for(N)), dim3(kBlock), 0, st, L0.f32.p, N, 0.0f);
+            vcycle<float>(m, 0, st, true);
             int nb = red_blocks(N);
             hipLaunchKernelGGL(k_correct_f32, dim3(nb), dim3(kBlock), 0, st, p, L0.f32.p, N,
                                m->red + 2 * kRed);
             IB_TRY(mixed_defect(m, false, st, check));
         } else {
-            vcycle<double>(m, 0, st);
+            vcycle<double>(m, 0, st, false);
             if (check) IB_TRY(fp64_norms(m, false, st));
         }
         ++cycles;
