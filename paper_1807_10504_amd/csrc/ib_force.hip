@@ -300,16 +300,41 @@ int launch_coefficients(Ctx* c, const double* H, double rin, double rout, double
 // deterministic sums: fixed number of blocks, fixed tree inside a block
 constexpr int kRedBlocks = 1024;
 
-__global__ void k_sum_final(const double* __restrict__ in, int n, double* __restrict__ out) {
-    __shared__ double sh[kBlock];
-    double acc = 0.0;
-    for (int q = threadIdx.x; q < n; q += blockDim.x) acc += in[q];
-    double r = block_reduce_sum(acc, sh);
-    if (threadIdx.x == 0) *out = r;
+// One workgroup of 1024 threads; each thread keeps 8 accumulators so that its
+// loads are independent (one memory latency per 8192 partials instead of one
+// per load), then a fixed butterfly inside each wave and a fixed serial sum
+// over the 16 wave totals.
+constexpr int kSumThreads = 1024;
+
+__global__ __launch_bounds__(kSumThreads) void k_sum_final(const double* __restrict__ in, int n,
+                                                           double* __restrict__ out) {
+    __shared__ double sh[kSumThreads / 64];
+    const int t = threadIdx.x;
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = 0.0;
+    int q = t;
+    for (; q + 7 * kSumThreads < n; q += 8 * kSumThreads) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += in[q + u * kSumThreads];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        if (q + u * kSumThreads < n) a[u] += in[q + u * kSumThreads];
+    double v = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s);
+    if ((t & 63) == 0) sh[t >> 6] = v;
+    __syncthreads();
+    if (t == 0) {
+        double r = 0.0;
+        for (int w = 0; w < kSumThreads / 64; ++w) r += sh[w];
+        *out = r;
+    }
 }
 
 int device_sum(const double* partials, int n, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, st, partials, n, out);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kSumThreads), 0, st, partials, n, out);
     IB_HIP(hipGetLastError());
     return IB_OK;
 }
