@@ -263,6 +263,81 @@ int project_step(ib_ctx* ctx, mg_handle* m, const ib_params* prm, ib_state* st,
                  ib_outputs* out, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Momentum predictor (Section 2.1, eq ns1_new with the surface tension moved
+ * to the projection):
+ *   rho^{n+1}_f (u* - u^n)/dt = -(3/2 C(u^n) - 1/2 C(u^{n-1})) + 1/2 (D u* + D u^n)
+ * Adams-Bashforth advection C (eq ad_bf), Crank-Nicolson viscous stress D
+ * (eq cr_ni), per face component d on the periodic staggered grid:
+ *   C_d = (1/h) sum_e [flux on the high side - flux on the low side along e],
+ *     e = d: rho_cell ((u_d + u_d of the cell's other face)/2)^2 at the cells
+ *            c and c - e_d;
+ *     e != d: mean of the 4 cells around the edge x mean of the two u_e
+ *            faces meeting at the edge x mean of the two u_d faces there;
+ *   D_d = (1/h^2) sum_e [mu_+ (u_d(c+e_e) - u_d(c)) - mu_- (u_d(c) - u_d(c-e_e))],
+ *     mu at the cells c, c - e_d for e = d, the 4-cell edge mean otherwise;
+ *   rho_f = (rho_c + rho_{c-e_d})/2 (the projection's face density).
+ * mu is the dynamic viscosity; every array below is a device cell/face array
+ * of the context's grid, FP64, owned by the caller. */
+typedef struct ib_flow ib_flow;
+
+typedef struct {
+    int sweeps;              /* red-black Gauss-Seidel sweeps of the implicit system */
+    double rel_res;          /* ||g - M u*|| / ||g|| at exit (M = rho_f/dt - D/2) */
+    int first_step;          /* 1: the advection history was empty (explicit Euler) */
+} ib_flow_stats;
+
+typedef struct {
+    double mu_in, mu_out;    /* drop and ambient dynamic viscosities (>= 0) */
+    double rtol;             /* tolerance of the implicit viscous system */
+    int max_sweeps;          /* sweeps allowed (IB_ENOTCONV beyond) */
+} ib_flow_params;
+
+/* C(u) of eq ad_bf for every component; rho: device cell densities. A may not
+ * alias u. */
+int ib_advection(ib_ctx* ctx, const double* const u[3], const double* rho, double* const A[3],
+                 void* stream);
+
+/* D u of eq cr_ni for every component; mu: device cell viscosities. V may not
+ * alias u. */
+int ib_viscous(ib_ctx* ctx, const double* const u[3], const double* mu, double* const V[3],
+               void* stream);
+
+/* The predictor's state: the advection term of the previous step (Adams-
+ * Bashforth history), H of the previous step (flow_step), and workspace, all
+ * allocated here (about 4 dim + 4 grid arrays). Errors: IB_EINVAL, IB_ENOMEM. */
+int  ib_flow_create(const ib_grid* g, ib_flow** out);
+void ib_flow_destroy(ib_flow* f);
+/* forget the history: the next predictor step is explicit Euler in the
+ * advection and flow_step recomputes H of the current markers */
+int  ib_flow_reset(ib_flow* f);
+
+/* u* of eq ns1_new from u^n, the cell densities of levels n (rho_n, in C) and
+ * n+1 (rho_np1, on the left), and the cell viscosities mu (both halves of
+ * the Crank-Nicolson term). The implicit system (rho_f/dt - D/2) u* = g is
+ * solved by red-black Gauss-Seidel on the faces of each component (red =
+ * index sum even), starting from u^n, until ||g - M u*||_2 <= rtol ||g||_2
+ * over all components (the norm is read on the host after every sweep:
+ * syncs). Stores C(u^n) as the next step's history. u_star may not alias u.
+ * Errors: IB_EINVAL, IB_ENOTCONV (u_star holds the last sweep), IB_ENAN. */
+int ib_predict(ib_flow* f, const double* const u[3], const double* rho_n, const double* rho_np1,
+               const double* mu, double dt, double rtol, int max_sweeps, double* const u_star[3],
+               ib_flow_stats* stats, void* stream);
+
+/* One step of the full 2D method (the 3D surface is static: IB_EINVAL):
+ *   markers: U = interp(u^n) (st->u_star holds u^n), advanced by dt U and
+ *   relocated on the least-squares B-spline (X_host in place);
+ *   H^{n+1}, F from the relocated markers; rho^n from the previous step's H
+ *   (the first step after create/reset computes H of the incoming markers);
+ *   u* = ib_predict; projection with u*: coefficients, right side, warm start
+ *   (WS_ZERO or WS_PREV), solve, update into out->u (which may alias u^n).
+ * out->p, out->u, out->U required; out->H, out->F, out->b optional as in
+ * project_step. Syncs (marker round trip, predictor and multigrid norms).
+ * Errors: as project_step and ib_predict. */
+int flow_step(ib_ctx* ctx, ib_flow* f, mg_handle* m, const ib_params* prm,
+              const ib_flow_params* fp, ib_state* st, ib_outputs* out, ib_flow_stats* fstats,
+              void* stream);
+
+/* ---------------------------------------------------------------------------
  * a3 -- host FP64 least-squares B-spline relocation (Section 4), 2D closed
  * curve of n markers. X, U: host n*2. Advances X* = X + dt U, fits a
  * periodic cubic B-spline (knot spacing L/round(L/1.5h), at least 7 spans)

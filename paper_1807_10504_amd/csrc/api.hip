@@ -50,8 +50,6 @@ static int check_surface(Ctx* c, const ib_surface* s, bool need_force) {
 
 }  // namespace ib
 
-struct ib_ctx : ib::Ctx {};
-
 namespace ib {
 
 static int free_ctx(ib_ctx* c) {
@@ -177,8 +175,10 @@ extern "C" int ib_interp(ib_ctx* c, const double* const u[3], const ib_surface* 
     return launch_interp(c, u, s, U, (hipStream_t)stream);
 }
 
-static int spread_impl(Ctx* c, const ib_surface* s, int mode, double* const F[3], double* H,
-                       hipStream_t st) {
+namespace ib {
+
+int spread_impl(Ctx* c, const ib_surface* s, int mode, double* const F[3], double* H,
+                hipStream_t st) {
     if (mode == IB_SPREAD_IRROT || H) IB_TRY(launch_heaviside(c, s, H, st));
     if (mode == IB_SPREAD_IRROT) IB_TRY(launch_irrot_force(c, s, H, F, st));
     else IB_TRY(launch_spread_delta(c, s, F, st));
@@ -191,6 +191,49 @@ static int spread_impl(Ctx* c, const ib_surface* s, int mode, double* const F[3]
     }
     return IB_OK;
 }
+
+// 2D: markers of stt->X_host (n of them) advanced by dt U (U on the device)
+// and relocated on the least-squares B-spline on the host; X_host is updated
+// in place and s points at the relocated device copies with their force data.
+int relocate_2d(Ctx* c, const ib_params* prm, ib_state* stt, const double* U_dev, double* fs_host,
+                ib_surface* s, hipStream_t st) {
+    const int n = s->n_markers;
+    std::vector<double> U(2 * (size_t)n), Xn(2 * (size_t)n), fs(n), ds(n), nr(2 * (size_t)n);
+    IB_HIP(hipMemcpyAsync(U.data(), U_dev, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, st));
+    IB_HIP(hipStreamSynchronize(st));
+    IB_TRY(ib_relocate_bspline(n, stt->X_host, U.data(), prm->dt, c->d.h, prm->sigma, Xn.data(),
+                               fs.data(), ds.data(), nr.data()));
+    std::memcpy(stt->X_host, Xn.data(), sizeof(double) * 2 * n);
+    if (fs_host) std::memcpy(fs_host, fs.data(), sizeof(double) * n);
+    IB_HIP(hipMemcpyAsync(c->mX, Xn.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice, st));
+    IB_HIP(hipMemcpyAsync(c->mfs, fs.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+    IB_HIP(hipMemcpyAsync(c->mds, ds.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+    IB_HIP(hipMemcpyAsync(c->mnrm, nr.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice, st));
+    // the host vectors must outlive the copies
+    IB_HIP(hipStreamSynchronize(st));
+    s->X = c->mX;
+    s->fs = c->mfs;
+    s->ds = c->mds;
+    s->nrm = c->mnrm;
+    return IB_OK;
+}
+
+// a6 + a8: rho and beta of level n+1 into the context, the hierarchy from them
+int coefficients_and_hierarchy(Ctx* c, mg_handle* m, const ib_params* prm, const double* H,
+                               hipStream_t st) {
+    IB_TRY(launch_coefficients(c, H, prm->rho_in, prm->rho_out, c->beta, c->rho, st));
+    if (mg_takes_density(m)) IB_TRY(mg_update_density(m, c->rho, st));
+    else IB_TRY(mg_update_coeffs(m, c->beta, st));
+    return IB_OK;
+}
+
+// a7, a10, a9, a11 on the context's beta: right side from u_star and F, warm
+// start, solve, update. Returns IB_OK or IB_ENOTCONV (the update is done).
+int solve_and_update(Ctx* c, mg_handle* m, const ib_params* prm, ib_state* stt, ib_outputs* out,
+                     const double* const u_star[3], const double* H, double* const F[3],
+                     hipStream_t st);
+
+}  // namespace ib
 
 extern "C" int ib_spread(ib_ctx* c, const ib_surface* s, int mode, double* const F[3], double* H,
                          void* stream) {
@@ -264,25 +307,7 @@ extern "C" int project_step(ib_ctx* c, mg_handle* m, const ib_params* prm, ib_st
     // a2: marker velocities
     IB_TRY(launch_interp(c, stt->u_star, &s, out->U, st));
     // a3: 2D marker advance and least-squares relocation on the host
-    if (dim == 2) {
-        std::vector<double> U(2 * (size_t)n), Xn(2 * (size_t)n), fs(n), ds(n), nr(2 * (size_t)n);
-        IB_HIP(hipMemcpyAsync(U.data(), out->U, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, st));
-        IB_HIP(hipStreamSynchronize(st));
-        IB_TRY(ib_relocate_bspline(n, stt->X_host, U.data(), prm->dt, c->d.h, prm->sigma, Xn.data(),
-                                   fs.data(), ds.data(), nr.data()));
-        std::memcpy(stt->X_host, Xn.data(), sizeof(double) * 2 * n);
-        if (out->fs_host) std::memcpy(out->fs_host, fs.data(), sizeof(double) * n);
-        IB_HIP(hipMemcpyAsync(c->mX, Xn.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice, st));
-        IB_HIP(hipMemcpyAsync(c->mfs, fs.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
-        IB_HIP(hipMemcpyAsync(c->mds, ds.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
-        IB_HIP(hipMemcpyAsync(c->mnrm, nr.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice, st));
-        // the host vectors must outlive the copies
-        IB_HIP(hipStreamSynchronize(st));
-        s.X = c->mX;
-        s.fs = c->mfs;
-        s.ds = c->mds;
-        s.nrm = c->mnrm;
-    }
+    if (dim == 2) IB_TRY(relocate_2d(c, prm, stt, out->U, out->fs_host, &s, st));
     // a4, a5: Heaviside and face force
     double* H = out->H ? out->H : c->H;
     double* F[3];
@@ -291,13 +316,17 @@ extern "C" int project_step(ib_ctx* c, mg_handle* m, const ib_params* prm, ib_st
              "project_step: spread mode");
     IB_TRY(spread_impl(c, &s, prm->spread_mode, F, H, st));
     // a6: coefficients, a8: hierarchy
-    IB_TRY(launch_coefficients(c, H, prm->rho_in, prm->rho_out, c->beta, c->rho, st));
-    if (mg_takes_density(m)) IB_TRY(mg_update_density(m, c->rho, st));
-    else IB_TRY(mg_update_coeffs(m, c->beta, st));
+    IB_TRY(coefficients_and_hierarchy(c, m, prm, H, st));
+    return solve_and_update(c, m, prm, stt, out, stt->u_star, H, F, st);
+}
+
+int ib::solve_and_update(Ctx* c, mg_handle* m, const ib_params* prm, ib_state* stt, ib_outputs* out,
+                         const double* const u_star[3], const double* H, double* const F[3],
+                         hipStream_t st) {
     // a7: right side
     const double* Fc[3] = {F[0], F[1], F[2]};
     const double* bc[3] = {c->beta[0], c->beta[1], c->beta[2]};
-    IB_TRY(launch_rhs(c, stt->u_star, Fc, bc, prm->dt, c->b, st));
+    IB_TRY(launch_rhs(c, u_star, Fc, bc, prm->dt, c->b, st));
     // a9, a10: warm start and solve
     long N = c->d.cells();
     if (out->b) IB_HIP(hipMemcpyAsync(out->b, c->b, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
@@ -334,6 +363,6 @@ extern "C" int project_step(ib_ctx* c, mg_handle* m, const ib_params* prm, ib_st
     int rc = mg_solve(m, c->b, out->p, prm->rtol, prm->max_cycles, prm->fixed_cycles, &out->stats, st);
     if (rc != IB_OK && rc != IB_ENOTCONV) return rc;
     // a11: velocity update
-    IB_TRY(launch_update(c, stt->u_star, Fc, bc, out->p, prm->dt, out->u, st));
+    IB_TRY(launch_update(c, u_star, Fc, bc, out->p, prm->dt, out->u, st));
     return rc;
 }

@@ -150,7 +150,20 @@ int read_flags(Ctx* c, int* host_flags, hipStream_t st);
 // deterministic reduction helpers (fixed tree: block partials then one block)
 int device_sum(const double* partials_in, int n, double* out_dev, hipStream_t st);
 
+// pieces of the step shared by project_step and flow_step (api.hip)
+int spread_impl(Ctx* c, const ib_surface* s, int mode, double* const F[3], double* H, hipStream_t st);
+int relocate_2d(Ctx* c, const ib_params* prm, ib_state* stt, const double* U_dev, double* fs_host,
+                ib_surface* s, hipStream_t st);
+int coefficients_and_hierarchy(Ctx* c, mg_handle* m, const ib_params* prm, const double* H,
+                               hipStream_t st);
+int solve_and_update(Ctx* c, mg_handle* m, const ib_params* prm, ib_state* stt, ib_outputs* out,
+                     const double* const u_star[3], const double* H, double* const F[3],
+                     hipStream_t st);
+
 }  // namespace ib
+
+// the opaque context handle of the C ABI is the library's context
+struct ib_ctx : ib::Ctx {};
 
 // 1 when the multigrid's finest level reads cell densities directly (mg.hip)
 int mg_takes_density(const mg_handle* m);

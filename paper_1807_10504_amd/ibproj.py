@@ -29,7 +29,8 @@ EXPORTS = ("ib_create", "ib_destroy", "ib_bin_markers", "ib_interp", "ib_spread"
            "ib_nn_set_params", "ib_nn_get_params", "ib_nn_predict", "ib_nn_gradients",
            "ib_nn_train_step",
            "ib_diagnostics", "ib_profile_enable", "ib_profile_reset", "ib_profile_read",
-           "ib_last_error")
+           "ib_advection", "ib_viscous", "ib_flow_create", "ib_flow_destroy", "ib_flow_reset",
+           "ib_predict", "flow_step", "ib_last_error")
 
 PROF_KINDS = ("smooth64", "smooth32", "restrict64", "restrict32", "prolong64", "prolong32", "resid",
               "sweep64", "sweep32", "sweep64_rho", "sweep_zero")
@@ -80,6 +81,18 @@ class Outputs(C.Structure):
                 ("F", C.c_void_p * 3), ("fs_host", C.c_void_p), ("b", C.c_void_p),
                 ("stats", MgStats), ("guess_accepted", C.c_int), ("guess_rel_res", C.c_double),
                 ("prev_rel_res", C.c_double)]
+
+
+class FlowStats(C.Structure):
+    _fields_ = [("sweeps", C.c_int), ("rel_res", C.c_double), ("first_step", C.c_int)]
+
+    def as_dict(self):
+        return dict(sweeps=self.sweeps, rel_res=self.rel_res, first_step=self.first_step)
+
+
+class FlowParams(C.Structure):
+    _fields_ = [("mu_in", C.c_double), ("mu_out", C.c_double), ("rtol", C.c_double),
+                ("max_sweeps", C.c_int)]
 
 
 class Diag(C.Structure):
@@ -135,6 +148,14 @@ def load(path: str = LIB_PATH):
         "ib_profile_enable": (None, [i32]),
         "ib_profile_reset": (None, []),
         "ib_profile_read": (i32, [i32, P(C.c_longlong), P(f64)]),
+        "ib_advection": (i32, [vp, vp * 3, vp, vp * 3, vp]),
+        "ib_viscous": (i32, [vp, vp * 3, vp, vp * 3, vp]),
+        "ib_flow_create": (i32, [P(Grid), P(vp)]),
+        "ib_flow_destroy": (None, [vp]),
+        "ib_flow_reset": (i32, [vp]),
+        "ib_predict": (i32, [vp, vp * 3, vp, vp, vp, f64, f64, i32, vp * 3, P(FlowStats), vp]),
+        "flow_step": (i32, [vp, vp, vp, P(Params), P(FlowParams), P(State), P(Outputs),
+                            P(FlowStats), vp]),
         "ib_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -315,11 +336,26 @@ class Context:
                                        C.byref(d), _stream()))
         return d.as_dict()
 
-    def project_step(self, mg: "Multigrid", params: dict, u_star, p_prev=None, surf=None,
-                     X_host=None, n_markers=None, out=None, nn: "Network" = None):
-        """One projection step. 2D: X_host (numpy, N x 2) is advanced and relocated in
-        place; 3D: surf is the static surface. Returns the outputs dict."""
+    def advection(self, u, rho, A=None):
+        """C(u) of eq ad_bf (per face component)."""
         import torch
+        if A is None:
+            A = [torch.empty(self.shape, dtype=torch.float64, device="cuda") for _ in range(self.dim)]
+        _check(self.lib.ib_advection(self.ptr, _vec3(u, torch.float64), _dptr(rho, torch.float64),
+                                     _vec3(A, torch.float64), _stream()))
+        return A
+
+    def viscous(self, u, mu, V=None):
+        """D u of eq cr_ni (per face component)."""
+        import torch
+        if V is None:
+            V = [torch.empty(self.shape, dtype=torch.float64, device="cuda") for _ in range(self.dim)]
+        _check(self.lib.ib_viscous(self.ptr, _vec3(u, torch.float64), _dptr(mu, torch.float64),
+                                   _vec3(V, torch.float64), _stream()))
+        return V
+
+    @staticmethod
+    def _params(params, p_prev):
         prm = Params()
         prm.rho_in = params["rho_in"]
         prm.rho_out = params["rho_out"]
@@ -330,19 +366,10 @@ class Context:
         prm.fixed_cycles = params.get("fixed_cycles", 0)
         prm.spread_mode = params.get("spread_mode", IB_SPREAD_IRROT)
         prm.warm_start = params.get("warm_start", WS_PREV if p_prev is not None else WS_ZERO)
-        st = State()
-        st.u_star = _vec3(u_star, torch.float64)
-        st.p_prev = _dptr(p_prev, torch.float64)
-        if self.dim == 2:
-            st.surf = Surface()
-            st.surf.n_markers = int(X_host.shape[0])
-            st.X_host = _hptr(X_host)
-            nm = int(X_host.shape[0])
-        else:
-            st.surf = surf
-            st.X_host = None
-            nm = surf.n_markers
-        st.nn = nn.ptr if nn is not None else None
+        return prm
+
+    def _outputs(self, out, nm):
+        import torch
         if out is None:
             out = {}
         o = Outputs()
@@ -359,6 +386,28 @@ class Context:
         fs_host = out.get("fs_host")
         o.fs_host = _hptr(fs_host) if fs_host is not None else None
         o.b = _dptr(out.get("b"), torch.float64)
+        return out, o
+
+    def project_step(self, mg: "Multigrid", params: dict, u_star, p_prev=None, surf=None,
+                     X_host=None, n_markers=None, out=None, nn: "Network" = None):
+        """One projection step. 2D: X_host (numpy, N x 2) is advanced and relocated in
+        place; 3D: surf is the static surface. Returns the outputs dict."""
+        import torch
+        prm = self._params(params, p_prev)
+        st = State()
+        st.u_star = _vec3(u_star, torch.float64)
+        st.p_prev = _dptr(p_prev, torch.float64)
+        if self.dim == 2:
+            st.surf = Surface()
+            st.surf.n_markers = int(X_host.shape[0])
+            st.X_host = _hptr(X_host)
+            nm = int(X_host.shape[0])
+        else:
+            st.surf = surf
+            st.X_host = None
+            nm = surf.n_markers
+        st.nn = nn.ptr if nn is not None else None
+        out, o = self._outputs(out, nm)
         rc = self.lib.project_step(self.ptr, mg.ptr, C.byref(prm), C.byref(st), C.byref(o), _stream())
         out["stats"] = o.stats.as_dict()
         out["guess"] = dict(accepted=o.guess_accepted, rel_res=o.guess_rel_res,
@@ -367,6 +416,72 @@ class Context:
             return out
         _check(rc)
         return out
+
+    def flow_step(self, mg: "Multigrid", flow: "Flow", params: dict, u, X_host, p_prev=None,
+                  out=None):
+        """One step of the full 2D method: markers advanced with u^n (X_host, numpy N x 2,
+        updated in place), H and force of the new markers, predictor (params: mu_in,
+        mu_out, pred_rtol, pred_max_sweeps), projection. Returns the outputs dict with
+        'stats' (multigrid) and 'flow' (predictor)."""
+        import torch
+        prm = self._params(params, p_prev)
+        fp = FlowParams()
+        fp.mu_in = params.get("mu_in", 0.0)
+        fp.mu_out = params.get("mu_out", 0.0)
+        fp.rtol = params.get("pred_rtol", 1e-12)
+        fp.max_sweeps = params.get("pred_max_sweeps", 200)
+        st = State()
+        st.u_star = _vec3(u, torch.float64)
+        st.p_prev = _dptr(p_prev, torch.float64)
+        st.surf = Surface()
+        st.surf.n_markers = int(X_host.shape[0])
+        st.X_host = _hptr(X_host)
+        st.nn = None
+        out, o = self._outputs(out, int(X_host.shape[0]))
+        fs = FlowStats()
+        rc = self.lib.flow_step(self.ptr, flow.ptr, mg.ptr, C.byref(prm), C.byref(fp), C.byref(st),
+                                C.byref(o), C.byref(fs), _stream())
+        out["stats"] = o.stats.as_dict()
+        out["flow"] = fs.as_dict()
+        _check(rc)
+        return out
+
+
+class Flow:
+    """Momentum predictor state (Adams-Bashforth history, previous H, workspace)."""
+
+    def __init__(self, dim, n, h):
+        self.lib = load()
+        self.dim = dim
+        self.shape = tuple(reversed(tuple(n[:dim])))
+        self.grid = make_grid(dim, n, h)
+        self.ptr = C.c_void_p()
+        _check(self.lib.ib_flow_create(C.byref(self.grid), C.byref(self.ptr)))
+
+    def close(self):
+        if self.ptr:
+            self.lib.ib_flow_destroy(self.ptr)
+            self.ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self):
+        _check(self.lib.ib_flow_reset(self.ptr))
+
+    def predict(self, u, rho_n, rho_np1, mu, dt, rtol=1e-12, max_sweeps=200, u_star=None):
+        """u* of eq ns1_new; returns (u_star, stats dict)."""
+        import torch
+        if u_star is None:
+            u_star = [torch.empty(self.shape, dtype=torch.float64, device="cuda") for _ in range(self.dim)]
+        fs = FlowStats()
+        _check(self.lib.ib_predict(self.ptr, _vec3(u, torch.float64), _dptr(rho_n, torch.float64),
+                                   _dptr(rho_np1, torch.float64), _dptr(mu, torch.float64), dt, rtol,
+                                   int(max_sweeps), _vec3(u_star, torch.float64), C.byref(fs), _stream()))
+        return u_star, fs.as_dict()
 
 
 class Multigrid:

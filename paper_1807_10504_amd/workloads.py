@@ -57,6 +57,12 @@ def mode_shape(n: int, R: float, eps: float = 0.1, centre=(0.5, 0.5), seed: int 
     return np.stack([centre[0] + r * np.cos(th), centre[1] + r * np.sin(th)], axis=1)
 
 
+def ellipse_markers(n: int, R: float, beta: float, centre=(0.5, 0.5)) -> np.ndarray:
+    """eq osc: x = x' + R cos(theta) beta, y = y' + R sin(theta) / beta."""
+    th = 2.0 * np.pi * np.arange(n) / n
+    return np.stack([centre[0] + R * np.cos(th) * beta, centre[1] + R * np.sin(th) / beta], axis=1)
+
+
 def perturbed_circle(n: int = 126, g: float = 1e-3) -> np.ndarray:
     """Markers of the curvature-sensitivity illustration (eq interpol_cir).
 
@@ -224,3 +230,14 @@ def oscillating_drop_2d_512(seed: int | None = None) -> Workload:
     n = (512, 512)
     return Workload("oscillating_drop_2d_512", 2, n, 1.0 / 512, 1.0, 1e-3, 1.0, 2e-5, 1000,
                     mode_shape(1024, 0.2, 0.1, seed=seed, extra_amp=0.02 if seed is not None else 0.0))
+
+
+def oscillating_drop_2d_osc(n: int = 256, h: float = 0.01, beta: float = 1.03,
+                            markers: int = 256) -> Workload:
+    """The free oscillation of Section 5 (Table osc): a drop of R = 0.2 stretched by
+    beta (eq osc), densities 1 / 0.01, viscosities 0.01 / 1e-5, sigma = 1, on an
+    n^2 periodic box of spacing h, centred; dt = 1e-4."""
+    c = 0.5 * n * h
+    return Workload(f"oscillating_drop_2d_{n}_h{h:g}", 2, (n, n), h, 1.0, 0.01, 1.0, 1e-4, 2600,
+                    ellipse_markers(markers, 0.2, beta, centre=(c, c)),
+                    extra=dict(mu_in=0.01, mu_out=1e-5, beta=beta, R=0.2))

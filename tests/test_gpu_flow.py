@@ -1,0 +1,228 @@
+"""Momentum predictor and the full 2D flow step on the GPU against the oracle
+(eqs ns1_new, ad_bf, cr_ni), and the oscillating drop of Section 5.2.
+
+* ib_advection / ib_viscous element by element against oracle.flow on ragged
+  2D and 3D grids with variable density and viscosity (1e-13 of the largest
+  value);
+* ib_predict against the oracle's exactly solved Crank-Nicolson system, first
+  step (Euler advection) and second step (Adams-Bashforth history kept in
+  the handle), 2D and 3D, ratio 1000 densities (1e-11 relative L2);
+* a single shear mode is multiplied by the Crank-Nicolson factor;
+* flow_step: three steps of the full 2D method against oracle.flow_step_2d
+  (markers, velocity, pressure);
+* the free oscillation of a drop stretched by 1.03 (eq osc, Table osc) at
+  h = 0.01: the first-cycle period within 3 % of eq osc_p (the paper's new
+  scheme is 1.75 % off at this spacing).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import flow as oflow
+from oracle import poisson
+from paper_1807_10504_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def ib():
+    from paper_1807_10504_amd import ibproj
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    ibproj.load()
+    return ibproj
+
+
+def _drop_H(shape):
+    g = np.indices(shape)
+    r = np.sqrt(sum(((g[a] + 0.5) / shape[a] - 0.5) ** 2 for a in range(len(shape))))
+    return np.clip((0.3 - r) * max(shape) / 3 + 0.5, 0.0, 1.0)
+
+
+def _fields(shape, seed):
+    rng = np.random.default_rng(seed)
+    dim = len(shape)
+    u = [rng.standard_normal(shape) for _ in range(dim)]
+    H = _drop_H(shape)
+    rho = poisson.density(H, 1.0, 1e-3)
+    mu = poisson.density(H, 1e-2, 1e-4)
+    return u, H, rho, mu
+
+
+@pytest.mark.parametrize("shape", [(48, 64), (16, 20, 24)])
+def test_advection_viscous_parity(ib, shape):
+    dim = len(shape)
+    n = tuple(reversed(shape))
+    h = 1.0 / n[0]
+    u, H, rho, mu = _fields(shape, 81)
+    ctx = ib.Context(dim, n, h, max_markers=16)
+    ud = [dev(a) for a in u]
+    A = [host(a) for a in ctx.advection(ud, dev(rho))]
+    V = [host(a) for a in ctx.viscous(ud, dev(mu))]
+    Ao = oflow.advection(u, rho, h)
+    Vo = oflow.viscous(u, mu, h)
+    for d in range(dim):
+        ea = np.abs(A[d] - Ao[d]).max() / np.abs(Ao[d]).max()
+        ev = np.abs(V[d] - Vo[d]).max() / np.abs(Vo[d]).max()
+        print(f"{shape} component {d}: advection {ea:.1e}, viscous {ev:.1e}")
+        assert ea <= 1e-13 and ev <= 1e-13
+
+
+@pytest.mark.parametrize("shape", [(64, 48), (16, 16, 24)])
+def test_predict_parity_two_steps(ib, shape):
+    dim = len(shape)
+    n = tuple(reversed(shape))
+    h = 1.0 / n[0]
+    dt = 2e-4
+    u, H, rho, mu = _fields(shape, 82)
+    rng = np.random.default_rng(83)
+    rho1 = poisson.density(np.clip(H + 0.05 * rng.standard_normal(shape) * (H > 0) * (H < 1), 0, 1),
+                           1.0, 1e-3)
+    fl = ib.Flow(dim, n, h)
+    ud = [dev(a) for a in u]
+    us, st = fl.predict(ud, dev(rho), dev(rho1), dev(mu), dt, rtol=1e-13)
+    uo, adv = oflow.predict(u, rho, rho1, mu, dt, h)
+    assert st["first_step"] == 1 and st["rel_res"] <= 1e-13
+    errs = [rel_l2(host(us[d]), uo[d]) for d in range(dim)]
+    # second step: the handle's history against the oracle's
+    u2 = [a + 0.1 * rng.standard_normal(shape) for a in uo]
+    us2, st2 = fl.predict([dev(a) for a in u2], dev(rho1), dev(rho), dev(mu), dt, rtol=1e-13)
+    uo2, _ = oflow.predict(u2, rho1, rho, mu, dt, h, adv_prev=adv)
+    assert st2["first_step"] == 0
+    errs += [rel_l2(host(us2[d]), uo2[d]) for d in range(dim)]
+    print(f"{shape}: sweeps {st['sweeps']}, {st2['sweeps']}; rel L2 vs oracle {max(errs):.2e}")
+    assert max(errs) <= 1e-11
+    # a reset forgets the history: the next step is Euler again
+    fl.reset()
+    _, st3 = fl.predict(ud, dev(rho), dev(rho1), dev(mu), dt, rtol=1e-13)
+    assert st3["first_step"] == 1
+
+
+def test_predict_crank_nicolson_mode(ib):
+    n = 32
+    h = 1.0 / n
+    rho, mu, dt = 0.8, 0.05, 0.02
+    j, i = np.indices((n, n))
+    ud = np.cos(2 * np.pi * (j + 0.5) * h)
+    fl = ib.Flow(2, (n, n), h)
+    one = np.ones((n, n))
+    us, st = fl.predict([dev(ud), dev(np.zeros_like(ud))], dev(rho * one), dev(rho * one),
+                        dev(mu * one), dt, rtol=1e-14)
+    lam = mu * (2 * np.cos(2 * np.pi * h) - 2) / (h * h)
+    g = (1 + 0.5 * dt * lam / rho) / (1 - 0.5 * dt * lam / rho)
+    assert np.abs(host(us[0]) - g * ud).max() <= 1e-13
+    assert np.abs(host(us[1])).max() <= 1e-14
+
+
+def test_predict_errors(ib):
+    fl = ib.Flow(2, (16, 16), 1 / 16)
+    a = torch.zeros((16, 16), dtype=torch.float64, device="cuda")
+    with pytest.raises(ib.IbError):
+        fl.predict([a, a], a, a, a, -1.0)
+    with pytest.raises(ib.IbError):
+        fl.predict([a, a], a, a, a, 1e-3, u_star=[a, a])       # aliasing
+    with pytest.raises(ib.IbError):
+        ib.Flow(2, (15, 16), 1 / 16)
+
+
+def test_flow_step_parity_2d(ib):
+    n = (64, 64)
+    h = 1.0 / 64
+    prm = dict(rho_in=1.0, rho_out=1e-3, mu_in=1e-2, mu_out=1e-4, sigma=1.0, dt=1e-4, rtol=1e-12,
+               pred_rtol=1e-13, warm_start=ib.WS_PREV)
+    X0 = W.ellipse_markers(128, 0.25, 1.1)
+    ctx = ib.Context(2, n, h, max_markers=256)
+    mg = ib.Multigrid(2, n, h)
+    fl = ib.Flow(2, n, h)
+    u = [torch.zeros((64, 64), dtype=torch.float64, device="cuda") for _ in range(2)]
+    p = torch.zeros((64, 64), dtype=torch.float64, device="cuda")
+    Xg = X0.copy()
+    # oracle state
+    from oracle import heaviside
+    uo = [np.zeros((64, 64)) for _ in range(2)]
+    Xo = X0.copy()
+    Ho = heaviside.heaviside_2d(Xo, n, h)
+    advo, po = None, None
+    for step in range(3):
+        out = ctx.flow_step(mg, fl, prm, u, Xg, p_prev=p, out={"p": p, "u": u})
+        r = oflow.flow_step_2d(n, h, 1.0, 1e-3, 1e-2, 1e-4, 1.0, 1e-4, uo, Xo, Ho, adv_prev=advo,
+                               p_prev=po, rtol=1e-12)
+        uo, Xo, Ho, advo, po = r["u"], r["X"], r["H"], r["adv"], r["p"]
+        eu = max(np.abs(host(u[d]) - uo[d]).max() for d in range(2)) / max(np.abs(a).max() for a in uo)
+        ep = rel_l2(host(p), po)
+        ex = np.abs(Xg - Xo).max()
+        print(f"step {step}: sweeps {out['flow']['sweeps']}, cycles {out['stats']['cycles']} "
+              f"(oracle {r['cycles']}); |du|/|u| {eu:.1e}, p {ep:.1e}, X {ex:.1e}", flush=True)
+        assert out["flow"]["first_step"] == (1 if step == 0 else 0)
+        assert eu <= 1e-9 and ep <= 1e-10 and ex <= 1e-12
+
+
+def test_flow_step_errors(ib):
+    ctx3 = ib.Context(3, (16, 16, 16), 1 / 16, max_markers=16)
+    mg3 = ib.Multigrid(3, (16, 16, 16), 1 / 16)
+    fl3 = ib.Flow(3, (16, 16, 16), 1 / 16)
+    u = [torch.zeros((16, 16, 16), dtype=torch.float64, device="cuda") for _ in range(3)]
+    with pytest.raises(ib.IbError):
+        ctx3.flow_step(mg3, fl3, dict(rho_in=1, rho_out=1, dt=1e-3), u, np.zeros((8, 2)))
+    ctx = ib.Context(2, (32, 32), 1 / 32, max_markers=64)
+    mg = ib.Multigrid(2, (32, 32), 1 / 32)
+    fl = ib.Flow(2, (64, 64), 1 / 64)          # another grid
+    u2 = [torch.zeros((32, 32), dtype=torch.float64, device="cuda") for _ in range(2)]
+    with pytest.raises(ib.IbError):
+        ctx.flow_step(mg, fl, dict(rho_in=1, rho_out=1, dt=1e-3), u2, W.circle_markers(32, 0.25))
+
+
+def test_oscillating_drop_period(ib):
+    wl = W.oscillating_drop_2d_osc()
+    n, h = wl.n, wl.h
+    prm = dict(rho_in=wl.rho_in, rho_out=wl.rho_out, mu_in=wl.extra["mu_in"], mu_out=wl.extra["mu_out"],
+               sigma=wl.sigma, dt=wl.dt, rtol=1e-10, pred_rtol=1e-12, warm_start=ib.WS_PREV)
+    ctx = ib.Context(2, n, h, max_markers=len(wl.X))
+    mg = ib.Multigrid(2, n, h, krylov=1)
+    fl = ib.Flow(2, n, h)
+    shape = tuple(reversed(n))
+    u = [torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(2)]
+    p = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    X = wl.X.copy()
+    diam = [np.ptp(X[:, 0])]
+    out = {"p": p, "u": u}
+    for step in range(wl.steps):
+        out = ctx.flow_step(mg, fl, prm, u, X, p_prev=p, out=out)
+        diam.append(np.ptp(X[:, 0]))
+        if step % 500 == 0:
+            print(f"step {step}: x-diameter {diam[-1]:.5f}, predictor sweeps {out['flow']['sweeps']}, "
+                  f"cycles {out['stats']['cycles']}", flush=True)
+    d = np.array(diam)
+    t = np.arange(len(d)) * wl.dt
+    kmin = int(np.argmin(d[: len(d) // 2 + 200]))
+    kmax = kmin + int(np.argmax(d[kmin:]))
+    assert 0 < kmin < kmax < len(d) - 1, (kmin, kmax)
+    # parabola through the three samples around the discrete maximum
+    y0, y1, y2 = d[kmax - 1], d[kmax], d[kmax + 1]
+    T = t[kmax] + 0.5 * wl.dt * (y0 - y2) / (y0 - 2 * y1 + y2)
+    T_exact = GOLD["oscillation_periods"]["period_2d"]
+    T_paper = GOLD["oscillation_period_table_2d"]["period_new"][1]
+    err = abs(T - T_exact) / T_exact
+    print(f"first-cycle period {T:.4f} (eq osc_p {T_exact}, {100 * err:.2f} %; the paper's new scheme "
+          f"at h = 0.01: {T_paper})")
+    assert err <= 0.03
+    # the oscillation decays (viscosity) and the area is kept to the relocation's accuracy
+    assert d[kmax] < d[0]

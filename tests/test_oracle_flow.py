@@ -175,3 +175,20 @@ def test_predictor_crank_nicolson_factor():
     g = (1 + 0.5 * dt * lam / rho) / (1 - 0.5 * dt * lam / rho)
     assert np.abs(us[0] - g * ud).max() <= 1e-13
     assert np.abs(us[1]).max() <= 1e-14
+
+
+def test_oscillation_period_formulas_match_printed_values():
+    """eqs osc_p and aosc_p with n = 2, r = 0.2, sigma = 1 give the printed
+    periods for drop density 1 and ambient 0.01 (the reading of the garbled
+    parameter sentence of Section 5.2 that the flow tests use)."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+    n, r, sigma, rd, ra = 2, 0.2, 1.0, 1.0, 0.01
+    t2 = 2 * np.pi * np.sqrt((rd + ra) * r ** 3 / ((n ** 3 - n) * sigma))
+    tax = 2 * np.pi * np.sqrt(((n + 1) * rd + n * ra) * r ** 3 / (n * (n - 1) * (n + 1) * (n + 2) * sigma))
+    assert abs(t2 - gold["oscillation_periods"]["period_2d"]) < 5e-6
+    assert abs(tax - gold["oscillation_periods"]["period_axisymmetric"]) < 5e-6
+    tab = gold["oscillation_period_table_2d"]
+    for T, pct in zip(tab["period_new"], tab["discrepancy_new_percent"]):
+        assert abs(100 * abs(T - t2) / t2 - pct) < 0.02
