@@ -221,6 +221,88 @@ def bench_2d_c2(ib, torch, steps=200):
     return out
 
 
+def bench_flow_osc(ib, torch):
+    """Full 2D flow steps (markers, H and force, momentum predictor, projection) on the
+    free oscillation of Section 5.2 at h = 0.01 (Table osc): steps/s over the first
+    oscillation cycle and the measured period against eq osc_p and the paper's."""
+    from paper_1807_10504_amd import workloads as W
+    wl = W.oscillating_drop_2d_osc()
+    n, h = wl.n, wl.h
+    prm = dict(rho_in=wl.rho_in, rho_out=wl.rho_out, mu_in=wl.extra["mu_in"], mu_out=wl.extra["mu_out"],
+               sigma=wl.sigma, dt=wl.dt, rtol=1e-10, pred_rtol=1e-12, warm_start=ib.WS_PREV)
+    ctx = ib.Context(2, n, h, max_markers=len(wl.X))
+    mg = ib.Multigrid(2, n, h, krylov=1)
+    fl = ib.Flow(2, n, h)
+    shape = tuple(reversed(n))
+    u = [torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(2)]
+    p = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    X = wl.X.copy()
+    diam = [float(np.ptp(X[:, 0]))]
+    sweeps, cycles = [], []
+    out = {"p": p, "u": u}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(wl.steps):
+        out = ctx.flow_step(mg, fl, prm, u, X, p_prev=p, out=out)
+        diam.append(float(np.ptp(X[:, 0])))
+        sweeps.append(out["flow"]["sweeps"])
+        cycles.append(out["stats"]["cycles"])
+        if k % 1000 == 999:
+            log(f"  flow step {k + 1}/{wl.steps}")
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    d = np.array(diam)
+    kmin = int(np.argmin(d[: len(d) // 2 + 200]))
+    kmax = kmin + int(np.argmax(d[kmin:]))
+    y0, y1, y2 = d[kmax - 1], d[kmax], d[kmax + 1]
+    T = (kmax + 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2)) * wl.dt
+    T_exact = 2 * np.pi * np.sqrt((wl.rho_in + wl.rho_out) * 0.2 ** 3 / (6 * wl.sigma))
+    return dict(
+        workload=(f"{wl.name}: Table osc drop, R=0.2 stretched by 1.03 (eq osc), 256 markers, rho 1/0.01, "
+                  f"mu 0.01/1e-5, sigma=1, 256^2 periodic box at h=0.01, dt=1e-4, {wl.steps} full steps "
+                  "(AB2 advection + Crank-Nicolson viscosity + irrotational force + FCG projection, WS_PREV)"),
+        steps_per_s=round(wl.steps / secs, 2), ms_per_step=round(1e3 * secs / wl.steps, 3),
+        mean_predictor_sweeps=float(np.mean(sweeps)), mean_cycles=float(np.mean(cycles)),
+        period=round(float(T), 5), period_eq_osc_p=round(float(T_exact), 5),
+        discrepancy_percent=round(100 * abs(T - T_exact) / T_exact, 2),
+        paper_new_scheme_h001=dict(period=0.2346, discrepancy_percent=1.75))
+
+
+def bench_predictor_3d(ib, torch, nc=256, calls=5):
+    """The momentum predictor alone at nc^3 (FP64): a smooth drop of radius 0.3 with
+    densities 1/1e-3 and viscosities 1e-2/1e-4, seeded velocities of size 0.1,
+    dt = 5e-5, Adams-Bashforth history present, system solved to 1e-12."""
+    shape = (nc, nc, nc)
+    h = 1.0 / nc
+    z = (np.arange(nc) + 0.5) * h - 0.5
+    r = np.sqrt(z[:, None, None] ** 2 + z[None, :, None] ** 2 + z[None, None, :] ** 2)
+    H = torch.from_numpy(np.clip((0.3 - r) / (3 * h) + 0.5, 0.0, 1.0)).cuda()
+    rho = 1e-3 + (1.0 - 1e-3) * H
+    mu = 1e-4 + (1e-2 - 1e-4) * H
+    g = torch.Generator(device="cpu").manual_seed(7)
+    u = [(0.1 * torch.randn(shape, generator=g, dtype=torch.float64)).cuda() for _ in range(3)]
+    us = [torch.empty_like(a) for a in u]
+    fl = ib.Flow(3, (nc, nc, nc), h)
+    fl.predict(u, rho, rho, mu, 5e-5, rtol=1e-12, u_star=us)      # fills the history
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sw = []
+    for _ in range(calls):
+        _, st = fl.predict(u, rho, rho, mu, 5e-5, rtol=1e-12, u_star=us)
+        sw.append(st["sweeps"])
+    torch.cuda.synchronize()
+    secs = (time.perf_counter() - t0) / calls
+    N = float(nc) ** 3
+    s = float(np.mean(sw))
+    # copy u -> u* 48 B, right side 120 B, per sweep 104 B (two colour passes) + residual 64 B
+    algo = (48 + 120 + s * (104 + 64)) * N
+    fl.close()
+    return dict(workload=f"predictor_3d_{nc}: smooth drop, rho 1/1e-3, mu 1e-2/1e-4, dt 5e-5, rtol 1e-12",
+                ms_per_call=round(1e3 * secs, 3), sweeps=s,
+                algorithmic_bytes=algo, achieved_GBs=round(algo / secs / 1e9, 1),
+                frac_hbm=round(algo / secs / 1e9 / HBM_PEAK_GBS, 4))
+
+
 def bench_2d_c4_nn(ib, torch, n=512, steps=48, train_iters=300):
     """Learned warm start: oscillating drop (mode 2, amplitude 0.1), projection-only
     dynamics; the network is trained on pairs the multigrid generates and judged
@@ -379,6 +461,8 @@ def main():
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D workloads (C2, learned warm start)")
     ap.add_argument("--no-nn3d", action="store_true", help="skip the 3D learned warm start")
     ap.add_argument("--nn3d-iters", type=int, default=60, help="training iterations of the 3D network")
+    ap.add_argument("--no-flow", action="store_true",
+                    help="skip the full 2D flow steps and the 3D momentum predictor")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MB (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -488,6 +572,11 @@ def main():
         line["c2_2d"] = bench_2d_c2(ib, torch)
         log("== 2D 512^2 learned warm start")
         line["nn_2d"] = bench_2d_c4_nn(ib, torch)
+    if not args.no_flow:
+        log("== 2D full flow steps: Table osc oscillating drop at h = 0.01")
+        line["flow_2d_osc"] = bench_flow_osc(ib, torch)
+        log(f"== momentum predictor at {args.size}^3")
+        line["predictor_3d"] = bench_predictor_3d(ib, torch, args.size)
     if not args.no_cpu_baseline:
         log("== CPU oracle baseline (bounded sample)")
         line["cpu_baseline"] = cpu_baseline(wl, variants[f"fp64_cold_{names[head_k]}"]["mean_cycles"],
