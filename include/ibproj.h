@@ -338,6 +338,37 @@ int flow_step(ib_ctx* ctx, ib_flow* f, mg_handle* m, const ib_params* prm,
               void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Axisymmetric projection step (Section 2.1: the same discretisation in
+ * cylindrical coordinates; eq curv_ax; the static drop of Section 5.1).
+ * The grid g (dim 2, n = {nr, nz}) is the meridian half plane r in [0, nr h],
+ * z in [0, nz h], periodic in z; arrays nz x nr with r fastest. u_r lives on
+ * the face at r = i h: face column 0 is the axis and (one period on) the
+ * outer wall, and holds u_r = 0. With r_i = i h, r_c = (i + 1/2) h:
+ *   b_c = r_c div(u_star/dt + beta F) = (r_{i+1} w_r(i+1) - r_i w_r(i))/h
+ *                                   + r_c (w_z(k+1) - w_z(k))/h, mean removed,
+ *   (1/h^2) sum_faces beta'_f (p_nb - p_c) = b with beta'_r = r_i beta_r,
+ *   beta'_z = r_c beta_z (solved by the mg handle, set up for g),
+ *   u = u_star + dt beta (F - grad p), u_r = 0 on face column 0.
+ * The interface is given as the meridian curve mirrored about the axis: a
+ * closed counter-clockwise polyline in a doubled plane x in [0, 2 nr h] whose
+ * axis is x = nr h (X_host, n_markers points, advanced by dt U and relocated
+ * on the least-squares B-spline like a 2D curve). sigma kappa adds the
+ * azimuthal curvature -n_r / r to the in-plane one (eq curv_ax; r = x - nr h,
+ * n toward the drop; on the axis it equals the in-plane one). H and the
+ * irrotational face force are built on the doubled plane and copied to the
+ * half plane. The handle holds a context for each plane. */
+typedef struct ib_axi ib_axi;
+int  ib_axi_create(const ib_grid* g, int max_markers, ib_axi** out);
+void ib_axi_destroy(ib_axi* a);
+/* st->u_star: the half-plane velocity (u_r, u_z); st->p_prev with WS_PREV;
+ * out: p, u (may alias u_star), U (n_markers x 2, doubled-plane marker
+ * velocities) required; H, F (half plane), b, fs_host optional. Spreading is
+ * irrotational only; warm start WS_ZERO or WS_PREV. Syncs as project_step.
+ * Errors: as project_step. */
+int  axi_project_step(ib_axi* a, mg_handle* m, const ib_params* prm, ib_state* st,
+                      ib_outputs* out, void* stream);
+
+/* ---------------------------------------------------------------------------
  * a3 -- host FP64 least-squares B-spline relocation (Section 4), 2D closed
  * curve of n markers. X, U: host n*2. Advances X* = X + dt U, fits a
  * periodic cubic B-spline (knot spacing L/round(L/1.5h), at least 7 spans)

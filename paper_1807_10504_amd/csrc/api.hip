@@ -196,13 +196,22 @@ int spread_impl(Ctx* c, const ib_surface* s, int mode, double* const F[3], doubl
 // and relocated on the least-squares B-spline on the host; X_host is updated
 // in place and s points at the relocated device copies with their force data.
 int relocate_2d(Ctx* c, const ib_params* prm, ib_state* stt, const double* U_dev, double* fs_host,
-                ib_surface* s, hipStream_t st) {
+                ib_surface* s, hipStream_t st, double axis_x) {
     const int n = s->n_markers;
     std::vector<double> U(2 * (size_t)n), Xn(2 * (size_t)n), fs(n), ds(n), nr(2 * (size_t)n);
     IB_HIP(hipMemcpyAsync(U.data(), U_dev, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, st));
     IB_HIP(hipStreamSynchronize(st));
     IB_TRY(ib_relocate_bspline(n, stt->X_host, U.data(), prm->dt, c->d.h, prm->sigma, Xn.data(),
                                fs.data(), ds.data(), nr.data()));
+    if (std::isfinite(axis_x)) {
+        // a meridian curve mirrored about the axis x = axis_x: add the azimuthal
+        // curvature -n_r / r (eq curv_ax), equal to the in-plane one on the axis
+        const double h = c->d.h;
+        for (int k = 0; k < n; ++k) {
+            const double r = Xn[2 * k] - axis_x;
+            fs[k] += std::fabs(r) < 1e-8 * h ? fs[k] : prm->sigma * (-nr[2 * k] / r);
+        }
+    }
     std::memcpy(stt->X_host, Xn.data(), sizeof(double) * 2 * n);
     if (fs_host) std::memcpy(fs_host, fs.data(), sizeof(double) * n);
     IB_HIP(hipMemcpyAsync(c->mX, Xn.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice, st));
@@ -307,7 +316,7 @@ extern "C" int project_step(ib_ctx* c, mg_handle* m, const ib_params* prm, ib_st
     // a2: marker velocities
     IB_TRY(launch_interp(c, stt->u_star, &s, out->U, st));
     // a3: 2D marker advance and least-squares relocation on the host
-    if (dim == 2) IB_TRY(relocate_2d(c, prm, stt, out->U, out->fs_host, &s, st));
+    if (dim == 2) IB_TRY(relocate_2d(c, prm, stt, out->U, out->fs_host, &s, st, NAN));
     // a4, a5: Heaviside and face force
     double* H = out->H ? out->H : c->H;
     double* F[3];

@@ -152,8 +152,10 @@ int device_sum(const double* partials_in, int n, double* out_dev, hipStream_t st
 
 // pieces of the step shared by project_step and flow_step (api.hip)
 int spread_impl(Ctx* c, const ib_surface* s, int mode, double* const F[3], double* H, hipStream_t st);
+// axis_x: NaN, or the axis of a mirrored axisymmetric meridian curve (adds
+// the azimuthal curvature to sigma kappa)
 int relocate_2d(Ctx* c, const ib_params* prm, ib_state* stt, const double* U_dev, double* fs_host,
-                ib_surface* s, hipStream_t st);
+                ib_surface* s, hipStream_t st, double axis_x);
 int coefficients_and_hierarchy(Ctx* c, mg_handle* m, const ib_params* prm, const double* H,
                                hipStream_t st);
 int solve_and_update(Ctx* c, mg_handle* m, const ib_params* prm, ib_state* stt, ib_outputs* out,

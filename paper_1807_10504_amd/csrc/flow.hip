@@ -473,7 +473,7 @@ extern "C" int flow_step(ib_ctx* ctx, ib_flow* f, mg_handle* m, const ib_params*
     }
     // markers: interpolation of u^n, advance and relocation
     IB_TRY(launch_interp(c, stt->u_star, &s, out->U, st));
-    IB_TRY(relocate_2d(c, prm, stt, out->U, out->fs_host, &s, st));
+    IB_TRY(relocate_2d(c, prm, stt, out->U, out->fs_host, &s, st, NAN));
     // H^{n+1} and the face force
     double* H = out->H ? out->H : c->H;
     double* F[3];

@@ -30,7 +30,8 @@ EXPORTS = ("ib_create", "ib_destroy", "ib_bin_markers", "ib_interp", "ib_spread"
            "ib_nn_train_step",
            "ib_diagnostics", "ib_profile_enable", "ib_profile_reset", "ib_profile_read",
            "ib_advection", "ib_viscous", "ib_flow_create", "ib_flow_destroy", "ib_flow_reset",
-           "ib_predict", "flow_step", "ib_last_error")
+           "ib_predict", "flow_step", "ib_axi_create", "ib_axi_destroy", "axi_project_step",
+           "ib_last_error")
 
 PROF_KINDS = ("smooth64", "smooth32", "restrict64", "restrict32", "prolong64", "prolong32", "resid",
               "sweep64", "sweep32", "sweep64_rho", "sweep_zero")
@@ -156,6 +157,9 @@ def load(path: str = LIB_PATH):
         "ib_predict": (i32, [vp, vp * 3, vp, vp, vp, f64, f64, i32, vp * 3, P(FlowStats), vp]),
         "flow_step": (i32, [vp, vp, vp, P(Params), P(FlowParams), P(State), P(Outputs),
                             P(FlowStats), vp]),
+        "ib_axi_create": (i32, [P(Grid), i32, P(vp)]),
+        "ib_axi_destroy": (None, [vp]),
+        "axi_project_step": (i32, [vp, vp, P(Params), P(State), P(Outputs), vp]),
         "ib_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -482,6 +486,50 @@ class Flow:
                                    _dptr(rho_np1, torch.float64), _dptr(mu, torch.float64), dt, rtol,
                                    int(max_sweeps), _vec3(u_star, torch.float64), C.byref(fs), _stream()))
         return u_star, fs.as_dict()
+
+
+class Axisym:
+    """Axisymmetric projection on the meridian half plane (nr x nz cells, spacing h).
+    Markers are the meridian curve mirrored about the axis, closed and counter-
+    clockwise, in a doubled plane whose axis is x = nr h."""
+
+    def __init__(self, nr, nz, h, max_markers):
+        self.lib = load()
+        self.nr, self.nz, self.h = nr, nz, float(h)
+        self.dim = 2
+        self.shape = (nz, nr)
+        self.grid = make_grid(2, (nr, nz), h)
+        self.ptr = C.c_void_p()
+        _check(self.lib.ib_axi_create(C.byref(self.grid), int(max_markers), C.byref(self.ptr)))
+
+    def close(self):
+        if self.ptr:
+            self.lib.ib_axi_destroy(self.ptr)
+            self.ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def project_step(self, mg: "Multigrid", params: dict, u_star, X_host, p_prev=None, out=None):
+        """One axisymmetric projection step; X_host (numpy, N x 2) is advanced and
+        relocated in place. Returns the outputs dict (half-plane fields)."""
+        import torch
+        prm = Context._params(params, p_prev)
+        st = State()
+        st.u_star = _vec3(u_star, torch.float64)
+        st.p_prev = _dptr(p_prev, torch.float64)
+        st.surf = Surface()
+        st.surf.n_markers = int(X_host.shape[0])
+        st.X_host = _hptr(X_host)
+        st.nn = None
+        out, o = Context._outputs(self, out, int(X_host.shape[0]))
+        rc = self.lib.axi_project_step(self.ptr, mg.ptr, C.byref(prm), C.byref(st), C.byref(o), _stream())
+        out["stats"] = o.stats.as_dict()
+        _check(rc)
+        return out
 
 
 class Multigrid:

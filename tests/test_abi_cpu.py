@@ -19,7 +19,7 @@ def _declared():
     txt = open(os.path.join(ROOT, "include", "ibproj.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     names = set(re.findall(r"\b([a-z_0-9]+)\s*\(", txt))
-    return {n for n in names if n.startswith(("ib_", "mg_", "project_", "flow_"))}
+    return {n for n in names if n.startswith(("ib_", "mg_", "project_", "flow_", "axi_"))}
 
 
 def test_library_exports_every_declared_symbol():
