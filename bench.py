@@ -268,6 +268,66 @@ def bench_flow_osc(ib, torch):
         paper_new_scheme_h001=dict(period=0.2346, discrepancy_percent=1.75))
 
 
+def bench_static_tables(ib, torch, reps=3):
+    """Tables staticdrop_2d and staticdrop_axis of Section 5.1: a drop of diameter 0.4
+    (2D: box centre; axisymmetric: on the axis), rho 1 / 0.01, sigma = 1, one projection
+    step of 1e-3 from rest, at dx = 0.02 ... 0.00125. Box 1.28 (2D) and 0.64 x 1.28
+    (meridian half plane), periodic; markers about 0.63 dx apart. Reports |dP - exact|
+    beside the paper's new-scheme column and the step time."""
+    from paper_1807_10504_amd import workloads as W
+    dxs = [0.02, 0.01, 0.005, 0.0025, 0.00125]
+    paper_2d = [1.1082e-3, 4.1935e-4, 5.5086e-4, 2.2961e-4, 1.2822e-4]
+    paper_ax = [4.0890e-3, 1.3275e-3, 1.2220e-3, 4.8848e-4, 2.2793e-4]
+    rows = []
+    for dx, p2, pa in zip(dxs, paper_2d, paper_ax):
+        nm = int(round(2 * np.pi * 0.2 / (0.63 * dx))) // 4 * 4
+        prm = dict(rho_in=1.0, rho_out=0.01, sigma=1.0, dt=1e-3, rtol=1e-10, warm_start=ib.WS_ZERO)
+        # 2D
+        n = int(round(1.28 / dx))
+        ctx = ib.Context(2, (n, n), dx, max_markers=nm)
+        mg = ib.Multigrid(2, (n, n), dx, krylov=1)
+        zero = [torch.zeros((n, n), dtype=torch.float64, device="cuda") for _ in range(2)]
+        times = []
+        for _ in range(reps):
+            X = W.circle_markers(nm, 0.2, centre=(0.64, 0.64))
+            out = {"H": torch.empty((n, n), dtype=torch.float64, device="cuda")}
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = ctx.project_step(mg, prm, zero, X_host=X, out=out)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        e2 = abs(ctx.diagnostics(p=out["p"], H=out["H"])["dP"] - 5.0)
+        ms2 = 1e3 * min(times)
+        ctx.close()
+        mg.close()
+        # axisymmetric
+        nr = int(round(0.64 / dx))
+        ax = ib.Axisym(nr, 2 * nr, dx, max_markers=nm)
+        mg = ib.Multigrid(2, (nr, 2 * nr), dx, krylov=1)
+        zero = [torch.zeros((2 * nr, nr), dtype=torch.float64, device="cuda") for _ in range(2)]
+        times = []
+        for _ in range(reps):
+            X = W.circle_markers(nm, 0.2, centre=(nr * dx, nr * dx))
+            out = {"H": torch.empty((2 * nr, nr), dtype=torch.float64, device="cuda")}
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = ax.project_step(mg, prm, zero, X, out=out)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        hc = ib.Context(2, (nr, 2 * nr), dx, max_markers=16)
+        ea = abs(hc.diagnostics(p=out["p"], H=out["H"])["dP"] - 10.0)
+        msa = 1e3 * min(times)
+        ax.close()
+        mg.close()
+        hc.close()
+        rows.append(dict(dx=dx, markers=nm, err_2d=float(f"{e2:.4e}"), paper_new_2d=p2, ms_2d=round(ms2, 3),
+                         err_axis=float(f"{ea:.4e}"), paper_new_axis=pa, ms_axis=round(msa, 3)))
+        log(f"  dx {dx}: 2D |dP-5| {e2:.3e} (paper {p2}), axis |dP-10| {ea:.3e} (paper {pa})")
+    return dict(workload="Tables staticdrop_2d / staticdrop_axis: D = 0.4, rho 1/0.01, sigma 1, one step "
+                         "of 1e-3 from rest; 2D box 1.28, axisymmetric half plane 0.64 x 1.28, periodic; "
+                         "flexible-CG projection to 1e-10", rows=rows)
+
+
 def bench_predictor_3d(ib, torch, nc=256, calls=5):
     """The momentum predictor alone at nc^3 (FP64): a smooth drop of radius 0.3 with
     densities 1/1e-3 and viscosities 1e-2/1e-4, seeded velocities of size 0.1,
@@ -575,6 +635,8 @@ def main():
     if not args.no_flow:
         log("== 2D full flow steps: Table osc oscillating drop at h = 0.01")
         line["flow_2d_osc"] = bench_flow_osc(ib, torch)
+        log("== static drop tables (2D and axisymmetric)")
+        line["static_tables"] = bench_static_tables(ib, torch)
         log(f"== momentum predictor at {args.size}^3")
         line["predictor_3d"] = bench_predictor_3d(ib, torch, args.size)
     if not args.no_cpu_baseline:
