@@ -120,3 +120,165 @@ def project_step(nr, nz, h, rho_in, rho_out, sigma, dt, u_star, Xd, rtol=1e-10, 
     out = project(u_star, H, F, rho_in, rho_out, dt, h, p_prev=p_prev, rtol=rtol)
     out.update(U=U, X=Xn, fs=ft, H=H, F=F)
     return out
+
+
+# ----------------------------------------------------------------------------
+# Momentum predictor in the meridian plane (eq ns1_new with eqs ad_bf, cr_ni
+# written on the annular control volumes; no swirl)
+# ----------------------------------------------------------------------------
+# Control volumes (per radian): u_r of face (i, k) spans r in [r_i - h/2,
+# r_i + h/2], volume r_i h^2; u_z of face (i, k) is the cell's column, volume
+# r_c h^2. Fluxes through each side carry its radius as area factor.
+#   C_r = [r_c(i) rho(i) ur_c(i)^2 - r_c(i-1) rho(i-1) ur_c(i-1)^2] / (r_i h)
+#         + [rho_e uz_e ur_e |top - |bottom] / h,
+#   C_z = [r_{i+1} rho_e ur_e uz_e |right - r_i rho_e ur_e uz_e |left] / (r_c h)
+#         + [rho(k) uz_c(k)^2 - rho(k-1) uz_c(k-1)^2] / h,
+# with cell means ur_c(i) = (u_r(i) + u_r(i+1))/2, uz_c(k) = (u_z(k) + u_z(k+1))/2
+# and edge values the means of the two faces meeting there (rho_e: the four
+# cells around the edge). The viscous stress is the vector Laplacian form of
+# div(mu grad u) per component, with the hoop term of u_r:
+#   D_r = [r_c(i) mu(i) (u_r(i+1) - u_r(i)) - r_c(i-1) mu(i-1) (u_r(i) - u_r(i-1))] / (r_i h^2)
+#         + [mu_e (u_r(k+1) - u_r(k)) |top - mu_e (u_r(k) - u_r(k-1)) |bottom] / h^2
+#         - mu_f u_r / r_i^2,       mu_f = (mu(i-1) + mu(i)) / 2,
+#   D_z = [r_{i+1} mu_e (u_z(i+1) - u_z(i)) |right - r_i mu_e (u_z(i) - u_z(i-1)) |left] / (r_c h^2)
+#         + [mu(k) (u_z(k+1) - u_z(k)) - mu(k-1) (u_z(k) - u_z(k-1))] / h^2.
+# Boundaries: u_r = 0 on the axis and the outer wall (face column 0); the outer
+# wall is free of shear (the right edge of the last column carries no D_z flux);
+# the axis edges have zero radius. Readings: the paper only says the planar
+# schemes are used in cylindrical coordinates.
+def advection(u, rho, h):
+    ur, uz = u
+    nz, nr = ur.shape
+    ri, rc = radii(nr, h)
+    R = lambda a, s: np.roll(a, -s, axis=1)      # value at i + s
+    Z = lambda a, s: np.roll(a, -s, axis=0)      # value at k + s
+    # C_r on face (i, k)
+    urc = 0.5 * (ur + R(ur, 1))                  # cell i mean (wall face of the last column is 0)
+    rcv = rc[None, :]
+    flux_c = rcv * rho * urc * urc               # at cell i
+    radial = (flux_c - R(flux_c, -1)) / np.where(ri > 0, ri, 1.0)[None, :]
+    # top edge of face (i, k): between cells (i-1, k), (i, k), (i-1, k+1), (i, k+1)
+    uz_e = 0.5 * (Z(uz, 1) + Z(R(uz, -1), 1))
+    ur_e = 0.5 * (ur + Z(ur, 1))
+    rho_e = 0.25 * (rho + R(rho, -1) + Z(rho, 1) + Z(R(rho, -1), 1))
+    ftop = rho_e * uz_e * ur_e
+    Cr = (radial + ftop - Z(ftop, -1)) / h
+    Cr[:, 0] = 0.0
+    # C_z on face (i, k): right edge between cells (i, k-1), (i+1, k-1), (i, k), (i+1, k)
+    ur_e2 = 0.5 * (R(ur, 1) + Z(R(ur, 1), -1))
+    uz_e2 = 0.5 * (uz + R(uz, 1))
+    rho_e2 = 0.25 * (rho + R(rho, 1) + Z(rho, -1) + Z(R(rho, 1), -1))
+    rip = (ri + h)[None, :]
+    fr = rip * rho_e2 * ur_e2 * uz_e2            # right edge (zero at the wall: u_r = 0 there)
+    fl = R(fr, -1) * (ri > 0)[None, :]           # left edge = right edge of column i - 1; zero on the axis
+    uzc = 0.5 * (uz + Z(uz, 1))
+    fz = rho * uzc * uzc
+    Cz = ((fr - fl) / rcv + fz - Z(fz, -1)) / h
+    return [Cr, Cz]
+
+
+def _visc_coefs(mu, h):
+    """Per component the coefficients (c_lo, c_hi) along r and z and the
+    diagonal extra term, such that D x = sum c_hi (x_hi - x) - c_lo (x - x_lo) - extra x."""
+    nz, nr = mu.shape
+    ri, rc = radii(nr, h)
+    R = lambda a, s: np.roll(a, -s, axis=1)
+    Z = lambda a, s: np.roll(a, -s, axis=0)
+    rsafe = np.where(ri > 0, ri, 1.0)[None, :]
+    h2 = h * h
+    # u_r
+    r_hi = rc[None, :] * mu / (rsafe * h2)
+    r_lo = R(rc[None, :] * mu, -1) / (rsafe * h2)
+    e_top = 0.25 * (mu + R(mu, -1) + Z(mu, 1) + Z(R(mu, -1), 1))
+    z_hi = e_top / h2
+    z_lo = Z(e_top, -1) / h2
+    mu_f = 0.5 * (mu + R(mu, -1))
+    extra = mu_f / (rsafe * rsafe)
+    cr = dict(r=(r_lo, r_hi), z=(z_lo, z_hi), extra=extra)
+    # u_z
+    e_right = 0.25 * (mu + R(mu, 1) + Z(mu, -1) + Z(R(mu, 1), -1))
+    last = np.zeros(nr, dtype=bool)
+    last[-1] = True
+    rhi = np.where(last[None, :], 0.0, (ri + h)[None, :] * e_right) / (rc[None, :] * h2)
+    rlo = np.where((ri > 0)[None, :], ri[None, :] * R(e_right, -1), 0.0) / (rc[None, :] * h2)
+    cz = dict(r=(rlo, rhi), z=(Z(mu, -1) / h2, mu / h2), extra=np.zeros_like(mu))
+    return cr, cz
+
+
+def viscous(u, mu, h):
+    R = lambda a, s: np.roll(a, -s, axis=1)
+    Z = lambda a, s: np.roll(a, -s, axis=0)
+    out = []
+    for x, co in zip(u, _visc_coefs(mu, h)):
+        (rlo, rhi), (zlo, zhi) = co["r"], co["z"]
+        D = (rhi * (R(x, 1) - x) - rlo * (x - R(x, -1)) + zhi * (Z(x, 1) - x) - zlo * (x - Z(x, -1))
+             - co["extra"] * x)
+        out.append(D)
+    out[0][:, 0] = 0.0
+    return out
+
+
+def _matrix(co, shape):
+    import scipy.sparse as sp
+    nz, nr = shape
+    N = nz * nr
+    idx = np.arange(N).reshape(shape)
+    (rlo, rhi), (zlo, zhi) = co["r"], co["z"]
+    rows = [idx] * 5
+    cols = [idx, np.roll(idx, -1, axis=1), np.roll(idx, 1, axis=1), np.roll(idx, -1, axis=0),
+            np.roll(idx, 1, axis=0)]
+    vals = [-(rhi + rlo + zhi + zlo + co["extra"]), rhi, rlo, zhi, zlo]
+    return sp.csr_matrix((np.concatenate([v.ravel() for v in vals]),
+                          (np.concatenate([r.ravel() for r in rows]),
+                           np.concatenate([c.ravel() for c in cols]))), shape=(N, N))
+
+
+def predict(u, rho_n, rho_np1, mu, dt, h, adv_prev=None):
+    """u* of eq ns1_new on the meridian plane (Adams-Bashforth advection, Crank-
+    Nicolson viscous stress, system solved exactly); u_r stays zero on face
+    column 0. Returns (u_star, C(u^n))."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    adv = advection(u, rho_n, h)
+    ab = adv if adv_prev is None else [1.5 * a - 0.5 * b for a, b in zip(adv, adv_prev)]
+    vis = viscous(u, mu, h)
+    shape = u[0].shape
+    cos = _visc_coefs(mu, h)
+    out = []
+    for d in range(2):
+        ax = 1 if d == 0 else 0
+        rf = 0.5 * (rho_np1 + np.roll(rho_np1, 1, axis=ax))
+        g = rf / dt * u[d] - ab[d] + 0.5 * vis[d]
+        M = sp.diags(rf.ravel() / dt) - 0.5 * _matrix(cos[d], shape)
+        if d == 0:
+            # face column 0 is fixed at zero: identity rows, and no coupling into it
+            fix = np.zeros(shape, dtype=bool)
+            fix[:, 0] = True
+            f = fix.ravel()
+            M = M.tolil()
+            M[f, :] = 0.0
+            M = M.tocsr()
+            M = M + sp.diags(f.astype(np.float64))
+            g = np.where(fix, 0.0, g)
+        out.append(spla.spsolve(M.tocsc(), g.ravel()).reshape(shape))
+    return out, adv
+
+
+def flow_step(nr, nz, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, Xd, H_prev, adv_prev=None,
+              p_prev=None, rtol=1e-10):
+    """One step of the full axisymmetric method: markers advanced with u^n and
+    relocated (eq curv_ax), H^{n+1} and F, rho^n from H_prev, the predictor, the
+    projection of u*."""
+    ud = mirror_velocity(u, nr)
+    U = transfer.interp(ud, Xd, h)
+    Xn, fs, ds, nrm = bspline.relocate([tuple(x) for x in Xd], [tuple(v) for v in U], dt, h, sigma)
+    Xn, fs, nrm = np.array(Xn), np.array(fs), np.array(nrm)
+    ft = curvature_total(Xn, nrm, fs, sigma, nr * h, h)
+    H, F = interface(Xn, ft, nr, nz, h)
+    rho_n = poisson.density(H_prev, rho_in, rho_out)
+    rho1 = poisson.density(H, rho_in, rho_out)
+    mu = poisson.density(H, mu_in, mu_out)
+    u_star, adv = predict(u, rho_n, rho1, mu, dt, h, adv_prev)
+    out = project(u_star, H, F, rho_in, rho_out, dt, h, p_prev=p_prev, rtol=rtol)
+    out.update(U=U, X=Xn, fs=ft, H=H, F=F, u_star=u_star, adv=adv)
+    return out

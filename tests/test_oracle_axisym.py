@@ -88,3 +88,113 @@ def test_static_drop_axis_table_band():
     print(f"axisymmetric static drop at dx = {h}: |dP - 10| = {err:.3e} (paper: new {g['new'][0]}, "
           f"conventional {g['conventional'][0]})")
     assert err < 5.0 * max(g["conventional"])
+
+
+# ---------------------------------------------------------------------------
+# momentum predictor on the meridian plane
+# ---------------------------------------------------------------------------
+def _tg_axi(n):
+    """A smooth divergence-free axisymmetric field from a stream function and a
+    smooth density: the largest difference between its discrete advection and
+    the exact one (sympy), averaged over each control volume."""
+    import sympy as S
+    r, z = S.symbols("r z")
+    psi = r ** 2 * (1 - r) ** 2 * S.sin(2 * S.pi * z)
+    ur = -S.diff(psi, z) / r
+    uz = S.diff(psi, r) / r
+    rho = 1 + S.Rational(3, 10) * S.cos(S.pi * r) * S.sin(2 * S.pi * z)
+    Cr = S.diff(r * rho * ur * ur, r) / r + S.diff(rho * ur * uz, z)
+    Cz = S.diff(r * rho * ur * uz, r) / r + S.diff(rho * uz * uz, z)
+    f = {k: S.lambdify((r, z), S.simplify(v), "numpy") for k, v in
+         dict(ur=ur, uz=uz, rho=rho, Cr=Cr, Cz=Cz).items()}
+    h = 1.0 / n
+    k, i = np.indices((n, n))
+    rf, zc = i * h, (k + 0.5) * h          # u_r faces
+    rc, zf = (i + 0.5) * h, k * h          # u_z faces
+    rsafe = np.where(rf > 0, rf, 1.0)
+    u = [np.where(rf > 0, f["ur"](rsafe, zc), 0.0), f["uz"](rc, zf)]
+    rho_c = f["rho"]((i + 0.5) * h, (k + 0.5) * h)
+    C = axisym.advection(u, rho_c, h)
+    # a finite volume of an annulus holds the r-weighted mean over its radial
+    # extent (on the axis column its centroid sits at 2h/3, not h/2): compare
+    # with that mean (4-point Gauss-Legendre in r)
+    xg, wg = np.polynomial.legendre.leggauss(4)
+
+    def rmean(F, lo, zz):
+        num = sum(w * (lo + 0.5 * h * (1 + x)) * F(lo + 0.5 * h * (1 + x), zz) for x, w in zip(xg, wg))
+        den = sum(w * (lo + 0.5 * h * (1 + x)) for x, w in zip(xg, wg))
+        return num / np.where(den == 0.0, 1.0, den)
+    er = np.abs(C[0] - rmean(f["Cr"], rf - 0.5 * h, zc))
+    ez = np.abs(C[1] - rmean(f["Cz"], rc - 0.5 * h, zf))
+    far = (slice(None), slice(n // 4, None))
+    near = (slice(None), slice(1, n // 4))
+    return max(er[far].max(), ez[far].max()), max(er[near].max(), ez[near].max())
+
+
+def test_axi_advection_convergence():
+    """Second order away from the axis (r >= 1/4); next to the axis the axial
+    fluxes use point values at the face radius while the annular volumes hold
+    r-weighted means, an O(h) difference in the first columns: first order
+    there."""
+    (f1, n1), (f2, n2) = _tg_axi(32), _tg_axi(64)
+    assert 3.5 < f1 / f2 < 4.5, (f1, f2)
+    assert n1 / n2 > 1.6, (n1, n2)
+
+
+def test_axi_z_momentum_conserved():
+    rng = np.random.default_rng(11)
+    nz, nr, h = 12, 10, 0.1
+    u = [rng.standard_normal((nz, nr)), rng.standard_normal((nz, nr))]
+    u[0][:, 0] = 0.0
+    rho = 0.2 + rng.random((nz, nr))
+    C = axisym.advection(u, rho, h)
+    _, rc = axisym.radii(nr, h)
+    assert abs(np.sum(rc[None, :] * C[1])) <= 1e-12 * np.sum(np.abs(rc[None, :] * C[1]))
+
+
+def test_axi_viscous_exact_cases():
+    nz, nr, h, mu = 6, 16, 0.05, 0.3
+    ri, rc = axisym.radii(nr, h)
+    m = np.full((nz, nr), mu)
+    # u_z = r^2: (1/r) d/dr (r d/dr r^2) = 4, exact on the annular stencil
+    D = axisym.viscous([np.zeros((nz, nr)), np.broadcast_to(rc ** 2, (nz, nr)).copy()], m, h)
+    assert np.abs(D[1][:, :-1] - 4 * mu).max() <= 1e-11
+    # u_r = r: the vector Laplacian (1/r)(r u_r')' - u_r / r^2 vanishes (hoop term)
+    D = axisym.viscous([np.broadcast_to(ri, (nz, nr)).copy(), np.zeros((nz, nr))], m, h)
+    assert np.abs(D[0][:, 1:-1]).max() <= 1e-11
+
+
+def test_axi_predictor_euler_and_crank_nicolson():
+    rng = np.random.default_rng(12)
+    nz, nr, h, dt = 8, 12, 0.1, 1e-3
+    u = [rng.standard_normal((nz, nr)), rng.standard_normal((nz, nr))]
+    u[0][:, 0] = 0.0
+    rho_n = 0.5 + rng.random((nz, nr))
+    rho1 = 0.5 + rng.random((nz, nr))
+    us, adv = axisym.predict(u, rho_n, rho1, np.zeros((nz, nr)), dt, h)
+    for d in range(2):
+        rf = 0.5 * (rho1 + np.roll(rho1, 1, axis=1 if d == 0 else 0))
+        euler = u[d] - dt * adv[d] / rf
+        if d == 0:
+            euler[:, 0] = 0.0
+        assert np.abs(us[d] - euler).max() <= 1e-13 * np.abs(u[d]).max()
+    # an axial shear u_z(r) has no advection; with uniform rho and mu the
+    # predictor multiplies an eigenvector of the radial operator by the
+    # Crank-Nicolson factor
+    rho, mu, dt = 0.8, 0.05, 0.05
+    ones = np.ones((nz, nr))
+    probe = [np.zeros((nz, nr)), np.zeros((nz, nr))]
+    L = np.zeros((nr, nr))
+    for j in range(nr):
+        probe[1][:] = 0.0
+        probe[1][:, j] = 1.0
+        L[:, j] = axisym.viscous(probe, mu * ones, h)[1][0]
+    lam, V = np.linalg.eig(L)
+    q = int(np.argsort(lam.real)[3])
+    v = V[:, q].real
+    uz = np.broadcast_to(v, (nz, nr)).copy()
+    us, adv = axisym.predict([np.zeros((nz, nr)), uz], rho * ones, rho * ones, mu * ones, dt, h)
+    assert np.abs(adv[1]).max() <= 1e-13 and np.abs(adv[0]).max() <= 1e-13
+    g = (1 + 0.5 * dt * lam[q].real / rho) / (1 - 0.5 * dt * lam[q].real / rho)
+    assert np.abs(us[1] - g * uz).max() <= 1e-12
+    assert np.abs(us[0]).max() <= 1e-14
