@@ -354,7 +354,7 @@ int flow_step(ib_ctx* ctx, ib_flow* f, mg_handle* m, const ib_params* prm,
  * axis is x = nr h (X_host, n_markers points, advanced by dt U and relocated
  * on the least-squares B-spline like a 2D curve). sigma kappa adds the
  * azimuthal curvature -n_r / r to the in-plane one (eq curv_ax; r = x - nr h,
- * n toward the drop; on the axis it equals the in-plane one). H and the
+ * n toward the drop; within a quarter cell of the axis it is taken equal to the in-plane one). H and the
  * irrotational face force are built on the doubled plane and copied to the
  * half plane. The handle holds a context for each plane. */
 typedef struct ib_axi ib_axi;
@@ -367,6 +367,33 @@ void ib_axi_destroy(ib_axi* a);
  * Errors: as project_step. */
 int  axi_project_step(ib_axi* a, mg_handle* m, const ib_params* prm, ib_state* st,
                       ib_outputs* out, void* stream);
+
+/* Momentum predictor on the meridian plane (eq ns1_new with eqs ad_bf and
+ * cr_ni written on the annular control volumes, no swirl). With r_i = i h,
+ * r_c = (i + 1/2) h, cell means ur_c(i) = (u_r(i) + u_r(i+1))/2,
+ * uz_c(k) = (u_z(k) + u_z(k+1))/2 and edge values the means of the two faces
+ * (four cells for rho and mu) meeting at the edge:
+ *   C_r = [r_c(i) rho ur_c^2 |cell i - |cell i-1] / (r_i h) + [rho u_z u_r |top - |bottom] / h
+ *   C_z = [r rho u_r u_z |right edge - |left edge] / (r_c h) + [rho uz_c^2 |cell k - |cell k-1] / h
+ *   D_r = [r_c mu (u_r(i+1) - u_r(i)) - r_c mu (u_r(i) - u_r(i-1))] / (r_i h^2)
+ *         + [mu_e du_r/dz |top - |bottom] / h - (mu(i-1) + mu(i))/2 u_r / r_i^2
+ *   D_z = [r mu_e du_z/dr |right - |left] / (r_c h^2) + [mu du_z/dz |k - |k-1] / h
+ * u_r = 0 on face column 0 (axis, outer wall); the outer wall is free of
+ * shear; the axis edges have zero radius. The implicit system is solved by
+ * red-black Gauss-Seidel (index sum parity) to ||g - M u*|| <= rtol ||g||,
+ * read after every sweep (syncs). The handle keeps the Adams-Bashforth
+ * history; ib_axi_reset forgets it (and the previous H of axi_flow_step). */
+int  ib_axi_reset(ib_axi* a);
+int  axi_predict(ib_axi* a, const double* const u[2], const double* rho_n, const double* rho_np1,
+                 const double* mu, double dt, double rtol, int max_sweeps, double* const u_star[2],
+                 ib_flow_stats* stats, void* stream);
+/* One step of the full axisymmetric method: markers advanced with u^n
+ * (st->u_star) and relocated (eq curv_ax), H^{n+1} and F, rho^n from the
+ * previous step's H (computed from the incoming markers after create/reset),
+ * predictor, projection of u* into out (p, u, U required; u may alias u^n).
+ * Warm start WS_ZERO or WS_PREV. Errors: as axi_project_step and axi_predict. */
+int  axi_flow_step(ib_axi* a, mg_handle* m, const ib_params* prm, const ib_flow_params* fp,
+                   ib_state* st, ib_outputs* out, ib_flow_stats* fstats, void* stream);
 
 /* ---------------------------------------------------------------------------
  * a3 -- host FP64 least-squares B-spline relocation (Section 4), 2D closed

@@ -205,11 +205,14 @@ int relocate_2d(Ctx* c, const ib_params* prm, ib_state* stt, const double* U_dev
                                fs.data(), ds.data(), nr.data()));
     if (std::isfinite(axis_x)) {
         // a meridian curve mirrored about the axis x = axis_x: add the azimuthal
-        // curvature -n_r / r (eq curv_ax), equal to the in-plane one on the axis
+        // curvature -n_r / r (eq curv_ax). Within a quarter cell of the axis
+        // n_r / r is rounding noise over a tiny radius (a pole marker drifts off
+        // the axis by ~1e-9): take the limit, the in-plane curvature (exact to
+        // O(r^2) for a surface meeting the axis square)
         const double h = c->d.h;
         for (int k = 0; k < n; ++k) {
             const double r = Xn[2 * k] - axis_x;
-            fs[k] += std::fabs(r) < 1e-8 * h ? fs[k] : prm->sigma * (-nr[2 * k] / r);
+            fs[k] += std::fabs(r) < 0.25 * h ? fs[k] : prm->sigma * (-nr[2 * k] / r);
         }
     }
     std::memcpy(stt->X_host, Xn.data(), sizeof(double) * 2 * n);

@@ -31,6 +31,7 @@ EXPORTS = ("ib_create", "ib_destroy", "ib_bin_markers", "ib_interp", "ib_spread"
            "ib_diagnostics", "ib_profile_enable", "ib_profile_reset", "ib_profile_read",
            "ib_advection", "ib_viscous", "ib_flow_create", "ib_flow_destroy", "ib_flow_reset",
            "ib_predict", "flow_step", "ib_axi_create", "ib_axi_destroy", "axi_project_step",
+           "ib_axi_reset", "axi_predict", "axi_flow_step",
            "ib_last_error")
 
 PROF_KINDS = ("smooth64", "smooth32", "restrict64", "restrict32", "prolong64", "prolong32", "resid",
@@ -160,6 +161,9 @@ def load(path: str = LIB_PATH):
         "ib_axi_create": (i32, [P(Grid), i32, P(vp)]),
         "ib_axi_destroy": (None, [vp]),
         "axi_project_step": (i32, [vp, vp, P(Params), P(State), P(Outputs), vp]),
+        "ib_axi_reset": (i32, [vp]),
+        "axi_predict": (i32, [vp, vp * 2, vp, vp, vp, f64, f64, i32, vp * 2, P(FlowStats), vp]),
+        "axi_flow_step": (i32, [vp, vp, P(Params), P(FlowParams), P(State), P(Outputs), P(FlowStats), vp]),
         "ib_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -528,6 +532,47 @@ class Axisym:
         out, o = Context._outputs(self, out, int(X_host.shape[0]))
         rc = self.lib.axi_project_step(self.ptr, mg.ptr, C.byref(prm), C.byref(st), C.byref(o), _stream())
         out["stats"] = o.stats.as_dict()
+        _check(rc)
+        return out
+
+    def reset(self):
+        _check(self.lib.ib_axi_reset(self.ptr))
+
+    def predict(self, u, rho_n, rho_np1, mu, dt, rtol=1e-12, max_sweeps=200, u_star=None):
+        """u* of the meridian-plane predictor; returns (u_star, stats dict)."""
+        import torch
+        if u_star is None:
+            u_star = [torch.empty(self.shape, dtype=torch.float64, device="cuda") for _ in range(2)]
+        fs = FlowStats()
+        uv = (C.c_void_p * 2)(*[_dptr(x, torch.float64) for x in u])
+        sv = (C.c_void_p * 2)(*[_dptr(x, torch.float64) for x in u_star])
+        _check(self.lib.axi_predict(self.ptr, uv, _dptr(rho_n, torch.float64), _dptr(rho_np1, torch.float64),
+                                    _dptr(mu, torch.float64), dt, rtol, int(max_sweeps), sv, C.byref(fs),
+                                    _stream()))
+        return u_star, fs.as_dict()
+
+    def flow_step(self, mg: "Multigrid", params: dict, u, X_host, p_prev=None, out=None):
+        """One full axisymmetric step (params as Context.flow_step)."""
+        import torch
+        prm = Context._params(params, p_prev)
+        fp = FlowParams()
+        fp.mu_in = params.get("mu_in", 0.0)
+        fp.mu_out = params.get("mu_out", 0.0)
+        fp.rtol = params.get("pred_rtol", 1e-12)
+        fp.max_sweeps = params.get("pred_max_sweeps", 200)
+        st = State()
+        st.u_star = _vec3(u, torch.float64)
+        st.p_prev = _dptr(p_prev, torch.float64)
+        st.surf = Surface()
+        st.surf.n_markers = int(X_host.shape[0])
+        st.X_host = _hptr(X_host)
+        st.nn = None
+        out, o = Context._outputs(self, out, int(X_host.shape[0]))
+        fs = FlowStats()
+        rc = self.lib.axi_flow_step(self.ptr, mg.ptr, C.byref(prm), C.byref(fp), C.byref(st), C.byref(o),
+                                    C.byref(fs), _stream())
+        out["stats"] = o.stats.as_dict()
+        out["flow"] = fs.as_dict()
         _check(rc)
         return out
 

@@ -192,3 +192,13 @@ def test_oscillation_period_formulas_match_printed_values():
     tab = gold["oscillation_period_table_2d"]
     for T, pct in zip(tab["period_new"], tab["discrepancy_new_percent"]):
         assert abs(100 * abs(T - t2) / t2 - pct) < 0.02
+
+
+def test_table_osc_axis_rows_match_eq_aosc_p():
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+    T = gold["oscillation_periods"]["period_axisymmetric"]
+    tab = gold["oscillation_period_table_axis"]
+    for Tn, pct in zip(tab["period_new"], tab["discrepancy_new_percent"]):
+        assert abs(100 * abs(Tn - T) / T - pct) < 0.02
