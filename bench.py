@@ -221,51 +221,78 @@ def bench_2d_c2(ib, torch, steps=200):
     return out
 
 
-def bench_flow_osc(ib, torch):
-    """Full 2D flow steps (markers, H and force, momentum predictor, projection) on the
-    free oscillation of Section 5.2 at h = 0.01 (Table osc): steps/s over the first
-    oscillation cycle and the measured period against eq osc_p and the paper's."""
-    from paper_1807_10504_amd import workloads as W
-    wl = W.oscillating_drop_2d_osc()
-    n, h = wl.n, wl.h
-    prm = dict(rho_in=wl.rho_in, rho_out=wl.rho_out, mu_in=wl.extra["mu_in"], mu_out=wl.extra["mu_out"],
-               sigma=wl.sigma, dt=wl.dt, rtol=1e-10, pred_rtol=1e-12, warm_start=ib.WS_PREV)
-    ctx = ib.Context(2, n, h, max_markers=len(wl.X))
-    mg = ib.Multigrid(2, n, h, krylov=1)
-    fl = ib.Flow(2, n, h)
-    shape = tuple(reversed(n))
-    u = [torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(2)]
-    p = torch.zeros(shape, dtype=torch.float64, device="cuda")
-    X = wl.X.copy()
-    diam = [float(np.ptp(X[:, 0]))]
-    sweeps, cycles = [], []
-    out = {"p": p, "u": u}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(wl.steps):
-        out = ctx.flow_step(mg, fl, prm, u, X, p_prev=p, out=out)
-        diam.append(float(np.ptp(X[:, 0])))
-        sweeps.append(out["flow"]["sweeps"])
-        cycles.append(out["stats"]["cycles"])
-        if k % 1000 == 999:
-            log(f"  flow step {k + 1}/{wl.steps}")
-    torch.cuda.synchronize()
-    secs = time.perf_counter() - t0
-    d = np.array(diam)
+def _osc_period(d, dt):
+    """First return of the diameter signal to its maximum after its first minimum
+    (parabola through the three samples around the discrete maximum)."""
+    d = np.asarray(d)
     kmin = int(np.argmin(d[: len(d) // 2 + 200]))
     kmax = kmin + int(np.argmax(d[kmin:]))
     y0, y1, y2 = d[kmax - 1], d[kmax], d[kmax + 1]
-    T = (kmax + 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2)) * wl.dt
-    T_exact = 2 * np.pi * np.sqrt((wl.rho_in + wl.rho_out) * 0.2 ** 3 / (6 * wl.sigma))
-    return dict(
-        workload=(f"{wl.name}: Table osc drop, R=0.2 stretched by 1.03 (eq osc), 256 markers, rho 1/0.01, "
-                  f"mu 0.01/1e-5, sigma=1, 256^2 periodic box at h=0.01, dt=1e-4, {wl.steps} full steps "
-                  "(AB2 advection + Crank-Nicolson viscosity + irrotational force + FCG projection, WS_PREV)"),
-        steps_per_s=round(wl.steps / secs, 2), ms_per_step=round(1e3 * secs / wl.steps, 3),
-        mean_predictor_sweeps=float(np.mean(sweeps)), mean_cycles=float(np.mean(cycles)),
-        period=round(float(T), 5), period_eq_osc_p=round(float(T_exact), 5),
-        discrepancy_percent=round(100 * abs(T - T_exact) / T_exact, 2),
-        paper_new_scheme_h001=dict(period=0.2346, discrepancy_percent=1.75))
+    return float((kmax + 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2)) * dt)
+
+
+def _osc_run(ib, torch, axis, n, h, dt, steps, markers):
+    """Full flow steps of the Table osc drop (R = 0.2 stretched by 1.03, rho 1/0.01,
+    mu 0.01/1e-5, sigma 1) on an n^2 periodic box (2D) or n x n meridian half plane."""
+    from paper_1807_10504_amd import workloads as W
+    prm = dict(rho_in=1.0, rho_out=0.01, mu_in=0.01, mu_out=1e-5, sigma=1.0, dt=dt, rtol=1e-10,
+               pred_rtol=1e-12, warm_start=ib.WS_PREV)
+    mg = ib.Multigrid(2, (n, n), h, krylov=1)
+    if axis:
+        X = W.ellipse_markers(markers, 0.2, 1.03, centre=(n * h, 0.5 * n * h))
+        solver = ib.Axisym(n, n, h, max_markers=markers)
+        step = lambda u, p, out: solver.flow_step(mg, prm, u, X, p_prev=p, out=out)
+    else:
+        X = W.ellipse_markers(markers, 0.2, 1.03, centre=(0.5 * n * h, 0.5 * n * h))
+        ctx = ib.Context(2, (n, n), h, max_markers=markers)
+        fl = ib.Flow(2, (n, n), h)
+        step = lambda u, p, out: ctx.flow_step(mg, fl, prm, u, X, p_prev=p, out=out)
+    u = [torch.zeros((n, n), dtype=torch.float64, device="cuda") for _ in range(2)]
+    p = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    out = {"p": p, "u": u}
+    diam = [float(np.ptp(X[:, 0]))]
+    sweeps, cycles = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        out = step(u, p, out)
+        diam.append(float(np.ptp(X[:, 0])))
+        sweeps.append(out["flow"]["sweeps"])
+        cycles.append(out["stats"]["cycles"])
+        if k % 2000 == 1999:
+            log(f"  {'axisymmetric' if axis else '2D'} h={h}: flow step {k + 1}/{steps}")
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    return dict(period=round(_osc_period(diam, dt), 5), steps=steps, steps_per_s=round(steps / secs, 2),
+                ms_per_step=round(1e3 * secs / steps, 3), mean_predictor_sweeps=round(float(np.mean(sweeps)), 2),
+                mean_cycles=round(float(np.mean(cycles)), 2))
+
+
+def bench_flow_osc(ib, torch):
+    """Full flow steps (markers, H and force, momentum predictor, projection) on the
+    free oscillation of Section 5.2 (Table osc), 2D and axisymmetric, at h = 0.01
+    and 0.005: steps/s and the first-cycle period against eqs osc_p / aosc_p and
+    the paper's new-scheme values."""
+    T2 = 2 * np.pi * np.sqrt(1.01 * 0.2 ** 3 / 6.0)
+    Ta = 2 * np.pi * np.sqrt((3 * 1.0 + 2 * 0.01) * 0.2 ** 3 / 24.0)
+    res = {}
+    for axis, T, paper in ((False, T2, {0.01: 0.2346, 0.005: 0.2328}), (True, Ta, {0.01: 0.2024})):
+        for h, n, dt, steps, nm in ((0.01, 256, 1e-4, 2600 if not axis else 2300, 256),
+                                    (0.005, 512, 5e-5, 5200 if not axis else 4600, 512)):
+            r = _osc_run(ib, torch, axis, n, h, dt, steps, nm)
+            r["discrepancy_percent"] = round(100 * abs(r["period"] - T) / T, 2)
+            r["exact_period"] = round(float(T), 5)
+            if h in paper:
+                r["paper_new_scheme"] = paper[h]
+            res[f"{'axis' if axis else '2d'}_h{h:g}"] = r
+            log(f"  {'axisymmetric' if axis else '2D'} h={h}: period {r['period']} ({r['discrepancy_percent']} %), "
+                f"{r['steps_per_s']} steps/s")
+    res["workload"] = ("Table osc drop: R=0.2 stretched by 1.03 (eq osc), rho 1/0.01, mu 0.01/1e-5, sigma=1; "
+                       "2D: n^2 periodic box; axisymmetric: n x n meridian half plane (axis, outer wall at "
+                       "r = n h, periodic along the axis); n = 256 at h = 0.01 (dt 1e-4), 512 at h = 0.005 "
+                       "(dt 5e-5); AB2 advection, Crank-Nicolson viscosity, irrotational force, FCG projection "
+                       "warm-started from p_prev; markers 0.5 h apart")
+    return res
 
 
 def bench_static_tables(ib, torch, reps=3):
@@ -633,8 +660,8 @@ def main():
         log("== 2D 512^2 learned warm start")
         line["nn_2d"] = bench_2d_c4_nn(ib, torch)
     if not args.no_flow:
-        log("== 2D full flow steps: Table osc oscillating drop at h = 0.01")
-        line["flow_2d_osc"] = bench_flow_osc(ib, torch)
+        log("== full flow steps: Table osc oscillating drops (2D and axisymmetric)")
+        line["flow_osc"] = bench_flow_osc(ib, torch)
         log("== static drop tables (2D and axisymmetric)")
         line["static_tables"] = bench_static_tables(ib, torch)
         log(f"== momentum predictor at {args.size}^3")

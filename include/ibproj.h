@@ -448,6 +448,8 @@ int ib_diagnostics(ib_ctx* ctx, const double* p, const double* H, const double* 
  *     from cell densities (mg_update_density)
  *   IB_PROF_SWEEP_ZERO -- a single-pass sweep from p = 0 (the first sweep of a
  *     V-cycle whose level starts from zero; p is not read), either precision
+ *   IB_PROF_SWEEP_DOTS -- the float64 density sweep that also takes the
+ *     flexible-CG inner products (the last post-smoothing sweep of the finest level)
  *   IB_PROF_RESTRICT64 / IB_PROF_RESTRICT32 -- residual + restriction
  *   IB_PROF_PROLONG64 / IB_PROF_PROLONG32 -- prolongation + correction
  *   IB_PROF_RESID -- float64 residual norm / defect
@@ -455,7 +457,8 @@ int ib_diagnostics(ib_ctx* ctx, const double* p, const double* H, const double* 
  * Process-wide; not thread safe. */
 enum { IB_PROF_SMOOTH64 = 0, IB_PROF_SMOOTH32, IB_PROF_RESTRICT64, IB_PROF_RESTRICT32,
        IB_PROF_PROLONG64, IB_PROF_PROLONG32, IB_PROF_RESID, IB_PROF_SWEEP64,
-       IB_PROF_SWEEP32, IB_PROF_SWEEP64_RHO, IB_PROF_SWEEP_ZERO, IB_PROF_KINDS };
+       IB_PROF_SWEEP32, IB_PROF_SWEEP64_RHO, IB_PROF_SWEEP_ZERO, IB_PROF_SWEEP_DOTS,
+       IB_PROF_KINDS };
 void ib_profile_enable(int on);
 void ib_profile_reset(void);
 int  ib_profile_read(int kind, long long* launches, double* total_ms);

@@ -49,6 +49,12 @@ struct Level {
     // finest level only: cell densities from which the float64 kernels form
     // the face coefficients themselves (f64.beta is then unused)
     const double* rho = nullptr;
+    // finest level of the float64 density path inside the flexible CG: the
+    // last post-smoothing sweep also leaves the partial inner products of
+    // the preconditioned residual with b (and with dots_q when not null)
+    bool dots_on = false;
+    const double* dots_q = nullptr;
+    double* dots_part = nullptr;
 };
 
 }  // namespace ib
@@ -485,13 +491,18 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
 // written, b, rho) instead of 48 with three stored face arrays; the update is
 // the one above, operand for operand, so the results are bitwise those of
 // the stored-face sweep.
-template <int TX, int TY, int NT, bool ZERO>
+// DOTS: the sweep also leaves per-workgroup partial sums of (b, p_new) and,
+// when qv is not null, (qv, p_new) in part[bid] and part[nwg + bid] (the
+// flexible-CG inner products of the preconditioned residual, taken from the
+// values the black lanes write).
+template <int TX, int TY, int NT, bool ZERO, bool DOTS = false>
 __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const double* __restrict__ pin,
                                                        double* __restrict__ pout,
                                                        const double* __restrict__ bb,
                                                        const double* __restrict__ rho, Dims d,
                                                        double h2, int TZ, int ntx, int nty,
-                                                       int nzc) {
+                                                       int nzc, const double* __restrict__ qv = nullptr,
+                                                       double* __restrict__ part = nullptr) {
     // region of p and rho: the tile and a two-cell halo; b: the one-cell ring
     constexpr int RX = TX + 4, RY = TY + 4, RN = RX * RY;
     constexpr int ZW = RX - 2, ZN = ZW * (RY - 2);
@@ -501,6 +512,8 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const double* __restrict_
     __shared__ double P[4][RN];
     __shared__ double R[4][RN];
     __shared__ double B[2][ZN];
+    __shared__ double red[DOTS ? 2 * (NT / 64) : 1];
+    double acc_b = 0.0, acc_q = 0.0;
     const int nw = ntx * nty * nzc;
     const int bid = blockIdx.x;
     const int w = (nw % 8 == 0) ? (bid % 8) * (nw / 8) + bid / 8 : bid;
@@ -629,6 +642,14 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const double* __restrict_
                 double* o = pout + base + (long)(y - 2) * d.nx + 2 * m;
                 o[par] = v;
                 o[1 - par] = r;
+                if constexpr (DOTS) {
+                    const double* Bk = B[kb & 1] + (y - 1) * ZW;
+                    acc_b += Bk[1 + par + 2 * m] * v + Bk[2 - par + 2 * m] * r;
+                    if (qv) {
+                        const double* qq = qv + base + (long)(y - 2) * d.nx + 2 * m;
+                        acc_q += qq[par] * v + qq[1 - par] * r;
+                    }
+                }
             }
         }
         lds_barrier();
@@ -637,6 +658,27 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const double* __restrict_
     for (int k = z0 - 1; k <= z1; k += 2) {
         step(SA, k);
         step(SB, k + 1);
+    }
+    if constexpr (DOTS) {
+        // fixed-order workgroup sums
+        for (int off = 32; off > 0; off >>= 1) {
+            acc_b += __shfl_xor(acc_b, off);
+            acc_q += __shfl_xor(acc_q, off);
+        }
+        if ((t & 63) == 0) {
+            red[t >> 6] = acc_b;
+            red[NT / 64 + (t >> 6)] = acc_q;
+        }
+        __syncthreads();
+        if (t == 0) {
+            double sb = 0.0, sq = 0.0;
+            for (int i = 0; i < NT / 64; ++i) {
+                sb += red[i];
+                sq += red[NT / 64 + i];
+            }
+            part[bid] = sb;
+            part[nw + bid] = sq;
+        }
     }
 }
 
@@ -1349,6 +1391,134 @@ __global__ __launch_bounds__(CG_NT) void k_cg_dir_apply_rho(const TZ* __restrict
     }
 }
 
+// Residual of a finest level given by densities, restricted to the coarse
+// right side, as a z-march with the tiling of k_cg_dir_apply_rho: p and rho of
+// each plane staged on the tile plus a one-cell ring (three-plane rings,
+// loaded two steps ahead), b read per cell. Each fine residual is formed
+// operand for operand as apply_row_rho does, and the 2 x 2 x 2 children are
+// summed in the order of k_residual_restrict64 (x pairs by a lane exchange;
+// then the y pair of the lower plane plus the y pair of the upper), so the
+// coarse right side is bitwise that kernel's. Reads p and rho 1.29 times (the
+// ring) and b once, instead of re-reading the neighbour rows and planes of
+// small blocks through the cache.
+__global__ __launch_bounds__(CG_NT) void k_resrestrict_rho(const double* __restrict__ p,
+                                                           const double* __restrict__ bb,
+                                                           const double* __restrict__ rho, Dims dm,
+                                                           double inv_h2, int TZr, int ntx, int nty,
+                                                           int nzc, double* __restrict__ bc) {
+    __shared__ double PP[3][CG_RN];
+    __shared__ double RR[3][CG_RN];
+    __shared__ double XS[2][CG_TY][CG_TX / 2];
+    const int nw = ntx * nty * nzc;
+    const int bid = blockIdx.x;
+    const int w = (nw % 8 == 0) ? (bid % 8) * (nw / 8) + bid / 8 : bid;
+    const int tx = w % ntx;
+    const int r0 = w / ntx;
+    const int ty = r0 % nty;
+    const int zc = r0 / nty;
+    const int i0 = tx * CG_TX - 1, j0 = ty * CG_TY - 1;
+    const int z0 = zc * TZr, z1 = z0 + TZr;
+    const long plane = (long)dm.nx * dm.ny;
+    const int t = threadIdx.x;
+    auto gofs = [&](int x, int y) {
+        return (long)wrap_near(j0 + y, dm.ny) * dm.nx + wrap_near(i0 + x, dm.nx);
+    };
+    long gp[CG_NL];
+    bool vp[CG_NL];
+#pragma unroll
+    for (int s = 0; s < CG_NL; ++s) {
+        int qq = t + s * CG_NT;
+        vp[s] = qq < CG_RN;
+        gp[s] = vp[s] ? gofs(qq % CG_RX, qq / CG_RX) : gofs(0, 0);
+    }
+    const int lx = t % CG_TX, ly = t / CG_TX;  // one cell of the tile per thread
+    const int c = (ly + 1) * CG_RX + lx + 1;
+    const long own = (long)(j0 + 1 + ly) * dm.nx + (i0 + 1 + lx);
+    auto pl = [&](int k) { return (long)wrap_near(k, dm.nz) * plane; };
+    struct Stage {
+        double p[CG_NL], r[CG_NL], b;
+    };
+    Stage SA, SB;
+    // a stage carries p and rho of plane k + 1 and b of plane k
+    auto fetch = [&](Stage& S, int k) {
+        const long bp = pl(k + 1);
+#pragma unroll
+        for (int s = 0; s < CG_NL; ++s) {
+            S.p[s] = p[bp + gp[s]];
+            S.r[s] = rho[bp + gp[s]];
+        }
+        S.b = bb[pl(k) + own];
+    };
+    auto commit = [&](const Stage& S, int k) {
+#pragma unroll
+        for (int s = 0; s < CG_NL; ++s)
+            if (s * CG_NT + CG_NT <= CG_RN || vp[s]) {
+                PP[(k + 4) % 3][t + s * CG_NT] = S.p[s];
+                RR[(k + 4) % 3][t + s * CG_NT] = S.r[s];
+            }
+    };
+    {
+        const long a = pl(z0 - 1), a0 = pl(z0);
+#pragma unroll
+        for (int s = 0; s < CG_NL; ++s)
+            if (vp[s]) {
+                PP[(z0 + 2) % 3][t + s * CG_NT] = p[a + gp[s]];
+                RR[(z0 + 2) % 3][t + s * CG_NT] = rho[a + gp[s]];
+                PP[z0 % 3][t + s * CG_NT] = p[a0 + gp[s]];
+                RR[z0 % 3][t + s * CG_NT] = rho[a0 + gp[s]];
+            }
+    }
+    fetch(SA, z0);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(SB, z0 + 1);
+    auto step = [&](Stage& S, int k) {
+        commit(S, k);
+        const double bv = S.b;
+        // past the range the loads re-read plane z1 - 1 (its stage is not committed)
+        fetch(S, k + 2 < z1 ? k + 2 : z1 - 1);
+        lds_barrier();
+        const double* Pc = PP[k % 3];
+        const double* Rc = RR[k % 3];
+        const double rc = Rc[c];
+        const double rxp = Rc[c + 1], rxm = Rc[c - 1], ryp = Rc[c + CG_RX], rym = Rc[c - CG_RX];
+        const double rzp = RR[(k + 1) % 3][c], rzm = RR[(k + 2) % 3][c];
+        double bxp, bxm, byp, bym, bzp, bzm;
+        if (rxp == rc && rxm == rc && ryp == rc && rym == rc && rzp == rc && rzm == rc) {
+            bxp = bxm = byp = bym = bzp = bzm = 1.0 / rc;
+        } else {
+            bxp = 2.0 / (rxp + rc);
+            bxm = 2.0 / (rc + rxm);
+            byp = 2.0 / (ryp + rc);
+            bym = 2.0 / (rc + rym);
+            bzp = 2.0 / (rzp + rc);
+            bzm = 2.0 / (rc + rzm);
+        }
+        const double pc = Pc[c];
+        double sv = bxp * (Pc[c + 1] - pc) - bxm * (pc - Pc[c - 1]);
+        sv += byp * (Pc[c + CG_RX] - pc) - bym * (pc - Pc[c - CG_RX]);
+        sv += bzp * (PP[(k + 1) % 3][c] - pc) - bzm * (pc - PP[(k + 2) % 3][c]);
+        const double r = bv - sv * inv_h2;
+        const double rx = r + __shfl_xor(r, 1);
+        if ((lx & 1) == 0) XS[k & 1][ly][lx >> 1] = rx;
+        lds_barrier();
+        if ((k & 1) && t < (CG_TX / 2) * (CG_TY / 2)) {
+            const int cx = t % (CG_TX / 2), cy = t / (CG_TX / 2);
+            const double v = (XS[0][2 * cy][cx] + XS[0][2 * cy + 1][cx]) +
+                             (XS[1][2 * cy][cx] + XS[1][2 * cy + 1][cx]);
+            const int cnx = dm.nx >> 1, cny = dm.ny >> 1;
+            const long o = ((long)(k >> 1) * cny + (ty * (CG_TY / 2) + cy)) * cnx + (tx * (CG_TX / 2) + cx);
+            bc[o] = v * 0.125;
+        }
+        // the next commit overwrites plane k - 1's slot and the next plane's sums
+        lds_barrier();
+    };
+    // steps z0 .. z1 - 1 in pairs (stage A: even planes, B: odd); z0 and TZr are even
+    for (int k = z0; k < z1; k += 2) {
+        step(SA, k);
+        step(SB, k + 1);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // tile of the density sweep: 64 x 8 cells, 512 threads (2 workgroups per CU)
@@ -1374,10 +1544,13 @@ static void launch_rbgs(Level& L, int color, hipStream_t st, bool finest) {
 
 // zero: the sweep starts from p = 0 (pin is not read)
 template <typename T>
-static void launch_fused(Level& L, T* pin, T* pout, hipStream_t st, bool finest, bool zero) {
+static void launch_fused(Level& L, T* pin, T* pout, hipStream_t st, bool finest, bool zero,
+                         bool dots = false) {
     // sweeps from p = 0 read less and are timed under their own kind
     ProfScope ps(zero ? IB_PROF_SWEEP_ZERO
-                      : (sizeof(T) == 8 ? (L.rho ? IB_PROF_SWEEP64_RHO : IB_PROF_SWEEP64) : IB_PROF_SWEEP32),
+                      : dots ? IB_PROF_SWEEP_DOTS
+                             : (sizeof(T) == 8 ? (L.rho ? IB_PROF_SWEEP64_RHO : IB_PROF_SWEEP64)
+                                               : IB_PROF_SWEEP32),
                  st, finest);
     LevelT<T>& A = lvl<T>(L);
     T h2 = (T)(L.d.h * L.d.h);
@@ -1385,7 +1558,11 @@ static void launch_fused(Level& L, T* pin, T* pout, hipStream_t st, bool finest,
     if constexpr (sizeof(T) == 8) {
         if (L.rho) {
             const int rx = L.d.nx / kRTX, ry = L.d.ny / kRTY, rz = L.d.nz / L.rtz;
-            if (zero)
+            if (dots)
+                hipLaunchKernelGGL((k_rbgs_fused_rho<kRTX, kRTY, kRNT, false, true>), dim3(rx * ry * rz),
+                                   dim3(kRNT), 0, st, pin, pout, A.b, L.rho, L.d, h2, L.rtz, rx, ry, rz,
+                                   L.dots_q, L.dots_part);
+            else if (zero)
                 hipLaunchKernelGGL((k_rbgs_fused_rho<kRTX, kRTY, kRNT, true>), dim3(rx * ry * rz), dim3(kRNT),
                                    0, st, pin, pout, A.b, L.rho, L.d, h2, L.rtz, rx, ry, rz);
             else
@@ -1405,13 +1582,16 @@ static void launch_fused(Level& L, T* pin, T* pout, hipStream_t st, bool finest,
 // nu red-black sweeps on level L; returns the buffer holding the result.
 // zero_first: the level starts from p = 0, which a single-pass first sweep
 // takes without reading (the caller then need not fill p)
+// dots_last: the last sweep leaves the inner products of Level::dots_*
 template <typename T>
-static T* smooth(Level& L, T* cur, int nu, hipStream_t st, bool finest, bool zero_first) {
+static T* smooth(Level& L, T* cur, int nu, hipStream_t st, bool finest, bool zero_first,
+                 bool dots_last = false) {
     LevelT<T>& A = lvl<T>(L);
     for (int s = 0; s < nu; ++s) {
         if (L.fused) {
             T* other = cur == A.p ? A.alt : A.p;
-            launch_fused<T>(L, cur, other, st, finest, zero_first && s == 0);
+            launch_fused<T>(L, cur, other, st, finest, zero_first && s == 0,
+                            dots_last && s == nu - 1 && !(zero_first && s == 0));
             cur = other;
         } else {
             T* save = A.p;
@@ -1471,7 +1651,13 @@ static void vcycle(mg_handle* m, int l, hipStream_t st, bool zero_start) {
         const dim3 g64(L.d.nx / 64, L.d.ny / 2, L.d.nz / 2);
         bool done = false;
         if constexpr (sizeof(T) == 8) {
-            if (L.rho) {  // set only where nx % 64 == 0 in 3D
+            if (L.rho && L.d.ny % CG_TY == 0 && L.rtz > 0 && L.rtz % 2 == 0) {
+                // tiled z-march (nx % 64 == 0 where rho is set)
+                const int tx = L.d.nx / CG_TX, ty = L.d.ny / CG_TY, tz = L.d.nz / L.rtz;
+                hipLaunchKernelGGL(k_resrestrict_rho, dim3(tx * ty * tz), dim3(CG_NT), 0, st, cur, A.b, L.rho,
+                                   L.d, inv_h2, L.rtz, tx, ty, tz, B.b);
+                done = true;
+            } else if (L.rho) {  // set only where nx % 64 == 0 in 3D
                 hipLaunchKernelGGL((k_residual_restrict64<double, CoefRho>), g64, dim3(kBlock), 0, st,
                                    cur, A.b, CoefRho{L.rho}, L.d, inv_h2, B.b);
                 done = true;
@@ -1500,7 +1686,7 @@ static void vcycle(mg_handle* m, int l, hipStream_t st, bool zero_start) {
         else
             hipLaunchKernelGGL((k_prolong_add<T, 3>), pg, dim3(bx), 0, st, cur, B.p, L.d);
     }
-    cur = smooth<T>(L, cur, m->o.nu2, st, fin, false);
+    cur = smooth<T>(L, cur, m->o.nu2, st, fin, false, sizeof(T) == 8 && L.dots_on);
     if (cur != A.p)
         (void)hipMemcpyAsync(A.p, cur, sizeof(T) * L.d.cells(), hipMemcpyDeviceToDevice, st);
 }
@@ -1933,6 +2119,9 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
     const int cg_tz = fused ? L0.d.nz / L0.rtz : 0;
     const int cg_wgs = cg_tx * cg_ty * cg_tz;
     IB_CHECK(!fused || cg_wgs <= kRed, IB_EINVAL, "mg_solve: too many workgroups for the partial sums");
+    // the inner products of z = V(r) come from the last post-smoothing sweep
+    // of the finest level (the same tiling: cg_wgs workgroups)
+    const bool fold = fused && !mixed && L0.fused && m->o.nu2 >= 1;
     int it = 0, slot = KS_RZ0;
     int skip = 0, last_check = 0, checks = 0;
     double rel_check = rel;
@@ -1946,9 +2135,20 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
             return fail(IB_ENOTCONV, "mg_solve: no convergence within max_cycles");
         }
         const bool check = fixed > 0 || skip == 0 || it + 1 >= max_it;
+        if (fold) {
+            L0.dots_on = true;
+            L0.dots_q = it == 0 ? nullptr : m->kq;
+            L0.dots_part = pa;
+        }
         precond();
+        L0.dots_on = false;
         const int rz_old = slot;
-        if (it == 0) {
+        if (fold) {
+            const int next = it == 0 ? slot : (slot == KS_RZ0 ? KS_RZ1 : KS_RZ0);
+            IB_TRY(device_sum(pa, cg_wgs, m->ks + next, st));
+            if (it > 0) IB_TRY(device_sum(pa + cg_wgs, cg_wgs, m->ks + KS_QZ, st));
+            slot = next;
+        } else if (it == 0) {
             IB_TRY(dots(nullptr, slot));
         } else {
             const int next = slot == KS_RZ0 ? KS_RZ1 : KS_RZ0;
