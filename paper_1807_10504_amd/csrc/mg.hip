@@ -734,6 +734,9 @@ __global__ __launch_bounds__(kBlock) void k_residual_restrict64(const T* __restr
 // p_fine += P e_coarse (cell-centred linear, 3/4 and 1/4 per axis)
 template <typename T, int DIM>
 __global__ void k_prolong_add(T* __restrict__ p, const T* __restrict__ e, Dims f) {
+    // every product and sum rounded on its own (no fused multiply-add), so that
+    // the blocked and the persistent forms give the same bits
+#pragma clang fp contract(off)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= f.nx) return;
     const int j = blockIdx.y, k = blockIdx.z;
@@ -759,6 +762,50 @@ __global__ void k_prolong_add(T* __restrict__ p, const T* __restrict__ e, Dims f
         v = a * (a * r00 + q * r01) + q * (a * r10 + q * r11);
     }
     p[((long)k * f.ny + j) * f.nx + i] += v;
+}
+
+// The same prolongation in 3D with one thread per coarse cell: it loads the
+// 27 coarse values around it once and adds the corrections of its 8 children
+// (each formed exactly as in k_prolong_add), so consecutive threads update
+// consecutive pairs of fine cells along x.
+template <typename T>
+__global__ void k_prolong_add_blk(T* __restrict__ p, const T* __restrict__ e, Dims f) {
+#pragma clang fp contract(off)
+    const int cx = f.nx >> 1, cy = f.ny >> 1, cz = f.nz >> 1;
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= cx) return;
+    const int J = blockIdx.y, K = blockIdx.z;
+    const int Im = I == 0 ? cx - 1 : I - 1, Ip = I + 1 == cx ? 0 : I + 1;
+    const int Jm = J == 0 ? cy - 1 : J - 1, Jp = J + 1 == cy ? 0 : J + 1;
+    const int Km = K == 0 ? cz - 1 : K - 1, Kp = K + 1 == cz ? 0 : K + 1;
+    const long pl = (long)cx * cy;
+    // E[z][y][x] with offsets -1, 0, +1
+    T E[3][3][3];
+    const int ks[3] = {Km, K, Kp}, js[3] = {Jm, J, Jp}, is[3] = {Im, I, Ip};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) E[a][b][c] = e[ks[a] * pl + (long)js[b] * cx + is[c]];
+    const T a = T(0.75), q = T(0.25);
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+            // the second coarse cell along each axis: below for the even child, above for the odd
+            const int z2 = dz ? 2 : 0, y2 = dy ? 2 : 0;
+            T* row = p + ((long)(2 * K + dz) * f.ny + (2 * J + dy)) * f.nx + 2 * I;
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const int x2 = dx ? 2 : 0;
+                const T r00 = a * E[1][1][1] + q * E[1][1][x2];
+                const T r01 = a * E[1][y2][1] + q * E[1][y2][x2];
+                const T r10 = a * E[z2][1][1] + q * E[z2][1][x2];
+                const T r11 = a * E[z2][y2][1] + q * E[z2][y2][x2];
+                row[dx] += a * (a * r00 + q * r01) + q * (a * r10 + q * r11);
+            }
+        }
 }
 
 template <typename T>
@@ -992,6 +1039,8 @@ __device__ void pv_restrict(const PersistLevels<T>& L, int l) {
 
 template <typename T, int DIM>
 __device__ void pv_prolong(const PersistLevels<T>& L, int l) {
+    // products and sums rounded one by one, as in k_prolong_add(_blk)
+#pragma clang fp contract(off)
     const Dims f = L.d[l];
     T* __restrict__ p = L.p[l];
     const T* __restrict__ e = L.p[l + 1];
@@ -1681,10 +1730,13 @@ static void vcycle(mg_handle* m, int l, hipStream_t st, bool zero_start) {
         ProfScope ps(sizeof(T) == 8 ? IB_PROF_PROLONG64 : IB_PROF_PROLONG32, st, fin);
         int bx = std::min(L.d.nx, kBlock);
         dim3 pg((L.d.nx + bx - 1) / bx, L.d.ny, L.d.nz);
-        if (L.d.dim == 2)
+        if (L.d.dim == 2) {
             hipLaunchKernelGGL((k_prolong_add<T, 2>), pg, dim3(bx), 0, st, cur, B.p, L.d);
-        else
-            hipLaunchKernelGGL((k_prolong_add<T, 3>), pg, dim3(bx), 0, st, cur, B.p, L.d);
+        } else {
+            const int cxn = L.d.nx / 2, cb = std::min(cxn, 128);
+            hipLaunchKernelGGL((k_prolong_add_blk<T>), dim3((cxn + cb - 1) / cb, L.d.ny / 2, L.d.nz / 2),
+                               dim3(cb), 0, st, cur, B.p, L.d);
+        }
     }
     cur = smooth<T>(L, cur, m->o.nu2, st, fin, false, sizeof(T) == 8 && L.dots_on);
     if (cur != A.p)
