@@ -132,13 +132,20 @@ __global__ void k_nearest_2d(const double* __restrict__ X, int n, const double* 
     }
 }
 
-// 3D scatter: one thread per (triangle, orientation)
-__global__ void k_nearest_3d(const double* __restrict__ X, int nv, const int32_t* __restrict__ T,
-                             int nt, const double* __restrict__ H, Dims d,
-                             unsigned long long* __restrict__ best) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 3 * nt) return;
-    int comp = t / nt, e = t - comp * nt;
+// 3D scatter: one wavefront per (triangle, orientation); its 64 lanes split
+// the faces of the triangle's reach box (about 8 each), so the loads of H
+// that decide each face are independent across lanes instead of a chain of
+// several hundred dependent loads in one thread
+constexpr int kNearLanes = 64;
+
+__global__ __launch_bounds__(256) void k_nearest_3d(const double* __restrict__ X, int nv,
+                                                    const int32_t* __restrict__ T, int nt,
+                                                    const double* __restrict__ H, Dims d,
+                                                    unsigned long long* __restrict__ best) {
+    const long task = ((long)blockIdx.x * blockDim.x + threadIdx.x) / kNearLanes;
+    const int lane = threadIdx.x % kNearLanes;
+    if (task >= 3L * nt) return;
+    int comp = (int)(task / nt), e = (int)(task - (long)comp * nt);
     for (int r = 0; r < 3; ++r) {
         int v = T[3 * e + r];
         if (v < 0 || v >= nv) return;  // reported by the Heaviside pass
@@ -160,20 +167,39 @@ __global__ void k_nearest_3d(const double* __restrict__ X, int nv, const int32_t
     }
     unsigned long long* B = best + (long)comp * d.cells();
     long stride = comp == 0 ? 1 : (comp == 1 ? (long)d.nx : (long)d.nx * d.ny);
-    for (int k = lo[2]; k <= hi[2]; ++k)
-        for (int j = lo[1]; j <= hi[1]; ++j)
-            for (int i = lo[0]; i <= hi[0]; ++i) {
-                long cc = cell_index(d, i, j, k);
-                int ic = comp == 0 ? i : (comp == 1 ? j : k);
-                long cm = ic == 0 ? cc + (long)(nn[comp] - 1) * stride : cc - stride;
-                if (fabs(H[cc] - H[cm]) <= kDhEps) continue;
-                double p[3] = {(i + (comp == 0 ? 0.0 : 0.5)) * h, (j + (comp == 1 ? 0.0 : 0.5)) * h,
-                               (k + (comp == 2 ? 0.0 : 0.5)) * h};
-                double w[3];
-                double d2 = tri_closest(p, a, b, c, w);
-                if (d2 >= R2) continue;
-                atomicMin(&B[cc], make_key(d2, inv_h2, e));
-            }
+    // faces farther from the centroid than R plus the circumradius cannot be
+    // within R of the triangle: skipped before any load (the bound is widened
+    // by a relative 1e-9 so that rounding never rejects a face within reach)
+    double g[3], rad2 = 0.0;
+    for (int r = 0; r < 3; ++r) g[r] = (a[r] + b[r] + c[r]) * (1.0 / 3.0);
+    for (const double* v : {a, b, c}) {
+        double s2 = 0.0;
+        for (int r = 0; r < 3; ++r) s2 += (v[r] - g[r]) * (v[r] - g[r]);
+        rad2 = fmax(rad2, s2);
+    }
+    const double reach = R + sqrt(rad2);
+    const double bound = reach * reach * (1.0 + 1e-9);
+    const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+    if (ex <= 0 || ey <= 0 || ez <= 0) return;
+    const int nbox = ex * ey * ez;
+    for (int f = lane; f < nbox; f += kNearLanes) {
+        const int i = lo[0] + f % ex;
+        const int rr = f / ex;
+        const int j = lo[1] + rr % ey;
+        const int k = lo[2] + rr / ey;
+        double p[3] = {(i + (comp == 0 ? 0.0 : 0.5)) * h, (j + (comp == 1 ? 0.0 : 0.5)) * h,
+                       (k + (comp == 2 ? 0.0 : 0.5)) * h};
+        const double gx = p[0] - g[0], gy = p[1] - g[1], gz = p[2] - g[2];
+        if (gx * gx + gy * gy + gz * gz > bound) continue;
+        long cc = cell_index(d, i, j, k);
+        int ic = comp == 0 ? i : (comp == 1 ? j : k);
+        long cm = ic == 0 ? cc + (long)(nn[comp] - 1) * stride : cc - stride;
+        if (fabs(H[cc] - H[cm]) <= kDhEps) continue;
+        double w[3];
+        double d2 = tri_closest(p, a, b, c, w);
+        if (d2 >= R2) continue;
+        atomicMin(&B[cc], make_key(d2, inv_h2, e));
+    }
 }
 
 // face pass: F = f dH / h, reset keys
@@ -237,7 +263,7 @@ int launch_irrot_force(Ctx* c, const ib_surface* s, const double* H, double* con
     } else {
         int nt = s->n_elems;
         IB_CHECK(nt < (1 << kElemBits), IB_EINVAL, "ib_spread: too many triangles");
-        hipLaunchKernelGGL(k_nearest_3d, dim3(grid_for(3L * nt)), dim3(kBlock), 0, st, s->X, n,
+        hipLaunchKernelGGL(k_nearest_3d, dim3(grid_for(3L * nt * kNearLanes)), dim3(kBlock), 0, st, s->X, n,
                            s->elems, nt, H, c->d, c->best);
         for (int comp = 0; comp < 3; ++comp)
             hipLaunchKernelGGL(k_irrot_force<3>, dim3(grid_for(c->d.cells())), dim3(kBlock), 0, st,
