@@ -236,7 +236,7 @@ def _matrix(co, shape):
                            np.concatenate([c.ravel() for c in cols]))), shape=(N, N))
 
 
-def predict(u, rho_n, rho_np1, mu, dt, h, adv_prev=None):
+def predict(u, rho_n, rho_np1, mu, dt, h, adv_prev=None, f_body=None):
     """u* of eq ns1_new on the meridian plane (Adams-Bashforth advection, Crank-
     Nicolson viscous stress, system solved exactly); u_r stays zero on face
     column 0. Returns (u_star, C(u^n))."""
@@ -252,6 +252,8 @@ def predict(u, rho_n, rho_np1, mu, dt, h, adv_prev=None):
         ax = 1 if d == 0 else 0
         rf = 0.5 * (rho_np1 + np.roll(rho_np1, 1, axis=ax))
         g = rf / dt * u[d] - ab[d] + 0.5 * vis[d]
+        if f_body is not None and f_body[d] is not None:
+            g = g + f_body[d]
         M = sp.diags(rf.ravel() / dt) - 0.5 * _matrix(cos[d], shape)
         if d == 0:
             # face column 0 is fixed at zero: identity rows, and no coupling into it
@@ -268,7 +270,7 @@ def predict(u, rho_n, rho_np1, mu, dt, h, adv_prev=None):
 
 
 def flow_step(nr, nz, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, Xd, H_prev, adv_prev=None,
-              p_prev=None, rtol=1e-10):
+              p_prev=None, rtol=1e-10, gravity=0.0, frame_a=0.0, mass_target=None):
     """One step of the full axisymmetric method: markers advanced with u^n and
     relocated (eq curv_ax), H^{n+1} and F, rho^n from H_prev, the predictor, the
     projection of u*."""
@@ -276,12 +278,22 @@ def flow_step(nr, nz, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, Xd, H_pre
     U = transfer.interp(ud, Xd, h)
     Xn, fs, ds, nrm = bspline.relocate([tuple(x) for x in Xd], [tuple(v) for v in U], dt, h, sigma)
     Xn, fs, nrm = np.array(Xn), np.array(fs), np.array(nrm)
+    if mass_target is not None:
+        from . import dynamics
+        Xn, _ = dynamics.mass_correct(Xn, nrm, mass_target, nr * h, h)
     ft = curvature_total(Xn, nrm, fs, sigma, nr * h, h)
     H, F = interface(Xn, ft, nr, nz, h)
     rho_n = poisson.density(H_prev, rho_in, rho_out)
     rho1 = poisson.density(H, rho_in, rho_out)
     mu = poisson.density(H, mu_in, mu_out)
-    u_star, adv = predict(u, rho_n, rho1, mu, dt, h, adv_prev)
+    f_body = None
+    if gravity != 0.0 or frame_a != 0.0:
+        from . import dynamics
+        _, rc = radii(nr, h)
+        rho_mean = float(np.sum(rho1 * rc[None, :]) / (nz * np.sum(rc)))
+        rf = 0.5 * (rho1 + np.roll(rho1, 1, axis=0))
+        f_body = [None, dynamics.body_force(rf, rho_mean, gravity, frame_a)]
+    u_star, adv = predict(u, rho_n, rho1, mu, dt, h, adv_prev, f_body)
     out = project(u_star, H, F, rho_in, rho_out, dt, h, p_prev=p_prev, rtol=rtol)
     out.update(U=U, X=Xn, fs=ft, H=H, F=F, u_star=u_star, adv=adv)
     return out

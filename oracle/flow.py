@@ -124,9 +124,10 @@ def face_density(rho, dim, d):
     return 0.5 * (rho + _at(rho, dim, {d: -1}))
 
 
-def predict(u, rho_n, rho_np1, mu, dt, h, adv_prev=None):
+def predict(u, rho_n, rho_np1, mu, dt, h, adv_prev=None, f_body=None):
     """u* of eq ns1_new; returns (u_star, C(u^n)) -- the latter is the
-    Adams-Bashforth history for the next step."""
+    Adams-Bashforth history for the next step. f_body: optional body force
+    density per component (faces), added to the right side."""
     dim = len(u)
     adv = advection(u, rho_n, h)
     ab = adv if adv_prev is None else [1.5 * a - 0.5 * b for a, b in zip(adv, adv_prev)]
@@ -135,13 +136,15 @@ def predict(u, rho_n, rho_np1, mu, dt, h, adv_prev=None):
     for d in range(dim):
         rf = face_density(rho_np1, dim, d)
         g = rf / dt * u[d] - ab[d] + 0.5 * vis[d]
+        if f_body is not None and f_body[d] is not None:
+            g = g + f_body[d]
         M = sp.diags(rf.ravel() / dt) - 0.5 * viscous_matrix(mu, h, d, dim)
         u_star.append(spla.spsolve(M.tocsc(), g.ravel()).reshape(u[d].shape))
     return u_star, adv
 
 
 def flow_step_2d(n, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, X, H_prev, adv_prev=None,
-                 p_prev=None, rtol=1e-10, max_cycles=100):
+                 p_prev=None, rtol=1e-10, max_cycles=100, gravity=0.0, frame_a=0.0, mass_target=None):
     """One step of the full 2D method (Section 2.1 fractional step, Section 2.2
     transfer, Section 3.2 irrotational force, Section 4 relocation):
       1. U = interpolation of u^n to the markers; markers advanced by dt U and
@@ -154,12 +157,20 @@ def flow_step_2d(n, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, X, H_prev, 
     U = transfer.interp(u, X, h)
     Xn, fs, ds, nrm = bspline.relocate([tuple(x) for x in X], [tuple(v) for v in U], dt, h, sigma)
     Xn, fs = np.array(Xn), np.array(fs)
+    if mass_target is not None:
+        from . import dynamics
+        Xn, _ = dynamics.mass_correct(Xn, np.array(nrm), mass_target, None, h)
     H = heaviside.heaviside_2d(Xn, n, h)
     F = force.irrotational_force(H, Xn, fs, h)
     rho_n = poisson.density(H_prev, rho_in, rho_out)
     rho1 = poisson.density(H, rho_in, rho_out)
     mu = poisson.density(H, mu_in, mu_out)
-    u_star, adv = predict(u, rho_n, rho1, mu, dt, h, adv_prev)
+    f_body = None
+    if gravity != 0.0 or frame_a != 0.0:
+        from . import dynamics
+        rf = face_density(rho1, 2, 1)
+        f_body = [None, dynamics.body_force(rf, rho1.mean(), gravity, frame_a)]
+    u_star, adv = predict(u, rho_n, rho1, mu, dt, h, adv_prev, f_body)
     beta = poisson.face_beta(rho1)
     b = poisson.rhs(u_star, F, beta, dt, h)
     p, cycles, _ = poisson.mg_solve(b, beta, h, p0=p_prev, rtol=rtol, max_cycles=max_cycles)
