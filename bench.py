@@ -295,6 +295,80 @@ def bench_flow_osc(ib, torch):
     return res
 
 
+# Table afd_param sets 1 and 2 (D = 1, rho_ambient = 1, sigma = 1, d = v = 10):
+# g from the Eotvos number, mu_ambient from the Morton number
+AFD_SETS = {1: (0.3, 3.333e-4), 2: (9.0, 1.440e-2)}
+
+
+def _free_fall_run(ib, torch, eo, mo, h=0.0125, nr=128, nz=256, dt=5e-4, steps=8000, markers=512):
+    """Axisymmetric free fall of a D = 1 drop (Section 5.3, Table afd_param) in the
+    restoring non-inertial frame (c1 = c2 = 0.1), weight (rho - rho_mean) g along -z,
+    mass correction every 20 steps. Slip Reynolds number rho_a D |W_a - W_d| / mu_a
+    from the r-weighted mean axial velocities of the ambient (H = 0) and drop (H = 1)
+    cells."""
+    from paper_1807_10504_amd import workloads as W
+    rho_a, rho_d, sigma, D = 1.0, 10.0, 1.0, 1.0
+    g = eo * sigma / ((rho_d - rho_a) * D * D)
+    mu_a = (mo * rho_a ** 2 * sigma ** 3 / (g * (rho_d - rho_a))) ** 0.25
+    prm = dict(rho_in=rho_d, rho_out=rho_a, mu_in=10 * mu_a, mu_out=mu_a, sigma=sigma, dt=dt, rtol=1e-10,
+               pred_rtol=1e-12, warm_start=ib.WS_PREV, gravity=-g, frame=True, c1=0.1, c2=0.1,
+               mass_every=20)
+    mg = ib.Multigrid(2, (nr, nz), h, krylov=1)
+    axis = nr * h
+    X = W.circle_markers(markers, 0.5 * D, centre=(axis, 0.5 * nz * h))
+    solver = ib.Axisym(nr, nz, h, max_markers=markers)
+    u = [torch.zeros((nz, nr), dtype=torch.float64, device="cuda") for _ in range(2)]
+    p = torch.zeros((nz, nr), dtype=torch.float64, device="cuda")
+    H = torch.zeros((nz, nr), dtype=torch.float64, device="cuda")
+    out = {"p": p, "u": u, "H": H}
+    rc = ((torch.arange(nr, dtype=torch.float64, device="cuda") + 0.5) * h)[None, :]
+    re_hist, com_hist, vol_hist, corrections = [], [], [], 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        out = solver.flow_step(mg, prm, u, X, p_prev=p, out=out)
+        f = out["flow"]
+        com_hist.append(f["com"])
+        vol_hist.append(f["measure"])
+        corrections += f["mass_delta"] != 0.0
+        if k % 200 == 199:
+            wz = 0.5 * (u[1] + torch.roll(u[1], -1, 0))      # cell-centred axial velocity
+            wd = float((wz * H * rc).sum() / (H * rc).sum())
+            wa = float((wz * (1 - H) * rc).sum() / ((1 - H) * rc).sum())
+            re_hist.append(rho_a * D * abs(wa - wd) / mu_a)
+        if k % 2000 == 1999:
+            log(f"  free fall Eo={eo}: step {k + 1}/{steps}, Re {re_hist[-1]:.4f}")
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    v0 = vol_hist[0]
+    return dict(eotvos=eo, morton=mo, g=round(g, 6), mu_ambient=round(mu_a, 6), steps=steps, t_end=steps * dt,
+                steps_per_s=round(steps / secs, 2), ms_per_step=round(1e3 * secs / steps, 3),
+                reynolds_end=round(re_hist[-1], 5),
+                reynolds_change_last_10pct=round(abs(re_hist[-1] - re_hist[-len(re_hist) // 10 - 1]) /
+                                                 re_hist[-1], 5),
+                reynolds_every_0p1=[round(r, 4) for r in re_hist],
+                com_drift_over_D=float(f"{abs(com_hist[-1] - com_hist[0]) / D:.3e}"),
+                volume_rel_change_max=float(f"{max(abs(v - v0) for v in vol_hist) / v0:.3e}"),
+                mass_corrections=int(corrections))
+
+
+def bench_free_fall(ib, torch):
+    """Free-fall drops of Table afd_param sets 1 and 2 at h = 0.0125 on the meridian
+    plane: steps/s of the full step with weight, frame and mass correction, and
+    the slip Reynolds number's history (the paper plots it; no value is printed)."""
+    res = {}
+    for k in (1, 2):
+        r = _free_fall_run(ib, torch, *AFD_SETS[k])
+        res[f"set{k}"] = r
+        log(f"  free fall set {k}: Re {r['reynolds_end']} (last-10% change {r['reynolds_change_last_10pct']}), "
+            f"COM drift {r['com_drift_over_D']} D, {r['steps_per_s']} steps/s")
+    res["workload"] = ("Table afd_param sets 1-2: D=1 drop, rho 10/1, mu 10 mu_a/mu_a, sigma=1, g from Eo, "
+                       "mu_a from Mo; 128 x 256 meridian half plane at h=0.0125 (r <= 1.6 D, periodic "
+                       "z of 3.2 D), dt 5e-4, 8000 steps (t = 4), 512 markers; weight (rho - rho_mean) g, "
+                       "restoring frame c1 = c2 = 0.1, mass correction every 20 steps")
+    return res
+
+
 def bench_static_tables(ib, torch, reps=3):
     """Tables staticdrop_2d and staticdrop_axis of Section 5.1: a drop of diameter 0.4
     (2D: box centre; axisymmetric: on the axis), rho 1 / 0.01, sigma = 1, one projection
@@ -664,6 +738,8 @@ def main():
         line["flow_osc"] = bench_flow_osc(ib, torch)
         log("== static drop tables (2D and axisymmetric)")
         line["static_tables"] = bench_static_tables(ib, torch)
+        log("== free-fall drops (Table afd_param sets 1-2, axisymmetric)")
+        line["free_fall"] = bench_free_fall(ib, torch)
         log(f"== momentum predictor at {args.size}^3")
         line["predictor_3d"] = bench_predictor_3d(ib, torch, args.size)
     if not args.no_cpu_baseline:

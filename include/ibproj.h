@@ -284,12 +284,35 @@ typedef struct {
     int sweeps;              /* red-black Gauss-Seidel sweeps of the implicit system */
     double rel_res;          /* ||g - M u*|| / ||g|| at exit (M = rho_f/dt - D/2) */
     int first_step;          /* 1: the advection history was empty (explicit Euler) */
+    /* free-fall bookkeeping of flow_step / axi_flow_step (zero when off) */
+    double frame_a;          /* frame acceleration applied in this step */
+    double com;              /* vertical centroid of the incoming markers */
+    double measure;          /* their enclosed area / volume of revolution */
+    double mass_delta;       /* normal displacement of the mass correction (0: none) */
 } ib_flow_stats;
 
 typedef struct {
     double mu_in, mu_out;    /* drop and ambient dynamic viscosities (>= 0) */
     double rtol;             /* tolerance of the implicit viscous system */
     int max_sweeps;          /* sweeps allowed (IB_ENOTCONV beyond) */
+    /* free-fall runs (Section 2.1: non-inertial frame, conservation of mass);
+       all zero for none. The vertical axis is y in 2D and the axis of the
+       meridian plane. */
+    double gravity;          /* g along the vertical axis, applied as the force
+                                density (rho - rho_mean) g on the vertical faces
+                                (rho_mean: volume mean of rho^{n+1}; the periodic
+                                box takes no net force) */
+    int frame;               /* 1: frame acceleration a = -c1 (COM_n - COM_0)/dt
+                                - c2 (COM_n - COM_{n-1})/dt on the drop's centre of
+                                mass (eq fictitious read as a restoring control),
+                                force density rho a on the vertical faces */
+    double c1, c2;           /* its constants (Section 2.1: 0.1 and 0.1) */
+    int mass_every;          /* > 0: every this many steps, when the enclosed
+                                area / volume differs from the first step's by more
+                                than 1e-6 relatively, all markers move by one
+                                distance along their normals (bisection to 1e-12) */
+    double mass_target;      /* > 0: the area / volume the correction restores
+                                instead of the first step's */
 } ib_flow_params;
 
 /* C(u) of eq ad_bf for every component; rho: device cell densities. A may not
@@ -409,6 +432,21 @@ int  axi_flow_step(ib_axi* a, mg_handle* m, const ib_params* prm, const ib_flow_
 int ib_relocate_bspline(int n, const double* X, const double* U, double dt, double h,
                         double sigma, double* X_out, double* fs_out, double* ds_out,
                         double* nrm_out);
+
+/* Enclosed area (axis_x NaN: the closed planar polygon X, n x 2) or volume
+ * of revolution about x = axis_x of the region the mirrored meridian curve
+ * encloses on the side x >= axis_x, and the y (axial) coordinate of its
+ * centroid. Host arrays. Errors: IB_EINVAL, IB_EGEOM (empty curve). */
+int ib_enclosed_measure(int n, const double* X, double axis_x, double* measure, double* com);
+
+/* Mass correction (Section 2.1, conservation of mass): when |V - target| >
+ * trigger target (V as ib_enclosed_measure), move every marker of X (host,
+ * n x 2, in place) by one distance delta along its unit normal nrm (n x 2,
+ * toward the drop), delta by bisection on [-h, h] until |V - target| <=
+ * tol target (at most 200 halvings). delta (may be NULL) receives it (0 when
+ * no correction was needed). Errors: IB_EINVAL. */
+int ib_mass_correct(int n, double* X, const double* nrm, double target, double axis_x, double h,
+                    double trigger, double tol, double* delta);
 
 /* 3D surface geometry (the paper stops at curves; this is the library's
  * extension for static closed meshes): cotangent-formula curvature force

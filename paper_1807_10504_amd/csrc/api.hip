@@ -196,13 +196,17 @@ int spread_impl(Ctx* c, const ib_surface* s, int mode, double* const F[3], doubl
 // and relocated on the least-squares B-spline on the host; X_host is updated
 // in place and s points at the relocated device copies with their force data.
 int relocate_2d(Ctx* c, const ib_params* prm, ib_state* stt, const double* U_dev, double* fs_host,
-                ib_surface* s, hipStream_t st, double axis_x) {
+                ib_surface* s, hipStream_t st, double axis_x, const double* mass_target,
+                double* mass_delta) {
     const int n = s->n_markers;
     std::vector<double> U(2 * (size_t)n), Xn(2 * (size_t)n), fs(n), ds(n), nr(2 * (size_t)n);
     IB_HIP(hipMemcpyAsync(U.data(), U_dev, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, st));
     IB_HIP(hipStreamSynchronize(st));
     IB_TRY(ib_relocate_bspline(n, stt->X_host, U.data(), prm->dt, c->d.h, prm->sigma, Xn.data(),
                                fs.data(), ds.data(), nr.data()));
+    if (mass_target)
+        IB_TRY(ib_mass_correct(n, Xn.data(), nr.data(), *mass_target, axis_x, c->d.h, 1e-6, 1e-12,
+                               mass_delta));
     if (std::isfinite(axis_x)) {
         // a meridian curve mirrored about the axis x = axis_x: add the azimuthal
         // curvature -n_r / r (eq curv_ax). Within a quarter cell of the axis
@@ -319,7 +323,7 @@ extern "C" int project_step(ib_ctx* c, mg_handle* m, const ib_params* prm, ib_st
     // a2: marker velocities
     IB_TRY(launch_interp(c, stt->u_star, &s, out->U, st));
     // a3: 2D marker advance and least-squares relocation on the host
-    if (dim == 2) IB_TRY(relocate_2d(c, prm, stt, out->U, out->fs_host, &s, st, NAN));
+    if (dim == 2) IB_TRY(relocate_2d(c, prm, stt, out->U, out->fs_host, &s, st, NAN, nullptr, nullptr));
     // a4, a5: Heaviside and face force
     double* H = out->H ? out->H : c->H;
     double* F[3];

@@ -198,7 +198,7 @@ __global__ void k_axi_pred_rhs(const double* __restrict__ ur, const double* __re
                                const double* __restrict__ mu, const double* __restrict__ Ar_prev,
                                const double* __restrict__ Az_prev, int first, int nr, int nz, double h,
                                double inv_dt, double* __restrict__ Ar, double* __restrict__ Az,
-                               double* __restrict__ gr, double* __restrict__ gz) {
+                               double* __restrict__ gr, double* __restrict__ gz, Body B, int body_on) {
     const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= (long)nr * nz) return;
     const AxiIdx X(c, nr, nz);
@@ -219,7 +219,9 @@ __global__ void k_axi_pred_rhs(const double* __restrict__ ur, const double* __re
     const double ab = first ? a : 1.5 * a - 0.5 * Az_prev[c];
     axi_visc_z(X, h, mu, co);
     const double rf = 0.5 * (rho1[c] + rho1[X.at(0, -1)]);
-    gz[c] = rf * inv_dt * uz[c] - ab + 0.5 * axi_apply(X, uz, co);
+    double gv = rf * inv_dt * uz[c] - ab + 0.5 * axi_apply(X, uz, co);
+    if (body_on) gv += B.at(rf);
+    gz[c] = gv;
 }
 
 __global__ void k_axi_helm_sweep(double* __restrict__ xr, double* __restrict__ xz,
@@ -299,6 +301,8 @@ struct ib_axi {
     double* Hn = nullptr;
     double* rho_n = nullptr;
     double* mu = nullptr;
+    double* mred = nullptr;   // density-sum partials (kMeanParts) + the sum
+    FreeFall ff;
 };
 
 static void free_axi(ib_axi* a) {
@@ -307,7 +311,7 @@ static void free_axi(ib_axi* a) {
     if (a->half) ib_destroy(a->half);
     for (double* p : {a->ud[0], a->ud[1], a->wb[0], a->wb[1], a->red, a->adv[0][0], a->adv[0][1],
                       a->adv[1][0], a->adv[1][1], a->g[0], a->g[1], a->ustar[0], a->ustar[1], a->Hn,
-                      a->rho_n, a->mu})
+                      a->rho_n, a->mu, a->mred})
         if (p) hipFree(p);
     if (a->host) hipHostFree(a->host);
     delete a;
@@ -340,6 +344,7 @@ extern "C" int ib_axi_create(const ib_grid* g, int max_markers, ib_axi** out) {
     }
     for (double** p : {&a->Hn, &a->rho_n, &a->mu}) ok = ok && hipMalloc((void**)p, half) == hipSuccess;
     ok = ok && hipMalloc((void**)&a->red, sizeof(double) * (2 * kAxiRed + 2)) == hipSuccess;
+    ok = ok && hipMalloc((void**)&a->mred, sizeof(double) * (kMeanParts + 1)) == hipSuccess;
     ok = ok && hipHostMalloc((void**)&a->host, 2 * sizeof(double)) == hipSuccess;
     if (!ok) {
         free_axi(a);
@@ -401,7 +406,8 @@ static int axi_solve_update(ib_axi* a, mg_handle* m, const ib_params* prm, ib_st
 // them, advance and relocation with the azimuthal curvature, H and F of the
 // doubled plane copied to the half plane (H, Fh)
 static int axi_interface(ib_axi* a, const ib_params* prm, ib_state* stt, ib_outputs* out,
-                         ib_surface* s, double* H, double* const Fh[2], hipStream_t st) {
+                         ib_surface* s, double* H, double* const Fh[2], hipStream_t st,
+                         const double* mass_target = nullptr, double* mass_delta = nullptr) {
     Ctx* F = a->full;
     const int nr = a->nr, nz = a->nz;
     const long N = (long)nr * nz;
@@ -409,7 +415,7 @@ static int axi_interface(ib_axi* a, const ib_params* prm, ib_state* stt, ib_outp
                        stt->u_star[1], nr, nz, a->ud[0], a->ud[1]);
     const double* udc[3] = {a->ud[0], a->ud[1], a->ud[1]};
     IB_TRY(launch_interp(F, udc, s, out->U, st));
-    IB_TRY(relocate_2d(F, prm, stt, out->U, out->fs_host, s, st, (double)nr * a->h));
+    IB_TRY(relocate_2d(F, prm, stt, out->U, out->fs_host, s, st, (double)nr * a->h, mass_target, mass_delta));
     double* Ff[3] = {F->F[0], F->F[1], F->F[1]};
     IB_TRY(spread_impl(F, s, IB_SPREAD_IRROT, Ff, F->H, st));
     const size_t row = sizeof(double) * nr, frow = 2 * row;
@@ -459,7 +465,7 @@ extern "C" int axi_project_step(ib_axi* a, mg_handle* m, const ib_params* prm, i
 
 static int axi_predict_impl(ib_axi* a, const double* const u[2], const double* rho_n,
                             const double* rho1, const double* mu, double dt, double rtol, int max_sweeps,
-                            double* const ustar[2], ib_flow_stats* S, hipStream_t st) {
+                            double* const ustar[2], ib_flow_stats* S, const Body& B, hipStream_t st) {
     const int nr = a->nr, nz = a->nz;
     const long N = (long)nr * nz;
     const double inv_dt = 1.0 / dt, h = a->h;
@@ -469,7 +475,8 @@ static int axi_predict_impl(ib_axi* a, const double* const u[2], const double* r
     for (int q = 0; q < 2; ++q)
         IB_HIP(hipMemcpyAsync(ustar[q], u[q], sizeof(double) * N, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_axi_pred_rhs, dim3(grid_for(N)), dim3(kBlock), 0, st, u[0], u[1], rho_n, rho1, mu,
-                       Ap[0], Ap[1], first, nr, nz, h, inv_dt, Ac[0], Ac[1], a->g[0], a->g[1]);
+                       Ap[0], Ap[1], first, nr, nz, h, inv_dt, Ac[0], Ac[1], a->g[0], a->g[1], B,
+                       B.on() ? 1 : 0);
     IB_HIP(hipGetLastError());
     a->cur ^= 1;
     a->have_adv = 1;
@@ -514,6 +521,7 @@ extern "C" int ib_axi_reset(ib_axi* a) {
     IB_CHECK(a, IB_EINVAL, "ib_axi_reset: null handle");
     a->have_adv = 0;
     a->have_H = 0;
+    a->ff = FreeFall();
     return IB_OK;
 }
 
@@ -526,8 +534,9 @@ extern "C" int axi_predict(ib_axi* a, const double* const u[2], const double* rh
         IB_CHECK(u[q] && u_star[q], IB_EINVAL, "axi_predict: null velocity array");
         IB_CHECK(u[q] != u_star[q], IB_EINVAL, "axi_predict: u_star may not alias u");
     }
-    ib_flow_stats loc;
-    return axi_predict_impl(a, u, rho_n, rho_np1, mu, dt, rtol, max_sweeps, u_star, stats ? stats : &loc,
+    ib_flow_stats loc{};
+    const Body none{0.0, 0.0, 0.0, nullptr};
+    return axi_predict_impl(a, u, rho_n, rho_np1, mu, dt, rtol, max_sweeps, u_star, stats ? stats : &loc, none,
                             (hipStream_t)stream);
 }
 
@@ -536,6 +545,7 @@ extern "C" int axi_flow_step(ib_axi* a, mg_handle* m, const ib_params* prm, cons
     IB_TRY(axi_check(a, m, prm, stt, out, "axi_flow_step"));
     IB_CHECK(fp && fp->mu_in >= 0 && fp->mu_out >= 0 && fp->rtol > 0 && fp->max_sweeps > 0, IB_EINVAL,
              "axi_flow_step: viscosities, rtol, max_sweeps");
+    IB_TRY(check_freefall(fp, "axi_flow_step"));
     hipStream_t st = (hipStream_t)stream;
     Ctx* F = a->full;
     Ctx* Hc = a->half;
@@ -558,14 +568,26 @@ extern "C" int axi_flow_step(ib_axi* a, mg_handle* m, const ib_params* prm, cons
     }
     double* H = out->H ? out->H : Hc->H;
     double* Fh[2] = {out->F[0] ? out->F[0] : Hc->F[0], out->F[1] ? out->F[1] : Hc->F[1]};
-    IB_TRY(axi_interface(a, prm, stt, out, &s, H, Fh, st));
+    ib_flow_stats loc{};
+    ib_flow_stats* FS = fstats ? fstats : &loc;
+    const double* mass_target = nullptr;
+    const double axis_x = (double)nr * a->h;
+    IB_CHECK(freefall_begin(&a->ff, fp, n, stt->X_host, axis_x, prm->dt, FS, &mass_target) == IB_OK, IB_EGEOM,
+             "axi_flow_step: the markers enclose no volume");
+    IB_TRY(axi_interface(a, prm, stt, out, &s, H, Fh, st, mass_target, &FS->mass_delta));
     IB_TRY(launch_coefficients(Hc, a->Hn, prm->rho_in, prm->rho_out, nullptr, a->rho_n, st));
     IB_TRY(launch_coefficients(Hc, H, fp->mu_in, fp->mu_out, nullptr, a->mu, st));
     IB_TRY(axi_coefficients(a, m, prm, H, Fh[0], st));
-    ib_flow_stats loc;
+    // body force with rho_mean the r-weighted volume mean of rho^{n+1}
+    // (sum over columns of (i + 1/2) h is h nr^2 / 2)
+    Body B{fp->gravity, FS->frame_a, 1.0 / ((double)nz * (0.5 * a->h * (double)nr * (double)nr)), nullptr};
+    if (fp->gravity != 0.0) {
+        IB_TRY(density_sum(Hc->rho, N, nr, a->h, 1, a->mred, a->mred + kMeanParts, st));
+        B.rsum = a->mred + kMeanParts;
+    }
     const double* un[2] = {stt->u_star[0], stt->u_star[1]};
     IB_TRY(axi_predict_impl(a, un, a->rho_n, Hc->rho, a->mu, prm->dt, fp->rtol, fp->max_sweeps, a->ustar,
-                            fstats ? fstats : &loc, st));
+                            FS, B, st));
     const double* us[2] = {a->ustar[0], a->ustar[1]};
     int rc = axi_solve_update(a, m, prm, stt, out, us, Fh, st);
     if (rc != IB_OK && rc != IB_ENOTCONV) return rc;

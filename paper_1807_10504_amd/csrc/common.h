@@ -7,6 +7,7 @@
 #include <string>
 
 #include "../../include/ibproj.h"
+#include "freefall.h"
 
 namespace ib {
 
@@ -82,6 +83,19 @@ __device__ inline double block_reduce_sum(double v, double* sh) {
     return r;
 }
 
+// body force density on the vertical faces of the free-fall runs:
+//   (rho_f - rho_mean) grav + rho_f fa,  rho_mean = *rsum * inv_w
+// (rsum: a device sum of the density; NULL when grav is 0)
+struct Body {
+    double grav, fa, inv_w;
+    const double* rsum;
+    __device__ double at(double rf) const {
+        const double rm = rsum ? *rsum * inv_w : 0.0;
+        return (rf - rm) * grav + rf * fa;
+    }
+    bool on() const { return grav != 0.0 || fa != 0.0; }
+};
+
 // fixed-point scale of the deterministic integer accumulation of Heaviside
 // contributions: 1.0 (a full cell) maps to 2^56
 constexpr double kFixScale = 72057594037927936.0;        // 2^56
@@ -154,8 +168,21 @@ int device_sum(const double* partials_in, int n, double* out_dev, hipStream_t st
 int spread_impl(Ctx* c, const ib_surface* s, int mode, double* const F[3], double* H, hipStream_t st);
 // axis_x: NaN, or the axis of a mirrored axisymmetric meridian curve (adds
 // the azimuthal curvature to sigma kappa)
+// mass_target: NULL, or the area / volume the relocated markers are corrected
+// to (ib_mass_correct; its displacement to *mass_delta when not NULL)
 int relocate_2d(Ctx* c, const ib_params* prm, ib_state* stt, const double* U_dev, double* fs_host,
-                ib_surface* s, hipStream_t st, double axis_x);
+                ib_surface* s, hipStream_t st, double axis_x, const double* mass_target,
+                double* mass_delta);
+
+// sum of rho over the cells (weighted == 0) or of rho (i + 1/2) h over the
+// cells of an nr-wide meridian plane (weighted == 1), into *out (device);
+// part holds at least kMeanParts partials
+constexpr int kMeanParts = 1024;
+int density_sum(const double* rho, long N, int nr, double h, int weighted, double* part, double* out,
+                hipStream_t st);
+
+// validation of the free-fall fields of ib_flow_params
+int check_freefall(const ib_flow_params* fp, const char* who);
 int coefficients_and_hierarchy(Ctx* c, mg_handle* m, const ib_params* prm, const double* H,
                                hipStream_t st);
 int solve_and_update(Ctx* c, mg_handle* m, const ib_params* prm, ib_state* stt, ib_outputs* out,

@@ -146,10 +146,12 @@ __global__ void k_viscous(Vec3 u, const double* __restrict__ mu, Dims d, Out3 V)
 
 // right side of the implicit system and the advection history:
 //   A = C(u^n);  g = rho_f/dt u^n - (A or 3/2 A - 1/2 A_prev) + D u^n / 2
+// (+ the body force on the y faces when body_on)
 template <int DIM>
 __global__ void k_pred_rhs(Vec3 u, const double* __restrict__ rho_n,
                            const double* __restrict__ rho1, const double* __restrict__ mu,
-                           Vec3 Aprev, int first, Dims d, double inv_dt, Out3 A, Out3 g) {
+                           Vec3 Aprev, int first, Dims d, double inv_dt, Out3 A, Out3 g, Body B,
+                           int body_on) {
     const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.cells()) return;
     const Sten<DIM> S = sten_of<DIM>(d, c);
@@ -163,8 +165,22 @@ __global__ void k_pred_rhs(Vec3 u, const double* __restrict__ rho_n,
         visc_coefs<DIM>(S, c, mu, q, mp, mm);
         const double vis = visc_sum<DIM>(S, c, u.p[q], mp, mm) * inv_h2;
         const double rf = 0.5 * (rho1[c] + rho1[S.at(q, -1)]);
-        g.p[q][c] = rf * inv_dt * u.p[q][c] - ab + 0.5 * vis;
+        double gv = rf * inv_dt * u.p[q][c] - ab + 0.5 * vis;
+        if (q == 1 && body_on) gv += B.at(rf);
+        g.p[q][c] = gv;
     }
+}
+
+// block partials of sum rho (weighted: sum rho (i + 1/2) h, i the column of
+// an nr-wide plane)
+__global__ void k_density_sum(const double* __restrict__ rho, long N, int nr, double h, int weighted,
+                              double* __restrict__ part) {
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long)gridDim.x * blockDim.x)
+        acc += weighted ? rho[c] * (((double)(c % nr) + 0.5) * h) : rho[c];
+    const double s = block_reduce_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 // one colour of a Gauss-Seidel sweep of (rho_f/dt - D/2) x = g, every component
@@ -250,6 +266,8 @@ struct ib_flow {
     int have_H = 0;
     double* red = nullptr;    // 2 * kFlowRed partials + 2 sums
     double* host = nullptr;   // pinned: the two sums
+    double* mred = nullptr;   // density-sum partials (kMeanParts) + the sum
+    FreeFall ff;
 };
 
 static void free_flow(ib_flow* f) {
@@ -261,7 +279,7 @@ static void free_flow(ib_flow* f) {
         if (f->g[q]) hipFree(f->g[q]);
         if (f->ustar[q]) hipFree(f->ustar[q]);
     }
-    for (double* p : {f->Hn, f->rho_n, f->mu, f->red})
+    for (double* p : {f->Hn, f->rho_n, f->mu, f->red, f->mred})
         if (p) hipFree(p);
     if (f->host) hipHostFree(f->host);
     delete f;
@@ -295,6 +313,7 @@ extern "C" int ib_flow_create(const ib_grid* g, ib_flow** out) {
     alloc(&f->rho_n, bytes);
     alloc(&f->mu, bytes);
     alloc(&f->red, sizeof(double) * (2 * kFlowRed + 2));
+    alloc(&f->mred, sizeof(double) * (kMeanParts + 1));
     if (ok && hipHostMalloc((void**)&f->host, 2 * sizeof(double)) != hipSuccess) ok = false;
     if (!ok) {
         free_flow(f);
@@ -310,6 +329,7 @@ extern "C" int ib_flow_reset(ib_flow* f) {
     IB_CHECK(f, IB_EINVAL, "ib_flow_reset: null handle");
     f->have_adv = 0;
     f->have_H = 0;
+    f->ff = FreeFall();
     return IB_OK;
 }
 
@@ -345,9 +365,30 @@ extern "C" int ib_viscous(ib_ctx* ctx, const double* const u[3], const double* m
     return IB_OK;
 }
 
+namespace ib {
+
+int density_sum(const double* rho, long N, int nr, double h, int weighted, double* part, double* out,
+                hipStream_t st) {
+    const int nb = (int)std::min<long>(kMeanParts, (long)grid_for(N));
+    hipLaunchKernelGGL(k_density_sum, dim3(nb), dim3(kBlock), 0, st, rho, N, nr, h, weighted, part);
+    IB_HIP(hipGetLastError());
+    return device_sum(part, nb, out, st);
+}
+
+int check_freefall(const ib_flow_params* fp, const char* who) {
+    IB_CHECK(std::isfinite(fp->gravity) && std::isfinite(fp->c1) && std::isfinite(fp->c2) &&
+                 (fp->frame == 0 || fp->frame == 1) && fp->mass_every >= 0 &&
+                 std::isfinite(fp->mass_target),
+             IB_EINVAL, std::string(who) + ": gravity, frame, c1, c2, mass_every, mass_target");
+    return IB_OK;
+}
+
+}  // namespace ib
+
 static int predict_impl(ib_flow* f, const double* const u[3], const double* rho_n,
                         const double* rho1, const double* mu, double dt, double rtol,
-                        int max_sweeps, double* const ustar[3], ib_flow_stats* S, hipStream_t st) {
+                        int max_sweeps, double* const ustar[3], ib_flow_stats* S, const Body& B,
+                        hipStream_t st) {
     const Dims& d = f->d;
     const int dim = d.dim;
     const long N = d.cells();
@@ -361,10 +402,10 @@ static int predict_impl(ib_flow* f, const double* const u[3], const double* rho_
         IB_HIP(hipMemcpyAsync(ustar[q], u[q], sizeof(double) * N, hipMemcpyDeviceToDevice, st));
     if (dim == 2)
         hipLaunchKernelGGL(k_pred_rhs<2>, g1, blk, 0, st, vec3(u, 2), rho_n, rho1, mu, vec3(Aprev, 2),
-                           first, d, inv_dt, out3(Acur, 2), out3(f->g, 2));
+                           first, d, inv_dt, out3(Acur, 2), out3(f->g, 2), B, B.on() ? 1 : 0);
     else
         hipLaunchKernelGGL(k_pred_rhs<3>, g1, blk, 0, st, vec3(u, 3), rho_n, rho1, mu, vec3(Aprev, 3),
-                           first, d, inv_dt, out3(Acur, 3), out3(f->g, 3));
+                           first, d, inv_dt, out3(Acur, 3), out3(f->g, 3), B, B.on() ? 1 : 0);
     IB_HIP(hipGetLastError());
     // the history advances whatever the solve does
     f->cur ^= 1;
@@ -429,8 +470,9 @@ extern "C" int ib_predict(ib_flow* f, const double* const u[3], const double* rh
         IB_CHECK(u[q] && u_star[q], IB_EINVAL, "ib_predict: null velocity array");
         IB_CHECK(u[q] != u_star[q], IB_EINVAL, "ib_predict: u_star may not alias u");
     }
-    ib_flow_stats loc;
-    return predict_impl(f, u, rho_n, rho_np1, mu, dt, rtol, max_sweeps, u_star, stats ? stats : &loc,
+    ib_flow_stats loc{};
+    const Body none{0.0, 0.0, 0.0, nullptr};
+    return predict_impl(f, u, rho_n, rho_np1, mu, dt, rtol, max_sweeps, u_star, stats ? stats : &loc, none,
                         (hipStream_t)stream);
 }
 
@@ -449,6 +491,7 @@ extern "C" int flow_step(ib_ctx* ctx, ib_flow* f, mg_handle* m, const ib_params*
              "flow_step: dt and densities must be positive");
     IB_CHECK(fp->mu_in >= 0 && fp->mu_out >= 0 && fp->rtol > 0 && fp->max_sweeps > 0, IB_EINVAL,
              "flow_step: viscosities, rtol, max_sweeps");
+    IB_TRY(check_freefall(fp, "flow_step"));
     IB_CHECK(prm->warm_start == WS_ZERO || prm->warm_start == WS_PREV, IB_EINVAL,
              "flow_step: warm start must be WS_ZERO or WS_PREV");
     IB_CHECK(prm->spread_mode == IB_SPREAD_IRROT || prm->spread_mode == IB_SPREAD_DELTA, IB_EINVAL,
@@ -471,9 +514,15 @@ extern "C" int flow_step(ib_ctx* ctx, ib_flow* f, mg_handle* m, const ib_params*
         IB_CHECK(fl[0] == 0, IB_EGEOM, "flow_step: an offset curve comes within 4h of the box sides");
         f->have_H = 1;
     }
-    // markers: interpolation of u^n, advance and relocation
+    // free fall: centroid and measure of the incoming markers
+    ib_flow_stats loc{};
+    ib_flow_stats* FS = fstats ? fstats : &loc;
+    const double* mass_target = nullptr;
+    IB_CHECK(freefall_begin(&f->ff, fp, n, stt->X_host, NAN, prm->dt, FS, &mass_target) == IB_OK, IB_EGEOM,
+             "flow_step: the markers enclose no area");
+    // markers: interpolation of u^n, advance, relocation (and mass correction)
     IB_TRY(launch_interp(c, stt->u_star, &s, out->U, st));
-    IB_TRY(relocate_2d(c, prm, stt, out->U, out->fs_host, &s, st, NAN));
+    IB_TRY(relocate_2d(c, prm, stt, out->U, out->fs_host, &s, st, NAN, mass_target, &FS->mass_delta));
     // H^{n+1} and the face force
     double* H = out->H ? out->H : c->H;
     double* F[3];
@@ -483,11 +532,14 @@ extern "C" int flow_step(ib_ctx* ctx, ib_flow* f, mg_handle* m, const ib_params*
     IB_TRY(launch_coefficients(c, f->Hn, prm->rho_in, prm->rho_out, nullptr, f->rho_n, st));
     IB_TRY(launch_coefficients(c, H, fp->mu_in, fp->mu_out, nullptr, f->mu, st));
     IB_TRY(coefficients_and_hierarchy(c, m, prm, H, st));
-    // predictor
-    ib_flow_stats loc;
-    ib_flow_stats* FS = fstats ? fstats : &loc;
+    // predictor, with the body force (rho_mean: volume mean of rho^{n+1})
+    Body B{fp->gravity, FS->frame_a, 1.0 / (double)N, nullptr};
+    if (fp->gravity != 0.0) {
+        IB_TRY(density_sum(c->rho, N, c->d.nx, c->d.h, 0, f->mred, f->mred + kMeanParts, st));
+        B.rsum = f->mred + kMeanParts;
+    }
     IB_TRY(predict_impl(f, stt->u_star, f->rho_n, c->rho, f->mu, prm->dt, fp->rtol, fp->max_sweeps,
-                        f->ustar, FS, st));
+                        f->ustar, FS, B, st));
     // projection of u*
     const double* us[3] = {f->ustar[0], f->ustar[1], f->ustar[1]};
     int rc = solve_and_update(c, m, prm, stt, out, us, H, F, st);

@@ -31,7 +31,7 @@ EXPORTS = ("ib_create", "ib_destroy", "ib_bin_markers", "ib_interp", "ib_spread"
            "ib_diagnostics", "ib_profile_enable", "ib_profile_reset", "ib_profile_read",
            "ib_advection", "ib_viscous", "ib_flow_create", "ib_flow_destroy", "ib_flow_reset",
            "ib_predict", "flow_step", "ib_axi_create", "ib_axi_destroy", "axi_project_step",
-           "ib_axi_reset", "axi_predict", "axi_flow_step",
+           "ib_axi_reset", "axi_predict", "axi_flow_step", "ib_enclosed_measure", "ib_mass_correct",
            "ib_last_error")
 
 PROF_KINDS = ("smooth64", "smooth32", "restrict64", "restrict32", "prolong64", "prolong32", "resid",
@@ -86,15 +86,38 @@ class Outputs(C.Structure):
 
 
 class FlowStats(C.Structure):
-    _fields_ = [("sweeps", C.c_int), ("rel_res", C.c_double), ("first_step", C.c_int)]
+    _fields_ = [("sweeps", C.c_int), ("rel_res", C.c_double), ("first_step", C.c_int),
+                ("frame_a", C.c_double), ("com", C.c_double), ("measure", C.c_double),
+                ("mass_delta", C.c_double)]
 
     def as_dict(self):
-        return dict(sweeps=self.sweeps, rel_res=self.rel_res, first_step=self.first_step)
+        return dict(sweeps=self.sweeps, rel_res=self.rel_res, first_step=self.first_step,
+                    frame_a=self.frame_a, com=self.com, measure=self.measure,
+                    mass_delta=self.mass_delta)
 
 
 class FlowParams(C.Structure):
     _fields_ = [("mu_in", C.c_double), ("mu_out", C.c_double), ("rtol", C.c_double),
-                ("max_sweeps", C.c_int)]
+                ("max_sweeps", C.c_int), ("gravity", C.c_double), ("frame", C.c_int),
+                ("c1", C.c_double), ("c2", C.c_double), ("mass_every", C.c_int),
+                ("mass_target", C.c_double)]
+
+    @staticmethod
+    def from_dict(params):
+        """mu_in, mu_out, pred_rtol, pred_max_sweeps; free fall: gravity, frame (bool),
+        c1, c2 (0.1 each by default), mass_every, mass_target (0: the first step's)."""
+        fp = FlowParams()
+        fp.mu_in = params.get("mu_in", 0.0)
+        fp.mu_out = params.get("mu_out", 0.0)
+        fp.rtol = params.get("pred_rtol", 1e-12)
+        fp.max_sweeps = params.get("pred_max_sweeps", 200)
+        fp.gravity = params.get("gravity", 0.0)
+        fp.frame = 1 if params.get("frame", False) else 0
+        fp.c1 = params.get("c1", 0.1)
+        fp.c2 = params.get("c2", 0.1)
+        fp.mass_every = int(params.get("mass_every", 0))
+        fp.mass_target = params.get("mass_target", 0.0)
+        return fp
 
 
 class Diag(C.Structure):
@@ -164,6 +187,8 @@ def load(path: str = LIB_PATH):
         "ib_axi_reset": (i32, [vp]),
         "axi_predict": (i32, [vp, vp * 2, vp, vp, vp, f64, f64, i32, vp * 2, P(FlowStats), vp]),
         "axi_flow_step": (i32, [vp, vp, P(Params), P(FlowParams), P(State), P(Outputs), P(FlowStats), vp]),
+        "ib_enclosed_measure": (i32, [i32, vp, f64, P(f64), P(f64)]),
+        "ib_mass_correct": (i32, [i32, vp, vp, f64, f64, f64, f64, f64, P(f64)]),
         "ib_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -429,15 +454,12 @@ class Context:
                   out=None):
         """One step of the full 2D method: markers advanced with u^n (X_host, numpy N x 2,
         updated in place), H and force of the new markers, predictor (params: mu_in,
-        mu_out, pred_rtol, pred_max_sweeps), projection. Returns the outputs dict with
+        mu_out, pred_rtol, pred_max_sweeps; free fall: gravity, frame, c1, c2,
+        mass_every -- FlowParams.from_dict), projection. Returns the outputs dict with
         'stats' (multigrid) and 'flow' (predictor)."""
         import torch
         prm = self._params(params, p_prev)
-        fp = FlowParams()
-        fp.mu_in = params.get("mu_in", 0.0)
-        fp.mu_out = params.get("mu_out", 0.0)
-        fp.rtol = params.get("pred_rtol", 1e-12)
-        fp.max_sweeps = params.get("pred_max_sweeps", 200)
+        fp = FlowParams.from_dict(params)
         st = State()
         st.u_star = _vec3(u, torch.float64)
         st.p_prev = _dptr(p_prev, torch.float64)
@@ -555,11 +577,7 @@ class Axisym:
         """One full axisymmetric step (params as Context.flow_step)."""
         import torch
         prm = Context._params(params, p_prev)
-        fp = FlowParams()
-        fp.mu_in = params.get("mu_in", 0.0)
-        fp.mu_out = params.get("mu_out", 0.0)
-        fp.rtol = params.get("pred_rtol", 1e-12)
-        fp.max_sweeps = params.get("pred_max_sweeps", 200)
+        fp = FlowParams.from_dict(params)
         st = State()
         st.u_star = _vec3(u, torch.float64)
         st.p_prev = _dptr(p_prev, torch.float64)
@@ -748,6 +766,30 @@ def relocate_bspline(X, U, dt, h, sigma):
     _check(lib.ib_relocate_bspline(n, _hptr(X), _hptr(U), dt, h, sigma, _hptr(Xo), _hptr(fs),
                                    _hptr(ds), _hptr(nrm)))
     return Xo, fs, ds, nrm
+
+
+def enclosed_measure(X, axis_x=None):
+    """(enclosed area, vertical centroid) of the closed polygon X, or (volume of
+    revolution about x = axis_x, axial centroid) of the mirrored meridian curve."""
+    lib = load()
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    v, c = C.c_double(), C.c_double()
+    _check(lib.ib_enclosed_measure(X.shape[0], _hptr(X), float("nan") if axis_x is None else float(axis_x),
+                                   C.byref(v), C.byref(c)))
+    return v.value, c.value
+
+
+def mass_correct(X, nrm, target, axis_x=None, h=1.0, trigger=1e-6, tol=1e-12):
+    """Markers moved along their normals back to the enclosed measure `target`;
+    returns (X corrected, displacement)."""
+    lib = load()
+    Xc = np.array(X, dtype=np.float64, order="C")
+    nrm = np.ascontiguousarray(nrm, dtype=np.float64)
+    d = C.c_double()
+    _check(lib.ib_mass_correct(Xc.shape[0], _hptr(Xc), _hptr(nrm), float(target),
+                               float("nan") if axis_x is None else float(axis_x), float(h), float(trigger),
+                               float(tol), C.byref(d)))
+    return Xc, d.value
 
 
 def surface_geometry_3d(V, T, sigma):

@@ -86,3 +86,38 @@ def test_surface_geometry_3d_matches_oracle(level):
     assert np.max(np.abs(fs - fo)) <= 1e-12 * np.max(np.abs(fo))
     assert np.max(np.abs(ds - Ao)) <= 1e-14 * np.max(Ao)
     assert np.max(np.abs(nrm - no)) <= 1e-13
+
+
+@pytest.mark.parametrize("axis", [None, 0.5])
+def test_enclosed_measure_matches_oracle(axis):
+    from oracle import dynamics
+    for X in (W.circle_markers(256, 0.25), W.mode_shape(256, 0.2, 0.1), W.ellipse_markers(200, 0.2, 1.1)):
+        v, c = ibproj.enclosed_measure(X, axis)
+        vo, co = dynamics.measure(X, axis)
+        assert abs(v - vo) <= 1e-13 * abs(vo) and abs(c - co) <= 1e-13
+    with pytest.raises(ibproj.IbError) as e:
+        ibproj.enclosed_measure(np.zeros((2, 2)), axis)
+    assert e.value.code == ibproj.IB_EINVAL
+
+
+@pytest.mark.parametrize("axis", [None, 0.5])
+def test_mass_correction_matches_oracle(axis):
+    """The relocation's normals point into the drop, so a shrunk drop takes a
+    negative displacement; the host correction agrees with the oracle's."""
+    from oracle import dynamics
+    X0 = W.circle_markers(256, 0.25)
+    h = 1 / 64
+    _, _, _, nrm = ibproj.relocate_bspline(X0, np.zeros_like(X0), 0.0, h, 1.0)
+    assert np.all(np.sum(nrm * (np.array([0.5, 0.5]) - X0), axis=1) > 0)
+    target, _ = dynamics.measure(X0, axis)
+    for s in (2e-4, -1e-4):
+        X = X0 + s * nrm
+        Xc, d = ibproj.mass_correct(X, nrm, target, axis, h)
+        Xo, do = dynamics.mass_correct(X, nrm, target, axis, h)
+        assert abs(dynamics.measure(Xc, axis)[0] - target) <= 2e-12 * target
+        assert abs(d - do) <= 1e-11 and abs(d + s) <= 1e-9
+        assert np.max(np.abs(Xc - Xo)) <= 1e-11
+    Xc, d = ibproj.mass_correct(X0 + 1e-10 * nrm, nrm, target, axis, h)
+    assert d == 0.0
+    with pytest.raises(ibproj.IbError):
+        ibproj.mass_correct(X0, nrm, -1.0, axis, h)

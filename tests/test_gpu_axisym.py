@@ -189,6 +189,50 @@ def test_axi_flow_step_parity(ib):
         assert eu <= 1e-9 and ep <= 1e-10 and ex <= 1e-12
 
 
+def test_axi_flow_step_freefall_parity(ib):
+    """Weight, restoring frame and mass correction (a volume 2e-4 above the
+    initial one) on the meridian plane over three steps against the oracle."""
+    from oracle import dynamics, heaviside
+    nr, nz = 32, 64
+    h = 1.0 / 32
+    dt = 1e-4
+    axis = nr * h
+    X0 = W.ellipse_markers(128, 0.25, 1.1, centre=(axis, 1.0))
+    V0, c0 = dynamics.measure(X0, axis)
+    target = V0 * (1 + 2e-4)
+    prm = dict(rho_in=1.0, rho_out=1e-3, mu_in=1e-2, mu_out=1e-4, sigma=1.0, dt=dt, rtol=1e-12,
+               pred_rtol=1e-13, warm_start=ib.WS_PREV, gravity=-5.0, frame=True, mass_every=1,
+               mass_target=target)
+    ax = ib.Axisym(nr, nz, h, max_markers=256)
+    mg = ib.Multigrid(2, (nr, nz), h)
+    u = [torch.zeros((nz, nr), dtype=torch.float64, device="cuda") for _ in range(2)]
+    p = torch.zeros((nz, nr), dtype=torch.float64, device="cuda")
+    Xg = X0.copy()
+    uo = [np.zeros((nz, nr)), np.zeros((nz, nr))]
+    Xo = X0.copy()
+    Ho = heaviside.heaviside_2d(Xo, (2 * nr, nz), h)[:, nr:]
+    advo, po, c_prev = None, None, c0
+    for step in range(3):
+        _, c = dynamics.measure(Xo, axis)
+        a = dynamics.frame_acceleration(c0, c_prev, c, dt)
+        c_prev = c
+        out = ax.flow_step(mg, prm, u, Xg, p_prev=p, out={"p": p, "u": u})
+        r = oaxi.flow_step(nr, nz, h, 1.0, 1e-3, 1e-2, 1e-4, 1.0, dt, uo, Xo, Ho, adv_prev=advo,
+                           p_prev=po, rtol=1e-12, gravity=-5.0, frame_a=a, mass_target=target)
+        uo, Xo, Ho, advo, po = r["u"], r["X"], r["H"], r["adv"], r["p"]
+        f = out["flow"]
+        eu = max(np.abs(host(u[d]) - uo[d]).max() for d in range(2)) / max(np.abs(x).max() for x in uo)
+        ep = np.linalg.norm(host(p) - po) / np.linalg.norm(po)
+        ex = np.abs(Xg - Xo).max()
+        print(f"step {step}: frame a {f['frame_a']:.3e} (oracle {a:.3e}), mass delta {f['mass_delta']:.2e}, "
+              f"|du|/|u| {eu:.1e}, p {ep:.1e}, X {ex:.1e}", flush=True)
+        assert abs(f["frame_a"] - a) <= 1e-7 and abs(f["com"] - c) <= 1e-12
+        assert (f["mass_delta"] != 0.0) == (step == 0)
+        # restored to 1e-12 by the correction, then within its trigger (1e-6)
+        assert abs(dynamics.measure(Xg, axis)[0] - target) <= (2e-12 if step == 0 else 1e-6) * target
+        assert eu <= 1e-9 and ep <= 1e-10 and ex <= 1e-12
+
+
 def test_axi_oscillating_drop_period(ib):
     """Table osc, axisymmetric rows: the drop on the axis stretched by 1.03
     along r (eq osc), h = 0.01, rho 1 / 0.01, mu 0.01 / 1e-5; the first-cycle

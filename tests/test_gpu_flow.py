@@ -175,6 +175,56 @@ def test_flow_step_parity_2d(ib):
         assert eu <= 1e-9 and ep <= 1e-10 and ex <= 1e-12
 
 
+def test_flow_step_freefall_parity_2d(ib):
+    """Weight (rho - rho_mean) g, the restoring frame acceleration and the mass
+    correction (restoring an area 2e-4 above the initial one) over three steps
+    against the oracle, which takes the frame acceleration and the target from
+    the harness."""
+    from oracle import dynamics, heaviside
+    n = (64, 64)
+    h = 1.0 / 64
+    dt = 1e-4
+    X0 = W.ellipse_markers(128, 0.25, 1.1)
+    V0, c0 = dynamics.measure(X0)
+    target = V0 * (1 + 2e-4)
+    prm = dict(rho_in=1.0, rho_out=1e-3, mu_in=1e-2, mu_out=1e-4, sigma=1.0, dt=dt, rtol=1e-12,
+               pred_rtol=1e-13, warm_start=ib.WS_PREV, gravity=-5.0, frame=True, mass_every=1,
+               mass_target=target)
+    ctx = ib.Context(2, n, h, max_markers=256)
+    mg = ib.Multigrid(2, n, h)
+    fl = ib.Flow(2, n, h)
+    u = [torch.zeros((64, 64), dtype=torch.float64, device="cuda") for _ in range(2)]
+    p = torch.zeros((64, 64), dtype=torch.float64, device="cuda")
+    Xg = X0.copy()
+    uo = [np.zeros((64, 64)) for _ in range(2)]
+    Xo = X0.copy()
+    Ho = heaviside.heaviside_2d(Xo, n, h)
+    advo, po, c_prev = None, None, c0
+    for step in range(3):
+        _, c = dynamics.measure(Xo)
+        a = dynamics.frame_acceleration(c0, c_prev, c, dt)
+        c_prev = c
+        out = ctx.flow_step(mg, fl, prm, u, Xg, p_prev=p, out={"p": p, "u": u})
+        r = oflow.flow_step_2d(n, h, 1.0, 1e-3, 1e-2, 1e-4, 1.0, dt, uo, Xo, Ho, adv_prev=advo,
+                               p_prev=po, rtol=1e-12, gravity=-5.0, frame_a=a, mass_target=target)
+        uo, Xo, Ho, advo, po = r["u"], r["X"], r["H"], r["adv"], r["p"]
+        f = out["flow"]
+        eu = max(np.abs(host(u[d]) - uo[d]).max() for d in range(2)) / max(np.abs(x).max() for x in uo)
+        ep = rel_l2(host(p), po)
+        ex = np.abs(Xg - Xo).max()
+        print(f"step {step}: frame a {f['frame_a']:.3e} (oracle {a:.3e}), mass delta {f['mass_delta']:.2e}, "
+              f"|du|/|u| {eu:.1e}, p {ep:.1e}, X {ex:.1e}", flush=True)
+        assert abs(f["frame_a"] - a) <= 1e-7 and abs(f["com"] - c) <= 1e-12
+        assert (f["mass_delta"] != 0.0) == (step == 0)
+        # restored to 1e-12 by the correction, then within its trigger (1e-6)
+        assert abs(dynamics.measure(Xg)[0] - target) <= (2e-12 if step == 0 else 1e-6) * target
+        assert eu <= 1e-9 and ep <= 1e-10 and ex <= 1e-12
+    # the light fluid rises, the drop sinks: net vertical momentum of the box stays ~0
+    rho = poisson.density(Ho, 1.0, 1e-3)
+    mom = float(np.sum(oflow.face_density(rho, 2, 1) * host(u[1])))
+    assert abs(mom) <= 1e-3 * float(np.sum(oflow.face_density(rho, 2, 1) * np.abs(host(u[1]))))
+
+
 def test_flow_step_errors(ib):
     ctx3 = ib.Context(3, (16, 16, 16), 1 / 16, max_markers=16)
     mg3 = ib.Multigrid(3, (16, 16, 16), 1 / 16)
