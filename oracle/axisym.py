@@ -132,13 +132,14 @@ def project_step(nr, nz, h, rho_in, rho_out, sigma, dt, u_star, Xd, rtol=1e-10, 
 # Control volumes (per radian): u_r of face (i, k) spans r in [r_i - h/2,
 # r_i + h/2], volume r_i h^2; u_z of face (i, k) is the cell's column, volume
 # r_c h^2. Fluxes through each side carry its radius as area factor.
-#   C_r = [r_c(i) rho(i) ur_c(i)^2 - r_c(i-1) rho(i-1) ur_c(i-1)^2] / (r_i h)
-#         + [rho_e uz_e ur_e |top - |bottom] / h,
-#   C_z = [r_{i+1} rho_e ur_e uz_e |right - r_i rho_e ur_e uz_e |left] / (r_c h)
-#         + [rho(k) uz_c(k)^2 - rho(k-1) uz_c(k-1)^2] / h,
-# with cell means ur_c(i) = (u_r(i) + u_r(i+1))/2, uz_c(k) = (u_z(k) + u_z(k+1))/2
-# and edge values the means of the two faces meeting there (rho_e: the four
-# cells around the edge). The viscous stress is the vector Laplacian form of
+#   C_r = rho_f { [r_c(i) ur_c(i)^2 - r_c(i-1) ur_c(i-1)^2] / (r_i h)
+#                 + [uz_e ur_e |top - |bottom] / h },
+#   C_z = rho_f { [r_{i+1} ur_e uz_e |right - r_i ur_e uz_e |left] / (r_c h)
+#                 + [uz_c(k)^2 - uz_c(k-1)^2] / h },
+# with cell means ur_c(i) = (u_r(i) + u_r(i+1))/2, uz_c(k) = (u_z(k) + u_z(k+1))/2,
+# edge values the means of the two faces meeting there, and rho_f the mean of
+# the two cells of the face (the density outside the divergence, as in the
+# planar predictor). The viscous stress is the vector Laplacian form of
 # div(mu grad u) per component, with the hoop term of u_r:
 #   D_r = [r_c(i) mu(i) (u_r(i+1) - u_r(i)) - r_c(i-1) mu(i-1) (u_r(i) - u_r(i-1))] / (r_i h^2)
 #         + [mu_e (u_r(k+1) - u_r(k)) |top - mu_e (u_r(k) - u_r(k-1)) |bottom] / h^2
@@ -158,25 +159,23 @@ def advection(u, rho, h):
     # C_r on face (i, k)
     urc = 0.5 * (ur + R(ur, 1))                  # cell i mean (wall face of the last column is 0)
     rcv = rc[None, :]
-    flux_c = rcv * rho * urc * urc               # at cell i
+    flux_c = rcv * urc * urc                     # at cell i
     radial = (flux_c - R(flux_c, -1)) / np.where(ri > 0, ri, 1.0)[None, :]
     # top edge of face (i, k): between cells (i-1, k), (i, k), (i-1, k+1), (i, k+1)
     uz_e = 0.5 * (Z(uz, 1) + Z(R(uz, -1), 1))
     ur_e = 0.5 * (ur + Z(ur, 1))
-    rho_e = 0.25 * (rho + R(rho, -1) + Z(rho, 1) + Z(R(rho, -1), 1))
-    ftop = rho_e * uz_e * ur_e
-    Cr = (radial + ftop - Z(ftop, -1)) / h
+    ftop = uz_e * ur_e
+    Cr = 0.5 * (rho + R(rho, -1)) * (radial + ftop - Z(ftop, -1)) / h
     Cr[:, 0] = 0.0
     # C_z on face (i, k): right edge between cells (i, k-1), (i+1, k-1), (i, k), (i+1, k)
     ur_e2 = 0.5 * (R(ur, 1) + Z(R(ur, 1), -1))
     uz_e2 = 0.5 * (uz + R(uz, 1))
-    rho_e2 = 0.25 * (rho + R(rho, 1) + Z(rho, -1) + Z(R(rho, 1), -1))
     rip = (ri + h)[None, :]
-    fr = rip * rho_e2 * ur_e2 * uz_e2            # right edge (zero at the wall: u_r = 0 there)
+    fr = rip * ur_e2 * uz_e2                     # right edge (zero at the wall: u_r = 0 there)
     fl = R(fr, -1) * (ri > 0)[None, :]           # left edge = right edge of column i - 1; zero on the axis
     uzc = 0.5 * (uz + Z(uz, 1))
-    fz = rho * uzc * uzc
-    Cz = ((fr - fl) / rcv + fz - Z(fz, -1)) / h
+    fz = uzc * uzc
+    Cz = 0.5 * (rho + Z(rho, -1)) * ((fr - fl) / rcv + fz - Z(fz, -1)) / h
     return [Cr, Cz]
 
 
