@@ -268,6 +268,76 @@ def _osc_run(ib, torch, axis, n, h, dt, steps, markers):
                 mean_cycles=round(float(np.mean(cycles)), 2))
 
 
+def _osc_history(ib, torch, spread_mode, beta, steps, every, n=256, h=0.01, dt=1e-4, markers=256):
+    """The Table osc drop (reading of Section 5.2: R = 0.2, rho 1/0.01, mu 0.01/1e-5,
+    sigma 1) stretched by beta, full flow steps with the irrotational or the
+    conventional spreading; every `every` steps: TKE (eq tke), the axis ratio, and
+    |sum of the grid force| / sum over markers of |sigma kappa| ds."""
+    from paper_1807_10504_amd import workloads as W
+    prm = dict(rho_in=1.0, rho_out=0.01, mu_in=0.01, mu_out=1e-5, sigma=1.0, dt=dt, rtol=1e-10,
+               pred_rtol=1e-12, warm_start=ib.WS_PREV, spread_mode=spread_mode)
+    mg = ib.Multigrid(2, (n, n), h, krylov=1)
+    X = W.ellipse_markers(markers, 0.2, beta, centre=(0.5 * n * h, 0.5 * n * h))
+    ctx = ib.Context(2, (n, n), h, max_markers=markers)
+    fl = ib.Flow(2, (n, n), h)
+    u = [torch.zeros((n, n), dtype=torch.float64, device="cuda") for _ in range(2)]
+    p = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    F = [torch.zeros((n, n), dtype=torch.float64, device="cuda") for _ in range(2)]
+    fs = np.zeros(markers)
+    out = {"p": p, "u": u, "F": F, "fs_host": fs}
+    hist = dict(t=[], tke=[], axis_ratio=[], force_ratio=[])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        out = ctx.flow_step(mg, fl, prm, u, X, p_prev=p, out=out)
+        if (k + 1) % every == 0:
+            d = ctx.diagnostics(u=u, F=F)
+            edge = np.linalg.norm(np.roll(X, -1, 0) - X, axis=1)
+            ds = 0.5 * (edge + np.roll(edge, 1))
+            hist["t"].append(round((k + 1) * dt, 6))
+            hist["tke"].append(float(f"{d['tke']:.4e}"))
+            hist["axis_ratio"].append(round(float(np.ptp(X[:, 0]) / np.ptp(X[:, 1])), 5))
+            hist["force_ratio"].append(float(f"{np.hypot(*d['force_sum'][:2]) / np.sum(np.abs(fs) * ds):.3e}"))
+    torch.cuda.synchronize()
+    hist["steps_per_s"] = round(steps / (time.perf_counter() - t0), 2)
+    return hist
+
+
+def bench_osc_energy(ib, torch, steps=10000, every=100):
+    """Eq tke over the first second of the Table osc drop (h = 0.01) with the new and
+    the conventional spreading (the paper's TKE figure: the new scheme's decays, the
+    conventional one's is held up by parasitic currents), per 0.2 s window its mean
+    and its floor (the minimum, where the oscillation's kinetic energy passes
+    through zero); and the large deformation beta = 1.3 with its grid-force ratio
+    (the paper: at most of order 1e-4)."""
+    res = {}
+    win = max(1, int(round(0.2 / (every * 1e-4))))
+    for name, mode in (("new", ib.IB_SPREAD_IRROT), ("conventional", ib.IB_SPREAD_DELTA)):
+        r = _osc_history(ib, torch, mode, 1.03, steps, every)
+        tke = np.array(r["tke"])
+        res[f"tke_{name}"] = dict(
+            window_s=0.2, steps_per_s=r["steps_per_s"],
+            mean=[float(f"{tke[k:k + win].mean():.3e}") for k in range(0, len(tke), win)],
+            floor=[float(f"{tke[k:k + win].min():.3e}") for k in range(0, len(tke), win)],
+            force_ratio_max=max(r["force_ratio"]))
+        log(f"  TKE {name}: window means {res[f'tke_{name}']['mean']}, floors {res[f'tke_{name}']['floor']}, "
+            f"{r['steps_per_s']} steps/s")
+    res["floor_ratio_conventional_over_new"] = [round(c / n, 2) for c, n in
+                                                zip(res["tke_conventional"]["floor"], res["tke_new"]["floor"])]
+    r = _osc_history(ib, torch, ib.IB_SPREAD_IRROT, 1.3, 4000, 50)
+    res["deform_beta1.3"] = dict(steps=4000, t_end=0.4, steps_per_s=r["steps_per_s"],
+                                 axis_ratio_min=min(r["axis_ratio"]), axis_ratio_max=max(r["axis_ratio"]),
+                                 force_ratio_max=max(r["force_ratio"]),
+                                 force_ratio_mean=float(f"{np.mean(r['force_ratio']):.3e}"))
+    log(f"  beta 1.3: axis ratio {min(r['axis_ratio'])} .. {max(r['axis_ratio'])}, force ratio max "
+        f"{max(r['force_ratio']):.2e}")
+    res["workload"] = ("Table osc drop (R=0.2, rho 1/0.01, mu 0.01/1e-5, sigma 1) at h=0.01 on 256^2, dt 1e-4, "
+                       "256 markers: beta 1.03 for 1 s with the new and the conventional spreading (eq tke every "
+                       "0.01 s), beta 1.3 for 0.4 s (axis ratio; |sum of grid force| / sum |sigma kappa| ds "
+                       "every 0.005 s)")
+    return res
+
+
 def bench_flow_osc(ib, torch):
     """Full flow steps (markers, H and force, momentum predictor, projection) on the
     free oscillation of Section 5.2 (Table osc), 2D and axisymmetric, at h = 0.01
@@ -738,6 +808,8 @@ def main():
         line["flow_osc"] = bench_flow_osc(ib, torch)
         log("== static drop tables (2D and axisymmetric)")
         line["static_tables"] = bench_static_tables(ib, torch)
+        log("== oscillating drop energy (new vs conventional) and large deformation")
+        line["osc_energy"] = bench_osc_energy(ib, torch)
         log("== free-fall drops (Table afd_param sets 1-2, axisymmetric)")
         line["free_fall"] = bench_free_fall(ib, torch)
         log(f"== momentum predictor at {args.size}^3")

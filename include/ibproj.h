@@ -266,13 +266,15 @@ int project_step(ib_ctx* ctx, mg_handle* m, const ib_params* prm, ib_state* st,
  * Momentum predictor (Section 2.1, eq ns1_new with the surface tension moved
  * to the projection):
  *   rho^{n+1}_f (u* - u^n)/dt = -(3/2 C(u^n) - 1/2 C(u^{n-1})) + 1/2 (D u* + D u^n)
- * Adams-Bashforth advection C (eq ad_bf), Crank-Nicolson viscous stress D
- * (eq cr_ni), per face component d on the periodic staggered grid:
- *   C_d = (1/h) sum_e [flux on the high side - flux on the low side along e],
- *     e = d: rho_cell ((u_d + u_d of the cell's other face)/2)^2 at the cells
- *            c and c - e_d;
- *     e != d: mean of the 4 cells around the edge x mean of the two u_e
- *            faces meeting at the edge x mean of the two u_d faces there;
+ * Adams-Bashforth advection C (eqs ns_1, ad_bf), Crank-Nicolson viscous
+ * stress D (eq cr_ni), per face component d on the periodic staggered grid:
+ *   C_d = rho_f (1/h) sum_e [flux on the high side - flux on the low side along e],
+ *     e = d: ((u_d + u_d of the cell's other face)/2)^2 at the cells c and
+ *            c - e_d;
+ *     e != d: mean of the two u_e faces meeting at the edge x mean of the two
+ *            u_d faces there;
+ *   the density stays outside the surface sum, as eq ns_1 writes rho div(u u)
+ *   (with rho inside, a moving interface would take a -u d rho/dt source);
  *   D_d = (1/h^2) sum_e [mu_+ (u_d(c+e_e) - u_d(c)) - mu_- (u_d(c) - u_d(c-e_e))],
  *     mu at the cells c, c - e_d for e = d, the 4-cell edge mean otherwise;
  *   rho_f = (rho_c + rho_{c-e_d})/2 (the projection's face density).
@@ -315,8 +317,8 @@ typedef struct {
                                 instead of the first step's */
 } ib_flow_params;
 
-/* C(u) of eq ad_bf for every component; rho: device cell densities. A may not
- * alias u. */
+/* C(u) as above for every component; rho: device cell densities (rho_f is
+ * the mean of the face's two cells). A may not alias u. */
 int ib_advection(ib_ctx* ctx, const double* const u[3], const double* rho, double* const A[3],
                  void* stream);
 
@@ -394,10 +396,11 @@ int  axi_project_step(ib_axi* a, mg_handle* m, const ib_params* prm, ib_state* s
 /* Momentum predictor on the meridian plane (eq ns1_new with eqs ad_bf and
  * cr_ni written on the annular control volumes, no swirl). With r_i = i h,
  * r_c = (i + 1/2) h, cell means ur_c(i) = (u_r(i) + u_r(i+1))/2,
- * uz_c(k) = (u_z(k) + u_z(k+1))/2 and edge values the means of the two faces
- * (four cells for rho and mu) meeting at the edge:
- *   C_r = [r_c(i) rho ur_c^2 |cell i - |cell i-1] / (r_i h) + [rho u_z u_r |top - |bottom] / h
- *   C_z = [r rho u_r u_z |right edge - |left edge] / (r_c h) + [rho uz_c^2 |cell k - |cell k-1] / h
+ * uz_c(k) = (u_z(k) + u_z(k+1))/2, edge values the means of the two faces
+ * (four cells for mu) meeting at the edge and rho_f the mean of the face's
+ * two cells (the density outside the surface sum, as in the planar form):
+ *   C_r = rho_f { [r_c(i) ur_c^2 |cell i - |cell i-1] / (r_i h) + [u_z u_r |top - |bottom] / h }
+ *   C_z = rho_f { [r u_r u_z |right edge - |left edge] / (r_c h) + [uz_c^2 |cell k - |cell k-1] / h }
  *   D_r = [r_c mu (u_r(i+1) - u_r(i)) - r_c mu (u_r(i) - u_r(i-1))] / (r_i h^2)
  *         + [mu_e du_r/dz |top - |bottom] / h - (mu(i-1) + mu(i))/2 u_r / r_i^2
  *   D_z = [r mu_e du_z/dr |right - |left] / (r_c h^2) + [mu du_z/dz |k - |k-1] / h

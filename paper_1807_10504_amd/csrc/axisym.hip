@@ -111,46 +111,46 @@ struct AxiIdx {
     }
 };
 
-// rho u_z u_r on the top edge of the u_r face (i, k + dk): cells i-1, i at k+dk, k+dk+1
-__device__ __forceinline__ double axi_ftop(const AxiIdx& X, int dk, const double* ur, const double* uz,
-                                           const double* rho) {
+// u_z u_r on the top edge of the u_r face (i, k + dk): cells i-1, i at k+dk, k+dk+1
+__device__ __forceinline__ double axi_ftop(const AxiIdx& X, int dk, const double* ur, const double* uz) {
     const double uze = 0.5 * (uz[X.at(0, dk + 1)] + uz[X.at(-1, dk + 1)]);
     const double ure = 0.5 * (ur[X.at(0, dk)] + ur[X.at(0, dk + 1)]);
-    const double re = 0.25 * (((rho[X.at(0, dk)] + rho[X.at(-1, dk)]) + rho[X.at(0, dk + 1)]) +
-                              rho[X.at(-1, dk + 1)]);
-    return re * uze * ure;
+    return uze * ure;
 }
 
-// r_{i+1+di} rho u_r u_z on the right edge of the u_z face (i + di, k)
+// r_{i+1+di} u_r u_z on the right edge of the u_z face (i + di, k)
 __device__ __forceinline__ double axi_fright(const AxiIdx& X, int di, double h, const double* ur,
-                                             const double* uz, const double* rho) {
+                                             const double* uz) {
     const double ure = 0.5 * (ur[X.at(di + 1, 0)] + ur[X.at(di + 1, -1)]);
     const double uze = 0.5 * (uz[X.at(di, 0)] + uz[X.at(di + 1, 0)]);
-    const double re = 0.25 * (((rho[X.at(di, 0)] + rho[X.at(di + 1, 0)]) + rho[X.at(di, -1)]) +
-                              rho[X.at(di + 1, -1)]);
-    return ((double)(X.i + di + 1) * h) * re * ure * uze;
+    return ((double)(X.i + di + 1) * h) * ure * uze;
 }
 
+// C_r and C_z: the face density times the annular surface sum of u u . ds
+// over the control volume (the density outside the divergence, as in the
+// planar predictor)
 __device__ double axi_adv_r(const AxiIdx& X, double h, const double* ur, const double* uz,
                             const double* rho) {
     const double ri = (double)X.i * h;
     const double u0 = 0.5 * (ur[X.c] + ur[X.at(1, 0)]);
     const double um = 0.5 * (ur[X.at(-1, 0)] + ur[X.c]);
-    const double fc = (((double)X.i + 0.5) * h) * rho[X.c] * u0 * u0;
-    const double fm = (((double)X.i - 0.5) * h) * rho[X.at(-1, 0)] * um * um;
+    const double fc = (((double)X.i + 0.5) * h) * u0 * u0;
+    const double fm = (((double)X.i - 0.5) * h) * um * um;
     const double radial = (fc - fm) / ri;
-    return (radial + (axi_ftop(X, 0, ur, uz, rho) - axi_ftop(X, -1, ur, uz, rho))) / h;
+    const double rf = 0.5 * (rho[X.c] + rho[X.at(-1, 0)]);
+    return rf * (radial + (axi_ftop(X, 0, ur, uz) - axi_ftop(X, -1, ur, uz))) / h;
 }
 
 __device__ double axi_adv_z(const AxiIdx& X, double h, const double* ur, const double* uz,
                             const double* rho) {
     const double rc = ((double)X.i + 0.5) * h;
-    const double fr = axi_fright(X, 0, h, ur, uz, rho);
-    const double fl = X.i > 0 ? axi_fright(X, -1, h, ur, uz, rho) : 0.0;
+    const double fr = axi_fright(X, 0, h, ur, uz);
+    const double fl = X.i > 0 ? axi_fright(X, -1, h, ur, uz) : 0.0;
     const double c0 = 0.5 * (uz[X.c] + uz[X.at(0, 1)]);
     const double cm = 0.5 * (uz[X.at(0, -1)] + uz[X.c]);
-    const double fz = rho[X.c] * c0 * c0 - rho[X.at(0, -1)] * cm * cm;
-    return ((fr - fl) / rc + fz) / h;
+    const double fz = c0 * c0 - cm * cm;
+    const double rf = 0.5 * (rho[X.c] + rho[X.at(0, -1)]);
+    return rf * ((fr - fl) / rc + fz) / h;
 }
 
 // viscous coefficients: D x = c[1] (x_r+ - x) - c[0] (x - x_r-) + c[3] (x_z+ - x)

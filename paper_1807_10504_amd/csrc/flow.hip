@@ -53,10 +53,11 @@ __device__ __forceinline__ Sten<DIM> sten_of(const Dims& d, long c) {
     return Sten<DIM>(d, i, j, k);
 }
 
-// C_d at the face of cell c (eq ad_bf), times h
+// surface sum of u u . ds over the control volume of the d-face of cell c
+// (eq ad_bf without the density), over h^(DIM-1); C_d is the face density
+// times this over h (eq ns_1 has rho outside the divergence)
 template <int DIM>
-__device__ double adv_flux_sum(const Sten<DIM>& S, long c, const double* const* u,
-                               const double* __restrict__ rho, int d) {
+__device__ double adv_flux_sum(const Sten<DIM>& S, long c, const double* const* u, int d) {
     const double* ud = u[d];
     const long cmd = S.at(d, -1);
     double acc = 0.0;
@@ -65,7 +66,7 @@ __device__ double adv_flux_sum(const Sten<DIM>& S, long c, const double* const* 
         if (e == d) {
             const double up = 0.5 * (ud[S.at(d, 1)] + ud[c]);
             const double um = 0.5 * (ud[c] + ud[cmd]);
-            acc += rho[c] * up * up - rho[cmd] * um * um;
+            acc += up * up - um * um;
         } else {
             const double* ue = u[e];
             const long cp = S.at(e, 1), cpd = S.at(e, 1, d, -1);
@@ -74,9 +75,7 @@ __device__ double adv_flux_sum(const Sten<DIM>& S, long c, const double* const* 
             const double udp = 0.5 * (ud[c] + ud[cp]);
             const double vem = 0.5 * (ue[c] + ue[cmd]);
             const double udm = 0.5 * (ud[c] + ud[cm]);
-            const double rp = 0.25 * (((rho[c] + rho[cmd]) + rho[cp]) + rho[cpd]);
-            const double rm = 0.25 * (((rho[c] + rho[cmd]) + rho[cm]) + rho[cmm]);
-            acc += rp * vep * udp - rm * vem * udm;
+            acc += vep * udp - vem * udm;
         }
     }
     return acc;
@@ -127,7 +126,8 @@ __global__ void k_advection(Vec3 u, const double* __restrict__ rho, Dims d, Out3
     const Sten<DIM> S = sten_of<DIM>(d, c);
     const double inv_h = 1.0 / d.h;
 #pragma unroll
-    for (int q = 0; q < DIM; ++q) A.p[q][c] = adv_flux_sum<DIM>(S, c, u.p, rho, q) * inv_h;
+    for (int q = 0; q < DIM; ++q)
+        A.p[q][c] = 0.5 * (rho[c] + rho[S.at(q, -1)]) * adv_flux_sum<DIM>(S, c, u.p, q) * inv_h;
 }
 
 template <int DIM>
@@ -158,7 +158,7 @@ __global__ void k_pred_rhs(Vec3 u, const double* __restrict__ rho_n,
     const double inv_h = 1.0 / d.h, inv_h2 = inv_h * inv_h;
 #pragma unroll
     for (int q = 0; q < DIM; ++q) {
-        const double a = adv_flux_sum<DIM>(S, c, u.p, rho_n, q) * inv_h;
+        const double a = 0.5 * (rho_n[c] + rho_n[S.at(q, -1)]) * adv_flux_sum<DIM>(S, c, u.p, q) * inv_h;
         A.p[q][c] = a;
         const double ab = first ? a : 1.5 * a - 0.5 * Aprev.p[q][c];
         double mp[3], mm[3];
