@@ -154,7 +154,8 @@ def predict(u, rho_n, rho_np1, mu, dt, h, adv_prev=None, f_body=None):
 
 
 def flow_step_2d(n, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, X, H_prev, adv_prev=None,
-                 p_prev=None, rtol=1e-10, max_cycles=100, gravity=0.0, frame_a=0.0, mass_target=None):
+                 p_prev=None, rtol=1e-10, max_cycles=100, gravity=0.0, frame_a=0.0, mass_target=None,
+                 conventional=False, indicator_density=False):
     """One step of the full 2D method (Section 2.1 fractional step, Section 2.2
     transfer, Section 3.2 irrotational force, Section 4 relocation):
       1. U = interpolation of u^n to the markers; markers advanced by dt U and
@@ -163,7 +164,11 @@ def flow_step_2d(n, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, X, H_prev, 
       3. rho^n from H_prev, rho^{n+1} and mu^{n+1} from H^{n+1};
       4. u* from the predictor (eq ns1_new);
       5. projection: b = div(u*/dt + beta F), multigrid, u^{n+1} = u* +
-         dt beta (F - grad p) (eqs ps, ns2_new)."""
+         dt beta (F - grad p) (eqs ps, ns2_new).
+    conventional: F is the marker force spread by the discrete delta function
+    (eq delta) instead of the irrotational one; indicator_density: rho^{n+1} and
+    mu^{n+1} follow the indicator of eq ind_psn instead of H. H_prev is the field
+    the previous step's properties followed (returned as 'prop')."""
     U = transfer.interp(u, X, h)
     Xn, fs, ds, nrm = bspline.relocate([tuple(x) for x in X], [tuple(v) for v in U], dt, h, sigma)
     Xn, fs = np.array(Xn), np.array(fs)
@@ -171,10 +176,17 @@ def flow_step_2d(n, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, X, H_prev, 
         from . import dynamics
         Xn, _ = dynamics.mass_correct(Xn, np.array(nrm), mass_target, None, h)
     H = heaviside.heaviside_2d(Xn, n, h)
-    F = force.irrotational_force(H, Xn, fs, h)
+    if conventional:
+        F = transfer.spread_delta(transfer.marker_forces(fs, ds, nrm), Xn, n, h)
+    else:
+        F = force.irrotational_force(H, Xn, fs, h)
+    prop = H
+    if indicator_density:
+        from . import indicator
+        prop = indicator.indicator(Xn, np.array(ds), np.array(nrm), n, h)
     rho_n = poisson.density(H_prev, rho_in, rho_out)
-    rho1 = poisson.density(H, rho_in, rho_out)
-    mu = poisson.density(H, mu_in, mu_out)
+    rho1 = poisson.density(prop, rho_in, rho_out)
+    mu = poisson.density(prop, mu_in, mu_out)
     f_body = None
     if gravity != 0.0 or frame_a != 0.0:
         from . import dynamics
@@ -185,4 +197,4 @@ def flow_step_2d(n, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, X, H_prev, 
     b = poisson.rhs(u_star, F, beta, dt, h)
     p, cycles, _ = poisson.mg_solve(b, beta, h, p0=p_prev, rtol=rtol, max_cycles=max_cycles)
     u_new = poisson.velocity_update(u_star, F, beta, p, dt, h)
-    return dict(U=U, X=Xn, fs=fs, H=H, F=F, u_star=u_star, adv=adv, p=p, u=u_new, cycles=cycles)
+    return dict(U=U, X=Xn, fs=fs, H=H, prop=prop, F=F, u_star=u_star, adv=adv, p=p, u=u_new, cycles=cycles)
