@@ -268,14 +268,16 @@ def _osc_run(ib, torch, axis, n, h, dt, steps, markers):
                 mean_cycles=round(float(np.mean(cycles)), 2))
 
 
-def _osc_history(ib, torch, spread_mode, beta, steps, every, n=256, h=0.01, dt=1e-4, markers=256):
+def _osc_history(ib, torch, spread_mode, beta, steps, every, n=256, h=0.01, dt=1e-4, markers=256,
+                 indicator_density=False):
     """The Table osc drop (reading of Section 5.2: R = 0.2, rho 1/0.01, mu 0.01/1e-5,
     sigma 1) stretched by beta, full flow steps with the irrotational or the
     conventional spreading; every `every` steps: TKE (eq tke), the axis ratio, and
     |sum of the grid force| / sum over markers of |sigma kappa| ds."""
     from paper_1807_10504_amd import workloads as W
     prm = dict(rho_in=1.0, rho_out=0.01, mu_in=0.01, mu_out=1e-5, sigma=1.0, dt=dt, rtol=1e-10,
-               pred_rtol=1e-12, warm_start=ib.WS_PREV, spread_mode=spread_mode)
+               pred_rtol=1e-12, warm_start=ib.WS_PREV, spread_mode=spread_mode,
+               indicator_density=indicator_density)
     mg = ib.Multigrid(2, (n, n), h, krylov=1)
     X = W.ellipse_markers(markers, 0.2, beta, centre=(0.5 * n * h, 0.5 * n * h))
     ctx = ib.Context(2, (n, n), h, max_markers=markers)
@@ -312,8 +314,9 @@ def bench_osc_energy(ib, torch, steps=10000, every=100):
     (the paper: at most of order 1e-4)."""
     res = {}
     win = max(1, int(round(0.2 / (every * 1e-4))))
-    for name, mode in (("new", ib.IB_SPREAD_IRROT), ("conventional", ib.IB_SPREAD_DELTA)):
-        r = _osc_history(ib, torch, mode, 1.03, steps, every)
+    for name, mode, ind in (("new", ib.IB_SPREAD_IRROT, False), ("conventional", ib.IB_SPREAD_DELTA, False),
+                            ("conventional_indicator", ib.IB_SPREAD_DELTA, True)):
+        r = _osc_history(ib, torch, mode, 1.03, steps, every, indicator_density=ind)
         tke = np.array(r["tke"])
         res[f"tke_{name}"] = dict(
             window_s=0.2, steps_per_s=r["steps_per_s"],
@@ -332,10 +335,53 @@ def bench_osc_energy(ib, torch, steps=10000, every=100):
     log(f"  beta 1.3: axis ratio {min(r['axis_ratio'])} .. {max(r['axis_ratio'])}, force ratio max "
         f"{max(r['force_ratio']):.2e}")
     res["workload"] = ("Table osc drop (R=0.2, rho 1/0.01, mu 0.01/1e-5, sigma 1) at h=0.01 on 256^2, dt 1e-4, "
-                       "256 markers: beta 1.03 for 1 s with the new and the conventional spreading (eq tke every "
+                       "256 markers: beta 1.03 for 1 s with the new and the conventional spreading (the latter "
+                       "also with the properties from the indicator of eq ind_psn; eq tke every "
                        "0.01 s), beta 1.3 for 0.4 s (axis ratio; |sum of grid force| / sum |sigma kappa| ds "
                        "every 0.005 s)")
     return res
+
+
+def bench_conventional(ib, torch):
+    """Section 3.1's curl study and the conventional indicator (eq ind_psn): for a
+    circle R = 0.2 with a unit inward force, max |index-form curl| / max |F| of the
+    split (conventional) and irrotational delta vectors, and the indicator's L1
+    distance to the smoothed Heaviside, h = 1/64 ... 1/1024; the indicator solve's
+    time (flexible-CG multigrid to 1e-10)."""
+    from paper_1807_10504_amd import workloads as W
+    rows = []
+    for nn in (64, 128, 256, 512, 1024):
+        h = 1.0 / nn
+        m = int(round(2 * np.pi * 0.2 / (0.5 * h)))
+        X0 = W.circle_markers(m, 0.2)
+        X, _, ds, nrm = ib.relocate_bspline(X0, np.zeros_like(X0), 0.0, h, 1.0)
+        t = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (X, np.ones(m), ds, nrm)]
+        surf = ib.Surface()
+        surf.n_markers, surf.X, surf.fs, surf.ds, surf.nrm = (m, t[0].data_ptr(), t[1].data_ptr(),
+                                                              t[2].data_ptr(), t[3].data_ptr())
+        ctx = ib.Context(2, (nn, nn), h, max_markers=m)
+        F, H = ctx.spread(surf, ib.IB_SPREAD_IRROT)
+        Fc, _ = ctx.spread(surf, ib.IB_SPREAD_DELTA, want_H=False)
+        d, dc = ctx.diagnostics(F=F), ctx.diagnostics(F=Fc)
+        ind = ib.Indicator((nn, nn), h, max_markers=m)
+        I, st = ind.solve(ctx, t[0], t[3], t[2], rtol=1e-10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            I, st = ind.solve(ctx, t[0], t[3], t[2], rtol=1e-10, I=I)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / 5
+        l1 = float((I - H).abs().sum()) * h * h
+        rows.append(dict(h=f"1/{nn}", curl_over_fmax_conventional=round(dc["curl_max"] / dc["f_max"], 5),
+                         curl_over_fmax_irrotational=float(f"{d['curl_max'] / d['f_max']:.2e}"),
+                         indicator_l1_vs_H=float(f"{l1:.4e}"), indicator_cg_iterations=st["cycles"],
+                         indicator_ms=round(ms, 3)))
+        log(f"  h=1/{nn}: curl/|F| conventional {rows[-1]['curl_over_fmax_conventional']}, irrotational "
+            f"{rows[-1]['curl_over_fmax_irrotational']}; L1 |I - H| {l1:.3e}; indicator {ms:.2f} ms")
+    for a, b in zip(rows, rows[1:]):
+        b["l1_ratio"] = round(a["indicator_l1_vs_H"] / b["indicator_l1_vs_H"], 3)
+    return dict(rows=rows, workload="circle R=0.2 centred in the unit periodic box, markers 0.5 h apart "
+                                    "(B-spline relocation), unit force toward the drop")
 
 
 def bench_flow_osc(ib, torch):
@@ -808,6 +854,8 @@ def main():
         line["flow_osc"] = bench_flow_osc(ib, torch)
         log("== static drop tables (2D and axisymmetric)")
         line["static_tables"] = bench_static_tables(ib, torch)
+        log("== conventional delta vector: curl versus h, indicator function")
+        line["conventional"] = bench_conventional(ib, torch)
         log("== oscillating drop energy (new vs conventional) and large deformation")
         line["osc_energy"] = bench_osc_energy(ib, torch)
         log("== free-fall drops (Table afd_param sets 1-2, axisymmetric)")

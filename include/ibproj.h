@@ -315,6 +315,13 @@ typedef struct {
                                 distance along their normals (bisection to 1e-12) */
     double mass_target;      /* > 0: the area / volume the correction restores
                                 instead of the first step's */
+    int indicator_density;   /* 1 (flow_step with IB_SPREAD_DELTA only): rho^{n+1}
+                                and mu^{n+1} follow the indicator of eq ind_psn
+                                (ib_indicator_solve to the projection's rtol)
+                                instead of H -- the conventional scheme of
+                                Section 2.2. The first such step creates the
+                                indicator's hierarchy in the flow handle; the
+                                first step after a reset takes rho^n from H. */
 } ib_flow_params;
 
 /* C(u) as above for every component; rho: device cell densities (rho_f is
@@ -436,6 +443,28 @@ int ib_relocate_bspline(int n, const double* X, const double* U, double dt, doub
                         double sigma, double* X_out, double* fs_out, double* ds_out,
                         double* nrm_out);
 
+/* ---------------------------------------------------------------------------
+ * Indicator function of the conventional scheme (Section 2.2, eqs indicator
+ * and ind_psn; the Poisson problem of eq poisson_delta in Section 3.1):
+ *   div grad I = div delta_vec,  delta_vec = sum_k n_k ds_k delta_h(x - X_k)
+ * (eq delta_vec with the unit normal toward the drop, spread as IB_SPREAD_DELTA),
+ * 5-point Laplacian of the projection, periodic; the free constant makes the
+ * integral of I the shoelace area A of the markers: I = P + A / |Omega|, P the
+ * zero-mean solution. 2D. The handle owns a multigrid hierarchy with unit
+ * coefficients (flexible CG, V(2,2)) and its workspace (about 5 cell arrays). */
+typedef struct ib_indicator ib_indicator;
+
+/* Errors: IB_EINVAL (not 2D, grid not n_coarsest 2^L), IB_ENOMEM. Syncs. */
+int  ib_indicator_create(const ib_grid* g, int max_markers, ib_indicator** out);
+void ib_indicator_destroy(ib_indicator* ind);
+/* s: device X, nrm (unit, toward the drop), ds of a closed counter-clockwise
+ * curve (fs is not read); I: device cell array (output). Solves from zero to
+ * ||b - A P|| <= rtol ||b|| in at most max_cycles CG iterations (IB_ENOTCONV
+ * beyond; I then holds the last iterate, shifted). Uses the context's bins.
+ * stats may be NULL. Syncs once per iteration. */
+int  ib_indicator_solve(ib_ctx* ctx, ib_indicator* ind, const ib_surface* s, double rtol, int max_cycles,
+                        double* I, mg_stats* stats, void* stream);
+
 /* Enclosed area (axis_x NaN: the closed planar polygon X, n x 2) or volume
  * of revolution about x = axis_x of the region the mirrored meridian curve
  * encloses on the side x >= axis_x, and the y (axial) coordinate of its
@@ -450,6 +479,17 @@ int ib_enclosed_measure(int n, const double* X, double axis_x, double* measure, 
  * no correction was needed). Errors: IB_EINVAL. */
 int ib_mass_correct(int n, double* X, const double* nrm, double target, double axis_x, double h,
                     double trigger, double tol, double* delta);
+
+/* Marker deletion / addition of the conventional front tracking (Section 2.2,
+ * the foil of the B-spline relocation): the closed curve X (host, n x 2) is
+ * walked from marker 0; a marker closer than lo h to the last kept one is
+ * deleted (and the last kept one if it ends closer than lo h to marker 0,
+ * while more than three remain); every kept gap longer than hi h then gets one
+ * marker at its midpoint (the paper: lo = 1/2, hi = 3/2). X_out (host,
+ * max_out x 2) receives the curve, *n_out its length. Errors: IB_EINVAL
+ * (arguments, or max_out too small). */
+int ib_markers_add_delete(int n, const double* X, double h, double lo, double hi, int max_out,
+                          double* X_out, int* n_out);
 
 /* 3D surface geometry (the paper stops at curves; this is the library's
  * extension for static closed meshes): cotangent-formula curvature force

@@ -546,6 +546,7 @@ extern "C" int axi_flow_step(ib_axi* a, mg_handle* m, const ib_params* prm, cons
     IB_CHECK(fp && fp->mu_in >= 0 && fp->mu_out >= 0 && fp->rtol > 0 && fp->max_sweeps > 0, IB_EINVAL,
              "axi_flow_step: viscosities, rtol, max_sweeps");
     IB_TRY(check_freefall(fp, "axi_flow_step"));
+    IB_CHECK(fp->indicator_density == 0, IB_EINVAL, "axi_flow_step: the indicator density is planar only");
     hipStream_t st = (hipStream_t)stream;
     Ctx* F = a->full;
     Ctx* Hc = a->half;

@@ -114,3 +114,45 @@ int freefall_begin(FreeFall* s, const ib_flow_params* fp, int n, const double* X
 }
 
 }  // namespace ib
+
+// Marker deletion and addition of the conventional front tracking (Section
+// 2.2, after Singh et al.; the B-spline relocation replaces it): walk the
+// closed curve from marker 0 deleting markers closer than lo h to the last kept
+// one (and the last kept one when it ends closer than lo h to marker 0, while
+// more than three remain), then put one marker at the midpoint of every kept
+// gap longer than hi h.
+extern "C" int ib_markers_add_delete(int n, const double* X, double h, double lo, double hi, int max_out,
+                                     double* X_out, int* n_out) {
+    if (n < 3 || !X || !X_out || !n_out || !(h > 0.0) || !(lo >= 0.0) || !(hi > lo) || max_out < 1)
+        return ib::fail(IB_EINVAL, "ib_markers_add_delete: arguments");
+    std::vector<double> kept;
+    kept.reserve(2 * (size_t)n);
+    kept.push_back(X[0]);
+    kept.push_back(X[1]);
+    for (int k = 1; k < n; ++k) {
+        const double* last = &kept[kept.size() - 2];
+        if (std::hypot(X[2 * k] - last[0], X[2 * k + 1] - last[1]) >= lo * h) {
+            kept.push_back(X[2 * k]);
+            kept.push_back(X[2 * k + 1]);
+        }
+    }
+    size_t m = kept.size() / 2;
+    if (m > 3 && std::hypot(kept[0] - kept[2 * m - 2], kept[1] - kept[2 * m - 1]) < lo * h) --m;
+    int out = 0;
+    for (size_t k = 0; k < m; ++k) {
+        const size_t q = k + 1 == m ? 0 : k + 1;
+        const double ax = kept[2 * k], ay = kept[2 * k + 1], bx = kept[2 * q], by = kept[2 * q + 1];
+        if (out >= max_out) return ib::fail(IB_EINVAL, "ib_markers_add_delete: max_out too small");
+        X_out[2 * out] = ax;
+        X_out[2 * out + 1] = ay;
+        ++out;
+        if (std::hypot(bx - ax, by - ay) > hi * h) {
+            if (out >= max_out) return ib::fail(IB_EINVAL, "ib_markers_add_delete: max_out too small");
+            X_out[2 * out] = 0.5 * (ax + bx);
+            X_out[2 * out + 1] = 0.5 * (ay + by);
+            ++out;
+        }
+    }
+    *n_out = out;
+    return IB_OK;
+}

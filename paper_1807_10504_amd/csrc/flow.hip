@@ -268,6 +268,8 @@ struct ib_flow {
     double* host = nullptr;   // pinned: the two sums
     double* mred = nullptr;   // density-sum partials (kMeanParts) + the sum
     FreeFall ff;
+    ib_indicator* ind = nullptr;  // conventional scheme: indicator of eq ind_psn
+    double* prop = nullptr;       // the indicator field of the step
 };
 
 static void free_flow(ib_flow* f) {
@@ -279,8 +281,9 @@ static void free_flow(ib_flow* f) {
         if (f->g[q]) hipFree(f->g[q]);
         if (f->ustar[q]) hipFree(f->ustar[q]);
     }
-    for (double* p : {f->Hn, f->rho_n, f->mu, f->red, f->mred})
+    for (double* p : {f->Hn, f->rho_n, f->mu, f->red, f->mred, f->prop})
         if (p) hipFree(p);
+    if (f->ind) ib_indicator_destroy(f->ind);
     if (f->host) hipHostFree(f->host);
     delete f;
 }
@@ -492,6 +495,8 @@ extern "C" int flow_step(ib_ctx* ctx, ib_flow* f, mg_handle* m, const ib_params*
     IB_CHECK(fp->mu_in >= 0 && fp->mu_out >= 0 && fp->rtol > 0 && fp->max_sweeps > 0, IB_EINVAL,
              "flow_step: viscosities, rtol, max_sweeps");
     IB_TRY(check_freefall(fp, "flow_step"));
+    IB_CHECK(fp->indicator_density == 0 || (fp->indicator_density == 1 && prm->spread_mode == IB_SPREAD_DELTA),
+             IB_EINVAL, "flow_step: the indicator density goes with the conventional spreading");
     IB_CHECK(prm->warm_start == WS_ZERO || prm->warm_start == WS_PREV, IB_EINVAL,
              "flow_step: warm start must be WS_ZERO or WS_PREV");
     IB_CHECK(prm->spread_mode == IB_SPREAD_IRROT || prm->spread_mode == IB_SPREAD_DELTA, IB_EINVAL,
@@ -528,10 +533,19 @@ extern "C" int flow_step(ib_ctx* ctx, ib_flow* f, mg_handle* m, const ib_params*
     double* F[3];
     for (int e = 0; e < 3; ++e) F[e] = (out->F[e] && e < 2) ? out->F[e] : c->F[e];
     IB_TRY(spread_impl(c, &s, prm->spread_mode, F, H, st));
+    // the field the properties follow: H, or the conventional indicator
+    const double* P = H;
+    if (fp->indicator_density) {
+        if (!f->ind) IB_TRY(ib_indicator_create(&c->g, c->max_markers, &f->ind));
+        if (!f->prop) IB_HIP(hipMalloc((void**)&f->prop, sizeof(double) * N));
+        const int rci = ib_indicator_solve(ctx, f->ind, &s, prm->rtol, 100, f->prop, nullptr, st);
+        if (rci != IB_OK) return rci;
+        P = f->prop;
+    }
     // rho^n, mu^{n+1}; rho^{n+1} and beta with the hierarchy
     IB_TRY(launch_coefficients(c, f->Hn, prm->rho_in, prm->rho_out, nullptr, f->rho_n, st));
-    IB_TRY(launch_coefficients(c, H, fp->mu_in, fp->mu_out, nullptr, f->mu, st));
-    IB_TRY(coefficients_and_hierarchy(c, m, prm, H, st));
+    IB_TRY(launch_coefficients(c, P, fp->mu_in, fp->mu_out, nullptr, f->mu, st));
+    IB_TRY(coefficients_and_hierarchy(c, m, prm, P, st));
     // predictor, with the body force (rho_mean: volume mean of rho^{n+1})
     Body B{fp->gravity, FS->frame_a, 1.0 / (double)N, nullptr};
     if (fp->gravity != 0.0) {
@@ -544,6 +558,6 @@ extern "C" int flow_step(ib_ctx* ctx, ib_flow* f, mg_handle* m, const ib_params*
     const double* us[3] = {f->ustar[0], f->ustar[1], f->ustar[1]};
     int rc = solve_and_update(c, m, prm, stt, out, us, H, F, st);
     if (rc != IB_OK && rc != IB_ENOTCONV) return rc;
-    IB_HIP(hipMemcpyAsync(f->Hn, H, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    IB_HIP(hipMemcpyAsync(f->Hn, P, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
     return rc;
 }

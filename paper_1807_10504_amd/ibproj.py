@@ -32,6 +32,7 @@ EXPORTS = ("ib_create", "ib_destroy", "ib_bin_markers", "ib_interp", "ib_spread"
            "ib_advection", "ib_viscous", "ib_flow_create", "ib_flow_destroy", "ib_flow_reset",
            "ib_predict", "flow_step", "ib_axi_create", "ib_axi_destroy", "axi_project_step",
            "ib_axi_reset", "axi_predict", "axi_flow_step", "ib_enclosed_measure", "ib_mass_correct",
+           "ib_indicator_create", "ib_indicator_destroy", "ib_indicator_solve", "ib_markers_add_delete",
            "ib_last_error")
 
 PROF_KINDS = ("smooth64", "smooth32", "restrict64", "restrict32", "prolong64", "prolong32", "resid",
@@ -100,12 +101,13 @@ class FlowParams(C.Structure):
     _fields_ = [("mu_in", C.c_double), ("mu_out", C.c_double), ("rtol", C.c_double),
                 ("max_sweeps", C.c_int), ("gravity", C.c_double), ("frame", C.c_int),
                 ("c1", C.c_double), ("c2", C.c_double), ("mass_every", C.c_int),
-                ("mass_target", C.c_double)]
+                ("mass_target", C.c_double), ("indicator_density", C.c_int)]
 
     @staticmethod
     def from_dict(params):
         """mu_in, mu_out, pred_rtol, pred_max_sweeps; free fall: gravity, frame (bool),
-        c1, c2 (0.1 each by default), mass_every, mass_target (0: the first step's)."""
+        c1, c2 (0.1 each by default), mass_every, mass_target (0: the first step's);
+        indicator_density (conventional scheme: properties follow eq ind_psn's I)."""
         fp = FlowParams()
         fp.mu_in = params.get("mu_in", 0.0)
         fp.mu_out = params.get("mu_out", 0.0)
@@ -117,6 +119,7 @@ class FlowParams(C.Structure):
         fp.c2 = params.get("c2", 0.1)
         fp.mass_every = int(params.get("mass_every", 0))
         fp.mass_target = params.get("mass_target", 0.0)
+        fp.indicator_density = 1 if params.get("indicator_density", False) else 0
         return fp
 
 
@@ -189,6 +192,10 @@ def load(path: str = LIB_PATH):
         "axi_flow_step": (i32, [vp, vp, P(Params), P(FlowParams), P(State), P(Outputs), P(FlowStats), vp]),
         "ib_enclosed_measure": (i32, [i32, vp, f64, P(f64), P(f64)]),
         "ib_mass_correct": (i32, [i32, vp, vp, f64, f64, f64, f64, f64, P(f64)]),
+        "ib_markers_add_delete": (i32, [i32, vp, f64, f64, f64, i32, vp, P(i32)]),
+        "ib_indicator_create": (i32, [P(Grid), i32, P(vp)]),
+        "ib_indicator_destroy": (None, [vp]),
+        "ib_indicator_solve": (i32, [vp, vp, P(Surface), f64, i32, vp, P(MgStats), vp]),
         "ib_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -595,6 +602,46 @@ class Axisym:
         return out
 
 
+class Indicator:
+    """Indicator function of the conventional scheme (eq ind_psn) on a 2D grid."""
+
+    def __init__(self, n, h, max_markers):
+        self.lib = load()
+        self.grid = make_grid(2, n, h)
+        self.shape = tuple(reversed(tuple(n[:2])))
+        self.max_markers = int(max_markers)
+        self.ptr = C.c_void_p()
+        _check(self.lib.ib_indicator_create(C.byref(self.grid), self.max_markers, C.byref(self.ptr)))
+
+    def close(self):
+        if self.ptr:
+            self.lib.ib_indicator_destroy(self.ptr)
+            self.ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, ctx: "Context", X, nrm, ds, rtol=1e-12, max_cycles=100, I=None):
+        """I for the markers X (device tensor N x 2), unit normals nrm (N x 2, toward
+        the drop) and arc elements ds (N); returns (I, stats dict)."""
+        import torch
+        if I is None:
+            I = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+        s = Surface()
+        s.n_markers = int(X.shape[0])
+        s.X = _dptr(X, torch.float64)
+        s.nrm = _dptr(nrm, torch.float64)
+        s.ds = _dptr(ds, torch.float64)
+        st = MgStats()
+        rc = self.lib.ib_indicator_solve(ctx.ptr, self.ptr, C.byref(s), float(rtol), int(max_cycles),
+                                         _dptr(I, torch.float64), C.byref(st), _stream())
+        _check(rc)
+        return I, st.as_dict()
+
+
 class Multigrid:
     def __init__(self, dim, n, h, precision=MG_FP64, nu1=2, nu2=2, n_coarsest=4, krylov=0,
                  split_coarse=0):
@@ -790,6 +837,19 @@ def mass_correct(X, nrm, target, axis_x=None, h=1.0, trigger=1e-6, tol=1e-12):
                                float("nan") if axis_x is None else float(axis_x), float(h), float(trigger),
                                float(tol), C.byref(d)))
     return Xc, d.value
+
+
+def markers_add_delete(X, h, lo=0.5, hi=1.5):
+    """Conventional marker deletion (closer than lo h) and midpoint addition (gaps
+    beyond hi h) on the closed curve X; returns the new curve."""
+    lib = load()
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    cap = 2 * X.shape[0]
+    out = np.empty((cap, 2))
+    m = C.c_int()
+    _check(lib.ib_markers_add_delete(X.shape[0], _hptr(X), float(h), float(lo), float(hi), cap, _hptr(out),
+                                     C.byref(m)))
+    return out[: m.value].copy()
 
 
 def surface_geometry_3d(V, T, sigma):

@@ -121,3 +121,18 @@ def test_mass_correction_matches_oracle(axis):
     assert d == 0.0
     with pytest.raises(ibproj.IbError):
         ibproj.mass_correct(X0, nrm, -1.0, axis, h)
+
+
+def test_markers_add_delete_bit_exact():
+    from oracle import markers
+    h = 1 / 64
+    cases = [W.circle_markers(n, 0.25) for n in (60, 100, 300, 700)]
+    cases.append(W.jittered_circle(400, 0.25, 0.02, seed=4))
+    rng = np.random.default_rng(9)
+    th = np.sort(rng.uniform(0, 2 * np.pi, 250))
+    cases.append(np.stack([0.5 + 0.3 * np.cos(th), 0.5 + 0.2 * np.sin(th)], axis=1))
+    for X in cases:
+        Y = ibproj.markers_add_delete(X, h)
+        assert np.array_equal(Y, markers.add_delete(X, h))
+    with pytest.raises(ibproj.IbError):
+        ibproj.markers_add_delete(np.zeros((2, 2)), h)

@@ -230,6 +230,40 @@ def test_flow_step_freefall_parity_2d(ib):
     assert abs(mom) <= 1e-3 * float(np.sum(oflow.face_density(rho, 2, 1) * np.abs(host(u[1]))))
 
 
+def test_flow_step_conventional_indicator_parity_2d(ib):
+    """The conventional scheme of Section 2.2 (force spread by the discrete
+    delta function, properties from the indicator of eq ind_psn) over three full
+    steps against the oracle."""
+    from oracle import heaviside
+    n = (64, 64)
+    h = 1.0 / 64
+    prm = dict(rho_in=1.0, rho_out=1e-2, mu_in=1e-2, mu_out=1e-4, sigma=1.0, dt=1e-4, rtol=1e-12,
+               pred_rtol=1e-13, warm_start=ib.WS_PREV, spread_mode=ib.IB_SPREAD_DELTA, indicator_density=True)
+    X0 = W.ellipse_markers(128, 0.25, 1.1)
+    ctx = ib.Context(2, n, h, max_markers=256)
+    mg = ib.Multigrid(2, n, h)
+    fl = ib.Flow(2, n, h)
+    u = [torch.zeros((64, 64), dtype=torch.float64, device="cuda") for _ in range(2)]
+    p = torch.zeros((64, 64), dtype=torch.float64, device="cuda")
+    Xg = X0.copy()
+    uo = [np.zeros((64, 64)) for _ in range(2)]
+    Xo = X0.copy()
+    Po = heaviside.heaviside_2d(Xo, n, h)
+    advo, po = None, None
+    for step in range(3):
+        out = ctx.flow_step(mg, fl, prm, u, Xg, p_prev=p, out={"p": p, "u": u})
+        r = oflow.flow_step_2d(n, h, 1.0, 1e-2, 1e-2, 1e-4, 1.0, 1e-4, uo, Xo, Po, adv_prev=advo,
+                               p_prev=po, rtol=1e-12, conventional=True, indicator_density=True)
+        uo, Xo, Po, advo, po = r["u"], r["X"], r["prop"], r["adv"], r["p"]
+        eu = max(np.abs(host(u[d]) - uo[d]).max() for d in range(2)) / max(np.abs(a).max() for a in uo)
+        ep = rel_l2(host(p), po)
+        ex = np.abs(Xg - Xo).max()
+        print(f"step {step}: |du|/|u| {eu:.1e}, p {ep:.1e}, X {ex:.1e}", flush=True)
+        assert eu <= 1e-8 and ep <= 1e-9 and ex <= 1e-12
+    with pytest.raises(ib.IbError):            # the indicator goes with the conventional spreading
+        ctx.flow_step(mg, fl, dict(prm, spread_mode=ib.IB_SPREAD_IRROT), u, Xg.copy())
+
+
 def test_flow_step_errors(ib):
     ctx3 = ib.Context(3, (16, 16, 16), 1 / 16, max_markers=16)
     mg3 = ib.Multigrid(3, (16, 16, 16), 1 / 16)

@@ -1,0 +1,99 @@
+"""Indicator function of the conventional scheme on the GPU (eqs indicator,
+ind_psn) against the oracle, and the curl-versus-h study of Section 3.1.
+
+* ib_indicator_solve against oracle.indicator (exact periodic solve) on 64^2
+  (circle and a mode-2 shape) and on a 128 x 64 box: within 1e-9 (the
+  multigrid solves to 1e-13);
+* with h = 1/64, 1/128, 1/256 the conventional delta vector keeps a curl of
+  order its own size while the irrotational one has none, and the indicator's
+  L1 distance to the smoothed Heaviside falls at first order (the paper's
+  statement for the split delta vector).
+"""
+import numpy as np
+import pytest
+
+from oracle import bspline, indicator
+from paper_1807_10504_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ib():
+    from paper_1807_10504_amd import ibproj
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    ibproj.load()
+    return ibproj
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _curve(h, shape, centre):
+    m = int(round(2 * np.pi * 0.2 / (0.5 * h)))
+    if shape == "circle":
+        return W.circle_markers(m, 0.2, centre=centre)
+    return W.mode_shape(m, 0.2, 0.1, centre=centre)
+
+
+@pytest.mark.parametrize("case", [("circle", (64, 64)), ("mode", (64, 64)), ("circle", (128, 64))])
+def test_indicator_parity(ib, case):
+    shape, n = case
+    h = 1.0 / 64
+    centre = (0.5 * n[0] * h, 0.5 * n[1] * h)
+    X0 = _curve(h, shape, centre)
+    Xg, _, ds, nrm = ib.relocate_bspline(X0, np.zeros_like(X0), 0.0, h, 1.0)
+    Xo, _, dso, nro = bspline.relocate([tuple(x) for x in X0], [(0.0, 0.0)] * len(X0), 0.0, h, 1.0)
+    Io = indicator.indicator(np.array(Xo), np.array(dso), np.array(nro), n, h)
+    ctx = ib.Context(2, n, h, max_markers=len(X0))
+    ind = ib.Indicator(n, h, max_markers=len(X0))
+    I, st = ind.solve(ctx, dev(Xg), dev(nrm), dev(ds), rtol=1e-13)
+    torch.cuda.synchronize()
+    err = np.abs(I.cpu().numpy() - Io).max()
+    print(f"{shape} {n}: |I - oracle| {err:.2e}, CG iterations {st['cycles']}")
+    assert err <= 1e-9
+
+
+def test_indicator_errors(ib):
+    with pytest.raises(ib.IbError):
+        ib.Indicator((24, 20), 1 / 16, 10)                # the multigrid cannot coarsen it
+    import ctypes as C
+    g3 = ib.make_grid(3, (16, 16, 16), 1 / 16)
+    out = C.c_void_p()
+    assert ib.load().ib_indicator_create(C.byref(g3), 10, C.byref(out)) == ib.IB_EINVAL
+    ctx = ib.Context(2, (64, 64), 1 / 64, max_markers=512)
+    ind = ib.Indicator((64, 64), 1 / 64, max_markers=16)
+    X = dev(W.circle_markers(100, 0.2))
+    with pytest.raises(ib.IbError):
+        ind.solve(ctx, X, X, dev(np.ones(100)))       # more markers than the handle holds
+    other = ib.Indicator((32, 32), 1 / 32, max_markers=512)
+    with pytest.raises(ib.IbError):
+        other.solve(ctx, X, X, dev(np.ones(100)))     # another grid
+
+
+def test_curl_versus_h(ib):
+    l1, rows = [], []
+    for nn in (64, 128, 256):
+        h = 1.0 / nn
+        X0 = _curve(h, "circle", (0.5, 0.5))
+        X, fs, ds, nrm = ib.relocate_bspline(X0, np.zeros_like(X0), 0.0, h, 1.0)
+        N = len(X)
+        ctx = ib.Context(2, (nn, nn), h, max_markers=N)
+        surf = ib.Surface()
+        keep = [dev(X), dev(np.ones(N)), dev(ds), dev(nrm)]
+        surf.n_markers, surf.X, surf.fs, surf.ds, surf.nrm = (N, keep[0].data_ptr(), keep[1].data_ptr(),
+                                                              keep[2].data_ptr(), keep[3].data_ptr())
+        F, H = ctx.spread(surf, ib.IB_SPREAD_IRROT)
+        Fc, _ = ctx.spread(surf, ib.IB_SPREAD_DELTA, want_H=False)
+        d, dc = ctx.diagnostics(F=F), ctx.diagnostics(F=Fc)
+        ind = ib.Indicator((nn, nn), h, max_markers=N)
+        I, _ = ind.solve(ctx, keep[0], keep[3], keep[2], rtol=1e-12)
+        torch.cuda.synchronize()
+        l1.append(float((I - H).abs().sum()) * h * h)
+        rows.append((nn, d["curl_max"] / d["f_max"], dc["curl_max"] / dc["f_max"], l1[-1]))
+        print(f"h = 1/{nn}: curl/|F| irrotational {rows[-1][1]:.1e}, conventional {rows[-1][2]:.3f}; "
+              f"L1 |I - H| {l1[-1]:.3e}")
+        assert rows[-1][1] <= 1e-12 and rows[-1][2] > 1e-3
+    assert 1.6 < l1[0] / l1[1] < 2.6 and 1.6 < l1[1] / l1[2] < 2.6, l1
