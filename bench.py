@@ -384,6 +384,68 @@ def bench_conventional(ib, torch):
                                     "(B-spline relocation), unit force toward the drop")
 
 
+def _osc3d_run(ib, torch, nn, level, dt, frac):
+    """A drop R = 0.25 stretched by 1.1 along x (volume kept), rho 1/0.01, mu
+    0.01/1e-5, sigma 1, on an nn^3 unit periodic box, level-`level` icosphere,
+    moving-surface flow steps over `frac` of Lamb's l = 2 period: the time of
+    the first minimum of the x-extent (parabola through the samples around it)."""
+    from paper_1807_10504_amd import workloads as W
+    R, beta = 0.25, 1.1
+    h = 1.0 / nn
+    V, T = W.sphere_mesh(level, R, seed=3)
+    V = 0.5 + (V - 0.5) * np.array([beta, 1 / np.sqrt(beta), 1 / np.sqrt(beta)])
+    prm = dict(rho_in=1.0, rho_out=0.01, mu_in=0.01, mu_out=1e-5, sigma=1.0, dt=dt, rtol=1e-10,
+               pred_rtol=1e-12, warm_start=ib.WS_PREV)
+    n = (nn, nn, nn)
+    ctx = ib.Context(3, n, h, max_markers=len(V), max_elems=len(T))
+    mg = ib.Multigrid(3, n, h, krylov=1)
+    fl = ib.Flow(3, n, h)
+    u = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+    p = torch.zeros(n, dtype=torch.float64, device="cuda")
+    T_lamb = 2 * np.pi * np.sqrt((3 * 1.0 + 2 * 0.01) * R ** 3 / 24.0)
+    steps = int(frac * T_lamb / dt)
+    ext = [float(np.ptp(V[:, 0]))]
+    cycles, sweeps = [], []
+    out = {"p": p, "u": u}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        out = ctx.flow_step(mg, fl, prm, u, V, p_prev=p, out=out, tris=T)
+        ext.append(float(np.ptp(V[:, 0])))
+        cycles.append(out["stats"]["cycles"])
+        sweeps.append(out["flow"]["sweeps"])
+        if k % 1000 == 999:
+            log(f"  3D drop {nn}^3: step {k + 1}/{steps}")
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    d = np.array(ext)
+    k = int(np.argmin(d))
+    y0, y1, y2 = d[k - 1], d[k], d[k + 1]
+    t_min = (k + 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2)) * dt
+    return dict(vertices=len(V), triangles=len(T), steps=steps, steps_per_s=round(steps / secs, 2),
+                ms_per_step=round(1e3 * secs / steps, 3), half_period=round(float(t_min), 5),
+                lamb_half_period=round(0.5 * T_lamb, 5),
+                discrepancy_percent=round(100 * abs(t_min - 0.5 * T_lamb) / (0.5 * T_lamb), 2),
+                x_extent_start=round(d[0], 5), x_extent_min=round(float(d[k]), 5),
+                mean_cycles=round(float(np.mean(cycles)), 2), mean_predictor_sweeps=round(float(np.mean(sweeps)), 2))
+
+
+def bench_flow3d(ib, torch):
+    """Moving 3D drops (local least-squares surface reconstruction): the first
+    half-period of the l = 2 oscillation against Lamb's formula, and full steps/s,
+    at h = 1/64 (level-4 icosphere) and 1/128 (level 5)."""
+    res = {}
+    for nn, level, dt in ((64, 4, 2e-4), (128, 5, 1e-4)):
+        r = _osc3d_run(ib, torch, nn, level, dt, 0.62)
+        res[f"h1_{nn}"] = r
+        log(f"  3D drop {nn}^3: half period {r['half_period']} (Lamb {r['lamb_half_period']}, "
+            f"{r['discrepancy_percent']} %), {r['steps_per_s']} steps/s")
+    res["workload"] = ("drop R=0.25 stretched by 1.1 along x (volume kept), rho 1/0.01, mu 0.01/1e-5, sigma 1, "
+                       "unit periodic box; 64^3 with a level-4 icosphere (2562 vertices), dt 2e-4; 128^3 with "
+                       "level 5 (10242 vertices), dt 1e-4; 0.62 of Lamb's l = 2 period")
+    return res
+
+
 def bench_flow_osc(ib, torch):
     """Full flow steps (markers, H and force, momentum predictor, projection) on the
     free oscillation of Section 5.2 (Table osc), 2D and axisymmetric, at h = 0.01
@@ -858,6 +920,8 @@ def main():
         line["conventional"] = bench_conventional(ib, torch)
         log("== oscillating drop energy (new vs conventional) and large deformation")
         line["osc_energy"] = bench_osc_energy(ib, torch)
+        log("== moving 3D drops (local least-squares surface)")
+        line["flow3d"] = bench_flow3d(ib, torch)
         log("== free-fall drops (Table afd_param sets 1-2, axisymmetric)")
         line["free_fall"] = bench_free_fall(ib, torch)
         log(f"== momentum predictor at {args.size}^3")

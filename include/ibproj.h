@@ -237,8 +237,12 @@ typedef struct {
                                 2D: only n_markers is read; markers come from X_host. */
     double* X_host;          /* 2D: host n_markers*2, in: markers at step n, out: advanced
                                 by dt U and relocated on the least-squares B-spline.
-                                3D: NULL. */
+                                3D project_step: NULL. 3D flow_step: host
+                                n_markers*3 vertices, advanced by dt U and moved
+                                onto the local least-squares surface. */
     ib_nn* nn;               /* WS_NN: the network (of the grid's dimension), else NULL */
+    const int32_t* elems_host; /* 3D flow_step: host copy of surf.elems (the moving
+                                  surface's triangles); NULL otherwise */
 } ib_state;
 
 typedef struct {
@@ -355,11 +359,17 @@ int ib_predict(ib_flow* f, const double* const u[3], const double* rho_n, const 
                const double* mu, double dt, double rtol, int max_sweeps, double* const u_star[3],
                ib_flow_stats* stats, void* stream);
 
-/* One step of the full 2D method (the 3D surface is static: IB_EINVAL):
+/* One step of the full method, 2D or 3D:
  *   markers: U = interp(u^n) (st->u_star holds u^n), advanced by dt U and
- *   relocated on the least-squares B-spline (X_host in place);
+ *   relocated on the least-squares B-spline (2D) or moved onto the local
+ *   least-squares surface of ib_surface_lsq_3d (3D; the surface's normals,
+ *   curvature force and areas come from the same fit) -- X_host in place;
+ *   3D also needs st->surf.n_elems, st->surf.elems (device) and
+ *   st->elems_host; the mesh keeps its connectivity (no remeshing), and the
+ *   free-fall frame and mass correction are planar only (IB_EINVAL);
  *   H^{n+1}, F from the relocated markers; rho^n from the previous step's H
- *   (the first step after create/reset computes H of the incoming markers);
+ *   (the first step after create/reset computes H of the incoming markers,
+ *   in 3D offset along the normals of their reconstruction);
  *   u* = ib_predict; projection with u*: coefficients, right side, warm start
  *   (WS_ZERO or WS_PREV), solve, update into out->u (which may alias u^n).
  * out->p, out->u, out->U required; out->H, out->F, out->b optional as in
@@ -490,6 +500,22 @@ int ib_mass_correct(int n, double* X, const double* nrm, double target, double a
  * (arguments, or max_out too small). */
 int ib_markers_add_delete(int n, const double* X, double h, double lo, double hi, int max_out,
                           double* X_out, int* n_out);
+
+/* Local least-squares reconstruction of a moving closed triangulated surface
+ * (the 3D counterpart of the least-squares B-spline of Section 4; the paper
+ * leaves surfaces to future work). Per vertex: the inward angle-weighted
+ * normal n and a tangent frame (t1 = projection of the coordinate axis least
+ * aligned with n, t2 = n x t1); the vertex's two-ring (itself included) in
+ * frame coordinates scaled by L (mean distance of the other ring vertices);
+ * the least-squares quadric z = g + d x + e y + a x^2 + b xy + c y^2. Outputs
+ * (host): V_out = V + g L n (the vertex on the fitted surface), nrm = (n - d t1
+ * - e t2)/sqrt(1 + d^2 + e^2), fs = sigma [(1 + e^2) 2a - 2de b + (1 + d^2) 2c] /
+ * (L (1 + d^2 + e^2)^(3/2)) (sigma times the sum of principal curvatures,
+ * positive for a convex drop), ds = a third of the adjacent triangles' areas of
+ * V_out. V: nv x 3, T: nt x 3 outward counter-clockwise. Errors: IB_EINVAL,
+ * IB_EGEOM (a degenerate neighbourhood). */
+int ib_surface_lsq_3d(int nv, const double* V, int nt, const int* T, double sigma, double* V_out, double* fs,
+                      double* ds, double* nrm);
 
 /* 3D surface geometry (the paper stops at curves; this is the library's
  * extension for static closed meshes): cotangent-formula curvature force

@@ -198,3 +198,29 @@ def flow_step_2d(n, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, X, H_prev, 
     p, cycles, _ = poisson.mg_solve(b, beta, h, p0=p_prev, rtol=rtol, max_cycles=max_cycles)
     u_new = poisson.velocity_update(u_star, F, beta, p, dt, h)
     return dict(U=U, X=Xn, fs=fs, H=H, prop=prop, F=F, u_star=u_star, adv=adv, p=p, u=u_new, cycles=cycles)
+
+
+def flow_step_3d(n, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, V, T, H_prev, adv_prev=None,
+                 p_prev=None, rtol=1e-10, max_cycles=100):
+    """One step with a moving closed triangulated surface (the 3D counterpart of
+    flow_step_2d; the paper leaves moving surfaces to future work):
+      1. U = interpolation of u^n to the vertices; V + dt U moved onto the local
+         least-squares surface (surface3d.lsq_reconstruct: vertices, normals,
+         sigma kappa, vertex areas); the triangles are kept;
+      2. H^{n+1} from the surfaces offset along those normals, F the
+         irrotational face force (nearest triangle);
+      3. - 5. as flow_step_2d."""
+    from . import surface3d
+    U = transfer.interp(u, V, h)
+    Vn, fs, ds, nrm = surface3d.lsq_reconstruct(np.asarray(V) + dt * U, T, sigma)
+    H = heaviside.heaviside_3d(Vn, T, n, h, nrm=nrm)
+    F = force.irrotational_force(H, Vn, fs, h, tris=T)
+    rho_n = poisson.density(H_prev, rho_in, rho_out)
+    rho1 = poisson.density(H, rho_in, rho_out)
+    mu = poisson.density(H, mu_in, mu_out)
+    u_star, adv = predict(u, rho_n, rho1, mu, dt, h, adv_prev)
+    beta = poisson.face_beta(rho1)
+    b = poisson.rhs(u_star, F, beta, dt, h)
+    p, cycles, _ = poisson.mg_solve(b, beta, h, p0=p_prev, rtol=rtol, max_cycles=max_cycles)
+    u_new = poisson.velocity_update(u_star, F, beta, p, dt, h)
+    return dict(U=U, X=Vn, fs=fs, H=H, F=F, u_star=u_star, adv=adv, p=p, u=u_new, cycles=cycles)

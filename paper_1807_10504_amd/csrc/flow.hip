@@ -9,6 +9,8 @@
 // neighbours are formed once per thread.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <vector>
 
 #include "common.h"
 
@@ -479,24 +481,52 @@ extern "C" int ib_predict(ib_flow* f, const double* const u[3], const double* rh
                         (hipStream_t)stream);
 }
 
+// 3D: the vertices advanced by dt U (host) and moved onto the local
+// least-squares surface, whose normals, curvature force and areas go to the
+// device marker buffers of the context
+static int relocate_3d(Ctx* c, const ib_params* prm, ib_state* stt, const double* U_dev, double* fs_host,
+                       ib_surface* s, hipStream_t st) {
+    const int n = s->n_markers;
+    std::vector<double> U(3 * (size_t)n), Xa(3 * (size_t)n), Xn(3 * (size_t)n), fs(n), ds(n), nr(3 * (size_t)n);
+    IB_HIP(hipMemcpyAsync(U.data(), U_dev, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, st));
+    IB_HIP(hipStreamSynchronize(st));
+    for (size_t k = 0; k < 3 * (size_t)n; ++k) Xa[k] = stt->X_host[k] + prm->dt * U[k];
+    IB_TRY(ib_surface_lsq_3d(n, Xa.data(), s->n_elems, stt->elems_host, prm->sigma, Xn.data(), fs.data(),
+                             ds.data(), nr.data()));
+    std::memcpy(stt->X_host, Xn.data(), sizeof(double) * 3 * n);
+    if (fs_host) std::memcpy(fs_host, fs.data(), sizeof(double) * n);
+    IB_HIP(hipMemcpyAsync(c->mX, Xn.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, st));
+    IB_HIP(hipMemcpyAsync(c->mfs, fs.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+    IB_HIP(hipMemcpyAsync(c->mds, ds.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+    IB_HIP(hipMemcpyAsync(c->mnrm, nr.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, st));
+    IB_HIP(hipStreamSynchronize(st));  // the host vectors must outlive the copies
+    s->X = c->mX;
+    s->fs = c->mfs;
+    s->ds = c->mds;
+    s->nrm = c->mnrm;
+    return IB_OK;
+}
+
 extern "C" int flow_step(ib_ctx* ctx, ib_flow* f, mg_handle* m, const ib_params* prm,
                          const ib_flow_params* fp, ib_state* stt, ib_outputs* out,
                          ib_flow_stats* fstats, void* stream) {
     IB_CHECK(ctx && f && m && prm && fp && stt && out, IB_EINVAL, "flow_step: null argument");
     Ctx* c = ctx;
-    IB_CHECK(c->d.dim == 2, IB_EINVAL, "flow_step: 2D only (3D surfaces are static)");
-    IB_CHECK(f->d.nx == c->d.nx && f->d.ny == c->d.ny && f->d.dim == 2 && f->d.h == c->d.h, IB_EINVAL,
-             "flow_step: the flow handle belongs to another grid");
+    const int dim = c->d.dim;
+    IB_CHECK(f->d.nx == c->d.nx && f->d.ny == c->d.ny && f->d.nz == c->d.nz && f->d.dim == dim &&
+                 f->d.h == c->d.h,
+             IB_EINVAL, "flow_step: the flow handle belongs to another grid");
     IB_CHECK(out->p && out->U, IB_EINVAL, "flow_step: p and U outputs are required");
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < dim; ++q)
         IB_CHECK(stt->u_star[q] && out->u[q], IB_EINVAL, "flow_step: null velocity array");
     IB_CHECK(prm->dt > 0 && prm->rho_in > 0 && prm->rho_out > 0, IB_EINVAL,
              "flow_step: dt and densities must be positive");
     IB_CHECK(fp->mu_in >= 0 && fp->mu_out >= 0 && fp->rtol > 0 && fp->max_sweeps > 0, IB_EINVAL,
              "flow_step: viscosities, rtol, max_sweeps");
     IB_TRY(check_freefall(fp, "flow_step"));
-    IB_CHECK(fp->indicator_density == 0 || (fp->indicator_density == 1 && prm->spread_mode == IB_SPREAD_DELTA),
-             IB_EINVAL, "flow_step: the indicator density goes with the conventional spreading");
+    IB_CHECK(fp->indicator_density == 0 ||
+                 (fp->indicator_density == 1 && prm->spread_mode == IB_SPREAD_DELTA && dim == 2),
+             IB_EINVAL, "flow_step: the indicator density goes with the conventional spreading in 2D");
     IB_CHECK(prm->warm_start == WS_ZERO || prm->warm_start == WS_PREV, IB_EINVAL,
              "flow_step: warm start must be WS_ZERO or WS_PREV");
     IB_CHECK(prm->spread_mode == IB_SPREAD_IRROT || prm->spread_mode == IB_SPREAD_DELTA, IB_EINVAL,
@@ -505,33 +535,56 @@ extern "C" int flow_step(ib_ctx* ctx, ib_flow* f, mg_handle* m, const ib_params*
     hipStream_t st = (hipStream_t)stream;
     ib_surface s = stt->surf;
     const int n = s.n_markers;
-    IB_CHECK(n >= 3 && n <= c->max_markers, IB_EINVAL, "flow_step: marker count");
+    if (dim == 3) {
+        IB_CHECK(n >= 4 && n <= c->max_markers, IB_EINVAL, "flow_step: vertex count");
+        IB_CHECK(s.n_elems >= 4 && s.n_elems <= c->max_elems && s.elems && stt->elems_host, IB_EINVAL,
+                 "flow_step: 3D needs the triangles (device surf.elems and elems_host)");
+        IB_CHECK(!fp->frame && fp->mass_every == 0, IB_EINVAL,
+                 "flow_step: the free-fall frame and mass correction are planar only");
+    } else {
+        IB_CHECK(n >= 3 && n <= c->max_markers, IB_EINVAL, "flow_step: marker count");
+        s.elems = nullptr;
+        s.n_elems = 0;
+    }
     const long N = c->d.cells();
-    IB_HIP(hipMemcpyAsync(c->mX, stt->X_host, sizeof(double) * 2 * n, hipMemcpyHostToDevice, st));
+    IB_HIP(hipMemcpyAsync(c->mX, stt->X_host, sizeof(double) * dim * n, hipMemcpyHostToDevice, st));
     s.X = c->mX;
-    s.elems = nullptr;
-    s.n_elems = 0;
-    // H of the incoming markers when there is no previous step
+    // H of the incoming markers when there is no previous step (3D: offsets
+    // along the normals of the incoming surface's reconstruction)
     if (!f->have_H) {
+        if (dim == 3) {
+            std::vector<double> Vt(3 * (size_t)n), fs(n), ds(n), nr(3 * (size_t)n);
+            IB_TRY(ib_surface_lsq_3d(n, stt->X_host, s.n_elems, stt->elems_host, prm->sigma, Vt.data(), fs.data(),
+                                     ds.data(), nr.data()));
+            IB_HIP(hipMemcpyAsync(c->mnrm, nr.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, st));
+            IB_HIP(hipStreamSynchronize(st));
+            s.nrm = c->mnrm;
+        }
         IB_TRY(launch_heaviside(c, &s, f->Hn, st));
         int fl[3];
         IB_TRY(read_flags(c, fl, st));
-        IB_CHECK(fl[0] == 0, IB_EGEOM, "flow_step: an offset curve comes within 4h of the box sides");
+        IB_CHECK(fl[0] == 0, IB_EGEOM, "flow_step: an offset surface comes within 4h of the box sides");
         f->have_H = 1;
     }
-    // free fall: centroid and measure of the incoming markers
+    // free fall (2D): centroid and measure of the incoming markers
     ib_flow_stats loc{};
     ib_flow_stats* FS = fstats ? fstats : &loc;
     const double* mass_target = nullptr;
-    IB_CHECK(freefall_begin(&f->ff, fp, n, stt->X_host, NAN, prm->dt, FS, &mass_target) == IB_OK, IB_EGEOM,
-             "flow_step: the markers enclose no area");
+    if (dim == 2)
+        IB_CHECK(freefall_begin(&f->ff, fp, n, stt->X_host, NAN, prm->dt, FS, &mass_target) == IB_OK, IB_EGEOM,
+                 "flow_step: the markers enclose no area");
+    else
+        FS->frame_a = FS->com = FS->measure = FS->mass_delta = 0.0;
     // markers: interpolation of u^n, advance, relocation (and mass correction)
     IB_TRY(launch_interp(c, stt->u_star, &s, out->U, st));
-    IB_TRY(relocate_2d(c, prm, stt, out->U, out->fs_host, &s, st, NAN, mass_target, &FS->mass_delta));
+    if (dim == 2)
+        IB_TRY(relocate_2d(c, prm, stt, out->U, out->fs_host, &s, st, NAN, mass_target, &FS->mass_delta));
+    else
+        IB_TRY(relocate_3d(c, prm, stt, out->U, out->fs_host, &s, st));
     // H^{n+1} and the face force
     double* H = out->H ? out->H : c->H;
     double* F[3];
-    for (int e = 0; e < 3; ++e) F[e] = (out->F[e] && e < 2) ? out->F[e] : c->F[e];
+    for (int e = 0; e < 3; ++e) F[e] = (out->F[e] && e < dim) ? out->F[e] : c->F[e];
     IB_TRY(spread_impl(c, &s, prm->spread_mode, F, H, st));
     // the field the properties follow: H, or the conventional indicator
     const double* P = H;
@@ -555,7 +608,7 @@ extern "C" int flow_step(ib_ctx* ctx, ib_flow* f, mg_handle* m, const ib_params*
     IB_TRY(predict_impl(f, stt->u_star, f->rho_n, c->rho, f->mu, prm->dt, fp->rtol, fp->max_sweeps,
                         f->ustar, FS, B, st));
     // projection of u*
-    const double* us[3] = {f->ustar[0], f->ustar[1], f->ustar[1]};
+    const double* us[3] = {f->ustar[0], f->ustar[1], dim == 3 ? f->ustar[2] : f->ustar[1]};
     int rc = solve_and_update(c, m, prm, stt, out, us, H, F, st);
     if (rc != IB_OK && rc != IB_ENOTCONV) return rc;
     IB_HIP(hipMemcpyAsync(f->Hn, P, sizeof(double) * N, hipMemcpyDeviceToDevice, st));

@@ -32,7 +32,7 @@ EXPORTS = ("ib_create", "ib_destroy", "ib_bin_markers", "ib_interp", "ib_spread"
            "ib_advection", "ib_viscous", "ib_flow_create", "ib_flow_destroy", "ib_flow_reset",
            "ib_predict", "flow_step", "ib_axi_create", "ib_axi_destroy", "axi_project_step",
            "ib_axi_reset", "axi_predict", "axi_flow_step", "ib_enclosed_measure", "ib_mass_correct",
-           "ib_indicator_create", "ib_indicator_destroy", "ib_indicator_solve", "ib_markers_add_delete",
+           "ib_indicator_create", "ib_indicator_destroy", "ib_indicator_solve", "ib_markers_add_delete", "ib_surface_lsq_3d",
            "ib_last_error")
 
 PROF_KINDS = ("smooth64", "smooth32", "restrict64", "restrict32", "prolong64", "prolong32", "resid",
@@ -76,7 +76,7 @@ class Params(C.Structure):
 
 class State(C.Structure):
     _fields_ = [("u_star", C.c_void_p * 3), ("p_prev", C.c_void_p), ("surf", Surface),
-                ("X_host", C.c_void_p), ("nn", C.c_void_p)]
+                ("X_host", C.c_void_p), ("nn", C.c_void_p), ("elems_host", C.c_void_p)]
 
 
 class Outputs(C.Structure):
@@ -193,6 +193,7 @@ def load(path: str = LIB_PATH):
         "ib_enclosed_measure": (i32, [i32, vp, f64, P(f64), P(f64)]),
         "ib_mass_correct": (i32, [i32, vp, vp, f64, f64, f64, f64, f64, P(f64)]),
         "ib_markers_add_delete": (i32, [i32, vp, f64, f64, f64, i32, vp, P(i32)]),
+        "ib_surface_lsq_3d": (i32, [i32, vp, i32, vp, f64, vp, vp, vp, vp]),
         "ib_indicator_create": (i32, [P(Grid), i32, P(vp)]),
         "ib_indicator_destroy": (None, [vp]),
         "ib_indicator_solve": (i32, [vp, vp, P(Surface), f64, i32, vp, P(MgStats), vp]),
@@ -458,12 +459,13 @@ class Context:
         return out
 
     def flow_step(self, mg: "Multigrid", flow: "Flow", params: dict, u, X_host, p_prev=None,
-                  out=None):
-        """One step of the full 2D method: markers advanced with u^n (X_host, numpy N x 2,
-        updated in place), H and force of the new markers, predictor (params: mu_in,
-        mu_out, pred_rtol, pred_max_sweeps; free fall: gravity, frame, c1, c2,
-        mass_every -- FlowParams.from_dict), projection. Returns the outputs dict with
-        'stats' (multigrid) and 'flow' (predictor)."""
+                  out=None, tris=None):
+        """One step of the full method: markers advanced with u^n (X_host, numpy N x dim,
+        updated in place; 3D: the vertices of the surface whose triangles `tris`,
+        numpy int32 M x 3, stay fixed), H and force of the new markers, predictor
+        (params: mu_in, mu_out, pred_rtol, pred_max_sweeps; free fall: gravity, frame,
+        c1, c2, mass_every -- FlowParams.from_dict), projection. Returns the outputs dict
+        with 'stats' (multigrid) and 'flow' (predictor)."""
         import torch
         prm = self._params(params, p_prev)
         fp = FlowParams.from_dict(params)
@@ -474,6 +476,18 @@ class Context:
         st.surf.n_markers = int(X_host.shape[0])
         st.X_host = _hptr(X_host)
         st.nn = None
+        st.elems_host = None
+        if self.dim == 3:
+            if tris is None:
+                raise ValueError("a 3D flow step needs the surface's triangles")
+            tris = np.ascontiguousarray(tris, dtype=np.int32)
+            cached = getattr(self, "_tris_host", None)
+            if cached is None or cached.shape != tris.shape or not np.array_equal(cached, tris):
+                self._tris_host = tris.copy()
+                self._tris_dev = torch.from_numpy(self._tris_host).cuda()
+            st.surf.n_elems = int(tris.shape[0])
+            st.surf.elems = self._tris_dev.data_ptr()
+            st.elems_host = _hptr(self._tris_host, np.int32)
         out, o = self._outputs(out, int(X_host.shape[0]))
         fs = FlowStats()
         rc = self.lib.flow_step(self.ptr, flow.ptr, mg.ptr, C.byref(prm), C.byref(fp), C.byref(st),
@@ -850,6 +864,21 @@ def markers_add_delete(X, h, lo=0.5, hi=1.5):
     _check(lib.ib_markers_add_delete(X.shape[0], _hptr(X), float(h), float(lo), float(hi), cap, _hptr(out),
                                      C.byref(m)))
     return out[: m.value].copy()
+
+
+def surface_lsq_3d(V, T, sigma):
+    """Local least-squares reconstruction of a closed triangulated surface: returns
+    (V', fs, ds, nrm)."""
+    lib = load()
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.int32)
+    Vo = np.empty_like(V)
+    fs = np.empty(V.shape[0])
+    ds = np.empty(V.shape[0])
+    nrm = np.empty_like(V)
+    _check(lib.ib_surface_lsq_3d(V.shape[0], _hptr(V), T.shape[0], _hptr(T, np.int32), float(sigma), _hptr(Vo), _hptr(fs),
+                                 _hptr(ds), _hptr(nrm)))
+    return Vo, fs, ds, nrm
 
 
 def surface_geometry_3d(V, T, sigma):

@@ -136,3 +136,18 @@ def test_markers_add_delete_bit_exact():
         assert np.array_equal(Y, markers.add_delete(X, h))
     with pytest.raises(ibproj.IbError):
         ibproj.markers_add_delete(np.zeros((2, 2)), h)
+
+
+@pytest.mark.parametrize("level", [2, 3])
+def test_surface_lsq_3d_matches_oracle(level):
+    V, T = W.sphere_mesh(level, 0.25, seed=3)
+    rng = np.random.default_rng(level)
+    V = V + 1e-3 * rng.uniform(-1, 1, V.shape)            # not on a sphere
+    Vo, fs, ds, nrm = ibproj.surface_lsq_3d(V, T, 1.0)
+    Vr, fr, dr, nr = surface3d.lsq_reconstruct(V, T, 1.0)
+    assert np.abs(Vo - Vr).max() <= 1e-14
+    assert np.abs(fs - fr).max() <= 1e-11 * np.abs(fr).max()
+    assert np.abs(ds - dr).max() <= 1e-15 * dr.max() * 10
+    assert np.abs(nrm - nr).max() <= 1e-12
+    with pytest.raises(ibproj.IbError):
+        ibproj.surface_lsq_3d(V, np.where(T == 0, len(V), T), 1.0)
