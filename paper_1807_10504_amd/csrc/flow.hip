@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "common.h"
+#include "surface_gpu.h"
 
 namespace ib {
 
@@ -271,6 +272,7 @@ struct ib_flow {
     double* mred = nullptr;   // density-sum partials (kMeanParts) + the sum
     FreeFall ff;
     ib_indicator* ind = nullptr;  // conventional scheme: indicator of eq ind_psn
+    SurfMesh mesh;                // 3D: the moving surface's connectivity on the device
     double* prop = nullptr;       // the indicator field of the step
 };
 
@@ -286,6 +288,7 @@ static void free_flow(ib_flow* f) {
     for (double* p : {f->Hn, f->rho_n, f->mu, f->red, f->mred, f->prop})
         if (p) hipFree(p);
     if (f->ind) ib_indicator_destroy(f->ind);
+    f->mesh.release();
     if (f->host) hipHostFree(f->host);
     delete f;
 }
@@ -481,25 +484,17 @@ extern "C" int ib_predict(ib_flow* f, const double* const u[3], const double* rh
                         (hipStream_t)stream);
 }
 
-// 3D: the vertices advanced by dt U (host) and moved onto the local
-// least-squares surface, whose normals, curvature force and areas go to the
-// device marker buffers of the context
-static int relocate_3d(Ctx* c, const ib_params* prm, ib_state* stt, const double* U_dev, double* fs_host,
-                       ib_surface* s, hipStream_t st) {
+// 3D: the vertices advanced by dt U and moved onto the local least-squares
+// surface on the device (its normals, curvature force and areas into the
+// context's marker buffers); the host copy of the vertices follows
+static int relocate_3d(ib_flow* f, Ctx* c, const ib_params* prm, ib_state* stt, const double* U_dev,
+                       double* fs_host, ib_surface* s, hipStream_t st) {
     const int n = s->n_markers;
-    std::vector<double> U(3 * (size_t)n), Xa(3 * (size_t)n), Xn(3 * (size_t)n), fs(n), ds(n), nr(3 * (size_t)n);
-    IB_HIP(hipMemcpyAsync(U.data(), U_dev, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, st));
+    IB_TRY(f->mesh.prepare(n, s->n_elems, stt->elems_host));
+    IB_TRY(f->mesh.reconstruct(c->mX, U_dev, prm->dt, prm->sigma, c->mX, c->mfs, c->mds, c->mnrm, st));
+    IB_HIP(hipMemcpyAsync(stt->X_host, c->mX, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, st));
+    if (fs_host) IB_HIP(hipMemcpyAsync(fs_host, c->mfs, sizeof(double) * n, hipMemcpyDeviceToHost, st));
     IB_HIP(hipStreamSynchronize(st));
-    for (size_t k = 0; k < 3 * (size_t)n; ++k) Xa[k] = stt->X_host[k] + prm->dt * U[k];
-    IB_TRY(ib_surface_lsq_3d(n, Xa.data(), s->n_elems, stt->elems_host, prm->sigma, Xn.data(), fs.data(),
-                             ds.data(), nr.data()));
-    std::memcpy(stt->X_host, Xn.data(), sizeof(double) * 3 * n);
-    if (fs_host) std::memcpy(fs_host, fs.data(), sizeof(double) * n);
-    IB_HIP(hipMemcpyAsync(c->mX, Xn.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, st));
-    IB_HIP(hipMemcpyAsync(c->mfs, fs.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
-    IB_HIP(hipMemcpyAsync(c->mds, ds.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
-    IB_HIP(hipMemcpyAsync(c->mnrm, nr.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, st));
-    IB_HIP(hipStreamSynchronize(st));  // the host vectors must outlive the copies
     s->X = c->mX;
     s->fs = c->mfs;
     s->ds = c->mds;
@@ -580,7 +575,7 @@ extern "C" int flow_step(ib_ctx* ctx, ib_flow* f, mg_handle* m, const ib_params*
     if (dim == 2)
         IB_TRY(relocate_2d(c, prm, stt, out->U, out->fs_host, &s, st, NAN, mass_target, &FS->mass_delta));
     else
-        IB_TRY(relocate_3d(c, prm, stt, out->U, out->fs_host, &s, st));
+        IB_TRY(relocate_3d(f, c, prm, stt, out->U, out->fs_host, &s, st));
     // H^{n+1} and the face force
     double* H = out->H ? out->H : c->H;
     double* F[3];
