@@ -802,6 +802,10 @@ def main():
     ap.add_argument("--nn3d-iters", type=int, default=60, help="training iterations of the 3D network")
     ap.add_argument("--no-flow", action="store_true",
                     help="skip the full 2D flow steps and the 3D momentum predictor")
+    ap.add_argument("--section", default=None,
+                    choices=("flow_osc", "static_tables", "conventional", "osc_energy", "flow3d", "free_fall",
+                             "predictor_3d"),
+                    help="run only this section of the flow measurements and print its JSON (for profiling)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MB (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -816,6 +820,12 @@ def main():
     from paper_1807_10504_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     ib.load()
+    if args.section:
+        run = {"flow_osc": bench_flow_osc, "static_tables": bench_static_tables, "conventional": bench_conventional,
+               "osc_energy": bench_osc_energy, "flow3d": bench_flow3d, "free_fall": bench_free_fall,
+               "predictor_3d": lambda ib_, t_: bench_predictor_3d(ib_, t_, args.size)}[args.section]
+        print(json.dumps({args.section: run(ib, torch)}), flush=True)
+        return
     wl = W.static_drop_3d(args.size, args.level, seed=3)
     log(f"workload {wl.name}: {len(wl.X)} markers, {len(wl.tris)} triangles")
     geo = ib.surface_geometry_3d(wl.X, wl.tris, wl.sigma)
