@@ -269,8 +269,8 @@ def test_flow_step_errors(ib):
     mg3 = ib.Multigrid(3, (16, 16, 16), 1 / 16)
     fl3 = ib.Flow(3, (16, 16, 16), 1 / 16)
     u = [torch.zeros((16, 16, 16), dtype=torch.float64, device="cuda") for _ in range(3)]
-    with pytest.raises(ib.IbError):
-        ctx3.flow_step(mg3, fl3, dict(rho_in=1, rho_out=1, dt=1e-3), u, np.zeros((8, 2)))
+    with pytest.raises(ValueError):                # a 3D step needs the surface's triangles
+        ctx3.flow_step(mg3, fl3, dict(rho_in=1, rho_out=1, dt=1e-3), u, np.zeros((8, 3)))
     ctx = ib.Context(2, (32, 32), 1 / 32, max_markers=64)
     mg = ib.Multigrid(2, (32, 32), 1 / 32)
     fl = ib.Flow(2, (64, 64), 1 / 64)          # another grid
