@@ -201,7 +201,7 @@ def flow_step_2d(n, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, X, H_prev, 
 
 
 def flow_step_3d(n, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, V, T, H_prev, adv_prev=None,
-                 p_prev=None, rtol=1e-10, max_cycles=100):
+                 p_prev=None, rtol=1e-10, max_cycles=100, gravity=0.0):
     """One step with a moving closed triangulated surface (the 3D counterpart of
     flow_step_2d; the paper leaves moving surfaces to future work):
       1. U = interpolation of u^n to the vertices; V + dt U moved onto the local
@@ -209,7 +209,8 @@ def flow_step_3d(n, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, V, T, H_pre
          sigma kappa, vertex areas); the triangles are kept;
       2. H^{n+1} from the surfaces offset along those normals, F the
          irrotational face force (nearest triangle);
-      3. - 5. as flow_step_2d."""
+      3. - 5. as flow_step_2d (gravity: the weight (rho - rho_mean) g on the y
+         faces, as in the planar step)."""
     from . import surface3d
     U = transfer.interp(u, V, h)
     Vn, fs, ds, nrm = surface3d.lsq_reconstruct(np.asarray(V) + dt * U, T, sigma)
@@ -218,7 +219,11 @@ def flow_step_3d(n, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, V, T, H_pre
     rho_n = poisson.density(H_prev, rho_in, rho_out)
     rho1 = poisson.density(H, rho_in, rho_out)
     mu = poisson.density(H, mu_in, mu_out)
-    u_star, adv = predict(u, rho_n, rho1, mu, dt, h, adv_prev)
+    f_body = None
+    if gravity != 0.0:
+        from . import dynamics
+        f_body = [None, dynamics.body_force(face_density(rho1, 3, 1), rho1.mean(), gravity, 0.0), None]
+    u_star, adv = predict(u, rho_n, rho1, mu, dt, h, adv_prev, f_body)
     beta = poisson.face_beta(rho1)
     b = poisson.rhs(u_star, F, beta, dt, h)
     p, cycles, _ = poisson.mg_solve(b, beta, h, p0=p_prev, rtol=rtol, max_cycles=max_cycles)

@@ -3,7 +3,8 @@ surface reconstruction (the 3D counterpart of Section 4's B-spline; the
 paper's future work) against the oracle, and a free oscillation.
 
 * two steps of flow_step in 3D against oracle.flow.flow_step_3d on 16^3 and
-  32 x 16 x 16 (an ellipsoidal drop, density ratio 100): vertices to 1e-12,
+  32 x 16 x 16 (an ellipsoidal drop, density ratio 100; on 16^3 also with the
+  weight (rho - rho_mean) g along y): vertices to 1e-12,
   velocity to 1e-9 of its maximum, pressure to 1e-10;
 * a drop stretched by 1.1 along x (level-4 icosphere, R = 0.25, h = 1/64)
   contracts: its x-extent passes through the sphere's diameter and its
@@ -34,14 +35,14 @@ def host(t):
     return t.cpu().numpy()
 
 
-@pytest.mark.parametrize("n", [(16, 16, 16), (32, 16, 16)])
-def test_flow_step_3d_parity(ib, n):
+@pytest.mark.parametrize("n,grav", [((16, 16, 16), 0.0), ((32, 16, 16), 0.0), ((16, 16, 16), -5.0)])
+def test_flow_step_3d_parity(ib, n, grav):
     h = 1.0 / 16
     c = np.array([0.5 * n[0] * h, 0.5, 0.5])
     V0, T = W.sphere_mesh(1, 0.12, seed=3)
     V0 = c + (V0 - 0.5) * np.array([1.1, 1 / np.sqrt(1.1), 1 / np.sqrt(1.1)])
     prm = dict(rho_in=1.0, rho_out=1e-2, mu_in=1e-2, mu_out=1e-4, sigma=1.0, dt=1e-4, rtol=1e-12,
-               pred_rtol=1e-13, warm_start=ib.WS_PREV)
+               pred_rtol=1e-13, warm_start=ib.WS_PREV, gravity=grav)
     shape = tuple(reversed(n))
     ctx = ib.Context(3, n, h, max_markers=len(V0), max_elems=len(T))
     mg = ib.Multigrid(3, n, h, n_coarsest=2)
@@ -56,12 +57,12 @@ def test_flow_step_3d_parity(ib, n):
     for step in range(2):
         out = ctx.flow_step(mg, fl, prm, u, Vg, p_prev=p, out={"p": p, "u": u}, tris=T)
         r = oflow.flow_step_3d(n, h, 1.0, 1e-2, 1e-2, 1e-4, 1.0, 1e-4, uo, Vo, T, Ho, adv_prev=advo,
-                               p_prev=po, rtol=1e-12)
+                               p_prev=po, rtol=1e-12, gravity=grav)
         uo, Vo, Ho, advo, po = r["u"], r["X"], r["H"], r["adv"], r["p"]
         eu = max(np.abs(host(u[d]) - uo[d]).max() for d in range(3)) / max(np.abs(a).max() for a in uo)
         ep = np.linalg.norm(host(p) - po) / np.linalg.norm(po)
         ex = np.abs(Vg - Vo).max()
-        print(f"{n} step {step}: sweeps {out['flow']['sweeps']}, cycles {out['stats']['cycles']} "
+        print(f"{n} g={grav} step {step}: sweeps {out['flow']['sweeps']}, cycles {out['stats']['cycles']} "
               f"(oracle {r['cycles']}); |du|/|u| {eu:.1e}, p {ep:.1e}, X {ex:.1e}", flush=True)
         assert eu <= 1e-9 and ep <= 1e-10 and ex <= 1e-12
 
