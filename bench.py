@@ -625,19 +625,20 @@ def bench_predictor_3d(ib, torch, nc=256, calls=5):
     fl.predict(u, rho, rho, mu, 5e-5, rtol=1e-12, u_star=us)      # fills the history
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sw = []
+    sw, ck = [], []
     for _ in range(calls):
         _, st = fl.predict(u, rho, rho, mu, 5e-5, rtol=1e-12, u_star=us)
         sw.append(st["sweeps"])
+        ck.append(st["checks"])
     torch.cuda.synchronize()
     secs = (time.perf_counter() - t0) / calls
     N = float(nc) ** 3
-    s = float(np.mean(sw))
-    # copy u -> u* 48 B, right side 120 B, per sweep 104 B (two colour passes) + residual 64 B
-    algo = (48 + 120 + s * (104 + 64)) * N
+    s, c = float(np.mean(sw)), float(np.mean(ck))
+    # copy u -> u* 48 B, right side 120 B, per sweep 104 B (two colour passes), per residual check 64 B
+    algo = (48 + 120 + s * 104 + c * 64) * N
     fl.close()
     return dict(workload=f"predictor_3d_{nc}: smooth drop, rho 1/1e-3, mu 1e-2/1e-4, dt 5e-5, rtol 1e-12",
-                ms_per_call=round(1e3 * secs, 3), sweeps=s,
+                ms_per_call=round(1e3 * secs, 3), sweeps=s, residual_checks=c,
                 algorithmic_bytes=algo, achieved_GBs=round(algo / secs / 1e9, 1),
                 frac_hbm=round(algo / secs / 1e9 / HBM_PEAK_GBS, 4))
 

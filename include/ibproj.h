@@ -295,6 +295,7 @@ typedef struct {
     double com;              /* vertical centroid of the incoming markers */
     double measure;          /* their enclosed area / volume of revolution */
     double mass_delta;       /* normal displacement of the mass correction (0: none) */
+    int checks;              /* residual evaluations of the implicit system */
 } ib_flow_stats;
 
 typedef struct {
@@ -352,8 +353,10 @@ int  ib_flow_reset(ib_flow* f);
  * the Crank-Nicolson term). The implicit system (rho_f/dt - D/2) u* = g is
  * solved by red-black Gauss-Seidel on the faces of each component (red =
  * index sum even), starting from u^n, until ||g - M u*||_2 <= rtol ||g||_2
- * over all components (the norm is read on the host after every sweep:
- * syncs). Stores C(u^n) as the next step's history. u_star may not alias u.
+ * over all components (the norm is read on the host after every sweep from
+ * one sweep before the previous call's count on, so a call may run one sweep
+ * past the tolerance: syncs). Stores C(u^n) as the next step's history.
+ * u_star may not alias u.
  * Errors: IB_EINVAL, IB_ENOTCONV (u_star holds the last sweep), IB_ENAN. */
 int ib_predict(ib_flow* f, const double* const u[3], const double* rho_n, const double* rho_np1,
                const double* mu, double dt, double rtol, int max_sweeps, double* const u_star[3],
@@ -424,7 +427,7 @@ int  axi_project_step(ib_axi* a, mg_handle* m, const ib_params* prm, ib_state* s
  * u_r = 0 on face column 0 (axis, outer wall); the outer wall is free of
  * shear; the axis edges have zero radius. The implicit system is solved by
  * red-black Gauss-Seidel (index sum parity) to ||g - M u*|| <= rtol ||g||,
- * read after every sweep (syncs). The handle keeps the Adams-Bashforth
+ * read as in ib_predict (syncs). The handle keeps the Adams-Bashforth
  * history; ib_axi_reset forgets it (and the previous H of axi_flow_step). */
 int  ib_axi_reset(ib_axi* a);
 int  axi_predict(ib_axi* a, const double* const u[2], const double* rho_n, const double* rho_np1,

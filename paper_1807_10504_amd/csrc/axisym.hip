@@ -296,6 +296,7 @@ struct ib_axi {
     // predictor state (axi_predict, axi_flow_step)
     double* adv[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     int cur = 0, have_adv = 0, have_H = 0;
+    int last_sweeps = 0;                  // sweeps of the previous predictor call
     double* g[2] = {nullptr, nullptr};
     double* ustar[2] = {nullptr, nullptr};
     double* Hn = nullptr;
@@ -485,11 +486,15 @@ static int axi_predict_impl(ib_axi* a, const double* const u[2], const double* r
     int sweeps = 0;
     double rel = 0.0;
     S->first_step = first;
+    S->checks = 0;
     while (true) {
         for (int colour = 0; colour < 2; ++colour)
             hipLaunchKernelGGL(k_axi_helm_sweep, dim3(grid_for(N / 2)), dim3(kBlock), 0, st, ustar[0],
                                ustar[1], a->g[0], a->g[1], rho1, mu, nr, nz, h, inv_dt, colour);
         ++sweeps;
+        // the residual is read from one sweep before the previous call's count on
+        if (sweeps < a->last_sweeps - 1 && sweeps < max_sweeps) continue;
+        ++S->checks;
         hipLaunchKernelGGL(k_axi_helm_resid, dim3(nb), dim3(kBlock), 0, st, ustar[0], ustar[1], a->g[0],
                            a->g[1], rho1, mu, nr, nz, h, inv_dt, a->red);
         IB_TRY(device_sum(a->red, nb, a->red + 2 * kAxiRed, st));
@@ -514,6 +519,7 @@ static int axi_predict_impl(ib_axi* a, const double* const u[2], const double* r
             return fail(IB_ENOTCONV, "axi_predict: the implicit viscous system did not converge");
     }
     S->rel_res = rel;
+    a->last_sweeps = sweeps;
     return IB_OK;
 }
 
@@ -521,6 +527,7 @@ extern "C" int ib_axi_reset(ib_axi* a) {
     IB_CHECK(a, IB_EINVAL, "ib_axi_reset: null handle");
     a->have_adv = 0;
     a->have_H = 0;
+    a->last_sweeps = 0;
     a->ff = FreeFall();
     return IB_OK;
 }

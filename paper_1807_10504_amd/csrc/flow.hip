@@ -267,6 +267,7 @@ struct ib_flow {
     double* rho_n = nullptr;
     double* mu = nullptr;
     int have_H = 0;
+    int last_sweeps = 0;      // sweeps of the previous predictor call
     double* red = nullptr;    // 2 * kFlowRed partials + 2 sums
     double* host = nullptr;   // pinned: the two sums
     double* mred = nullptr;   // density-sum partials (kMeanParts) + the sum
@@ -337,6 +338,7 @@ extern "C" int ib_flow_reset(ib_flow* f) {
     IB_CHECK(f, IB_EINVAL, "ib_flow_reset: null handle");
     f->have_adv = 0;
     f->have_H = 0;
+    f->last_sweeps = 0;
     f->ff = FreeFall();
     return IB_OK;
 }
@@ -422,6 +424,7 @@ static int predict_impl(ib_flow* f, const double* const u[3], const double* rho_
     int sweeps = 0;
     double rel = 0.0;
     S->first_step = first;
+    S->checks = 0;
     while (true) {
         for (int colour = 0; colour < 2; ++colour) {
             if (dim == 2)
@@ -432,6 +435,9 @@ static int predict_impl(ib_flow* f, const double* const u[3], const double* rho_
                                    d, inv_dt, colour);
         }
         ++sweeps;
+        // the residual is read from one sweep before the previous call's count on
+        if (sweeps < f->last_sweeps - 1 && sweeps < max_sweeps) continue;
+        ++S->checks;
         const double* xc[3] = {ustar[0], ustar[1], ustar[2]};
         if (dim == 2)
             hipLaunchKernelGGL(k_helm_resid<2>, dim3(nb), blk, 0, st, vec3(xc, 2), vec3(gc, 2), rho1, mu, d,
@@ -465,6 +471,7 @@ static int predict_impl(ib_flow* f, const double* const u[3], const double* rho_
     }
     S->sweeps = sweeps;
     S->rel_res = rel;
+    f->last_sweeps = sweeps;
     return IB_OK;
 }
 

@@ -89,12 +89,12 @@ class Outputs(C.Structure):
 class FlowStats(C.Structure):
     _fields_ = [("sweeps", C.c_int), ("rel_res", C.c_double), ("first_step", C.c_int),
                 ("frame_a", C.c_double), ("com", C.c_double), ("measure", C.c_double),
-                ("mass_delta", C.c_double)]
+                ("mass_delta", C.c_double), ("checks", C.c_int)]
 
     def as_dict(self):
         return dict(sweeps=self.sweeps, rel_res=self.rel_res, first_step=self.first_step,
                     frame_a=self.frame_a, com=self.com, measure=self.measure,
-                    mass_delta=self.mass_delta)
+                    mass_delta=self.mass_delta, checks=self.checks)
 
 
 class FlowParams(C.Structure):
