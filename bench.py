@@ -121,7 +121,7 @@ def bench_3d_nn(ib, torch, wl, geo, steps, warmup, sps64, pairs=24, train_iters=
     """Learned warm start at the full 3D size: the 3D network is trained on cold FP64
     solutions of perturbed spheres (random radius 0.2-0.3, l = 2 modes of amplitude
     0.15; not the benchmark sphere) and then gives the cold-start guess of the
-    benchmark step, judged by flexible CG in FP64 and mixed precision."""
+    benchmark step, evaluated by flexible CG in FP64 and mixed precision."""
     from paper_1807_10504_amd import workloads as W
     n, h = wl.n, wl.h
     shape = tuple(reversed(n))
@@ -170,7 +170,7 @@ def bench_3d_nn(ib, torch, wl, geo, steps, warmup, sps64, pairs=24, train_iters=
     t_inf = (time.perf_counter() - t0) / 5
     del samples, b, H, g
     out = dict(workload=f"{pairs} perturbed spheres at {n[0]}^3 (level-6 meshes, R 0.2-0.3, l=2 modes of "
-                        f"amplitude 0.15) -> training pairs from cold FP64 solves; judged on the benchmark "
+                        f"amplitude 0.15) -> training pairs from cold FP64 solves; evaluated on the benchmark "
                         f"sphere (not in the training set)",
                pairs_s=round(t_pairs, 2), train_iters=train_iters, train_s=round(t_train, 2),
                loss_first=float(np.mean(losses[:5])), loss_last=float(np.mean(losses[-10:])),
@@ -645,7 +645,7 @@ def bench_predictor_3d(ib, torch, nc=256, calls=5):
 
 def bench_2d_c4_nn(ib, torch, n=512, steps=48, train_iters=300):
     """Learned warm start: oscillating drop (mode 2, amplitude 0.1), projection-only
-    dynamics; the network is trained on pairs the multigrid generates and judged
+    dynamics; the network is trained on pairs the multigrid generates and evaluated
     on held-out steps against a zero start (cold) and against p_prev (warm)."""
     from paper_1807_10504_amd import workloads as W
     h = 1.0 / n
@@ -811,8 +811,8 @@ def main():
                     help="also run a plain device copy of this many MB (PMC byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU decomposition is described, not built)", file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is a design, not an implementation)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -5,7 +5,7 @@ A 6-layer convolutional network maps three per-cell channels
 (divergence right side, inverse density, previous pressure) to a correction
 of the previous pressure; multigrid then starts from
     p0 = p_prev + s_p * y,
-and remains the judge of the final answer.
+and alone decides the final answer.
 
 Definition (2D; the 3D network is the same with 3x3x3 taps):
   * inputs, normalised per sample: x0 = b h^2 / s_b, x1 = (1/rho) / max(1/rho),

@@ -2,8 +2,8 @@
 // uses multigrid alone). A 6-layer convolutional network with 3x3 (2D) or
 // 3x3x3 (3D) taps (circular padding, channels 3 -> 32 x 5 -> 1, ReLU between)
 // maps the normalised right side, inverse density and previous pressure to a
-// pressure correction; multigrid starts from p0 = p_prev + s_p * y and stays
-// the judge.
+// pressure correction; multigrid starts from p0 = p_prev + s_p * y and alone
+// decides the final answer.
 //
 // Precision: bfloat16 weights, activations and gradients in memory, float32
 // accumulation on the matrix cores (v_mfma_f32_16x16x32_bf16), float32
