@@ -151,3 +151,12 @@ def test_surface_lsq_3d_matches_oracle(level):
     assert np.abs(nrm - nr).max() <= 1e-12
     with pytest.raises(ibproj.IbError):
         ibproj.surface_lsq_3d(V, np.where(T == 0, len(V), T), 1.0)
+
+
+def test_surface_lsq_3d_degenerate_neighbourhood():
+    # a tetrahedron: every two-ring holds 4 vertices, too few for the quadric
+    V = np.array([[0.5, 0.5, 0.7], [0.6, 0.45, 0.4], [0.4, 0.45, 0.4], [0.5, 0.62, 0.4]])
+    T = np.array([[0, 1, 3], [0, 3, 2], [0, 2, 1], [1, 2, 3]], dtype=np.int32)
+    with pytest.raises(ibproj.IbError) as e:
+        ibproj.surface_lsq_3d(V, T, 1.0)
+    assert e.value.code == ibproj.IB_EGEOM

@@ -82,6 +82,12 @@ def test_flow_step_3d_errors(ib):
     big = ib.Context(3, n, h, max_markers=len(V), max_elems=len(T) - 1)
     with pytest.raises(ib.IbError):
         big.flow_step(mg, fl, prm, u, V.copy(), tris=T)               # more triangles than the context holds
+    # a tetrahedron: two-rings too small for the quadric fit (refused on the host)
+    Vt = np.array([[0.5, 0.5, 0.7], [0.6, 0.45, 0.4], [0.4, 0.45, 0.4], [0.5, 0.62, 0.4]])
+    Tt = np.array([[0, 1, 3], [0, 3, 2], [0, 2, 1], [1, 2, 3]], dtype=np.int32)
+    with pytest.raises(ib.IbError) as e:
+        ctx.flow_step(mg, fl, prm, u, Vt.copy(), tris=Tt)
+    assert e.value.code == ib.IB_EGEOM
 
 
 def test_oscillating_drop_3d(ib):
