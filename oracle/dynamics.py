@@ -54,25 +54,40 @@ def revolution_volume_centroid(X, axis_x):
     return V, zc
 
 
-def measure(X, axis_x=None):
-    """(enclosed area or volume, vertical centroid)."""
+def mesh_volume_centroid(V, T):
+    """Volume enclosed by the closed triangulated surface (V, T outward counter-
+    clockwise) and the y coordinate of its centroid (the vertical axis of the 3D
+    runs): the divergence theorem over the tetrahedra (origin, a, b, c), each of
+    volume a . (b x c) / 6 and centroid (a + b + c) / 4."""
+    V = np.asarray(V, dtype=np.float64)
+    a, b, c = V[T[:, 0]], V[T[:, 1]], V[T[:, 2]]
+    vt = np.einsum("ij,ij->i", a, np.cross(b, c)) / 6.0
+    vol = float(np.sum(vt))
+    cy = float(np.sum(vt * (a[:, 1] + b[:, 1] + c[:, 1]) / 4.0)) / vol
+    return vol, cy
+
+
+def measure(X, axis_x=None, T=None):
+    """(enclosed area, volume of revolution or mesh volume; vertical centroid)."""
+    if T is not None:
+        return mesh_volume_centroid(X, T)
     if axis_x is None:
         A, _, cy = polygon_area_centroid(X)
         return A, cy
     return revolution_volume_centroid(X, axis_x)
 
 
-def mass_correct(X, nrm, target, axis_x=None, h=1.0, trigger=1e-6, tol=1e-12):
-    """Move the markers along their normals (toward the drop for delta > 0) so
-    that the enclosed area / volume returns to target; unchanged when the
-    relative difference is at most `trigger`."""
-    v0, _ = measure(X, axis_x)
+def mass_correct(X, nrm, target, axis_x=None, h=1.0, trigger=1e-6, tol=1e-12, T=None):
+    """Move the markers (mesh vertices when T is given) along their normals
+    (toward the drop for delta > 0) so that the enclosed area / volume returns
+    to target; unchanged when the relative difference is at most `trigger`."""
+    v0, _ = measure(X, axis_x, T)
     if abs(v0 - target) <= trigger * abs(target):
         return X, 0.0
     lo, hi = -h, h          # volume decreases with delta
     for _ in range(200):
         mid = 0.5 * (lo + hi)
-        v, _ = measure(X + mid * nrm, axis_x)
+        v, _ = measure(X + mid * nrm, axis_x, T)
         if abs(v - target) <= tol * abs(target):
             break
         if v > target:

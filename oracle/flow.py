@@ -201,7 +201,7 @@ def flow_step_2d(n, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, X, H_prev, 
 
 
 def flow_step_3d(n, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, V, T, H_prev, adv_prev=None,
-                 p_prev=None, rtol=1e-10, max_cycles=100, gravity=0.0):
+                 p_prev=None, rtol=1e-10, max_cycles=100, gravity=0.0, frame_a=0.0, mass_target=None):
     """One step with a moving closed triangulated surface (the 3D counterpart of
     flow_step_2d; the paper leaves moving surfaces to future work):
       1. U = interpolation of u^n to the vertices; V + dt U moved onto the local
@@ -209,20 +209,25 @@ def flow_step_3d(n, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, V, T, H_pre
          sigma kappa, vertex areas); the triangles are kept;
       2. H^{n+1} from the surfaces offset along those normals, F the
          irrotational face force (nearest triangle);
-      3. - 5. as flow_step_2d (gravity: the weight (rho - rho_mean) g on the y
-         faces, as in the planar step)."""
+      3. - 5. as flow_step_2d (gravity, frame_a: the weight (rho - rho_mean) g
+         and the frame force rho a on the y faces; mass_target: the fitted
+         vertices moved along their normals to that enclosed volume, as in the
+         planar step)."""
     from . import surface3d
     U = transfer.interp(u, V, h)
     Vn, fs, ds, nrm = surface3d.lsq_reconstruct(np.asarray(V) + dt * U, T, sigma)
+    if mass_target is not None:
+        from . import dynamics
+        Vn, _ = dynamics.mass_correct(Vn, nrm, mass_target, None, h, T=T)
     H = heaviside.heaviside_3d(Vn, T, n, h, nrm=nrm)
     F = force.irrotational_force(H, Vn, fs, h, tris=T)
     rho_n = poisson.density(H_prev, rho_in, rho_out)
     rho1 = poisson.density(H, rho_in, rho_out)
     mu = poisson.density(H, mu_in, mu_out)
     f_body = None
-    if gravity != 0.0:
+    if gravity != 0.0 or frame_a != 0.0:
         from . import dynamics
-        f_body = [None, dynamics.body_force(face_density(rho1, 3, 1), rho1.mean(), gravity, 0.0), None]
+        f_body = [None, dynamics.body_force(face_density(rho1, 3, 1), rho1.mean(), gravity, frame_a), None]
     u_star, adv = predict(u, rho_n, rho1, mu, dt, h, adv_prev, f_body)
     beta = poisson.face_beta(rho1)
     b = poisson.rhs(u_star, F, beta, dt, h)

@@ -88,3 +88,29 @@ def test_body_force_net_zero_and_resting_fluid():
     rfa = 0.5 * (ra + np.roll(ra, 1, axis=0))
     fa = dynamics.body_force(rfa, rho_mean, -1.0, 0.0)
     assert abs(np.sum(fa * rc[None, :])) <= 1e-12 * np.sum(np.abs(fa) * rc[None, :])
+
+
+def test_mesh_volume_centroid_and_correction():
+    # a unit cube's 12 outward triangles: volume 1, centroid at its centre
+    Vc = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0], [0, 0, 1], [1, 0, 1], [1, 1, 1], [0, 1, 1]],
+                  dtype=float) + np.array([0.2, 0.3, 0.1])
+    Tc = np.array([[0, 2, 1], [0, 3, 2], [4, 5, 6], [4, 6, 7], [0, 1, 5], [0, 5, 4],
+                   [1, 2, 6], [1, 6, 5], [2, 3, 7], [2, 7, 6], [3, 0, 4], [3, 4, 7]])
+    vol, cy = dynamics.mesh_volume_centroid(Vc, Tc)
+    assert abs(vol - 1.0) <= 1e-14 and abs(cy - 0.8) <= 1e-14
+    # icospheres: inscribed volumes converge to 4/3 pi R^3 at second order, centroid exact
+    R = 0.25
+    errs = []
+    for level in (3, 4):
+        V, T = W.sphere_mesh(level, R, seed=3)
+        vol, cy = dynamics.mesh_volume_centroid(V, T)
+        errs.append(abs(vol - 4 / 3 * np.pi * R ** 3))
+        assert abs(cy - 0.5) <= 1e-12
+    assert 3.5 < errs[0] / errs[1] < 4.5
+    # the correction restores a shrunk mesh along the (inward) normals
+    from oracle import surface3d
+    V, T = W.sphere_mesh(3, R, seed=3)
+    target, _ = dynamics.measure(V, T=T)
+    nrm = surface3d.vertex_normals(V, T)
+    Vc2, delta = dynamics.mass_correct(V + 2e-4 * nrm, nrm, target, None, h=1 / 64, T=T)
+    assert abs(dynamics.measure(Vc2, T=T)[0] - target) <= 1e-12 * target and abs(delta + 2e-4) <= 1e-9
