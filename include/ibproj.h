@@ -368,8 +368,10 @@ int ib_predict(ib_flow* f, const double* const u[3], const double* rho_n, const 
  *   least-squares surface of ib_surface_lsq_3d (3D; the surface's normals,
  *   curvature force and areas come from the same fit) -- X_host in place;
  *   3D also needs st->surf.n_elems, st->surf.elems (device) and
- *   st->elems_host; the mesh keeps its connectivity (no remeshing), and the
- *   free-fall frame and mass correction are planar only (IB_EINVAL);
+ *   st->elems_host; the mesh keeps its connectivity (no remeshing); the
+ *   free-fall frame and mass correction use the mesh's volume and the y of
+ *   its centroid (ib_mesh_measure, ib_mesh_mass_correct on the fitted
+ *   vertices along their fitted normals);
  *   H^{n+1}, F from the relocated markers; rho^n from the previous step's H
  *   (the first step after create/reset computes H of the incoming markers,
  *   in 3D offset along the normals of their reconstruction);
@@ -483,6 +485,19 @@ int  ib_indicator_solve(ib_ctx* ctx, ib_indicator* ind, const ib_surface* s, dou
  * encloses on the side x >= axis_x, and the y (axial) coordinate of its
  * centroid. Host arrays. Errors: IB_EINVAL, IB_EGEOM (empty curve). */
 int ib_enclosed_measure(int n, const double* X, double axis_x, double* measure, double* com);
+
+/* Volume enclosed by a closed triangulated surface (V: nv x 3, T: nt x 3
+ * outward counter-clockwise, host) and the y coordinate of its centroid (the
+ * vertical axis of 3D runs), by the divergence theorem. Errors: IB_EINVAL,
+ * IB_EGEOM (no positive volume). */
+int ib_mesh_measure(int nv, const double* V, int nt, const int32_t* T, double* volume, double* com);
+
+/* The mass correction below for such a mesh: every vertex moves by one
+ * distance delta along its unit normal nrm (nv x 3, toward the drop), delta by
+ * bisection on [-h, h] to |V - target| <= tol target, when |V - target| >
+ * trigger target. V in place. Errors: IB_EINVAL. */
+int ib_mesh_mass_correct(int nv, double* V, const double* nrm, int nt, const int32_t* T, double target,
+                         double h, double trigger, double tol, double* delta);
 
 /* Mass correction (Section 2.1, conservation of mass): when |V - target| >
  * trigger target (V as ib_enclosed_measure), move every marker of X (host,

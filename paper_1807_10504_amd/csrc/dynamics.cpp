@@ -54,7 +54,61 @@ void measure(int n, const double* X, double axis_x, double* vol, double* com) {
     *com = (M_PI * vz) / (M_PI * v);
 }
 
+// volume enclosed by a closed outward mesh and the y of its centroid (the
+// divergence theorem over the tetrahedra origin, a, b, c)
+void mesh_measure(int nv, const double* V, int nt, const int* T, double* vol, double* com) {
+    (void)nv;
+    double v = 0.0, vy = 0.0;
+    for (int t = 0; t < nt; ++t) {
+        const double* a = V + 3 * T[3 * t];
+        const double* b = V + 3 * T[3 * t + 1];
+        const double* c = V + 3 * T[3 * t + 2];
+        const double cx = b[1] * c[2] - b[2] * c[1], cy = b[2] * c[0] - b[0] * c[2], cz = b[0] * c[1] - b[1] * c[0];
+        const double vt = (a[0] * cx + a[1] * cy + a[2] * cz) / 6.0;
+        v += vt;
+        vy += vt * (a[1] + b[1] + c[1]) / 4.0;
+    }
+    *vol = v;
+    *com = vy / v;
+}
+
 }  // namespace
+
+extern "C" int ib_mesh_measure(int nv, const double* V, int nt, const int* T, double* vol, double* com) {
+    if (nv < 4 || nt < 4 || !V || !T || !vol || !com) return ib::fail(IB_EINVAL, "ib_mesh_measure: arguments");
+    for (long i = 0; i < 3L * nt; ++i)
+        if (T[i] < 0 || T[i] >= nv) return ib::fail(IB_EINVAL, "ib_mesh_measure: triangle index out of range");
+    mesh_measure(nv, V, nt, T, vol, com);
+    if (!std::isfinite(*vol) || !(*vol > 0.0)) return ib::fail(IB_EGEOM, "ib_mesh_measure: no enclosed volume");
+    return IB_OK;
+}
+
+extern "C" int ib_mesh_mass_correct(int nv, double* V, const double* nrm, int nt, const int* T, double target,
+                                    double h, double trigger, double tol, double* delta) {
+    if (nv < 4 || nt < 4 || !V || !nrm || !T || !(target > 0.0) || !(h > 0.0))
+        return ib::fail(IB_EINVAL, "ib_mesh_mass_correct: arguments");
+    for (long i = 0; i < 3L * nt; ++i)
+        if (T[i] < 0 || T[i] >= nv) return ib::fail(IB_EINVAL, "ib_mesh_mass_correct: triangle index out of range");
+    double v, c;
+    mesh_measure(nv, V, nt, T, &v, &c);
+    if (delta) *delta = 0.0;
+    if (std::fabs(v - target) <= trigger * target) return IB_OK;
+    std::vector<double> Y(3 * (size_t)nv);
+    double lo = -h, hi = h, mid = 0.0;
+    for (int it = 0; it < 200; ++it) {
+        mid = 0.5 * (lo + hi);
+        for (size_t k = 0; k < 3 * (size_t)nv; ++k) Y[k] = V[k] + mid * nrm[k];
+        mesh_measure(nv, Y.data(), nt, T, &v, &c);
+        if (std::fabs(v - target) <= tol * target) break;
+        if (v > target)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    for (size_t k = 0; k < 3 * (size_t)nv; ++k) V[k] = Y[k];
+    if (delta) *delta = mid;
+    return IB_OK;
+}
 
 extern "C" int ib_enclosed_measure(int n, const double* X, double axis_x, double* vol, double* com) {
     if (n < 3 || !X || !vol || !com) return ib::fail(IB_EINVAL, "ib_enclosed_measure: arguments");
@@ -91,12 +145,13 @@ extern "C" int ib_mass_correct(int n, double* X, const double* nrm, double targe
 namespace ib {
 
 int freefall_begin(FreeFall* s, const ib_flow_params* fp, int n, const double* X, double axis_x,
-                   double dt, ib_flow_stats* st, const double** mass_target) {
+                   double dt, ib_flow_stats* st, const double** mass_target, int nt, const int* T) {
     *mass_target = nullptr;
     st->frame_a = st->com = st->measure = st->mass_delta = 0.0;
     if (!fp->frame && fp->mass_every <= 0) return IB_OK;
     double v, com;
-    if (ib_enclosed_measure(n, X, axis_x, &v, &com) != IB_OK) return IB_EGEOM;
+    const int rc = nt > 0 ? ib_mesh_measure(n, X, nt, T, &v, &com) : ib_enclosed_measure(n, X, axis_x, &v, &com);
+    if (rc != IB_OK) return IB_EGEOM;
     if (!s->have) {
         s->com0 = s->com_prev = com;
         s->vol0 = v;

@@ -541,8 +541,6 @@ extern "C" int flow_step(ib_ctx* ctx, ib_flow* f, mg_handle* m, const ib_params*
         IB_CHECK(n >= 4 && n <= c->max_markers, IB_EINVAL, "flow_step: vertex count");
         IB_CHECK(s.n_elems >= 4 && s.n_elems <= c->max_elems && s.elems && stt->elems_host, IB_EINVAL,
                  "flow_step: 3D needs the triangles (device surf.elems and elems_host)");
-        IB_CHECK(!fp->frame && fp->mass_every == 0, IB_EINVAL,
-                 "flow_step: the free-fall frame and mass correction are planar only");
     } else {
         IB_CHECK(n >= 3 && n <= c->max_markers, IB_EINVAL, "flow_step: marker count");
         s.elems = nullptr;
@@ -568,21 +566,29 @@ extern "C" int flow_step(ib_ctx* ctx, ib_flow* f, mg_handle* m, const ib_params*
         IB_CHECK(fl[0] == 0, IB_EGEOM, "flow_step: an offset surface comes within 4h of the box sides");
         f->have_H = 1;
     }
-    // free fall (2D): centroid and measure of the incoming markers
+    // free fall: centroid and measure of the incoming markers (3D: the mesh)
     ib_flow_stats loc{};
     ib_flow_stats* FS = fstats ? fstats : &loc;
     const double* mass_target = nullptr;
-    if (dim == 2)
-        IB_CHECK(freefall_begin(&f->ff, fp, n, stt->X_host, NAN, prm->dt, FS, &mass_target) == IB_OK, IB_EGEOM,
-                 "flow_step: the markers enclose no area");
-    else
-        FS->frame_a = FS->com = FS->measure = FS->mass_delta = 0.0;
+    IB_CHECK(freefall_begin(&f->ff, fp, n, stt->X_host, NAN, prm->dt, FS, &mass_target, dim == 3 ? s.n_elems : 0,
+                            dim == 3 ? stt->elems_host : nullptr) == IB_OK,
+             IB_EGEOM, "flow_step: the markers enclose no area / volume");
     // markers: interpolation of u^n, advance, relocation (and mass correction)
     IB_TRY(launch_interp(c, stt->u_star, &s, out->U, st));
     if (dim == 2)
         IB_TRY(relocate_2d(c, prm, stt, out->U, out->fs_host, &s, st, NAN, mass_target, &FS->mass_delta));
-    else
+    else {
         IB_TRY(relocate_3d(f, c, prm, stt, out->U, out->fs_host, &s, st));
+        if (mass_target) {
+            // the fitted vertices along their fitted normals, on the host
+            std::vector<double> nh(3 * (size_t)n);
+            IB_HIP(hipMemcpy(nh.data(), c->mnrm, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
+            IB_TRY(ib_mesh_mass_correct(n, stt->X_host, nh.data(), s.n_elems, stt->elems_host, *mass_target, c->d.h,
+                                        1e-6, 1e-12, &FS->mass_delta));
+            IB_HIP(hipMemcpyAsync(c->mX, stt->X_host, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st));
+            IB_HIP(hipStreamSynchronize(st));
+        }
+    }
     // H^{n+1} and the face force
     double* H = out->H ? out->H : c->H;
     double* F[3];

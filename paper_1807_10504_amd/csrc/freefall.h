@@ -20,7 +20,10 @@ struct FreeFall {
 // c2 (COM_n - COM_{n-1})/dt, else 0), and *mass_target with the first step's
 // measure (fp->mass_target when positive) when this step's relocated markers
 // take the mass correction (NULL otherwise). Does nothing but clear the stats when neither is on.
+// With nt > 0, X is a closed mesh (n vertices x 3, triangles T, host) and the
+// measure is its volume and the y of its centroid.
 int freefall_begin(FreeFall* s, const ib_flow_params* fp, int n, const double* X, double axis_x,
-                   double dt, ib_flow_stats* stats, const double** mass_target);
+                   double dt, ib_flow_stats* stats, const double** mass_target, int nt = 0,
+                   const int* T = nullptr);
 
 }  // namespace ib

@@ -32,7 +32,7 @@ EXPORTS = ("ib_create", "ib_destroy", "ib_bin_markers", "ib_interp", "ib_spread"
            "ib_advection", "ib_viscous", "ib_flow_create", "ib_flow_destroy", "ib_flow_reset",
            "ib_predict", "flow_step", "ib_axi_create", "ib_axi_destroy", "axi_project_step",
            "ib_axi_reset", "axi_predict", "axi_flow_step", "ib_enclosed_measure", "ib_mass_correct",
-           "ib_indicator_create", "ib_indicator_destroy", "ib_indicator_solve", "ib_markers_add_delete", "ib_surface_lsq_3d",
+           "ib_indicator_create", "ib_indicator_destroy", "ib_indicator_solve", "ib_markers_add_delete", "ib_surface_lsq_3d", "ib_mesh_measure", "ib_mesh_mass_correct",
            "ib_last_error")
 
 PROF_KINDS = ("smooth64", "smooth32", "restrict64", "restrict32", "prolong64", "prolong32", "resid",
@@ -194,6 +194,8 @@ def load(path: str = LIB_PATH):
         "ib_mass_correct": (i32, [i32, vp, vp, f64, f64, f64, f64, f64, P(f64)]),
         "ib_markers_add_delete": (i32, [i32, vp, f64, f64, f64, i32, vp, P(i32)]),
         "ib_surface_lsq_3d": (i32, [i32, vp, i32, vp, f64, vp, vp, vp, vp]),
+        "ib_mesh_measure": (i32, [i32, vp, i32, vp, P(f64), P(f64)]),
+        "ib_mesh_mass_correct": (i32, [i32, vp, vp, i32, vp, f64, f64, f64, f64, P(f64)]),
         "ib_indicator_create": (i32, [P(Grid), i32, P(vp)]),
         "ib_indicator_destroy": (None, [vp]),
         "ib_indicator_solve": (i32, [vp, vp, P(Surface), f64, i32, vp, P(MgStats), vp]),
@@ -851,6 +853,29 @@ def mass_correct(X, nrm, target, axis_x=None, h=1.0, trigger=1e-6, tol=1e-12):
                                float("nan") if axis_x is None else float(axis_x), float(h), float(trigger),
                                float(tol), C.byref(d)))
     return Xc, d.value
+
+
+def mesh_measure(V, T):
+    """(volume enclosed by the closed mesh, y of its centroid)."""
+    lib = load()
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.int32)
+    v, c = C.c_double(), C.c_double()
+    _check(lib.ib_mesh_measure(V.shape[0], _hptr(V), T.shape[0], _hptr(T, np.int32), C.byref(v), C.byref(c)))
+    return v.value, c.value
+
+
+def mesh_mass_correct(V, nrm, T, target, h, trigger=1e-6, tol=1e-12):
+    """Mesh vertices moved along their normals back to the enclosed volume `target`;
+    returns (V corrected, displacement)."""
+    lib = load()
+    Vc = np.array(V, dtype=np.float64, order="C")
+    nrm = np.ascontiguousarray(nrm, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.int32)
+    d = C.c_double()
+    _check(lib.ib_mesh_mass_correct(Vc.shape[0], _hptr(Vc), _hptr(nrm), T.shape[0], _hptr(T, np.int32),
+                                    float(target), float(h), float(trigger), float(tol), C.byref(d)))
+    return Vc, d.value
 
 
 def markers_add_delete(X, h, lo=0.5, hi=1.5):

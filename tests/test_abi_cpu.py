@@ -160,3 +160,20 @@ def test_surface_lsq_3d_degenerate_neighbourhood():
     with pytest.raises(ibproj.IbError) as e:
         ibproj.surface_lsq_3d(V, T, 1.0)
     assert e.value.code == ibproj.IB_EGEOM
+
+
+def test_mesh_measure_and_correction_match_oracle():
+    from oracle import dynamics, surface3d as s3
+    V, T = W.sphere_mesh(3, 0.25, seed=3)
+    V = 0.5 + (V - 0.5) * np.array([1.1, 0.95, 1.0])
+    v, c = ibproj.mesh_measure(V, T)
+    vo, co = dynamics.measure(V, T=T)
+    assert abs(v - vo) <= 1e-13 * vo and abs(c - co) <= 1e-13
+    nrm = s3.vertex_normals(V, T)
+    for sft in (2e-4, -1e-4):
+        Vc, d = ibproj.mesh_mass_correct(V + sft * nrm, nrm, T, vo, 1 / 64)
+        Vr, dr = dynamics.mass_correct(V + sft * nrm, nrm, vo, None, 1 / 64, T=T)
+        assert abs(d - dr) <= 1e-11 and np.abs(Vc - Vr).max() <= 1e-11
+        assert abs(dynamics.measure(Vc, T=T)[0] - vo) <= 2e-12 * vo
+    with pytest.raises(ibproj.IbError):
+        ibproj.mesh_measure(V, np.where(T == 0, len(V), T))

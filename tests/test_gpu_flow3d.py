@@ -67,6 +67,50 @@ def test_flow_step_3d_parity(ib, n, grav):
         assert eu <= 1e-9 and ep <= 1e-10 and ex <= 1e-12
 
 
+def test_flow_step_3d_freefall_parity(ib):
+    """Weight, restoring frame and mass correction (a volume 2e-4 above the
+    initial one) with a moving 3D surface over two steps against the oracle."""
+    from oracle import dynamics
+    n, h, dt = (16, 16, 16), 1.0 / 16, 1e-4
+    V0, T = W.sphere_mesh(1, 0.12, seed=3)
+    V0 = 0.5 + (V0 - 0.5) * np.array([1.1, 1 / np.sqrt(1.1), 1 / np.sqrt(1.1)])
+    vol0, c0 = dynamics.measure(V0, T=T)
+    target = vol0 * (1 + 2e-4)
+    prm = dict(rho_in=1.0, rho_out=1e-2, mu_in=1e-2, mu_out=1e-4, sigma=1.0, dt=dt, rtol=1e-12,
+               pred_rtol=1e-13, warm_start=ib.WS_PREV, gravity=-5.0, frame=True, mass_every=1,
+               mass_target=target)
+    ctx = ib.Context(3, n, h, max_markers=len(V0), max_elems=len(T))
+    mg = ib.Multigrid(3, n, h)
+    fl = ib.Flow(3, n, h)
+    u = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+    p = torch.zeros(n, dtype=torch.float64, device="cuda")
+    Vg = V0.copy()
+    uo = [np.zeros(n) for _ in range(3)]
+    Vo = V0.copy()
+    Ho = heaviside.heaviside_3d(Vo, T, n, h, nrm=surface3d.lsq_reconstruct(Vo, T, 1.0)[3])
+    advo, po, c_prev = None, None, c0
+    for step in range(2):
+        _, c = dynamics.measure(Vo, T=T)
+        a = dynamics.frame_acceleration(c0, c_prev, c, dt)
+        c_prev = c
+        out = ctx.flow_step(mg, fl, prm, u, Vg, p_prev=p, out={"p": p, "u": u}, tris=T)
+        r = oflow.flow_step_3d(n, h, 1.0, 1e-2, 1e-2, 1e-4, 1.0, dt, uo, Vo, T, Ho, adv_prev=advo, p_prev=po,
+                               rtol=1e-12, gravity=-5.0, frame_a=a, mass_target=target)
+        uo, Vo, Ho, advo, po = r["u"], r["X"], r["H"], r["adv"], r["p"]
+        f = out["flow"]
+        eu = max(np.abs(host(u[d]) - uo[d]).max() for d in range(3)) / max(np.abs(x).max() for x in uo)
+        ep = np.linalg.norm(host(p) - po) / np.linalg.norm(po)
+        ex = np.abs(Vg - Vo).max()
+        print(f"step {step}: frame a {f['frame_a']:.3e} (oracle {a:.3e}), mass delta {f['mass_delta']:.2e}, "
+              f"|du|/|u| {eu:.1e}, p {ep:.1e}, X {ex:.1e}", flush=True)
+        assert abs(f["frame_a"] - a) <= 1e-7 and abs(f["com"] - c) <= 1e-12
+        # the fit of this coarse mesh (42 vertices) changes the volume by more than
+        # the trigger every step, so every step is corrected back to the target
+        assert f["mass_delta"] != 0.0
+        assert abs(dynamics.measure(Vg, T=T)[0] - target) <= 2e-12 * target
+        assert eu <= 1e-9 and ep <= 1e-10 and ex <= 1e-12
+
+
 def test_flow_step_3d_errors(ib):
     n, h = (16, 16, 16), 1 / 16
     V, T = W.sphere_mesh(1, 0.12, seed=3)
@@ -77,8 +121,6 @@ def test_flow_step_3d_errors(ib):
     prm = dict(rho_in=1, rho_out=1, dt=1e-3)
     with pytest.raises(ValueError):
         ctx.flow_step(mg, fl, prm, u, V.copy())                       # no triangles
-    with pytest.raises(ib.IbError):
-        ctx.flow_step(mg, fl, dict(prm, frame=True), u, V.copy(), tris=T)   # planar only
     big = ib.Context(3, n, h, max_markers=len(V), max_elems=len(T) - 1)
     with pytest.raises(ib.IbError):
         big.flow_step(mg, fl, prm, u, V.copy(), tris=T)               # more triangles than the context holds
