@@ -81,10 +81,16 @@ def mirror_velocity(u, nr):
     return [ur, uz]
 
 
-def interface(Xd, fs_total, nr, nz, h):
-    """H and F of the half plane from the closed mirrored curve Xd."""
+def interface(Xd, fs_total, nr, nz, h, ds=None, nrm=None, conventional=False):
+    """H and F of the half plane from the closed mirrored curve Xd. conventional:
+    F is the marker force fs ds n spread by the discrete delta function on the
+    doubled plane (the surface delta of an axisymmetric surface, restricted to
+    the meridian plane, is the curve's delta)."""
     H2 = heaviside.heaviside_2d(Xd, (2 * nr, nz), h)
-    F2 = force.irrotational_force(H2, Xd, fs_total, h)
+    if conventional:
+        F2 = transfer.spread_delta(transfer.marker_forces(fs_total, ds, nrm), Xd, (2 * nr, nz), h)
+    else:
+        F2 = force.irrotational_force(H2, Xd, fs_total, h)
     H = H2[:, nr:].copy()
     F = [F2[0][:, nr:].copy(), F2[1][:, nr:].copy()]
     F[0][:, 0] = 0.0
@@ -110,7 +116,7 @@ def project(u_star, H, F, rho_in, rho_out, dt, h, p_prev=None, rtol=1e-10, max_c
     return dict(p=p, u=u, b=b, beta=beta, cycles=cycles, hist=hist)
 
 
-def project_step(nr, nz, h, rho_in, rho_out, sigma, dt, u_star, Xd, rtol=1e-10, p_prev=None):
+def project_step(nr, nz, h, rho_in, rho_out, sigma, dt, u_star, Xd, rtol=1e-10, p_prev=None, conventional=False):
     """One axisymmetric projection step: markers (closed mirrored curve in the
     doubled plane) advanced with the interpolated velocity and relocated on the
     least-squares B-spline, f from eq curv_ax, H and F, projection."""
@@ -119,7 +125,7 @@ def project_step(nr, nz, h, rho_in, rho_out, sigma, dt, u_star, Xd, rtol=1e-10, 
     Xn, fs, ds, nrm = bspline.relocate([tuple(x) for x in Xd], [tuple(v) for v in U], dt, h, sigma)
     Xn, fs, nrm = np.array(Xn), np.array(fs), np.array(nrm)
     ft = curvature_total(Xn, nrm, fs, sigma, nr * h, h)
-    H, F = interface(Xn, ft, nr, nz, h)
+    H, F = interface(Xn, ft, nr, nz, h, np.array(ds), nrm, conventional)
     out = project(u_star, H, F, rho_in, rho_out, dt, h, p_prev=p_prev, rtol=rtol)
     out.update(U=U, X=Xn, fs=ft, H=H, F=F)
     return out
@@ -269,7 +275,7 @@ def predict(u, rho_n, rho_np1, mu, dt, h, adv_prev=None, f_body=None):
 
 
 def flow_step(nr, nz, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, Xd, H_prev, adv_prev=None,
-              p_prev=None, rtol=1e-10, gravity=0.0, frame_a=0.0, mass_target=None):
+              p_prev=None, rtol=1e-10, gravity=0.0, frame_a=0.0, mass_target=None, conventional=False):
     """One step of the full axisymmetric method: markers advanced with u^n and
     relocated (eq curv_ax), H^{n+1} and F, rho^n from H_prev, the predictor, the
     projection of u*."""
@@ -281,7 +287,7 @@ def flow_step(nr, nz, h, rho_in, rho_out, mu_in, mu_out, sigma, dt, u, Xd, H_pre
         from . import dynamics
         Xn, _ = dynamics.mass_correct(Xn, nrm, mass_target, nr * h, h)
     ft = curvature_total(Xn, nrm, fs, sigma, nr * h, h)
-    H, F = interface(Xn, ft, nr, nz, h)
+    H, F = interface(Xn, ft, nr, nz, h, np.array(ds), nrm, conventional)
     rho_n = poisson.density(H_prev, rho_in, rho_out)
     rho1 = poisson.density(H, rho_in, rho_out)
     mu = poisson.density(H, mu_in, mu_out)

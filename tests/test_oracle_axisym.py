@@ -206,3 +206,21 @@ def test_axi_predictor_euler_and_crank_nicolson():
     g = (1 + 0.5 * dt * lam[q].real / rho) / (1 - 0.5 * dt * lam[q].real / rho)
     assert np.abs(us[1] - g * uz).max() <= 1e-12
     assert np.abs(us[0]).max() <= 1e-14
+
+
+def test_axi_conventional_force_totals():
+    """The conventional force on the doubled plane carries the marker forces'
+    total (partition of unity of the delta function); its axial component sums
+    to zero for a drop symmetric about z, and the half plane keeps half of the
+    radial magnitude."""
+    from oracle import bspline
+    nr, nz, h = 32, 64, 1 / 32
+    Xd = W.circle_markers(160, 0.3, centre=(nr * h, 1.0))
+    Xn, fs, ds, nrm = bspline.relocate([tuple(x) for x in Xd], [(0.0, 0.0)] * len(Xd), 0.0, h, 1.0)
+    Xn, fs, ds, nrm = np.array(Xn), np.array(fs), np.array(ds), np.array(nrm)
+    ft = axisym.curvature_total(Xn, nrm, fs, 1.0, nr * h, h)
+    H, F = axisym.interface(Xn, ft, nr, nz, h, ds, nrm, conventional=True)
+    Fm = (ft * ds)[:, None] * nrm
+    assert abs(F[1].sum() * h * h) <= 1e-12 * np.abs(Fm[:, 1]).sum()
+    right = Xn[:, 0] > nr * h
+    assert abs(F[0].sum() * h * h - Fm[right, 0].sum()) <= 0.02 * np.abs(Fm[right, 0]).sum()
