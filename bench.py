@@ -466,14 +466,17 @@ def bench_flow_osc(ib, torch):
             res[f"{'axis' if axis else '2d'}_h{h:g}"] = r
             log(f"  {'axisymmetric' if axis else '2D'} h={h}: period {r['period']} ({r['discrepancy_percent']} %), "
                 f"{r['steps_per_s']} steps/s")
-    # the conventional spreading's 2D periods (Table osc's other column)
-    for h, n, dt, steps, nm, paper in ((0.01, 256, 1e-4, 2600, 256, 0.2334), (0.005, 512, 5e-5, 5200, 512, 0.2326)):
-        r = _osc_run(ib, torch, False, n, h, dt, steps, nm, spread_mode=ib.IB_SPREAD_DELTA)
-        r["discrepancy_percent"] = round(100 * abs(r["period"] - T2) / T2, 2)
-        r["exact_period"] = round(float(T2), 5)
+    # the conventional spreading's periods (Table osc's other column)
+    for axis, T, h, n, dt, steps, nm, paper in ((False, T2, 0.01, 256, 1e-4, 2600, 256, 0.2334),
+                                                (False, T2, 0.005, 512, 5e-5, 5200, 512, 0.2326),
+                                                (True, Ta, 0.01, 256, 1e-4, 2300, 256, 0.2039)):
+        r = _osc_run(ib, torch, axis, n, h, dt, steps, nm, spread_mode=ib.IB_SPREAD_DELTA)
+        r["discrepancy_percent"] = round(100 * abs(r["period"] - T) / T, 2)
+        r["exact_period"] = round(float(T), 5)
         r["paper_conventional"] = paper
-        res[f"2d_conventional_h{h:g}"] = r
-        log(f"  2D conventional h={h}: period {r['period']} ({r['discrepancy_percent']} %), {r['steps_per_s']} steps/s")
+        res[f"{'axis' if axis else '2d'}_conventional_h{h:g}"] = r
+        log(f"  {'axisymmetric' if axis else '2D'} conventional h={h}: period {r['period']} "
+            f"({r['discrepancy_percent']} %), {r['steps_per_s']} steps/s")
     res["workload"] = ("Table osc drop: R=0.2 stretched by 1.03 (eq osc), rho 1/0.01, mu 0.01/1e-5, sigma=1; "
                        "2D: n^2 periodic box; axisymmetric: n x n meridian half plane (axis, outer wall at "
                        "r = n h, periodic along the axis); n = 256 at h = 0.01 (dt 1e-4), 512 at h = 0.005 "
@@ -567,8 +570,9 @@ def bench_static_tables(ib, torch, reps=3):
     paper_2d = [1.1082e-3, 4.1935e-4, 5.5086e-4, 2.2961e-4, 1.2822e-4]
     paper_ax = [4.0890e-3, 1.3275e-3, 1.2220e-3, 4.8848e-4, 2.2793e-4]
     paper_2d_conv = [1.6475e-3, 1.4186e-3, 1.1080e-3, 1.0822e-3, 1.0744e-3]
+    paper_ax_conv = [5.0019e-3, 8.8084e-4, 8.6586e-4, 1.8752e-3, 2.3319e-3]
     rows = []
-    for dx, p2, pa, pc in zip(dxs, paper_2d, paper_ax, paper_2d_conv):
+    for dx, p2, pa, pc, pac in zip(dxs, paper_2d, paper_ax, paper_2d_conv, paper_ax_conv):
         nm = int(round(2 * np.pi * 0.2 / (0.63 * dx))) // 4 * 4
         prm = dict(rho_in=1.0, rho_out=0.01, sigma=1.0, dt=1e-3, rtol=1e-10, warm_start=ib.WS_ZERO)
         # 2D
@@ -611,14 +615,19 @@ def bench_static_tables(ib, torch, reps=3):
         hc = ib.Context(2, (nr, 2 * nr), dx, max_markers=16)
         ea = abs(hc.diagnostics(p=out["p"], H=out["H"])["dP"] - 10.0)
         msa = 1e3 * min(times)
+        X = W.circle_markers(nm, 0.2, centre=(nr * dx, nr * dx))
+        out = {"H": torch.empty((2 * nr, nr), dtype=torch.float64, device="cuda")}
+        out = ax.project_step(mg, dict(prm, spread_mode=ib.IB_SPREAD_DELTA), zero, X, out=out)
+        eac = abs(hc.diagnostics(p=out["p"], H=out["H"])["dP"] - 10.0)
         ax.close()
         mg.close()
         hc.close()
         rows.append(dict(dx=dx, markers=nm, err_2d=float(f"{e2:.4e}"), paper_new_2d=p2, ms_2d=round(ms2, 3),
                          err_2d_conventional=float(f"{e2c:.4e}"), paper_conventional_2d=pc,
-                         err_axis=float(f"{ea:.4e}"), paper_new_axis=pa, ms_axis=round(msa, 3)))
+                         err_axis=float(f"{ea:.4e}"), paper_new_axis=pa, ms_axis=round(msa, 3),
+                         err_axis_conventional=float(f"{eac:.4e}"), paper_conventional_axis=pac))
         log(f"  dx {dx}: 2D |dP-5| {e2:.3e} (paper {p2}; conventional {e2c:.3e}, paper {pc}), "
-            f"axis |dP-10| {ea:.3e} (paper {pa})")
+            f"axis |dP-10| {ea:.3e} (paper {pa}; conventional {eac:.3e}, paper {pac})")
     return dict(workload="Tables staticdrop_2d / staticdrop_axis: D = 0.4, rho 1/0.01, sigma 1, one step "
                          "of 1e-3 from rest; 2D box 1.28, axisymmetric half plane 0.64 x 1.28, periodic; "
                          "flexible-CG projection to 1e-10", rows=rows)

@@ -409,8 +409,11 @@ int  ib_axi_create(const ib_grid* g, int max_markers, ib_axi** out);
 void ib_axi_destroy(ib_axi* a);
 /* st->u_star: the half-plane velocity (u_r, u_z); st->p_prev with WS_PREV;
  * out: p, u (may alias u_star), U (n_markers x 2, doubled-plane marker
- * velocities) required; H, F (half plane), b, fs_host optional. Spreading is
- * irrotational only; warm start WS_ZERO or WS_PREV. Syncs as project_step.
+ * velocities) required; H, F (half plane), b, fs_host optional. Spreading:
+ * IB_SPREAD_IRROT, or IB_SPREAD_DELTA (the marker force fs ds n spread by the
+ * delta function on the doubled plane: an axisymmetric surface's delta on the
+ * meridian plane is the curve's); warm start WS_ZERO or WS_PREV. Syncs as
+ * project_step.
  * Errors: as project_step. */
 int  axi_project_step(ib_axi* a, mg_handle* m, const ib_params* prm, ib_state* st,
                       ib_outputs* out, void* stream);

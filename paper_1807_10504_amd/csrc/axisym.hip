@@ -418,7 +418,10 @@ static int axi_interface(ib_axi* a, const ib_params* prm, ib_state* stt, ib_outp
     IB_TRY(launch_interp(F, udc, s, out->U, st));
     IB_TRY(relocate_2d(F, prm, stt, out->U, out->fs_host, s, st, (double)nr * a->h, mass_target, mass_delta));
     double* Ff[3] = {F->F[0], F->F[1], F->F[1]};
-    IB_TRY(spread_impl(F, s, IB_SPREAD_IRROT, Ff, F->H, st));
+    // irrotational, or the conventional delta-function spreading of fs ds n on the
+    // doubled plane (an axisymmetric surface's delta restricted to the meridian
+    // plane is the curve's delta); H is formed either way
+    IB_TRY(spread_impl(F, s, prm->spread_mode, Ff, F->H, st));
     const size_t row = sizeof(double) * nr, frow = 2 * row;
     IB_HIP(hipMemcpy2DAsync(H, row, F->H + nr, frow, row, nz, hipMemcpyDeviceToDevice, st));
     for (int q = 0; q < 2; ++q)
@@ -435,8 +438,8 @@ static int axi_check(ib_axi* a, mg_handle* m, const ib_params* prm, ib_state* st
              std::string(who) + ": u_star and X_host are required");
     IB_CHECK(prm->dt > 0 && prm->rho_in > 0 && prm->rho_out > 0, IB_EINVAL,
              std::string(who) + ": dt and densities must be positive");
-    IB_CHECK(prm->spread_mode == IB_SPREAD_IRROT, IB_EINVAL,
-             std::string(who) + ": only the irrotational spreading is provided");
+    IB_CHECK(prm->spread_mode == IB_SPREAD_IRROT || prm->spread_mode == IB_SPREAD_DELTA, IB_EINVAL,
+             std::string(who) + ": spread mode");
     IB_CHECK(prm->warm_start == WS_ZERO || prm->warm_start == WS_PREV, IB_EINVAL,
              std::string(who) + ": warm start must be WS_ZERO or WS_PREV");
     IB_CHECK(stt->surf.n_markers >= 3 && stt->surf.n_markers <= a->full->max_markers, IB_EINVAL,

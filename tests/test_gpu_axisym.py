@@ -42,16 +42,17 @@ def ib():
     return ibproj
 
 
-def _run(ib, nr, nz, h, Xd, u, dt, rho_out=0.01):
+def _run(ib, nr, nz, h, Xd, u, dt, rho_out=0.01, conventional=False):
     ax = ib.Axisym(nr, nz, h, max_markers=len(Xd))
     mg = ib.Multigrid(2, (nr, nz), h)
-    prm = dict(rho_in=1.0, rho_out=rho_out, sigma=1.0, dt=dt, rtol=1e-12, warm_start=ib.WS_ZERO)
+    prm = dict(rho_in=1.0, rho_out=rho_out, sigma=1.0, dt=dt, rtol=1e-12, warm_start=ib.WS_ZERO,
+               spread_mode=ib.IB_SPREAD_DELTA if conventional else ib.IB_SPREAD_IRROT)
     X = Xd.copy()
     out = {"H": torch.empty((nz, nr), dtype=torch.float64, device="cuda"),
            "F": [torch.empty((nz, nr), dtype=torch.float64, device="cuda") for _ in range(2)],
            "fs_host": np.zeros(len(Xd))}
     out = ax.project_step(mg, prm, [dev(a) for a in u], X, out=out)
-    ref = oaxi.project_step(nr, nz, h, 1.0, rho_out, 1.0, dt, u, Xd, rtol=1e-12)
+    ref = oaxi.project_step(nr, nz, h, 1.0, rho_out, 1.0, dt, u, Xd, rtol=1e-12, conventional=conventional)
     return X, out, ref
 
 
@@ -91,6 +92,25 @@ def test_static_drop_axis_parity_and_table(ib):
     assert np.all(u[0][:, 0] == 0.0)
 
 
+def test_static_drop_axis_conventional_parity(ib):
+    """The conventional spreading on the meridian plane against the oracle; its
+    pressure jump error at dx = 0.02 is of the size of the paper's conventional
+    column."""
+    g = GOLD["static_drop_axis_table"]
+    h = g["dx"][0]
+    nr, nz = 32, 64
+    n = int(round(2 * np.pi * 0.2 / (0.63 * h))) // 4 * 4
+    Xd = W.circle_markers(n, 0.2, centre=(nr * h, 0.5 * nz * h))
+    zero = [np.zeros((nz, nr)), np.zeros((nz, nr))]
+    X, out, ref = _run(ib, nr, nz, h, Xd, zero, 1e-3, conventional=True)
+    p, u, eu, scale = _compare(X, out, ref)
+    assert eu <= 1e-9 * max(scale, 1e-3)
+    err = abs(diag.pressure_jump(p, host(out["H"])) - 10.0)
+    print(f"conventional axisymmetric static drop, dx = {h}: |dP - 10| = {err:.3e} "
+          f"(paper: conventional {g['conventional'][0]})")
+    assert err < 5.0 * max(g["conventional"])
+
+
 def test_moving_axis_parity_and_divergence(ib):
     nr, nz, h = 32, 32, 1.0 / 32
     rng = np.random.default_rng(91)
@@ -117,7 +137,7 @@ def test_axis_errors(ib):
     mg = ib.Multigrid(2, (16, 32), 1 / 16)
     u = [torch.zeros((32, 16), dtype=torch.float64, device="cuda") for _ in range(2)]
     X = W.circle_markers(32, 0.25, centre=(1.0, 1.0))
-    for bad in (dict(spread_mode=ib.IB_SPREAD_DELTA), dict(warm_start=ib.WS_NN)):
+    for bad in (dict(spread_mode=7), dict(warm_start=ib.WS_NN)):
         prm = dict(rho_in=1.0, rho_out=0.01, dt=1e-3, **bad)
         with pytest.raises(ib.IbError):
             ax.project_step(mg, prm, u, X.copy())
