@@ -455,8 +455,10 @@ def bench_flow_osc(ib, torch):
     T2 = 2 * np.pi * np.sqrt(1.01 * 0.2 ** 3 / 6.0)
     Ta = 2 * np.pi * np.sqrt((3 * 1.0 + 2 * 0.01) * 0.2 ** 3 / 24.0)
     res = {}
-    for axis, T, paper in ((False, T2, {0.01: 0.2346, 0.005: 0.2328}), (True, Ta, {0.01: 0.2024})):
-        for h, n, dt, steps, nm in ((0.01, 256, 1e-4, 2600 if not axis else 2300, 256),
+    for axis, T, paper in ((False, T2, {0.02: 0.2411, 0.01: 0.2346, 0.005: 0.2328}),
+                           (True, Ta, {0.02: 0.2090, 0.01: 0.2024})):
+        for h, n, dt, steps, nm in ((0.02, 128, 2e-4, 1300 if not axis else 1150, 128),
+                                    (0.01, 256, 1e-4, 2600 if not axis else 2300, 256),
                                     (0.005, 512, 5e-5, 5200 if not axis else 4600, 512)):
             r = _osc_run(ib, torch, axis, n, h, dt, steps, nm)
             r["discrepancy_percent"] = round(100 * abs(r["period"] - T) / T, 2)
@@ -467,8 +469,10 @@ def bench_flow_osc(ib, torch):
             log(f"  {'axisymmetric' if axis else '2D'} h={h}: period {r['period']} ({r['discrepancy_percent']} %), "
                 f"{r['steps_per_s']} steps/s")
     # the conventional spreading's periods (Table osc's other column)
-    for axis, T, h, n, dt, steps, nm, paper in ((False, T2, 0.01, 256, 1e-4, 2600, 256, 0.2334),
+    for axis, T, h, n, dt, steps, nm, paper in ((False, T2, 0.02, 128, 2e-4, 1300, 128, 0.2348),
+                                                (False, T2, 0.01, 256, 1e-4, 2600, 256, 0.2334),
                                                 (False, T2, 0.005, 512, 5e-5, 5200, 512, 0.2326),
+                                                (True, Ta, 0.02, 128, 2e-4, 1150, 128, 0.2044),
                                                 (True, Ta, 0.01, 256, 1e-4, 2300, 256, 0.2039)):
         r = _osc_run(ib, torch, axis, n, h, dt, steps, nm, spread_mode=ib.IB_SPREAD_DELTA)
         r["discrepancy_percent"] = round(100 * abs(r["period"] - T) / T, 2)
@@ -479,7 +483,8 @@ def bench_flow_osc(ib, torch):
             f"({r['discrepancy_percent']} %), {r['steps_per_s']} steps/s")
     res["workload"] = ("Table osc drop: R=0.2 stretched by 1.03 (eq osc), rho 1/0.01, mu 0.01/1e-5, sigma=1; "
                        "2D: n^2 periodic box; axisymmetric: n x n meridian half plane (axis, outer wall at "
-                       "r = n h, periodic along the axis); n = 256 at h = 0.01 (dt 1e-4), 512 at h = 0.005 "
+                       "r = n h, periodic along the axis); n = 128 at h = 0.02 (dt 2e-4), 256 at h = 0.01 "
+                       "(dt 1e-4), 512 at h = 0.005 "
                        "(dt 5e-5); AB2 advection, Crank-Nicolson viscosity, irrotational force, FCG projection "
                        "warm-started from p_prev; markers 0.5 h apart")
     return res
