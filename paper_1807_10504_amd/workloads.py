@@ -63,6 +63,25 @@ def ellipse_markers(n: int, R: float, beta: float, centre=(0.5, 0.5)) -> np.ndar
     return np.stack([centre[0] + R * np.cos(th) * beta, centre[1] + R * np.sin(th) / beta], axis=1)
 
 
+def rotated_square_markers(h: float, angle_deg: float, L: float = 0.5, centre=(0.5, 0.5)):
+    """Markers 0.5 h apart on the sides of a square of side L rotated by angle_deg
+    about `centre`, counter-clockwise, with the inward unit normals of the sides
+    and the arc element of each marker: (X, nrm, ds)."""
+    th = np.deg2rad(angle_deg)
+    m = int(round(L / (0.5 * h)))
+    s = (np.arange(m) + 0.5) / m * L - L / 2
+    rot = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    pts, nv = [], []
+    for a, n in (((0, -1), (0, 1)), ((1, 0), (-1, 0)), ((0, 1), (0, -1)), ((-1, 0), (1, 0))):
+        c = np.array(a, dtype=float) * L / 2
+        t = np.array([-a[1], a[0]], dtype=float)
+        pts.append(c + s[:, None] * t)
+        nv.append(np.tile(n, (m, 1)).astype(float))
+    X = np.concatenate(pts) @ rot.T + np.asarray(centre, dtype=float)
+    nrm = np.concatenate(nv) @ rot.T
+    return X, nrm, np.full(len(X), L / m)
+
+
 def perturbed_circle(n: int = 126, g: float = 1e-3) -> np.ndarray:
     """Markers of the curvature-sensitivity illustration (eq interpol_cir).
 

@@ -97,3 +97,39 @@ def test_curl_versus_h(ib):
               f"L1 |I - H| {l1[-1]:.3e}")
         assert rows[-1][1] <= 1e-12 and rows[-1][2] > 1e-3
     assert 1.6 < l1[0] / l1[1] < 2.6 and 1.6 < l1[1] / l1[2] < 2.6, l1
+
+
+@pytest.mark.parametrize("angle", [0.0, 25.0])
+def test_inclined_interface_on_gpu(ib, angle):
+    """Section 3.1's straight interface at 256^2: the GPU's P of eq
+    poisson_delta against the oracle, and the remainder delta - grad P along the
+    middle of a side: a gradient to aliasing when axis-aligned, ~1.5 % at 25
+    degrees."""
+    from oracle import poisson
+    nn, L = 256, 0.5
+    h = 1.0 / nn
+    X, N, ds = W.rotated_square_markers(h, angle, L)
+    th = np.deg2rad(angle)
+    rot = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    jj, ii = np.indices((nn, nn))
+    P = np.stack([(ii + 0.5) * h - 0.5, (jj + 0.5) * h - 0.5], -1) @ rot
+    m = len(X)
+    ctx = ib.Context(2, (nn, nn), h, max_markers=m)
+    ind = ib.Indicator((nn, nn), h, max_markers=m)
+    t = [dev(a) for a in (X, np.ones(m), ds, N)]
+    I, st = ind.solve(ctx, t[0], t[3], t[2], rtol=1e-13)
+    surf = ib.Surface()
+    surf.n_markers, surf.X, surf.fs, surf.ds, surf.nrm = (m, t[0].data_ptr(), t[1].data_ptr(), t[2].data_ptr(),
+                                                          t[3].data_ptr())
+    F, _ = ctx.spread(surf, ib.IB_SPREAD_DELTA, want_H=False)
+    torch.cuda.synchronize()
+    Ig = I.cpu().numpy()
+    Fg = [f.cpu().numpy() for f in F[:2]]
+    Io = indicator.indicator(X, ds, N, (nn, nn), h)
+    assert np.abs(Ig - Io).max() <= 1e-9
+    g = poisson.gradient(Ig, h)
+    d = P[..., 1] + L / 2
+    mid = (np.abs(P[..., 0]) < L / 6) & (np.abs(d) < 4 * h)
+    ratio = max(np.abs(Fg[e] - g[e])[mid].max() for e in range(2)) / max(np.abs(Fg[e])[mid].max() for e in range(2))
+    print(f"{angle} degrees: |I - oracle| {np.abs(Ig - Io).max():.1e}, remainder / delta {ratio:.2e}")
+    assert (ratio <= 1e-4) if angle == 0.0 else (ratio >= 5e-3)
