@@ -23,7 +23,7 @@ CXX = os.environ.get("CXX", "g++")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-result", "-I" + os.path.join(ROOT, "include")]
-HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
+HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
               "-Wall", "-I" + os.path.join(ROOT, "include")]
 
 
@@ -53,7 +53,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
             if verbose and out.strip():
                 print(out)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    # the host units use OpenMP (GCC's runtime)
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lgomp"])
     os.replace(tmp, LIB)
     return LIB
 

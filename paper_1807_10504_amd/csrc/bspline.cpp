@@ -233,14 +233,20 @@ extern "C" int ib_relocate_bspline(int n, const double* X, const double* U, doub
         return ib::fail(IB_EGEOM, "ib_relocate_bspline: least-squares matrix not positive definite");
     int g = c.g;
     std::vector<double> ell(g), S(g + 1);
+    // the markers are independent once the curve is fitted: spans, arc lengths and
+    // the Newton inversions run in parallel, each with the arithmetic of the
+    // sequential loop (the span search from 0 ends where a search from the
+    // previous marker's span would)
+#pragma omp parallel for schedule(static) if (g >= 64)
     for (int s = 0; s < g; ++s) ell[s] = c.arc(s, 1.0);
     S[0] = 0.0;
     for (int s = 0; s < g; ++s) S[s + 1] = S[s] + ell[s];
     double Lc = S[g];
     double ds = Lc / n;
-    int s = 0;
+#pragma omp parallel for schedule(static) if (n >= 64)
     for (int k = 0; k < n; ++k) {
         double u;
+        int s = 0;
         locate(c, S, ell, (double)k * ds, &s, &u);
         c.point(s, u, &X_out[2 * k], &X_out[2 * k + 1]);
         double dx, dy;
@@ -252,9 +258,10 @@ extern "C" int ib_relocate_bspline(int n, const double* X, const double* U, doub
         }
     }
     std::vector<double> T(2 * (size_t)n);
-    s = 0;
+#pragma omp parallel for schedule(static) if (n >= 64)
     for (int k = 0; k < n; ++k) {
         double u;
+        int s = 0;
         locate(c, S, ell, ((double)k + 0.5) * ds, &s, &u);
         double dx, dy;
         c.deriv(s, u, &dx, &dy);
