@@ -137,8 +137,17 @@ bool fit(const std::vector<double>& X, int N, double h, Curve* out) {
     int g = (int)std::floor(L / (1.5 * h) + 0.5);
     if (g < 7) g = 7;
     double tau = L / g;
-    // normal matrix, dense storage, filled on the cyclic band
-    std::vector<double> M((size_t)g * g, 0.0), bx(g, 0.0), by(g, 0.0);
+    // normal matrix on the cyclic band: entry (i, j) with j = i + o (mod g),
+    // o in -3..3, at B[7 i + o + 3] (the basis of a point spans four cyclic
+    // neighbours, so no other entry is touched); accumulated in the order of a
+    // dense assembly
+    std::vector<double> B((size_t)7 * g, 0.0), bx(g, 0.0), by(g, 0.0);
+    auto boff = [&](int i, int j) {
+        int o = j - i;
+        if (o > 3) o -= g;
+        if (o < -3) o += g;
+        return 7 * i + o + 3;
+    };
     for (int k = 0; k < N; ++k) {
         double v = t[k] / tau;
         int s = span_of(v, g);
@@ -154,49 +163,71 @@ bool fit(const std::vector<double>& X, int N, double h, Curve* out) {
             by[ia] = by[ia] + b3[a] * yk;
             for (int b = 0; b < 4; ++b) {
                 int ib = idx[b];
-                M[(size_t)ia * g + ib] = M[(size_t)ia * g + ib] + b3[a] * b3[b];
+                B[boff(ia, ib)] = B[boff(ia, ib)] + b3[a] * b3[b];
             }
         }
     }
+    // value of the (dense) normal matrix at (i, j): zero off the cyclic band
+    auto Mv = [&](int i, int j) {
+        int o = j - i;
+        if (o > 3) o -= g;
+        if (o < -3) o += g;
+        return (o >= -3 && o <= 3) ? B[7 * i + o + 3] : 0.0;
+    };
     // envelope: first nonzero column of each row of the lower triangle
+    // (only the band columns i - 3 .. i and, near the end, the wrapped columns
+    // 0 .. i + 3 - g can be nonzero)
     std::vector<int> first(g);
     for (int i = 0; i < g; ++i) {
         int f = i;
-        for (int j = 0; j <= i; ++j)
-            if (M[(size_t)i * g + j] != 0.0) {
+        for (int j = 0; j <= i + 3 - g && j <= i; ++j)
+            if (Mv(i, j) != 0.0) {
                 f = j;
                 break;
             }
+        if (f == i)
+            for (int j = i - 3 < 0 ? 0 : i - 3; j <= i; ++j)
+                if (Mv(i, j) != 0.0) {
+                    f = j;
+                    break;
+                }
         first[i] = f;
     }
-    // Cholesky in row order over the envelope (fill-in stays inside it)
-    std::vector<double> Lm((size_t)g * g, 0.0);
+    // Cholesky in row order over the envelope (fill-in stays inside it); row i
+    // of the factor is stored from column first[i] on (profile storage)
+    std::vector<size_t> rs(g + 1, 0);
+    for (int i = 0; i < g; ++i) rs[i + 1] = rs[i] + (size_t)(i - first[i] + 1);
+    std::vector<double> Lp(rs[g], 0.0);
+    auto Lat = [&](int i, int k) -> double& { return Lp[rs[i] + (size_t)(k - first[i])]; };
     for (int i = 0; i < g; ++i) {
         for (int j = first[i]; j <= i; ++j) {
-            double s_ = M[(size_t)i * g + j];
+            double s_ = Mv(i, j);
             int k0 = first[i] > first[j] ? first[i] : first[j];
-            for (int k = k0; k < j; ++k) s_ = s_ - Lm[(size_t)i * g + k] * Lm[(size_t)j * g + k];
+            for (int k = k0; k < j; ++k) s_ = s_ - Lat(i, k) * Lat(j, k);
             if (i == j) {
                 if (!(s_ > 0.0)) return false;
-                Lm[(size_t)i * g + i] = std::sqrt(s_);
+                Lat(i, i) = std::sqrt(s_);
             } else {
-                Lm[(size_t)i * g + j] = s_ / Lm[(size_t)j * g + j];
+                Lat(i, j) = s_ / Lat(j, j);
             }
         }
     }
+    // rows whose envelope reaches back to column i, for the backward solve
+    std::vector<std::vector<int>> below(g);
+    for (int k = 0; k < g; ++k)
+        for (int i = first[k]; i < k; ++i) below[i].push_back(k);
     auto solve = [&](const std::vector<double>& rhs, std::vector<double>& c) {
         std::vector<double> z(g);
         for (int i = 0; i < g; ++i) {
             double s_ = rhs[i];
-            for (int k = first[i]; k < i; ++k) s_ = s_ - Lm[(size_t)i * g + k] * z[k];
-            z[i] = s_ / Lm[(size_t)i * g + i];
+            for (int k = first[i]; k < i; ++k) s_ = s_ - Lat(i, k) * z[k];
+            z[i] = s_ / Lat(i, i);
         }
         c.assign(g, 0.0);
         for (int i = g - 1; i >= 0; --i) {
             double s_ = z[i];
-            for (int k = i + 1; k < g; ++k)
-                if (first[k] <= i) s_ = s_ - Lm[(size_t)k * g + i] * c[k];
-            c[i] = s_ / Lm[(size_t)i * g + i];
+            for (int k : below[i]) s_ = s_ - Lat(k, i) * c[k];
+            c[i] = s_ / Lat(i, i);
         }
     };
     out->g = g;
