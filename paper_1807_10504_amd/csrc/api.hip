@@ -237,8 +237,12 @@ int relocate_2d(Ctx* c, const ib_params* prm, ib_state* stt, const double* U_dev
 // a6 + a8: rho and beta of level n+1 into the context, the hierarchy from them
 int coefficients_and_hierarchy(Ctx* c, mg_handle* m, const ib_params* prm, const double* H,
                                hipStream_t st) {
-    IB_TRY(launch_coefficients(c, H, prm->rho_in, prm->rho_out, c->beta, c->rho, st));
-    if (mg_takes_density(m)) IB_TRY(mg_update_density(m, c->rho, st));
+    // when the hierarchy takes the densities, nothing reads a stored beta: the
+    // right side and the update form it from rho as well
+    c->beta_from_rho = mg_takes_density(m) != 0;
+    IB_TRY(launch_coefficients(c, H, prm->rho_in, prm->rho_out, c->beta_from_rho ? nullptr : c->beta, c->rho,
+                               st));
+    if (c->beta_from_rho) IB_TRY(mg_update_density(m, c->rho, st));
     else IB_TRY(mg_update_coeffs(m, c->beta, st));
     return IB_OK;
 }
@@ -342,7 +346,8 @@ int ib::solve_and_update(Ctx* c, mg_handle* m, const ib_params* prm, ib_state* s
     // a7: right side
     const double* Fc[3] = {F[0], F[1], F[2]};
     const double* bc[3] = {c->beta[0], c->beta[1], c->beta[2]};
-    IB_TRY(launch_rhs(c, u_star, Fc, bc, prm->dt, c->b, st));
+    const double* rho_f = c->beta_from_rho ? c->rho : nullptr;
+    IB_TRY(launch_rhs(c, u_star, Fc, bc, prm->dt, c->b, st, rho_f));
     // a9, a10: warm start and solve
     long N = c->d.cells();
     if (out->b) IB_HIP(hipMemcpyAsync(out->b, c->b, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
@@ -379,6 +384,6 @@ int ib::solve_and_update(Ctx* c, mg_handle* m, const ib_params* prm, ib_state* s
     int rc = mg_solve(m, c->b, out->p, prm->rtol, prm->max_cycles, prm->fixed_cycles, &out->stats, st);
     if (rc != IB_OK && rc != IB_ENOTCONV) return rc;
     // a11: velocity update
-    IB_TRY(launch_update(c, u_star, Fc, bc, out->p, prm->dt, out->u, st));
+    IB_TRY(launch_update(c, u_star, Fc, bc, out->p, prm->dt, out->u, st, rho_f));
     return rc;
 }

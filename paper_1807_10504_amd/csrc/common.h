@@ -136,6 +136,7 @@ struct Ctx {
     double* F[3] = {nullptr, nullptr, nullptr};
     double* beta[3] = {nullptr, nullptr, nullptr};
     double* rho = nullptr;
+    bool beta_from_rho = false;   // the step's beta was not stored: form it from rho
     double* b = nullptr;
     // flags / scalars
     int* flags = nullptr;                // [0] geometry error, [1] band face without element
@@ -153,10 +154,13 @@ int launch_irrot_force(Ctx* c, const ib_surface* s, const double* H, double* con
 // beta (dim face arrays) and rho (cell densities) may each be null
 int launch_coefficients(Ctx* c, const double* H, double rin, double rout, double* const beta[3],
                         double* rho, hipStream_t st);
+// rhs / update: with rho (cell densities) set, the face coefficients are formed
+// from it where they are used, 2 / (rho_c + rho_{c-e}), bitwise the stored beta
+// (beta is then not read)
 int launch_rhs(Ctx* c, const double* const us[3], const double* const F[3], const double* const beta[3],
-               double dt, double* b, hipStream_t st);
+               double dt, double* b, hipStream_t st, const double* rho = nullptr);
 int launch_update(Ctx* c, const double* const us[3], const double* const F[3], const double* const beta[3],
-                  const double* p, double dt, double* const un[3], hipStream_t st);
+                  const double* p, double dt, double* const un[3], hipStream_t st, const double* rho = nullptr);
 int launch_diagnostics(Ctx* c, const double* p, const double* H, const double* const u[3],
                        const double* const F[3], ib_diag* out, hipStream_t st);
 int read_flags(Ctx* c, int* host_flags, hipStream_t st);

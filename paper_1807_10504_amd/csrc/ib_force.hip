@@ -367,13 +367,24 @@ int device_sum(const double* partials, int n, double* out, hipStream_t st) {
 
 // ---------------------------------------------------------------------------
 // a7 right side with partial sums for the mean
-template <int DIM>
+// face coefficient of the d-face of cell c: stored, or 2 / (rho_c + rho_{c-e_d})
+// (the stored value bit for bit)
+template <bool RHO>
+__device__ __forceinline__ double face_beta(const double* __restrict__ b, const double* __restrict__ rho, long c,
+                                           long cm) {
+    if constexpr (RHO)
+        return 2.0 / (rho[c] + rho[cm]);
+    else
+        return b[c];
+}
+
+template <int DIM, bool RHO>
 __global__ void k_rhs(const double* __restrict__ u0, const double* __restrict__ u1,
                       const double* __restrict__ u2, const double* __restrict__ F0,
                       const double* __restrict__ F1, const double* __restrict__ F2,
                       const double* __restrict__ b0, const double* __restrict__ b1,
-                      const double* __restrict__ b2, Dims d, double inv_dt, double* __restrict__ b,
-                      double* __restrict__ partial) {
+                      const double* __restrict__ b2, const double* __restrict__ rho, Dims d, double inv_dt,
+                      double* __restrict__ b, double* __restrict__ partial) {
     __shared__ double sh[kBlock];
     double acc = 0.0;
     long N = d.cells();
@@ -385,12 +396,22 @@ __global__ void k_rhs(const double* __restrict__ u0, const double* __restrict__ 
         int k = (int)(r / d.ny);
         long cx = i == d.nx - 1 ? c - (d.nx - 1) : c + 1;
         long cy = j == d.ny - 1 ? c - (long)(d.ny - 1) * d.nx : c + d.nx;
-        double s = ((u0[cx] * inv_dt + b0[cx] * F0[cx]) - (u0[c] * inv_dt + b0[c] * F0[c]));
-        s += ((u1[cy] * inv_dt + b1[cy] * F1[cy]) - (u1[c] * inv_dt + b1[c] * F1[c]));
+        long mx = 0, my = 0;
+        if constexpr (RHO) {
+            mx = i == 0 ? c + d.nx - 1 : c - 1;
+            my = j == 0 ? c + (long)(d.ny - 1) * d.nx : c - d.nx;
+        }
+        double s = ((u0[cx] * inv_dt + face_beta<RHO>(b0, rho, cx, c) * F0[cx]) -
+                    (u0[c] * inv_dt + face_beta<RHO>(b0, rho, c, mx) * F0[c]));
+        s += ((u1[cy] * inv_dt + face_beta<RHO>(b1, rho, cy, c) * F1[cy]) -
+              (u1[c] * inv_dt + face_beta<RHO>(b1, rho, c, my) * F1[c]));
         if (DIM == 3) {
             long pl = (long)d.nx * d.ny;
             long cz = k == d.nz - 1 ? c - (long)(d.nz - 1) * pl : c + pl;
-            s += ((u2[cz] * inv_dt + b2[cz] * F2[cz]) - (u2[c] * inv_dt + b2[c] * F2[c]));
+            long mz = 0;
+            if constexpr (RHO) mz = k == 0 ? c + (long)(d.nz - 1) * pl : c - pl;
+            s += ((u2[cz] * inv_dt + face_beta<RHO>(b2, rho, cz, c) * F2[cz]) -
+                  (u2[c] * inv_dt + face_beta<RHO>(b2, rho, c, mz) * F2[c]));
         }
         double v = s * inv_h;
         b[c] = v;
@@ -407,15 +428,27 @@ __global__ void k_sub_mean(double* __restrict__ x, long N, const double* __restr
 }
 
 int launch_rhs(Ctx* c, const double* const us[3], const double* const F[3],
-               const double* const beta[3], double dt, double* b, hipStream_t st) {
+               const double* const beta[3], double dt, double* b, hipStream_t st, const double* rho) {
     long N = c->d.cells();
     int blocks = (int)std::min<long>(kRedBlocks, (long)grid_for(N));
-    if (c->d.dim == 2)
-        hipLaunchKernelGGL(k_rhs<2>, dim3(blocks), dim3(kBlock), 0, st, us[0], us[1], us[1], F[0],
-                           F[1], F[1], beta[0], beta[1], beta[1], c->d, 1.0 / dt, b, c->red);
-    else
-        hipLaunchKernelGGL(k_rhs<3>, dim3(blocks), dim3(kBlock), 0, st, us[0], us[1], us[2], F[0],
-                           F[1], F[2], beta[0], beta[1], beta[2], c->d, 1.0 / dt, b, c->red);
+    const double* b0 = rho ? nullptr : beta[0];
+    const double* b1 = rho ? nullptr : beta[1];
+    const double* b2 = rho ? nullptr : beta[c->d.dim == 3 ? 2 : 1];
+    if (c->d.dim == 2) {
+        if (rho)
+            hipLaunchKernelGGL((k_rhs<2, true>), dim3(blocks), dim3(kBlock), 0, st, us[0], us[1], us[1], F[0],
+                               F[1], F[1], b0, b1, b1, rho, c->d, 1.0 / dt, b, c->red);
+        else
+            hipLaunchKernelGGL((k_rhs<2, false>), dim3(blocks), dim3(kBlock), 0, st, us[0], us[1], us[1], F[0],
+                               F[1], F[1], b0, b1, b1, rho, c->d, 1.0 / dt, b, c->red);
+    } else {
+        if (rho)
+            hipLaunchKernelGGL((k_rhs<3, true>), dim3(blocks), dim3(kBlock), 0, st, us[0], us[1], us[2], F[0],
+                               F[1], F[2], b0, b1, b2, rho, c->d, 1.0 / dt, b, c->red);
+        else
+            hipLaunchKernelGGL((k_rhs<3, false>), dim3(blocks), dim3(kBlock), 0, st, us[0], us[1], us[2], F[0],
+                               F[1], F[2], b0, b1, b2, rho, c->d, 1.0 / dt, b, c->red);
+    }
     IB_TRY(device_sum(c->red, blocks, c->red + kRedBlocks, st));
     hipLaunchKernelGGL(k_sub_mean, dim3(grid_for(N)), dim3(kBlock), 0, st, b, N, c->red + kRedBlocks);
     IB_HIP(hipGetLastError());
@@ -424,12 +457,13 @@ int launch_rhs(Ctx* c, const double* const us[3], const double* const F[3],
 
 // ---------------------------------------------------------------------------
 // a11 velocity update
-template <int DIM>
+template <int DIM, bool RHO>
 __global__ void k_update(const double* __restrict__ u0, const double* __restrict__ u1,
                          const double* __restrict__ u2, const double* __restrict__ F0,
                          const double* __restrict__ F1, const double* __restrict__ F2,
                          const double* __restrict__ b0, const double* __restrict__ b1,
-                         const double* __restrict__ b2, const double* __restrict__ p, Dims d,
+                         const double* __restrict__ b2, const double* __restrict__ rho,
+                         const double* __restrict__ p, Dims d,
                          double dt, double* __restrict__ o0, double* __restrict__ o1,
                          double* __restrict__ o2) {
     long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -443,14 +477,14 @@ __global__ void k_update(const double* __restrict__ u0, const double* __restrict
     long cx = i == 0 ? c + d.nx - 1 : c - 1;
     long cy = j == 0 ? c + (long)(d.ny - 1) * d.nx : c - d.nx;
     double gx = (pc - p[cx]) * inv_h, gy = (pc - p[cy]) * inv_h;
-    double v0 = u0[c] + dt * b0[c] * (F0[c] - gx);
-    double v1 = u1[c] + dt * b1[c] * (F1[c] - gy);
+    double v0 = u0[c] + dt * face_beta<RHO>(b0, rho, c, cx) * (F0[c] - gx);
+    double v1 = u1[c] + dt * face_beta<RHO>(b1, rho, c, cy) * (F1[c] - gy);
     double v2 = 0.0;
     if (DIM == 3) {
         long pl = (long)d.nx * d.ny;
         long cz = k == 0 ? c + (long)(d.nz - 1) * pl : c - pl;
         double gz = (pc - p[cz]) * inv_h;
-        v2 = u2[c] + dt * b2[c] * (F2[c] - gz);
+        v2 = u2[c] + dt * face_beta<RHO>(b2, rho, c, cz) * (F2[c] - gz);
     }
     o0[c] = v0;
     o1[c] = v1;
@@ -459,15 +493,26 @@ __global__ void k_update(const double* __restrict__ u0, const double* __restrict
 
 int launch_update(Ctx* c, const double* const us[3], const double* const F[3],
                   const double* const beta[3], const double* p, double dt, double* const un[3],
-                  hipStream_t st) {
-    if (c->d.dim == 2)
-        hipLaunchKernelGGL(k_update<2>, dim3(grid_for(c->d.cells())), dim3(kBlock), 0, st, us[0],
-                           us[1], us[1], F[0], F[1], F[1], beta[0], beta[1], beta[1], p, c->d, dt,
-                           un[0], un[1], un[1]);
-    else
-        hipLaunchKernelGGL(k_update<3>, dim3(grid_for(c->d.cells())), dim3(kBlock), 0, st, us[0],
-                           us[1], us[2], F[0], F[1], F[2], beta[0], beta[1], beta[2], p, c->d, dt,
-                           un[0], un[1], un[2]);
+                  hipStream_t st, const double* rho) {
+    const dim3 g(grid_for(c->d.cells())), blk(kBlock);
+    const double* b0 = rho ? nullptr : beta[0];
+    const double* b1 = rho ? nullptr : beta[1];
+    const double* b2 = rho ? nullptr : beta[c->d.dim == 3 ? 2 : 1];
+    if (c->d.dim == 2) {
+        if (rho)
+            hipLaunchKernelGGL((k_update<2, true>), g, blk, 0, st, us[0], us[1], us[1], F[0], F[1], F[1], b0, b1,
+                               b1, rho, p, c->d, dt, un[0], un[1], un[1]);
+        else
+            hipLaunchKernelGGL((k_update<2, false>), g, blk, 0, st, us[0], us[1], us[1], F[0], F[1], F[1], b0,
+                               b1, b1, rho, p, c->d, dt, un[0], un[1], un[1]);
+    } else {
+        if (rho)
+            hipLaunchKernelGGL((k_update<3, true>), g, blk, 0, st, us[0], us[1], us[2], F[0], F[1], F[2], b0, b1,
+                               b2, rho, p, c->d, dt, un[0], un[1], un[2]);
+        else
+            hipLaunchKernelGGL((k_update<3, false>), g, blk, 0, st, us[0], us[1], us[2], F[0], F[1], F[2], b0,
+                               b1, b2, rho, p, c->d, dt, un[0], un[1], un[2]);
+    }
     IB_HIP(hipGetLastError());
     return IB_OK;
 }
