@@ -142,27 +142,44 @@ __global__ void k_heaviside_2d(const double* __restrict__ off, int n, Jumps J, D
 
 // ---------------------------------------------------------------------------
 // 3D: one thread per (m, triangle)
+// vertices in vector registers: a variable index into a vector is a register
+// select, where one into an array would put the polygons in scratch memory.
+// Eight vertices suffice: each cut of a convex polygon by a half-plane adds at
+// most one vertex, and a piece is the triangle cut five times (four column
+// walls, then the plane z = c).
+typedef double Coord8 __attribute__((ext_vector_type(8)));
 struct Poly {
-    double x[10], y[10], z[10];
+    Coord8 x, y, z;
     int n;
 };
 
-// keep the part with coordinate(axis) >= v (ge) or <= v (!ge)
-__device__ __forceinline__ void clip(const Poly& in, Poly& out, int axis, double v, bool ge) {
+template <int AXIS>
+__device__ __forceinline__ double coord(const Poly& p, int r) {
+    if constexpr (AXIS == 0)
+        return p.x[r];
+    else if constexpr (AXIS == 1)
+        return p.y[r];
+    else
+        return p.z[r];
+}
+
+// keep the part with coordinate AXIS >= v (GE) or <= v (!GE)
+template <int AXIS, bool GE>
+__device__ __forceinline__ void clip(const Poly& in, Poly& out, double v) {
     out.n = 0;
     for (int r = 0; r < in.n; ++r) {
         int q = r + 1 == in.n ? 0 : r + 1;
-        double pr = axis == 0 ? in.x[r] : (axis == 1 ? in.y[r] : in.z[r]);
-        double pq = axis == 0 ? in.x[q] : (axis == 1 ? in.y[q] : in.z[q]);
-        double sr = ge ? pr - v : v - pr;
-        double sq = ge ? pq - v : v - pq;
-        if (sr >= 0.0 && out.n < 10) {
+        double pr = coord<AXIS>(in, r);
+        double pq = coord<AXIS>(in, q);
+        double sr = GE ? pr - v : v - pr;
+        double sq = GE ? pq - v : v - pq;
+        if (sr >= 0.0 && out.n < 8) {
             out.x[out.n] = in.x[r];
             out.y[out.n] = in.y[r];
             out.z[out.n] = in.z[r];
             ++out.n;
         }
-        if ((sr >= 0.0) != (sq >= 0.0) && out.n < 10) {
+        if ((sr >= 0.0) != (sq >= 0.0) && out.n < 8) {
             double tt = sr / (sr - sq);
             out.x[out.n] = in.x[r] + tt * (in.x[q] - in.x[r]);
             out.y[out.n] = in.y[r] + tt * (in.y[q] - in.y[r]);
@@ -173,8 +190,8 @@ __device__ __forceinline__ void clip(const Poly& in, Poly& out, int axis, double
 }
 
 // signed projected area and integral of max(z - c, 0) over the projection
-__device__ double g_poly(const Poly& p, double c, Poly& tmp) {
-    clip(p, tmp, 2, c, true);
+__device__ __forceinline__ double g_poly(const Poly& p, double c, Poly& tmp) {
+    clip<2, true>(p, tmp, c);
     if (tmp.n < 3) return 0.0;
     double s = 0.0;
     for (int r = 1; r + 1 < tmp.n; ++r) {
@@ -186,9 +203,10 @@ __device__ double g_poly(const Poly& p, double c, Poly& tmp) {
     return s;
 }
 
-__global__ void k_heaviside_3d(const double* __restrict__ off, int nv, const int32_t* __restrict__ T,
-                               int nt, Jumps J, Dims d, long long* __restrict__ A,
-                               long long* __restrict__ S, int* __restrict__ flags) {
+__global__ __launch_bounds__(256) void k_heaviside_3d(const double* __restrict__ off, int nv,
+                                                      const int32_t* __restrict__ T, int nt, Jumps J, Dims d,
+                                                      long long* __restrict__ A, long long* __restrict__ S,
+                                                      int* __restrict__ flags) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 4 * nt) return;
     int m = t / nt, e = t - m * nt;
@@ -216,13 +234,13 @@ __global__ void k_heaviside_3d(const double* __restrict__ off, int nv, const int
         if (j < 0 || j >= d.ny) continue;
         for (int i = i0; i <= i1; ++i) {
             if (i < 0 || i >= d.nx) continue;
-            clip(tri, a, 0, i * h, true);
+            clip<0, true>(tri, a, i * h);
             if (a.n < 3) continue;
-            clip(a, b, 0, (i + 1) * h, false);
+            clip<0, false>(a, b, (i + 1) * h);
             if (b.n < 3) continue;
-            clip(b, a, 1, j * h, true);
+            clip<1, true>(b, a, j * h);
             if (a.n < 3) continue;
-            clip(a, b, 1, (j + 1) * h, false);
+            clip<1, false>(a, b, (j + 1) * h);
             if (b.n < 3) continue;
             // b = the piece over column (i, j)
             double area = 0.0, zmn = b.z[0], zmx = b.z[0];
