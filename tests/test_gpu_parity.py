@@ -168,6 +168,24 @@ def test_heaviside_and_force_parity_3d(ib):
         assert np.max(np.abs(host(F[d]) - Fo[d])) <= 1e-11 * fmax
 
 
+def test_heaviside_and_force_parity_3d_coarse_mesh(ib):
+    """Level-1 icosphere on a 64^3 grid: triangles about 9h across, each
+    cutting many columns and planes (a coarse moving mesh on a fine grid)."""
+    V, T = W.sphere_mesh(1, 0.25, seed=3)
+    n = (64, 64, 64)
+    h = 1.0 / 64
+    ctx = ib.Context(3, n, h, max_markers=len(V), max_elems=len(T))
+    surf, keep, fs, ds, nrm = _surface3d(ib, V, T)
+    F, H = ctx.spread(surf, ib.IB_SPREAD_IRROT)
+    fo, Ao, no, _ = surface3d.surface_geometry(V, T, 1.0)
+    Ho = heaviside.heaviside_3d(V, T, n, h, nrm=no)
+    assert np.max(np.abs(host(H) - Ho)) <= 1e-13
+    Fo = force.irrotational_force(Ho, V, fo, h, T)
+    fmax = max(np.abs(f).max() for f in Fo)
+    for d in range(3):
+        assert np.max(np.abs(host(F[d]) - Fo[d])) <= 1e-11 * fmax
+
+
 def test_spread_is_deterministic(ib):
     V, T = W.sphere_mesh(3, 0.25, seed=3)
     n = (32, 32, 32)
