@@ -374,12 +374,14 @@ int ib::solve_and_update(Ctx* c, mg_handle* m, const ib_params* prm, ib_state* s
             IB_HIP(hipMemcpyAsync(out->p, stt->p_prev, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
         } else {
             IB_HIP(hipMemsetAsync(out->p, 0, sizeof(double) * N, st));
+            mg_hint_zero_guess(m);
         }
     } else if (prm->warm_start == WS_PREV && stt->p_prev) {
         if (stt->p_prev != out->p)
             IB_HIP(hipMemcpyAsync(out->p, stt->p_prev, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
     } else {
         IB_HIP(hipMemsetAsync(out->p, 0, sizeof(double) * N, st));
+        mg_hint_zero_guess(m);
     }
     int rc = mg_solve(m, c->b, out->p, prm->rtol, prm->max_cycles, prm->fixed_cycles, &out->stats, st);
     if (rc != IB_OK && rc != IB_ENOTCONV) return rc;

@@ -390,6 +390,7 @@ static int axi_solve_update(ib_axi* a, mg_handle* m, const ib_params* prm, ib_st
             IB_HIP(hipMemcpyAsync(out->p, stt->p_prev, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
     } else {
         IB_HIP(hipMemsetAsync(out->p, 0, sizeof(double) * N, st));
+        mg_hint_zero_guess(m);
     }
     int rc = mg_solve(m, Hc->b, out->p, prm->rtol, prm->max_cycles, prm->fixed_cycles, &out->stats, st);
     if (rc != IB_OK && rc != IB_ENOTCONV) return rc;

@@ -200,3 +200,7 @@ struct ib_ctx : ib::Ctx {};
 
 // 1 when the multigrid's finest level reads cell densities directly (mg.hip)
 int mg_takes_density(const mg_handle* m);
+// the caller has just zeroed the next solve's initial guess (on the solve's
+// stream): its first residual is b, so the first operator application is
+// skipped (the same residual and norms bit for bit); cleared by that solve
+void mg_hint_zero_guess(mg_handle* m);

@@ -62,6 +62,9 @@ struct Level {
 struct mg_handle {
     ib_grid g;
     mg_opts o;
+    // the next solve starts from a guess its caller has just zeroed
+    // (mg_hint_zero_guess): the first residual is then b itself
+    bool x_zero = false;
     std::vector<ib::Level> lv;
     // coarsest dense solve
     int nc = 0;                 // coarsest cells
@@ -1223,6 +1226,24 @@ __global__ void k_residual_vec(const double* __restrict__ x, const double* __res
     if (threadIdx.x == 0) partial_b2[blockIdx.x] = s;
 }
 
+// r = b for a zero guess (b - A 0 is b exactly), with the partial sums of
+// k_residual_vec in its order (r^2 and b^2 are then the same sum)
+__global__ void k_residual_zero(const double* __restrict__ b, int N, double* __restrict__ r,
+                                double* __restrict__ partial_r2, double* __restrict__ partial_b2) {
+    __shared__ double sh[kBlock];
+    double ab = 0.0;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < N; c += gridDim.x * blockDim.x) {
+        const double bv = b[c];
+        if (r) r[c] = bv;
+        ab += bv * bv;
+    }
+    const double s = block_reduce_sum(ab, sh);
+    if (threadIdx.x == 0) {
+        partial_r2[blockIdx.x] = s;
+        if (partial_b2) partial_b2[blockIdx.x] = s;
+    }
+}
+
 // q = A d with partial sums of d q
 template <int DIM, class K>
 __global__ void k_apply_dot(const double* __restrict__ dv, K co, Dims d, double inv_h2,
@@ -1746,7 +1767,8 @@ static void vcycle(mg_handle* m, int l, hipStream_t st, bool zero_start) {
 static int red_blocks(long N) { return (int)std::min<long>(kRed, (long)grid_for(N)); }
 
 // ||b - A p||^2 (and ||b||^2 when want_b) into m->host[0], m->host[1]; syncs
-static int fp64_norms(mg_handle* m, bool want_b, hipStream_t st) {
+// (zero: p is known to be zero, so r = b)
+static int fp64_norms(mg_handle* m, bool want_b, hipStream_t st, bool zero = false) {
     Level& L = m->lv[0];
     long N = L.d.cells();
     int nb = red_blocks(N);
@@ -1757,7 +1779,9 @@ static int fp64_norms(mg_handle* m, bool want_b, hipStream_t st) {
     ProfScope ps(IB_PROF_RESID, st, true);
     const CoefArrays<double> co{L.f64.beta[0], L.f64.beta[1],
                                 L.d.dim == 3 ? L.f64.beta[2] : L.f64.beta[1]};
-    if (L.rho)
+    if (zero)
+        hipLaunchKernelGGL(k_residual_zero, dim3(nb), dim3(kBlock), 0, st, L.f64.b, (int)N, nullptr, pr, pb);
+    else if (L.rho)
         hipLaunchKernelGGL((k_resid_norm<3, CoefRho>), dim3(nb), dim3(kBlock), 0, st, L.f64.p,
                            L.f64.b, CoefRho{L.rho}, L.d, inv_h2, pr, pb);
     else if (L.d.dim == 2)
@@ -2040,6 +2064,10 @@ static bool density_direct(const mg_handle* m) {
 
 int mg_takes_density(const mg_handle* m) { return m && density_direct(m) ? 1 : 0; }
 
+void mg_hint_zero_guess(mg_handle* m) {
+    if (m) m->x_zero = true;
+}
+
 extern "C" int mg_update_coeffs(mg_handle* m, const double* const beta[3], void* stream) {
     IB_CHECK(m && beta, IB_EINVAL, "mg_update_coeffs: null argument");
     for (int e = 0; e < m->g.dim; ++e)
@@ -2090,7 +2118,7 @@ extern "C" int mg_residual_norm(mg_handle* m, const double* b, const double* p, 
 // under MG_MIXED); same stopping logic and residual-check skipping as the
 // plain cycles, on the recursive residual
 static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, int max_it,
-                        int fixed, mg_stats* S, hipStream_t st) {
+                        int fixed, mg_stats* S, hipStream_t st, bool zero) {
     Level& L0 = m->lv[0];
     const long N = L0.d.cells();
     const int nb = red_blocks(N);
@@ -2104,7 +2132,9 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
     const dim3 g1(grid_for(N)), gr(nb), blk(kBlock);
     {
         ProfScope ps(IB_PROF_RESID, st, true);
-        if (L0.rho)
+        if (zero)
+            hipLaunchKernelGGL(k_residual_zero, gr, blk, 0, st, b, (int)N, m->kr, pa, pb);
+        else if (L0.rho)
             hipLaunchKernelGGL((k_residual_vec<3, CoefRho>), gr, blk, 0, st, x, b, CoefRho{L0.rho}, L0.d,
                                inv_h2, m->kr, pa, pb);
         else if (dim == 2)
@@ -2267,6 +2297,8 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
 extern "C" int mg_solve(mg_handle* m, const double* b, double* p, double rtol, int max_cycles,
                         int fixed_cycles, mg_stats* stats, void* stream) {
     IB_CHECK(m && b && p, IB_EINVAL, "mg_solve: null argument");
+    const bool zero = m->x_zero;   // a hint holds for this call only
+    m->x_zero = false;
     IB_CHECK(m->coeffs_ready, IB_EINVAL, "mg_solve: no coefficients yet (mg_update_coeffs or mg_update_density)");
     IB_CHECK(max_cycles >= 0 && fixed_cycles >= 0, IB_EINVAL, "mg_solve: cycle counts");
     hipStream_t st = (hipStream_t)stream;
@@ -2278,9 +2310,9 @@ extern "C" int mg_solve(mg_handle* m, const double* b, double* p, double rtol, i
     mg_stats loc;
     mg_stats* S = stats ? stats : &loc;
     S->cycles = 0;
-    if (m->o.krylov) return solve_krylov(m, b, p, rtol, max_cycles, fixed_cycles, S, st);
+    if (m->o.krylov) return solve_krylov(m, b, p, rtol, max_cycles, fixed_cycles, S, st, zero);
     if (mixed) IB_TRY(mixed_defect(m, true, st));
-    else IB_TRY(fp64_norms(m, true, st));
+    else IB_TRY(fp64_norms(m, true, st, zero));
     double bnorm = std::sqrt(m->host[1]);
     if (!(bnorm > 0.0)) {
         hipLaunchKernelGGL((k_fill<double>), dim3(grid_for(N)), dim3(kBlock), 0, st, p, N, 0.0);
