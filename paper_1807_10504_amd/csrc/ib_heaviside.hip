@@ -300,6 +300,37 @@ __global__ void k_heaviside_finish(Dims d, long long* __restrict__ A, long long*
     }
 }
 
+// 3D, the same with eight z-segments per column in parallel: a workgroup
+// holds 64 columns x 8 segments; each lane sums S over its segment, the
+// segment sums above it give the suffix it starts from (integer sums, so the
+// result is bit for bit the one-lane-per-column pass), then it runs down its
+// segment. Needs nz % 8 == 0 and nx ny % 64 == 0.
+constexpr int kFinCols = 64, kFinSegs = 8;
+__global__ __launch_bounds__(kFinCols* kFinSegs) void k_heaviside_finish_seg(Dims d, long long* __restrict__ A,
+                                                                            long long* __restrict__ S,
+                                                                            double* __restrict__ H) {
+    __shared__ long long segsum[kFinSegs][kFinCols];
+    const long plane = (long)d.nx * d.ny;
+    const int sl = d.nz / kFinSegs;
+    const long col = (long)blockIdx.x * kFinCols + threadIdx.x;
+    const int sg = threadIdx.y;
+    const int k0 = sg * sl;
+    long long acc = 0;
+    for (int k = k0; k < k0 + sl; ++k) acc += S[(long)k * plane + col];
+    segsum[sg][threadIdx.x] = acc;
+    __syncthreads();
+    long long run = 0;
+    for (int q = kFinSegs - 1; q > sg; --q) run += segsum[q][threadIdx.x];
+    for (int k = k0 + sl - 1; k >= k0; --k) {
+        const long idx = (long)k * plane + col;
+        run += S[idx];
+        long long v = A[idx] + run;
+        H[idx] = (double)v * kFixInv;
+        A[idx] = 0;
+        S[idx] = 0;
+    }
+}
+
 int launch_heaviside(Ctx* c, const ib_surface* s, double* H, hipStream_t st) {
     Jumps J = make_jumps();
     int n = s->n_markers;
@@ -319,8 +350,13 @@ int launch_heaviside(Ctx* c, const ib_surface* s, double* H, hipStream_t st) {
         int nt = s->n_elems;
         hipLaunchKernelGGL(k_heaviside_3d, dim3(grid_for(4L * nt)), dim3(kBlock), 0, st, c->offv,
                            n, s->elems, nt, J, c->d, c->accA, c->accS, c->flags);
-        hipLaunchKernelGGL(k_heaviside_finish, dim3(grid_for((long)c->d.nx * c->d.ny)),
-                           dim3(kBlock), 0, st, c->d, c->accA, c->accS, H);
+        const long ncol = (long)c->d.nx * c->d.ny;
+        if (c->d.nz % kFinSegs == 0 && ncol % kFinCols == 0)
+            hipLaunchKernelGGL(k_heaviside_finish_seg, dim3((unsigned)(ncol / kFinCols)), dim3(kFinCols, kFinSegs),
+                               0, st, c->d, c->accA, c->accS, H);
+        else
+            hipLaunchKernelGGL(k_heaviside_finish, dim3(grid_for(ncol)), dim3(kBlock), 0, st, c->d, c->accA,
+                               c->accS, H);
     }
     IB_HIP(hipGetLastError());
     return IB_OK;
