@@ -300,18 +300,18 @@ __global__ void k_heaviside_finish(Dims d, long long* __restrict__ A, long long*
     }
 }
 
-// 3D, the same with eight z-segments per column in parallel: a workgroup
+// the same with eight segments per column in parallel: a workgroup
 // holds 64 columns x 8 segments; each lane sums S over its segment, the
 // segment sums above it give the suffix it starts from (integer sums, so the
 // result is bit for bit the one-lane-per-column pass), then it runs down its
-// segment. Needs nz % 8 == 0 and nx ny % 64 == 0.
+// segment. Needs a column length divisible by 8 and a column count by 64.
 constexpr int kFinCols = 64, kFinSegs = 8;
 __global__ __launch_bounds__(kFinCols* kFinSegs) void k_heaviside_finish_seg(Dims d, long long* __restrict__ A,
                                                                             long long* __restrict__ S,
                                                                             double* __restrict__ H) {
     __shared__ long long segsum[kFinSegs][kFinCols];
-    const long plane = (long)d.nx * d.ny;
-    const int sl = d.nz / kFinSegs;
+    const long plane = d.dim == 2 ? (long)d.nx : (long)d.nx * d.ny;
+    const int sl = (d.dim == 2 ? d.ny : d.nz) / kFinSegs;
     const long col = (long)blockIdx.x * kFinCols + threadIdx.x;
     const int sg = threadIdx.y;
     const int k0 = sg * sl;
@@ -340,8 +340,12 @@ int launch_heaviside(Ctx* c, const ib_surface* s, double* H, hipStream_t st) {
                            c->d, c->offv, c->flags);
         hipLaunchKernelGGL(k_heaviside_2d, dim3(grid_for(4L * n)), dim3(kBlock), 0, st, c->offv,
                            n, J, c->d, c->accA, c->accS);
-        hipLaunchKernelGGL(k_heaviside_finish, dim3(grid_for(c->d.nx)), dim3(kBlock), 0, st, c->d,
-                           c->accA, c->accS, H);
+        if (c->d.ny % kFinSegs == 0 && c->d.nx % kFinCols == 0)
+            hipLaunchKernelGGL(k_heaviside_finish_seg, dim3((unsigned)(c->d.nx / kFinCols)),
+                               dim3(kFinCols, kFinSegs), 0, st, c->d, c->accA, c->accS, H);
+        else
+            hipLaunchKernelGGL(k_heaviside_finish, dim3(grid_for(c->d.nx)), dim3(kBlock), 0, st, c->d,
+                               c->accA, c->accS, H);
     } else {
         IB_CHECK(s->nrm && s->elems && s->n_elems > 0, IB_EINVAL,
                  "ib_spread: 3D surfaces need elems and nrm");
