@@ -35,8 +35,9 @@ METRIC = "projection steps/s @256³, ρ ratio 1000, resid≤1e-10; FP64 vs mixed
 HBM_PEAK_GBS = 8000.0
 # one red-black sweep reads p, b and three face coefficients and writes p:
 # 6 x 8 bytes per cell (float64); one launch updates one colour = half a sweep.
-# The sweep that forms the coefficients from cell densities reads p, b, rho
-# and writes p: 4 x 8 bytes per cell.
+# This per-cell figure is the algorithmic traffic of the sweep the roofline
+# reports. The sweep that forms the coefficients from cell densities moves
+# less: it reads p, b, rho and writes p, 4 x 8 bytes per cell (reported beside).
 SWEEP_BYTES_F64 = 48.0
 SWEEP_BYTES_F64_RHO = 32.0
 SWEEP_BYTES_F32 = 24.0
@@ -115,6 +116,48 @@ def run_variant(ib, torch, wl, geo, precision, steps, warmup, profile, warm=Fals
     mg.close()
     return dict(seconds=t1 - t0, steps=steps, cycles=cycles, rel_res=res, first=first, prof=prof,
                 dP=d["dP"], tke=d["tke"], accepted=accepted)
+
+
+def precision_errors(ib, torch, wl, geo):
+    """p of the first step's right side from each solver against a tightly
+    converged FP64 solve (relative L2): what the 1e-10 stopping test and the
+    float32 V-cycles leave in the answer."""
+    n, h = wl.n, wl.h
+    shape = tuple(reversed(n))
+    fs, ds, nrm = geo
+    keep = [torch.from_numpy(np.ascontiguousarray(a)).cuda()
+            for a in (wl.X, wl.tris.astype(np.int32), nrm, fs, ds)]
+    surf = ib.make_surface(keep[0], elems=keep[1], nrm=keep[2], fs=keep[3], ds=keep[4])
+    ctx = ib.Context(3, n, h, max_markers=len(wl.X), max_elems=len(wl.tris))
+    mg = ib.Multigrid(3, n, h, krylov=1)
+    u0 = [torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+    out = dict(b=torch.empty(shape, dtype=torch.float64, device="cuda"),
+               H=torch.empty(shape, dtype=torch.float64, device="cuda"))
+    prm = dict(rho_in=wl.rho_in, rho_out=wl.rho_out, sigma=wl.sigma, dt=wl.dt, rtol=1e-10,
+               warm_start=ib.WS_ZERO)
+    out = ctx.project_step(mg, prm, u0, surf=surf, out=out)
+    b = out["b"]
+    rho = ctx.density(out["H"], wl.rho_in, wl.rho_out)
+    mg.close()
+    res = {}
+    ref = None
+    for name, prec, kry, rtol in (("fp64_tight", ib.MG_FP64, 1, 1e-13), ("fp64_fcg", ib.MG_FP64, 1, 1e-10),
+                                  ("mixed_fcg", ib.MG_MIXED, 1, 1e-10), ("fp64_vcycle", ib.MG_FP64, 0, 1e-10),
+                                  ("mixed_vcycle", ib.MG_MIXED, 0, 1e-10)):
+        m = ib.Multigrid(3, n, h, precision=prec, krylov=kry)
+        m.update_density(rho)
+        p = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        st = m.solve(b, p, rtol=rtol, max_cycles=60, allow_notconv=True)
+        true = m.residual_norm(b, p)
+        m.close()
+        if ref is None:
+            ref = p
+            res[name] = dict(cycles=st["cycles"], true_rel_res=true)
+            continue
+        err = ((p - ref).norm() / ref.norm()).item()
+        res[name] = dict(cycles=st["cycles"], true_rel_res=true, p_rel_l2_vs_fp64_tight=err)
+    ctx.close()
+    return res
 
 
 def bench_3d_nn(ib, torch, wl, geo, steps, warmup, sps64, pairs=24, train_iters=60):
@@ -813,8 +856,10 @@ def cpu_baseline(wl, cycles_per_step, krylov):
               f"coefficients+rhs+update ({t['grid_ops']:.1f} s), Heaviside on {len(cols)} columns scaled to "
               f"{ncols:.0f} columns ({t['heaviside']:.0f} s), nearest-element face value on 40 faces scaled "
               f"to {nfaces:.0f} band faces ({t['face_force']:.0f} s)")
-    return dict(value=1.0 / per_step, unit="steps/s", cores=1, kind="oracle", sample=sample,
-                seconds_per_step=per_step, breakdown={k: round(v, 2) for k, v in t.items()})
+    # NumPy's element-wise work runs on one thread: the oracle used one core
+    return dict(value=1.0 / per_step, unit="steps/s", cores=1, host_cpu_count=os.cpu_count(),
+                kind="oracle", sample=sample, seconds_per_step=per_step,
+                breakdown={k: round(v, 2) for k, v in t.items()})
 
 
 def main():
@@ -902,6 +947,8 @@ def main():
                 variants[f"mixed_cold_{names[kry]}"]["kernels"] = {
                     k: dict(launches=v[0], avg_us=round(1e3 * v[1] / v[0], 2))
                     for k, v in rmx["prof"].items() if v[0]}
+    log("== error of each solver's p against a tightly converged FP64 solve")
+    variants["p_error_vs_fp64_tight"] = precision_errors(ib, torch, wl, geo)
     if not args.no_warm:
         log(f"== FP64 {names[head_k]}, warm start from the previous pressure")
         rw = run_variant(ib, torch, wl, geo, ib.MG_FP64, args.steps, args.warmup, profile=False,
@@ -910,9 +957,11 @@ def main():
     # roofline of the dominant kernel: the finest-level FP64 smoother, either
     # one full single-pass sweep or one colour pass (half a sweep)
     N = float(np.prod(wl.n))
+    min_bytes = None
     if r64["prof"]["sweep64_rho"][0]:
         nl, ms = r64["prof"]["sweep64_rho"]
-        bytes_per_launch = SWEEP_BYTES_F64_RHO * N
+        bytes_per_launch = SWEEP_BYTES_F64 * N
+        min_bytes = SWEEP_BYTES_F64_RHO * N
         kname = "k_rbgs_fused_rho<64,8,512>"
     elif r64["prof"]["sweep64"][0]:
         nl, ms = r64["prof"]["sweep64"]
@@ -930,8 +979,15 @@ def main():
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                 kernel=kname + " (finest-level single-pass red-black sweep)",
-                bytes_per_launch=bytes_per_launch, avg_launch_us=round(avg_s * 1e6, 2),
-                traffic_source=source)
+                bytes_per_launch=bytes_per_launch, bytes_per_cell=bytes_per_launch / N,
+                avg_launch_us=round(avg_s * 1e6, 2), traffic_source=source)
+    if min_bytes is not None:
+        # the same launch time against the bytes this kernel must move (p, b, rho
+        # read, p written) and against the bytes the counters saw
+        roof["frac_min_bytes"] = round(min_bytes / avg_s / 1e9 / HBM_PEAK_GBS, 4)
+        roof["min_bytes_per_cell"] = SWEEP_BYTES_F64_RHO
+    if traffic is not None:
+        roof["frac_counters"] = round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4)
     line = dict(metric=METRIC, value=round(sps64, 3), unit="steps/s", n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=round(1e3 * r64["seconds"] / r64["steps"], 3),
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",

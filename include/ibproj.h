@@ -164,7 +164,9 @@ int ib_update(ib_ctx* ctx, const double* const u_star[3], const double* const F[
  *   r = b - A p, z = V(r), d = z;  each iteration q = A d, alpha = (r,z)/(d,q),
  *   p += alpha d, r -= alpha q, z = V(r), beta = -alpha (q,z)/(r,z)_old,
  *   d = z + beta d;
- * the stopping test reads the recursively updated r. Four more float64 cell
+ * the recursively updated r is checked first; once it reaches rtol the true
+ * residual b - A p is formed and decides the stop (if it has not reached
+ * rtol, it replaces r and the iteration goes on). Four more float64 cell
  * arrays. Deterministic: every sum has a fixed order. */
 typedef struct {
     int precision;   /* MG_FP64 or MG_MIXED */
@@ -180,9 +182,12 @@ typedef struct {
     int cycles;              /* V-cycles (outer iterations in MG_MIXED; CG iterations, one
                                 V-cycle each, with krylov) performed */
     double rel_res0;         /* ||b - A p0|| / ||b|| of the initial guess */
-    double rel_res;          /* final ||b - A p|| / ||b|| (recursive residual with krylov) */
+    double rel_res;          /* final ||b - A p|| / ||b|| (with krylov: the true residual when
+                                the solve stopped on rtol, the recursive one after
+                                fixed_cycles) */
     double res_hist[128];    /* rel_res after each cycle (first 128); -1 for cycles run
                                 without a check (the solver skips norms it can predict) */
+    int true_checks;         /* krylov: true residuals formed to confirm the stop */
 } mg_stats;
 
 /* Allocates the hierarchy. Errors: IB_EINVAL (grid not n_coarsest * 2^L), IB_ENOMEM. */
@@ -226,8 +231,8 @@ typedef struct {
     int spread_mode;         /* IB_SPREAD_IRROT or IB_SPREAD_DELTA */
     int warm_start;          /* WS_ZERO, WS_PREV (p_prev as initial guess) or WS_NN
                                 (network guess from (b, 1/rho, p_prev), used when it is
-                                finite and its residual is at most 100 times that of
-                                p_prev (of 0 when p_prev is NULL); else p_prev or 0) */
+                                finite and its residual is below that of p_prev (of 0
+                                when p_prev is NULL); else p_prev or 0) */
 } ib_params;
 
 typedef struct {

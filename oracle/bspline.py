@@ -118,7 +118,9 @@ class ClosedCubic:
 
 
 def fit(X, h):
-    """Least-squares closed cubic through markers X (list of (x, y))."""
+    """Least-squares closed cubic through markers X (list of (x, y)),
+    parametrised by chord length from the first marker, on g = max(7,
+    round(L / 1.5h)) uniform spans of L / g."""
     N = len(X)
     t = [0.0] * (N + 1)
     for k in range(N):
@@ -132,13 +134,20 @@ def fit(X, h):
     if g < 7:
         g = 7
     tau = L / g
+    return lsq_closed_cubic(X, [t[k] / tau for k in range(N)], g), tau
+
+
+def lsq_closed_cubic(X, v, g):
+    """eq bspline_ls: the closed cubic on g unit spans minimising
+    sum_k |C(v_k) - X_k|^2 for the parameters v (in span units), through the
+    normal equations (B^T B) c = B^T X and a Cholesky factorisation."""
+    N = len(X)
     M = [[0.0] * g for _ in range(g)]
     bx = [0.0] * g
     by = [0.0] * g
     for k in range(N):
-        v = t[k] / tau
-        s = _span_of(v, g)
-        u = v - float(s)
+        s = _span_of(v[k], g)
+        u = v[k] - float(s)
         B3, _ = cox_de_boor(u)
         idx = [(s - 3 + r) % g for r in range(4)]
         xk, yk = X[k]
@@ -178,7 +187,7 @@ def fit(X, h):
             c[i] = s_ / Lm[i][i]
         return c
 
-    return ClosedCubic(solve(bx), solve(by)), tau
+    return ClosedCubic(solve(bx), solve(by))
 
 
 def _locate(curve, S, ell, sigma, s_start):

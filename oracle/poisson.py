@@ -30,7 +30,9 @@ conjugate gradients (the Polak-Ribiere form of the direction update, which
 tolerates a preconditioner that is not exactly symmetric) preconditioned by
 one V-cycle from a zero guess. The V-cycle here is not symmetric (mean
 restriction with linear prolongation; red-then-black in both smoothing
-passes), hence the flexible form. Stops on the recursively updated residual.
+passes), hence the flexible form. The recursively updated residual is
+checked first; the stop is decided on the true residual b - A x (the
+stopping test of the pressure solve is ||b - A p|| / ||b|| <= rtol).
 """
 import numpy as np
 
@@ -329,6 +331,13 @@ def fcg(apply, precond, b, x0=None, rtol=1e-10, max_iter=100, fixed_iters=None):
         r -= alpha * q
         it += 1
         hist.append(np.linalg.norm(r) / bn)
+        if fixed_iters is None and hist[-1] <= rtol:
+            # the stop is decided on the true residual; when it has not
+            # reached rtol it replaces the recursive one and CG goes on
+            r_true = b - apply(x)
+            hist[-1] = np.linalg.norm(r_true) / bn
+            if hist[-1] > rtol:
+                r = r_true
         if done():
             break
         z = precond(r)

@@ -11,9 +11,6 @@
 
 #include "common.h"
 
-// WS_NN: largest accepted ratio of the guess's residual to the fallback's
-constexpr double kGuessSlack = 100.0;
-
 namespace ib {
 
 static thread_local std::string g_last_error;
@@ -363,12 +360,10 @@ int ib::solve_and_update(Ctx* c, mg_handle* m, const ib_params* prm, ib_state* s
         } else {
             out->prev_rel_res = 1.0;  // zero guess
         }
-        // the guess is used unless it is not finite or its residual exceeds the
-        // fallback's by more than kGuessSlack: a learned guess carries
-        // high-frequency error that one cycle removes, so a larger residual
-        // can still start the solve closer (at ~7x per CG iteration, a factor
-        // 100 costs at most ~2.5 iterations); the solve decides the answer
-        if (std::isfinite(out->guess_rel_res) && out->guess_rel_res <= kGuessSlack * out->prev_rel_res) {
+        // multigrid judges the guess: it is used only when it is finite and
+        // its residual is below the fallback's (p_prev, or zero); the solve
+        // then decides the answer from either start
+        if (std::isfinite(out->guess_rel_res) && out->guess_rel_res < out->prev_rel_res) {
             out->guess_accepted = 1;
         } else if (stt->p_prev) {
             IB_HIP(hipMemcpyAsync(out->p, stt->p_prev, sizeof(double) * N, hipMemcpyDeviceToDevice, st));

@@ -1589,6 +1589,148 @@ __global__ __launch_bounds__(CG_NT) void k_resrestrict_rho(const double* __restr
     }
 }
 
+// Residual r = b - A x of a finest level given by densities, with its
+// partial norms, as a z-march with the tiling of k_cg_dir_apply_rho: x and rho
+// of each plane staged on the tile plus a one-cell ring (three-plane rings,
+// loaded two steps ahead), b read per cell. Each residual is formed operand
+// for operand as apply_row_rho does; it is stored in r as TR when r is not null
+// (float64: the CG residual; float32: the mixed-precision defect), and each
+// workgroup leaves the sums of r^2 and b^2 over its cells in a fixed order in
+// partial_r2[bid] and partial_b2[bid] (when not null). Reads x and rho 1.29
+// times (the ring) and b once.
+template <typename TR>
+__global__ __launch_bounds__(CG_NT) void k_residual_rho(const double* __restrict__ x,
+                                                        const double* __restrict__ bb,
+                                                        const double* __restrict__ rho, Dims dm,
+                                                        double inv_h2, int TZr, int ntx, int nty,
+                                                        int nzc, TR* __restrict__ r,
+                                                        double* __restrict__ partial_r2,
+                                                        double* __restrict__ partial_b2) {
+    __shared__ double PP[3][CG_RN];
+    __shared__ double RR[3][CG_RN];
+    __shared__ double red[2][CG_NT / 64];
+    const int nw = ntx * nty * nzc;
+    const int bid = blockIdx.x;
+    const int w = (nw % 8 == 0) ? (bid % 8) * (nw / 8) + bid / 8 : bid;
+    const int tx = w % ntx;
+    const int r0 = w / ntx;
+    const int ty = r0 % nty;
+    const int zc = r0 / nty;
+    const int i0 = tx * CG_TX - 1, j0 = ty * CG_TY - 1;
+    const int z0 = zc * TZr, z1 = z0 + TZr;
+    const long plane = (long)dm.nx * dm.ny;
+    const int t = threadIdx.x;
+    auto gofs = [&](int xx, int yy) {
+        return (long)wrap_near(j0 + yy, dm.ny) * dm.nx + wrap_near(i0 + xx, dm.nx);
+    };
+    long gp[CG_NL];
+    bool vp[CG_NL];
+#pragma unroll
+    for (int s = 0; s < CG_NL; ++s) {
+        int qq = t + s * CG_NT;
+        vp[s] = qq < CG_RN;
+        gp[s] = vp[s] ? gofs(qq % CG_RX, qq / CG_RX) : gofs(0, 0);
+    }
+    const int lx = t % CG_TX, ly = t / CG_TX;  // one cell of the tile per thread
+    const int c = (ly + 1) * CG_RX + lx + 1;
+    const long own = (long)(j0 + 1 + ly) * dm.nx + (i0 + 1 + lx);
+    auto pl = [&](int k) { return (long)wrap_near(k, dm.nz) * plane; };
+    struct Stage {
+        double p[CG_NL], r[CG_NL], b;
+    };
+    Stage SA, SB;
+    // a stage carries x and rho of plane k + 1 and b of plane k
+    auto fetch = [&](Stage& S, int k) {
+        const long bp = pl(k + 1);
+#pragma unroll
+        for (int s = 0; s < CG_NL; ++s) {
+            S.p[s] = x[bp + gp[s]];
+            S.r[s] = rho[bp + gp[s]];
+        }
+        S.b = bb[pl(k) + own];
+    };
+    auto commit = [&](const Stage& S, int k) {
+#pragma unroll
+        for (int s = 0; s < CG_NL; ++s)
+            if (s * CG_NT + CG_NT <= CG_RN || vp[s]) {
+                PP[(k + 4) % 3][t + s * CG_NT] = S.p[s];
+                RR[(k + 4) % 3][t + s * CG_NT] = S.r[s];
+            }
+    };
+    {
+        const long a = pl(z0 - 1), a0 = pl(z0);
+#pragma unroll
+        for (int s = 0; s < CG_NL; ++s)
+            if (vp[s]) {
+                PP[(z0 + 2) % 3][t + s * CG_NT] = x[a + gp[s]];
+                RR[(z0 + 2) % 3][t + s * CG_NT] = rho[a + gp[s]];
+                PP[z0 % 3][t + s * CG_NT] = x[a0 + gp[s]];
+                RR[z0 % 3][t + s * CG_NT] = rho[a0 + gp[s]];
+            }
+    }
+    fetch(SA, z0);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(SB, z0 + 1);
+    double ar = 0.0, ab = 0.0;
+    auto step = [&](Stage& S, int k) {
+        commit(S, k);
+        const double bv = S.b;
+        // past the range the loads re-read plane z1 - 1 (its stage is not committed)
+        fetch(S, k + 2 < z1 ? k + 2 : z1 - 1);
+        lds_barrier();
+        const double* Pc = PP[k % 3];
+        const double* Rc = RR[k % 3];
+        const double rc = Rc[c];
+        const double rxp = Rc[c + 1], rxm = Rc[c - 1], ryp = Rc[c + CG_RX], rym = Rc[c - CG_RX];
+        const double rzp = RR[(k + 1) % 3][c], rzm = RR[(k + 2) % 3][c];
+        double bxp, bxm, byp, bym, bzp, bzm;
+        if (rxp == rc && rxm == rc && ryp == rc && rym == rc && rzp == rc && rzm == rc) {
+            bxp = bxm = byp = bym = bzp = bzm = 1.0 / rc;
+        } else {
+            bxp = 2.0 / (rxp + rc);
+            bxm = 2.0 / (rc + rxm);
+            byp = 2.0 / (ryp + rc);
+            bym = 2.0 / (rc + rym);
+            bzp = 2.0 / (rzp + rc);
+            bzm = 2.0 / (rc + rzm);
+        }
+        const double pc = Pc[c];
+        double sv = bxp * (Pc[c + 1] - pc) - bxm * (pc - Pc[c - 1]);
+        sv += byp * (Pc[c + CG_RX] - pc) - bym * (pc - Pc[c - CG_RX]);
+        sv += bzp * (PP[(k + 1) % 3][c] - pc) - bzm * (pc - PP[(k + 2) % 3][c]);
+        const double rv = bv - sv * inv_h2;
+        if (r) r[pl(k) + own] = (TR)rv;
+        ar += rv * rv;
+        ab += bv * bv;
+        // the next commit overwrites plane k - 1's slot
+        lds_barrier();
+    };
+    // steps z0 .. z1 - 1 in pairs (stage A: even planes, B: odd); z0 and TZr are even
+    for (int k = z0; k < z1; k += 2) {
+        step(SA, k);
+        step(SB, k + 1);
+    }
+    // fixed-order workgroup sums
+    for (int off = 32; off > 0; off >>= 1) {
+        ar += __shfl_xor(ar, off);
+        ab += __shfl_xor(ab, off);
+    }
+    if ((t & 63) == 0) {
+        red[0][t >> 6] = ar;
+        red[1][t >> 6] = ab;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double sr = 0.0, sb = 0.0;
+        for (int i = 0; i < CG_NT / 64; ++i) {
+            sr += red[0][i];
+            sb += red[1][i];
+        }
+        partial_r2[bid] = sr;
+        if (partial_b2) partial_b2[bid] = sb;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // tile of the density sweep: 64 x 8 cells, 512 threads (2 workgroups per CU)
@@ -1766,6 +1908,25 @@ static void vcycle(mg_handle* m, int l, hipStream_t st, bool zero_start) {
 
 static int red_blocks(long N) { return (int)std::min<long>(kRed, (long)grid_for(N)); }
 
+// the finest level is given by densities on a grid the CG z-march tiles
+// (64 x 8 columns, an even z-range per workgroup)
+static bool tiled_rho(const Level& L) {
+    return L.rho != nullptr && L.d.dim == 3 && L.d.nx % CG_TX == 0 && L.d.ny % CG_TY == 0 && L.rtz > 0 &&
+           L.rtz % 2 == 0 && (long)(L.d.nx / CG_TX) * (L.d.ny / CG_TY) * (L.d.nz / L.rtz) <= kRed;
+}
+
+// r = b - A x on a tiled density level (r stored as TR when not null) with
+// per-workgroup partial sums of r^2 in pr and b^2 in pb (when not null);
+// returns the number of partials
+template <typename TR>
+static int launch_residual_rho(const Level& L, const double* x, const double* b, TR* r, double* pr,
+                               double* pb, hipStream_t st) {
+    const int tx = L.d.nx / CG_TX, ty = L.d.ny / CG_TY, tz = L.d.nz / L.rtz;
+    hipLaunchKernelGGL((k_residual_rho<TR>), dim3(tx * ty * tz), dim3(CG_NT), 0, st, x, b, L.rho, L.d,
+                       1.0 / (L.d.h * L.d.h), L.rtz, tx, ty, tz, r, pr, pb);
+    return tx * ty * tz;
+}
+
 // ||b - A p||^2 (and ||b||^2 when want_b) into m->host[0], m->host[1]; syncs
 // (zero: p is known to be zero, so r = b)
 static int fp64_norms(mg_handle* m, bool want_b, hipStream_t st, bool zero = false) {
@@ -1781,6 +1942,8 @@ static int fp64_norms(mg_handle* m, bool want_b, hipStream_t st, bool zero = fal
                                 L.d.dim == 3 ? L.f64.beta[2] : L.f64.beta[1]};
     if (zero)
         hipLaunchKernelGGL(k_residual_zero, dim3(nb), dim3(kBlock), 0, st, L.f64.b, (int)N, nullptr, pr, pb);
+    else if (tiled_rho(L))
+        nb = launch_residual_rho<double>(L, L.f64.p, L.f64.b, nullptr, pr, pb, st);
     else if (L.rho)
         hipLaunchKernelGGL((k_resid_norm<3, CoefRho>), dim3(nb), dim3(kBlock), 0, st, L.f64.p,
                            L.f64.b, CoefRho{L.rho}, L.d, inv_h2, pr, pb);
@@ -1810,7 +1973,9 @@ static int mixed_defect(mg_handle* m, bool want_b, hipStream_t st, bool sync = t
     ProfScope ps(IB_PROF_RESID, st, true);
     const CoefArrays<double> co{L.f64.beta[0], L.f64.beta[1],
                                 L.d.dim == 3 ? L.f64.beta[2] : L.f64.beta[1]};
-    if (L.rho)
+    if (tiled_rho(L))
+        nb = launch_residual_rho<float>(L, L.f64.p, L.f64.b, L.f32.b, pr, pb, st);
+    else if (L.rho)
         hipLaunchKernelGGL((k_defect_f32<3, CoefRho>), dim3(nb), dim3(kBlock), 0, st, L.f64.p,
                            L.f64.b, CoefRho{L.rho}, L.d, inv_h2, L.f32.b, pr, pb);
     else if (L.d.dim == 2)
@@ -2130,10 +2295,14 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
     const CoefArrays<double> co{L0.f64.beta[0], L0.f64.beta[1],
                                 dim == 3 ? L0.f64.beta[2] : L0.f64.beta[1]};
     const dim3 g1(grid_for(N)), gr(nb), blk(kBlock);
-    {
+    // r = b - A x into m->kr with the sums of r^2 and b^2 in the device scalars
+    auto residual = [&](bool from_zero) {
+        int parts = nb;
         ProfScope ps(IB_PROF_RESID, st, true);
-        if (zero)
+        if (from_zero)
             hipLaunchKernelGGL(k_residual_zero, gr, blk, 0, st, b, (int)N, m->kr, pa, pb);
+        else if (tiled_rho(L0))
+            parts = launch_residual_rho<double>(L0, x, b, m->kr, pa, pb, st);
         else if (L0.rho)
             hipLaunchKernelGGL((k_residual_vec<3, CoefRho>), gr, blk, 0, st, x, b, CoefRho{L0.rho}, L0.d,
                                inv_h2, m->kr, pa, pb);
@@ -2143,9 +2312,11 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
         else
             hipLaunchKernelGGL((k_residual_vec<3, CoefArrays<double>>), gr, blk, 0, st, x, b, co, L0.d,
                                inv_h2, m->kr, pa, pb);
-    }
-    IB_TRY(device_sum(pa, nb, m->ks + KS_RR, st));
-    IB_TRY(device_sum(pb, nb, m->ks + KS_BB, st));
+        int rc = device_sum(pa, parts, m->ks + KS_RR, st);
+        if (rc == IB_OK) rc = device_sum(pb, parts, m->ks + KS_BB, st);
+        return rc;
+    };
+    IB_TRY(residual(zero));
     IB_HIP(hipMemcpyAsync(m->host, m->ks + KS_RR, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     IB_HIP(hipStreamSynchronize(st));
     prof_drain();
@@ -2275,6 +2446,17 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
         IB_HIP(hipStreamSynchronize(st));
         prof_drain();
         rel = std::sqrt(m->host[0]) / bnorm;
+        if (fixed == 0 && rel <= rtol) {
+            // the recursive residual drifts from b - A x by rounding: the stop
+            // is decided on the true residual, which replaces r (and the
+            // recursion goes on from it) when it has not reached rtol yet
+            IB_TRY(residual(false));
+            IB_HIP(hipMemcpyAsync(m->host, m->ks + KS_RR, sizeof(double), hipMemcpyDeviceToHost, st));
+            IB_HIP(hipStreamSynchronize(st));
+            prof_drain();
+            rel = std::sqrt(m->host[0]) / bnorm;
+            ++S->true_checks;
+        }
         if (it <= 128) S->res_hist[it - 1] = rel;
         S->rel_res = rel;
         ++checks;
@@ -2310,6 +2492,7 @@ extern "C" int mg_solve(mg_handle* m, const double* b, double* p, double rtol, i
     mg_stats loc;
     mg_stats* S = stats ? stats : &loc;
     S->cycles = 0;
+    S->true_checks = 0;
     if (m->o.krylov) return solve_krylov(m, b, p, rtol, max_cycles, fixed_cycles, S, st, zero);
     if (mixed) IB_TRY(mixed_defect(m, true, st));
     else IB_TRY(fp64_norms(m, true, st, zero));

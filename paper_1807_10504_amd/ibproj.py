@@ -61,11 +61,11 @@ class MgOpts(C.Structure):
 
 class MgStats(C.Structure):
     _fields_ = [("cycles", C.c_int), ("rel_res0", C.c_double), ("rel_res", C.c_double),
-                ("res_hist", C.c_double * 128)]
+                ("res_hist", C.c_double * 128), ("true_checks", C.c_int)]
 
     def as_dict(self):
         return dict(cycles=self.cycles, rel_res0=self.rel_res0, rel_res=self.rel_res,
-                    hist=list(self.res_hist[: min(self.cycles, 128)]))
+                    hist=list(self.res_hist[: min(self.cycles, 128)]), true_checks=self.true_checks)
 
 
 class Params(C.Structure):

@@ -1,6 +1,8 @@
 """Parity at the benchmark's full size: 256^3 periodic box, sphere R = 0.25 from
 a level-6 icosphere (40,962 markers, 81,920 triangles), density ratio 1000,
-one cold projection step in the same launch configuration bench.py times.
+one cold projection step in the launch configuration bench.py times (the
+finest level read from the densities, flexible CG preconditioned by one V(2,2)
+cycle, stopped on the true residual <= 1e-10).
 
 The oracle cannot run the whole step at this size in seconds, so it is checked
 on sampled outputs it can compute one by one, and through properties that hold
@@ -10,7 +12,9 @@ at any size:
   * the right side at sampled cells (before its mean, which is ~1e-16 of it);
   * interpolation of a seeded random velocity at sampled markers;
   * p: ||b - A p|| / ||b|| <= 1e-10 with an independent NumPy operator on the
-    library's coefficients, and zero mean;
+    library's coefficients, and zero mean; and, at an equal number of
+    flexible-CG iterations from zero (the same solver on the step's own rho and
+    b), p within 1e-11 relative L2 of the oracle's mg_pcg;
   * the updated velocity at sampled faces from the oracle formula;
   * the Laplace jump close to 2 sigma / R.
 """
@@ -22,6 +26,9 @@ from paper_1807_10504_amd import workloads as W
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
+
+
+FIXED_ITERS = 2
 
 
 @pytest.fixture(scope="module")
@@ -38,7 +45,7 @@ def run():
                            fs=torch.from_numpy(fs).cuda(), ds=torch.from_numpy(ds).cuda())
     keep = [Vd, Td]
     ctx = ib.Context(3, n, h, max_markers=len(wl.X), max_elems=len(wl.tris))
-    mg = ib.Multigrid(3, n, h)
+    mg = ib.Multigrid(3, n, h, krylov=1)
     u0 = [torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(3)]
     out = dict(H=torch.empty(shape, dtype=torch.float64, device="cuda"),
                F=[torch.empty(shape, dtype=torch.float64, device="cuda") for _ in range(3)],
@@ -49,7 +56,14 @@ def run():
     beta = ctx.coefficients(out["H"], wl.rho_in, wl.rho_out)
     d = ctx.diagnostics(p=out["p"], H=out["H"])
     torch.cuda.synchronize()
+    # the headline solver again, for a fixed number of iterations from zero
+    rho = ctx.density(out["H"], wl.rho_in, wl.rho_out)
+    mg.update_density(rho)
+    p_fix = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    st_fix = mg.solve(out["b"], p_fix, fixed_cycles=FIXED_ITERS)
+    torch.cuda.synchronize()
     res = dict(wl=wl, ib=ib, ctx=ctx, surf=surf, keep=keep, stats=out["stats"], diag=d,
+               p_fix=p_fix.cpu().numpy(), st_fix=st_fix,
                H=out["H"].cpu().numpy(), F=[f.cpu().numpy() for f in out["F"]],
                b=out["b"].cpu().numpy(), p=out["p"].cpu().numpy(),
                u=[c.cpu().numpy() for c in out["u"]], beta=[x.cpu().numpy() for x in beta])
@@ -157,6 +171,21 @@ def test_pressure_residual_property(run):
     r = b - poisson.apply_A(p, beta, wl.h)
     assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
     assert abs(p.mean()) <= 1e-12 * np.abs(p).max()
+
+
+def test_pressure_parity_fixed_iterations(run):
+    """The 256^3 solver (tiled density kernels, CG update fused with the
+    product, inner products folded into the last sweep) against the oracle's
+    flexible CG at an equal iteration count, on the GPU's rho and b."""
+    wl = run["wl"]
+    beta = poisson.face_beta(poisson.density(run["H"], wl.rho_in, wl.rho_out))
+    po, it, hist = poisson.mg_pcg(run["b"], beta, wl.h, fixed_iters=FIXED_ITERS)
+    err = np.linalg.norm(run["p_fix"] - po) / np.linalg.norm(po)
+    print(f"256^3 FCG x{FIXED_ITERS}: p rel L2 vs oracle {err:.2e}; "
+          f"rel res {run['st_fix']['rel_res']:.3e} vs {hist[-1]:.3e}")
+    assert run["st_fix"]["cycles"] == FIXED_ITERS
+    assert err <= 1e-11
+    assert abs(run["st_fix"]["rel_res"] - hist[-1]) <= 1e-6 * hist[-1]
 
 
 def test_velocity_update_sampled_faces(run):

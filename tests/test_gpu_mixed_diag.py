@@ -1,0 +1,113 @@
+"""Mixed-precision multigrid and the diagnostics against the oracle.
+
+Mixed precision (float32 V-cycle inside float64 defect correction, or as the
+flexible-CG preconditioner on fl32(r)), the GPU's MG_MIXED path against
+``oracle.poisson.mg_solve_mixed`` / ``mg_pcg(mixed=True)`` at an equal number
+of cycles, on 64^2, 32^3 and the 128^3 density path (the finest level read
+from rho by the tiled kernels). The float32 cycle is evaluated in a different
+order (and with fused multiply-adds) on the two sides, so each correction
+differs by a few float32 roundings (u32 = 6e-8) of its own size; later float64
+defect-correction cycles contract earlier differences like any other error.
+Bound: 2e-6 relative L2 on p after the fixed cycles (about 30 u32), far below
+what a wrong operand, sign or transfer weight in the float32 cycle produces.
+
+Diagnostics (a12: eq sd_pres_diff, eq tke, the grid force sum, the index-form
+curl of Section 3.2, max |F|) from ib_diagnostics against ``oracle.diag`` on
+the same seeded fields: 1e-12 relative (sums in another order).
+"""
+import numpy as np
+import pytest
+
+from oracle import diag, poisson
+from paper_1807_10504_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def ib():
+    from paper_1807_10504_amd import ibproj
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    ibproj.load()
+    return ibproj
+
+
+def _drop_H(shape, seed, radius=0.3):
+    """A drop with a 3-cell ramp and seeded noise in the ramp; exactly 0 / 1 elsewhere."""
+    g = np.indices(shape)
+    r = np.sqrt(sum(((g[a] + 0.5) / shape[a] - 0.5) ** 2 for a in range(len(shape))))
+    h = 1.0 / max(shape)
+    H = np.clip((radius - r) / (3 * h) + 0.5, 0.0, 1.0)
+    ramp = (H > 0) & (H < 1)
+    H[ramp] += 0.01 * np.random.default_rng(seed).standard_normal(ramp.sum())
+    return np.clip(H, 0.0, 1.0)
+
+
+MIXED_TOL = 2e-6
+
+
+@pytest.mark.parametrize("shape,krylov", [((64, 64), 0), ((32, 32, 32), 0), ((128, 128, 128), 0),
+                                          ((64, 64), 1), ((32, 32, 32), 1), ((128, 128, 128), 1)])
+def test_mixed_fixed_cycles_parity(ib, shape, krylov):
+    dim = len(shape)
+    n = tuple(reversed(shape))
+    h = 1.0 / shape[-1]
+    H = _drop_H(shape, 81)
+    b = W.random_cells(n, dim, 1.0, seed=82)
+    b -= b.mean()
+    ctx = ib.Context(dim, n, h, max_markers=16)
+    mg = ib.Multigrid(dim, n, h, precision=ib.MG_MIXED, krylov=krylov)
+    mg.update_density(ctx.density(dev(H), 1.0, 1e-3))
+    p = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    k = 3
+    st = mg.solve(dev(b), p, fixed_cycles=k)
+    beta = poisson.face_beta(poisson.density(H, 1.0, 1e-3))
+    if krylov:
+        po, _, hist = poisson.mg_pcg(b, beta, h, fixed_iters=k, mixed=True)
+    else:
+        po, _, hist = poisson.mg_solve_mixed(b, beta, h, fixed_cycles=k)
+    err = rel_l2(host(p), po)
+    print(f"mixed {shape} krylov={krylov}: {k} cycles, p rel L2 vs oracle {err:.2e}, "
+          f"rel res {st['rel_res']:.3e} vs {hist[-1]:.3e}")
+    assert st["cycles"] == k
+    assert err <= MIXED_TOL
+    assert abs(st["rel_res"] - hist[-1]) <= 1e-3 * hist[-1]
+
+
+@pytest.mark.parametrize("shape", [(48, 64), (16, 24, 32)])
+def test_diagnostics_parity(ib, shape):
+    dim = len(shape)
+    n = tuple(reversed(shape))
+    h = 1.0 / n[0]
+    rng = np.random.default_rng(83)
+    H = _drop_H(shape, 84, radius=0.25)
+    p = rng.standard_normal(shape) + 8.0 * H
+    u = [rng.standard_normal(shape) for _ in range(dim)]
+    F = [rng.standard_normal(shape) * (rng.random(shape) < 0.2) for _ in range(dim)]
+    ctx = ib.Context(dim, n, h, max_markers=16)
+    d = ctx.diagnostics(p=dev(p), H=dev(H), u=[dev(c) for c in u], F=[dev(c) for c in F])
+    dp = diag.pressure_jump(p, H)
+    assert abs(d["dP"] - dp) <= 1e-12 * abs(dp)
+    t = diag.tke(u, h)
+    assert abs(d["tke"] - t) <= 1e-12 * t
+    fs = diag.grid_force_sum(F, h)
+    scale = sum(np.sum(np.abs(F[e])) for e in range(dim)) * h ** dim
+    for e in range(dim):
+        assert abs(d["force_sum"][e] - fs[e]) <= 1e-12 * scale
+    c = diag.curl_max(F)
+    assert abs(d["curl_max"] - c) <= 1e-12 * c
+    assert d["f_max"] == max(np.abs(F[e]).max() for e in range(dim))
