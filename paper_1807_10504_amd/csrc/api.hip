@@ -1,8 +1,6 @@
 // C ABI entry points: context, transfer/spread/coefficients/rhs/update calls,
 // diagnostics, and the projection step that chains them (Section 2.1
 // fractional step with the surface tension in the projection, eq ns2_new).
-#include <hipcub/hipcub.hpp>
-
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -51,8 +49,7 @@ namespace ib {
 
 static int free_ctx(ib_ctx* c) {
     if (!c) return IB_OK;
-    void* ptrs[] = {c->bin_key, c->bin_idx, c->bin_key_sorted, c->bin_order, c->tile_start,
-                    c->sort_tmp, c->accA, c->accS, c->best, c->offv, c->mX, c->mfs, c->mds,
+    void* ptrs[] = {c->bin_key, c->bin_order, c->tile_start, c->bin_count, c->scan_part, c->accA, c->accS, c->best, c->offv, c->mX, c->mfs, c->mds,
                     c->mnrm, c->H, c->F[0], c->F[1], c->F[2], c->beta[0], c->beta[1],
                     c->beta[2], c->rho, c->b, c->flags, c->red};
     for (void* p : ptrs)
@@ -90,6 +87,10 @@ extern "C" int ib_create(const ib_grid* g, int max_markers, int max_elems, ib_ct
     c->tny = g->n[1] / kTile;
     c->tnz = g->dim == 3 ? g->n[2] / kTile : 1;
     c->n_tiles = c->tnx * c->tny * c->tnz;
+    if ((long)c->n_tiles > kMaxTiles) {
+        delete c;
+        return fail(IB_EINVAL, "ib_create: more than 2^24 - 1 tiles of 4^dim cells");
+    }
     int dim = g->dim;
     long M = max_markers;
     bool ok = true;
@@ -97,17 +98,10 @@ extern "C" int ib_create(const ib_grid* g, int max_markers, int max_elems, ib_ct
         if (ok && hipMalloc(p, bytes) != hipSuccess) ok = false;
     };
     alloc((void**)&c->bin_key, M * sizeof(int32_t));
-    alloc((void**)&c->bin_idx, M * sizeof(int32_t));
-    alloc((void**)&c->bin_key_sorted, M * sizeof(int32_t));
     alloc((void**)&c->bin_order, M * sizeof(int32_t));
     alloc((void**)&c->tile_start, (c->n_tiles + 1) * sizeof(int32_t));
-    if (ok) {
-        size_t bytes = 0;
-        hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, c->bin_key, c->bin_key_sorted,
-                                           c->bin_idx, c->bin_order, (int)M, 0, 31);
-        c->sort_tmp_bytes = std::max<size_t>(bytes, 16);
-        alloc(&c->sort_tmp, c->sort_tmp_bytes);
-    }
+    alloc((void**)&c->bin_count, (c->n_tiles + 1) * sizeof(int32_t));
+    alloc((void**)&c->scan_part, (kScanTile + 1) * sizeof(int32_t));
     alloc((void**)&c->accA, cells * sizeof(long long));
     alloc((void**)&c->accS, cells * sizeof(long long));
     alloc((void**)&c->best, (size_t)dim * cells * sizeof(unsigned long long));

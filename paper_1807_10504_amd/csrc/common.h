@@ -103,6 +103,10 @@ constexpr double kFixInv = 1.0 / 72057594037927936.0;
 
 // tile edge (cells) of the marker bins
 constexpr int kTile = 4;
+// exclusive scan of the tile counts: blocks of 1024 threads x 4 items, the
+// block totals scanned by one more block
+constexpr int kScanThreads = 1024, kScanItems = 4, kScanTile = kScanThreads * kScanItems;
+constexpr long kMaxTiles = (long)kScanTile * kScanTile - 1;
 
 // ---------------------------------------------------------------------------
 // context
@@ -113,12 +117,10 @@ struct Ctx {
     // binning
     int n_tiles, tnx, tny, tnz;
     int32_t* bin_key = nullptr;      // per marker tile key
-    int32_t* bin_idx = nullptr;      // 0..n-1
-    int32_t* bin_key_sorted = nullptr;
-    int32_t* bin_order = nullptr;    // sorted marker indices
+    int32_t* bin_order = nullptr;    // marker indices in tile order, ascending within a tile
     int32_t* tile_start = nullptr;   // n_tiles + 1
-    void* sort_tmp = nullptr;
-    size_t sort_tmp_bytes = 0;
+    int32_t* bin_count = nullptr;    // n_tiles + 1: per-tile counts, then scatter cursors
+    int32_t* scan_part = nullptr;    // kScanTile + 1: block totals of the two-level scan
     // Heaviside accumulators (int64, zeroed after every use)
     long long* accA = nullptr;
     long long* accS = nullptr;

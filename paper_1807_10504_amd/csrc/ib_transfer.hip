@@ -6,12 +6,11 @@
 // gathers its 4^dim faces.
 //
 // Conventional spreading: eq delta_vec, F(x_f) = sum_s F_s delta_h(x_f - X_s).
-// Markers are counting-sorted into tiles of 4^dim cells (stable radix sort on
-// the tile key); every face gathers the markers of the <= 2^dim tiles that
-// cover its kernel support, in tile order then marker order, so the sum has
-// a fixed order and the result is bitwise reproducible (no float atomics).
-#include <hipcub/hipcub.hpp>
-
+// Markers are counting-sorted into tiles of 4^dim cells (histogram of the
+// tile keys, exclusive scan, scatter, marker order restored within each
+// tile); every face gathers the markers of the <= 2^dim tiles that cover its
+// kernel support, in tile order then marker order, so the sum has a fixed
+// order and the result is bitwise reproducible (no float atomics).
 #include "common.h"
 
 namespace ib {
@@ -23,7 +22,7 @@ __device__ __forceinline__ double phi_dev(double q) {
 // ---------------------------------------------------------------------------
 // a1: binning
 __global__ void k_tile_keys(const double* __restrict__ X, int n, Dims d, int tnx, int tny,
-                            int32_t* __restrict__ key, int32_t* __restrict__ idx) {
+                            int32_t* __restrict__ key) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     int dim = d.dim;
@@ -34,42 +33,129 @@ __global__ void k_tile_keys(const double* __restrict__ X, int n, Dims d, int tnx
         c[e] = wrap((int)floor(v), nn[e]) / kTile;
     }
     key[s] = (c[2] * tny + c[1]) * tnx + c[0];
-    idx[s] = s;
 }
 
-__global__ void k_tile_start(const int32_t* __restrict__ sorted_key, int n, int n_tiles,
-                             int32_t* __restrict__ start) {
+__global__ void k_fill_i32(int32_t* __restrict__ x, int n, int32_t v) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t > n_tiles) return;
-    // first position with key >= t
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (sorted_key[mid] < t) lo = mid + 1;
-        else hi = mid;
+    if (t < n) x[t] = v;
+}
+
+// histogram of the tile keys (integer atomics: the counts do not depend on
+// the order the adds land in)
+__global__ void k_tile_count(const int32_t* __restrict__ key, int n, int32_t* __restrict__ count) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) atomicAdd(&count[key[s]], 1);
+}
+
+// Exclusive scan of in[0, n) into out in blocks of kScanTile items (each
+// thread four consecutive items; lane prefixes by shuffles, wave totals
+// through LDS); the block's total goes to part[blockIdx.x].
+__global__ __launch_bounds__(kScanThreads) void k_scan_block(const int32_t* __restrict__ in, int n,
+                                                             int32_t* __restrict__ out,
+                                                             int32_t* __restrict__ part) {
+    __shared__ int32_t wsum[kScanThreads / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const long base = (long)blockIdx.x * kScanTile + (long)t * kScanItems;
+    int32_t v[kScanItems];
+    int32_t own = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        v[q] = base + q < n ? in[base + q] : 0;
+        own += v[q];
     }
-    start[t] = lo;
+    // inclusive scan of the thread totals across the wave
+    int32_t inc = own;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(inc, off);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    if (t == 0) {
+        int32_t acc = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) {
+            const int32_t x = wsum[w];
+            wsum[w] = acc;
+            acc += x;
+        }
+        part[blockIdx.x] = acc;
+    }
+    __syncthreads();
+    int32_t run = wsum[wave] + inc - own;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        if (base + q < n) out[base + q] = run;
+        run += v[q];
+    }
+}
+
+__global__ void k_scan_add(int32_t* __restrict__ out, int n, const int32_t* __restrict__ part) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += part[i / kScanTile];
+}
+
+// slot of each marker in its tile (the order the atomics land in) ...
+__global__ void k_tile_scatter(const int32_t* __restrict__ key, int n, const int32_t* __restrict__ start,
+                               int32_t* __restrict__ cursor, int32_t* __restrict__ order) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int k = key[s];
+    order[start[k] + atomicAdd(&cursor[k], 1)] = s;
+}
+
+// ... then each tile's markers back into ascending index (a stable sort's
+// order); tiles hold a handful of markers, so one thread sorts one tile
+__global__ void k_tile_order(const int32_t* __restrict__ start, int n_tiles, int32_t* __restrict__ order) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const int a = start[t], b = start[t + 1];
+    for (int i = a + 1; i < b; ++i) {
+        const int32_t v = order[i];
+        int j = i - 1;
+        while (j >= a && order[j] > v) {
+            order[j + 1] = order[j];
+            --j;
+        }
+        order[j + 1] = v;
+    }
+}
+
+// tile_start = exclusive scan of the n_tiles + 1 counts (the last is 0, so
+// tile_start[n_tiles] = n)
+static int scan_tiles(Ctx* c, hipStream_t st) {
+    const int n = c->n_tiles + 1;
+    const int blocks = (int)((n + kScanTile - 1) / kScanTile);
+    IB_CHECK(blocks <= kScanTile, IB_EINVAL, "ib_bin_markers: too many tiles for the scan");
+    hipLaunchKernelGGL(k_scan_block, dim3(blocks), dim3(kScanThreads), 0, st, c->bin_count, n, c->tile_start,
+                       c->scan_part);
+    if (blocks > 1) {
+        // the block totals, scanned in place by one block (its own total is not needed)
+        hipLaunchKernelGGL(k_scan_block, dim3(1), dim3(kScanThreads), 0, st, c->scan_part, blocks,
+                           c->scan_part, c->scan_part + blocks);
+        hipLaunchKernelGGL(k_scan_add, dim3(grid_for(n)), dim3(kBlock), 0, st, c->tile_start, n, c->scan_part);
+    }
+    return IB_OK;
 }
 
 int launch_bin_markers(Ctx* c, const ib_surface* s, hipStream_t st) {
     int n = s->n_markers;
+    const int nt1 = c->n_tiles + 1;
     if (n == 0) {
-        IB_HIP(hipMemsetAsync(c->tile_start, 0, sizeof(int32_t) * (c->n_tiles + 1), st));
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nt1)), dim3(kBlock), 0, st, c->tile_start, nt1, 0);
+        IB_HIP(hipGetLastError());
         return IB_OK;
     }
     hipLaunchKernelGGL(k_tile_keys, dim3(grid_for(n)), dim3(kBlock), 0, st, s->X, n, c->d, c->tnx,
-                       c->tny, c->bin_key, c->bin_idx);
-    int end_bit = 1;
-    while ((1 << end_bit) <= c->n_tiles) ++end_bit;
-    size_t need = 0;
-    IB_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, need, c->bin_key, c->bin_key_sorted,
-                                               c->bin_idx, c->bin_order, n, 0, end_bit, st));
-    IB_CHECK(need <= c->sort_tmp_bytes, IB_ENOMEM, "ib_bin_markers: sort workspace too small");
-    size_t bytes = c->sort_tmp_bytes;
-    IB_HIP(hipcub::DeviceRadixSort::SortPairs(c->sort_tmp, bytes, c->bin_key, c->bin_key_sorted,
-                                               c->bin_idx, c->bin_order, n, 0, end_bit, st));
-    hipLaunchKernelGGL(k_tile_start, dim3(grid_for(c->n_tiles + 1)), dim3(kBlock), 0, st,
-                       c->bin_key_sorted, n, c->n_tiles, c->tile_start);
+                       c->tny, c->bin_key);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nt1)), dim3(kBlock), 0, st, c->bin_count, nt1, 0);
+    hipLaunchKernelGGL(k_tile_count, dim3(grid_for(n)), dim3(kBlock), 0, st, c->bin_key, n, c->bin_count);
+    IB_TRY(scan_tiles(c, st));
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nt1)), dim3(kBlock), 0, st, c->bin_count, nt1, 0);
+    hipLaunchKernelGGL(k_tile_scatter, dim3(grid_for(n)), dim3(kBlock), 0, st, c->bin_key, n, c->tile_start,
+                       c->bin_count, c->bin_order);
+    hipLaunchKernelGGL(k_tile_order, dim3(grid_for(c->n_tiles)), dim3(kBlock), 0, st, c->tile_start,
+                       c->n_tiles, c->bin_order);
     IB_HIP(hipGetLastError());
     return IB_OK;
 }

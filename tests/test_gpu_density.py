@@ -4,11 +4,12 @@ hierarchy (mg_update_coeffs) and against the oracle.
 * ib_density: rho bitwise the oracle's rho_out + (rho_in - rho_out) H (NumPy
   rounds the multiply and the add separately, as the library does), and
   2 / (rho_c + rho_{c-e_d}) bitwise the faces of ib_coefficients;
-* equal fixed cycles: p and the residual history bitwise those of the
-  stored-face path -- the finest kernels form the same coefficients and do
-  the same arithmetic -- on grids where the kernels read rho directly
-  (128^3; 256 x 128 x 128) and on grids where the faces are formed into the
-  handle (2D; 32^3), in FP64 and mixed precision;
+* equal fixed cycles: p bitwise that of the stored-face path -- the finest
+  kernels form the same coefficients and do the same arithmetic -- on grids
+  where the kernels read rho directly (128^3; 256 x 128 x 128) and on grids
+  where the faces are formed into the handle (2D; 32^3), in FP64 and mixed
+  precision; the residual history to 1e-13 (the tiled density kernels sum
+  their norms per tile);
 * the density path against the oracle's multigrid at equal cycles (1e-11).
 """
 import numpy as np
@@ -101,8 +102,10 @@ def test_density_path_bitwise_vs_faces(ib, shape, nc, prec):
     diff = np.max(np.abs(p0 - p1))
     print(f"{shape} {prec}: max |p_faces - p_density| = {diff:.3e}, rel_res {s1['rel_res']:.3e}")
     assert np.array_equal(p0, p1)
-    assert s0["hist"] == s1["hist"]
-    assert r0 == r1
+    # the norms of the tiled density kernels are summed per tile, those of the
+    # stored-face kernels per grid-stride block: equal up to summation order
+    assert np.allclose(s0["hist"], s1["hist"], rtol=1e-13, atol=0)
+    assert abs(r0 - r1) <= 1e-13 * r0
 
 
 def test_density_path_vs_oracle_128(ib):

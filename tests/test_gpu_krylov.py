@@ -101,7 +101,9 @@ def test_krylov_converged(ib, shape, prec):
     assert st["rel_res"] <= 1e-10
     # the stop is decided on the true residual
     assert true <= 1e-10
-    assert abs(st["rel_res"] - true) <= 1e-6 * true
+    # two evaluations of b - A p at ||r|| ~ 1e-11 ||b|| differ by the rounding
+    # of b - A p itself (~1e-16 ||b|| per cell)
+    assert abs(st["rel_res"] - true) <= 1e-3 * true
     assert st["cycles"] < res[0][0]["cycles"]
     if np.prod(shape) <= 32 ** 3:
         beta = poisson.face_beta(poisson.density(H, 1.0, 1e-3))

@@ -63,9 +63,12 @@ def _surface3d(ib, V, T, sigma=1.0):
 
 # ----------------------------------------------------------------------------
 # a1 binning
-@pytest.mark.parametrize("dim", [2, 3])
-def test_binning_bit_exact(ib, dim):
-    n = (64, 64) if dim == 2 else (32, 32, 32)
+@pytest.mark.parametrize("n", [(64, 64), (512, 512), (32, 32, 32), (128, 64, 64), (256, 256, 256)])
+def test_binning_bit_exact(ib, n):
+    """Counting sort (histogram, two-level exclusive scan, scatter, index order
+    within a tile) against the oracle's stable sort: one scan block (64^2,
+    32^3), several (512^2, 128 x 64 x 64), 65 blocks of 4096 tiles (256^3)."""
+    dim = len(n)
     h = 1.0 / n[0]
     rng = np.random.default_rng(17)
     X = rng.uniform(0.0, 1.0, size=(3000, dim))
@@ -80,6 +83,13 @@ def test_binning_bit_exact(ib, dim):
     assert np.array_equal(host(key), k0)
     assert np.array_equal(host(order), o0)
     assert np.array_equal(host(start), s0)
+
+
+def test_binning_no_markers(ib):
+    ctx = ib.Context(2, (64, 64), 1 / 64, max_markers=16)
+    surf = ib.make_surface(torch.zeros((0, 2), dtype=torch.float64, device="cuda"))
+    key, order, start = ctx.bin_markers(surf)
+    assert np.array_equal(host(start), np.zeros(257, dtype=np.int32))
 
 
 # ----------------------------------------------------------------------------
