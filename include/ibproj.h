@@ -218,6 +218,20 @@ void mg_destroy(mg_handle* m);
 /* ||b - A p||_2 / ||b||_2 on the finest level with the coefficients of the last
  * mg_update_coeffs (0 when b = 0). Syncs. */
 int  mg_residual_norm(mg_handle* m, const double* b, const double* p, double* rel, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the residual norm of
+ * mg_residual_norm without a handle and without any allocation or host sync.
+ * rho: device cell densities, the operator's face coefficients being
+ * 2 / (rho_c + rho_{c-e_d}) as after mg_update_density; b, p: device cell
+ * arrays; rel: one device double that receives ||b - A p||_2 / ||b||_2 (0 when
+ * b = 0) in stream order. Same kernels and summation order as
+ * mg_residual_norm on a handle given these densities. The partial sums live
+ * in a fixed device array of the library (128 KB per GPU, held until the
+ * process ends; nothing needs clearing between calls), shared by every call
+ * on that GPU: calls that overlap on one GPU race. At most 2^31 - 1 cells
+ * (IB_EINVAL beyond). Errors: IB_EINVAL, IB_EHIP. */
+int  mg_residual_norm_noalloc(const ib_grid* g, const double* rho, const double* b, const double* p,
+                              double* rel, void* stream);
 
 /* ---------------------------------------------------------------------------
  * One projection step (a1..a11). */

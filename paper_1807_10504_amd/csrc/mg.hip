@@ -23,6 +23,8 @@
 // single-pass tiled sweep; the others are one-thread-per-cell stencils.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <type_traits>
 #include <vector>
 
@@ -1908,6 +1910,20 @@ static void vcycle(mg_handle* m, int l, hipStream_t st, bool zero_start) {
 
 static int red_blocks(long N) { return (int)std::min<long>(kRed, (long)grid_for(N)); }
 
+// z-range per workgroup of the density kernels (64 x 8 tiles) on a 3D level
+// the single-pass smoother takes, or 0 where they do not apply
+static int density_rtz(const Dims& d) {
+    if (d.dim != 3 || d.nx % kFTX != 0 || d.ny % kFTY != 0 || d.nz < 32 || d.nz % 2 != 0 ||
+        d.cells() < 128L * 128 * 128 || d.nx % kRTX != 0)
+        return 0;
+    long rtiles = (long)(d.nx / kRTX) * (d.ny / kRTY);
+    int rtz = d.nz;
+    // 1024 workgroups on 256^3 (z-range 32): two rounds of the 512
+    // resident ones keep the z-marches short and the XCDs balanced
+    while (rtz % 4 == 0 && rtz > 16 && rtiles * (d.nz / rtz) < 1024) rtz /= 2;
+    return rtz;
+}
+
 // the finest level is given by densities on a grid the CG z-march tiles
 // (64 x 8 columns, an even z-range per workgroup)
 static bool tiled_rho(const Level& L) {
@@ -2080,14 +2096,7 @@ extern "C" int mg_setup(const ib_grid* g, const mg_opts* o, mg_handle** out) {
             int tz = lv.d.nz;
             while (tz % 4 == 0 && tz > 16 && tiles * (lv.d.nz / tz) < 1024) tz /= 2;
             lv.tz = tz;
-            if (lv.d.nx % kRTX == 0) {
-                long rtiles = (long)(lv.d.nx / kRTX) * (lv.d.ny / kRTY);
-                int rtz = lv.d.nz;
-                // 1024 workgroups on 256^3 (z-range 32): two rounds of the 512
-                // resident ones keep the z-marches short and the XCDs balanced
-                while (rtz % 4 == 0 && rtz > 16 && rtiles * (lv.d.nz / rtz) < 1024) rtz /= 2;
-                lv.rtz = rtz;
-            }
+            lv.rtz = density_rtz(lv.d);
         }
         if (l > 0) {
             if (hipMalloc(&lv.f64.p, N * sizeof(double)) != hipSuccess ||
@@ -2558,6 +2567,87 @@ extern "C" int mg_solve(mg_handle* m, const double* b, double* p, double rtol, i
         last_check = cycles;
     }
     if (cycles > 0) IB_TRY(remove_mean(m, false, st));
+    IB_HIP(hipGetLastError());
+    return IB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free residual norm: the partial sums of mg_residual_norm live in
+// a file-scope device array instead of the handle's workspace. Each GPU the
+// library runs on holds its own copy until the process ends; the host finds
+// its address once per device (hipGetSymbolAddress) and passes that address
+// to the kernels. Calls on one GPU share the array: overlapping calls race.
+namespace ib {
+
+constexpr int kScratchDoubles = 2 * kRed + 8;   // r^2 and b^2 partials, the two sums
+constexpr long kNoallocMaxCells = (1L << 31) - 1;  // the residual kernels index cells with int
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kScratchDevices] = {};
+
+// the current device's copy of `scratch` (looked up on its first use)
+static int scratch_on_device(double** out) {
+    int dev = -1;
+    IB_HIP(hipGetDevice(&dev));
+    IB_CHECK(dev >= 0 && dev < kScratchDevices, IB_EINVAL, "mg_residual_norm_noalloc: device ordinal");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(IB_EHIP, std::string("mg_residual_norm_noalloc: hipGetSymbolAddress failed: ") +
+                                     hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return IB_OK;
+}
+
+__global__ void k_rel_from_sums(const double* __restrict__ sums, double* __restrict__ rel) {
+    const double bb = sums[1];
+    *rel = bb > 0.0 ? sqrt(sums[0]) / sqrt(bb) : 0.0;
+}
+
+}  // namespace ib
+
+extern "C" int mg_residual_norm_noalloc(const ib_grid* g, const double* rho, const double* b,
+                                        const double* p, double* rel, void* stream) {
+    IB_CHECK(g && rho && b && p && rel, IB_EINVAL, "mg_residual_norm_noalloc: null argument");
+    IB_CHECK(g->dim == 2 || g->dim == 3, IB_EINVAL, "mg_residual_norm_noalloc: dim must be 2 or 3");
+    IB_CHECK(g->h > 0.0, IB_EINVAL, "mg_residual_norm_noalloc: h must be positive");
+    long cells = 1;
+    for (int e = 0; e < g->dim; ++e) {
+        IB_CHECK(g->n[e] >= 2, IB_EINVAL, "mg_residual_norm_noalloc: cells per axis must be >= 2");
+        cells *= g->n[e];
+        IB_CHECK(cells <= kNoallocMaxCells, IB_EINVAL,
+                 "mg_residual_norm_noalloc: grid larger than the maximum of 2^31 - 1 cells");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    double* sc = nullptr;
+    IB_TRY(scratch_on_device(&sc));
+    Level L;
+    L.d = make_dims(*g);
+    L.rho = rho;
+    L.rtz = density_rtz(L.d);
+    double* pr = sc;
+    double* pb = sc + kRed;
+    int parts = red_blocks(cells);
+    if (tiled_rho(L)) {
+        parts = launch_residual_rho<double>(L, p, b, nullptr, pr, pb, st);
+    } else {
+        const double inv_h2 = 1.0 / (L.d.h * L.d.h);
+        if (L.d.dim == 2)
+            hipLaunchKernelGGL((k_resid_norm<2, CoefRho>), dim3(parts), dim3(kBlock), 0, st, p, b,
+                               CoefRho{rho}, L.d, inv_h2, pr, pb);
+        else
+            hipLaunchKernelGGL((k_resid_norm<3, CoefRho>), dim3(parts), dim3(kBlock), 0, st, p, b,
+                               CoefRho{rho}, L.d, inv_h2, pr, pb);
+    }
+    IB_TRY(device_sum(pr, parts, sc + 2 * kRed, st));
+    IB_TRY(device_sum(pb, parts, sc + 2 * kRed + 1, st));
+    hipLaunchKernelGGL(k_rel_from_sums, dim3(1), dim3(1), 0, st, sc + 2 * kRed, rel);
     IB_HIP(hipGetLastError());
     return IB_OK;
 }

@@ -24,7 +24,7 @@ WS_ZERO, WS_PREV, WS_NN = 0, 1, 2
 EXPORTS = ("ib_create", "ib_destroy", "ib_bin_markers", "ib_interp", "ib_spread",
            "ib_coefficients", "ib_density", "ib_rhs", "ib_update", "mg_setup", "mg_update_coeffs",
            "mg_update_density", "mg_solve",
-           "mg_destroy", "mg_residual_norm", "project_step", "ib_relocate_bspline",
+           "mg_destroy", "mg_residual_norm", "mg_residual_norm_noalloc", "project_step", "ib_relocate_bspline",
            "ib_surface_geometry_3d", "ib_nn_param_count", "ib_nn_create", "ib_nn_destroy",
            "ib_nn_set_params", "ib_nn_get_params", "ib_nn_predict", "ib_nn_gradients",
            "ib_nn_train_step",
@@ -161,6 +161,7 @@ def load(path: str = LIB_PATH):
         "mg_solve": (i32, [vp, vp, vp, f64, i32, i32, P(MgStats), vp]),
         "mg_destroy": (None, [vp]),
         "mg_residual_norm": (i32, [vp, vp, vp, P(f64), vp]),
+        "mg_residual_norm_noalloc": (i32, [P(Grid), vp, vp, vp, vp, vp]),
         "ib_nn_param_count": (i32, [i32]),
         "ib_nn_create": (i32, [P(Grid), P(vp)]),
         "ib_nn_destroy": (None, [vp]),
@@ -795,6 +796,18 @@ def unflatten_params(flat, channels=(3, 32, 32, 32, 32, 32, 1), dim=2):
 
 # ----------------------------------------------------------------------------
 # kernel timing
+def residual_norm_noalloc(dim, n, h, rho, b, p, rel):
+    """||b - A p|| / ||b|| for the face coefficients 2 / (rho_c + rho_{c-e_d}),
+    written to the one-element float64 device tensor `rel` in stream order;
+    no handle, no allocation, no host sync (mg_residual_norm_noalloc)."""
+    import torch
+    lib = load()
+    g = make_grid(dim, n, h)
+    _check(lib.mg_residual_norm_noalloc(C.byref(g), _dptr(rho, torch.float64), _dptr(b, torch.float64),
+                                        _dptr(p, torch.float64), _dptr(rel, torch.float64), _stream()))
+    return rel
+
+
 def profile_enable(on=True):
     load().ib_profile_enable(1 if on else 0)
 

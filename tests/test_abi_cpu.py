@@ -46,6 +46,20 @@ def test_invalid_arguments_rejected_without_device():
     assert lib.mg_setup(C.byref(g), C.byref(o), C.byref(out)) == ibproj.IB_EINVAL
 
 
+def test_noalloc_residual_norm_rejects_oversized_grid():
+    """The allocation-free norm refuses grids beyond its 2^31 - 1 cells before
+    any device work (the pointers are never dereferenced)."""
+    import ctypes as C
+    lib = ibproj.load()
+    g = ibproj.make_grid(3, (2048, 2048, 1024), 1 / 2048)
+    fake = C.c_void_p(4096)
+    rc = lib.mg_residual_norm_noalloc(C.byref(g), fake, fake, fake, fake, None)
+    assert rc == ibproj.IB_EINVAL
+    assert b"maximum" in lib.ib_last_error()
+    g = ibproj.make_grid(4, (16, 16, 16), 1 / 16)
+    assert lib.mg_residual_norm_noalloc(C.byref(g), fake, fake, fake, fake, None) == ibproj.IB_EINVAL
+
+
 @pytest.mark.parametrize("case", ["c1_static", "c1_moving", "c2_jitter", "interpol_cir", "mode2"])
 def test_bspline_relocation_bit_exact(case):
     if case == "c1_static":
