@@ -590,6 +590,94 @@ def _free_fall_run(ib, torch, eo, mo, h=0.0125, nr=128, nz=256, dt=5e-4, steps=8
                 mass_corrections=int(corrections))
 
 
+def bench_c5(ib, torch, steps=2000, train_steps=400, train_iters=600, nr=256, nz=1024):
+    """Axisymmetric free-falling water drop in air, SI units: (r, z) meridian half
+    plane of nr x nz cells, h = 31.25 um (8 mm x 32 mm), drop radius 1 mm on the
+    axis, rho 1000 / 1.2 kg/m^3, mu 1e-3 / 1.8e-5 Pa s, sigma 0.072 N/m, g 9.81,
+    512 contour markers with seeded 1 % radial noise (mirror-symmetric about the
+    axis); restoring frame, weight, mass correction every 20 steps; multigrid in
+    mixed precision (float32 V(2,2) cycles in float64 defect correction; the
+    flexible CG loses positivity of (r, V r) on this r-weighted system, so the
+    plain cycles are the solver here). Two runs from
+    the same start: both take train_steps steps warm-started from p_prev, whose
+    pairs (b, 1/rho, p_prev -> p) train the warm network; then one continues
+    `steps` steps with the learned warm start (multigrid judging every guess),
+    the other from p_prev."""
+    from paper_1807_10504_amd import workloads as W
+    h = 8e-3 / nr
+    R = 1e-3
+    dt = 5e-6   # capillary limit sqrt(rho_mean h^3 / (2 pi sigma)) = 5.8e-6 s
+    prm = dict(rho_in=1000.0, rho_out=1.2, mu_in=1e-3, mu_out=1.8e-5, sigma=0.072, dt=dt, rtol=1e-10,
+               pred_rtol=1e-12, warm_start=ib.WS_PREV, gravity=-9.81, frame=True, c1=0.1, c2=0.1,
+               mass_every=20)
+    axis = nr * h
+    X0 = W.axis_symmetric_jittered_circle(512, R, 0.01, 5, (axis, 0.5 * nz * h))
+    runs = {}
+    net = ib.Network((nr, nz), h)
+    net.set_params(W.network_init(3))
+    shape = (nz, nr)
+    for mode in ("nn", "prev"):
+        mg = ib.Multigrid(2, (nr, nz), h, precision=ib.MG_MIXED, krylov=0)
+        solver = ib.Axisym(nr, nz, h, max_markers=512)
+        X = X0.copy()
+        u = [torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(2)]
+        p = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        pairs = []
+        for k in range(train_steps):
+            pp = p.clone()
+            out = dict(p=torch.empty(shape, dtype=torch.float64, device="cuda"),
+                       u=[torch.empty(shape, dtype=torch.float64, device="cuda") for _ in range(2)],
+                       b=torch.empty(shape, dtype=torch.float64, device="cuda"),
+                       H=torch.empty(shape, dtype=torch.float64, device="cuda"))
+            out = solver.flow_step(mg, prm, u, X, p_prev=p, out=out)
+            if mode == "nn" and k >= 2:
+                pairs.append((out["b"], out["H"], pp, out["p"]))
+            u, p = out["u"], out["p"]
+        if mode == "nn":
+            rng = np.random.default_rng(5)
+            t0 = time.perf_counter()
+            losses = []
+            for it in range(train_iters):
+                idx = rng.choice(len(pairs), size=4, replace=False)
+                losses.append(net.train_step([pairs[i] for i in idx], prm["rho_in"], prm["rho_out"], 2e-3))
+            torch.cuda.synchronize()
+            runs["train"] = dict(pairs=len(pairs), iters=train_iters, seconds=round(time.perf_counter() - t0, 2),
+                                 loss_first=float(np.mean(losses[:10])), loss_last=float(np.mean(losses[-50:])))
+            del pairs
+        cycles, accepted = [], []
+        bufs = [dict(p=torch.empty(shape, dtype=torch.float64, device="cuda"),
+                     u=[torch.empty(shape, dtype=torch.float64, device="cuda") for _ in range(2)]) for _ in range(2)]
+        p_cur = p.clone()
+        prm_run = dict(prm, warm_start=ib.WS_NN if mode == "nn" else ib.WS_PREV)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            o = solver.flow_step(mg, prm_run, u, X, p_prev=p_cur, out=bufs[k % 2],
+                                 nn=net if mode == "nn" else None)
+            u, p_cur = o["u"], o["p"]
+            cycles.append(o["stats"]["cycles"])
+            accepted.append(o["guess"]["accepted"])
+            if k % 1000 == 999:
+                log(f"  C5 {mode}: step {k + 1}/{steps}, cycles {np.mean(cycles[-1000:]):.2f}")
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        runs[mode] = dict(steps=steps, steps_per_s=round(steps / secs, 2), ms_per_step=round(1e3 * secs / steps, 3),
+                          mean_vcycles=float(np.mean(cycles)),
+                          guess_accepted=float(np.mean(accepted)) if mode == "nn" else None,
+                          p_final=p_cur)
+        mg.close()
+        solver.close()
+    net.close()
+    d = (runs["nn"].pop("p_final") - runs["prev"]["p_final"]).norm().item() / runs["prev"]["p_final"].norm().item()
+    runs["prev"].pop("p_final")
+    runs["p_rel_l2_nn_vs_prev_after_run"] = d
+    runs["workload"] = (f"axisymmetric free-falling water drop in air: {nr} x {nz} meridian half plane, h = 31.25 um, "
+                        f"R = 1 mm, rho 1000/1.2, mu 1e-3/1.8e-5, sigma 0.072, g 9.81, 512 markers with 1% seeded "
+                        f"noise, dt = 5e-6 s; mixed-precision V(2,2) cycles; {train_steps} steps from p_prev to train "
+                        f"the warm network, then {steps} steps with it vs from p_prev")
+    return runs
+
+
 def bench_free_fall(ib, torch):
     """Free-fall drops of Table afd_param sets 1 and 2 at h = 0.0125 on the meridian
     plane: steps/s of the full step with weight, frame and mass correction, and
@@ -717,65 +805,101 @@ def bench_predictor_3d(ib, torch, nc=256, calls=5):
                 frac_hbm=round(algo / secs / 1e9 / HBM_PEAK_GBS, 4))
 
 
-def bench_2d_c4_nn(ib, torch, n=512, steps=48, train_iters=300):
-    """Learned warm start: oscillating drop (mode 2, amplitude 0.1), projection-only
-    dynamics; the network is trained on pairs the multigrid generates and evaluated
-    on held-out steps against a zero start (cold) and against p_prev (warm)."""
+def bench_2d_c4_nn(ib, torch, n=512, trajectories=20, steps=100, train_iters=1500, evals=20):
+    """Learned warm start on the oscillating-drop configuration: seeded
+    trajectories of projection-only dynamics (u* = u^n) from r = R(1 + 0.1 cos 2theta
+    + seeded modes 3..6 of amplitude <= 0.02), the pairs (b, 1/rho, p_prev -> p)
+    the multigrid generates along them, the last trajectory held out. Two networks:
+    cold (from b and 1/rho alone) and warm (with p_prev). Reported: V-cycles from
+    the guesses against zero and against p_prev on held-out steps, the solve time
+    with inference, and the converged pressure's error against the oracle's
+    tightly converged solve of the same step."""
+    from oracle import poisson
     from paper_1807_10504_amd import workloads as W
     h = 1.0 / n
     shape = (n, n)
-    X = W.mode_shape(1024, 0.2, 0.1)
-    ctx = ib.Context(2, (n, n), h, max_markers=len(X))
+    ctx = ib.Context(2, (n, n), h, max_markers=1024)
     mg = ib.Multigrid(2, (n, n), h)
-    u = [torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(2)]
     prm = dict(rho_in=1.0, rho_out=1e-3, sigma=1.0, dt=2e-5, rtol=1e-10, warm_start=ib.WS_PREV)
-    p_prev, samples = None, []
+    trajs = []
     t0 = time.perf_counter()
-    for s in range(steps):
-        o = dict(b=torch.empty(shape, dtype=torch.float64, device="cuda"),
-                 H=torch.empty(shape, dtype=torch.float64, device="cuda"))
-        pp = p_prev.clone() if p_prev is not None else torch.zeros(shape, dtype=torch.float64, device="cuda")
-        o = ctx.project_step(mg, prm, u, p_prev=p_prev, X_host=X, out=o)
-        samples.append((o["b"], o["H"], pp, o["p"].clone()))
-        u, p_prev = o["u"], o["p"]
+    for tr in range(trajectories):
+        X = W.mode_shape(1024, 0.2, 0.1, seed=100 + tr, extra_amp=0.02)
+        u = [torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(2)]
+        p_prev, pairs = None, []
+        for s_ in range(steps):
+            o = dict(b=torch.empty(shape, dtype=torch.float64, device="cuda"),
+                     H=torch.empty(shape, dtype=torch.float64, device="cuda"))
+            pp = p_prev.clone() if p_prev is not None else torch.zeros(shape, dtype=torch.float64, device="cuda")
+            o = ctx.project_step(mg, prm, u, p_prev=p_prev, X_host=X, out=o)
+            if s_ >= 2:
+                pairs.append((o["b"], o["H"], pp, o["p"].clone()))
+            u, p_prev = o["u"], o["p"]
+        trajs.append(pairs)
+        if (tr + 1) % 5 == 0:
+            log(f"  trajectory {tr + 1}/{trajectories}")
     torch.cuda.synchronize()
     t_pairs = time.perf_counter() - t0
-    train, held = samples[4:steps - 8], samples[steps - 8:]
-    net = ib.Network((n, n), h)
-    net.set_params(W.network_init(1))
-    rng = np.random.default_rng(1)
-    t0 = time.perf_counter()
-    losses = []
-    for it in range(train_iters):
-        idx = rng.choice(len(train), size=4, replace=False)
-        losses.append(net.train_step([(train[i][0], train[i][1], None, train[i][3]) for i in idx],
-                                     1.0, 1e-3, 2e-3))
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    cyc_nn, cyc_zero, t_nn, t_zero = [], [], 0.0, 0.0
-    for (b, H, pp, p) in held:
-        beta = ctx.coefficients(H, 1.0, 1e-3)
-        mg.update_coeffs(beta)
-        torch.cuda.synchronize()
+    train = [smp for tr in trajs[:-1] for smp in tr]
+    held = trajs[-1]
+    out = dict(workload=f"oscillating drop 2D {n}^2, r=R(1+0.1cos2theta+seeded modes 3-6 <=0.02), R=0.2, 1024 "
+                        f"markers, rho ratio 1000, dt=2e-5; {trajectories} seeded trajectories x {steps} "
+                        f"projection steps -> {len(train)} training pairs, the last trajectory "
+                        f"({len(held)} steps) held out",
+               pairs=len(train), pairs_s=round(t_pairs, 2))
+    nets = {}
+    for kind in ("cold", "warm"):
+        net = ib.Network((n, n), h)
+        net.set_params(W.network_init(1 if kind == "cold" else 2))
+        rng = np.random.default_rng(1)
         t0 = time.perf_counter()
-        g = net.predict(b, H, None, 1.0, 1e-3)
-        s1 = mg.solve(b, g, rtol=1e-10)
+        losses = []
+        for it in range(train_iters):
+            idx = rng.choice(len(train), size=4, replace=False)
+            batch = [(train[i][0], train[i][1], None if kind == "cold" else train[i][2], train[i][3]) for i in idx]
+            losses.append(net.train_step(batch, 1.0, 1e-3, 2e-3))
         torch.cuda.synchronize()
-        t_nn += time.perf_counter() - t0
-        z = torch.zeros_like(p)
-        t0 = time.perf_counter()
-        s2 = mg.solve(b, z, rtol=1e-10)
-        torch.cuda.synchronize()
-        t_zero += time.perf_counter() - t0
-        cyc_nn.append(s1["cycles"])
-        cyc_zero.append(s2["cycles"])
-    return dict(workload=f"oscillating drop 2D {n}^2, r=R(1+0.1cos2theta), R=0.2, 1024 markers, rho ratio 1000, "
-                         f"dt=2e-5, {steps} projection steps -> {len(train)} training pairs, {len(held)} held out",
-                pairs_s=round(t_pairs, 2), train_s=round(t_train, 2),
-                loss_first=float(np.mean(losses[:5])), loss_last=float(np.mean(losses[-20:])),
-                cold_cycles_zero=float(np.mean(cyc_zero)), cold_cycles_nn=float(np.mean(cyc_nn)),
-                cold_solve_ms_zero=round(1e3 * t_zero / len(held), 3),
-                cold_solve_ms_nn_incl_inference=round(1e3 * t_nn / len(held), 3))
+        out[f"{kind}_train_s"] = round(time.perf_counter() - t0, 2)
+        out[f"{kind}_loss_first"] = float(np.mean(losses[:10]))
+        out[f"{kind}_loss_last"] = float(np.mean(losses[-50:]))
+        nets[kind] = net
+    sel = np.linspace(0, len(held) - 1, evals).astype(int)
+    res = {k: [] for k in ("zero", "cold_nn", "prev", "warm_nn")}
+    t = {k: 0.0 for k in res}
+    finals = []
+    for i in sel:
+        b, H, pp, p = held[i]
+        mg.update_coeffs(ctx.coefficients(H, 1.0, 1e-3))
+        for key, start in (("zero", None), ("cold_nn", "cold"), ("prev", pp), ("warm_nn", "warm")):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if key == "zero":
+                x = torch.zeros_like(p)
+            elif key == "prev":
+                x = pp.clone()
+            else:
+                x = nets[start].predict(b, H, None if start == "cold" else pp, 1.0, 1e-3)
+            st = mg.solve(b, x, rtol=1e-10)
+            torch.cuda.synchronize()
+            t[key] += time.perf_counter() - t0
+            res[key].append(st["cycles"])
+            if key == "cold_nn" and len(finals) < 3:
+                finals.append((b.cpu().numpy(), H.cpu().numpy(), x.cpu().numpy()))
+    for k in res:
+        out[f"cycles_{k}"] = float(np.mean(res[k]))
+        out[f"solve_ms_{k}"] = round(1e3 * t[k] / len(sel), 3)
+    # the converged answer from the learned start against the oracle
+    errs = []
+    for (b, H, x) in finals:
+        beta = poisson.face_beta(poisson.density(H, 1.0, 1e-3))
+        po, _, _ = poisson.mg_pcg(b, beta, h, rtol=1e-13, max_iter=100)
+        errs.append(float(np.linalg.norm(x - po) / np.linalg.norm(po)))
+    out["cold_nn_p_rel_l2_vs_oracle_tight"] = max(errs)
+    for net in nets.values():
+        net.close()
+    mg.close()
+    ctx.close()
+    return out
 
 
 def cpu_baseline(wl, cycles_per_step, krylov):
@@ -877,11 +1001,15 @@ def main():
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D workloads (C2, learned warm start)")
     ap.add_argument("--no-nn3d", action="store_true", help="skip the 3D learned warm start")
     ap.add_argument("--nn3d-iters", type=int, default=60, help="training iterations of the 3D network")
+    ap.add_argument("--c5-steps", type=int, default=2000,
+                    help="steps of the axisymmetric free-fall run with and without the learned warm start")
+    ap.add_argument("--c4-steps", type=int, default=100,
+                    help="projection steps per oscillating-drop trajectory (20 trajectories) for the 2D network")
     ap.add_argument("--no-flow", action="store_true",
                     help="skip the full 2D flow steps and the 3D momentum predictor")
     ap.add_argument("--section", default=None,
                     choices=("flow_osc", "static_tables", "conventional", "osc_energy", "flow3d", "free_fall",
-                             "predictor_3d"),
+                             "predictor_3d", "c5", "c4"),
                     help="run only this section of the flow measurements and print its JSON (for profiling)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MB (PMC byte-counter calibration)")
@@ -900,7 +1028,9 @@ def main():
     if args.section:
         run = {"flow_osc": bench_flow_osc, "static_tables": bench_static_tables, "conventional": bench_conventional,
                "osc_energy": bench_osc_energy, "flow3d": bench_flow3d, "free_fall": bench_free_fall,
-               "predictor_3d": lambda ib_, t_: bench_predictor_3d(ib_, t_, args.size)}[args.section]
+               "predictor_3d": lambda ib_, t_: bench_predictor_3d(ib_, t_, args.size),
+               "c5": lambda ib_, t_: bench_c5(ib_, t_, steps=args.c5_steps),
+               "c4": lambda ib_, t_: bench_2d_c4_nn(ib_, t_, steps=args.c4_steps)}[args.section]
         print(json.dumps({args.section: run(ib, torch)}), flush=True)
         return
     wl = W.static_drop_3d(args.size, args.level, seed=3)
@@ -1007,8 +1137,8 @@ def main():
     if not args.no_2d:
         log("== 2D 512^2 jittered drop: FP64 vs mixed, 200 steps")
         line["c2_2d"] = bench_2d_c2(ib, torch)
-        log("== 2D 512^2 learned warm start")
-        line["nn_2d"] = bench_2d_c4_nn(ib, torch)
+        log("== 2D 512^2 learned warm start (oscillating-drop trajectories)")
+        line["nn_2d"] = bench_2d_c4_nn(ib, torch, steps=args.c4_steps)
     if not args.no_flow:
         log("== full flow steps: Table osc oscillating drops (2D and axisymmetric)")
         line["flow_osc"] = bench_flow_osc(ib, torch)
@@ -1022,6 +1152,8 @@ def main():
         line["flow3d"] = bench_flow3d(ib, torch)
         log("== free-fall drops (Table afd_param sets 1-2, axisymmetric)")
         line["free_fall"] = bench_free_fall(ib, torch)
+        log("== axisymmetric free-falling water drop, 256 x 1024, mixed precision + learned warm start")
+        line["c5_free_fall_nn"] = bench_c5(ib, torch, steps=args.c5_steps)
         log(f"== momentum predictor at {args.size}^3")
         line["predictor_3d"] = bench_predictor_3d(ib, torch, args.size)
     if not args.no_cpu_baseline:

@@ -244,9 +244,11 @@ typedef struct {
     int fixed_cycles;        /* > 0: exactly this many cycles (parity runs) */
     int spread_mode;         /* IB_SPREAD_IRROT or IB_SPREAD_DELTA */
     int warm_start;          /* WS_ZERO, WS_PREV (p_prev as initial guess) or WS_NN
-                                (network guess from (b, 1/rho, p_prev), used when it is
-                                finite and its residual is below that of p_prev (of 0
-                                when p_prev is NULL); else p_prev or 0) */
+                                (network guess from (b, 1/rho, p_prev), the start when it
+                                is finite and its error in the operator's energy norm is
+                                below the fallback's, p_prev or 0 when p_prev is NULL,
+                                judged by the energy functional of ib_outputs; else the
+                                fallback) */
 } ib_params;
 
 typedef struct {
@@ -275,7 +277,10 @@ typedef struct {
     mg_stats stats;
     int guess_accepted;      /* WS_NN: 1 when the network guess was used */
     double guess_rel_res;    /* WS_NN: ||b - A p_nn|| / ||b|| */
-    double prev_rel_res;     /* WS_NN: ||b - A p_prev|| / ||b|| */
+    double prev_rel_res;     /* WS_NN: the same of the fallback (1 for the zero start) */
+    double guess_energy;     /* WS_NN: E(p_nn) = p_nn . (b + r), r = b - A p_nn; with
+                                K = -A, E(x) = ||x - p||_K^2 - ||p||_K^2 */
+    double prev_energy;      /* WS_NN: E of the fallback (0 for the zero start) */
 } ib_outputs;
 
 /* Runs interp -> (2D: D2H U, host advance + B-spline relocation, H2D) ->

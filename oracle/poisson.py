@@ -23,7 +23,10 @@ cycle, stop when ||b - A p||_2 / ||b||_2 <= rtol.
 
 Mixed precision: the same V-cycle in float32 (float32 coefficients, float32
 right side and correction, coarsest level in float64) inside a float64
-defect-correction loop r = b - A p (float64), p += V32(fl32(r)).
+defect-correction loop r = b - A p (float64), p += V32(fl32(r)). The float32
+coefficients are the float64 ones rounded, except on a finest level given by
+its cell densities (rho passed): there the densities are rounded to float32
+and each face coefficient is formed in float32, 2 / (fl32(rho_L) + fl32(rho_R)).
 
 Krylov variant (an extension; the paper only names multigrid): flexible
 conjugate gradients (the Polak-Ribiere form of the direction update, which
@@ -222,13 +225,23 @@ def fft_solve(b, beta_const, h):
 # ----------------------------------------------------------------------------
 # Multigrid
 # ----------------------------------------------------------------------------
+def face_beta_f32(rho):
+    """Float32 face coefficients formed in float32 from the float32 densities."""
+    r = np.asarray(rho, dtype=np.float64).astype(np.float32)
+    dim = r.ndim
+    return [np.float32(2.0) / (r + np.roll(r, 1, axis=dim - 1 - d)) for d in range(dim)]
+
+
 class Hierarchy:
-    def __init__(self, beta, h, n_coarsest=4, dtype=np.float64):
+    def __init__(self, beta, h, n_coarsest=4, dtype=np.float64, rho=None):
         self.levels = []
         b = [np.asarray(x, dtype=np.float64) for x in beta]
         hl = h
         while True:
-            self.levels.append(([x.astype(dtype) for x in b], hl))
+            if not self.levels and rho is not None and dtype == np.float32:
+                self.levels.append((face_beta_f32(rho), hl))
+            else:
+                self.levels.append(([x.astype(dtype) for x in b], hl))
             if min(b[0].shape) <= n_coarsest:
                 break
             b = coarsen_beta(b)
@@ -277,9 +290,10 @@ def mg_solve(b, beta, h, p0=None, rtol=1e-10, max_cycles=100, nu1=2, nu2=2, n_co
 
 
 def mg_solve_mixed(b, beta, h, p0=None, rtol=1e-10, max_cycles=100, nu1=2, nu2=2,
-                   n_coarsest=4, fixed_cycles=None):
-    """Float32 V-cycle inside float64 defect correction."""
-    hier = Hierarchy(beta, h, n_coarsest, dtype=np.float32)
+                   n_coarsest=4, fixed_cycles=None, rho=None):
+    """Float32 V-cycle inside float64 defect correction (rho: the finest
+    level's cell densities, from which its float32 coefficients are formed)."""
+    hier = Hierarchy(beta, h, n_coarsest, dtype=np.float32, rho=rho)
     p = np.zeros_like(b) if p0 is None else np.array(p0, dtype=np.float64)
     hist = [rel_residual(p, b, beta, h)]
     cycles = 0
@@ -348,10 +362,11 @@ def fcg(apply, precond, b, x0=None, rtol=1e-10, max_iter=100, fixed_iters=None):
 
 
 def mg_pcg(b, beta, h, p0=None, rtol=1e-10, max_iter=100, nu1=2, nu2=2, n_coarsest=4,
-           fixed_iters=None, mixed=False):
+           fixed_iters=None, mixed=False, rho=None):
     """FCG with one V(nu1, nu2) cycle from zero as preconditioner (float32
-    V-cycle on fl32(r) when mixed); mean of p removed at the end."""
-    hier = Hierarchy(beta, h, n_coarsest, dtype=np.float32 if mixed else np.float64)
+    V-cycle on fl32(r) when mixed, its finest coefficients from rho when
+    given); mean of p removed at the end."""
+    hier = Hierarchy(beta, h, n_coarsest, dtype=np.float32 if mixed else np.float64, rho=rho)
 
     def precond(r):
         if mixed:

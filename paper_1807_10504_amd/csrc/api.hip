@@ -331,6 +331,35 @@ extern "C" int project_step(ib_ctx* c, mg_handle* m, const ib_params* prm, ib_st
     return solve_and_update(c, m, prm, stt, out, stt->u_star, H, F, st);
 }
 
+int ib::nn_warm_start(mg_handle* m, ib_state* stt, ib_outputs* out, double rho_in, double rho_out,
+                      const double* b, const double* H, long N, hipStream_t st) {
+    IB_CHECK(stt->nn, IB_EINVAL, "WS_NN needs a network");
+    IB_CHECK(stt->p_prev != out->p, IB_EINVAL, "WS_NN needs p_prev distinct from p");
+    IB_CHECK(nn_cells(stt->nn) == N, IB_EINVAL, "WS_NN: the network's grid differs from the step's");
+    IB_TRY(ib_nn_predict(stt->nn, b, H, stt->p_prev, rho_in, rho_out, out->p, st));
+    // multigrid judges the guess by its error in the operator's energy norm,
+    // the norm in which the conjugate gradients and the V-cycles converge:
+    // with K = -A, E(x) = x . (b + r(x)) = ||x - p||_K^2 - ||p||_K^2 is
+    // computable from the residual, so the guess is used when it is finite
+    // and E(guess) < E(fallback) (p_prev, or zero with E = 0). The residual
+    // alone judges a learned guess badly: its high-frequency error, which the
+    // first sweeps remove, dominates the residual but not the energy
+    double eg = 0.0, ef = 0.0;
+    IB_TRY(mg_energy(m, b, out->p, &out->guess_rel_res, &eg, st));
+    IB_TRY(mg_energy(m, b, stt->p_prev, &out->prev_rel_res, &ef, st));
+    out->guess_energy = eg;
+    out->prev_energy = ef;
+    if (std::isfinite(eg) && std::isfinite(out->guess_rel_res) && eg < ef) {
+        out->guess_accepted = 1;
+    } else if (stt->p_prev) {
+        IB_HIP(hipMemcpyAsync(out->p, stt->p_prev, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    } else {
+        IB_HIP(hipMemsetAsync(out->p, 0, sizeof(double) * N, st));
+        mg_hint_zero_guess(m);
+    }
+    return IB_OK;
+}
+
 int ib::solve_and_update(Ctx* c, mg_handle* m, const ib_params* prm, ib_state* stt, ib_outputs* out,
                          const double* const u_star[3], const double* H, double* const F[3],
                          hipStream_t st) {
@@ -344,27 +373,9 @@ int ib::solve_and_update(Ctx* c, mg_handle* m, const ib_params* prm, ib_state* s
     if (out->b) IB_HIP(hipMemcpyAsync(out->b, c->b, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
     out->guess_accepted = 0;
     out->guess_rel_res = out->prev_rel_res = 0.0;
+    out->guess_energy = out->prev_energy = 0.0;
     if (prm->warm_start == WS_NN) {
-        IB_CHECK(stt->nn, IB_EINVAL, "project_step: WS_NN needs a network");
-        IB_CHECK(stt->p_prev != out->p, IB_EINVAL, "project_step: WS_NN needs p_prev distinct from p");
-        IB_TRY(ib_nn_predict(stt->nn, c->b, H, stt->p_prev, prm->rho_in, prm->rho_out, out->p, st));
-        IB_TRY(mg_residual_norm(m, c->b, out->p, &out->guess_rel_res, st));
-        if (stt->p_prev) {
-            IB_TRY(mg_residual_norm(m, c->b, stt->p_prev, &out->prev_rel_res, st));
-        } else {
-            out->prev_rel_res = 1.0;  // zero guess
-        }
-        // multigrid judges the guess: it is used only when it is finite and
-        // its residual is below the fallback's (p_prev, or zero); the solve
-        // then decides the answer from either start
-        if (std::isfinite(out->guess_rel_res) && out->guess_rel_res < out->prev_rel_res) {
-            out->guess_accepted = 1;
-        } else if (stt->p_prev) {
-            IB_HIP(hipMemcpyAsync(out->p, stt->p_prev, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-        } else {
-            IB_HIP(hipMemsetAsync(out->p, 0, sizeof(double) * N, st));
-            mg_hint_zero_guess(m);
-        }
+        IB_TRY(nn_warm_start(m, stt, out, prm->rho_in, prm->rho_out, c->b, H, N, st));
     } else if (prm->warm_start == WS_PREV && stt->p_prev) {
         if (stt->p_prev != out->p)
             IB_HIP(hipMemcpyAsync(out->p, stt->p_prev, sizeof(double) * N, hipMemcpyDeviceToDevice, st));

@@ -374,7 +374,7 @@ static int axi_coefficients(ib_axi* a, mg_handle* m, const ib_params* prm, const
 // right side from u_star and F, warm start, solve, update, u_r = 0 on the axis column
 static int axi_solve_update(ib_axi* a, mg_handle* m, const ib_params* prm, ib_state* stt,
                             ib_outputs* out, const double* const us[2], double* const Fh[2],
-                            hipStream_t st) {
+                            const double* H, hipStream_t st) {
     Ctx* Hc = a->half;
     const int nr = a->nr, nz = a->nz;
     const long N = (long)nr * nz;
@@ -385,7 +385,13 @@ static int axi_solve_update(ib_axi* a, mg_handle* m, const ib_params* prm, ib_st
     hipLaunchKernelGGL(k_axi_sub_mean, dim3(grid_for(N)), dim3(kBlock), 0, st, Hc->b, N,
                        a->red + 2 * kAxiRed);
     if (out->b) IB_HIP(hipMemcpyAsync(out->b, Hc->b, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-    if (prm->warm_start == WS_PREV && stt->p_prev) {
+    out->guess_accepted = 0;
+    out->guess_rel_res = out->prev_rel_res = 0.0;
+    out->guess_energy = out->prev_energy = 0.0;
+    if (prm->warm_start == WS_NN) {
+        // the network sees the r-weighted right side of the meridian plane
+        IB_TRY(nn_warm_start(m, stt, out, prm->rho_in, prm->rho_out, Hc->b, H, N, st));
+    } else if (prm->warm_start == WS_PREV && stt->p_prev) {
         if (stt->p_prev != out->p)
             IB_HIP(hipMemcpyAsync(out->p, stt->p_prev, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
     } else {
@@ -441,8 +447,9 @@ static int axi_check(ib_axi* a, mg_handle* m, const ib_params* prm, ib_state* st
              std::string(who) + ": dt and densities must be positive");
     IB_CHECK(prm->spread_mode == IB_SPREAD_IRROT || prm->spread_mode == IB_SPREAD_DELTA, IB_EINVAL,
              std::string(who) + ": spread mode");
-    IB_CHECK(prm->warm_start == WS_ZERO || prm->warm_start == WS_PREV, IB_EINVAL,
-             std::string(who) + ": warm start must be WS_ZERO or WS_PREV");
+    IB_CHECK(prm->warm_start == WS_ZERO || prm->warm_start == WS_PREV ||
+                 (prm->warm_start == WS_NN && stt->nn),
+             IB_EINVAL, std::string(who) + ": warm start must be WS_ZERO, WS_PREV or WS_NN with a network");
     IB_CHECK(stt->surf.n_markers >= 3 && stt->surf.n_markers <= a->full->max_markers, IB_EINVAL,
              std::string(who) + ": marker count");
     return IB_OK;
@@ -465,7 +472,7 @@ extern "C" int axi_project_step(ib_axi* a, mg_handle* m, const ib_params* prm, i
     IB_TRY(axi_interface(a, prm, stt, out, &s, H, Fh, st));
     IB_TRY(axi_coefficients(a, m, prm, H, Fh[0], st));
     const double* us[2] = {stt->u_star[0], stt->u_star[1]};
-    return axi_solve_update(a, m, prm, stt, out, us, Fh, st);
+    return axi_solve_update(a, m, prm, stt, out, us, Fh, H, st);
 }
 
 static int axi_predict_impl(ib_axi* a, const double* const u[2], const double* rho_n,
@@ -601,7 +608,7 @@ extern "C" int axi_flow_step(ib_axi* a, mg_handle* m, const ib_params* prm, cons
     IB_TRY(axi_predict_impl(a, un, a->rho_n, Hc->rho, a->mu, prm->dt, fp->rtol, fp->max_sweeps, a->ustar,
                             FS, B, st));
     const double* us[2] = {a->ustar[0], a->ustar[1]};
-    int rc = axi_solve_update(a, m, prm, stt, out, us, Fh, st);
+    int rc = axi_solve_update(a, m, prm, stt, out, us, Fh, H, st);
     if (rc != IB_OK && rc != IB_ENOTCONV) return rc;
     IB_HIP(hipMemcpyAsync(a->Hn, H, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
     return rc;

@@ -206,3 +206,16 @@ int mg_takes_density(const mg_handle* m);
 // stream): its first residual is b, so the first operator application is
 // skipped (the same residual and norms bit for bit); cleared by that solve
 void mg_hint_zero_guess(mg_handle* m);
+// ||b - A x|| / ||b|| and the energy functional E(x) = x . (b + b - A x) of a
+// start x (NULL: zero, E = 0); the smaller E, the smaller the error in the
+// operator's energy norm; syncs (mg.hip)
+int mg_energy(mg_handle* m, const double* b, const double* x, double* rel, double* E, hipStream_t st);
+namespace ib {
+// WS_NN: the network's guess into out->p, judged by multigrid against the
+// fallback (stt->p_prev, or zero) and replaced by it when it loses; sets the
+// guess fields of out (api.hip)
+int nn_warm_start(mg_handle* m, ib_state* stt, ib_outputs* out, double rho_in, double rho_out,
+                  const double* b, const double* H, long N, hipStream_t st);
+}  // namespace ib
+// cells of the grid the network handle was created for (0 for null)
+long nn_cells(const ib_nn* nn);

@@ -51,6 +51,10 @@ struct Level {
     // finest level only: cell densities from which the float64 kernels form
     // the face coefficients themselves (f64.beta is then unused)
     const double* rho = nullptr;
+    // ... and their float32 roundings, from which the float32 kernels of the
+    // mixed-precision cycle form theirs in float32 (stored in f32.beta[0];
+    // f32.beta[1..2] are then unused)
+    const float* rho32 = nullptr;
     // finest level of the float64 density path inside the flexible CG: the
     // last post-smoothing sweep also leaves the partial inner products of
     // the preconditioned residual with b (and with dots_q when not null)
@@ -96,6 +100,9 @@ struct mg_handle {
 namespace ib {
 
 constexpr int kRed = 8192;
+// residual checks skipped at most in a row on the predicted rate (an early,
+// erratic rate must not carry the solve far past its tolerance)
+constexpr int kMaxSkip = 4;
 
 // ---------------------------------------------------------------------------
 // optional event timing of finest-level launches
@@ -205,6 +212,19 @@ struct CoefRho {
     __device__ double yr(const Nb& n) const { return f(n.yp, n.c); }
     __device__ double zl(const Nb& n) const { return f(n.c, n.zm); }
     __device__ double zr(const Nb& n) const { return f(n.zp, n.c); }
+};
+
+// ... or in float32 from float32 densities (the mixed-precision cycle's finest
+// level on the density path), 2 / (rho_hi + rho_lo) rounded in float32
+struct CoefRhoF {
+    const float* __restrict__ rho;
+    __device__ float f(long hi, long lo) const { return 2.0f / (rho[hi] + rho[lo]); }
+    __device__ float xl(const Nb& n) const { return f(n.c, n.xm); }
+    __device__ float xr(const Nb& n) const { return f(n.xp, n.c); }
+    __device__ float yl(const Nb& n) const { return f(n.c, n.ym); }
+    __device__ float yr(const Nb& n) const { return f(n.yp, n.c); }
+    __device__ float zl(const Nb& n) const { return f(n.c, n.zm); }
+    __device__ float zr(const Nb& n) const { return f(n.zp, n.c); }
 };
 
 // densities: where all neighbours share the cell's density, every face is
@@ -492,7 +512,8 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
 // The same single-pass sweep on a finest level given by cell densities: the
 // workgroup stages p and rho on the tile plus the two-cell halo and b on the
 // one-cell ring, and forms each face coefficient 2 / (rho_hi + rho_lo) where
-// it is used. That is 32 bytes of memory traffic per cell (p read and
+// it is used (in T: float64, or float32 from the float32 densities of the
+// mixed-precision cycle, 16 bytes per cell). That is 32 bytes of memory traffic per cell (p read and
 // written, b, rho) instead of 48 with three stored face arrays; the update is
 // the one above, operand for operand, so the results are bitwise those of
 // the stored-face sweep.
@@ -500,12 +521,12 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
 // when qv is not null, (qv, p_new) in part[bid] and part[nwg + bid] (the
 // flexible-CG inner products of the preconditioned residual, taken from the
 // values the black lanes write).
-template <int TX, int TY, int NT, bool ZERO, bool DOTS = false>
-__global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const double* __restrict__ pin,
-                                                       double* __restrict__ pout,
-                                                       const double* __restrict__ bb,
-                                                       const double* __restrict__ rho, Dims d,
-                                                       double h2, int TZ, int ntx, int nty,
+template <typename T, int TX, int TY, int NT, bool ZERO, bool DOTS = false>
+__global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin,
+                                                       T* __restrict__ pout,
+                                                       const T* __restrict__ bb,
+                                                       const T* __restrict__ rho, Dims d,
+                                                       T h2, int TZ, int ntx, int nty,
                                                        int nzc, const double* __restrict__ qv = nullptr,
                                                        double* __restrict__ part = nullptr) {
     // region of p and rho: the tile and a two-cell halo; b: the one-cell ring
@@ -514,9 +535,13 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const double* __restrict_
     constexpr int NL = (RN + NT - 1) / NT, NZL = (ZN + NT - 1) / NT;
     constexpr int RedRow = (RX - 2) / 2, RedN = RedRow * (RY - 2);
     constexpr int BlackRow = TX / 2, BlackN = BlackRow * TY;
-    __shared__ double P[4][RN];
-    __shared__ double R[4][RN];
-    __shared__ double B[2][ZN];
+    static_assert(!DOTS || sizeof(T) == 8, "the inner products are taken in the float64 sweep");
+    // rings of five planes of p and rho and three of b: the black update of
+    // plane k - 1 reads planes k - 2 .. k while the next step already stages
+    // plane k + 2 (and b of k + 1), so no barrier separates them
+    __shared__ T P[5][RN];
+    __shared__ T R[5][RN];
+    __shared__ T B[3][ZN];
     __shared__ double red[DOTS ? 2 * (NT / 64) : 1];
     double acc_b = 0.0, acc_q = 0.0;
     const int nw = ntx * nty * nzc;
@@ -555,74 +580,85 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const double* __restrict_
     // two register stages, alternating: the planes of step k, p(k+1), rho(k+1)
     // and b(k), are loaded two steps ahead
     struct Stage {
-        double p[NL], r[NL], b[NZL];
+        T p[NL], r[NL], b[NZL];
     };
     Stage SA, SB;
     auto fetch = [&](Stage& S, int k) {
         long bp = pl(k + 1), bk = pl(k);
 #pragma unroll
         for (int s = 0; s < NL; ++s) {
-            S.p[s] = ZERO ? 0.0 : pin[bp + gp[s]];
+            S.p[s] = ZERO ? T(0) : pin[bp + gp[s]];
             S.r[s] = rho[bp + gp[s]];
         }
 #pragma unroll
         for (int s = 0; s < NZL; ++s) S.b[s] = bb[bk + gz[s]];
     };
+    // ring slots; planes k >= z0 - 2 >= -2
+    auto s5 = [](int k) { return (k + 10) % 5; };
+    auto s3 = [](int k) { return (k + 9) % 3; };
     auto commit = [&](const Stage& S, int k) {
+        T* Pn = P[s5(k + 1)];
+        T* Rn = R[s5(k + 1)];
+        T* Bk = B[s3(k)];
 #pragma unroll
         for (int s = 0; s < NL; ++s)
             if (s * NT + NT <= RN || vp[s]) {
-                P[(k + 1) & 3][t + s * NT] = S.p[s];
-                R[(k + 1) & 3][t + s * NT] = S.r[s];
+                Pn[t + s * NT] = S.p[s];
+                Rn[t + s * NT] = S.r[s];
             }
 #pragma unroll
         for (int s = 0; s < NZL; ++s)
-            if (s * NT + NT <= ZN || vz[s]) B[k & 1][t + s * NT] = S.b[s];
+            if (s * NT + NT <= ZN || vz[s]) Bk[t + s * NT] = S.b[s];
     };
     {
         long a = pl(z0 - 2), a1 = pl(z0 - 1);
 #pragma unroll
         for (int s = 0; s < NL; ++s)
             if (vp[s]) {
-                P[(z0 - 2) & 3][t + s * NT] = ZERO ? 0.0 : pin[a + gp[s]];
-                P[(z0 - 1) & 3][t + s * NT] = ZERO ? 0.0 : pin[a1 + gp[s]];
-                R[(z0 - 2) & 3][t + s * NT] = rho[a + gp[s]];
-                R[(z0 - 1) & 3][t + s * NT] = rho[a1 + gp[s]];
+                P[s5(z0 - 2)][t + s * NT] = ZERO ? T(0) : pin[a + gp[s]];
+                P[s5(z0 - 1)][t + s * NT] = ZERO ? T(0) : pin[a1 + gp[s]];
+                R[s5(z0 - 2)][t + s * NT] = rho[a + gp[s]];
+                R[s5(z0 - 1)][t + s * NT] = rho[a1 + gp[s]];
             }
     }
     fetch(SA, z0 - 1);
     // keep stage A's loads ahead of stage B's (the wait counts assume that order)
     __builtin_amdgcn_sched_barrier(0);
     fetch(SB, z0);
-    auto update = [&](int x, int y, int kk) {
+    // plane slots of kk - 1, kk, kk + 1 and b's slot of kk
+    struct Slots {
+        int d, c, u, b;
+    };
+    auto slots = [&](int kk) { return Slots{s5(kk - 1), s5(kk), s5(kk + 1), s3(kk)}; };
+    auto update = [&](int x, int y, const Slots& sl) {
         const int c = y * RX + x;
         const int iz = (y - 1) * ZW + (x - 1);
-        const double* Pc = P[kk & 3];
-        const double* Pd = P[(kk - 1) & 3];
-        const double* Pu = P[(kk + 1) & 3];
-        const double* Rc = R[kk & 3];
-        const double rc = Rc[c];
-        const double rxp = Rc[c + 1], rxm = Rc[c - 1], ryp = Rc[c + RX], rym = Rc[c - RX];
-        const double rzp = R[(kk + 1) & 3][c], rzm = R[(kk - 1) & 3][c];
-        double bxp, bxm, byp, bym, bzp, bzm;
+        const T* Pc = P[sl.c];
+        const T* Pd = P[sl.d];
+        const T* Pu = P[sl.u];
+        const T* Rc = R[sl.c];
+        const T rc = Rc[c];
+        const T rxp = Rc[c + 1], rxm = Rc[c - 1], ryp = Rc[c + RX], rym = Rc[c - RX];
+        const T rzp = R[sl.u][c], rzm = R[sl.d][c];
+        T bxp, bxm, byp, bym, bzp, bzm;
         if (rxp == rc && rxm == rc && ryp == rc && rym == rc && rzp == rc && rzm == rc) {
             // away from the interface: 2 / (rc + rc) is exactly 1 / rc, one division
-            bxp = bxm = byp = bym = bzp = bzm = 1.0 / rc;
+            bxp = bxm = byp = bym = bzp = bzm = T(1) / rc;
         } else {
-            bxp = 2.0 / (rxp + rc);
-            bxm = 2.0 / (rc + rxm);
-            byp = 2.0 / (ryp + rc);
-            bym = 2.0 / (rc + rym);
-            bzp = 2.0 / (rzp + rc);
-            bzm = 2.0 / (rc + rzm);
+            bxp = T(2) / (rxp + rc);
+            bxm = T(2) / (rc + rxm);
+            byp = T(2) / (ryp + rc);
+            bym = T(2) / (rc + rym);
+            bzp = T(2) / (rzp + rc);
+            bzm = T(2) / (rc + rzm);
         }
-        double num = bxp * Pc[c + 1] + bxm * Pc[c - 1];
-        double diag = bxp + bxm;
+        T num = bxp * Pc[c + 1] + bxm * Pc[c - 1];
+        T diag = bxp + bxm;
         num += byp * Pc[c + RX] + bym * Pc[c - RX];
         diag += byp + bym;
         num += bzp * Pu[c] + bzm * Pd[c];
         diag += bzp + bzm;
-        return (num - h2 * B[kk & 1][iz]) / diag;
+        return (num - h2 * B[sl.b][iz]) / diag;
     };
     auto step = [&](Stage& S, int k) {
         commit(S, k);
@@ -630,25 +666,27 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const double* __restrict_
         // committed), which keeps the loads unconditional
         fetch(S, k + 2 <= z1 ? k + 2 : z1);
         lds_barrier();
+        const Slots sr = slots(k);
         for (int q = t; q < RedN; q += NT) {
             int y = 1 + q / RedRow;
             int x = 1 + ((i0 + 1 + j0 + y + k) & 1) + 2 * (q % RedRow);
-            P[k & 3][y * RX + x] = update(x, y, k);
+            P[sr.c][y * RX + x] = update(x, y, sr);
         }
         lds_barrier();
         const int kb = k - 1;
         if (kb >= z0 && kb < z1) {
+            const Slots sb = slots(kb);
             const long base = pl(kb) + (long)(j0 + 2) * d.nx + (i0 + 2);
             for (int q = t; q < BlackN; q += NT) {
                 int y = 2 + q / BlackRow, m = q % BlackRow;
                 int par = (i0 + 3 + j0 + y + kb) & 1;
-                double v = update(2 + par + 2 * m, y, kb);
-                double r = P[kb & 3][y * RX + 3 - par + 2 * m];
-                double* o = pout + base + (long)(y - 2) * d.nx + 2 * m;
+                T v = update(2 + par + 2 * m, y, sb);
+                T r = P[sb.c][y * RX + 3 - par + 2 * m];
+                T* o = pout + base + (long)(y - 2) * d.nx + 2 * m;
                 o[par] = v;
                 o[1 - par] = r;
                 if constexpr (DOTS) {
-                    const double* Bk = B[kb & 1] + (y - 1) * ZW;
+                    const T* Bk = B[sb.b] + (y - 1) * ZW;
                     acc_b += Bk[1 + par + 2 * m] * v + Bk[2 - par + 2 * m] * r;
                     if (qv) {
                         const double* qq = qv + base + (long)(y - 2) * d.nx + 2 * m;
@@ -657,7 +695,9 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const double* __restrict_
                 }
             }
         }
-        lds_barrier();
+        // no barrier here: the next step's commit writes the slots of planes
+        // k - 3 (p, rho) and k (b), which this black update does not read,
+        // and its first barrier orders everything after
     };
     // steps z0 - 1 .. z1 in pairs (stage A, stage B); TZ is even
     for (int k = z0 - 1; k <= z1; k += 2) {
@@ -1267,11 +1307,12 @@ __global__ void k_apply_dot(const double* __restrict__ dv, K co, Dims d, double 
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// alpha = (r,z) / (d,q); x += alpha d; r -= alpha q; partial sums of r^2
+// alpha = (r,z) / (d,q); x += alpha d; r -= alpha q; partial sums of r^2;
+// r32 (when not null) = fl32(r), the next float32 preconditioner's right side
 __global__ void k_pcg_xr(double* __restrict__ x, double* __restrict__ r,
                          const double* __restrict__ dv, const double* __restrict__ q, long N,
                          const double* __restrict__ ks, int rz_slot,
-                         double* __restrict__ partial) {
+                         double* __restrict__ partial, float* __restrict__ r32) {
     __shared__ double sh[kBlock];
     const double alpha = ks[rz_slot] / ks[KS_DQ];
     double acc = 0.0;
@@ -1279,6 +1320,7 @@ __global__ void k_pcg_xr(double* __restrict__ x, double* __restrict__ r,
         x[c] += alpha * dv[c];
         double rv = r[c] - alpha * q[c];
         r[c] = rv;
+        if (r32) r32[c] = (float)rv;
         acc += rv * rv;
     }
     double s = block_reduce_sum(acc, sh);
@@ -1733,6 +1775,33 @@ __global__ __launch_bounds__(CG_NT) void k_residual_rho(const double* __restrict
     }
 }
 
+// For the learned guess's judge: r = b - A x with partial sums of r^2, b^2 and
+// x (b + r) per block
+template <int DIM, class K>
+__global__ void k_energy(const double* __restrict__ x, const double* __restrict__ b, K co, Dims d,
+                         double inv_h2, double* __restrict__ partial_r2, double* __restrict__ partial_b2,
+                         double* __restrict__ partial_e) {
+    __shared__ double sh[kBlock];
+    double ar = 0.0, ab = 0.0, ae = 0.0;
+    const int N = (int)d.cells(), nx = d.nx, ny = d.ny;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < N; c += gridDim.x * blockDim.x) {
+        const int i = c % nx;
+        const int rr = c / nx;
+        const Nb n = neighbours(d, i, rr % ny, rr / ny, DIM);
+        const double bv = b[c];
+        const double rv = bv - apply_row<double, DIM>(x, co, n) * inv_h2;
+        ar += rv * rv;
+        ab += bv * bv;
+        ae += x[c] * (bv + rv);
+    }
+    double v = block_reduce_sum(ar, sh);
+    if (threadIdx.x == 0) partial_r2[blockIdx.x] = v;
+    v = block_reduce_sum(ab, sh);
+    if (threadIdx.x == 0) partial_b2[blockIdx.x] = v;
+    v = block_reduce_sum(ae, sh);
+    if (threadIdx.x == 0) partial_e[blockIdx.x] = v;
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // tile of the density sweep: 64 x 8 cells, 512 threads (2 workgroups per CU)
@@ -1773,15 +1842,27 @@ static void launch_fused(Level& L, T* pin, T* pout, hipStream_t st, bool finest,
         if (L.rho) {
             const int rx = L.d.nx / kRTX, ry = L.d.ny / kRTY, rz = L.d.nz / L.rtz;
             if (dots)
-                hipLaunchKernelGGL((k_rbgs_fused_rho<kRTX, kRTY, kRNT, false, true>), dim3(rx * ry * rz),
+                hipLaunchKernelGGL((k_rbgs_fused_rho<double, kRTX, kRTY, kRNT, false, true>), dim3(rx * ry * rz),
                                    dim3(kRNT), 0, st, pin, pout, A.b, L.rho, L.d, h2, L.rtz, rx, ry, rz,
                                    L.dots_q, L.dots_part);
             else if (zero)
-                hipLaunchKernelGGL((k_rbgs_fused_rho<kRTX, kRTY, kRNT, true>), dim3(rx * ry * rz), dim3(kRNT),
-                                   0, st, pin, pout, A.b, L.rho, L.d, h2, L.rtz, rx, ry, rz);
+                hipLaunchKernelGGL((k_rbgs_fused_rho<double, kRTX, kRTY, kRNT, true>), dim3(rx * ry * rz),
+                                   dim3(kRNT), 0, st, pin, pout, A.b, L.rho, L.d, h2, L.rtz, rx, ry, rz);
             else
-                hipLaunchKernelGGL((k_rbgs_fused_rho<kRTX, kRTY, kRNT, false>), dim3(rx * ry * rz), dim3(kRNT),
-                                   0, st, pin, pout, A.b, L.rho, L.d, h2, L.rtz, rx, ry, rz);
+                hipLaunchKernelGGL((k_rbgs_fused_rho<double, kRTX, kRTY, kRNT, false>), dim3(rx * ry * rz),
+                                   dim3(kRNT), 0, st, pin, pout, A.b, L.rho, L.d, h2, L.rtz, rx, ry, rz);
+            return;
+        }
+    } else {
+        if (L.rho32) {
+            // the float32 cycle's finest level from the float32 densities
+            const int rx = L.d.nx / kRTX, ry = L.d.ny / kRTY, rz = L.d.nz / L.rtz;
+            if (zero)
+                hipLaunchKernelGGL((k_rbgs_fused_rho<float, kRTX, kRTY, kRNT, true>), dim3(rx * ry * rz),
+                                   dim3(kRNT), 0, st, pin, pout, A.b, L.rho32, L.d, h2, L.rtz, rx, ry, rz);
+            else
+                hipLaunchKernelGGL((k_rbgs_fused_rho<float, kRTX, kRTY, kRNT, false>), dim3(rx * ry * rz),
+                                   dim3(kRNT), 0, st, pin, pout, A.b, L.rho32, L.d, h2, L.rtz, rx, ry, rz);
             return;
         }
     }
@@ -1816,6 +1897,51 @@ static T* smooth(Level& L, T* cur, int nu, hipStream_t st, bool finest, bool zer
         }
     }
     return cur;
+}
+
+// the coarse right side B.b = R (A.b - A_L cur) of level L (mean of the 2^dim
+// children of the fine residual)
+template <typename T>
+static void restrict_residual(Level& L, Level& C, const T* cur, hipStream_t st, bool fin) {
+    LevelT<T>& A = lvl<T>(L);
+    LevelT<T>& B = lvl<T>(C);
+    T inv_h2 = (T)(1.0 / (L.d.h * L.d.h));
+    long nc = C.d.cells();
+    {
+        ProfScope ps(sizeof(T) == 8 ? IB_PROF_RESTRICT64 : IB_PROF_RESTRICT32, st, fin);
+        const CoefArrays<T> co{A.beta[0], A.beta[1], L.d.dim == 3 ? A.beta[2] : A.beta[1]};
+        const dim3 g64(L.d.nx / 64, L.d.ny / 2, L.d.nz / 2);
+        bool done = false;
+        if constexpr (sizeof(T) == 8) {
+            if (L.rho && L.d.ny % CG_TY == 0 && L.rtz > 0 && L.rtz % 2 == 0) {
+                // tiled z-march (nx % 64 == 0 where rho is set)
+                const int tx = L.d.nx / CG_TX, ty = L.d.ny / CG_TY, tz = L.d.nz / L.rtz;
+                hipLaunchKernelGGL(k_resrestrict_rho, dim3(tx * ty * tz), dim3(CG_NT), 0, st, cur, A.b, L.rho,
+                                   L.d, inv_h2, L.rtz, tx, ty, tz, B.b);
+                done = true;
+            } else if (L.rho) {  // set only where nx % 64 == 0 in 3D
+                hipLaunchKernelGGL((k_residual_restrict64<double, CoefRho>), g64, dim3(kBlock), 0, st,
+                                   cur, A.b, CoefRho{L.rho}, L.d, inv_h2, B.b);
+                done = true;
+            }
+        } else {
+            if (L.rho32 && L.d.nx % 64 == 0) {
+                hipLaunchKernelGGL((k_residual_restrict64<float, CoefRhoF>), g64, dim3(kBlock), 0, st, cur, A.b,
+                                   CoefRhoF{L.rho32}, L.d, inv_h2, B.b);
+                done = true;
+            }
+        }
+        if (done) {
+        } else if (L.d.dim == 2)
+            hipLaunchKernelGGL((k_residual_restrict<T, 2>), dim3(grid_for(nc)), dim3(kBlock), 0, st,
+                               cur, A.b, co, L.d, inv_h2, B.b);
+        else if (L.d.nx % 64 == 0)
+            hipLaunchKernelGGL((k_residual_restrict64<T, CoefArrays<T>>), g64, dim3(kBlock), 0, st,
+                               cur, A.b, co, L.d, inv_h2, B.b);
+        else
+            hipLaunchKernelGGL((k_residual_restrict<T, 3>), dim3(grid_for(nc)), dim3(kBlock), 0, st,
+                               cur, A.b, co, L.d, inv_h2, B.b);
+    }
 }
 
 // zero_start: level l starts from p = 0; on levels with the single-pass
@@ -1857,37 +1983,8 @@ static void vcycle(mg_handle* m, int l, hipStream_t st, bool zero_start) {
     LevelT<T>& B = lvl<T>(C);
     bool fin = l == 0;
     T* cur = smooth<T>(L, A.p, m->o.nu1, st, fin, zero_start);
-    T inv_h2 = (T)(1.0 / (L.d.h * L.d.h));
-    long nc = C.d.cells();
-    {
-        ProfScope ps(sizeof(T) == 8 ? IB_PROF_RESTRICT64 : IB_PROF_RESTRICT32, st, fin);
-        const CoefArrays<T> co{A.beta[0], A.beta[1], L.d.dim == 3 ? A.beta[2] : A.beta[1]};
-        const dim3 g64(L.d.nx / 64, L.d.ny / 2, L.d.nz / 2);
-        bool done = false;
-        if constexpr (sizeof(T) == 8) {
-            if (L.rho && L.d.ny % CG_TY == 0 && L.rtz > 0 && L.rtz % 2 == 0) {
-                // tiled z-march (nx % 64 == 0 where rho is set)
-                const int tx = L.d.nx / CG_TX, ty = L.d.ny / CG_TY, tz = L.d.nz / L.rtz;
-                hipLaunchKernelGGL(k_resrestrict_rho, dim3(tx * ty * tz), dim3(CG_NT), 0, st, cur, A.b, L.rho,
-                                   L.d, inv_h2, L.rtz, tx, ty, tz, B.b);
-                done = true;
-            } else if (L.rho) {  // set only where nx % 64 == 0 in 3D
-                hipLaunchKernelGGL((k_residual_restrict64<double, CoefRho>), g64, dim3(kBlock), 0, st,
-                                   cur, A.b, CoefRho{L.rho}, L.d, inv_h2, B.b);
-                done = true;
-            }
-        }
-        if (done) {
-        } else if (L.d.dim == 2)
-            hipLaunchKernelGGL((k_residual_restrict<T, 2>), dim3(grid_for(nc)), dim3(kBlock), 0, st,
-                               cur, A.b, co, L.d, inv_h2, B.b);
-        else if (L.d.nx % 64 == 0)
-            hipLaunchKernelGGL((k_residual_restrict64<T, CoefArrays<T>>), g64, dim3(kBlock), 0, st,
-                               cur, A.b, co, L.d, inv_h2, B.b);
-        else
-            hipLaunchKernelGGL((k_residual_restrict<T, 3>), dim3(grid_for(nc)), dim3(kBlock), 0, st,
-                               cur, A.b, co, L.d, inv_h2, B.b);
-    }
+    const long nc = C.d.cells();
+    restrict_residual<T>(L, C, cur, st, fin);
     if (l + 1 != last && !C.fused)
         hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(nc)), dim3(kBlock), 0, st, B.p, nc, (T)0);
     vcycle<T>(m, l + 1, st, true);
@@ -1909,6 +2006,7 @@ static void vcycle(mg_handle* m, int l, hipStream_t st, bool zero_start) {
 }
 
 static int red_blocks(long N) { return (int)std::min<long>(kRed, (long)grid_for(N)); }
+
 
 // z-range per workgroup of the density kernels (64 x 8 tiles) on a 3D level
 // the single-pass smoother takes, or 0 where they do not apply
@@ -2206,10 +2304,11 @@ static int update_hierarchy(mg_handle* m, const double* const beta[3], const dou
     }
     if (m->o.precision == MG_MIXED)
         for (auto& L : m->lv) {
+            L.rho32 = nullptr;
             if (L.rho) {
-                hipLaunchKernelGGL((k_beta_from_rho<3, float>), dim3(grid_for(L.d.cells())), dim3(kBlock),
-                                   0, st, CoefRho{L.rho}, L.d, L.f32.beta[0], L.f32.beta[1],
-                                   L.f32.beta[2]);
+                hipLaunchKernelGGL(k_cast_f32, dim3(grid_for(L.d.cells())), dim3(kBlock), 0, st, L.rho,
+                                   L.f32.beta[0], L.d.cells());
+                L.rho32 = L.f32.beta[0];
                 continue;
             }
             for (int e = 0; e < dim; ++e)
@@ -2240,6 +2339,51 @@ int mg_takes_density(const mg_handle* m) { return m && density_direct(m) ? 1 : 0
 
 void mg_hint_zero_guess(mg_handle* m) {
     if (m) m->x_zero = true;
+}
+
+// For a start x (NULL: zero): ||b - A x|| / ||b|| and the energy functional
+// E(x) = x . (b + r(x)), r = b - A x. With K = -A (positive definite on
+// zero-mean vectors) and K p = -b, E(x) = ||x - p||_K^2 - ||p||_K^2: of two
+// starts, the smaller E has the smaller error in the energy norm, the norm in
+// which conjugate gradients and multigrid converge. E(0) = 0; constants do
+// not change E (b has zero sum). Syncs.
+int mg_energy(mg_handle* m, const double* b, const double* x, double* rel, double* E, hipStream_t st) {
+    IB_CHECK(m && b && rel && E, IB_EINVAL, "mg_energy: null argument");
+    IB_CHECK(m->coeffs_ready, IB_EINVAL, "mg_energy: no coefficients yet");
+    if (!x) {
+        *rel = 1.0;
+        *E = 0.0;
+        return IB_OK;
+    }
+    Level& L = m->lv[0];
+    const long N = L.d.cells();
+    const int nb = red_blocks(N);
+    const double inv_h2 = 1.0 / (L.d.h * L.d.h);
+    double* pr = m->red;
+    double* pb = m->red + kRed;
+    double* pe = m->red + 2 * kRed;
+    const CoefArrays<double> co{L.f64.beta[0], L.f64.beta[1], L.d.dim == 3 ? L.f64.beta[2] : L.f64.beta[1]};
+    if (L.rho)
+        hipLaunchKernelGGL((k_energy<3, CoefRho>), dim3(nb), dim3(kBlock), 0, st, x, b, CoefRho{L.rho}, L.d,
+                           inv_h2, pr, pb, pe);
+    else if (L.d.dim == 2)
+        hipLaunchKernelGGL((k_energy<2, CoefArrays<double>>), dim3(nb), dim3(kBlock), 0, st, x, b, co, L.d,
+                           inv_h2, pr, pb, pe);
+    else
+        hipLaunchKernelGGL((k_energy<3, CoefArrays<double>>), dim3(nb), dim3(kBlock), 0, st, x, b, co, L.d,
+                           inv_h2, pr, pb, pe);
+    double* fin = m->red + 3 * kRed + 4;
+    IB_TRY(device_sum(pr, nb, fin, st));
+    IB_TRY(device_sum(pb, nb, fin + 1, st));
+    IB_TRY(device_sum(pe, nb, fin + 2, st));
+    IB_HIP(hipMemcpyAsync(m->host + 4, fin, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    IB_HIP(hipStreamSynchronize(st));
+    prof_drain();
+    const double bn = std::sqrt(m->host[5]);
+    *rel = bn > 0.0 ? std::sqrt(m->host[4]) / bn : 0.0;
+    *E = m->host[6];
+    IB_HIP(hipGetLastError());
+    return IB_OK;
 }
 
 extern "C" int mg_update_coeffs(mg_handle* m, const double* const beta[3], void* stream) {
@@ -2338,10 +2482,13 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
     }
     double rel = std::sqrt(m->host[0]) / bnorm;
     S->rel_res0 = S->rel_res = rel;
-    // z = V(r) from zero
+    // z = V(r) from zero; fl32(r) is left by the r update of the previous
+    // iteration unless r was formed anew (the first iteration, a true residual)
+    bool r32_ready = false;
     auto precond = [&]() {
         if (mixed) {
-            hipLaunchKernelGGL(k_cast_f32, g1, blk, 0, st, m->kr, L0.f32.b, N);
+            if (!r32_ready) hipLaunchKernelGGL(k_cast_f32, g1, blk, 0, st, m->kr, L0.f32.b, N);
+            r32_ready = false;
             if (!L0.fused) hipLaunchKernelGGL((k_fill<float>), g1, blk, 0, st, L0.f32.p, N, 0.0f);
             vcycle<float>(m, 0, st, true);
         } else {
@@ -2442,7 +2589,9 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
                                    inv_h2, m->kq, pa);
             IB_TRY(device_sum(pa, nb, m->ks + KS_DQ, st));
         }
-        hipLaunchKernelGGL(k_pcg_xr, gr, blk, 0, st, x, m->kr, m->kd, m->kq, N, m->ks, slot, pa);
+        hipLaunchKernelGGL(k_pcg_xr, gr, blk, 0, st, x, m->kr, m->kd, m->kq, N, m->ks, slot, pa,
+                           mixed ? L0.f32.b : nullptr);
+        r32_ready = mixed;
         IB_TRY(device_sum(pa, nb, m->ks + KS_RR, st));
         ++it;
         S->cycles = it;
@@ -2460,6 +2609,7 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
             // is decided on the true residual, which replaces r (and the
             // recursion goes on from it) when it has not reached rtol yet
             IB_TRY(residual(false));
+            r32_ready = false;
             IB_HIP(hipMemcpyAsync(m->host, m->ks + KS_RR, sizeof(double), hipMemcpyDeviceToHost, st));
             IB_HIP(hipStreamSynchronize(st));
             prof_drain();
@@ -2473,7 +2623,7 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
             double rho = std::pow(rel / rel_check, 1.0 / (double)(it - last_check));
             if (rho < 0.9) {
                 int need = (int)std::ceil(std::log(rtol / rel) / std::log(rho));
-                skip = std::max(0, need - 2);
+                skip = std::min(std::max(0, need - 2), kMaxSkip);
             }
         }
         rel_check = rel;
@@ -2560,7 +2710,7 @@ extern "C" int mg_solve(mg_handle* m, const double* b, double* p, double rtol, i
             double rho = std::pow(rel / rel_check, 1.0 / (double)(cycles - last_check));
             if (rho < 0.9) {
                 int need = (int)std::ceil(std::log(rtol / rel) / std::log(rho));
-                skip = std::max(0, need - 2);
+                skip = std::min(std::max(0, need - 2), kMaxSkip);
             }
         }
         rel_check = rel;

@@ -508,6 +508,8 @@ extern "C" int ib_nn_create(const ib_grid* g, ib_nn** out) {
 
 extern "C" void ib_nn_destroy(ib_nn* n) { nn_free(n); }
 
+long nn_cells(const ib_nn* nn) { return nn ? nn->N : 0; }
+
 // params: host float32, per layer W[co][ci][(kz)][ky][kx] (unpadded channel counts) then b[co]
 extern "C" int ib_nn_set_params(ib_nn* n, const float* params, int count) {
     IB_CHECK(n && params, IB_EINVAL, "ib_nn_set_params: null argument");

@@ -83,7 +83,7 @@ class Outputs(C.Structure):
     _fields_ = [("p", C.c_void_p), ("u", C.c_void_p * 3), ("U", C.c_void_p), ("H", C.c_void_p),
                 ("F", C.c_void_p * 3), ("fs_host", C.c_void_p), ("b", C.c_void_p),
                 ("stats", MgStats), ("guess_accepted", C.c_int), ("guess_rel_res", C.c_double),
-                ("prev_rel_res", C.c_double)]
+                ("prev_rel_res", C.c_double), ("guess_energy", C.c_double), ("prev_energy", C.c_double)]
 
 
 class FlowStats(C.Structure):
@@ -455,7 +455,8 @@ class Context:
         rc = self.lib.project_step(self.ptr, mg.ptr, C.byref(prm), C.byref(st), C.byref(o), _stream())
         out["stats"] = o.stats.as_dict()
         out["guess"] = dict(accepted=o.guess_accepted, rel_res=o.guess_rel_res,
-                            prev_rel_res=o.prev_rel_res)
+                            prev_rel_res=o.prev_rel_res,
+                            energy=o.guess_energy, prev_energy=o.prev_energy)
         if rc == IB_ENOTCONV and params.get("allow_notconv", False):
             return out
         _check(rc)
@@ -563,7 +564,8 @@ class Axisym:
         except Exception:
             pass
 
-    def project_step(self, mg: "Multigrid", params: dict, u_star, X_host, p_prev=None, out=None):
+    def project_step(self, mg: "Multigrid", params: dict, u_star, X_host, p_prev=None, out=None,
+                     nn: "Network" = None):
         """One axisymmetric projection step; X_host (numpy, N x 2) is advanced and
         relocated in place. Returns the outputs dict (half-plane fields)."""
         import torch
@@ -574,10 +576,12 @@ class Axisym:
         st.surf = Surface()
         st.surf.n_markers = int(X_host.shape[0])
         st.X_host = _hptr(X_host)
-        st.nn = None
+        st.nn = nn.ptr if nn is not None else None
         out, o = Context._outputs(self, out, int(X_host.shape[0]))
         rc = self.lib.axi_project_step(self.ptr, mg.ptr, C.byref(prm), C.byref(st), C.byref(o), _stream())
         out["stats"] = o.stats.as_dict()
+        out["guess"] = dict(accepted=o.guess_accepted, rel_res=o.guess_rel_res, prev_rel_res=o.prev_rel_res,
+                            energy=o.guess_energy, prev_energy=o.prev_energy)
         _check(rc)
         return out
 
@@ -597,7 +601,8 @@ class Axisym:
                                     _stream()))
         return u_star, fs.as_dict()
 
-    def flow_step(self, mg: "Multigrid", params: dict, u, X_host, p_prev=None, out=None):
+    def flow_step(self, mg: "Multigrid", params: dict, u, X_host, p_prev=None, out=None,
+                  nn: "Network" = None):
         """One full axisymmetric step (params as Context.flow_step)."""
         import torch
         prm = Context._params(params, p_prev)
@@ -608,12 +613,14 @@ class Axisym:
         st.surf = Surface()
         st.surf.n_markers = int(X_host.shape[0])
         st.X_host = _hptr(X_host)
-        st.nn = None
+        st.nn = nn.ptr if nn is not None else None
         out, o = Context._outputs(self, out, int(X_host.shape[0]))
         fs = FlowStats()
         rc = self.lib.axi_flow_step(self.ptr, mg.ptr, C.byref(prm), C.byref(fp), C.byref(st), C.byref(o),
                                     C.byref(fs), _stream())
         out["stats"] = o.stats.as_dict()
+        out["guess"] = dict(accepted=o.guess_accepted, rel_res=o.guess_rel_res, prev_rel_res=o.prev_rel_res,
+                            energy=o.guess_energy, prev_energy=o.prev_energy)
         out["flow"] = fs.as_dict()
         _check(rc)
         return out

@@ -42,6 +42,22 @@ def jittered_circle(n: int, R: float, amp: float, seed: int, centre=(0.5, 0.5)) 
     return np.stack([centre[0] + r * np.cos(th), centre[1] + r * np.sin(th)], axis=1)
 
 
+def axis_symmetric_jittered_circle(n: int, R: float, amp: float, seed: int, centre) -> np.ndarray:
+    """Markers on a circle centred on the axis x = centre[0] with radius
+    R(1 + amp xi_k), xi uniform in (-1, 1) from PCG64(seed), mirrored about the
+    axis (xi of theta and pi - theta equal; n even): a meridian curve of a
+    body of revolution."""
+    assert n % 2 == 0
+    rng = np.random.default_rng(seed)
+    xi = rng.uniform(-1.0, 1.0, size=n)
+    k = np.arange(n)
+    mirror = (n // 2 - k) % n
+    xi = np.where(k <= mirror, xi, xi[mirror])
+    th = 2.0 * np.pi * k / n
+    r = R * (1.0 + amp * xi)
+    return np.stack([centre[0] + r * np.cos(th), centre[1] + r * np.sin(th)], axis=1)
+
+
 def mode_shape(n: int, R: float, eps: float = 0.1, centre=(0.5, 0.5), seed: int | None = None,
                extra_amp: float = 0.0) -> np.ndarray:
     """r(theta) = R(1 + eps cos 2theta [+ sum_m a_m cos(m theta + phi_m), m = 3..6])."""

@@ -7,9 +7,13 @@ hierarchy (mg_update_coeffs) and against the oracle.
 * equal fixed cycles: p bitwise that of the stored-face path -- the finest
   kernels form the same coefficients and do the same arithmetic -- on grids
   where the kernels read rho directly (128^3; 256 x 128 x 128) and on grids
-  where the faces are formed into the handle (2D; 32^3), in FP64 and mixed
-  precision; the residual history to 1e-13 (the tiled density kernels sum
-  their norms per tile);
+  where the faces are formed into the handle (2D; 32^3), in FP64 and (2D)
+  mixed precision; the residual history to 1e-13 (the tiled density kernels
+  sum their norms per tile);
+* mixed precision where the kernels read rho directly: the float32 cycle
+  forms its finest coefficients in float32 from float32 densities, against
+  the oracle's mixed solver given the densities (and the stored-face path
+  against it without them), 1e-8 after three cycles;
 * the density path against the oracle's multigrid at equal cycles (1e-11).
 """
 import numpy as np
@@ -67,7 +71,6 @@ CASES = [
     ((64, 64), 4, "fp64"),
     ((32, 32, 32), 4, "fp64"),
     ((128, 128, 128), 4, "fp64"),
-    ((128, 128, 128), 4, "mixed"),
     ((128, 128, 256), 2, "fp64"),
     ((64, 64), 4, "mixed"),
 ]
@@ -127,6 +130,35 @@ def test_density_path_vs_oracle_128(ib):
     print(f"density path vs oracle at 128^3, 3 cycles: rel L2 {err:.2e}")
     assert err <= 1e-11
     assert abs(st["rel_res"] - hist[-1]) <= 1e-6 * hist[-1]
+
+
+def test_density_path_mixed_vs_oracle_128(ib):
+    shape = (128, 128, 128)
+    n = shape
+    h = 1.0 / 128
+    Hn = _drop_H(shape, 4)
+    b = W.random_cells(n, 3, 1.0, seed=63)
+    b -= b.mean()
+    ctx = ib.Context(3, n, h, max_markers=16)
+    rho = ctx.density(dev(Hn), 1.0, 1e-3)
+    beta = ctx.coefficients(dev(Hn), 1.0, 1e-3)
+    rho_o = poisson.density(Hn, 1.0, 1e-3)
+    beta_o = poisson.face_beta(rho_o)
+    for mode in ("density", "faces"):
+        mg = ib.Multigrid(3, n, h, precision=ib.MG_MIXED)
+        if mode == "density":
+            mg.update_density(rho)
+        else:
+            mg.update_coeffs(beta)
+        p = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        st = mg.solve(dev(b), p, fixed_cycles=3)
+        mg.close()
+        po, _, hist = poisson.mg_solve_mixed(b, beta_o, h, fixed_cycles=3,
+                                             rho=rho_o if mode == "density" else None)
+        err = float(np.linalg.norm(host(p) - po) / np.linalg.norm(po))
+        print(f"mixed {mode} path vs oracle at 128^3, 3 cycles: rel L2 {err:.2e}")
+        assert err <= 1e-8
+        assert abs(st["rel_res"] - hist[-1]) <= 1e-3 * hist[-1]
 
 
 def test_density_null_and_errors(ib):

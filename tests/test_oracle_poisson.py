@@ -126,6 +126,36 @@ def test_mixed_precision_reaches_fp64_tolerance(shape):
     assert np.linalg.norm(p32 - pt) <= 1e-7 * np.linalg.norm(pt)
 
 
+def test_mixed_precision_from_float32_densities():
+    """The float32 cycle whose finest coefficients are formed in float32 from
+    float32 densities: uniform density gives exactly 1/fl32(rho) on every face,
+    a face across a jump is 2 / (fl32(rho_L) + fl32(rho_R)) rounded once, and
+    the defect correction still reaches 1e-10 with an answer within the FP64
+    error bound."""
+    r = np.full((4, 4), 0.3)
+    for f in poisson.face_beta_f32(r):
+        assert f.dtype == np.float32
+        assert np.all(f == np.float32(1.0) / np.float32(0.3))
+    r[1, 2] = 1e-3
+    fx = poisson.face_beta_f32(r)[0]
+    assert fx[1, 2] == np.float32(2.0) / np.float32(np.float32(1e-3) + np.float32(0.3))
+    shape = (32, 32, 32)
+    g = np.indices(shape)
+    rr = np.sqrt(sum(((g[a] + 0.5) / 32 - 0.5) ** 2 for a in range(3)))
+    rho = poisson.density(np.clip((0.3 - rr) * 32 / 3 + 0.5, 0.0, 1.0), 1.0, 1e-3)
+    beta = poisson.face_beta(rho)
+    h = 1.0 / 32
+    b = W.random_cells(shape, 3, 1.0, seed=33)
+    b -= b.mean()
+    pt, _, _ = poisson.mg_solve(b, beta, h, rtol=1e-14, max_cycles=200)
+    p32, c32, h32 = poisson.mg_solve_mixed(b, beta, h, rtol=1e-10, rho=rho)
+    assert h32[-1] <= 1e-10
+    assert np.linalg.norm(p32 - pt) <= 1e-7 * np.linalg.norm(pt)
+    pk, ck, hk = poisson.mg_pcg(b, beta, h, rtol=1e-10, mixed=True, rho=rho)
+    assert hk[-1] <= 1e-10 and ck < c32
+    assert np.linalg.norm(pk - pt) <= 1e-7 * np.linalg.norm(pt)
+
+
 def test_projection_makes_velocity_divergence_free():
     shape = (32, 32)
     h = 1.0 / 32
