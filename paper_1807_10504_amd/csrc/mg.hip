@@ -640,18 +640,18 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
         const T rc = Rc[c];
         const T rxp = Rc[c + 1], rxm = Rc[c - 1], ryp = Rc[c + RX], rym = Rc[c - RX];
         const T rzp = R[sl.u][c], rzm = R[sl.d][c];
-        T bxp, bxm, byp, bym, bzp, bzm;
         if (rxp == rc && rxm == rc && ryp == rc && rym == rc && rzp == rc && rzm == rc) {
-            // away from the interface: 2 / (rc + rc) is exactly 1 / rc, one division
-            bxp = bxm = byp = bym = bzp = bzm = T(1) / rc;
-        } else {
-            bxp = T(2) / (rxp + rc);
-            bxm = T(2) / (rc + rxm);
-            byp = T(2) / (ryp + rc);
-            bym = T(2) / (rc + rym);
-            bzp = T(2) / (rzp + rc);
-            bzm = T(2) / (rc + rzm);
+            // away from the interface every face is 1 / rc and the update is
+            // (sum of the six neighbours - h^2 b rc) / 6: no division
+            const T sn = ((Pc[c + 1] + Pc[c - 1]) + (Pc[c + RX] + Pc[c - RX])) + (Pu[c] + Pd[c]);
+            return (sn - h2 * B[sl.b][iz] * rc) * T(1.0 / 6.0);
         }
+        const T bxp = T(2) / (rxp + rc);
+        const T bxm = T(2) / (rc + rxm);
+        const T byp = T(2) / (ryp + rc);
+        const T bym = T(2) / (rc + rym);
+        const T bzp = T(2) / (rzp + rc);
+        const T bzm = T(2) / (rc + rzm);
         T num = bxp * Pc[c + 1] + bxm * Pc[c - 1];
         T diag = bxp + bxm;
         num += byp * Pc[c + RX] + bym * Pc[c - RX];

@@ -42,19 +42,19 @@ def jittered_circle(n: int, R: float, amp: float, seed: int, centre=(0.5, 0.5)) 
     return np.stack([centre[0] + r * np.cos(th), centre[1] + r * np.sin(th)], axis=1)
 
 
-def axis_symmetric_jittered_circle(n: int, R: float, amp: float, seed: int, centre) -> np.ndarray:
-    """Markers on a circle centred on the axis x = centre[0] with radius
-    R(1 + amp xi_k), xi uniform in (-1, 1) from PCG64(seed), mirrored about the
-    axis (xi of theta and pi - theta equal; n even): a meridian curve of a
-    body of revolution."""
-    assert n % 2 == 0
+def axis_symmetric_shape(n: int, R: float, amp: float, seed: int, centre, modes=range(2, 7)) -> np.ndarray:
+    """Markers on the meridian curve of a body of revolution about the axis
+    x = centre[0]: r(psi) = R(1 + sum_m a_m cos(m psi)), psi the angle from the
+    axis direction, a_m uniform in (-amp, amp) from PCG64(seed) for the modes
+    given (even in psi, so the curve is mirror-symmetric about the axis)."""
     rng = np.random.default_rng(seed)
-    xi = rng.uniform(-1.0, 1.0, size=n)
-    k = np.arange(n)
-    mirror = (n // 2 - k) % n
-    xi = np.where(k <= mirror, xi, xi[mirror])
-    th = 2.0 * np.pi * k / n
-    r = R * (1.0 + amp * xi)
+    a = rng.uniform(-amp, amp, size=len(list(modes)))
+    th = 2.0 * np.pi * np.arange(n) / n
+    psi = th - 0.5 * np.pi
+    r = np.ones(n)
+    for am, m in zip(a, modes):
+        r = r + am * np.cos(m * psi)
+    r = R * r
     return np.stack([centre[0] + r * np.cos(th), centre[1] + r * np.sin(th)], axis=1)
 
 

@@ -4,12 +4,12 @@ hierarchy (mg_update_coeffs) and against the oracle.
 * ib_density: rho bitwise the oracle's rho_out + (rho_in - rho_out) H (NumPy
   rounds the multiply and the add separately, as the library does), and
   2 / (rho_c + rho_{c-e_d}) bitwise the faces of ib_coefficients;
-* equal fixed cycles: p bitwise that of the stored-face path -- the finest
-  kernels form the same coefficients and do the same arithmetic -- on grids
-  where the kernels read rho directly (128^3; 256 x 128 x 128) and on grids
-  where the faces are formed into the handle (2D; 32^3), in FP64 and (2D)
-  mixed precision; the residual history to 1e-13 (the tiled density kernels
-  sum their norms per tile);
+* equal fixed cycles: p of the density path against the stored-face path,
+  bitwise on grids where the faces are formed into the handle (2D; 32^3; FP64
+  and 2D mixed) and to 1e-13 where the kernels read rho directly (128^3;
+  256 x 128 x 128: the sweep updates cells away from the interface without a
+  division); the residual history to 1e-13 (the tiled density kernels sum
+  their norms per tile);
 * mixed precision where the kernels read rho directly: the float32 cycle
   forms its finest coefficients in float32 from float32 densities, against
   the oracle's mixed solver given the densities (and the stored-face path
@@ -104,7 +104,13 @@ def test_density_path_bitwise_vs_faces(ib, shape, nc, prec):
     (p0, s0, r0), (p1, s1, r1) = out
     diff = np.max(np.abs(p0 - p1))
     print(f"{shape} {prec}: max |p_faces - p_density| = {diff:.3e}, rel_res {s1['rel_res']:.3e}")
-    assert np.array_equal(p0, p1)
+    if dim == 3 and min(shape) >= 128:
+        # the tiled density sweep updates cells away from the interface
+        # without a division, (sum of neighbours - h^2 b rho) / 6: equal to
+        # the stored-face sweep to rounding
+        assert np.linalg.norm(p0 - p1) <= 1e-13 * np.linalg.norm(p0)
+    else:
+        assert np.array_equal(p0, p1)
     # the norms of the tiled density kernels are summed per tile, those of the
     # stored-face kernels per grid-stride block: equal up to summation order
     assert np.allclose(s0["hist"], s1["hist"], rtol=1e-13, atol=0)
