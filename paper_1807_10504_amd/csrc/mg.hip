@@ -330,6 +330,10 @@ constexpr int kFXLoads = (kFXN + kBlock - 1) / kBlock;
 constexpr int kFYLoads = (kFYN + kBlock - 1) / kBlock;
 constexpr int kFZLoads = (kFZN + kBlock - 1) / kBlock;
 
+// two adjacent values of T in one memory operation
+template <typename T>
+using Vec2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+
 // barrier for LDS traffic only: global loads issued before it stay in flight
 __device__ __forceinline__ void lds_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
@@ -359,6 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
     const int i0 = tx * kFTX - 2, j0 = ty * kFTY - 2;
     const int z0 = zc * TZ, z1 = z0 + TZ;
     const long plane = (long)d.nx * d.ny;
+    using V2 = Vec2<T>;
     const int t = threadIdx.x;
     // tile origins are at least -2 and regions end within one period
     auto gofs = [&](int x, int y) { return wrap_near(j0 + y, d.ny) * d.nx + wrap_near(i0 + x, d.nx); };
@@ -494,9 +499,12 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
                 int par = (i0 + 3 + j0 + y + kb) & 1;
                 T v = update(2 + par + 2 * m, y, kb);
                 T r = P[kb & 3][y * kFRX + 3 - par + 2 * m];
-                T* o = pout + base + (long)(y - 2) * d.nx + 2 * m;
-                o[par] = v;
-                o[1 - par] = r;
+                // the black cell and the red one beside it in one 2-wide store
+                // (the pair starts at an even x: 16-byte aligned in float64)
+                V2 w2;
+                w2.x = par ? r : v;
+                w2.y = par ? v : r;
+                *reinterpret_cast<V2*>(pout + base + (long)(y - 2) * d.nx + 2 * m) = w2;
             }
         }
         // the next commit overwrites the plane below k - 1
@@ -532,15 +540,20 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
     // region of p and rho: the tile and a two-cell halo; b: the one-cell ring
     constexpr int RX = TX + 4, RY = TY + 4, RN = RX * RY;
     constexpr int ZW = RX - 2, ZN = ZW * (RY - 2);
-    constexpr int NL = (RN + NT - 1) / NT, NZL = (ZN + NT - 1) / NT;
+    // p and rho move in pairs of cells along x (the region starts at an even x
+    // and RX is even, so pair q is cells 2q, 2q + 1 of the region and a pair
+    // never straddles the periodic seam)
+    constexpr int RN2 = RN / 2;
+    static_assert(RX % 2 == 0 && TX % 2 == 0, "the region must split into pairs along x");
+    constexpr int NL = (RN2 + NT - 1) / NT, NZL = (ZN + NT - 1) / NT;
     constexpr int RedRow = (RX - 2) / 2, RedN = RedRow * (RY - 2);
     constexpr int BlackRow = TX / 2, BlackN = BlackRow * TY;
     static_assert(!DOTS || sizeof(T) == 8, "the inner products are taken in the float64 sweep");
     // rings of five planes of p and rho and three of b: the black update of
     // plane k - 1 reads planes k - 2 .. k while the next step already stages
     // plane k + 2 (and b of k + 1), so no barrier separates them
-    __shared__ T P[5][RN];
-    __shared__ T R[5][RN];
+    __shared__ __align__(16) T P[5][RN];
+    __shared__ __align__(16) T R[5][RN];
     __shared__ T B[3][ZN];
     __shared__ double red[DOTS ? 2 * (NT / 64) : 1];
     double acc_b = 0.0, acc_q = 0.0;
@@ -554,11 +567,12 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
     const int i0 = tx * TX - 2, j0 = ty * TY - 2;
     const int z0 = zc * TZ, z1 = z0 + TZ;
     const long plane = (long)d.nx * d.ny;
+    using V2 = Vec2<T>;
     const int t = threadIdx.x;
     // tile origins are at least -2 and regions end within one period
     auto gofs = [&](int x, int y) { return wrap_near(j0 + y, d.ny) * d.nx + wrap_near(i0 + x, d.nx); };
     // every lane issues every load (slots past a region re-read its first
-    // cell and are not stored), so the loads are unconditional and the
+    // cell or pair and are not stored), so the loads are unconditional and the
     // compiler's wait counts are exact: a commit waits for its own plane only,
     // not for the loads and stores issued after it
     int gp[NL], gz[NZL];
@@ -566,8 +580,8 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
 #pragma unroll
     for (int s = 0; s < NL; ++s) {
         int q = t + s * NT;
-        vp[s] = q < RN;
-        gp[s] = vp[s] ? gofs(q % RX, q / RX) : gofs(0, 0);
+        vp[s] = q < RN2;
+        gp[s] = vp[s] ? gofs(2 * (q % (RX / 2)), q / (RX / 2)) : gofs(0, 0);
     }
 #pragma unroll
     for (int s = 0; s < NZL; ++s) {
@@ -580,15 +594,22 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
     // two register stages, alternating: the planes of step k, p(k+1), rho(k+1)
     // and b(k), are loaded two steps ahead
     struct Stage {
-        T p[NL], r[NL], b[NZL];
+        V2 p[NL], r[NL];
+        T b[NZL];
     };
     Stage SA, SB;
+    auto ld2 = [](const T* a) { return *reinterpret_cast<const V2*>(a); };
     auto fetch = [&](Stage& S, int k) {
         long bp = pl(k + 1), bk = pl(k);
 #pragma unroll
         for (int s = 0; s < NL; ++s) {
-            S.p[s] = ZERO ? T(0) : pin[bp + gp[s]];
-            S.r[s] = rho[bp + gp[s]];
+            if constexpr (ZERO) {
+                S.p[s].x = T(0);
+                S.p[s].y = T(0);
+            } else {
+                S.p[s] = ld2(pin + bp + gp[s]);
+            }
+            S.r[s] = ld2(rho + bp + gp[s]);
         }
 #pragma unroll
         for (int s = 0; s < NZL; ++s) S.b[s] = bb[bk + gz[s]];
@@ -602,9 +623,9 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
         T* Bk = B[s3(k)];
 #pragma unroll
         for (int s = 0; s < NL; ++s)
-            if (s * NT + NT <= RN || vp[s]) {
-                Pn[t + s * NT] = S.p[s];
-                Rn[t + s * NT] = S.r[s];
+            if (s * NT + NT <= RN2 || vp[s]) {
+                *reinterpret_cast<V2*>(Pn + 2 * (t + s * NT)) = S.p[s];
+                *reinterpret_cast<V2*>(Rn + 2 * (t + s * NT)) = S.r[s];
             }
 #pragma unroll
         for (int s = 0; s < NZL; ++s)
@@ -615,10 +636,13 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
 #pragma unroll
         for (int s = 0; s < NL; ++s)
             if (vp[s]) {
-                P[s5(z0 - 2)][t + s * NT] = ZERO ? T(0) : pin[a + gp[s]];
-                P[s5(z0 - 1)][t + s * NT] = ZERO ? T(0) : pin[a1 + gp[s]];
-                R[s5(z0 - 2)][t + s * NT] = rho[a + gp[s]];
-                R[s5(z0 - 1)][t + s * NT] = rho[a1 + gp[s]];
+                const int c2 = 2 * (t + s * NT);
+                for (int e = 0; e < 2; ++e) {
+                    P[s5(z0 - 2)][c2 + e] = ZERO ? T(0) : pin[a + gp[s] + e];
+                    P[s5(z0 - 1)][c2 + e] = ZERO ? T(0) : pin[a1 + gp[s] + e];
+                    R[s5(z0 - 2)][c2 + e] = rho[a + gp[s] + e];
+                    R[s5(z0 - 1)][c2 + e] = rho[a1 + gp[s] + e];
+                }
             }
     }
     fetch(SA, z0 - 1);
@@ -682,9 +706,12 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
                 int par = (i0 + 3 + j0 + y + kb) & 1;
                 T v = update(2 + par + 2 * m, y, sb);
                 T r = P[sb.c][y * RX + 3 - par + 2 * m];
-                T* o = pout + base + (long)(y - 2) * d.nx + 2 * m;
-                o[par] = v;
-                o[1 - par] = r;
+                // the black cell and the red one beside it in one 2-wide store
+                // (the pair starts at an even x: 16-byte aligned in float64)
+                V2 w2;
+                w2.x = par ? r : v;
+                w2.y = par ? v : r;
+                *reinterpret_cast<V2*>(pout + base + (long)(y - 2) * d.nx + 2 * m) = w2;
                 if constexpr (DOTS) {
                     const T* Bk = B[sb.b] + (y - 1) * ZW;
                     acc_b += Bk[1 + par + 2 * m] * v + Bk[2 - par + 2 * m] * r;
