@@ -518,13 +518,15 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
 }
 
 // The same single-pass sweep on a finest level given by cell densities: the
-// workgroup stages p and rho on the tile plus the two-cell halo and b on the
-// one-cell ring, and forms each face coefficient 2 / (rho_hi + rho_lo) where
-// it is used (in T: float64, or float32 from the float32 densities of the
-// mixed-precision cycle, 16 bytes per cell). That is 32 bytes of memory traffic per cell (p read and
-// written, b, rho) instead of 48 with three stored face arrays; the update is
-// the one above, operand for operand, so the results are bitwise those of
-// the stored-face sweep.
+// workgroup stages p and rho on the tile plus the two-cell halo in LDS and
+// forms each face coefficient 2 / (rho_hi + rho_lo) where it is used (in T:
+// float64, or float32 from the float32 densities of the mixed-precision
+// cycle). b is read once per update straight into the registers of the lane
+// that makes it (two steps ahead, like p and rho), so LDS holds p and rho
+// only: 65 KB for a 64 x 8 float64 tile, two workgroups per CU. That is 32
+// bytes of memory traffic per cell (p read and written, b, rho) instead of 48
+// with three stored face arrays; the update is the one above, operand for
+// operand, so the results are bitwise those of the stored-face sweep.
 // DOTS: the sweep also leaves per-workgroup partial sums of (b, p_new) and,
 // when qv is not null, (qv, p_new) in part[bid] and part[nwg + bid] (the
 // flexible-CG inner products of the preconditioned residual, taken from the
@@ -537,24 +539,26 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
                                                        T h2, int TZ, int ntx, int nty,
                                                        int nzc, const double* __restrict__ qv = nullptr,
                                                        double* __restrict__ part = nullptr) {
-    // region of p and rho: the tile and a two-cell halo; b: the one-cell ring
+    // region of p and rho: the tile and a two-cell halo
     constexpr int RX = TX + 4, RY = TY + 4, RN = RX * RY;
-    constexpr int ZW = RX - 2, ZN = ZW * (RY - 2);
     // p and rho move in pairs of cells along x (the region starts at an even x
     // and RX is even, so pair q is cells 2q, 2q + 1 of the region and a pair
     // never straddles the periodic seam)
     constexpr int RN2 = RN / 2;
     static_assert(RX % 2 == 0 && TX % 2 == 0, "the region must split into pairs along x");
-    constexpr int NL = (RN2 + NT - 1) / NT, NZL = (ZN + NT - 1) / NT;
+    constexpr int NL = (RN2 + NT - 1) / NT;
+    // red updates: the one-cell ring region, half of each row; black updates:
+    // the tile, one lane per pair of cells (its black cell and the red one
+    // beside it, which it also writes)
     constexpr int RedRow = (RX - 2) / 2, RedN = RedRow * (RY - 2);
     constexpr int BlackRow = TX / 2, BlackN = BlackRow * TY;
+    constexpr int NR = (RedN + NT - 1) / NT, NB = (BlackN + NT - 1) / NT;
     static_assert(!DOTS || sizeof(T) == 8, "the inner products are taken in the float64 sweep");
-    // rings of five planes of p and rho and three of b: the black update of
-    // plane k - 1 reads planes k - 2 .. k while the next step already stages
-    // plane k + 2 (and b of k + 1), so no barrier separates them
+    // rings of five planes: the black update of plane k - 1 reads planes
+    // k - 2 .. k while the next step already stages plane k + 2, so no
+    // barrier separates them
     __shared__ __align__(16) T P[5][RN];
     __shared__ __align__(16) T R[5][RN];
-    __shared__ T B[3][ZN];
     __shared__ double red[DOTS ? 2 * (NT / 64) : 1];
     double acc_b = 0.0, acc_q = 0.0;
     const int nw = ntx * nty * nzc;
@@ -572,22 +576,35 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
     // tile origins are at least -2 and regions end within one period
     auto gofs = [&](int x, int y) { return wrap_near(j0 + y, d.ny) * d.nx + wrap_near(i0 + x, d.nx); };
     // every lane issues every load (slots past a region re-read its first
-    // cell or pair and are not stored), so the loads are unconditional and the
-    // compiler's wait counts are exact: a commit waits for its own plane only,
+    // cell or pair and are not used), so the loads are unconditional and the
+    // compiler's wait counts are exact: a step waits for its own plane only,
     // not for the loads and stores issued after it
-    int gp[NL], gz[NZL];
-    bool vp[NL], vz[NZL];
+    int gp[NL];
+    bool vp[NL];
 #pragma unroll
     for (int s = 0; s < NL; ++s) {
         int q = t + s * NT;
         vp[s] = q < RN2;
         gp[s] = vp[s] ? gofs(2 * (q % (RX / 2)), q / (RX / 2)) : gofs(0, 0);
     }
+    // b of a lane's red cell (row ry, x = 1 + e + 2 c with e the parity of the
+    // plane's first red cell in that row) and of its black pair (tile cells,
+    // never across the seam)
+    int gr[NR][2], er[NR], gb[NB];
 #pragma unroll
-    for (int s = 0; s < NZL; ++s) {
+    for (int s = 0; s < NR; ++s) {
         int q = t + s * NT;
-        vz[s] = q < ZN;
-        gz[s] = vz[s] ? gofs(1 + q % ZW, 1 + q / ZW) : gofs(1, 1);
+        q = q < RedN ? q : 0;
+        const int y = 1 + q / RedRow, c = q % RedRow;
+        er[s] = (i0 + 1 + j0 + y) & 1;
+        gr[s][0] = gofs(1 + 2 * c, y);
+        gr[s][1] = gofs(2 + 2 * c, y);
+    }
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+        int q = t + s * NT;
+        q = q < BlackN ? q : 0;
+        gb[s] = (j0 + 2 + q / BlackRow) * d.nx + (i0 + 2) + 2 * (q % BlackRow);
     }
     // planes z0 - 2 .. z1 + 2 lie within one period of the box
     auto pl = [&](int k) { return (long)wrap_near(k, d.nz) * plane; };
@@ -595,7 +612,8 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
     // and b(k), are loaded two steps ahead
     struct Stage {
         V2 p[NL], r[NL];
-        T b[NZL];
+        T br[NR];
+        V2 bk[NB];
     };
     Stage SA, SB;
     auto ld2 = [](const T* a) { return *reinterpret_cast<const V2*>(a); };
@@ -612,24 +630,21 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
             S.r[s] = ld2(rho + bp + gp[s]);
         }
 #pragma unroll
-        for (int s = 0; s < NZL; ++s) S.b[s] = bb[bk + gz[s]];
+        for (int s = 0; s < NR; ++s) S.br[s] = bb[bk + gr[s][(er[s] + k) & 1]];
+#pragma unroll
+        for (int s = 0; s < NB; ++s) S.bk[s] = ld2(bb + bk + gb[s]);
     };
     // ring slots; planes k >= z0 - 2 >= -2
     auto s5 = [](int k) { return (k + 10) % 5; };
-    auto s3 = [](int k) { return (k + 9) % 3; };
     auto commit = [&](const Stage& S, int k) {
         T* Pn = P[s5(k + 1)];
         T* Rn = R[s5(k + 1)];
-        T* Bk = B[s3(k)];
 #pragma unroll
         for (int s = 0; s < NL; ++s)
             if (s * NT + NT <= RN2 || vp[s]) {
                 *reinterpret_cast<V2*>(Pn + 2 * (t + s * NT)) = S.p[s];
                 *reinterpret_cast<V2*>(Rn + 2 * (t + s * NT)) = S.r[s];
             }
-#pragma unroll
-        for (int s = 0; s < NZL; ++s)
-            if (s * NT + NT <= ZN || vz[s]) Bk[t + s * NT] = S.b[s];
     };
     {
         long a = pl(z0 - 2), a1 = pl(z0 - 1);
@@ -649,14 +664,13 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
     // keep stage A's loads ahead of stage B's (the wait counts assume that order)
     __builtin_amdgcn_sched_barrier(0);
     fetch(SB, z0);
-    // plane slots of kk - 1, kk, kk + 1 and b's slot of kk
+    // plane slots of kk - 1, kk, kk + 1
     struct Slots {
-        int d, c, u, b;
+        int d, c, u;
     };
-    auto slots = [&](int kk) { return Slots{s5(kk - 1), s5(kk), s5(kk + 1), s3(kk)}; };
-    auto update = [&](int x, int y, const Slots& sl) {
+    auto slots = [&](int kk) { return Slots{s5(kk - 1), s5(kk), s5(kk + 1)}; };
+    auto update = [&](int x, int y, const Slots& sl, T bv) {
         const int c = y * RX + x;
-        const int iz = (y - 1) * ZW + (x - 1);
         const T* Pc = P[sl.c];
         const T* Pd = P[sl.d];
         const T* Pu = P[sl.u];
@@ -668,7 +682,7 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
             // away from the interface every face is 1 / rc and the update is
             // (sum of the six neighbours - h^2 b rc) / 6: no division
             const T sn = ((Pc[c + 1] + Pc[c - 1]) + (Pc[c + RX] + Pc[c - RX])) + (Pu[c] + Pd[c]);
-            return (sn - h2 * B[sl.b][iz] * rc) * T(1.0 / 6.0);
+            return (sn - h2 * bv * rc) * T(1.0 / 6.0);
         }
         const T bxp = T(2) / (rxp + rc);
         const T bxm = T(2) / (rc + rxm);
@@ -682,49 +696,70 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
         diag += byp + bym;
         num += bzp * Pu[c] + bzm * Pd[c];
         diag += bzp + bzm;
-        return (num - h2 * B[sl.b][iz]) / diag;
+        return (num - h2 * bv) / diag;
     };
+    // b pairs of the plane whose black cells the next step updates
+    V2 bcar[NB];
+#pragma unroll
+    for (int s = 0; s < NB; ++s) bcar[s] = V2{};
     auto step = [&](Stage& S, int k) {
         commit(S, k);
+        T brk[NR];
+        V2 bkk[NB];
+#pragma unroll
+        for (int s = 0; s < NR; ++s) brk[s] = S.br[s];
+#pragma unroll
+        for (int s = 0; s < NB; ++s) bkk[s] = S.bk[s];
         // in flight for two steps; past the range it re-reads plane z1 (not
         // committed), which keeps the loads unconditional
         fetch(S, k + 2 <= z1 ? k + 2 : z1);
         lds_barrier();
         const Slots sr = slots(k);
-        for (int q = t; q < RedN; q += NT) {
-            int y = 1 + q / RedRow;
-            int x = 1 + ((i0 + 1 + j0 + y + k) & 1) + 2 * (q % RedRow);
-            P[sr.c][y * RX + x] = update(x, y, sr);
+#pragma unroll
+        for (int s = 0; s < NR; ++s) {
+            const int q = t + s * NT;
+            if (q < RedN) {
+                int y = 1 + q / RedRow;
+                int x = 1 + ((i0 + 1 + j0 + y + k) & 1) + 2 * (q % RedRow);
+                P[sr.c][y * RX + x] = update(x, y, sr, brk[s]);
+            }
         }
         lds_barrier();
         const int kb = k - 1;
         if (kb >= z0 && kb < z1) {
             const Slots sb = slots(kb);
             const long base = pl(kb) + (long)(j0 + 2) * d.nx + (i0 + 2);
-            for (int q = t; q < BlackN; q += NT) {
-                int y = 2 + q / BlackRow, m = q % BlackRow;
-                int par = (i0 + 3 + j0 + y + kb) & 1;
-                T v = update(2 + par + 2 * m, y, sb);
-                T r = P[sb.c][y * RX + 3 - par + 2 * m];
-                // the black cell and the red one beside it in one 2-wide store
-                // (the pair starts at an even x: 16-byte aligned in float64)
-                V2 w2;
-                w2.x = par ? r : v;
-                w2.y = par ? v : r;
-                *reinterpret_cast<V2*>(pout + base + (long)(y - 2) * d.nx + 2 * m) = w2;
-                if constexpr (DOTS) {
-                    const T* Bk = B[sb.b] + (y - 1) * ZW;
-                    acc_b += Bk[1 + par + 2 * m] * v + Bk[2 - par + 2 * m] * r;
-                    if (qv) {
-                        const double* qq = qv + base + (long)(y - 2) * d.nx + 2 * m;
-                        acc_q += qq[par] * v + qq[1 - par] * r;
+#pragma unroll
+            for (int s = 0; s < NB; ++s) {
+                const int q = t + s * NT;
+                if (q < BlackN) {
+                    int y = 2 + q / BlackRow, m = q % BlackRow;
+                    int par = (i0 + 3 + j0 + y + kb) & 1;
+                    const T bv = par ? bcar[s].y : bcar[s].x;
+                    T v = update(2 + par + 2 * m, y, sb, bv);
+                    T r = P[sb.c][y * RX + 3 - par + 2 * m];
+                    // the black cell and the red one beside it in one 2-wide store
+                    // (the pair starts at an even x: 16-byte aligned in float64)
+                    V2 w2;
+                    w2.x = par ? r : v;
+                    w2.y = par ? v : r;
+                    *reinterpret_cast<V2*>(pout + base + (long)(y - 2) * d.nx + 2 * m) = w2;
+                    if constexpr (DOTS) {
+                        const T br2 = par ? bcar[s].x : bcar[s].y;
+                        acc_b += bv * v + br2 * r;
+                        if (qv) {
+                            const double* qq = qv + base + (long)(y - 2) * d.nx + 2 * m;
+                            acc_q += qq[par] * v + qq[1 - par] * r;
+                        }
                     }
                 }
             }
         }
-        // no barrier here: the next step's commit writes the slots of planes
-        // k - 3 (p, rho) and k (b), which this black update does not read,
-        // and its first barrier orders everything after
+#pragma unroll
+        for (int s = 0; s < NB; ++s) bcar[s] = bkk[s];
+        // no barrier here: the next step's commit writes the slots of plane
+        // k - 3, which this black update does not read, and its first barrier
+        // orders everything after
     };
     // steps z0 - 1 .. z1 in pairs (stage A, stage B); TZ is even
     for (int k = z0 - 1; k <= z1; k += 2) {
