@@ -45,7 +45,7 @@ SWEEP_BYTES_F32 = 24.0
 # (FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000, the factors an elementwise copy of
 # known size reads), recorded with the kernel they were taken on; any other
 # kernel reports null
-TRAFFIC = {"k_rbgs_fused_rho<64,8,512>": (636.7e6, "profiles/rbgs_fused_rho_256cube_hbm_counters.txt")}
+TRAFFIC = {}
 
 
 def log(msg):
@@ -1095,7 +1095,7 @@ def main():
         nl, ms = r64["prof"]["sweep64_rho"]
         bytes_per_launch = SWEEP_BYTES_F64 * N
         min_bytes = SWEEP_BYTES_F64_RHO * N
-        kname = "k_rbgs_fused_rho<64,8,512>"
+        kname = "k_rbgs_fused_rho<32,16,512>"
     elif r64["prof"]["sweep64"][0]:
         nl, ms = r64["prof"]["sweep64"]
         bytes_per_launch = SWEEP_BYTES_F64 * N

@@ -523,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
 // float64, or float32 from the float32 densities of the mixed-precision
 // cycle). b is read once per update straight into the registers of the lane
 // that makes it (two steps ahead, like p and rho), so LDS holds p and rho
-// only: 65 KB for a 64 x 8 float64 tile, two workgroups per CU. That is 32
+// only: 58 KB for a 32 x 16 float64 tile, two workgroups per CU. That is 32
 // bytes of memory traffic per cell (p read and written, b, rho) instead of 48
 // with three stored face arrays; the update is the one above, operand for
 // operand, so the results are bitwise those of the stored-face sweep.
@@ -1866,8 +1866,9 @@ __global__ void k_energy(const double* __restrict__ x, const double* __restrict_
 
 // ---------------------------------------------------------------------------
 // host side
-// tile of the density sweep: 64 x 8 cells, 512 threads (2 workgroups per CU)
-constexpr int kRTX = 64, kRTY = 8, kRNT = 512;
+// tile of the density sweep: 32 x 16 cells, 512 threads (2 workgroups per
+// CU); its halo region holds 1.41 cells per tile cell against 1.59 for 64 x 8
+constexpr int kRTX = 32, kRTY = 16, kRNT = 512;
 
 template <typename T> LevelT<T>& lvl(Level& L);
 template <> LevelT<double>& lvl<double>(Level& L) { return L.f64; }
@@ -2070,11 +2071,12 @@ static void vcycle(mg_handle* m, int l, hipStream_t st, bool zero_start) {
 static int red_blocks(long N) { return (int)std::min<long>(kRed, (long)grid_for(N)); }
 
 
-// z-range per workgroup of the density kernels (64 x 8 tiles) on a 3D level
-// the single-pass smoother takes, or 0 where they do not apply
+// z-range per workgroup of the density kernels (the sweep's 32 x 16 tiles
+// and the 64 x 8 tiles of the CG and residual kernels, as many of either) on a
+// 3D level the single-pass smoother takes, or 0 where they do not apply
 static int density_rtz(const Dims& d) {
     if (d.dim != 3 || d.nx % kFTX != 0 || d.ny % kFTY != 0 || d.nz < 32 || d.nz % 2 != 0 ||
-        d.cells() < 128L * 128 * 128 || d.nx % kRTX != 0)
+        d.cells() < 128L * 128 * 128 || d.nx % kRTX != 0 || d.ny % kRTY != 0)
         return 0;
     long rtiles = (long)(d.nx / kRTX) * (d.ny / kRTY);
     int rtz = d.nz;
@@ -2591,8 +2593,10 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
     const int cg_wgs = cg_tx * cg_ty * cg_tz;
     IB_CHECK(!fused || cg_wgs <= kRed, IB_EINVAL, "mg_solve: too many workgroups for the partial sums");
     // the inner products of z = V(r) come from the last post-smoothing sweep
-    // of the finest level (the same tiling: cg_wgs workgroups)
+    // of the finest level (sweep_wgs partial sums of each)
     const bool fold = fused && !mixed && L0.fused && m->o.nu2 >= 1;
+    const int sweep_wgs = fold ? (L0.d.nx / kRTX) * (L0.d.ny / kRTY) * (L0.d.nz / L0.rtz) : 0;
+    IB_CHECK(sweep_wgs <= kRed, IB_EINVAL, "mg_solve: too many sweep workgroups for the partial sums");
     int it = 0, slot = KS_RZ0;
     int skip = 0, last_check = 0, checks = 0;
     double rel_check = rel;
@@ -2616,8 +2620,8 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
         const int rz_old = slot;
         if (fold) {
             const int next = it == 0 ? slot : (slot == KS_RZ0 ? KS_RZ1 : KS_RZ0);
-            IB_TRY(device_sum(pa, cg_wgs, m->ks + next, st));
-            if (it > 0) IB_TRY(device_sum(pa + cg_wgs, cg_wgs, m->ks + KS_QZ, st));
+            IB_TRY(device_sum(pa, sweep_wgs, m->ks + next, st));
+            if (it > 0) IB_TRY(device_sum(pa + sweep_wgs, sweep_wgs, m->ks + KS_QZ, st));
             slot = next;
         } else if (it == 0) {
             IB_TRY(dots(nullptr, slot));
