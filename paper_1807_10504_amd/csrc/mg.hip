@@ -527,11 +527,12 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
 // bytes of memory traffic per cell (p read and written, b, rho) instead of 48
 // with three stored face arrays; the update is the one above, operand for
 // operand, so the results are bitwise those of the stored-face sweep.
-// DOTS: the sweep also leaves per-workgroup partial sums of (b, p_new) and,
-// when qv is not null, (qv, p_new) in part[bid] and part[nwg + bid] (the
-// flexible-CG inner products of the preconditioned residual, taken from the
-// values the black lanes write).
-template <typename T, int TX, int TY, int NT, bool ZERO, bool DOTS = false>
+// DOTS (1 or 2): the sweep also leaves per-workgroup partial sums of
+// (b, p_new) and, for DOTS = 2, (qv, p_new) in part[bid] and part[nwg + bid]
+// (the flexible-CG inner products of the preconditioned residual, taken from
+// the values the black lanes write); qv is read in pairs two steps ahead,
+// like b.
+template <typename T, int TX, int TY, int NT, bool ZERO, int DOTS = 0>
 __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin,
                                                        T* __restrict__ pout,
                                                        const T* __restrict__ bb,
@@ -553,7 +554,8 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
     constexpr int RedRow = (RX - 2) / 2, RedN = RedRow * (RY - 2);
     constexpr int BlackRow = TX / 2, BlackN = BlackRow * TY;
     constexpr int NR = (RedN + NT - 1) / NT, NB = (BlackN + NT - 1) / NT;
-    static_assert(!DOTS || sizeof(T) == 8, "the inner products are taken in the float64 sweep");
+    static_assert(DOTS == 0 || sizeof(T) == 8, "the inner products are taken in the float64 sweep");
+    constexpr int NQ = DOTS == 2 ? NB : 0;
     // rings of five planes: the black update of plane k - 1 reads planes
     // k - 2 .. k while the next step already stages plane k + 2, so no
     // barrier separates them
@@ -608,17 +610,23 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
     }
     // planes z0 - 2 .. z1 + 2 lie within one period of the box
     auto pl = [&](int k) { return (long)wrap_near(k, d.nz) * plane; };
-    // two register stages, alternating: the planes of step k, p(k+1), rho(k+1)
-    // and b(k), are loaded two steps ahead
+    // two register stages, alternating. A stage holds what step k reads from
+    // memory: p and rho of plane k + 1 (committed to LDS at the step's start,
+    // loaded two steps ahead), b of its red cells on plane k and the b (and
+    // qv) pairs of its black cells on plane k - 1 (used after the step's
+    // barriers, loaded at the end of step k - 2). Every value is consumed
+    // before the stage is loaded again, so no loaded register is copied and
+    // no wait drains the loads issued after it.
     struct Stage {
         V2 p[NL], r[NL];
         T br[NR];
         V2 bk[NB];
+        double2 qk[NQ > 0 ? NQ : 1];
     };
     Stage SA, SB;
     auto ld2 = [](const T* a) { return *reinterpret_cast<const V2*>(a); };
-    auto fetch = [&](Stage& S, int k) {
-        long bp = pl(k + 1), bk = pl(k);
+    auto fetch_pr = [&](Stage& S, int k) {
+        const long bp = pl(k + 1);
 #pragma unroll
         for (int s = 0; s < NL; ++s) {
             if constexpr (ZERO) {
@@ -629,10 +637,15 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
             }
             S.r[s] = ld2(rho + bp + gp[s]);
         }
+    };
+    auto fetch_b = [&](Stage& S, int k) {
+        const long bk = pl(k), bq = pl(k - 1);
 #pragma unroll
         for (int s = 0; s < NR; ++s) S.br[s] = bb[bk + gr[s][(er[s] + k) & 1]];
 #pragma unroll
-        for (int s = 0; s < NB; ++s) S.bk[s] = ld2(bb + bk + gb[s]);
+        for (int s = 0; s < NB; ++s) S.bk[s] = ld2(bb + bq + gb[s]);
+#pragma unroll
+        for (int s = 0; s < NQ; ++s) S.qk[s] = *reinterpret_cast<const double2*>(qv + bq + gb[s]);
     };
     // ring slots; planes k >= z0 - 2 >= -2
     auto s5 = [](int k) { return (k + 10) % 5; };
@@ -660,10 +673,12 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
                 }
             }
     }
-    fetch(SA, z0 - 1);
+    fetch_pr(SA, z0 - 1);
+    fetch_b(SA, z0 - 1);
     // keep stage A's loads ahead of stage B's (the wait counts assume that order)
     __builtin_amdgcn_sched_barrier(0);
-    fetch(SB, z0);
+    fetch_pr(SB, z0);
+    fetch_b(SB, z0);
     // plane slots of kk - 1, kk, kk + 1
     struct Slots {
         int d, c, u;
@@ -698,21 +713,12 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
         diag += bzp + bzm;
         return (num - h2 * bv) / diag;
     };
-    // b pairs of the plane whose black cells the next step updates
-    V2 bcar[NB];
-#pragma unroll
-    for (int s = 0; s < NB; ++s) bcar[s] = V2{};
     auto step = [&](Stage& S, int k) {
         commit(S, k);
-        T brk[NR];
-        V2 bkk[NB];
-#pragma unroll
-        for (int s = 0; s < NR; ++s) brk[s] = S.br[s];
-#pragma unroll
-        for (int s = 0; s < NB; ++s) bkk[s] = S.bk[s];
-        // in flight for two steps; past the range it re-reads plane z1 (not
-        // committed), which keeps the loads unconditional
-        fetch(S, k + 2 <= z1 ? k + 2 : z1);
+        // past the range the loads re-read plane z1 (not used), which keeps
+        // them unconditional
+        const int kn = k + 2 <= z1 ? k + 2 : z1;
+        fetch_pr(S, kn);
         lds_barrier();
         const Slots sr = slots(k);
 #pragma unroll
@@ -721,7 +727,7 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
             if (q < RedN) {
                 int y = 1 + q / RedRow;
                 int x = 1 + ((i0 + 1 + j0 + y + k) & 1) + 2 * (q % RedRow);
-                P[sr.c][y * RX + x] = update(x, y, sr, brk[s]);
+                P[sr.c][y * RX + x] = update(x, y, sr, S.br[s]);
             }
         }
         lds_barrier();
@@ -735,7 +741,7 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
                 if (q < BlackN) {
                     int y = 2 + q / BlackRow, m = q % BlackRow;
                     int par = (i0 + 3 + j0 + y + kb) & 1;
-                    const T bv = par ? bcar[s].y : bcar[s].x;
+                    const T bv = par ? S.bk[s].y : S.bk[s].x;
                     T v = update(2 + par + 2 * m, y, sb, bv);
                     T r = P[sb.c][y * RX + 3 - par + 2 * m];
                     // the black cell and the red one beside it in one 2-wide store
@@ -744,19 +750,19 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
                     w2.x = par ? r : v;
                     w2.y = par ? v : r;
                     *reinterpret_cast<V2*>(pout + base + (long)(y - 2) * d.nx + 2 * m) = w2;
-                    if constexpr (DOTS) {
-                        const T br2 = par ? bcar[s].x : bcar[s].y;
+                    if constexpr (DOTS > 0) {
+                        const T br2 = par ? S.bk[s].x : S.bk[s].y;
                         acc_b += bv * v + br2 * r;
-                        if (qv) {
-                            const double* qq = qv + base + (long)(y - 2) * d.nx + 2 * m;
-                            acc_q += qq[par] * v + qq[1 - par] * r;
-                        }
+                    }
+                    if constexpr (DOTS == 2) {
+                        const double qb = par ? S.qk[s].y : S.qk[s].x;
+                        const double qr = par ? S.qk[s].x : S.qk[s].y;
+                        acc_q += qb * v + qr * r;
                     }
                 }
             }
         }
-#pragma unroll
-        for (int s = 0; s < NB; ++s) bcar[s] = bkk[s];
+        fetch_b(S, kn);
         // no barrier here: the next step's commit writes the slots of plane
         // k - 3, which this black update does not read, and its first barrier
         // orders everything after
@@ -766,7 +772,7 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
         step(SA, k);
         step(SB, k + 1);
     }
-    if constexpr (DOTS) {
+    if constexpr (DOTS > 0) {
         // fixed-order workgroup sums
         for (int off = 32; off > 0; off >>= 1) {
             acc_b += __shfl_xor(acc_b, off);
@@ -1435,19 +1441,22 @@ __global__ void k_pcg_dir(double* __restrict__ dv, const TZ* __restrict__ z, lon
 // z-march as the sweep: a workgroup owns a CG_TX x CG_TY tile and a z-range,
 // stages the new d and rho of each plane on the tile plus a one-cell ring in
 // LDS (three-plane rings), and loads the planes two steps ahead. The
-// arithmetic of each q is that of apply_row_rho, operand for operand.
+// arithmetic of each q is that of apply_row_rho, operand for operand. FIRST
+// (the first iteration, dnew = z) is a template argument, so that every step
+// issues the same loads and the waits for a staged plane never drain the
+// loads issued after it.
 constexpr int CG_TX = 64, CG_TY = 8, CG_NT = 512;
 constexpr int CG_RX = CG_TX + 2, CG_RY = CG_TY + 2, CG_RN = CG_RX * CG_RY;
 constexpr int CG_NL = (CG_RN + CG_NT - 1) / CG_NT;
 
-template <typename TZ>
+template <typename TZ, bool FIRST>
 __global__ __launch_bounds__(CG_NT) void k_cg_dir_apply_rho(const TZ* __restrict__ z,
                                                             const double* __restrict__ d,
                                                             double* __restrict__ dnew,
                                                             const double* __restrict__ rho,
                                                             double* __restrict__ q, Dims dm,
                                                             double inv_h2, const double* __restrict__ ks,
-                                                            int rz_old_slot, int first, int TZr,
+                                                            int rz_old_slot, int TZr,
                                                             int ntx, int nty, int nzc,
                                                             double* __restrict__ partial) {
     __shared__ double DN[3][CG_RN];
@@ -1466,7 +1475,7 @@ __global__ __launch_bounds__(CG_NT) void k_cg_dir_apply_rho(const TZ* __restrict
     const int t = threadIdx.x;
     // beta of the direction update from the device scalars
     double beta = 0.0;
-    if (!first) {
+    if (!FIRST) {
         const double rz = ks[rz_old_slot];
         const double alpha = rz / ks[KS_DQ];
         beta = -alpha * ks[KS_QZ] / rz;
@@ -1483,17 +1492,19 @@ __global__ __launch_bounds__(CG_NT) void k_cg_dir_apply_rho(const TZ* __restrict
         gp[s] = vp[s] ? gofs(qq % CG_RX, qq / CG_RX) : gofs(0, 0);
     }
     auto pl = [&](int k) { return (long)wrap_near(k, dm.nz) * plane; };
+    // a stage holds z, the old d and rho of a plane as loaded; the new
+    // direction is formed when the plane is committed to LDS
     struct Stage {
-        double dn[CG_NL], r[CG_NL];
+        TZ z[CG_NL];
+        double d[FIRST ? 1 : CG_NL], r[CG_NL];
     };
     Stage SA, SB;
-    // planes are loaded as the new direction d + ... and rho
     auto fetch = [&](Stage& S, int k) {
         const long b = pl(k);
 #pragma unroll
         for (int s = 0; s < CG_NL; ++s) {
-            const double zv = (double)z[b + gp[s]];
-            S.dn[s] = first ? zv : zv + beta * d[b + gp[s]];
+            S.z[s] = z[b + gp[s]];
+            if constexpr (!FIRST) S.d[s] = d[b + gp[s]];
             S.r[s] = rho[b + gp[s]];
         }
     };
@@ -1501,7 +1512,13 @@ __global__ __launch_bounds__(CG_NT) void k_cg_dir_apply_rho(const TZ* __restrict
 #pragma unroll
         for (int s = 0; s < CG_NL; ++s)
             if (s * CG_NT + CG_NT <= CG_RN || vp[s]) {
-                DN[(k + 3) % 3][t + s * CG_NT] = S.dn[s];
+                const double zv = (double)S.z[s];
+                double dv;
+                if constexpr (FIRST)
+                    dv = zv;
+                else
+                    dv = zv + beta * S.d[s];
+                DN[(k + 3) % 3][t + s * CG_NT] = dv;
                 RR[(k + 3) % 3][t + s * CG_NT] = S.r[s];
             }
     };
@@ -1615,16 +1632,20 @@ __global__ __launch_bounds__(CG_NT) void k_resrestrict_rho(const double* __restr
         double p[CG_NL], r[CG_NL], b;
     };
     Stage SA, SB;
-    // a stage carries p and rho of plane k + 1 and b of plane k
-    auto fetch = [&](Stage& S, int k) {
+    // a stage carries p and rho of plane k + 1 (committed at the start of step
+    // k, loaded two steps ahead) and b of plane k (used after the step's
+    // barrier, loaded at the end of step k - 2): each value is consumed before
+    // the stage is loaded again, so no loaded register is copied and no wait
+    // drains the loads issued after it
+    auto fetch_pr = [&](Stage& S, int k) {
         const long bp = pl(k + 1);
 #pragma unroll
         for (int s = 0; s < CG_NL; ++s) {
             S.p[s] = p[bp + gp[s]];
             S.r[s] = rho[bp + gp[s]];
         }
-        S.b = bb[pl(k) + own];
     };
+    auto fetch_b = [&](Stage& S, int k) { S.b = bb[pl(k) + own]; };
     auto commit = [&](const Stage& S, int k) {
 #pragma unroll
         for (int s = 0; s < CG_NL; ++s)
@@ -1644,14 +1665,16 @@ __global__ __launch_bounds__(CG_NT) void k_resrestrict_rho(const double* __restr
                 RR[z0 % 3][t + s * CG_NT] = rho[a0 + gp[s]];
             }
     }
-    fetch(SA, z0);
+    fetch_pr(SA, z0);
+    fetch_b(SA, z0);
     __builtin_amdgcn_sched_barrier(0);
-    fetch(SB, z0 + 1);
+    fetch_pr(SB, z0 + 1);
+    fetch_b(SB, z0 + 1);
     auto step = [&](Stage& S, int k) {
         commit(S, k);
-        const double bv = S.b;
-        // past the range the loads re-read plane z1 - 1 (its stage is not committed)
-        fetch(S, k + 2 < z1 ? k + 2 : z1 - 1);
+        // past the range the loads re-read plane z1 - 1 (its stage is not used)
+        const int kn = k + 2 < z1 ? k + 2 : z1 - 1;
+        fetch_pr(S, kn);
         lds_barrier();
         const double* Pc = PP[k % 3];
         const double* Rc = RR[k % 3];
@@ -1673,7 +1696,9 @@ __global__ __launch_bounds__(CG_NT) void k_resrestrict_rho(const double* __restr
         double sv = bxp * (Pc[c + 1] - pc) - bxm * (pc - Pc[c - 1]);
         sv += byp * (Pc[c + CG_RX] - pc) - bym * (pc - Pc[c - CG_RX]);
         sv += bzp * (PP[(k + 1) % 3][c] - pc) - bzm * (pc - PP[(k + 2) % 3][c]);
-        const double r = bv - sv * inv_h2;
+        const double r = S.b - sv * inv_h2;
+        __builtin_amdgcn_sched_barrier(0);
+        fetch_b(S, kn);
         const double rx = r + __shfl_xor(r, 1);
         if ((lx & 1) == 0) XS[k & 1][ly][lx >> 1] = rx;
         lds_barrier();
@@ -1704,7 +1729,7 @@ __global__ __launch_bounds__(CG_NT) void k_resrestrict_rho(const double* __restr
 // workgroup leaves the sums of r^2 and b^2 over its cells in a fixed order in
 // partial_r2[bid] and partial_b2[bid] (when not null). Reads x and rho 1.29
 // times (the ring) and b once.
-template <typename TR>
+template <typename TR, bool STORE>
 __global__ __launch_bounds__(CG_NT) void k_residual_rho(const double* __restrict__ x,
                                                         const double* __restrict__ bb,
                                                         const double* __restrict__ rho, Dims dm,
@@ -1745,16 +1770,20 @@ __global__ __launch_bounds__(CG_NT) void k_residual_rho(const double* __restrict
         double p[CG_NL], r[CG_NL], b;
     };
     Stage SA, SB;
-    // a stage carries x and rho of plane k + 1 and b of plane k
-    auto fetch = [&](Stage& S, int k) {
+    // a stage carries x and rho of plane k + 1 (committed at the start of step
+    // k, loaded two steps ahead) and b of plane k (used after the step's
+    // barrier, loaded at the end of step k - 2): each value is consumed before
+    // the stage is loaded again, so no loaded register is copied and no wait
+    // drains the loads issued after it
+    auto fetch_pr = [&](Stage& S, int k) {
         const long bp = pl(k + 1);
 #pragma unroll
         for (int s = 0; s < CG_NL; ++s) {
             S.p[s] = x[bp + gp[s]];
             S.r[s] = rho[bp + gp[s]];
         }
-        S.b = bb[pl(k) + own];
     };
+    auto fetch_b = [&](Stage& S, int k) { S.b = bb[pl(k) + own]; };
     auto commit = [&](const Stage& S, int k) {
 #pragma unroll
         for (int s = 0; s < CG_NL; ++s)
@@ -1774,15 +1803,17 @@ __global__ __launch_bounds__(CG_NT) void k_residual_rho(const double* __restrict
                 RR[z0 % 3][t + s * CG_NT] = rho[a0 + gp[s]];
             }
     }
-    fetch(SA, z0);
+    fetch_pr(SA, z0);
+    fetch_b(SA, z0);
     __builtin_amdgcn_sched_barrier(0);
-    fetch(SB, z0 + 1);
+    fetch_pr(SB, z0 + 1);
+    fetch_b(SB, z0 + 1);
     double ar = 0.0, ab = 0.0;
     auto step = [&](Stage& S, int k) {
         commit(S, k);
-        const double bv = S.b;
-        // past the range the loads re-read plane z1 - 1 (its stage is not committed)
-        fetch(S, k + 2 < z1 ? k + 2 : z1 - 1);
+        // past the range the loads re-read plane z1 - 1 (its stage is not used)
+        const int kn = k + 2 < z1 ? k + 2 : z1 - 1;
+        fetch_pr(S, kn);
         lds_barrier();
         const double* Pc = PP[k % 3];
         const double* Rc = RR[k % 3];
@@ -1804,10 +1835,15 @@ __global__ __launch_bounds__(CG_NT) void k_residual_rho(const double* __restrict
         double sv = bxp * (Pc[c + 1] - pc) - bxm * (pc - Pc[c - 1]);
         sv += byp * (Pc[c + CG_RX] - pc) - bym * (pc - Pc[c - CG_RX]);
         sv += bzp * (PP[(k + 1) % 3][c] - pc) - bzm * (pc - PP[(k + 2) % 3][c]);
+        const double bv = S.b;
         const double rv = bv - sv * inv_h2;
-        if (r) r[pl(k) + own] = (TR)rv;
+        if constexpr (STORE) r[pl(k) + own] = (TR)rv;
         ar += rv * rv;
         ab += bv * bv;
+        // b is used up before its stage is loaded again (keeps the compiler
+        // from holding two copies of it across the load)
+        __builtin_amdgcn_sched_barrier(0);
+        fetch_b(S, kn);
         // the next commit overwrites plane k - 1's slot
         lds_barrier();
     };
@@ -1904,10 +1940,14 @@ static void launch_fused(Level& L, T* pin, T* pout, hipStream_t st, bool finest,
     if constexpr (sizeof(T) == 8) {
         if (L.rho) {
             const int rx = L.d.nx / kRTX, ry = L.d.ny / kRTY, rz = L.d.nz / L.rtz;
-            if (dots)
-                hipLaunchKernelGGL((k_rbgs_fused_rho<double, kRTX, kRTY, kRNT, false, true>), dim3(rx * ry * rz),
+            if (dots && L.dots_q)
+                hipLaunchKernelGGL((k_rbgs_fused_rho<double, kRTX, kRTY, kRNT, false, 2>), dim3(rx * ry * rz),
                                    dim3(kRNT), 0, st, pin, pout, A.b, L.rho, L.d, h2, L.rtz, rx, ry, rz,
                                    L.dots_q, L.dots_part);
+            else if (dots)
+                hipLaunchKernelGGL((k_rbgs_fused_rho<double, kRTX, kRTY, kRNT, false, 1>), dim3(rx * ry * rz),
+                                   dim3(kRNT), 0, st, pin, pout, A.b, L.rho, L.d, h2, L.rtz, rx, ry, rz,
+                                   nullptr, L.dots_part);
             else if (zero)
                 hipLaunchKernelGGL((k_rbgs_fused_rho<double, kRTX, kRTY, kRNT, true>), dim3(rx * ry * rz),
                                    dim3(kRNT), 0, st, pin, pout, A.b, L.rho, L.d, h2, L.rtz, rx, ry, rz);
@@ -2100,8 +2140,14 @@ template <typename TR>
 static int launch_residual_rho(const Level& L, const double* x, const double* b, TR* r, double* pr,
                                double* pb, hipStream_t st) {
     const int tx = L.d.nx / CG_TX, ty = L.d.ny / CG_TY, tz = L.d.nz / L.rtz;
-    hipLaunchKernelGGL((k_residual_rho<TR>), dim3(tx * ty * tz), dim3(CG_NT), 0, st, x, b, L.rho, L.d,
-                       1.0 / (L.d.h * L.d.h), L.rtz, tx, ty, tz, r, pr, pb);
+    // whether r is stored is fixed at compile time: a store on one path only
+    // would make the loop's waits drain every load in flight
+    if (r)
+        hipLaunchKernelGGL((k_residual_rho<TR, true>), dim3(tx * ty * tz), dim3(CG_NT), 0, st, x, b, L.rho,
+                           L.d, 1.0 / (L.d.h * L.d.h), L.rtz, tx, ty, tz, r, pr, pb);
+    else
+        hipLaunchKernelGGL((k_residual_rho<TR, false>), dim3(tx * ty * tz), dim3(CG_NT), 0, st, x, b, L.rho,
+                           L.d, 1.0 / (L.d.h * L.d.h), L.rtz, tx, ty, tz, r, pr, pb);
     return tx * ty * tz;
 }
 
@@ -2632,14 +2678,22 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
         }
         if (fused) {
             // d = z + beta d, q = A d and (d, q) in one tiled pass
-            if (mixed)
-                hipLaunchKernelGGL((k_cg_dir_apply_rho<float>), dim3(cg_wgs), dim3(CG_NT), 0, st,
+            if (mixed && it == 0)
+                hipLaunchKernelGGL((k_cg_dir_apply_rho<float, true>), dim3(cg_wgs), dim3(CG_NT), 0, st,
                                    L0.f32.p, m->kd, m->kd2, L0.rho, m->kq, L0.d, inv_h2, m->ks, rz_old,
-                                   it == 0 ? 1 : 0, L0.rtz, cg_tx, cg_ty, cg_tz, pa);
-            else
-                hipLaunchKernelGGL((k_cg_dir_apply_rho<double>), dim3(cg_wgs), dim3(CG_NT), 0, st,
+                                   L0.rtz, cg_tx, cg_ty, cg_tz, pa);
+            else if (mixed)
+                hipLaunchKernelGGL((k_cg_dir_apply_rho<float, false>), dim3(cg_wgs), dim3(CG_NT), 0, st,
+                                   L0.f32.p, m->kd, m->kd2, L0.rho, m->kq, L0.d, inv_h2, m->ks, rz_old,
+                                   L0.rtz, cg_tx, cg_ty, cg_tz, pa);
+            else if (it == 0)
+                hipLaunchKernelGGL((k_cg_dir_apply_rho<double, true>), dim3(cg_wgs), dim3(CG_NT), 0, st,
                                    m->kz, m->kd, m->kd2, L0.rho, m->kq, L0.d, inv_h2, m->ks, rz_old,
-                                   it == 0 ? 1 : 0, L0.rtz, cg_tx, cg_ty, cg_tz, pa);
+                                   L0.rtz, cg_tx, cg_ty, cg_tz, pa);
+            else
+                hipLaunchKernelGGL((k_cg_dir_apply_rho<double, false>), dim3(cg_wgs), dim3(CG_NT), 0, st,
+                                   m->kz, m->kd, m->kd2, L0.rho, m->kq, L0.d, inv_h2, m->ks, rz_old,
+                                   L0.rtz, cg_tx, cg_ty, cg_tz, pa);
             std::swap(m->kd, m->kd2);
             IB_TRY(device_sum(pa, cg_wgs, m->ks + KS_DQ, st));
         } else {
