@@ -174,8 +174,10 @@ typedef struct {
     int n_coarsest;  /* cells per axis on the coarsest grid (4); n[d] = n_coarsest * 2^L */
     int krylov;      /* 0: V-cycles; 1: flexible CG preconditioned by one V-cycle */
     int split_coarse; /* 0: the levels of at most 32768 cells (generic restriction) run as
-                         one persistent workgroup per cycle; 1: one launch per phase
-                         (same results bit for bit; for comparison) */
+                         one persistent workgroup per cycle, and on a 3D density level the
+                         prolongation is folded into the first post-smoothing sweep;
+                         1: one launch per phase (same results bit for bit; for
+                         comparison) */
 } mg_opts;
 
 typedef struct {
@@ -602,6 +604,9 @@ int ib_diagnostics(ib_ctx* ctx, const double* p, const double* H, const double* 
  *     V-cycle whose level starts from zero; p is not read), either precision
  *   IB_PROF_SWEEP_DOTS -- the float64 density sweep that also takes the
  *     flexible-CG inner products (the last post-smoothing sweep of the finest level)
+ *   IB_PROF_SWEEP_PRO -- the density sweep that first adds the prolongated
+ *     coarse correction (the first post-smoothing sweep of the finest level,
+ *     in place of a separate prolongation), either precision
  *   IB_PROF_RESTRICT64 / IB_PROF_RESTRICT32 -- residual + restriction
  *   IB_PROF_PROLONG64 / IB_PROF_PROLONG32 -- prolongation + correction
  *   IB_PROF_RESID -- float64 residual norm / defect
@@ -610,7 +615,7 @@ int ib_diagnostics(ib_ctx* ctx, const double* p, const double* H, const double* 
 enum { IB_PROF_SMOOTH64 = 0, IB_PROF_SMOOTH32, IB_PROF_RESTRICT64, IB_PROF_RESTRICT32,
        IB_PROF_PROLONG64, IB_PROF_PROLONG32, IB_PROF_RESID, IB_PROF_SWEEP64,
        IB_PROF_SWEEP32, IB_PROF_SWEEP64_RHO, IB_PROF_SWEEP_ZERO, IB_PROF_SWEEP_DOTS,
-       IB_PROF_KINDS };
+       IB_PROF_SWEEP_PRO, IB_PROF_KINDS };
 void ib_profile_enable(int on);
 void ib_profile_reset(void);
 int  ib_profile_read(int kind, long long* launches, double* total_ms);

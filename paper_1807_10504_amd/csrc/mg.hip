@@ -517,6 +517,21 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
     }
 }
 
+// One fine cell's share of the cell-centred linear prolongation from its
+// eight coarse neighbours (3/4 and 1/4 per axis), every product and sum
+// rounded on its own as in k_prolong_add_blk: e111 is the coarse parent,
+// e11x its neighbour along x, e1y1 along y, ez11 along z, and so on.
+template <typename T>
+__device__ __forceinline__ T prolong_cell(T e111, T e11x, T e1y1, T e1yx, T ez11, T ez1x, T ezy1, T ezyx) {
+#pragma clang fp contract(off)
+    const T a = T(0.75), q = T(0.25);
+    const T r00 = a * e111 + q * e11x;
+    const T r01 = a * e1y1 + q * e1yx;
+    const T r10 = a * ez11 + q * ez1x;
+    const T r11 = a * ezy1 + q * ezyx;
+    return a * (a * r00 + q * r01) + q * (a * r10 + q * r11);
+}
+
 // The same single-pass sweep on a finest level given by cell densities: the
 // workgroup stages p and rho on the tile plus the two-cell halo in LDS and
 // forms each face coefficient 2 / (rho_hi + rho_lo) where it is used (in T:
@@ -532,14 +547,19 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_fused(const T* __restrict__ pin
 // (the flexible-CG inner products of the preconditioned residual, taken from
 // the values the black lanes write); qv is read in pairs two steps ahead,
 // like b.
-template <typename T, int TX, int TY, int NT, bool ZERO, int DOTS = 0>
+// PRO: the sweep starts from p + P ec, the coarse correction ec (on the grid
+// of half the cells along each axis) prolongated as each plane is staged, in
+// the order and rounding of k_prolong_add_blk, so the result is bitwise that
+// of prolongating first; p + P ec is never stored.
+template <typename T, int TX, int TY, int NT, bool ZERO, int DOTS = 0, bool PRO = false>
 __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin,
                                                        T* __restrict__ pout,
                                                        const T* __restrict__ bb,
                                                        const T* __restrict__ rho, Dims d,
                                                        T h2, int TZ, int ntx, int nty,
                                                        int nzc, const double* __restrict__ qv = nullptr,
-                                                       double* __restrict__ part = nullptr) {
+                                                       double* __restrict__ part = nullptr,
+                                                       const T* __restrict__ ec = nullptr) {
     // region of p and rho: the tile and a two-cell halo
     constexpr int RX = TX + 4, RY = TY + 4, RN = RX * RY;
     // p and rho move in pairs of cells along x (the region starts at an even x
@@ -555,7 +575,14 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
     constexpr int BlackRow = TX / 2, BlackN = BlackRow * TY;
     constexpr int NR = (RedN + NT - 1) / NT, NB = (BlackN + NT - 1) / NT;
     static_assert(DOTS == 0 || sizeof(T) == 8, "the inner products are taken in the float64 sweep");
+    static_assert(!PRO || (!ZERO && DOTS == 0), "the prolongation starts a plain sweep");
     constexpr int NQ = DOTS == 2 ? NB : 0;
+    // PRO: the coarse cells under the region and one more on each side (the
+    // region starts at an even x and y, so it covers whole coarse cells), in a
+    // ring of three coarse planes; NC loads per lane fill one coarse plane
+    constexpr int CX = RX / 2 + 2, CY = RY / 2 + 2, CN = CX * CY;
+    constexpr int NC = PRO ? (CN + NT - 1) / NT : 0;
+    __shared__ T EC[PRO ? 3 : 1][PRO ? CN : 1];
     // rings of five planes: the black update of plane k - 1 reads planes
     // k - 2 .. k while the next step already stages plane k + 2, so no
     // barrier separates them
@@ -610,6 +637,31 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
     }
     // planes z0 - 2 .. z1 + 2 lie within one period of the box
     auto pl = [&](int k) { return (long)wrap_near(k, d.nz) * plane; };
+    // coarse cell q of the ring's planes (origin (i0 / 2 - 1, j0 / 2 - 1), at
+    // least -2 and within one coarse period); coarse planes z0 / 2 - 2 ..
+    // z1 / 2 + 3 likewise
+    const int cnx = d.nx >> 1, cny = d.ny >> 1, cnz = d.nz >> 1;
+    int gc[NC > 0 ? NC : 1];
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        int q = t + s * NT;
+        q = q < CN ? q : 0;
+        gc[s] = wrap_near(j0 / 2 - 1 + q / CX, cny) * cnx + wrap_near(i0 / 2 - 1 + q % CX, cnx);
+    }
+    auto cpl = [&](int c) { return (long)wrap_near(c, cnz) * cny * cnx; };
+    auto s3 = [](int c) { return (c + 300) % 3; };
+    // P ec at region cells 2u, 2u + 1 of row y on plane kk: the even cell's
+    // second coarse neighbour along x is the one below, the odd cell's the one
+    // above; along y and z the parity of the row and plane decides the same way
+    auto prolong2 = [&](int y, int u, int kk, T& v0, T& v1) {
+        const int K = kk >> 1;
+        const T* E1 = EC[s3(K)];
+        const T* E2 = EC[s3((kk & 1) ? K + 1 : K - 1)];
+        const int cy = (y >> 1) + 1, cy2 = (y & 1) ? cy + 1 : cy - 1;
+        const int o1 = cy * CX + u + 1, o2 = cy2 * CX + u + 1;
+        v0 = prolong_cell<T>(E1[o1], E1[o1 - 1], E1[o2], E1[o2 - 1], E2[o1], E2[o1 - 1], E2[o2], E2[o2 - 1]);
+        v1 = prolong_cell<T>(E1[o1], E1[o1 + 1], E1[o2], E1[o2 + 1], E2[o1], E2[o1 + 1], E2[o2], E2[o2 + 1]);
+    };
     // two register stages, alternating. A stage holds what step k reads from
     // memory: p and rho of plane k + 1 (committed to LDS at the step's start,
     // loaded two steps ahead), b of its red cells on plane k and the b (and
@@ -617,11 +669,14 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
     // barriers, loaded at the end of step k - 2). Every value is consumed
     // before the stage is loaded again, so no loaded register is copied and
     // no wait drains the loads issued after it.
+    // PRO: stage A (the odd steps 2m + 1) also carries coarse plane m + 2,
+    // loaded at the end of step 2m - 1 and staged after the first barrier
     struct Stage {
         V2 p[NL], r[NL];
         T br[NR];
         V2 bk[NB];
         double2 qk[NQ > 0 ? NQ : 1];
+        T ce[NC > 0 ? NC : 1];
     };
     Stage SA, SB;
     auto ld2 = [](const T* a) { return *reinterpret_cast<const V2*>(a); };
@@ -647,6 +702,15 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
 #pragma unroll
         for (int s = 0; s < NQ; ++s) S.qk[s] = *reinterpret_cast<const double2*>(qv + bq + gb[s]);
     };
+    auto fetch_c = [&](Stage& S, int c) {
+#pragma unroll
+        for (int s = 0; s < NC; ++s) S.ce[s] = ec[cpl(c) + gc[s]];
+    };
+    auto stage_c = [&](const Stage& S, int c) {
+#pragma unroll
+        for (int s = 0; s < NC; ++s)
+            if (s * NT + NT <= CN || t + s * NT < CN) EC[s3(c)][t + s * NT] = S.ce[s];
+    };
     // ring slots; planes k >= z0 - 2 >= -2
     auto s5 = [](int k) { return (k + 10) % 5; };
     auto commit = [&](const Stage& S, int k) {
@@ -655,19 +719,46 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
 #pragma unroll
         for (int s = 0; s < NL; ++s)
             if (s * NT + NT <= RN2 || vp[s]) {
-                *reinterpret_cast<V2*>(Pn + 2 * (t + s * NT)) = S.p[s];
+                V2 pv = S.p[s];
+                if constexpr (PRO) {
+                    const int q = t + s * NT;
+                    T v0, v1;
+                    prolong2(q / (RX / 2), q % (RX / 2), k + 1, v0, v1);
+                    pv.x = pv.x + v0;
+                    pv.y = pv.y + v1;
+                }
+                *reinterpret_cast<V2*>(Pn + 2 * (t + s * NT)) = pv;
                 *reinterpret_cast<V2*>(Rn + 2 * (t + s * NT)) = S.r[s];
             }
     };
+    if constexpr (PRO) {
+        // coarse planes z0 / 2 - 2 .. z0 / 2 serve the first three fine planes
+        for (int c = z0 / 2 - 2; c <= z0 / 2; ++c) {
+            fetch_c(SA, c);
+            stage_c(SA, c);
+        }
+        __syncthreads();
+    }
     {
         long a = pl(z0 - 2), a1 = pl(z0 - 1);
 #pragma unroll
         for (int s = 0; s < NL; ++s)
             if (vp[s]) {
-                const int c2 = 2 * (t + s * NT);
+                const int q = t + s * NT, c2 = 2 * q;
+                T v[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
+                if constexpr (PRO) {
+                    prolong2(q / (RX / 2), q % (RX / 2), z0 - 2, v[0][0], v[0][1]);
+                    prolong2(q / (RX / 2), q % (RX / 2), z0 - 1, v[1][0], v[1][1]);
+                }
                 for (int e = 0; e < 2; ++e) {
-                    P[s5(z0 - 2)][c2 + e] = ZERO ? T(0) : pin[a + gp[s] + e];
-                    P[s5(z0 - 1)][c2 + e] = ZERO ? T(0) : pin[a1 + gp[s] + e];
+                    T pa = ZERO ? T(0) : pin[a + gp[s] + e];
+                    T pb = ZERO ? T(0) : pin[a1 + gp[s] + e];
+                    if constexpr (PRO) {
+                        pa = pa + v[0][e];
+                        pb = pb + v[1][e];
+                    }
+                    P[s5(z0 - 2)][c2 + e] = pa;
+                    P[s5(z0 - 1)][c2 + e] = pb;
                     R[s5(z0 - 2)][c2 + e] = rho[a + gp[s] + e];
                     R[s5(z0 - 1)][c2 + e] = rho[a1 + gp[s] + e];
                 }
@@ -675,6 +766,7 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
     }
     fetch_pr(SA, z0 - 1);
     fetch_b(SA, z0 - 1);
+    if constexpr (PRO) fetch_c(SA, z0 / 2 + 1);
     // keep stage A's loads ahead of stage B's (the wait counts assume that order)
     __builtin_amdgcn_sched_barrier(0);
     fetch_pr(SB, z0);
@@ -713,13 +805,20 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
         diag += bzp + bzm;
         return (num - h2 * bv) / diag;
     };
-    auto step = [&](Stage& S, int k) {
+    // ODD: stage A's steps k = 2m + 1 (z0 is even)
+    auto step = [&](Stage& S, int k, auto odd) {
         commit(S, k);
         // past the range the loads re-read plane z1 (not used), which keeps
         // them unconditional
         const int kn = k + 2 <= z1 ? k + 2 : z1;
         fetch_pr(S, kn);
         lds_barrier();
+        if constexpr (PRO && decltype(odd)::value) {
+            // coarse plane m + 2 replaces m - 1, last read by the commit of
+            // fine plane 2m at step 2m - 1; first read at step 2m + 2, after
+            // this step's second barrier
+            stage_c(S, (k - 1) / 2 + 2);
+        }
         const Slots sr = slots(k);
 #pragma unroll
         for (int s = 0; s < NR; ++s) {
@@ -763,14 +862,15 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
             }
         }
         fetch_b(S, kn);
+        if constexpr (PRO && decltype(odd)::value) fetch_c(S, (k - 1) / 2 + 3);
         // no barrier here: the next step's commit writes the slots of plane
         // k - 3, which this black update does not read, and its first barrier
         // orders everything after
     };
     // steps z0 - 1 .. z1 in pairs (stage A, stage B); TZ is even
     for (int k = z0 - 1; k <= z1; k += 2) {
-        step(SA, k);
-        step(SB, k + 1);
+        step(SA, k, std::true_type{});
+        step(SB, k + 1, std::false_type{});
     }
     if constexpr (DOTS > 0) {
         // fixed-order workgroup sums
@@ -1924,15 +2024,18 @@ static void launch_rbgs(Level& L, int color, hipStream_t st, bool finest) {
                            A.beta[0], A.beta[1], A.beta[2], L.d, h2, color);
 }
 
-// zero: the sweep starts from p = 0 (pin is not read)
+// zero: the sweep starts from p = 0 (pin is not read); pe (density levels
+// only): the sweep starts from pin + P pe, pe the correction on the coarse
+// level below (the prolongation folded into the sweep)
 template <typename T>
 static void launch_fused(Level& L, T* pin, T* pout, hipStream_t st, bool finest, bool zero,
-                         bool dots = false) {
+                         bool dots = false, const T* pe = nullptr) {
     // sweeps from p = 0 read less and are timed under their own kind
     ProfScope ps(zero ? IB_PROF_SWEEP_ZERO
                       : dots ? IB_PROF_SWEEP_DOTS
-                             : (sizeof(T) == 8 ? (L.rho ? IB_PROF_SWEEP64_RHO : IB_PROF_SWEEP64)
-                                               : IB_PROF_SWEEP32),
+                             : pe ? IB_PROF_SWEEP_PRO
+                                  : (sizeof(T) == 8 ? (L.rho ? IB_PROF_SWEEP64_RHO : IB_PROF_SWEEP64)
+                                                    : IB_PROF_SWEEP32),
                  st, finest);
     LevelT<T>& A = lvl<T>(L);
     T h2 = (T)(L.d.h * L.d.h);
@@ -1951,6 +2054,10 @@ static void launch_fused(Level& L, T* pin, T* pout, hipStream_t st, bool finest,
             else if (zero)
                 hipLaunchKernelGGL((k_rbgs_fused_rho<double, kRTX, kRTY, kRNT, true>), dim3(rx * ry * rz),
                                    dim3(kRNT), 0, st, pin, pout, A.b, L.rho, L.d, h2, L.rtz, rx, ry, rz);
+            else if (pe)
+                hipLaunchKernelGGL((k_rbgs_fused_rho<double, kRTX, kRTY, kRNT, false, 0, true>),
+                                   dim3(rx * ry * rz), dim3(kRNT), 0, st, pin, pout, A.b, L.rho, L.d, h2, L.rtz,
+                                   rx, ry, rz, nullptr, nullptr, pe);
             else
                 hipLaunchKernelGGL((k_rbgs_fused_rho<double, kRTX, kRTY, kRNT, false>), dim3(rx * ry * rz),
                                    dim3(kRNT), 0, st, pin, pout, A.b, L.rho, L.d, h2, L.rtz, rx, ry, rz);
@@ -1963,6 +2070,10 @@ static void launch_fused(Level& L, T* pin, T* pout, hipStream_t st, bool finest,
             if (zero)
                 hipLaunchKernelGGL((k_rbgs_fused_rho<float, kRTX, kRTY, kRNT, true>), dim3(rx * ry * rz),
                                    dim3(kRNT), 0, st, pin, pout, A.b, L.rho32, L.d, h2, L.rtz, rx, ry, rz);
+            else if (pe)
+                hipLaunchKernelGGL((k_rbgs_fused_rho<float, kRTX, kRTY, kRNT, false, 0, true>),
+                                   dim3(rx * ry * rz), dim3(kRNT), 0, st, pin, pout, A.b, L.rho32, L.d, h2,
+                                   L.rtz, rx, ry, rz, nullptr, nullptr, pe);
             else
                 hipLaunchKernelGGL((k_rbgs_fused_rho<float, kRTX, kRTY, kRNT, false>), dim3(rx * ry * rz),
                                    dim3(kRNT), 0, st, pin, pout, A.b, L.rho32, L.d, h2, L.rtz, rx, ry, rz);
@@ -1983,13 +2094,13 @@ static void launch_fused(Level& L, T* pin, T* pout, hipStream_t st, bool finest,
 // dots_last: the last sweep leaves the inner products of Level::dots_*
 template <typename T>
 static T* smooth(Level& L, T* cur, int nu, hipStream_t st, bool finest, bool zero_first,
-                 bool dots_last = false) {
+                 bool dots_last = false, const T* pe = nullptr) {
     LevelT<T>& A = lvl<T>(L);
     for (int s = 0; s < nu; ++s) {
         if (L.fused) {
             T* other = cur == A.p ? A.alt : A.p;
             launch_fused<T>(L, cur, other, st, finest, zero_first && s == 0,
-                            dots_last && s == nu - 1 && !(zero_first && s == 0));
+                            dots_last && s == nu - 1 && !(zero_first && s == 0), s == 0 ? pe : nullptr);
             cur = other;
         } else {
             T* save = A.p;
@@ -2091,7 +2202,11 @@ static void vcycle(mg_handle* m, int l, hipStream_t st, bool zero_start) {
     if (l + 1 != last && !C.fused)
         hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(nc)), dim3(kBlock), 0, st, B.p, nc, (T)0);
     vcycle<T>(m, l + 1, st, true);
-    {
+    // on a 3D density level with at least two post-smoothing sweeps the first
+    // (a plain sweep) adds the prolongated correction as it stages p
+    const bool fold = L.fused && L.d.dim == 3 && m->o.nu2 >= 2 && !m->o.split_coarse &&
+                      (sizeof(T) == 8 ? L.rho != nullptr : L.rho32 != nullptr);
+    if (!fold) {
         ProfScope ps(sizeof(T) == 8 ? IB_PROF_PROLONG64 : IB_PROF_PROLONG32, st, fin);
         int bx = std::min(L.d.nx, kBlock);
         dim3 pg((L.d.nx + bx - 1) / bx, L.d.ny, L.d.nz);
@@ -2103,7 +2218,7 @@ static void vcycle(mg_handle* m, int l, hipStream_t st, bool zero_start) {
                                dim3(cb), 0, st, cur, B.p, L.d);
         }
     }
-    cur = smooth<T>(L, cur, m->o.nu2, st, fin, false, sizeof(T) == 8 && L.dots_on);
+    cur = smooth<T>(L, cur, m->o.nu2, st, fin, false, sizeof(T) == 8 && L.dots_on, fold ? B.p : nullptr);
     if (cur != A.p)
         (void)hipMemcpyAsync(A.p, cur, sizeof(T) * L.d.cells(), hipMemcpyDeviceToDevice, st);
 }

@@ -36,7 +36,7 @@ EXPORTS = ("ib_create", "ib_destroy", "ib_bin_markers", "ib_interp", "ib_spread"
            "ib_last_error")
 
 PROF_KINDS = ("smooth64", "smooth32", "restrict64", "restrict32", "prolong64", "prolong32", "resid",
-              "sweep64", "sweep32", "sweep64_rho", "sweep_zero", "sweep_dots")
+              "sweep64", "sweep32", "sweep64_rho", "sweep_zero", "sweep_dots", "sweep_pro")
 
 
 class IbError(RuntimeError):

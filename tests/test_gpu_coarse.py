@@ -1,7 +1,10 @@
-"""The persistent coarse-level kernel (one workgroup runs the sub-V-cycle of the
-levels with at most 32768 cells) against the launch-per-phase cycle: p and
-the residual history bitwise equal, on 2D and 3D hierarchies, FP64 and mixed,
-plain cycles and flexible CG, and for other smoothing counts."""
+"""The fused phases of the cycle against the launch-per-phase cycle: the
+persistent coarse-level kernel (one workgroup runs the sub-V-cycle of the
+levels with at most 32768 cells) and, on 3D density levels (128^3 and up),
+the prolongation folded into the first post-smoothing sweep. p and the
+residual history bitwise equal, on 2D and 3D hierarchies, FP64 and mixed,
+plain cycles and flexible CG, other smoothing counts, and the 256^3 flexible
+CG of the headline step."""
 import numpy as np
 import pytest
 
@@ -27,7 +30,9 @@ def _H(shape):
 
 CASES = [((512, 512), "fp64", 0, (2, 2)), ((128, 128, 128), "fp64", 0, (2, 2)),
          ((128, 128, 128), "mixed", 1, (2, 2)), ((32, 32, 32), "fp64", 1, (1, 1)),
-         ((64, 64, 64), "mixed", 0, (2, 1)), ((256, 256), "mixed", 1, (2, 2))]
+         ((64, 64, 64), "mixed", 0, (2, 1)), ((256, 256), "mixed", 1, (2, 2)),
+         ((128, 128, 128), "fp64", 1, (1, 3)), ((128, 128, 128), "mixed", 0, (2, 2)),
+         ((256, 256, 256), "fp64", 1, (2, 2))]
 
 
 @pytest.mark.parametrize("shape,prec,krylov,nu", CASES)
