@@ -1321,6 +1321,250 @@ __global__ __launch_bounds__(kPersistThreads) void k_coarse_vcycle(PersistLevels
     }
 }
 
+// The same sub-V-cycle for 3D hierarchies with its data in LDS and
+// registers. The first level (at most kPersistCells cells) keeps p, b and the
+// residual in LDS, and each thread keeps the six face coefficients of its own
+// cells in registers (up to four of each colour); the smaller
+// levels keep p, b, the residual and the face
+// coefficients in an LDS pool. Global memory is read once per cycle (the
+// first level's p, b and coefficients, the smaller levels' coefficients, the
+// coarsest inverse) and written once (the first level's p). Each phase forms
+// every value with the operands and the order of k_coarse_vcycle (the
+// residual of a fine cell is formed once and the restriction sums the eight
+// children in the same order), so the cycle is bitwise the same.
+constexpr int kLdsPool = 512 + 64 + 8 + 1;  // levels below the first: an eighth of the one above each
+constexpr int kLdsThreads = 512;
+
+template <typename T>
+__global__ __launch_bounds__(kLdsThreads) void k_coarse_vcycle_lds(PersistLevels<T> L) {
+    constexpr int NT = kLdsThreads;
+    constexpr int NS = (kPersistCells / 2 + NT - 1) / NT;  // cells of each colour per thread
+    __shared__ T P0[kPersistCells], B0[kPersistCells], R0[kPersistCells];
+    __shared__ T PP[kLdsPool], BB[kLdsPool], RR[kLdsPool], X0[kLdsPool], X1[kLdsPool], X2[kLdsPool];
+    __shared__ double sb[kMaxCoarse];
+    __shared__ int OFF[kPersistMaxLevels];
+    const int t = threadIdx.x;
+    const int last = L.n - 1;
+    if (t == 0) {
+        int o = 0;
+        for (int l = 1; l < L.n; ++l) {
+            OFF[l] = o;
+            o += (int)L.d[l].cells();
+        }
+    }
+    // first level: the cells of colour c dealt t, t + NT (as k_rbgs deals them)
+    const Dims d0 = L.d[0];
+    const int n0 = (int)d0.cells(), half0 = n0 >> 1, hx0 = d0.nx >> 1;
+    // the periodic neighbours of cell (i, j, k) as 32-bit offsets
+    struct Nb32 {
+        int c, xm, xp, ym, yp, zm, zp;
+    };
+    auto nb32 = [](const Dims& d, int i, int j, int k) {
+        Nb32 n;
+        const int pl = d.nx * d.ny;
+        n.c = (k * d.ny + j) * d.nx + i;
+        n.xm = i == 0 ? n.c + d.nx - 1 : n.c - 1;
+        n.xp = i == d.nx - 1 ? n.c - (d.nx - 1) : n.c + 1;
+        n.ym = j == 0 ? n.c + (d.ny - 1) * d.nx : n.c - d.nx;
+        n.yp = j == d.ny - 1 ? n.c - (d.ny - 1) * d.nx : n.c + d.nx;
+        n.zm = k == 0 ? n.c + (d.nz - 1) * pl : n.c - pl;
+        n.zp = k == d.nz - 1 ? n.c - (d.nz - 1) * pl : n.c + pl;
+        return n;
+    };
+    int cl[2][NS];
+    T bxl[2][NS], bxr[2][NS], byl[2][NS], byr[2][NS], bzl[2][NS], bzr[2][NS];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int t2 = t + s * NT;
+            cl[c][s] = -1;
+            bxl[c][s] = bxr[c][s] = byl[c][s] = byr[c][s] = bzl[c][s] = bzr[c][s] = T(0);
+            if (t2 < half0) {
+                const int i2 = t2 % hx0, r = t2 / hx0;
+                const int j = r % d0.ny, k = r / d0.ny;
+                const int i = 2 * i2 + ((j + k + c) & 1);
+                const Nb32 n = nb32(d0, i, j, k);
+                cl[c][s] = n.c;
+                bxr[c][s] = L.b0[0][n.xp];
+                bxl[c][s] = L.b0[0][n.c];
+                byr[c][s] = L.b1[0][n.yp];
+                byl[c][s] = L.b1[0][n.c];
+                bzr[c][s] = L.b2[0][n.zp];
+                bzl[c][s] = L.b2[0][n.c];
+                B0[n.c] = L.b[0][n.c];
+                P0[n.c] = L.p[0][n.c];
+            }
+        }
+    __syncthreads();
+    // coefficients of the smaller levels (the coarsest is solved directly)
+    for (int l = 1; l < last; ++l) {
+        const int nl = (int)L.d[l].cells(), o = OFF[l];
+        for (int u = t; u < nl; u += NT) {
+            X0[o + u] = L.b0[l][u];
+            X1[o + u] = L.b1[l][u];
+            X2[o + u] = L.b2[l][u];
+        }
+    }
+    const T h20 = (T)(d0.h * d0.h);
+    auto cell_nb = [&](const Dims& d, int u) {
+        const int i = u % d.nx, r = u / d.nx;
+        return nb32(d, i, r % d.ny, r / d.ny);
+    };
+    auto sweep0 = [&](int c) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (cl[c][s] < 0) continue;
+            const Nb32 n = cell_nb(d0, cl[c][s]);
+            T br = bxr[c][s], bl = bxl[c][s];
+            T num = br * P0[n.xp] + bl * P0[n.xm];
+            T diag = br + bl;
+            br = byr[c][s];
+            bl = byl[c][s];
+            num += br * P0[n.yp] + bl * P0[n.ym];
+            diag += br + bl;
+            br = bzr[c][s];
+            bl = bzl[c][s];
+            num += br * P0[n.zp] + bl * P0[n.zm];
+            diag += br + bl;
+            P0[n.c] = (num - h20 * B0[n.c]) / diag;
+        }
+    };
+    auto resid0 = [&]() {
+        const T inv_h2 = (T)(1.0 / (d0.h * d0.h));
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (cl[c][s] < 0) continue;
+                const Nb32 n = cell_nb(d0, cl[c][s]);
+                const T pc = P0[n.c];
+                T sv = bxr[c][s] * (P0[n.xp] - pc) - bxl[c][s] * (pc - P0[n.xm]);
+                sv += byr[c][s] * (P0[n.yp] - pc) - byl[c][s] * (pc - P0[n.ym]);
+                sv += bzr[c][s] * (P0[n.zp] - pc) - bzl[c][s] * (pc - P0[n.zm]);
+                R0[n.c] = B0[n.c] - sv * inv_h2;
+            }
+    };
+    auto sweepl = [&](int l, int c) {
+        const Dims d = L.d[l];
+        const int o = OFF[l], hx = d.nx >> 1, half = (int)(d.cells() >> 1);
+        const T h2 = (T)(d.h * d.h);
+        for (int t2 = t; t2 < half; t2 += NT) {
+            const int i2 = t2 % hx, r = t2 / hx;
+            const int j = r % d.ny, k = r / d.ny;
+            const Nb32 n = nb32(d, 2 * i2 + ((j + k + c) & 1), j, k);
+            T br = X0[o + n.xp], bl = X0[o + n.c];
+            T num = br * PP[o + n.xp] + bl * PP[o + n.xm];
+            T diag = br + bl;
+            br = X1[o + n.yp];
+            bl = X1[o + n.c];
+            num += br * PP[o + n.yp] + bl * PP[o + n.ym];
+            diag += br + bl;
+            br = X2[o + n.zp];
+            bl = X2[o + n.c];
+            num += br * PP[o + n.zp] + bl * PP[o + n.zm];
+            diag += br + bl;
+            PP[o + n.c] = (num - h2 * BB[o + n.c]) / diag;
+        }
+    };
+    auto residl = [&](int l) {
+        const Dims d = L.d[l];
+        const int o = OFF[l], nl = (int)d.cells();
+        const T inv_h2 = (T)(1.0 / (d.h * d.h));
+        for (int u = t; u < nl; u += NT) {
+            const Nb32 n = cell_nb(d, u);
+            const T pc = PP[o + n.c];
+            T sv = X0[o + n.xp] * (PP[o + n.xp] - pc) - X0[o + n.c] * (pc - PP[o + n.xm]);
+            sv += X1[o + n.yp] * (PP[o + n.yp] - pc) - X1[o + n.c] * (pc - PP[o + n.ym]);
+            sv += X2[o + n.zp] * (PP[o + n.zp] - pc) - X2[o + n.c] * (pc - PP[o + n.zm]);
+            RR[o + u] = BB[o + u] - sv * inv_h2;
+        }
+    };
+    // coarse right side of level l + 1 from the residuals of level l (children
+    // summed in the order dz, dy, dx, from zero), and p of level l + 1 zeroed
+    // unless it is the coarsest
+    auto restrictl = [&](int l) {
+        const Dims f = L.d[l];
+        const T* R = l == 0 ? R0 : RR + OFF[l];
+        const int oc = OFF[l + 1];
+        const int cx = f.nx >> 1, cy = f.ny >> 1, cz = f.nz >> 1;
+        const bool fill = l + 1 != last;
+        for (int u = t; u < cx * cy * cz; u += NT) {
+            const int I = u % cx, r = u / cx;
+            const int J = r % cy, K = r / cy;
+            T acc = 0;
+            for (int dz = 0; dz < 2; ++dz)
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx)
+                        acc += R[((2 * K + dz) * f.ny + (2 * J + dy)) * f.nx + 2 * I + dx];
+            BB[oc + u] = acc * T(0.125);
+            if (fill) PP[oc + u] = T(0);
+        }
+    };
+    // p of level l += P e, e = p of level l + 1
+    auto prolongl = [&](int l) {
+        const Dims f = L.d[l];
+        const T* e = PP + OFF[l + 1];
+        T* p = l == 0 ? P0 : PP + OFF[l];
+        const int cx = f.nx >> 1, cy = f.ny >> 1, cz = f.nz >> 1;
+        for (int u = t; u < (int)f.cells(); u += NT) {
+            const int i = u % f.nx, r = u / f.nx;
+            const int j = r % f.ny, k = r / f.ny;
+            const int I = i >> 1, J = j >> 1, K = k >> 1;
+            const int I2 = (i & 1) ? (I + 1 == cx ? 0 : I + 1) : (I == 0 ? cx - 1 : I - 1);
+            const int J2 = (j & 1) ? (J + 1 == cy ? 0 : J + 1) : (J == 0 ? cy - 1 : J - 1);
+            const int K2 = (k & 1) ? (K + 1 == cz ? 0 : K + 1) : (K == 0 ? cz - 1 : K - 1);
+            const int pl = cx * cy;
+            const T* e0 = e + K * pl;
+            const T* e1 = e + K2 * pl;
+            const T v = prolong_cell<T>(e0[J * cx + I], e0[J * cx + I2], e0[J2 * cx + I], e0[J2 * cx + I2],
+                                        e1[J * cx + I], e1[J * cx + I2], e1[J2 * cx + I], e1[J2 * cx + I2]);
+            p[u] = p[u] + v;
+        }
+    };
+    __syncthreads();
+    for (int l = 0; l < last; ++l) {
+        for (int s = 0; s < L.nu1; ++s)
+            for (int c = 0; c < 2; ++c) {
+                if (l == 0)
+                    sweep0(c);
+                else
+                    sweepl(l, c);
+                __syncthreads();
+            }
+        if (l == 0)
+            resid0();
+        else
+            residl(l);
+        __syncthreads();
+        restrictl(l);
+        __syncthreads();
+    }
+    // coarsest: x = (-M^{-1}) b, float64 sums
+    const int oc = OFF[last];
+    for (int q = t; q < L.nc; q += NT) sb[q] = (double)BB[oc + q];
+    __syncthreads();
+    for (int r = t; r < L.nc; r += NT) {
+        double s = 0.0;
+        for (int c = 0; c < L.nc; ++c) s += L.minv[(long)r * L.nc + c] * sb[c];
+        PP[oc + r] = (T)s;
+    }
+    __syncthreads();
+    for (int l = last - 1; l >= 0; --l) {
+        prolongl(l);
+        __syncthreads();
+        for (int s = 0; s < L.nu2; ++s)
+            for (int c = 0; c < 2; ++c) {
+                if (l == 0)
+                    sweep0(c);
+                else
+                    sweepl(l, c);
+                __syncthreads();
+            }
+    }
+    for (int u = t; u < n0; u += NT) L.p[0][u] = P0[u];
+}
+
 // ---------------------------------------------------------------------------
 // norms: partial sums of r^2 (and of p) per block
 template <int DIM, class K>
@@ -2183,7 +2427,12 @@ static void vcycle(mg_handle* m, int l, hipStream_t st, bool zero_start) {
             P.b1[i] = Ai.beta[1];
             P.b2[i] = Li.d.dim == 3 ? Ai.beta[2] : Ai.beta[1];
         }
-        if (L.d.dim == 3)
+        // 3D: the LDS-resident form when the levels below the first fit its pool
+        long pool = 0;
+        for (int i = 1; i < P.n; ++i) pool += P.d[i].cells();
+        if (L.d.dim == 3 && L.d.cells() <= kPersistCells && pool <= kLdsPool && P.nc <= kMaxCoarse)
+            hipLaunchKernelGGL((k_coarse_vcycle_lds<T>), dim3(1), dim3(kLdsThreads), 0, st, P);
+        else if (L.d.dim == 3)
             hipLaunchKernelGGL((k_coarse_vcycle<T, 3>), dim3(1), dim3(kPersistThreads), 0, st, P);
         else
             hipLaunchKernelGGL((k_coarse_vcycle<T, 2>), dim3(1), dim3(kPersistThreads), 0, st, P);
