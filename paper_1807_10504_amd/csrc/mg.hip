@@ -1739,6 +1739,33 @@ __global__ void k_pcg_xr(double* __restrict__ x, double* __restrict__ r,
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// The x/r update with the x part left to the next direction pass (which
+// makes it as k_cg_dir_apply_rho<..., XUPD>): r -= alpha q, fl32(r) when r32
+// is given, partial sums of r^2; alpha formed as k_pcg_xr forms it.
+__global__ void k_pcg_r(double* __restrict__ r, const double* __restrict__ q, long N,
+                        const double* __restrict__ ks, int rz_slot, double* __restrict__ partial,
+                        float* __restrict__ r32) {
+    __shared__ double sh[kBlock];
+    const double alpha = ks[rz_slot] / ks[KS_DQ];
+    double acc = 0.0;
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long)gridDim.x * blockDim.x) {
+        double rv = r[c] - alpha * q[c];
+        r[c] = rv;
+        if (r32) r32[c] = (float)rv;
+        acc += rv * rv;
+    }
+    double s = block_reduce_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// the x part of k_pcg_xr on its own (a deferred update made before x is read)
+__global__ void k_pcg_x(double* __restrict__ x, const double* __restrict__ dv, long N,
+                        const double* __restrict__ ks, int rz_slot) {
+    const double alpha = ks[rz_slot] / ks[KS_DQ];
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long)gridDim.x * blockDim.x)
+        x[c] += alpha * dv[c];
+}
+
 // partial sums of r z and (when q is given) q z; z is the float64 V-cycle
 // output or the float32 one
 template <typename TZ>
@@ -1788,12 +1815,15 @@ __global__ void k_pcg_dir(double* __restrict__ dv, const TZ* __restrict__ z, lon
 // arithmetic of each q is that of apply_row_rho, operand for operand. FIRST
 // (the first iteration, dnew = z) is a template argument, so that every step
 // issues the same loads and the waits for a staged plane never drain the
-// loads issued after it.
+// loads issued after it. XUPD: the pass also makes the previous iteration's
+// x += alpha d on its tile (alpha = rz_old / dq from the device scalars, as
+// the x/r update forms it; d the old direction, which the pass reads anyway),
+// so that update need not read d and write x again.
 constexpr int CG_TX = 64, CG_TY = 8, CG_NT = 512;
 constexpr int CG_RX = CG_TX + 2, CG_RY = CG_TY + 2, CG_RN = CG_RX * CG_RY;
 constexpr int CG_NL = (CG_RN + CG_NT - 1) / CG_NT;
 
-template <typename TZ, bool FIRST>
+template <typename TZ, bool FIRST, bool XUPD = false>
 __global__ __launch_bounds__(CG_NT) void k_cg_dir_apply_rho(const TZ* __restrict__ z,
                                                             const double* __restrict__ d,
                                                             double* __restrict__ dnew,
@@ -1802,7 +1832,9 @@ __global__ __launch_bounds__(CG_NT) void k_cg_dir_apply_rho(const TZ* __restrict
                                                             double inv_h2, const double* __restrict__ ks,
                                                             int rz_old_slot, int TZr,
                                                             int ntx, int nty, int nzc,
-                                                            double* __restrict__ partial) {
+                                                            double* __restrict__ partial,
+                                                            double* __restrict__ x = nullptr) {
+    static_assert(!(FIRST && XUPD), "the first iteration has no previous update");
     __shared__ double DN[3][CG_RN];
     __shared__ double RR[3][CG_RN];
     __shared__ double red[CG_NT / 64];
@@ -1818,12 +1850,14 @@ __global__ __launch_bounds__(CG_NT) void k_cg_dir_apply_rho(const TZ* __restrict
     const long plane = (long)dm.nx * dm.ny;
     const int t = threadIdx.x;
     // beta of the direction update from the device scalars
-    double beta = 0.0;
+    double beta = 0.0, alpha = 0.0;
     if (!FIRST) {
         const double rz = ks[rz_old_slot];
-        const double alpha = rz / ks[KS_DQ];
+        alpha = rz / ks[KS_DQ];
         beta = -alpha * ks[KS_QZ] / rz;
     }
+    const int lx = t % CG_TX, ly = t / CG_TX;  // one cell of the tile per thread
+    const long own = (long)(j0 + 1 + ly) * dm.nx + (i0 + 1 + lx);
     auto gofs = [&](int x, int y) {
         return (long)wrap_near(j0 + y, dm.ny) * dm.nx + wrap_near(i0 + x, dm.nx);
     };
@@ -1837,10 +1871,12 @@ __global__ __launch_bounds__(CG_NT) void k_cg_dir_apply_rho(const TZ* __restrict
     }
     auto pl = [&](int k) { return (long)wrap_near(k, dm.nz) * plane; };
     // a stage holds z, the old d and rho of a plane as loaded; the new
-    // direction is formed when the plane is committed to LDS
+    // direction is formed when the plane is committed to LDS (XUPD: with x and
+    // the old d of the lane's own cell, updated at the same commit)
     struct Stage {
         TZ z[CG_NL];
         double d[FIRST ? 1 : CG_NL], r[CG_NL];
+        double xo, dv;
     };
     Stage SA, SB;
     auto fetch = [&](Stage& S, int k) {
@@ -1851,8 +1887,16 @@ __global__ __launch_bounds__(CG_NT) void k_cg_dir_apply_rho(const TZ* __restrict
             if constexpr (!FIRST) S.d[s] = d[b + gp[s]];
             S.r[s] = rho[b + gp[s]];
         }
+        if constexpr (XUPD) {
+            S.xo = x[b + own];
+            S.dv = d[b + own];
+        }
     };
     auto commit = [&](const Stage& S, int k) {
+        // the x update of plane k on this workgroup's tile (planes z0 .. z1 - 1
+        // are committed once each; z0 - 1 and z1 belong to the neighbours)
+        if constexpr (XUPD)
+            if (k >= z0 && k < z1) x[pl(k) + own] = S.xo + alpha * S.dv;
 #pragma unroll
         for (int s = 0; s < CG_NL; ++s)
             if (s * CG_NT + CG_NT <= CG_RN || vp[s]) {
@@ -1878,7 +1922,6 @@ __global__ __launch_bounds__(CG_NT) void k_cg_dir_apply_rho(const TZ* __restrict
     fetch(SA, z0 + 1);
     __builtin_amdgcn_sched_barrier(0);
     fetch(SB, z0 + 2);
-    const int lx = t % CG_TX, ly = t / CG_TX;  // one cell of the tile per thread
     const int c = (ly + 1) * CG_RX + lx + 1;
     double acc = 0.0;
     auto step = [&](Stage& S, int k) {
@@ -3010,11 +3053,19 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
     int it = 0, slot = KS_RZ0;
     int skip = 0, last_check = 0, checks = 0;
     double rel_check = rel;
+    // on the tiled path x += alpha d rides on the next direction pass; x lags
+    // by that update (pending) until it is made before x is read
+    bool pending = false;
+    auto flush = [&]() {
+        if (pending) hipLaunchKernelGGL(k_pcg_x, g1, blk, 0, st, x, m->kd, N, m->ks, slot);
+        pending = false;
+    };
     while (true) {
         if (!std::isfinite(rel)) return fail(IB_ENAN, "mg_solve: residual is not finite");
         if (fixed > 0 ? it >= fixed : rel <= rtol) break;
         if (fixed == 0 && it >= max_it) {
             S->cycles = it;
+            flush();
             restore();
             IB_TRY(remove_mean(m, false, st));
             return fail(IB_ENOTCONV, "mg_solve: no convergence within max_cycles");
@@ -3046,6 +3097,10 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
                 hipLaunchKernelGGL((k_cg_dir_apply_rho<float, true>), dim3(cg_wgs), dim3(CG_NT), 0, st,
                                    L0.f32.p, m->kd, m->kd2, L0.rho, m->kq, L0.d, inv_h2, m->ks, rz_old,
                                    L0.rtz, cg_tx, cg_ty, cg_tz, pa);
+            else if (mixed && pending)
+                hipLaunchKernelGGL((k_cg_dir_apply_rho<float, false, true>), dim3(cg_wgs), dim3(CG_NT), 0, st,
+                                   L0.f32.p, m->kd, m->kd2, L0.rho, m->kq, L0.d, inv_h2, m->ks, rz_old,
+                                   L0.rtz, cg_tx, cg_ty, cg_tz, pa, x);
             else if (mixed)
                 hipLaunchKernelGGL((k_cg_dir_apply_rho<float, false>), dim3(cg_wgs), dim3(CG_NT), 0, st,
                                    L0.f32.p, m->kd, m->kd2, L0.rho, m->kq, L0.d, inv_h2, m->ks, rz_old,
@@ -3054,6 +3109,10 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
                 hipLaunchKernelGGL((k_cg_dir_apply_rho<double, true>), dim3(cg_wgs), dim3(CG_NT), 0, st,
                                    m->kz, m->kd, m->kd2, L0.rho, m->kq, L0.d, inv_h2, m->ks, rz_old,
                                    L0.rtz, cg_tx, cg_ty, cg_tz, pa);
+            else if (pending)
+                hipLaunchKernelGGL((k_cg_dir_apply_rho<double, false, true>), dim3(cg_wgs), dim3(CG_NT), 0,
+                                   st, m->kz, m->kd, m->kd2, L0.rho, m->kq, L0.d, inv_h2, m->ks, rz_old,
+                                   L0.rtz, cg_tx, cg_ty, cg_tz, pa, x);
             else
                 hipLaunchKernelGGL((k_cg_dir_apply_rho<double, false>), dim3(cg_wgs), dim3(CG_NT), 0, st,
                                    m->kz, m->kd, m->kd2, L0.rho, m->kq, L0.d, inv_h2, m->ks, rz_old,
@@ -3073,8 +3132,16 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
                                    inv_h2, m->kq, pa);
             IB_TRY(device_sum(pa, nb, m->ks + KS_DQ, st));
         }
-        hipLaunchKernelGGL(k_pcg_xr, gr, blk, 0, st, x, m->kr, m->kd, m->kq, N, m->ks, slot, pa,
-                           mixed ? L0.f32.b : nullptr);
+        // the pending update was made by the direction pass above
+        pending = false;
+        if (fused) {
+            hipLaunchKernelGGL(k_pcg_r, gr, blk, 0, st, m->kr, m->kq, N, m->ks, slot, pa,
+                               mixed ? L0.f32.b : nullptr);
+            pending = true;
+        } else {
+            hipLaunchKernelGGL(k_pcg_xr, gr, blk, 0, st, x, m->kr, m->kd, m->kq, N, m->ks, slot, pa,
+                               mixed ? L0.f32.b : nullptr);
+        }
         r32_ready = mixed;
         IB_TRY(device_sum(pa, nb, m->ks + KS_RR, st));
         ++it;
@@ -3092,6 +3159,7 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
             // the recursive residual drifts from b - A x by rounding: the stop
             // is decided on the true residual, which replaces r (and the
             // recursion goes on from it) when it has not reached rtol yet
+            flush();
             IB_TRY(residual(false));
             r32_ready = false;
             IB_HIP(hipMemcpyAsync(m->host, m->ks + KS_RR, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -3113,6 +3181,7 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
         rel_check = rel;
         last_check = it;
     }
+    flush();
     restore();
     if (it > 0) IB_TRY(remove_mean(m, false, st));
     IB_HIP(hipGetLastError());
