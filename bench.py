@@ -1121,6 +1121,19 @@ def main():
         roof["min_bytes_per_cell"] = SWEEP_BYTES_F64_RHO
     if traffic is not None:
         roof["frac_counters"] = round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4)
+    # all four forms of the finest density sweep together (per step: plain, with
+    # the prolongation folded in, zero-start, with the CG inner products), each
+    # against the bytes its form must move (the first iteration's inner-product
+    # sweep reads no q: one launch in twelve counted 8 bytes per cell high)
+    forms = {"sweep64_rho": SWEEP_BYTES_F64_RHO, "sweep_pro": SWEEP_BYTES_F64_RHO + 1.0,
+             "sweep_zero": SWEEP_BYTES_F64_RHO - 8.0, "sweep_dots": SWEEP_BYTES_F64_RHO + 8.0}
+    if all(r64["prof"].get(k, (0, 0))[0] for k in forms):
+        tb = sum(r64["prof"][k][0] * b * N for k, b in forms.items())
+        tt = sum(r64["prof"][k][1] for k in forms) / 1e3
+        roof["all_sweep_forms"] = dict(launches=sum(r64["prof"][k][0] for k in forms),
+                                       ms=round(1e3 * tt, 2), bytes=tb,
+                                       frac_min_bytes=round(tb / tt / 1e9 / HBM_PEAK_GBS, 4),
+                                       min_bytes_per_cell=forms)
     line = dict(metric=METRIC, value=round(sps64, 3), unit="steps/s", n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=round(1e3 * r64["seconds"] / r64["steps"], 3),
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
