@@ -602,8 +602,9 @@ int ib_diagnostics(ib_ctx* ctx, const double* p, const double* H, const double* 
  *     from cell densities (mg_update_density)
  *   IB_PROF_SWEEP_ZERO -- a single-pass sweep from p = 0 (the first sweep of a
  *     V-cycle whose level starts from zero; p is not read), either precision
- *   IB_PROF_SWEEP_DOTS -- the float64 density sweep that also takes the
- *     flexible-CG inner products (the last post-smoothing sweep of the finest level)
+ *   IB_PROF_SWEEP_DOTS -- the density sweep that also takes the flexible-CG
+ *     inner products (the last post-smoothing sweep of the finest level),
+ *     either precision (float32: against the float64 residual)
  *   IB_PROF_SWEEP_PRO -- the density sweep that first adds the prolongated
  *     coarse correction (the first post-smoothing sweep of the finest level,
  *     in place of a separate prolongation), either precision

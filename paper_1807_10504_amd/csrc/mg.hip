@@ -61,6 +61,7 @@ struct Level {
     bool dots_on = false;
     const double* dots_q = nullptr;
     double* dots_part = nullptr;
+    const double* dots_r = nullptr;  // the float64 residual (float32 cycle)
 };
 
 }  // namespace ib
@@ -546,7 +547,8 @@ __device__ __forceinline__ T prolong_cell(T e111, T e11x, T e1y1, T e1yx, T ez11
 // (b, p_new) and, for DOTS = 2, (qv, p_new) in part[bid] and part[nwg + bid]
 // (the flexible-CG inner products of the preconditioned residual, taken from
 // the values the black lanes write); qv is read in pairs two steps ahead,
-// like b.
+// like b. The float32 sweep of the mixed cycle takes them in float64 against
+// the float64 residual rv instead of its fl32(b), also read in pairs.
 // PRO: the sweep starts from p + P ec, the coarse correction ec (on the grid
 // of half the cells along each axis) prolongated as each plane is staged, in
 // the order and rounding of k_prolong_add_blk, so the result is bitwise that
@@ -559,7 +561,8 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
                                                        T h2, int TZ, int ntx, int nty,
                                                        int nzc, const double* __restrict__ qv = nullptr,
                                                        double* __restrict__ part = nullptr,
-                                                       const T* __restrict__ ec = nullptr) {
+                                                       const T* __restrict__ ec = nullptr,
+                                                       const double* __restrict__ rv = nullptr) {
     // region of p and rho: the tile and a two-cell halo
     constexpr int RX = TX + 4, RY = TY + 4, RN = RX * RY;
     // p and rho move in pairs of cells along x (the region starts at an even x
@@ -574,9 +577,10 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
     constexpr int RedRow = (RX - 2) / 2, RedN = RedRow * (RY - 2);
     constexpr int BlackRow = TX / 2, BlackN = BlackRow * TY;
     constexpr int NR = (RedN + NT - 1) / NT, NB = (BlackN + NT - 1) / NT;
-    static_assert(DOTS == 0 || sizeof(T) == 8, "the inner products are taken in the float64 sweep");
     static_assert(!PRO || (!ZERO && DOTS == 0), "the prolongation starts a plain sweep");
     constexpr int NQ = DOTS == 2 ? NB : 0;
+    // float32 inner products: the float64 residual's pairs of the black lanes
+    constexpr int NRV = (DOTS > 0 && sizeof(T) == 4) ? NB : 0;
     // PRO: the coarse cells under the region and one more on each side (the
     // region starts at an even x and y, so it covers whole coarse cells), in a
     // ring of three coarse planes; NC loads per lane fill one coarse plane
@@ -676,6 +680,7 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
         T br[NR];
         V2 bk[NB];
         double2 qk[NQ > 0 ? NQ : 1];
+        double2 rk[NRV > 0 ? NRV : 1];
         T ce[NC > 0 ? NC : 1];
     };
     Stage SA, SB;
@@ -701,6 +706,8 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
         for (int s = 0; s < NB; ++s) S.bk[s] = ld2(bb + bq + gb[s]);
 #pragma unroll
         for (int s = 0; s < NQ; ++s) S.qk[s] = *reinterpret_cast<const double2*>(qv + bq + gb[s]);
+#pragma unroll
+        for (int s = 0; s < NRV; ++s) S.rk[s] = *reinterpret_cast<const double2*>(rv + bq + gb[s]);
     };
     auto fetch_c = [&](Stage& S, int c) {
 #pragma unroll
@@ -849,14 +856,18 @@ __global__ __launch_bounds__(NT) void k_rbgs_fused_rho(const T* __restrict__ pin
                     w2.x = par ? r : v;
                     w2.y = par ? v : r;
                     *reinterpret_cast<V2*>(pout + base + (long)(y - 2) * d.nx + 2 * m) = w2;
-                    if constexpr (DOTS > 0) {
+                    if constexpr (DOTS > 0 && sizeof(T) == 8) {
                         const T br2 = par ? S.bk[s].x : S.bk[s].y;
                         acc_b += bv * v + br2 * r;
+                    } else if constexpr (DOTS > 0) {
+                        const double rb = par ? S.rk[s].y : S.rk[s].x;
+                        const double rr = par ? S.rk[s].x : S.rk[s].y;
+                        acc_b += rb * (double)v + rr * (double)r;
                     }
                     if constexpr (DOTS == 2) {
                         const double qb = par ? S.qk[s].y : S.qk[s].x;
                         const double qr = par ? S.qk[s].x : S.qk[s].y;
-                        acc_q += qb * v + qr * r;
+                        acc_q += qb * (double)v + qr * (double)r;
                     }
                 }
             }
@@ -2354,7 +2365,15 @@ static void launch_fused(Level& L, T* pin, T* pout, hipStream_t st, bool finest,
         if (L.rho32) {
             // the float32 cycle's finest level from the float32 densities
             const int rx = L.d.nx / kRTX, ry = L.d.ny / kRTY, rz = L.d.nz / L.rtz;
-            if (zero)
+            if (dots && L.dots_q)
+                hipLaunchKernelGGL((k_rbgs_fused_rho<float, kRTX, kRTY, kRNT, false, 2>), dim3(rx * ry * rz),
+                                   dim3(kRNT), 0, st, pin, pout, A.b, L.rho32, L.d, h2, L.rtz, rx, ry, rz,
+                                   L.dots_q, L.dots_part, nullptr, L.dots_r);
+            else if (dots)
+                hipLaunchKernelGGL((k_rbgs_fused_rho<float, kRTX, kRTY, kRNT, false, 1>), dim3(rx * ry * rz),
+                                   dim3(kRNT), 0, st, pin, pout, A.b, L.rho32, L.d, h2, L.rtz, rx, ry, rz,
+                                   nullptr, L.dots_part, nullptr, L.dots_r);
+            else if (zero)
                 hipLaunchKernelGGL((k_rbgs_fused_rho<float, kRTX, kRTY, kRNT, true>), dim3(rx * ry * rz),
                                    dim3(kRNT), 0, st, pin, pout, A.b, L.rho32, L.d, h2, L.rtz, rx, ry, rz);
             else if (pe)
@@ -2510,7 +2529,7 @@ static void vcycle(mg_handle* m, int l, hipStream_t st, bool zero_start) {
                                dim3(cb), 0, st, cur, B.p, L.d);
         }
     }
-    cur = smooth<T>(L, cur, m->o.nu2, st, fin, false, sizeof(T) == 8 && L.dots_on, fold ? B.p : nullptr);
+    cur = smooth<T>(L, cur, m->o.nu2, st, fin, false, L.dots_on, fold ? B.p : nullptr);
     if (cur != A.p)
         (void)hipMemcpyAsync(A.p, cur, sizeof(T) * L.d.cells(), hipMemcpyDeviceToDevice, st);
 }
@@ -3046,8 +3065,9 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
     const int cg_wgs = cg_tx * cg_ty * cg_tz;
     IB_CHECK(!fused || cg_wgs <= kRed, IB_EINVAL, "mg_solve: too many workgroups for the partial sums");
     // the inner products of z = V(r) come from the last post-smoothing sweep
-    // of the finest level (sweep_wgs partial sums of each)
-    const bool fold = fused && !mixed && L0.fused && m->o.nu2 >= 1;
+    // of the finest level (sweep_wgs partial sums of each; the float32 sweep
+    // of the mixed cycle takes them against the float64 r)
+    const bool fold = fused && L0.fused && m->o.nu2 >= 1 && (!mixed || L0.rho32 != nullptr);
     const int sweep_wgs = fold ? (L0.d.nx / kRTX) * (L0.d.ny / kRTY) * (L0.d.nz / L0.rtz) : 0;
     IB_CHECK(sweep_wgs <= kRed, IB_EINVAL, "mg_solve: too many sweep workgroups for the partial sums");
     int it = 0, slot = KS_RZ0;
@@ -3075,6 +3095,7 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
             L0.dots_on = true;
             L0.dots_q = it == 0 ? nullptr : m->kq;
             L0.dots_part = pa;
+            L0.dots_r = m->kr;
         }
         precond();
         L0.dots_on = false;
