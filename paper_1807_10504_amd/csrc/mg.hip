@@ -1991,15 +1991,19 @@ __global__ __launch_bounds__(CG_NT) void k_cg_dir_apply_rho(const TZ* __restrict
 // then the y pair of the lower plane plus the y pair of the upper), so the
 // coarse right side is bitwise that kernel's. Reads p and rho 1.29 times (the
 // ring) and b once, instead of re-reading the neighbour rows and planes of
-// small blocks through the cache.
-__global__ __launch_bounds__(CG_NT) void k_resrestrict_rho(const double* __restrict__ p,
-                                                           const double* __restrict__ bb,
-                                                           const double* __restrict__ rho, Dims dm,
-                                                           double inv_h2, int TZr, int ntx, int nty,
-                                                           int nzc, double* __restrict__ bc) {
-    __shared__ double PP[3][CG_RN];
-    __shared__ double RR[3][CG_RN];
-    __shared__ double XS[2][CG_TY][CG_TX / 2];
+// small blocks through the cache. T = float: the float32 finest level of the
+// mixed cycle, its faces formed from the float32 densities as CoefRhoF forms
+// them (2 / (rho + rho') is 1 / rho exactly where the densities agree), so the
+// coarse right side is bitwise that of k_residual_restrict64<float, CoefRhoF>.
+template <typename T>
+__global__ __launch_bounds__(CG_NT) void k_resrestrict_rho(const T* __restrict__ p,
+                                                           const T* __restrict__ bb,
+                                                           const T* __restrict__ rho, Dims dm,
+                                                           T inv_h2, int TZr, int ntx, int nty,
+                                                           int nzc, T* __restrict__ bc) {
+    __shared__ T PP[3][CG_RN];
+    __shared__ T RR[3][CG_RN];
+    __shared__ T XS[2][CG_TY][CG_TX / 2];
     const int nw = ntx * nty * nzc;
     const int bid = blockIdx.x;
     const int w = (nw % 8 == 0) ? (bid % 8) * (nw / 8) + bid / 8 : bid;
@@ -2027,7 +2031,7 @@ __global__ __launch_bounds__(CG_NT) void k_resrestrict_rho(const double* __restr
     const long own = (long)(j0 + 1 + ly) * dm.nx + (i0 + 1 + lx);
     auto pl = [&](int k) { return (long)wrap_near(k, dm.nz) * plane; };
     struct Stage {
-        double p[CG_NL], r[CG_NL], b;
+        T p[CG_NL], r[CG_NL], b;
     };
     Stage SA, SB;
     // a stage carries p and rho of plane k + 1 (committed at the start of step
@@ -2074,39 +2078,39 @@ __global__ __launch_bounds__(CG_NT) void k_resrestrict_rho(const double* __restr
         const int kn = k + 2 < z1 ? k + 2 : z1 - 1;
         fetch_pr(S, kn);
         lds_barrier();
-        const double* Pc = PP[k % 3];
-        const double* Rc = RR[k % 3];
-        const double rc = Rc[c];
-        const double rxp = Rc[c + 1], rxm = Rc[c - 1], ryp = Rc[c + CG_RX], rym = Rc[c - CG_RX];
-        const double rzp = RR[(k + 1) % 3][c], rzm = RR[(k + 2) % 3][c];
-        double bxp, bxm, byp, bym, bzp, bzm;
+        const T* Pc = PP[k % 3];
+        const T* Rc = RR[k % 3];
+        const T rc = Rc[c];
+        const T rxp = Rc[c + 1], rxm = Rc[c - 1], ryp = Rc[c + CG_RX], rym = Rc[c - CG_RX];
+        const T rzp = RR[(k + 1) % 3][c], rzm = RR[(k + 2) % 3][c];
+        T bxp, bxm, byp, bym, bzp, bzm;
         if (rxp == rc && rxm == rc && ryp == rc && rym == rc && rzp == rc && rzm == rc) {
-            bxp = bxm = byp = bym = bzp = bzm = 1.0 / rc;
+            bxp = bxm = byp = bym = bzp = bzm = T(1) / rc;
         } else {
-            bxp = 2.0 / (rxp + rc);
-            bxm = 2.0 / (rc + rxm);
-            byp = 2.0 / (ryp + rc);
-            bym = 2.0 / (rc + rym);
-            bzp = 2.0 / (rzp + rc);
-            bzm = 2.0 / (rc + rzm);
+            bxp = T(2) / (rxp + rc);
+            bxm = T(2) / (rc + rxm);
+            byp = T(2) / (ryp + rc);
+            bym = T(2) / (rc + rym);
+            bzp = T(2) / (rzp + rc);
+            bzm = T(2) / (rc + rzm);
         }
-        const double pc = Pc[c];
-        double sv = bxp * (Pc[c + 1] - pc) - bxm * (pc - Pc[c - 1]);
+        const T pc = Pc[c];
+        T sv = bxp * (Pc[c + 1] - pc) - bxm * (pc - Pc[c - 1]);
         sv += byp * (Pc[c + CG_RX] - pc) - bym * (pc - Pc[c - CG_RX]);
         sv += bzp * (PP[(k + 1) % 3][c] - pc) - bzm * (pc - PP[(k + 2) % 3][c]);
-        const double r = S.b - sv * inv_h2;
+        const T r = S.b - sv * inv_h2;
         __builtin_amdgcn_sched_barrier(0);
         fetch_b(S, kn);
-        const double rx = r + __shfl_xor(r, 1);
+        const T rx = r + __shfl_xor(r, 1);
         if ((lx & 1) == 0) XS[k & 1][ly][lx >> 1] = rx;
         lds_barrier();
         if ((k & 1) && t < (CG_TX / 2) * (CG_TY / 2)) {
             const int cx = t % (CG_TX / 2), cy = t / (CG_TX / 2);
-            const double v = (XS[0][2 * cy][cx] + XS[0][2 * cy + 1][cx]) +
+            const T v = (XS[0][2 * cy][cx] + XS[0][2 * cy + 1][cx]) +
                              (XS[1][2 * cy][cx] + XS[1][2 * cy + 1][cx]);
             const int cnx = dm.nx >> 1, cny = dm.ny >> 1;
             const long o = ((long)(k >> 1) * cny + (ty * (CG_TY / 2) + cy)) * cnx + (tx * (CG_TX / 2) + cx);
-            bc[o] = v * 0.125;
+            bc[o] = v * T(0.125);
         }
         // the next commit overwrites plane k - 1's slot and the next plane's sums
         lds_barrier();
@@ -2436,8 +2440,8 @@ static void restrict_residual(Level& L, Level& C, const T* cur, hipStream_t st, 
             if (L.rho && L.d.ny % CG_TY == 0 && L.rtz > 0 && L.rtz % 2 == 0) {
                 // tiled z-march (nx % 64 == 0 where rho is set)
                 const int tx = L.d.nx / CG_TX, ty = L.d.ny / CG_TY, tz = L.d.nz / L.rtz;
-                hipLaunchKernelGGL(k_resrestrict_rho, dim3(tx * ty * tz), dim3(CG_NT), 0, st, cur, A.b, L.rho,
-                                   L.d, inv_h2, L.rtz, tx, ty, tz, B.b);
+                hipLaunchKernelGGL(k_resrestrict_rho<double>, dim3(tx * ty * tz), dim3(CG_NT), 0, st, cur, A.b,
+                                   L.rho, L.d, inv_h2, L.rtz, tx, ty, tz, B.b);
                 done = true;
             } else if (L.rho) {  // set only where nx % 64 == 0 in 3D
                 hipLaunchKernelGGL((k_residual_restrict64<double, CoefRho>), g64, dim3(kBlock), 0, st,
@@ -2445,7 +2449,13 @@ static void restrict_residual(Level& L, Level& C, const T* cur, hipStream_t st, 
                 done = true;
             }
         } else {
-            if (L.rho32 && L.d.nx % 64 == 0) {
+            if (L.rho32 && L.d.ny % CG_TY == 0 && L.rtz > 0 && L.rtz % 2 == 0 && L.d.nx % CG_TX == 0) {
+                // the same tiled z-march on the float32 densities
+                const int tx = L.d.nx / CG_TX, ty = L.d.ny / CG_TY, tz = L.d.nz / L.rtz;
+                hipLaunchKernelGGL(k_resrestrict_rho<float>, dim3(tx * ty * tz), dim3(CG_NT), 0, st, cur, A.b,
+                                   L.rho32, L.d, inv_h2, L.rtz, tx, ty, tz, B.b);
+                done = true;
+            } else if (L.rho32 && L.d.nx % 64 == 0) {
                 hipLaunchKernelGGL((k_residual_restrict64<float, CoefRhoF>), g64, dim3(kBlock), 0, st, cur, A.b,
                                    CoefRhoF{L.rho32}, L.d, inv_h2, B.b);
                 done = true;
