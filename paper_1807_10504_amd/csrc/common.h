@@ -169,6 +169,10 @@ int read_flags(Ctx* c, int* host_flags, hipStream_t st);
 
 // deterministic reduction helpers (fixed tree: block partials then one block)
 int device_sum(const double* partials_in, int n, double* out_dev, hipStream_t st);
+// two independent sums of n partials each in one launch (bitwise those of two
+// device_sum calls)
+int device_sum2(const double* partials0, const double* partials1, int n, double* out0, double* out1,
+                hipStream_t st);
 
 // pieces of the step shared by project_step and flow_step (api.hip)
 int spread_impl(Ctx* c, const ib_surface* s, int mode, double* const F[3], double* H, hipStream_t st);

@@ -326,15 +326,20 @@ int launch_coefficients(Ctx* c, const double* H, double rin, double rout, double
 // deterministic sums: fixed number of blocks, fixed tree inside a block
 constexpr int kRedBlocks = 1024;
 
-// One workgroup of 1024 threads; each thread keeps 8 accumulators so that its
-// loads are independent (one memory latency per 8192 partials instead of one
-// per load), then a fixed butterfly inside each wave and a fixed serial sum
-// over the 16 wave totals.
+// One workgroup of 1024 threads per sum; each thread keeps 8 accumulators so
+// that its loads are independent (one memory latency per 8192 partials instead
+// of one per load), then a fixed butterfly inside each wave and a fixed serial
+// sum over the 16 wave totals. Workgroup 1 (when launched) makes a second,
+// independent sum of as many partials the same way.
 constexpr int kSumThreads = 1024;
 
-__global__ __launch_bounds__(kSumThreads) void k_sum_final(const double* __restrict__ in, int n,
-                                                           double* __restrict__ out) {
+__global__ __launch_bounds__(kSumThreads) void k_sum_final(const double* __restrict__ in0, int n,
+                                                           double* __restrict__ out0,
+                                                           const double* __restrict__ in1,
+                                                           double* __restrict__ out1) {
     __shared__ double sh[kSumThreads / 64];
+    const double* __restrict__ in = blockIdx.x ? in1 : in0;
+    double* __restrict__ out = blockIdx.x ? out1 : out0;
     const int t = threadIdx.x;
     double a[8];
 #pragma unroll
@@ -360,7 +365,14 @@ __global__ __launch_bounds__(kSumThreads) void k_sum_final(const double* __restr
 }
 
 int device_sum(const double* partials, int n, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kSumThreads), 0, st, partials, n, out);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kSumThreads), 0, st, partials, n, out, partials, out);
+    IB_HIP(hipGetLastError());
+    return IB_OK;
+}
+
+int device_sum2(const double* partials0, const double* partials1, int n, double* out0, double* out1,
+                hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_final, dim3(2), dim3(kSumThreads), 0, st, partials0, n, out0, partials1, out1);
     IB_HIP(hipGetLastError());
     return IB_OK;
 }

@@ -2614,8 +2614,10 @@ static int fp64_norms(mg_handle* m, bool want_b, hipStream_t st, bool zero = fal
         hipLaunchKernelGGL((k_resid_norm<3, CoefArrays<double>>), dim3(nb), dim3(kBlock), 0, st,
                            L.f64.p, L.f64.b, co, L.d, inv_h2, pr, pb);
     }
-    IB_TRY(device_sum(pr, nb, m->red + 3 * kRed, st));
-    if (want_b) IB_TRY(device_sum(pb, nb, m->red + 3 * kRed + 1, st));
+    if (want_b)
+        IB_TRY(device_sum2(pr, pb, nb, m->red + 3 * kRed, m->red + 3 * kRed + 1, st));
+    else
+        IB_TRY(device_sum(pr, nb, m->red + 3 * kRed, st));
     IB_HIP(hipMemcpyAsync(m->host, m->red + 3 * kRed, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
     IB_HIP(hipStreamSynchronize(st));
     prof_drain();
@@ -2646,8 +2648,10 @@ static int mixed_defect(mg_handle* m, bool want_b, hipStream_t st, bool sync = t
                            L.f64.p, L.f64.b, co, L.d, inv_h2, L.f32.b, pr, pb);
     }
     if (!sync) return IB_OK;
-    IB_TRY(device_sum(pr, nb, m->red + 3 * kRed, st));
-    if (want_b) IB_TRY(device_sum(pb, nb, m->red + 3 * kRed + 1, st));
+    if (want_b)
+        IB_TRY(device_sum2(pr, pb, nb, m->red + 3 * kRed, m->red + 3 * kRed + 1, st));
+    else
+        IB_TRY(device_sum(pr, nb, m->red + 3 * kRed, st));
     IB_HIP(hipMemcpyAsync(m->host, m->red + 3 * kRed, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
     IB_HIP(hipStreamSynchronize(st));
     prof_drain();
@@ -3011,9 +3015,7 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
         else
             hipLaunchKernelGGL((k_residual_vec<3, CoefArrays<double>>), gr, blk, 0, st, x, b, co, L0.d,
                                inv_h2, m->kr, pa, pb);
-        int rc = device_sum(pa, parts, m->ks + KS_RR, st);
-        if (rc == IB_OK) rc = device_sum(pb, parts, m->ks + KS_BB, st);
-        return rc;
+        return device_sum2(pa, pb, parts, m->ks + KS_RR, m->ks + KS_BB, st);
     };
     IB_TRY(residual(zero));
     IB_HIP(hipMemcpyAsync(m->host, m->ks + KS_RR, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -3055,9 +3057,8 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
             hipLaunchKernelGGL((k_pcg_dots<float>), gr, blk, 0, st, m->kr, q, L0.f32.p, N, pa, pb);
         else
             hipLaunchKernelGGL((k_pcg_dots<double>), gr, blk, 0, st, m->kr, q, m->kz, N, pa, pb);
-        int rc = device_sum(pa, nb, m->ks + rz_slot, st);
-        if (rc == IB_OK && q) rc = device_sum(pb, nb, m->ks + KS_QZ, st);
-        return rc;
+        if (q) return device_sum2(pa, pb, nb, m->ks + rz_slot, m->ks + KS_QZ, st);
+        return device_sum(pa, nb, m->ks + rz_slot, st);
     };
     auto direction = [&](int rz_old_slot, int first) {
         if (mixed)
@@ -3112,8 +3113,10 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
         const int rz_old = slot;
         if (fold) {
             const int next = it == 0 ? slot : (slot == KS_RZ0 ? KS_RZ1 : KS_RZ0);
-            IB_TRY(device_sum(pa, sweep_wgs, m->ks + next, st));
-            if (it > 0) IB_TRY(device_sum(pa + sweep_wgs, sweep_wgs, m->ks + KS_QZ, st));
+            if (it > 0)
+                IB_TRY(device_sum2(pa, pa + sweep_wgs, sweep_wgs, m->ks + next, m->ks + KS_QZ, st));
+            else
+                IB_TRY(device_sum(pa, sweep_wgs, m->ks + next, st));
             slot = next;
         } else if (it == 0) {
             IB_TRY(dots(nullptr, slot));
@@ -3379,8 +3382,7 @@ extern "C" int mg_residual_norm_noalloc(const ib_grid* g, const double* rho, con
             hipLaunchKernelGGL((k_resid_norm<3, CoefRho>), dim3(parts), dim3(kBlock), 0, st, p, b,
                                CoefRho{rho}, L.d, inv_h2, pr, pb);
     }
-    IB_TRY(device_sum(pr, parts, sc + 2 * kRed, st));
-    IB_TRY(device_sum(pb, parts, sc + 2 * kRed + 1, st));
+    IB_TRY(device_sum2(pr, pb, parts, sc + 2 * kRed, sc + 2 * kRed + 1, st));
     hipLaunchKernelGGL(k_rel_from_sums, dim3(1), dim3(1), 0, st, sc + 2 * kRed, rel);
     IB_HIP(hipGetLastError());
     return IB_OK;
