@@ -637,6 +637,15 @@ int  ib_nn_create(const ib_grid* g, ib_nn** out);
 void ib_nn_destroy(ib_nn* nn);
 int  ib_nn_set_params(ib_nn* nn, const float* params, int count);
 int  ib_nn_get_params(ib_nn* nn, float* params, int count);
+/* Convolution kernel. IB_NN_CONV_AUTO (the default): in 3D with n[1] a
+ * multiple of 8, the tiled kernel (a workgroup keeps the layer's weights in
+ * LDS and marches a 64 x 8 tile along z, staging each input plane once for
+ * the three output planes it touches); otherwise, and with
+ * IB_NN_CONV_DIRECT, the direct kernel (a wave reads its input slab from
+ * memory for every tap). Both add the 27 taps of an output in the same order
+ * and give identical results. IB_EINVAL for another kind. */
+enum { IB_NN_CONV_AUTO = 0, IB_NN_CONV_DIRECT = 1 };
+int  ib_nn_set_conv(ib_nn* nn, int kind);
 /* p0 (device cells) from b, H (device cells; rho from H as in ib_coefficients),
  * p_prev (device cells or NULL = 0). */
 int  ib_nn_predict(ib_nn* nn, const double* b, const double* H, const double* p_prev,

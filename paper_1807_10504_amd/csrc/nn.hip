@@ -24,6 +24,7 @@
 // rows they touch in LDS and accumulates the (tap, co-block, ci-block)
 // 16 x 16 tiles; per-workgroup partials are summed in a fixed order.
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -174,6 +175,186 @@ __global__ __launch_bounds__(kBlock) void k_nn_conv(const u16* __restrict__ X, c
     const int px = lane >> 2, ch = (lane & 3) * 8;
     uint4 v = *reinterpret_cast<const uint4*>(&tile[wave][px][ch]);
     *reinterpret_cast<uint4*>(Y + (row0 + px) * kC + ch) = v;
+}
+
+// ---------------------------------------------------------------------------
+// 3D convolution, tiled: a 512-lane workgroup owns a 64 x 8 pixel tile
+// (x, y) over a range of planes. The layer's weights stay in LDS for the
+// whole range; each input plane (the tile with a one-pixel halo) is staged in
+// LDS once and feeds the three output planes it touches (kz = 0, 1, 2), so
+// every plane is read from memory once per range and every A fragment once
+// per (ky, kx). Wave w owns output row w of the tile: 4 blocks of 16 pixels x
+// 2 blocks of 16 output channels, for 3 output planes in flight. Every
+// accumulator receives its 27 taps in increasing tap order with the same
+// operands as k_nn_conv, so the two kernels give identical results.
+constexpr int kTX = 64, kTY = 8, kTThreads = 512;
+constexpr int kTRows = kTY + 2, kTPx = kTX + 2;
+constexpr int kTPxs = 68;                         // LDS pixel stride (bank spread)
+constexpr int kTPlane = kTRows * 4 * kTPxs;       // 16-byte units per staged plane
+constexpr int kTSlots = kTRows * kTPx * 4;        // 16-byte loads per plane
+constexpr int kTLoads = (kTSlots + kTThreads - 1) / kTThreads;
+constexpr int kTW = 27 * 2 * 64;                  // 16-byte weight fragments
+constexpr int kTWLoads = (kTW + kTThreads - 1) / kTThreads;
+
+template <int MODE, int R>
+__device__ __forceinline__ void conv3_plane(const bf16x8* __restrict__ P, const bf16x8* __restrict__ Ws,
+                                            f32x4 (&acc)[3][4][2], int w, int m, int kg, int lane) {
+    constexpr int NCB = MODE == 1 ? 1 : 2;  // MODE 1 stores channel 0 only
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc[R][j][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky) {
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+            bf16x8 a[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a[j] = P[((w + ky) * 4 + kg) * kTPxs + 16 * j + m + kx];
+            // this plane is input plane kz of the output plane held in set (R - kz) mod 3
+#pragma unroll
+            for (int kz = 0; kz < 3; ++kz) {
+                const int S = (R - kz + 3) % 3, tap = 9 * kz + 3 * ky + kx;
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) {
+                    const bf16x8 b = Ws[(tap * 2 + cb) * 64 + lane];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[S][j][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j], b, acc[S][j][cb], 0, 0, 0);
+                }
+            }
+        }
+    }
+}
+
+// bias / ReLU (MODE 0), channel 0 in float32 (MODE 1) or the ReLU mask of
+// act (MODE 2) for the 64 pixels of one output row starting at pixel row0
+template <int MODE>
+__device__ __forceinline__ void conv3_store(const f32x4 (&a)[4][2], long row0, const float* __restrict__ bias,
+                                            const u16* __restrict__ act, u16* __restrict__ Y,
+                                            float* __restrict__ Yf, u16 (*ep)[kC], int m, int kg, int lane) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const long r = row0 + 16 * j;
+        if (MODE == 1) {
+            if (m == 0) {
+                const float b0 = bias[0];
+                float4 o;
+                o.x = a[j][0][0] + b0;
+                o.y = a[j][0][1] + b0;
+                o.z = a[j][0][2] + b0;
+                o.w = a[j][0][3] + b0;
+                *reinterpret_cast<float4*>(Yf + r + 4 * kg) = o;
+            }
+            continue;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int px = 4 * kg + i;
+            float v0 = a[j][0][i], v1 = a[j][1][i];
+            if (MODE == 0) {
+                ep[px][m] = f2bf(fmaxf(v0 + bias[m], 0.f));
+                ep[px][16 + m] = f2bf(fmaxf(v1 + bias[16 + m], 0.f));
+            } else {
+                const u16* ar = act + (r + px) * kC;
+                const u16 h0 = f2bf(v0), h1 = f2bf(v1);
+                ep[px][m] = bf2f(ar[m]) > 0.f ? h0 : (u16)0;
+                ep[px][16 + m] = bf2f(ar[16 + m]) > 0.f ? h1 : (u16)0;
+            }
+        }
+        // the tile is private to the wave, whose LDS accesses complete in order
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int px = lane >> 2, ch = (lane & 3) * 8;
+        const uint4 v = *reinterpret_cast<const uint4*>(&ep[px][ch]);
+        *reinterpret_cast<uint4*>(Y + (r + px) * kC + ch) = v;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kTThreads) void k_nn_conv3_tiled(const u16* __restrict__ X,
+                                                              const u16* __restrict__ Wl,
+                                                              const float* __restrict__ bias,
+                                                              const u16* __restrict__ act,
+                                                              u16* __restrict__ Y, float* __restrict__ Yf,
+                                                              int D, int H, int W, int ZR) {
+    __shared__ bf16x8 Ws[kTW];
+    __shared__ bf16x8 Ps[2][kTPlane];
+    __shared__ u16 Ep[kTThreads / 64][16][kC];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int m = lane & 15, kg = lane >> 4;
+    const int ntx = W / kTX, nty = H / kTY, nzr = (D + ZR - 1) / ZR;
+    const int nb = ntx * nty * nzr, bid = blockIdx.x;
+    // blocks are dealt round-robin to the 8 XCDs: give each XCD a contiguous
+    // range of tiles so that neighbouring tiles share halo rows in its L2
+    const int wt = (nb % 8 == 0) ? (bid % 8) * (nb / 8) + bid / 8 : bid;
+    const int tx = wt % ntx, ty = (wt / ntx) % nty, zr = wt / (ntx * nty);
+    const int x0 = tx * kTX, y0 = ty * kTY, z0 = zr * ZR;
+    const int nz = min(ZR, D - z0), nt = nz + 2;  // input planes z0 - 1 .. z0 + nz
+    const long HW = (long)H * W;
+
+    // weights: LDS fragment (tap, cb, lane) = Wl[cb 16 + m][tap][8 kg .. 8 kg + 7]
+#pragma unroll
+    for (int s = 0; s < kTWLoads; ++s) {
+        const int q = tid + s * kTThreads;
+        if (q < kTW) {
+            const int l = q & 63, tc = q >> 6;
+            const int tap = tc >> 1, cb = tc & 1, mm = l & 15, kk = l >> 4;
+            Ws[q] = *reinterpret_cast<const bf16x8*>(Wl + ((cb * 16 + mm) * 27 + tap) * kC + kk * 8);
+        }
+    }
+    // plane staging: slot q = 16 bytes (chunk c of pixel px in halo row r);
+    // slots past the plane re-read slot 0 and are not stored
+    int goff[kTLoads], loff[kTLoads];
+#pragma unroll
+    for (int s = 0; s < kTLoads; ++s) {
+        int q = tid + s * kTThreads;
+        const bool v = q < kTSlots;
+        if (!v) q = 0;
+        const int c = q & 3, px = (q >> 2) % kTPx, r = (q >> 2) / kTPx;
+        goff[s] = (wrap_near(y0 - 1 + r, H) * W + wrap_near(x0 - 1 + px, W)) * kC + c * 8;
+        loff[s] = v ? (r * 4 + c) * kTPxs + px : -1;
+    }
+    bf16x8 pre[kTLoads];
+    auto fetch = [&](int t) {
+        const u16* base = X + (long)wrap_near(z0 - 1 + t, D) * HW * kC;
+#pragma unroll
+        for (int s = 0; s < kTLoads; ++s) pre[s] = *reinterpret_cast<const bf16x8*>(base + goff[s]);
+    };
+    auto commit = [&](int t) {
+        bf16x8* P = Ps[t & 1];
+#pragma unroll
+        for (int s = 0; s < kTLoads; ++s)
+            if (loff[s] >= 0) P[loff[s]] = pre[s];
+    };
+    fetch(0);
+    commit(0);
+    __syncthreads();
+
+    f32x4 acc[3][4][2];
+    // output row of this wave; pixel index of (z0 + u, y0 + wave, x0) is rowz + u H W
+    const long rowz = ((long)z0 * H + y0 + wave) * W + x0;
+    auto step = [&](auto rc, int t) {
+        constexpr int R = decltype(rc)::value;
+        const bool more = t + 1 < nt;
+        if (more) fetch(t + 1);
+        conv3_plane<MODE, R>(Ps[t & 1], Ws, acc, wave, m, kg, lane);
+        // input plane t completes output plane t - 2 (set (R + 1) mod 3)
+        if (t >= 2)
+            conv3_store<MODE>(acc[(R + 1) % 3], rowz + (long)(t - 2) * HW, bias, act, Y, Yf, Ep[wave], m, kg,
+                              lane);
+        if (more) commit(t + 1);
+        __syncthreads();
+    };
+    for (int t = 0; t < nt; t += 3) {
+        step(std::integral_constant<int, 0>{}, t);
+        if (t + 1 < nt) step(std::integral_constant<int, 1>{}, t + 1);
+        if (t + 2 < nt) step(std::integral_constant<int, 2>{}, t + 2);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -356,7 +537,42 @@ struct ib_nn {
     double* scale = nullptr;  // s_b, s_p, s_r
     double* host = nullptr;   // pinned
     int step = 0;
+    int conv = IB_NN_CONV_AUTO;
 };
+
+// planes per workgroup of the tiled kernel: 16, halved while the grid has
+// fewer than 1024 workgroups (at least 4)
+static int conv3_range(const ib_nn* n) {
+    const long xy = (long)(n->W / kTX) * (n->H / kTY);
+    int zr = 16;
+    while (zr > 4 && xy * ((n->D + zr - 1) / zr) < 1024) zr /= 2;
+    return zr;
+}
+
+static bool conv3_tiled(const ib_nn* n) {
+    return n->dim == 3 && n->conv == IB_NN_CONV_AUTO && n->W % kTX == 0 && n->H % kTY == 0;
+}
+
+// one convolution layer: MODE 0 (bias, ReLU), 1 (float32 channel 0) or 2
+// (input gradient through the ReLU mask of act)
+template <int MODE>
+static void nn_conv(const ib_nn* n, const u16* X, const u16* Wl, const float* bias, const u16* act, u16* Y,
+                    float* Yf, hipStream_t st) {
+    if (conv3_tiled(n)) {
+        const int zr = conv3_range(n);
+        const int nb = (n->W / kTX) * (n->H / kTY) * ((n->D + zr - 1) / zr);
+        hipLaunchKernelGGL((k_nn_conv3_tiled<MODE>), dim3(nb), dim3(kTThreads), 0, st, X, Wl, bias, act, Y, Yf,
+                           n->D, n->H, n->W, zr);
+        return;
+    }
+    dim3 grid(n->W / 64, n->H, n->D);
+    if (n->dim == 3)
+        hipLaunchKernelGGL((k_nn_conv<MODE, 3>), grid, dim3(kBlock), 0, st, X, Wl, bias, act, Y, Yf, n->D, n->H,
+                           n->W);
+    else
+        hipLaunchKernelGGL((k_nn_conv<MODE, 2>), grid, dim3(kBlock), 0, st, X, Wl, bias, act, Y, Yf, n->D, n->H,
+                           n->W);
+}
 
 static int nn_forward(ib_nn* n, const double* b, const double* H, const double* pp, double rin,
                       double rout, hipStream_t st) {
@@ -366,29 +582,14 @@ static int nn_forward(ib_nn* n, const double* b, const double* H, const double* 
     hipLaunchKernelGGL(k_nn_scales, dim3(1), dim3(kBlock), 0, st, n->red, nb, n->N, n->scale);
     hipLaunchKernelGGL(k_nn_input, dim3(grid_for(n->N)), dim3(kBlock), 0, st, b, H, pp, n->N, h2, rin,
                        rout, n->scale, n->act[0]);
-    dim3 grid(n->W / 64, n->H, n->D);
     const long ws = wsize(n->taps);
     for (int l = 0; l < kLayers; ++l) {
         const u16* Wl = n->Wl + (long)l * ws;
         const float* bias = n->bias + l * kC;
-        const bool last = l == kLayers - 1;
-        u16* Y = last ? nullptr : n->act[l + 1];
-        float* Yf = last ? n->yf : nullptr;
-        if (n->dim == 3) {
-            if (last)
-                hipLaunchKernelGGL((k_nn_conv<1, 3>), grid, dim3(kBlock), 0, st, n->act[l], Wl, bias,
-                                   nullptr, Y, Yf, n->D, n->H, n->W);
-            else
-                hipLaunchKernelGGL((k_nn_conv<0, 3>), grid, dim3(kBlock), 0, st, n->act[l], Wl, bias,
-                                   nullptr, Y, Yf, n->D, n->H, n->W);
-        } else {
-            if (last)
-                hipLaunchKernelGGL((k_nn_conv<1, 2>), grid, dim3(kBlock), 0, st, n->act[l], Wl, bias,
-                                   nullptr, Y, Yf, n->D, n->H, n->W);
-            else
-                hipLaunchKernelGGL((k_nn_conv<0, 2>), grid, dim3(kBlock), 0, st, n->act[l], Wl, bias,
-                                   nullptr, Y, Yf, n->D, n->H, n->W);
-        }
+        if (l == kLayers - 1)
+            nn_conv<1>(n, n->act[l], Wl, bias, nullptr, nullptr, n->yf, st);
+        else
+            nn_conv<0>(n, n->act[l], Wl, bias, nullptr, n->act[l + 1], nullptr, st);
     }
     IB_HIP(hipGetLastError());
     return IB_OK;
@@ -403,7 +604,6 @@ static int nn_backward(ib_nn* n, const double* b, const double* H, const double*
     hipLaunchKernelGGL(k_nn_loss, dim3(nb), dim3(kBlock), 0, st, n->yf, p, pp, n->scale, n->N, n->g[0],
                        n->red);
     IB_TRY(device_sum(n->red, nb, n->red + 4 * 1024, st));
-    dim3 grid(n->W / 64, n->H, n->D);
     const int ps = psize(n->taps);
     const long ws = wsize(n->taps);
     int cur = 0;
@@ -417,16 +617,8 @@ static int nn_backward(ib_nn* n, const double* b, const double* H, const double*
                                n->D, n->H, n->W, n->part);
         hipLaunchKernelGGL(k_nn_grad_reduce, dim3(grid_for(ps)), dim3(kBlock), 0, st, n->part,
                            kGradBlocks, ps, n->grad + (long)l * ps);
-        if (l > 0) {
-            if (n->dim == 3)
-                hipLaunchKernelGGL((k_nn_conv<2, 3>), grid, dim3(kBlock), 0, st, n->g[cur],
-                                   n->Wt + (long)l * ws, nullptr, n->act[l], n->g[1 - cur], nullptr,
-                                   n->D, n->H, n->W);
-            else
-                hipLaunchKernelGGL((k_nn_conv<2, 2>), grid, dim3(kBlock), 0, st, n->g[cur],
-                                   n->Wt + (long)l * ws, nullptr, n->act[l], n->g[1 - cur], nullptr,
-                                   n->D, n->H, n->W);
-        }
+        if (l > 0)
+            nn_conv<2>(n, n->g[cur], n->Wt + (long)l * ws, nullptr, n->act[l], n->g[1 - cur], nullptr, st);
         cur = 1 - cur;
     }
     IB_HIP(hipGetLastError());
@@ -507,6 +699,13 @@ extern "C" int ib_nn_create(const ib_grid* g, ib_nn** out) {
 }
 
 extern "C" void ib_nn_destroy(ib_nn* n) { nn_free(n); }
+
+extern "C" int ib_nn_set_conv(ib_nn* n, int kind) {
+    IB_CHECK(n, IB_EINVAL, "ib_nn_set_conv: null network");
+    IB_CHECK(kind == IB_NN_CONV_AUTO || kind == IB_NN_CONV_DIRECT, IB_EINVAL, "ib_nn_set_conv: unknown kind");
+    n->conv = kind;
+    return IB_OK;
+}
 
 long nn_cells(const ib_nn* nn) { return nn ? nn->N : 0; }
 
