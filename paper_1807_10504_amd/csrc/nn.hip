@@ -110,11 +110,18 @@ __global__ void k_nn_input(const double* __restrict__ b, const double* __restric
     float v0 = (float)(b[c] * h2 / scale[0]);
     float v1 = (float)((1.0 / (rout + (rin - rout) * H[c])) / scale[2]);
     float v2 = (float)((pp ? pp[c] : 0.0) / scale[1]);
-    u16* o = X + c * kC;
-    o[0] = f2bf(v0);
-    o[1] = f2bf(v1);
-    o[2] = f2bf(v2);
-    for (int q = 3; q < kC; ++q) o[q] = 0;
+    // channels 0 .. 2 and 29 zero channels as four 16-byte stores
+    uint4 q0;
+    q0.x = (unsigned)f2bf(v0) | ((unsigned)f2bf(v1) << 16);
+    q0.y = f2bf(v2);
+    q0.z = 0u;
+    q0.w = 0u;
+    const uint4 z = {0u, 0u, 0u, 0u};
+    uint4* o = reinterpret_cast<uint4*>(X + c * kC);
+    o[0] = q0;
+    o[1] = z;
+    o[2] = z;
+    o[3] = z;
 }
 
 // ---------------------------------------------------------------------------
@@ -196,14 +203,62 @@ constexpr int kTLoads = (kTSlots + kTThreads - 1) / kTThreads;
 constexpr int kTW = 27 * 2 * 64;                  // 16-byte weight fragments
 constexpr int kTWLoads = (kTW + kTThreads - 1) / kTThreads;
 
-template <int MODE, int R>
+// operands of one (ky, kx) step: the input fragments of the wave's 4 pixel
+// blocks and the weight fragments of the three taps (kz, ky, kx)
+struct Conv3Ops {
+    bf16x8 a[4];
+    bf16x8 b[3][2];
+};
+
+template <int NCB>
+__device__ __forceinline__ void conv3_load(Conv3Ops& o, const bf16x8* __restrict__ P,
+                                           const bf16x8* __restrict__ Ws, int i, int w, int m, int kg,
+                                           int lane) {
+    const int ky = i / 3, kx = i % 3;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o.a[j] = P[((w + ky) * 4 + kg) * kTPxs + 16 * j + m + kx];
+#pragma unroll
+    for (int kz = 0; kz < 3; ++kz)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) o.b[kz][cb] = Ws[((9 * kz + i) * 2 + cb) * 64 + lane];
+}
+
+// bit kz of mask: the output plane this input plane feeds as tap plane kz
+// lies in the range (a plane at either end of the march feeds fewer). The
+// full form loads the operands of step i + 1 while the matrix cores work on
+// step i.
+template <int MODE, int R, bool FULL>
 __device__ __forceinline__ void conv3_plane(const bf16x8* __restrict__ P, const bf16x8* __restrict__ Ws,
-                                            f32x4 (&acc)[3][4][2], int w, int m, int kg, int lane) {
+                                            f32x4 (&acc)[3][4][2], int w, int m, int kg, int lane, int mask) {
     constexpr int NCB = MODE == 1 ? 1 : 2;  // MODE 1 stores channel 0 only
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) acc[R][j][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // (the input-gradient form keeps the plain order: its epilogue leaves
+    // no registers for a second operand set)
+    if (FULL && MODE != 2) {
+        Conv3Ops o[2];
+        conv3_load<NCB>(o[0], P, Ws, 0, w, m, kg, lane);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            if (i + 1 < 9) conv3_load<NCB>(o[(i + 1) & 1], P, Ws, i + 1, w, m, kg, lane);
+            __builtin_amdgcn_sched_barrier(0);
+            const Conv3Ops& c = o[i & 1];
+#pragma unroll
+            for (int kz = 0; kz < 3; ++kz) {
+                const int S = (R - kz + 3) % 3;
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[S][j][cb] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(c.a[j], c.b[kz][cb], acc[S][j][cb], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        return;
+    }
 #pragma unroll
     for (int ky = 0; ky < 3; ++ky) {
 #pragma unroll
@@ -215,6 +270,7 @@ __device__ __forceinline__ void conv3_plane(const bf16x8* __restrict__ P, const 
 #pragma unroll
             for (int kz = 0; kz < 3; ++kz) {
                 const int S = (R - kz + 3) % 3, tap = 9 * kz + 3 * ky + kx;
+                if (!((mask >> kz) & 1)) continue;
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb) {
                     const bf16x8 b = Ws[(tap * 2 + cb) * 64 + lane];
@@ -342,7 +398,11 @@ __global__ __launch_bounds__(kTThreads) void k_nn_conv3_tiled(const u16* __restr
         constexpr int R = decltype(rc)::value;
         const bool more = t + 1 < nt;
         if (more) fetch(t + 1);
-        conv3_plane<MODE, R>(Ps[t & 1], Ws, acc, wave, m, kg, lane);
+        const int mask = (t < nz ? 1 : 0) | (t >= 1 && t <= nz ? 2 : 0) | (t >= 2 ? 4 : 0);
+        if (mask == 7)
+            conv3_plane<MODE, R, true>(Ps[t & 1], Ws, acc, wave, m, kg, lane, 7);
+        else
+            conv3_plane<MODE, R, false>(Ps[t & 1], Ws, acc, wave, m, kg, lane, mask);
         // input plane t completes output plane t - 2 (set (R + 1) mod 3)
         if (t >= 2)
             conv3_store<MODE>(acc[(R + 1) % 3], rowz + (long)(t - 2) * HW, bias, act, Y, Yf, Ep[wave], m, kg,
@@ -370,9 +430,17 @@ __global__ void k_nn_loss(const float* __restrict__ y, const double* __restrict_
         double t = (p[c] - (pp ? pp[c] : 0.0)) * inv_sp;
         double d = (double)y[c] - t;
         acc += d * d;
-        u16* o = G + c * kC;
-        o[0] = f2bf((float)(2.0 * d / (double)N));
-        for (int q = 1; q < kC; ++q) o[q] = 0;
+        uint4 q0;
+        q0.x = f2bf((float)(2.0 * d / (double)N));
+        q0.y = 0u;
+        q0.z = 0u;
+        q0.w = 0u;
+        const uint4 z = {0u, 0u, 0u, 0u};
+        uint4* o = reinterpret_cast<uint4*>(G + c * kC);
+        o[0] = q0;
+        o[1] = z;
+        o[2] = z;
+        o[3] = z;
     }
     double r = block_reduce_sum(acc, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = r;
@@ -544,7 +612,7 @@ struct ib_nn {
 // fewer than 1024 workgroups (at least 4)
 static int conv3_range(const ib_nn* n) {
     const long xy = (long)(n->W / kTX) * (n->H / kTY);
-    int zr = 16;
+    int zr = 32;
     while (zr > 4 && xy * ((n->D + zr - 1) / zr) < 1024) zr /= 2;
     return zr;
 }
