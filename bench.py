@@ -218,6 +218,12 @@ def bench_3d_nn(ib, torch, wl, geo, steps, warmup, sps64, pairs=24, train_iters=
                pairs_s=round(t_pairs, 2), train_iters=train_iters, train_s=round(t_train, 2),
                loss_first=float(np.mean(losses[:5])), loss_last=float(np.mean(losses[-10:])),
                inference_ms=round(1e3 * t_inf, 3))
+    # useful work of one inference: 2 x 27 taps x c_in x c_out per voxel and layer
+    # (channels 3 -> 32 x 5 -> 1), against the dense bf16 matrix-core peak
+    chans = (3, 32, 32, 32, 32, 32, 1)
+    flop = 2.0 * 27 * sum(a * b for a, b in zip(chans[:-1], chans[1:])) * n[0] * n[1] * n[2]
+    out["inference_tflops"] = round(flop / t_inf / 1e12, 1)
+    out["inference_frac_bf16_peak"] = round(flop / t_inf / 2.5e15, 3)
     for name, prec in (("fp64", ib.MG_FP64), ("mixed", ib.MG_MIXED)):
         log(f"== {name} flexible CG from the 3D network's guess, cold every step")
         r = run_variant(ib, torch, wl, geo, prec, steps, warmup, profile=False, krylov=1, nn=net)

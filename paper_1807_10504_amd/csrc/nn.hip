@@ -102,26 +102,24 @@ __global__ void k_nn_scales(const double* __restrict__ part, int nb, long N, dou
     }
 }
 
+// one lane per 16-byte chunk of a pixel's 32 bfloat16 channels (a wave
+// writes 16 whole pixels, 1 KB, with one store): chunk 0 holds channels
+// 0 .. 2, the rest are zero padding
 __global__ void k_nn_input(const double* __restrict__ b, const double* __restrict__ H,
                            const double* __restrict__ pp, long N, double h2, double rin, double rout,
                            const double* __restrict__ scale, u16* __restrict__ X) {
-    long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= N) return;
-    float v0 = (float)(b[c] * h2 / scale[0]);
-    float v1 = (float)((1.0 / (rout + (rin - rout) * H[c])) / scale[2]);
-    float v2 = (float)((pp ? pp[c] : 0.0) / scale[1]);
-    // channels 0 .. 2 and 29 zero channels as four 16-byte stores
-    uint4 q0;
-    q0.x = (unsigned)f2bf(v0) | ((unsigned)f2bf(v1) << 16);
-    q0.y = f2bf(v2);
-    q0.z = 0u;
-    q0.w = 0u;
-    const uint4 z = {0u, 0u, 0u, 0u};
-    uint4* o = reinterpret_cast<uint4*>(X + c * kC);
-    o[0] = q0;
-    o[1] = z;
-    o[2] = z;
-    o[3] = z;
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 4 * N) return;
+    const long c = q >> 2;
+    uint4 v = {0u, 0u, 0u, 0u};
+    if ((q & 3) == 0) {
+        float v0 = (float)(b[c] * h2 / scale[0]);
+        float v1 = (float)((1.0 / (rout + (rin - rout) * H[c])) / scale[2]);
+        float v2 = (float)((pp ? pp[c] : 0.0) / scale[1]);
+        v.x = (unsigned)f2bf(v0) | ((unsigned)f2bf(v1) << 16);
+        v.y = f2bf(v2);
+    }
+    reinterpret_cast<uint4*>(X)[q] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -648,7 +646,7 @@ static int nn_forward(ib_nn* n, const double* b, const double* H, const double* 
     double h2 = n->h * n->h;
     hipLaunchKernelGGL(k_nn_stats, dim3(nb), dim3(kBlock), 0, st, b, H, pp, n->N, h2, rin, rout, n->red);
     hipLaunchKernelGGL(k_nn_scales, dim3(1), dim3(kBlock), 0, st, n->red, nb, n->N, n->scale);
-    hipLaunchKernelGGL(k_nn_input, dim3(grid_for(n->N)), dim3(kBlock), 0, st, b, H, pp, n->N, h2, rin,
+    hipLaunchKernelGGL(k_nn_input, dim3(grid_for(4 * n->N)), dim3(kBlock), 0, st, b, H, pp, n->N, h2, rin,
                        rout, n->scale, n->act[0]);
     const long ws = wsize(n->taps);
     for (int l = 0; l < kLayers; ++l) {
