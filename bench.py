@@ -805,8 +805,9 @@ def bench_predictor_3d(ib, torch, nc=256, calls=5):
     secs = (time.perf_counter() - t0) / calls
     N = float(nc) ** 3
     s, c = float(np.mean(sw)), float(np.mean(ck))
-    # copy u -> u* 48 B, right side 120 B, per sweep 104 B (two colour passes), per residual check 64 B
-    algo = (48 + 120 + s * 104 + c * 64) * N
+    # copy u -> u* 48 B, right side 120 B, per sweep 88 B (x read and written, g, rho and mu read
+    # once: what any full sweep must move), per residual check 64 B
+    algo = (48 + 120 + s * 88 + c * 64) * N
     fl.close()
     return dict(workload=f"predictor_3d_{nc}: smooth drop, rho 1/1e-3, mu 1e-2/1e-4, dt 5e-5, rtol 1e-12",
                 ms_per_call=round(1e3 * secs, 3), sweeps=s, residual_checks=c,

@@ -373,6 +373,14 @@ void ib_flow_destroy(ib_flow* f);
 /* forget the history: the next predictor step is explicit Euler in the
  * advection and flow_step recomputes H of the current markers */
 int  ib_flow_reset(ib_flow* f);
+/* Sweep kernel of the predictor's red-black Gauss-Seidel. IB_FLOW_SWEEP_AUTO
+ * (the default): on 3D grids with n[0] a multiple of 32 and n[1] of 8, one
+ * single-pass sweep (a workgroup marches a 32 x 8 column tile along z,
+ * updating red cells of a plane and black cells of the plane below it from
+ * LDS); otherwise, and with IB_FLOW_SWEEP_COLOUR, one launch per colour. Both
+ * give identical results. IB_EINVAL for another kind. */
+enum { IB_FLOW_SWEEP_AUTO = 0, IB_FLOW_SWEEP_COLOUR = 1 };
+int  ib_flow_set_sweep(ib_flow* f, int kind);
 
 /* u* of eq ns1_new from u^n, the cell densities of levels n (rho_n, in C) and
  * n+1 (rho_np1, on the left), and the cell viscosities mu (both halves of

@@ -65,6 +65,15 @@ __host__ __device__ inline int wrap(int i, int n) {
 }
 
 // the same for -n <= i < 2n, without a division
+// (i, j, k) of cell c, x fastest; grids have fewer than 2^31 cells (checked
+// where they are made), so 32-bit divisions do, not the emulated 64-bit ones
+__device__ __forceinline__ void cell_ijk(long c, int nx, int ny, int& i, int& j, int& k) {
+    const unsigned cu = (unsigned)c, r = cu / (unsigned)nx;
+    i = (int)(cu - r * (unsigned)nx);
+    j = (int)(r % (unsigned)ny);
+    k = (int)(r / (unsigned)ny);
+}
+
 __host__ __device__ inline int wrap_near(int i, int n) {
     return i < 0 ? i + n : (i >= n ? i - n : i);
 }

@@ -49,10 +49,8 @@ struct Sten {
 
 template <int DIM>
 __device__ __forceinline__ Sten<DIM> sten_of(const Dims& d, long c) {
-    int i = (int)(c % d.nx);
-    long r = c / d.nx;
-    int j = (int)(r % d.ny);
-    int k = (int)(r / d.ny);
+    int i, j, k;
+    cell_ijk(c, d.nx, d.ny, i, j, k);
     return Sten<DIM>(d, i, j, k);
 }
 
@@ -84,6 +82,15 @@ __device__ double adv_flux_sum(const Sten<DIM>& S, long c, const double* const* 
     return acc;
 }
 
+// viscosity on the edge shared by the faces of cells c and c + e (both of
+// orientation d, e != d): the mean of the four cells around it, mc = mu[c],
+// md = mu[c - e_d], ma = mu[c + e], mad = mu[c + e - e_d]
+__device__ __forceinline__ double edge_mu(double mc, double md, double ma, double mad) {
+#pragma clang fp contract(off)
+    const double base = mc + md;
+    return 0.25 * ((base + ma) + mad);
+}
+
 // viscosities on the high (mp) and low (mm) side of the face of cell c along
 // each axis: the cells c, c - e_d along d, the 4-cell edge means across
 template <int DIM>
@@ -96,11 +103,29 @@ __device__ void visc_coefs(const Sten<DIM>& S, long c, const double* __restrict_
             mp[e] = mu[c];
             mm[e] = mu[cmd];
         } else {
-            const double base = mu[c] + mu[cmd];
-            mp[e] = 0.25 * ((base + mu[S.at(e, 1)]) + mu[S.at(e, 1, d, -1)]);
-            mm[e] = 0.25 * ((base + mu[S.at(e, -1)]) + mu[S.at(e, -1, d, -1)]);
+            mp[e] = edge_mu(mu[c], mu[cmd], mu[S.at(e, 1)], mu[S.at(e, 1, d, -1)]);
+            mm[e] = edge_mu(mu[c], mu[cmd], mu[S.at(e, -1)], mu[S.at(e, -1, d, -1)]);
         }
     }
+}
+
+// Gauss-Seidel value of one face of (rho_f/dt - D/2) x = g: xp / xm the
+// neighbours along +e / -e, mp / mm their viscosities (visc_coefs). Every
+// product and sum is rounded on its own, so the value does not depend on
+// how the kernel around it lets the compiler fuse multiply-adds (the
+// single-pass and the one-colour sweeps agree bit for bit).
+template <int DIM>
+__device__ __forceinline__ double helm_face(const double* mp, const double* mm, const double* xp,
+                                            const double* xm, double gv, double rf, double inv_dt,
+                                            double half_h2) {
+#pragma clang fp contract(off)
+    double sdiag = 0.0, nb = 0.0;
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) {
+        sdiag += mp[e] + mm[e];
+        nb += mp[e] * xp[e] + mm[e] * xm[e];
+    }
+    return (gv + half_h2 * nb) / (rf * inv_dt + half_h2 * sdiag);
 }
 
 // D_d at the face of cell c (eq cr_ni), times h^2
@@ -201,17 +226,225 @@ __global__ void k_helm_sweep(Out3 x, Vec3 g, const double* __restrict__ rho1,
     const double half_h2 = 0.5 / (d.h * d.h);
 #pragma unroll
     for (int q = 0; q < DIM; ++q) {
-        double mp[3], mm[3];
+        double mp[3], mm[3], xp[3], xm[3];
         visc_coefs<DIM>(S, c, mu, q, mp, mm);
         const double rf = 0.5 * (rho1[c] + rho1[S.at(q, -1)]);
-        double sdiag = 0.0, nb = 0.0;
         const double* xq = x.p[q];
 #pragma unroll
         for (int e = 0; e < DIM; ++e) {
-            sdiag += mp[e] + mm[e];
-            nb += mp[e] * xq[S.at(e, 1)] + mm[e] * xq[S.at(e, -1)];
+            xp[e] = xq[S.at(e, 1)];
+            xm[e] = xq[S.at(e, -1)];
         }
-        x.p[q][c] = (g.p[q][c] + half_h2 * nb) / (rf * inv_dt + half_h2 * sdiag);
+        x.p[q][c] = helm_face<DIM>(mp, mm, xp, xm, g.p[q][c], rf, inv_dt, half_h2);
+    }
+}
+
+// One full red-black sweep of the 3D system, every component, in a single
+// pass (nx % 32 == 0, ny % 8 == 0, nz % TZ == 0 with TZ even). A workgroup
+// owns a 32 x 8 column tile and the z-range [z0, z1) and marches upward: at
+// plane step k it updates the red cells of plane k on the tile and a
+// one-cell ring around it, then the black cells of plane k - 1 on the tile,
+// and writes plane k - 1. Ring values are recomputed by the neighbouring
+// tile from the same inputs, and x is double-buffered (read xin, write
+// xout), so no workgroup reads what another writes during the sweep: red
+// reads only old black values, black only new red values, as in the two
+// one-colour launches of k_helm_sweep, whose per-face arithmetic (helm_face,
+// edge_mu) it shares. The components' planes, mu and rho_f's densities are
+// staged in LDS over the tile and a two-cell halo, loaded into registers
+// two steps ahead; g is read where a cell is updated.
+constexpr int kHTX = 32, kHTY = 8;
+constexpr int kHRX = kHTX + 4, kHRY = kHTY + 4, kHRN = kHRX * kHRY;
+constexpr int kHLoads = (kHRN + kBlock - 1) / kBlock;
+constexpr int kHRedRow = (kHRX - 2) / 2, kHRedN = kHRedRow * (kHRY - 2);
+constexpr int kHBlackRow = kHTX / 2, kHBlackN = kHBlackRow * kHTY;
+
+__device__ __forceinline__ int hmod3(int k) { return ((k % 3) + 3) % 3; }
+
+__global__ __launch_bounds__(kBlock) void k_helm_fused(Vec3 xin, Out3 xout, Vec3 g,
+                                                       const double* __restrict__ rho1,
+                                                       const double* __restrict__ mu, Dims d, double inv_dt,
+                                                       int TZ, int ntx, int nty, int nzc) {
+    __shared__ double X[3][4][kHRN];
+    __shared__ double M[4][kHRN];
+    __shared__ double R[3][kHRN];
+    const int nw = ntx * nty * nzc;
+    const int bid = blockIdx.x;
+    // blocks are dealt round-robin to the 8 XCDs: give each XCD a contiguous
+    // range of tiles so that halo rows are shared in its L2
+    const int w = (nw % 8 == 0) ? (bid % 8) * (nw / 8) + bid / 8 : bid;
+    const int tx = w % ntx;
+    const int r0 = w / ntx;
+    const int ty = r0 % nty;
+    const int zc = r0 / nty;
+    const int i0 = tx * kHTX - 2, j0 = ty * kHTY - 2;
+    const int z0 = zc * TZ, z1 = z0 + TZ;
+    const long plane = (long)d.nx * d.ny;
+    const double half_h2 = 0.5 / (d.h * d.h);
+    const int t = threadIdx.x;
+    // tile origins are at least -2 and regions end within one period
+    auto gofs = [&](int x, int y) { return wrap_near(j0 + y, d.ny) * d.nx + wrap_near(i0 + x, d.nx); };
+    // every lane issues every load (slots past the region re-read its first
+    // cell and are not stored)
+    int gp[kHLoads];
+    bool vp[kHLoads];
+#pragma unroll
+    for (int s = 0; s < kHLoads; ++s) {
+        const int q = t + s * kBlock;
+        vp[s] = q < kHRN;
+        gp[s] = vp[s] ? gofs(q % kHRX, q / kHRX) : gofs(0, 0);
+    }
+    // planes z0 - 2 .. z1 + 2 lie within one period of the box
+    auto pl = [&](int k) { return (long)wrap_near(k, d.nz) * plane; };
+    // the lane's red cell of plane k (region position; lanes past the red
+    // cells take the first) and black cell of plane k - 1 (past the black
+    // cells: the first); every lane updates at most one of each
+    static_assert(kHRedN <= kBlock && kHBlackN <= kBlock, "one red and one black cell per lane");
+    const bool has_red = t < kHRedN, has_black = t < kHBlackN;
+    const int ry = 1 + (has_red ? t : 0) / kHRedRow, rm = (has_red ? t : 0) % kHRedRow;
+    const int by = 2 + (has_black ? t : 0) / kHBlackRow, bm = (has_black ? t : 0) % kHBlackRow;
+    auto red_x = [&](int k) { return 1 + ((i0 + 1 + j0 + ry + k) & 1) + 2 * rm; };
+    auto black_par = [&](int kb) { return (i0 + 3 + j0 + by + kb) & 1; };
+    // register stages, alternating: x and mu of plane k + 1, the densities
+    // of plane k, g at the lane's red cell of plane k and black cell of plane k - 1
+    struct Stage {
+        double x[3][kHLoads], m[kHLoads], r[kHLoads], gr[3], gb[3];
+    };
+    Stage SA, SB;
+    // planes at the step's commit, g after the step has used it: no value is
+    // overwritten while its load is in flight
+    auto fetch_planes = [&](Stage& S, int k) {
+        const long bu = pl(k + 1), bk = pl(k);
+#pragma unroll
+        for (int s = 0; s < kHLoads; ++s) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) S.x[q][s] = xin.p[q][bu + gp[s]];
+            S.m[s] = mu[bu + gp[s]];
+            S.r[s] = rho1[bk + gp[s]];
+        }
+    };
+    auto fetch_g = [&](Stage& S, int k) {
+        const long gr = pl(k) + gofs(red_x(k), ry);
+        const long gb = pl(k - 1) + gofs(2 + black_par(k - 1) + 2 * bm, by);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            S.gr[q] = g.p[q][gr];
+            S.gb[q] = g.p[q][gb];
+        }
+    };
+    auto commit = [&](const Stage& S, int k) {
+#pragma unroll
+        for (int s = 0; s < kHLoads; ++s)
+            if (s * kBlock + kBlock <= kHRN || vp[s]) {
+                const int c = t + s * kBlock;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) X[q][(k + 1) & 3][c] = S.x[q][s];
+                M[(k + 1) & 3][c] = S.m[s];
+                R[hmod3(k)][c] = S.r[s];
+            }
+    };
+    {
+        const long a = pl(z0 - 2), a1 = pl(z0 - 1);
+#pragma unroll
+        for (int s = 0; s < kHLoads; ++s)
+            if (vp[s]) {
+                const int c = t + s * kBlock;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    X[q][(z0 - 2) & 3][c] = xin.p[q][a + gp[s]];
+                    X[q][(z0 - 1) & 3][c] = xin.p[q][a1 + gp[s]];
+                }
+                M[(z0 - 2) & 3][c] = mu[a + gp[s]];
+                M[(z0 - 1) & 3][c] = mu[a1 + gp[s]];
+                R[hmod3(z0 - 2)][c] = rho1[a + gp[s]];
+            }
+    }
+    fetch_planes(SA, z0 - 1);
+    fetch_g(SA, z0 - 1);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch_planes(SB, z0);
+    fetch_g(SB, z0);
+    // component q of the cell at region position (x, y) of plane kk
+    auto update = [&](int q, int x, int y, int kk, double gv) {
+        const int c = y * kHRX + x;
+        const double* Xc = X[q][kk & 3];
+        const double* Xd = X[q][(kk - 1) & 3];
+        const double* Xu = X[q][(kk + 1) & 3];
+        const double* Mc = M[kk & 3];
+        const double* Md = M[(kk - 1) & 3];
+        const double* Mu = M[(kk + 1) & 3];
+        const double* Rc = R[hmod3(kk)];
+        const double xp[3] = {Xc[c + 1], Xc[c + kHRX], Xu[c]};
+        const double xm[3] = {Xc[c - 1], Xc[c - kHRX], Xd[c]};
+        double mp[3], mm[3], rf;
+        if (q == 0) {
+            mp[0] = Mc[c];
+            mm[0] = Mc[c - 1];
+            mp[1] = edge_mu(Mc[c], Mc[c - 1], Mc[c + kHRX], Mc[c + kHRX - 1]);
+            mm[1] = edge_mu(Mc[c], Mc[c - 1], Mc[c - kHRX], Mc[c - kHRX - 1]);
+            mp[2] = edge_mu(Mc[c], Mc[c - 1], Mu[c], Mu[c - 1]);
+            mm[2] = edge_mu(Mc[c], Mc[c - 1], Md[c], Md[c - 1]);
+            rf = 0.5 * (Rc[c] + Rc[c - 1]);
+        } else if (q == 1) {
+            mp[0] = edge_mu(Mc[c], Mc[c - kHRX], Mc[c + 1], Mc[c + 1 - kHRX]);
+            mm[0] = edge_mu(Mc[c], Mc[c - kHRX], Mc[c - 1], Mc[c - 1 - kHRX]);
+            mp[1] = Mc[c];
+            mm[1] = Mc[c - kHRX];
+            mp[2] = edge_mu(Mc[c], Mc[c - kHRX], Mu[c], Mu[c - kHRX]);
+            mm[2] = edge_mu(Mc[c], Mc[c - kHRX], Md[c], Md[c - kHRX]);
+            rf = 0.5 * (Rc[c] + Rc[c - kHRX]);
+        } else {
+            mp[0] = edge_mu(Mc[c], Md[c], Mc[c + 1], Md[c + 1]);
+            mm[0] = edge_mu(Mc[c], Md[c], Mc[c - 1], Md[c - 1]);
+            mp[1] = edge_mu(Mc[c], Md[c], Mc[c + kHRX], Md[c + kHRX]);
+            mm[1] = edge_mu(Mc[c], Md[c], Mc[c - kHRX], Md[c - kHRX]);
+            mp[2] = Mc[c];
+            mm[2] = Md[c];
+            rf = 0.5 * (Rc[c] + R[hmod3(kk - 1)][c]);
+        }
+        return helm_face<3>(mp, mm, xp, xm, gv, rf, inv_dt, half_h2);
+    };
+    auto step = [&](Stage& S, int k) {
+        commit(S, k);
+        // in flight for two steps; past the range it re-reads plane z1 (not
+        // committed), which keeps the loads unconditional
+        const int kn = k + 2 <= z1 ? k + 2 : z1;
+        fetch_planes(S, kn);
+        __syncthreads();
+        // red cells of plane k on the tile and its one-cell ring
+        if (has_red) {
+            const int x = red_x(k);
+            double v[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) v[q] = update(q, x, ry, k, S.gr[q]);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) X[q][k & 3][ry * kHRX + x] = v[q];
+        }
+        __syncthreads();
+        const int kb = k - 1;
+        if (kb >= z0 && kb < z1 && has_black) {
+            // black cells of plane k - 1 on the tile, written with the red cell
+            // beside them (the pair starts at an even x)
+            const long base = pl(kb) + (long)(j0 + 2) * d.nx + (i0 + 2);
+            const int par = black_par(kb);
+            const int xb = 2 + par + 2 * bm;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const double v = update(q, xb, by, kb, S.gb[q]);
+                const double r = X[q][kb & 3][by * kHRX + 3 - par + 2 * bm];
+                double2 w2;
+                w2.x = par ? r : v;
+                w2.y = par ? v : r;
+                *reinterpret_cast<double2*>(xout.p[q] + base + (long)(by - 2) * d.nx + 2 * bm) = w2;
+            }
+        }
+        fetch_g(S, kn);
+        // the next commit overwrites the planes below k - 1
+        __syncthreads();
+    };
+    // steps z0 - 1 .. z1 in pairs (stage A, stage B); TZ is even
+    for (int k = z0 - 1; k <= z1; k += 2) {
+        step(SA, k);
+        step(SB, k + 1);
     }
 }
 
@@ -275,7 +508,20 @@ struct ib_flow {
     ib_indicator* ind = nullptr;  // conventional scheme: indicator of eq ind_psn
     SurfMesh mesh;                // 3D: the moving surface's connectivity on the device
     double* prop = nullptr;       // the indicator field of the step
+    double* alt[3] = {nullptr, nullptr, nullptr};  // second x of the single-pass 3D sweep
+    int sweep = IB_FLOW_SWEEP_AUTO;
 };
+
+// the single-pass sweep applies to 3D grids of whole 32 x 8 column tiles
+static bool helm_tiled_grid(const Dims& d) { return d.dim == 3 && d.nx % kHTX == 0 && d.ny % kHTY == 0; }
+
+// planes per workgroup of the single-pass sweep: the largest of 16, 8, 4, 2
+// that divides nz
+static int helm_tz(const Dims& d) {
+    for (int tz = 16; tz > 2; tz /= 2)
+        if (d.nz % tz == 0) return tz;
+    return 2;
+}
 
 static void free_flow(ib_flow* f) {
     if (!f) return;
@@ -286,7 +532,7 @@ static void free_flow(ib_flow* f) {
         if (f->g[q]) hipFree(f->g[q]);
         if (f->ustar[q]) hipFree(f->ustar[q]);
     }
-    for (double* p : {f->Hn, f->rho_n, f->mu, f->red, f->mred, f->prop})
+    for (double* p : {f->Hn, f->rho_n, f->mu, f->red, f->mred, f->prop, f->alt[0], f->alt[1], f->alt[2]})
         if (p) hipFree(p);
     if (f->ind) ib_indicator_destroy(f->ind);
     f->mesh.release();
@@ -318,6 +564,8 @@ extern "C" int ib_flow_create(const ib_grid* g, ib_flow** out) {
         alloc(&f->g[q], bytes);
         alloc(&f->ustar[q], bytes);
     }
+    if (helm_tiled_grid(f->d))
+        for (int q = 0; q < 3; ++q) alloc(&f->alt[q], bytes);
     alloc(&f->Hn, bytes);
     alloc(&f->rho_n, bytes);
     alloc(&f->mu, bytes);
@@ -333,6 +581,14 @@ extern "C" int ib_flow_create(const ib_grid* g, ib_flow** out) {
 }
 
 extern "C" void ib_flow_destroy(ib_flow* f) { free_flow(f); }
+
+extern "C" int ib_flow_set_sweep(ib_flow* f, int kind) {
+    IB_CHECK(f, IB_EINVAL, "ib_flow_set_sweep: null handle");
+    IB_CHECK(kind == IB_FLOW_SWEEP_AUTO || kind == IB_FLOW_SWEEP_COLOUR, IB_EINVAL,
+             "ib_flow_set_sweep: unknown kind");
+    f->sweep = kind;
+    return IB_OK;
+}
 
 extern "C" int ib_flow_reset(ib_flow* f) {
     IB_CHECK(f, IB_EINVAL, "ib_flow_reset: null handle");
@@ -425,20 +681,38 @@ static int predict_impl(ib_flow* f, const double* const u[3], const double* rho_
     double rel = 0.0;
     S->first_step = first;
     S->checks = 0;
+    // the single-pass sweep alternates between u* and f->alt; cur holds the
+    // latest iterate, copied into u* at the end
+    const bool tiled = f->sweep == IB_FLOW_SWEEP_AUTO && helm_tiled_grid(d) && f->alt[0];
+    const int tz = helm_tz(d), hx = d.nx / kHTX, hy = d.ny / kHTY;
+    double* cur[3] = {ustar[0], ustar[1], ustar[2]};
+    double* oth[3] = {f->alt[0], f->alt[1], f->alt[2]};
+    auto settle = [&]() -> int {
+        if (cur[0] != ustar[0])
+            for (int q = 0; q < dim; ++q)
+                IB_HIP(hipMemcpyAsync(ustar[q], cur[q], sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+        return IB_OK;
+    };
     while (true) {
-        for (int colour = 0; colour < 2; ++colour) {
-            if (dim == 2)
-                hipLaunchKernelGGL(k_helm_sweep<2>, gh, blk, 0, st, out3(ustar, 2), vec3(gc, 2), rho1, mu,
-                                   d, inv_dt, colour);
-            else
-                hipLaunchKernelGGL(k_helm_sweep<3>, gh, blk, 0, st, out3(ustar, 3), vec3(gc, 3), rho1, mu,
-                                   d, inv_dt, colour);
+        if (tiled) {
+            hipLaunchKernelGGL(k_helm_fused, dim3(hx * hy * (d.nz / tz)), blk, 0, st, vec3(cur, 3), out3(oth, 3),
+                               vec3(gc, 3), rho1, mu, d, inv_dt, tz, hx, hy, d.nz / tz);
+            std::swap(cur, oth);
+        } else {
+            for (int colour = 0; colour < 2; ++colour) {
+                if (dim == 2)
+                    hipLaunchKernelGGL(k_helm_sweep<2>, gh, blk, 0, st, out3(ustar, 2), vec3(gc, 2), rho1, mu,
+                                       d, inv_dt, colour);
+                else
+                    hipLaunchKernelGGL(k_helm_sweep<3>, gh, blk, 0, st, out3(ustar, 3), vec3(gc, 3), rho1, mu,
+                                       d, inv_dt, colour);
+            }
         }
         ++sweeps;
         // the residual is read from one sweep before the previous call's count on
         if (sweeps < f->last_sweeps - 1 && sweeps < max_sweeps) continue;
         ++S->checks;
-        const double* xc[3] = {ustar[0], ustar[1], ustar[2]};
+        const double* xc[3] = {cur[0], cur[1], cur[2]};
         if (dim == 2)
             hipLaunchKernelGGL(k_helm_resid<2>, dim3(nb), blk, 0, st, vec3(xc, 2), vec3(gc, 2), rho1, mu, d,
                                inv_dt, f->red);
@@ -453,11 +727,13 @@ static int predict_impl(ib_flow* f, const double* const u[3], const double* rho_
         if (!std::isfinite(rr) || !std::isfinite(gg)) {
             S->sweeps = sweeps;
             S->rel_res = rr;
+            IB_TRY(settle());
             return fail(IB_ENAN, "ib_predict: residual is not finite");
         }
         if (gg == 0.0) {
             // g = 0: the (nonsingular) system has the solution 0
             for (int q = 0; q < dim; ++q) IB_HIP(hipMemsetAsync(ustar[q], 0, sizeof(double) * N, st));
+            for (int q = 0; q < 3; ++q) cur[q] = ustar[q];
             rel = 0.0;
             break;
         }
@@ -466,9 +742,11 @@ static int predict_impl(ib_flow* f, const double* const u[3], const double* rho_
         if (sweeps >= max_sweeps) {
             S->sweeps = sweeps;
             S->rel_res = rel;
+            IB_TRY(settle());
             return fail(IB_ENOTCONV, "ib_predict: the implicit viscous system did not converge");
         }
     }
+    IB_TRY(settle());
     S->sweeps = sweeps;
     S->rel_res = rel;
     f->last_sweeps = sweeps;

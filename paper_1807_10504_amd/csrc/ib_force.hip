@@ -210,10 +210,8 @@ __global__ void k_irrot_force(const double* __restrict__ X, const int32_t* __res
                               double* __restrict__ F, int* __restrict__ flags) {
     long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.cells()) return;
-    int i = (int)(c % d.nx);
-    long r = c / d.nx;
-    int j = (int)(r % d.ny);
-    int k = (int)(r / d.ny);
+    int i, j, k;
+    cell_ijk(c, d.nx, d.ny, i, j, k);
     int ic = comp == 0 ? i : (comp == 1 ? j : k);
     int nn = comp == 0 ? d.nx : (comp == 1 ? d.ny : d.nz);
     long stride = comp == 0 ? 1 : (comp == 1 ? (long)d.nx : (long)d.nx * d.ny);
@@ -288,10 +286,8 @@ __global__ void k_coefficients(const double* __restrict__ H, Dims d, double rin,
                                double* __restrict__ b2, double* __restrict__ rho) {
     long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.cells()) return;
-    int i = (int)(c % d.nx);
-    long r = c / d.nx;
-    int j = (int)(r % d.ny);
-    int k = (int)(r / d.ny);
+    int i, j, k;
+    cell_ijk(c, d.nx, d.ny, i, j, k);
     double drho = rin - rout;
     double rc = cell_density(rout, drho, H[c]);
     if (rho) rho[c] = rc;
@@ -402,10 +398,8 @@ __global__ void k_rhs(const double* __restrict__ u0, const double* __restrict__ 
     long N = d.cells();
     double inv_h = 1.0 / d.h;
     for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long)gridDim.x * blockDim.x) {
-        int i = (int)(c % d.nx);
-        long r = c / d.nx;
-        int j = (int)(r % d.ny);
-        int k = (int)(r / d.ny);
+        int i, j, k;
+        cell_ijk(c, d.nx, d.ny, i, j, k);
         long cx = i == d.nx - 1 ? c - (d.nx - 1) : c + 1;
         long cy = j == d.ny - 1 ? c - (long)(d.ny - 1) * d.nx : c + d.nx;
         long mx = 0, my = 0;
@@ -480,10 +474,8 @@ __global__ void k_update(const double* __restrict__ u0, const double* __restrict
                          double* __restrict__ o2) {
     long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.cells()) return;
-    int i = (int)(c % d.nx);
-    long r = c / d.nx;
-    int j = (int)(r % d.ny);
-    int k = (int)(r / d.ny);
+    int i, j, k;
+    cell_ijk(c, d.nx, d.ny, i, j, k);
     double inv_h = 1.0 / d.h;
     double pc = p[c];
     long cx = i == 0 ? c + d.nx - 1 : c - 1;
@@ -559,10 +551,8 @@ __global__ void k_diag(const double* __restrict__ p, const double* __restrict__ 
             q[5] += F0[c];
             q[6] += F1[c];
             if (DIM == 3) q[7] += F2[c];
-            int i = (int)(c % d.nx);
-            long r = c / d.nx;
-            int j = (int)(r % d.ny);
-            int k = (int)(r / d.ny);
+            int i, j, k;
+            cell_ijk(c, d.nx, d.ny, i, j, k);
             long cx = i == 0 ? c + d.nx - 1 : c - 1;
             long cy = j == 0 ? c + (long)(d.ny - 1) * d.nx : c - d.nx;
             // index-form curl, (x, y) plane

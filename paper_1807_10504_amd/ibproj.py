@@ -21,6 +21,7 @@ IB_SPREAD_IRROT, IB_SPREAD_DELTA = 0, 1
 MG_FP64, MG_MIXED = 0, 1
 WS_ZERO, WS_PREV, WS_NN = 0, 1, 2
 NN_CONV_AUTO, NN_CONV_DIRECT = 0, 1
+FLOW_SWEEP_AUTO, FLOW_SWEEP_COLOUR = 0, 1
 
 EXPORTS = ("ib_create", "ib_destroy", "ib_bin_markers", "ib_interp", "ib_spread",
            "ib_coefficients", "ib_density", "ib_rhs", "ib_update", "mg_setup", "mg_update_coeffs",
@@ -28,7 +29,7 @@ EXPORTS = ("ib_create", "ib_destroy", "ib_bin_markers", "ib_interp", "ib_spread"
            "mg_destroy", "mg_residual_norm", "mg_residual_norm_noalloc", "project_step", "ib_relocate_bspline",
            "ib_surface_geometry_3d", "ib_nn_param_count", "ib_nn_create", "ib_nn_destroy",
            "ib_nn_set_params", "ib_nn_get_params", "ib_nn_predict", "ib_nn_gradients",
-           "ib_nn_train_step", "ib_nn_set_conv",
+           "ib_nn_train_step", "ib_nn_set_conv", "ib_flow_set_sweep",
            "ib_diagnostics", "ib_profile_enable", "ib_profile_reset", "ib_profile_read",
            "ib_advection", "ib_viscous", "ib_flow_create", "ib_flow_destroy", "ib_flow_reset",
            "ib_predict", "flow_step", "ib_axi_create", "ib_axi_destroy", "axi_project_step",
@@ -167,6 +168,7 @@ def load(path: str = LIB_PATH):
         "ib_nn_create": (i32, [P(Grid), P(vp)]),
         "ib_nn_destroy": (None, [vp]),
         "ib_nn_set_conv": (i32, [vp, i32]),
+        "ib_flow_set_sweep": (i32, [vp, i32]),
         "ib_nn_set_params": (i32, [vp, vp, i32]),
         "ib_nn_get_params": (i32, [vp, vp, i32]),
         "ib_nn_predict": (i32, [vp, vp, vp, vp, f64, f64, vp, vp]),
@@ -528,6 +530,10 @@ class Flow:
 
     def reset(self):
         _check(self.lib.ib_flow_reset(self.ptr))
+
+    def set_sweep(self, kind):
+        """FLOW_SWEEP_AUTO (single-pass sweep where the grid allows) or FLOW_SWEEP_COLOUR."""
+        _check(self.lib.ib_flow_set_sweep(self.ptr, int(kind)))
 
     def predict(self, u, rho_n, rho_np1, mu, dt, rtol=1e-12, max_sweeps=200, u_star=None):
         """u* of eq ns1_new; returns (u_star, stats dict)."""

@@ -6,7 +6,8 @@
   value);
 * ib_predict against the oracle's exactly solved Crank-Nicolson system, first
   step (Euler advection) and second step (Adams-Bashforth history kept in
-  the handle), 2D and 3D, ratio 1000 densities (1e-11 relative L2);
+  the handle), 2D and 3D, ratio 1000 densities (1e-11 relative L2); the 3D
+  single-pass sweep against the one-colour launches bit for bit;
 * a single shear mode is multiplied by the Crank-Nicolson factor;
 * flow_step: three steps of the full 2D method against oracle.flow_step_2d
   (markers, velocity, pressure);
@@ -119,6 +120,47 @@ def test_predict_parity_two_steps(ib, shape):
     fl.reset()
     _, st3 = fl.predict(ud, dev(rho), dev(rho1), dev(mu), dt, rtol=1e-13)
     assert st3["first_step"] == 1
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 64), (10, 24, 32), (4, 8, 32), (6, 8, 96)])
+def test_predict_single_pass_sweep_identical(ib, shape):
+    """The 3D single-pass sweep (32 x 8 column tiles marching along z) against
+    one launch per colour: u* and the statistics bit for bit over two steps
+    (Euler, then with the Adams-Bashforth history). The shapes give one and
+    several tiles in x and y and z-ranges of 16, 2 and 4 planes (10 and 6
+    planes: ranges of 2), down to a depth of 4 where the halo planes wrap."""
+    n = tuple(reversed(shape))
+    h = 1.0 / n[0]
+    dt = 2e-4
+    u, H, rho, mu = _fields(shape, 84)
+    rng = np.random.default_rng(85)
+    rho1 = poisson.density(np.clip(H + 0.05 * rng.standard_normal(shape) * (H > 0) * (H < 1), 0, 1),
+                           1.0, 1e-3)
+    du = [0.1 * rng.standard_normal(shape) for _ in range(3)]
+    out = {}
+    for kind in (ib.FLOW_SWEEP_COLOUR, ib.FLOW_SWEEP_AUTO):
+        fl = ib.Flow(3, n, h)
+        fl.set_sweep(kind)
+        us, st = fl.predict([dev(a) for a in u], dev(rho), dev(rho1), dev(mu), dt, rtol=1e-13)
+        first = [host(a) for a in us]
+        us2, st2 = fl.predict([dev(a + b) for a, b in zip(first, du)], dev(rho1), dev(rho), dev(mu), dt,
+                              rtol=1e-13)
+        out[kind] = (first, st, [host(a) for a in us2], st2)
+        fl.close()
+    c, t = out[ib.FLOW_SWEEP_COLOUR], out[ib.FLOW_SWEEP_AUTO]
+    print(f"{shape}: sweeps {c[1]['sweeps']}, {c[3]['sweeps']} / {t[1]['sweeps']}, {t[3]['sweeps']}")
+    for q in range(3):
+        assert np.array_equal(c[0][q], t[0][q])
+        assert np.array_equal(c[2][q], t[2][q])
+    for a, b in ((c[1], t[1]), (c[3], t[3])):
+        assert a["sweeps"] == b["sweeps"] and a["rel_res"] == b["rel_res"]
+
+
+def test_flow_set_sweep_rejects_unknown_kind(ib):
+    fl = ib.Flow(3, (32, 8, 4), 1.0 / 32)
+    with pytest.raises(ib.IbError):
+        fl.set_sweep(5)
+    fl.close()
 
 
 def test_predict_crank_nicolson_mode(ib):
