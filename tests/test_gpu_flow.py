@@ -122,13 +122,14 @@ def test_predict_parity_two_steps(ib, shape):
     assert st3["first_step"] == 1
 
 
-@pytest.mark.parametrize("shape", [(16, 16, 64), (10, 24, 32), (4, 8, 32), (6, 8, 96)])
+@pytest.mark.parametrize("shape", [(16, 16, 64), (10, 24, 32), (4, 8, 32), (6, 8, 96), (8, 32, 64)])
 def test_predict_single_pass_sweep_identical(ib, shape):
     """The 3D single-pass sweep (32 x 8 column tiles marching along z) against
     one launch per colour: u* and the statistics bit for bit over two steps
     (Euler, then with the Adams-Bashforth history). The shapes give one and
-    several tiles in x and y and z-ranges of 16, 2 and 4 planes (10 and 6
-    planes: ranges of 2), down to a depth of 4 where the halo planes wrap."""
+    several 32 x 8 tiles in x and y, and z-ranges of 16, 8, 4 and 2 planes
+    (10 and 6 planes: ranges of 2), down to a depth of 4 where the halo
+    planes wrap."""
     n = tuple(reversed(shape))
     h = 1.0 / n[0]
     dt = 2e-4
