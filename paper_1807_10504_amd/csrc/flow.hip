@@ -128,6 +128,53 @@ __device__ __forceinline__ double helm_face(const double* mp, const double* mm, 
     return (gv + half_h2 * nb) / (rf * inv_dt + half_h2 * sdiag);
 }
 
+// (rho_f/dt - D/2) x at one face, x = xc, its neighbours xp / xm along +e /
+// -e and their viscosities mp / mm (every product and sum rounded on its own)
+template <int DIM>
+__device__ __forceinline__ double helm_apply(const double* mp, const double* mm, const double* xp,
+                                             const double* xm, double xc, double rf, double inv_dt,
+                                             double inv_h2) {
+#pragma clang fp contract(off)
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) acc += mp[e] * (xp[e] - xc) - mm[e] * (xc - xm[e]);
+    return rf * inv_dt * xc - 0.5 * acc * inv_h2;
+}
+
+// the viscosities of visc_coefs and rho_f of face q of the cell at offset c
+// of LDS planes laid out with row length RX: M* the viscosities of the plane
+// (c), below (d) and above (u) it, Rc / Rd the densities of the plane and below
+template <int RX>
+__device__ __forceinline__ void lds_coefs(int q, int c, const double* Mc, const double* Md, const double* Mu,
+                                          const double* Rc, const double* Rd, double* mp, double* mm,
+                                          double& rf) {
+    if (q == 0) {
+        mp[0] = Mc[c];
+        mm[0] = Mc[c - 1];
+        mp[1] = edge_mu(Mc[c], Mc[c - 1], Mc[c + RX], Mc[c + RX - 1]);
+        mm[1] = edge_mu(Mc[c], Mc[c - 1], Mc[c - RX], Mc[c - RX - 1]);
+        mp[2] = edge_mu(Mc[c], Mc[c - 1], Mu[c], Mu[c - 1]);
+        mm[2] = edge_mu(Mc[c], Mc[c - 1], Md[c], Md[c - 1]);
+        rf = 0.5 * (Rc[c] + Rc[c - 1]);
+    } else if (q == 1) {
+        mp[0] = edge_mu(Mc[c], Mc[c - RX], Mc[c + 1], Mc[c + 1 - RX]);
+        mm[0] = edge_mu(Mc[c], Mc[c - RX], Mc[c - 1], Mc[c - 1 - RX]);
+        mp[1] = Mc[c];
+        mm[1] = Mc[c - RX];
+        mp[2] = edge_mu(Mc[c], Mc[c - RX], Mu[c], Mu[c - RX]);
+        mm[2] = edge_mu(Mc[c], Mc[c - RX], Md[c], Md[c - RX]);
+        rf = 0.5 * (Rc[c] + Rc[c - RX]);
+    } else {
+        mp[0] = edge_mu(Mc[c], Md[c], Mc[c + 1], Md[c + 1]);
+        mm[0] = edge_mu(Mc[c], Md[c], Mc[c - 1], Md[c - 1]);
+        mp[1] = edge_mu(Mc[c], Md[c], Mc[c + RX], Md[c + RX]);
+        mm[1] = edge_mu(Mc[c], Md[c], Mc[c - RX], Md[c - RX]);
+        mp[2] = Mc[c];
+        mm[2] = Md[c];
+        rf = 0.5 * (Rc[c] + Rd[c]);
+    }
+}
+
 // D_d at the face of cell c (eq cr_ni), times h^2
 template <int DIM>
 __device__ double visc_sum(const Sten<DIM>& S, long c, const double* __restrict__ ud,
@@ -376,31 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_helm_fused(Vec3 xin, Out3 xout, Vec3
         const double xp[3] = {Xc[c + 1], Xc[c + kHRX], Xu[c]};
         const double xm[3] = {Xc[c - 1], Xc[c - kHRX], Xd[c]};
         double mp[3], mm[3], rf;
-        if (q == 0) {
-            mp[0] = Mc[c];
-            mm[0] = Mc[c - 1];
-            mp[1] = edge_mu(Mc[c], Mc[c - 1], Mc[c + kHRX], Mc[c + kHRX - 1]);
-            mm[1] = edge_mu(Mc[c], Mc[c - 1], Mc[c - kHRX], Mc[c - kHRX - 1]);
-            mp[2] = edge_mu(Mc[c], Mc[c - 1], Mu[c], Mu[c - 1]);
-            mm[2] = edge_mu(Mc[c], Mc[c - 1], Md[c], Md[c - 1]);
-            rf = 0.5 * (Rc[c] + Rc[c - 1]);
-        } else if (q == 1) {
-            mp[0] = edge_mu(Mc[c], Mc[c - kHRX], Mc[c + 1], Mc[c + 1 - kHRX]);
-            mm[0] = edge_mu(Mc[c], Mc[c - kHRX], Mc[c - 1], Mc[c - 1 - kHRX]);
-            mp[1] = Mc[c];
-            mm[1] = Mc[c - kHRX];
-            mp[2] = edge_mu(Mc[c], Mc[c - kHRX], Mu[c], Mu[c - kHRX]);
-            mm[2] = edge_mu(Mc[c], Mc[c - kHRX], Md[c], Md[c - kHRX]);
-            rf = 0.5 * (Rc[c] + Rc[c - kHRX]);
-        } else {
-            mp[0] = edge_mu(Mc[c], Md[c], Mc[c + 1], Md[c + 1]);
-            mm[0] = edge_mu(Mc[c], Md[c], Mc[c - 1], Md[c - 1]);
-            mp[1] = edge_mu(Mc[c], Md[c], Mc[c + kHRX], Md[c + kHRX]);
-            mm[1] = edge_mu(Mc[c], Md[c], Mc[c - kHRX], Md[c - kHRX]);
-            mp[2] = Mc[c];
-            mm[2] = Md[c];
-            rf = 0.5 * (Rc[c] + R[hmod3(kk - 1)][c]);
-        }
+        lds_coefs<kHRX>(q, c, Mc, Md, Mu, Rc, R[hmod3(kk - 1)], mp, mm, rf);
         return helm_face<3>(mp, mm, xp, xm, gv, rf, inv_dt, half_h2);
     };
     auto step = [&](Stage& S, int k) {
@@ -448,6 +471,135 @@ __global__ __launch_bounds__(kBlock) void k_helm_fused(Vec3 xin, Out3 xout, Vec3
     }
 }
 
+// Block partials of ||g - M x||^2 and ||g||^2 on 3D grids of whole 32 x 8
+// column tiles: a workgroup marches its tile over the z-range [z0, z1), one
+// cell per lane and plane, with x, mu and the densities of the tile and a
+// one-cell ring staged in LDS two steps ahead and g in registers. The
+// per-face values are those of k_helm_resid (helm_apply, lds_coefs); the sums
+// run in another order.
+constexpr int kQRX = kHTX + 2, kQRY = 8 + 2, kQRN = kQRX * kQRY;
+constexpr int kQLoads = (kQRN + kBlock - 1) / kBlock;
+
+__global__ __launch_bounds__(kBlock) void k_helm_resid_tiled(Vec3 x, Vec3 g, const double* __restrict__ rho1,
+                                                             const double* __restrict__ mu, Dims d, double inv_dt,
+                                                             int TZ, int ntx, int nty, int nzc,
+                                                             double* __restrict__ part) {
+    static_assert(kHTX * 8 == kBlock, "one tile cell per lane");
+    __shared__ double X[3][3][kQRN];
+    __shared__ double M[3][kQRN];
+    __shared__ double R[2][kQRN];
+    __shared__ double sh[kBlock];
+    const int nw = ntx * nty * nzc;
+    const int bid = blockIdx.x;
+    const int w = (nw % 8 == 0) ? (bid % 8) * (nw / 8) + bid / 8 : bid;
+    const int tx = w % ntx;
+    const int r0 = w / ntx;
+    const int ty = r0 % nty;
+    const int zc = r0 / nty;
+    const int i0 = tx * kHTX - 1, j0 = ty * 8 - 1;
+    const int z0 = zc * TZ, z1 = z0 + TZ;
+    const long plane = (long)d.nx * d.ny;
+    const double inv_h2 = 1.0 / (d.h * d.h);
+    const int t = threadIdx.x;
+    auto gofs = [&](int xx, int yy) { return wrap_near(j0 + yy, d.ny) * d.nx + wrap_near(i0 + xx, d.nx); };
+    int gp[kQLoads];
+    bool vp[kQLoads];
+#pragma unroll
+    for (int s = 0; s < kQLoads; ++s) {
+        const int q = t + s * kBlock;
+        vp[s] = q < kQRN;
+        gp[s] = vp[s] ? gofs(q % kQRX, q / kQRX) : gofs(0, 0);
+    }
+    auto pl = [&](int k) { return (long)wrap_near(k, d.nz) * plane; };
+    // the lane's cell: region position (cx, cy), its offset in the plane
+    const int cx = 1 + t % kHTX, cy = 1 + t / kHTX, cc = cy * kQRX + cx;
+    const int go = gofs(cx, cy);
+    auto m3 = [](int k) { return ((k % 3) + 3) % 3; };
+    // register stages, alternating: x and mu of plane k + 1, the densities and g of plane k
+    struct Stage {
+        double x[3][kQLoads], m[kQLoads], r[kQLoads], gv[3];
+    };
+    Stage SA, SB;
+    auto fetch_planes = [&](Stage& S, int k) {
+        const long bu = pl(k + 1), bk = pl(k);
+#pragma unroll
+        for (int s = 0; s < kQLoads; ++s) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) S.x[q][s] = x.p[q][bu + gp[s]];
+            S.m[s] = mu[bu + gp[s]];
+            S.r[s] = rho1[bk + gp[s]];
+        }
+    };
+    auto fetch_g = [&](Stage& S, int k) {
+        const long b = pl(k) + go;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) S.gv[q] = g.p[q][b];
+    };
+    auto commit = [&](const Stage& S, int k) {
+#pragma unroll
+        for (int s = 0; s < kQLoads; ++s)
+            if (s * kBlock + kBlock <= kQRN || vp[s]) {
+                const int c = t + s * kBlock;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) X[q][m3(k + 1)][c] = S.x[q][s];
+                M[m3(k + 1)][c] = S.m[s];
+                R[k & 1][c] = S.r[s];
+            }
+    };
+    {
+        const long a = pl(z0 - 1), a1 = pl(z0);
+#pragma unroll
+        for (int s = 0; s < kQLoads; ++s)
+            if (vp[s]) {
+                const int c = t + s * kBlock;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    X[q][m3(z0 - 1)][c] = x.p[q][a + gp[s]];
+                    X[q][m3(z0)][c] = x.p[q][a1 + gp[s]];
+                }
+                M[m3(z0 - 1)][c] = mu[a + gp[s]];
+                M[m3(z0)][c] = mu[a1 + gp[s]];
+                R[(z0 - 1) & 1][c] = rho1[a + gp[s]];
+            }
+    }
+    fetch_planes(SA, z0);
+    fetch_g(SA, z0);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch_planes(SB, z0 + 1);
+    fetch_g(SB, z0 + 1);
+    double rr = 0.0, gg = 0.0;
+    auto step = [&](Stage& S, int k) {
+        commit(S, k);
+        const int kn = k + 2 < z1 ? k + 2 : z1 - 1;
+        fetch_planes(S, kn);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const double* Xc = X[q][m3(k)];
+            const double xp[3] = {Xc[cc + 1], Xc[cc + kQRX], X[q][m3(k + 1)][cc]};
+            const double xm[3] = {Xc[cc - 1], Xc[cc - kQRX], X[q][m3(k - 1)][cc]};
+            double mp[3], mm[3], rf;
+            lds_coefs<kQRX>(q, cc, M[m3(k)], M[m3(k - 1)], M[m3(k + 1)], R[k & 1], R[(k - 1) & 1], mp, mm, rf);
+            const double Mx = helm_apply<3>(mp, mm, xp, xm, Xc[cc], rf, inv_dt, inv_h2);
+            const double gv = S.gv[q];
+            rr += (gv - Mx) * (gv - Mx);
+            gg += gv * gv;
+        }
+        fetch_g(S, kn);
+        // the next commit overwrites the plane below k
+        __syncthreads();
+    };
+    // steps z0 .. z1 - 1 in pairs (stage A, stage B); TZ is even
+    for (int k = z0; k < z1; k += 2) {
+        step(SA, k);
+        step(SB, k + 1);
+    }
+    double s = block_reduce_sum(rr, sh);
+    if (t == 0) part[bid] = s;
+    s = block_reduce_sum(gg, sh);
+    if (t == 0) part[kFlowRed + bid] = s;
+}
+
 // block partials of ||g - M x||^2 and ||g||^2
 template <int DIM>
 __global__ void k_helm_resid(Vec3 x, Vec3 g, const double* __restrict__ rho1,
@@ -461,10 +613,16 @@ __global__ void k_helm_resid(Vec3 x, Vec3 g, const double* __restrict__ rho1,
         const Sten<DIM> S = sten_of<DIM>(d, c);
 #pragma unroll
         for (int q = 0; q < DIM; ++q) {
-            double mp[3], mm[3];
+            double mp[3], mm[3], xp[3], xm[3];
             visc_coefs<DIM>(S, c, mu, q, mp, mm);
             const double rf = 0.5 * (rho1[c] + rho1[S.at(q, -1)]);
-            const double Mx = rf * inv_dt * x.p[q][c] - 0.5 * visc_sum<DIM>(S, c, x.p[q], mp, mm) * inv_h2;
+            const double* xq = x.p[q];
+#pragma unroll
+            for (int e = 0; e < DIM; ++e) {
+                xp[e] = xq[S.at(e, 1)];
+                xm[e] = xq[S.at(e, -1)];
+            }
+            const double Mx = helm_apply<DIM>(mp, mm, xp, xm, xq[c], rf, inv_dt, inv_h2);
             const double gv = g.p[q][c];
             rr += (gv - Mx) * (gv - Mx);
             gg += gv * gv;
@@ -685,6 +843,12 @@ static int predict_impl(ib_flow* f, const double* const u[3], const double* rho_
     // latest iterate, copied into u* at the end
     const bool tiled = f->sweep == IB_FLOW_SWEEP_AUTO && helm_tiled_grid(d) && f->alt[0];
     const int tz = helm_tz(d), hx = d.nx / kHTX, hy = d.ny / kHTY;
+    // planes per workgroup of the tiled residual: the fewest (even, dividing
+    // nz) that keep the workgroups within the partial-sum buffer (0: none does)
+    int rtz = 0;
+    if (tiled)
+        for (int z = 2; z <= d.nz && !rtz; z *= 2)
+            if (d.nz % z == 0 && (long)hx * hy * (d.nz / z) <= kFlowRed) rtz = z;
     double* cur[3] = {ustar[0], ustar[1], ustar[2]};
     double* oth[3] = {f->alt[0], f->alt[1], f->alt[2]};
     auto settle = [&]() -> int {
@@ -713,14 +877,19 @@ static int predict_impl(ib_flow* f, const double* const u[3], const double* rho_
         if (sweeps < f->last_sweeps - 1 && sweeps < max_sweeps) continue;
         ++S->checks;
         const double* xc[3] = {cur[0], cur[1], cur[2]};
-        if (dim == 2)
+        int nbr = nb;  // partial sums written
+        if (tiled && rtz > 0) {
+            nbr = hx * (d.ny / 8) * (d.nz / rtz);
+            hipLaunchKernelGGL(k_helm_resid_tiled, dim3(nbr), blk, 0, st, vec3(xc, 3), vec3(gc, 3), rho1, mu, d,
+                               inv_dt, rtz, hx, d.ny / 8, d.nz / rtz, f->red);
+        } else if (dim == 2)
             hipLaunchKernelGGL(k_helm_resid<2>, dim3(nb), blk, 0, st, vec3(xc, 2), vec3(gc, 2), rho1, mu, d,
                                inv_dt, f->red);
         else
             hipLaunchKernelGGL(k_helm_resid<3>, dim3(nb), blk, 0, st, vec3(xc, 3), vec3(gc, 3), rho1, mu, d,
                                inv_dt, f->red);
-        IB_TRY(device_sum(f->red, nb, f->red + 2 * kFlowRed, st));
-        IB_TRY(device_sum(f->red + kFlowRed, nb, f->red + 2 * kFlowRed + 1, st));
+        IB_TRY(device_sum(f->red, nbr, f->red + 2 * kFlowRed, st));
+        IB_TRY(device_sum(f->red + kFlowRed, nbr, f->red + 2 * kFlowRed + 1, st));
         IB_HIP(hipMemcpyAsync(f->host, f->red + 2 * kFlowRed, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
         IB_HIP(hipStreamSynchronize(st));
         const double rr = f->host[0], gg = f->host[1];
