@@ -54,28 +54,50 @@ __device__ __forceinline__ Sten<DIM> sten_of(const Dims& d, long c) {
     return Sten<DIM>(d, i, j, k);
 }
 
+// The stencils below read their fields through accessors, u(q, a, s, b, t)
+// = component q at cell c + s e_a + t e_b (f(a, s, b, t) for one field), so
+// the one-thread-per-cell kernels (global memory through Sten) and the
+// tiled ones (LDS planes) share one arithmetic. Every product and sum is
+// rounded on its own: the two forms agree bit for bit.
+template <int DIM>
+struct GlobVec {
+    const Sten<DIM>& S;
+    const double* const* u;
+    __device__ double operator()(int q, int a, int s, int b = 0, int t = 0) const { return u[q][S.at(a, s, b, t)]; }
+};
+template <int DIM>
+struct GlobField {
+    const Sten<DIM>& S;
+    const double* f;
+    __device__ double operator()(int a, int s, int b = 0, int t = 0) const { return f[S.at(a, s, b, t)]; }
+};
+// one component of a vector accessor as a field accessor
+template <class UA>
+struct CompOf {
+    const UA& u;
+    int q;
+    __device__ double operator()(int a, int s, int b = 0, int t = 0) const { return u(q, a, s, b, t); }
+};
+
 // surface sum of u u . ds over the control volume of the d-face of cell c
 // (eq ad_bf without the density), over h^(DIM-1); C_d is the face density
 // times this over h (eq ns_1 has rho outside the divergence)
-template <int DIM>
-__device__ double adv_flux_sum(const Sten<DIM>& S, long c, const double* const* u, int d) {
-    const double* ud = u[d];
-    const long cmd = S.at(d, -1);
+template <int DIM, class UA>
+__device__ __forceinline__ double adv_flux(const UA& u, int d) {
+#pragma clang fp contract(off)
+    const double udc = u(d, 0, 0), udmd = u(d, d, -1);
     double acc = 0.0;
 #pragma unroll
     for (int e = 0; e < DIM; ++e) {
         if (e == d) {
-            const double up = 0.5 * (ud[S.at(d, 1)] + ud[c]);
-            const double um = 0.5 * (ud[c] + ud[cmd]);
+            const double up = 0.5 * (u(d, d, 1) + udc);
+            const double um = 0.5 * (udc + udmd);
             acc += up * up - um * um;
         } else {
-            const double* ue = u[e];
-            const long cp = S.at(e, 1), cpd = S.at(e, 1, d, -1);
-            const long cm = S.at(e, -1), cmm = S.at(e, -1, d, -1);
-            const double vep = 0.5 * (ue[cp] + ue[cpd]);
-            const double udp = 0.5 * (ud[c] + ud[cp]);
-            const double vem = 0.5 * (ue[c] + ue[cmd]);
-            const double udm = 0.5 * (ud[c] + ud[cm]);
+            const double vep = 0.5 * (u(e, e, 1) + u(e, e, 1, d, -1));
+            const double udp = 0.5 * (udc + u(d, e, 1));
+            const double vem = 0.5 * (u(e, 0, 0) + u(e, d, -1));
+            const double udm = 0.5 * (udc + u(d, e, -1));
             acc += vep * udp - vem * udm;
         }
     }
@@ -93,20 +115,26 @@ __device__ __forceinline__ double edge_mu(double mc, double md, double ma, doubl
 
 // viscosities on the high (mp) and low (mm) side of the face of cell c along
 // each axis: the cells c, c - e_d along d, the 4-cell edge means across
-template <int DIM>
-__device__ void visc_coefs(const Sten<DIM>& S, long c, const double* __restrict__ mu, int d,
-                           double* mp, double* mm) {
-    const long cmd = S.at(d, -1);
+template <int DIM, class FA>
+__device__ __forceinline__ void visc_coefs_acc(const FA& mu, int d, double* mp, double* mm) {
+    const double mc = mu(0, 0), md = mu(d, -1);
 #pragma unroll
     for (int e = 0; e < DIM; ++e) {
         if (e == d) {
-            mp[e] = mu[c];
-            mm[e] = mu[cmd];
+            mp[e] = mc;
+            mm[e] = md;
         } else {
-            mp[e] = edge_mu(mu[c], mu[cmd], mu[S.at(e, 1)], mu[S.at(e, 1, d, -1)]);
-            mm[e] = edge_mu(mu[c], mu[cmd], mu[S.at(e, -1)], mu[S.at(e, -1, d, -1)]);
+            mp[e] = edge_mu(mc, md, mu(e, 1), mu(e, 1, d, -1));
+            mm[e] = edge_mu(mc, md, mu(e, -1), mu(e, -1, d, -1));
         }
     }
+}
+
+template <int DIM>
+__device__ void visc_coefs(const Sten<DIM>& S, long c, const double* __restrict__ mu, int d,
+                           double* mp, double* mm) {
+    (void)c;
+    visc_coefs_acc<DIM>(GlobField<DIM>{S, mu}, d, mp, mm);
 }
 
 // Gauss-Seidel value of one face of (rho_f/dt - D/2) x = g: xp / xm the
@@ -175,16 +203,36 @@ __device__ __forceinline__ void lds_coefs(int q, int c, const double* Mc, const 
     }
 }
 
-// D_d at the face of cell c (eq cr_ni), times h^2
-template <int DIM>
-__device__ double visc_sum(const Sten<DIM>& S, long c, const double* __restrict__ ud,
-                           const double* mp, const double* mm) {
-    const double uc = ud[c];
+// D_d at the face of cell c (eq cr_ni), times h^2; ud the face values of component d
+template <int DIM, class FA>
+__device__ __forceinline__ double visc_sum_acc(const FA& ud, const double* mp, const double* mm) {
+#pragma clang fp contract(off)
+    const double uc = ud(0, 0);
     double acc = 0.0;
 #pragma unroll
-    for (int e = 0; e < DIM; ++e)
-        acc += mp[e] * (ud[S.at(e, 1)] - uc) - mm[e] * (uc - ud[S.at(e, -1)]);
+    for (int e = 0; e < DIM; ++e) acc += mp[e] * (ud(e, 1) - uc) - mm[e] * (uc - ud(e, -1));
     return acc;
+}
+
+// the right side of the implicit system and the advection term at face q of
+// one cell: A = C(u^n), g = rho_f/dt u^n - (A or 3/2 A - 1/2 A_prev) + D u^n / 2
+// (+ the body force on the y faces); rn, r1 the densities of levels n, n + 1
+template <int DIM, class UA, class FA, class RA>
+__device__ __forceinline__ void pred_rhs_face(const UA& u, const FA& mu, const RA& rn, const RA& r1, int q,
+                                              double aprev, int first, double inv_dt, double inv_h,
+                                              double inv_h2, const Body& B, int body_on, double& a_out,
+                                              double& g_out) {
+#pragma clang fp contract(off)
+    const double a = 0.5 * (rn(0, 0) + rn(q, -1)) * adv_flux<DIM>(u, q) * inv_h;
+    a_out = a;
+    const double ab = first ? a : 1.5 * a - 0.5 * aprev;
+    double mp[3], mm[3];
+    visc_coefs_acc<DIM>(mu, q, mp, mm);
+    const double vis = visc_sum_acc<DIM>(CompOf<UA>{u, q}, mp, mm) * inv_h2;
+    const double rf = 0.5 * (r1(0, 0) + r1(q, -1));
+    double gv = rf * inv_dt * u(q, 0, 0) - ab + 0.5 * vis;
+    if (q == 1 && body_on) gv += B.at(rf);
+    g_out = gv;
 }
 
 struct Vec3 {
@@ -200,9 +248,12 @@ __global__ void k_advection(Vec3 u, const double* __restrict__ rho, Dims d, Out3
     if (c >= d.cells()) return;
     const Sten<DIM> S = sten_of<DIM>(d, c);
     const double inv_h = 1.0 / d.h;
+    const GlobVec<DIM> U{S, u.p};
 #pragma unroll
-    for (int q = 0; q < DIM; ++q)
-        A.p[q][c] = 0.5 * (rho[c] + rho[S.at(q, -1)]) * adv_flux_sum<DIM>(S, c, u.p, q) * inv_h;
+    for (int q = 0; q < DIM; ++q) {
+#pragma clang fp contract(off)
+        A.p[q][c] = 0.5 * (rho[c] + rho[S.at(q, -1)]) * adv_flux<DIM>(U, q) * inv_h;
+    }
 }
 
 template <int DIM>
@@ -215,7 +266,7 @@ __global__ void k_viscous(Vec3 u, const double* __restrict__ mu, Dims d, Out3 V)
     for (int q = 0; q < DIM; ++q) {
         double mp[3], mm[3];
         visc_coefs<DIM>(S, c, mu, q, mp, mm);
-        V.p[q][c] = visc_sum<DIM>(S, c, u.p[q], mp, mm) * inv_h2;
+        V.p[q][c] = visc_sum_acc<DIM>(GlobField<DIM>{S, u.p[q]}, mp, mm) * inv_h2;
     }
 }
 
@@ -231,17 +282,14 @@ __global__ void k_pred_rhs(Vec3 u, const double* __restrict__ rho_n,
     if (c >= d.cells()) return;
     const Sten<DIM> S = sten_of<DIM>(d, c);
     const double inv_h = 1.0 / d.h, inv_h2 = inv_h * inv_h;
+    const GlobVec<DIM> U{S, u.p};
+    const GlobField<DIM> M{S, mu}, Rn{S, rho_n}, R1{S, rho1};
 #pragma unroll
     for (int q = 0; q < DIM; ++q) {
-        const double a = 0.5 * (rho_n[c] + rho_n[S.at(q, -1)]) * adv_flux_sum<DIM>(S, c, u.p, q) * inv_h;
+        double a, gv;
+        pred_rhs_face<DIM>(U, M, Rn, R1, q, first ? 0.0 : Aprev.p[q][c], first, inv_dt, inv_h, inv_h2, B, body_on,
+                           a, gv);
         A.p[q][c] = a;
-        const double ab = first ? a : 1.5 * a - 0.5 * Aprev.p[q][c];
-        double mp[3], mm[3];
-        visc_coefs<DIM>(S, c, mu, q, mp, mm);
-        const double vis = visc_sum<DIM>(S, c, u.p[q], mp, mm) * inv_h2;
-        const double rf = 0.5 * (rho1[c] + rho1[S.at(q, -1)]);
-        double gv = rf * inv_dt * u.p[q][c] - ab + 0.5 * vis;
-        if (q == 1 && body_on) gv += B.at(rf);
         g.p[q][c] = gv;
     }
 }
@@ -600,6 +648,159 @@ __global__ __launch_bounds__(kBlock) void k_helm_resid_tiled(Vec3 x, Vec3 g, con
     if (t == 0) part[kFlowRed + bid] = s;
 }
 
+// accessors of the tiled kernels: LDS planes with row length kQRX, the
+// plane k + oz of a ring of NS planes
+template <int NS>
+__device__ __forceinline__ int ring_slot(int k) {
+    return NS == 2 ? (k & 1) : ((k % NS) + NS) % NS;
+}
+__device__ __forceinline__ int lds_offset(int a, int s, int b, int t, int& oz) {
+    oz = (a == 2 ? s : 0) + (b == 2 ? t : 0);
+    return (a == 0 ? s : 0) + (b == 0 ? t : 0) + ((a == 1 ? s : 0) + (b == 1 ? t : 0)) * kQRX;
+}
+struct LdsVec {
+    const double (*U)[3][kQRN];
+    int k, cc;
+    __device__ double operator()(int q, int a, int s, int b = 0, int t = 0) const {
+        int oz;
+        const int o = lds_offset(a, s, b, t, oz);
+        return U[q][ring_slot<3>(k + oz)][cc + o];
+    }
+};
+template <int NS>
+struct LdsField {
+    const double (*F)[kQRN];
+    int k, cc;
+    __device__ double operator()(int a, int s, int b = 0, int t = 0) const {
+        int oz;
+        const int o = lds_offset(a, s, b, t, oz);
+        return F[ring_slot<NS>(k + oz)][cc + o];
+    }
+};
+
+// The right side and advection term of the 3D predictor (k_pred_rhs) on
+// grids of whole 32 x 8 column tiles: a workgroup marches its tile over the
+// z-range [z0, z1), one cell per lane and plane, with u, mu and the two
+// density levels of the tile and a one-cell ring staged in LDS two steps
+// ahead and A_prev in registers. Same per-face arithmetic (pred_rhs_face),
+// so the same values bit for bit.
+__global__ __launch_bounds__(kBlock) void k_pred_rhs_tiled(Vec3 u, const double* __restrict__ rho_n,
+                                                           const double* __restrict__ rho1,
+                                                           const double* __restrict__ mu, Vec3 Aprev, int first,
+                                                           Dims d, double inv_dt, Out3 A, Out3 g, Body B,
+                                                           int body_on, int TZ, int ntx, int nty, int nzc) {
+    static_assert(kHTX * 8 == kBlock, "one tile cell per lane");
+    __shared__ double UU[3][3][kQRN];
+    __shared__ double MM[3][kQRN];
+    __shared__ double RN[2][kQRN];
+    __shared__ double R1[2][kQRN];
+    const int nw = ntx * nty * nzc;
+    const int bid = blockIdx.x;
+    const int w = (nw % 8 == 0) ? (bid % 8) * (nw / 8) + bid / 8 : bid;
+    const int tx = w % ntx;
+    const int r0 = w / ntx;
+    const int ty = r0 % nty;
+    const int zc = r0 / nty;
+    const int i0 = tx * kHTX - 1, j0 = ty * 8 - 1;
+    const int z0 = zc * TZ, z1 = z0 + TZ;
+    const long plane = (long)d.nx * d.ny;
+    const double inv_h = 1.0 / d.h, inv_h2 = inv_h * inv_h;
+    const int t = threadIdx.x;
+    auto gofs = [&](int xx, int yy) { return wrap_near(j0 + yy, d.ny) * d.nx + wrap_near(i0 + xx, d.nx); };
+    int gp[kQLoads];
+    bool vp[kQLoads];
+#pragma unroll
+    for (int s = 0; s < kQLoads; ++s) {
+        const int q = t + s * kBlock;
+        vp[s] = q < kQRN;
+        gp[s] = vp[s] ? gofs(q % kQRX, q / kQRX) : gofs(0, 0);
+    }
+    auto pl = [&](int k) { return (long)wrap_near(k, d.nz) * plane; };
+    const int cx = 1 + t % kHTX, cy = 1 + t / kHTX, cc = cy * kQRX + cx;
+    const int go = gofs(cx, cy);
+    // register stages, alternating: u and mu of plane k + 1, the densities
+    // of plane k, A_prev at the lane's cell of plane k
+    struct Stage {
+        double u[3][kQLoads], m[kQLoads], rn[kQLoads], r1[kQLoads], ap[3];
+    };
+    Stage SA, SB;
+    auto fetch_planes = [&](Stage& S, int k) {
+        const long bu = pl(k + 1), bk = pl(k);
+#pragma unroll
+        for (int s = 0; s < kQLoads; ++s) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) S.u[q][s] = u.p[q][bu + gp[s]];
+            S.m[s] = mu[bu + gp[s]];
+            S.rn[s] = rho_n[bk + gp[s]];
+            S.r1[s] = rho1[bk + gp[s]];
+        }
+    };
+    auto fetch_ap = [&](Stage& S, int k) {
+        const long b = pl(k) + go;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) S.ap[q] = Aprev.p[q][b];  // allocated; ignored on a first step
+    };
+    auto commit = [&](const Stage& S, int k) {
+#pragma unroll
+        for (int s = 0; s < kQLoads; ++s)
+            if (s * kBlock + kBlock <= kQRN || vp[s]) {
+                const int c = t + s * kBlock;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) UU[q][ring_slot<3>(k + 1)][c] = S.u[q][s];
+                MM[ring_slot<3>(k + 1)][c] = S.m[s];
+                RN[k & 1][c] = S.rn[s];
+                R1[k & 1][c] = S.r1[s];
+            }
+    };
+    {
+        const long a = pl(z0 - 1), a1 = pl(z0);
+#pragma unroll
+        for (int s = 0; s < kQLoads; ++s)
+            if (vp[s]) {
+                const int c = t + s * kBlock;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    UU[q][ring_slot<3>(z0 - 1)][c] = u.p[q][a + gp[s]];
+                    UU[q][ring_slot<3>(z0)][c] = u.p[q][a1 + gp[s]];
+                }
+                MM[ring_slot<3>(z0 - 1)][c] = mu[a + gp[s]];
+                MM[ring_slot<3>(z0)][c] = mu[a1 + gp[s]];
+                RN[(z0 - 1) & 1][c] = rho_n[a + gp[s]];
+                R1[(z0 - 1) & 1][c] = rho1[a + gp[s]];
+            }
+    }
+    fetch_planes(SA, z0);
+    fetch_ap(SA, z0);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch_planes(SB, z0 + 1);
+    fetch_ap(SB, z0 + 1);
+    auto step = [&](Stage& S, int k) {
+        commit(S, k);
+        const int kn = k + 2 < z1 ? k + 2 : z1 - 1;
+        fetch_planes(S, kn);
+        __syncthreads();
+        const LdsVec U{UU, k, cc};
+        const LdsField<3> M{MM, k, cc};
+        const LdsField<2> Rn{RN, k, cc}, Rb{R1, k, cc};
+        const long o = pl(k) + go;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            double a, gv;
+            pred_rhs_face<3>(U, M, Rn, Rb, q, S.ap[q], first, inv_dt, inv_h, inv_h2, B, body_on, a, gv);
+            A.p[q][o] = a;
+            g.p[q][o] = gv;
+        }
+        fetch_ap(S, kn);
+        // the next commit overwrites the plane below k
+        __syncthreads();
+    };
+    // steps z0 .. z1 - 1 in pairs (stage A, stage B); TZ is even
+    for (int k = z0; k < z1; k += 2) {
+        step(SA, k);
+        step(SB, k + 1);
+    }
+}
+
 // block partials of ||g - M x||^2 and ||g||^2
 template <int DIM>
 __global__ void k_helm_resid(Vec3 x, Vec3 g, const double* __restrict__ rho1,
@@ -824,7 +1025,15 @@ static int predict_impl(ib_flow* f, const double* const u[3], const double* rho_
     const int nb = (int)std::min<long>(kFlowRed, (long)grid_for(N));
     for (int q = 0; q < dim; ++q)
         IB_HIP(hipMemcpyAsync(ustar[q], u[q], sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-    if (dim == 2)
+    // the single-pass sweep and the tiled right side and residual apply to
+    // 3D grids of whole 32 x 8 column tiles
+    const bool tiled = f->sweep == IB_FLOW_SWEEP_AUTO && helm_tiled_grid(d) && f->alt[0];
+    const int tz = helm_tz(d), hx = d.nx / kHTX, hy = d.ny / kHTY;
+    if (tiled)
+        hipLaunchKernelGGL(k_pred_rhs_tiled, dim3(hx * hy * (d.nz / tz)), blk, 0, st, vec3(u, 3), rho_n, rho1, mu,
+                           vec3(Aprev, 3), first, d, inv_dt, out3(Acur, 3), out3(f->g, 3), B, B.on() ? 1 : 0, tz,
+                           hx, hy, d.nz / tz);
+    else if (dim == 2)
         hipLaunchKernelGGL(k_pred_rhs<2>, g1, blk, 0, st, vec3(u, 2), rho_n, rho1, mu, vec3(Aprev, 2),
                            first, d, inv_dt, out3(Acur, 2), out3(f->g, 2), B, B.on() ? 1 : 0);
     else
@@ -841,8 +1050,6 @@ static int predict_impl(ib_flow* f, const double* const u[3], const double* rho_
     S->checks = 0;
     // the single-pass sweep alternates between u* and f->alt; cur holds the
     // latest iterate, copied into u* at the end
-    const bool tiled = f->sweep == IB_FLOW_SWEEP_AUTO && helm_tiled_grid(d) && f->alt[0];
-    const int tz = helm_tz(d), hx = d.nx / kHTX, hy = d.ny / kHTY;
     // planes per workgroup of the tiled residual: the fewest (even, dividing
     // nz) that keep the workgroups within the partial-sum buffer (0: none does)
     int rtz = 0;
