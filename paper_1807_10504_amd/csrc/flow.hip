@@ -346,7 +346,8 @@ __global__ void k_helm_sweep(Out3 x, Vec3 g, const double* __restrict__ rho1,
 // one-colour launches of k_helm_sweep, whose per-face arithmetic (helm_face,
 // edge_mu) it shares. The components' planes, mu and rho_f's densities are
 // staged in LDS over the tile and a two-cell halo, loaded into registers
-// two steps ahead; g is read where a cell is updated.
+// two steps ahead; g at the lane's red and black cells goes into registers
+// once the step has used the values before it.
 constexpr int kHTX = 32, kHTY = 8;
 constexpr int kHRX = kHTX + 4, kHRY = kHTY + 4, kHRN = kHRX * kHRY;
 constexpr int kHLoads = (kHRN + kBlock - 1) / kBlock;
