@@ -95,3 +95,21 @@ def test_adam_closed_form_scalar():
     # first step: m = 0.1 g, v = 0.001 g^2, mhat = g, vhat = g^2 -> w -= lr g / (|g| + eps)
     expect = np.float32(0.5) - np.float32(0.1) * np.float32(2.0) / (np.float32(2.0) + np.float32(1e-8))
     assert params[0][0][0, 0] == np.float64(np.float32(expect))
+
+
+def test_forward_of_a_13_cube_patch_gives_the_centre_value():
+    """Six 3x3x3 layers reach 6 cells: the oracle forward on the 13^3 periodic
+    patch around a voxel gives that voxel's output of the full-grid forward
+    (the sampled 256^3 parity test relies on it). 20^3 grid, voxels inside
+    and on the faces (their patches wrap around the box)."""
+    rng = np.random.default_rng(31)
+    n = 20
+    params = nn.init_params(9, dim=3)
+    params[5][0] *= 10.0
+    x = rng.standard_normal((3, n, n, n))
+    y, _ = nn.forward(params, x, use_bf16=True)
+    for k, j, i in [(10, 10, 10), (0, 5, 19), (19, 0, 7), (3, 17, 0), (6, 13, 2)]:
+        idx = [np.arange(c - 6, c + 7) % n for c in (k, j, i)]
+        patch = x[:, idx[0][:, None, None], idx[1][None, :, None], idx[2][None, None, :]]
+        yp, _ = nn.forward(params, patch, use_bf16=True)
+        assert abs(yp[6, 6, 6] - y[k, j, i]) <= 1e-12 * np.abs(y).max()
