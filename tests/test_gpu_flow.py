@@ -161,6 +161,35 @@ def test_predict_single_pass_sweep_identical(ib, shape):
         assert abs(a["rel_res"] - b["rel_res"]) <= 1e-12 * a["rel_res"]
 
 
+def test_predict_single_pass_identical_at_256(ib):
+    """At 256^3 (16-plane z-ranges, 4096 workgroups: the predictor the
+    benchmark times) the tiled right side, sweeps and residual checks give
+    the one-colour path's u* bit for bit, with the same sweeps and checks."""
+    n = 256
+    shape = (n, n, n)
+    h = 1.0 / n
+    gen = torch.Generator(device="cuda").manual_seed(86)
+    z = (torch.arange(n, dtype=torch.float64, device="cuda") + 0.5) * h - 0.5
+    r = torch.sqrt(z[:, None, None] ** 2 + z[None, :, None] ** 2 + z[None, None, :] ** 2)
+    H = torch.clamp((0.3 - r) / (3 * h) + 0.5, 0.0, 1.0)
+    rho = 1e-3 + (1.0 - 1e-3) * H
+    mu = 1e-4 + (1e-2 - 1e-4) * H
+    u = [0.1 * torch.randn(shape, dtype=torch.float64, device="cuda", generator=gen) for _ in range(3)]
+    out = {}
+    for kind in (ib.FLOW_SWEEP_COLOUR, ib.FLOW_SWEEP_AUTO):
+        fl = ib.Flow(3, (n, n, n), h)
+        fl.set_sweep(kind)
+        fl.predict(u, rho, rho, mu, 5e-5, rtol=1e-12)      # fills the history
+        us, st = fl.predict(u, rho, rho, mu, 5e-5, rtol=1e-12)
+        torch.cuda.synchronize()
+        out[kind] = ([a.clone() for a in us], st)
+        fl.close()
+    c, t = out[ib.FLOW_SWEEP_COLOUR], out[ib.FLOW_SWEEP_AUTO]
+    print(f"256^3: sweeps {c[1]['sweeps']} / {t[1]['sweeps']}, rel res {c[1]['rel_res']:.3e} / {t[1]['rel_res']:.3e}")
+    assert c[1]["sweeps"] == t[1]["sweeps"] and c[1]["checks"] == t[1]["checks"]
+    assert all(torch.equal(a, b) for a, b in zip(c[0], t[0]))
+
+
 def test_flow_set_sweep_rejects_unknown_kind(ib):
     fl = ib.Flow(3, (32, 8, 4), 1.0 / 32)
     with pytest.raises(ib.IbError):
