@@ -16,10 +16,14 @@
 // 3 ky + kx) and the flipped transpose Wt[ci][taps - 1 - tap][co] used by the
 // input gradient, which is then the same convolution kernel.
 //
-// A convolution is an implicit GEMM: a wave owns 16 pixels of one row and
-// all 32 output channels; for each tap it multiplies a 16 x 32 (pixel x
-// channel) slab of the shifted input by the 32 x 16 weight block of each half
-// of the output channels (two MFMA per tap). The weight gradient is a GEMM
+// A convolution is an implicit GEMM. In 3D (k_nn_conv3_tiled) a workgroup
+// keeps the layer's weights in LDS and marches a 64 x 8 pixel tile along z,
+// staging each input plane once for the three output planes it touches; in
+// 2D (and on 3D grids the tiles do not fit) k_nn_conv has a wave own 16
+// pixels of one row and all 32 output channels and, for each tap, multiply a
+// 16 x 32 (pixel x channel) slab of the shifted input by the 32 x 16 weight
+// block of each half of the output channels (two MFMA per tap); the two give
+// identical results. The weight gradient is a GEMM
 // over pixels: a workgroup stages 64 pixels of the gradient and the input
 // rows they touch in LDS and accumulates the (tap, co-block, ci-block)
 // 16 x 16 tiles; per-workgroup partials are summed in a fixed order.
