@@ -127,14 +127,49 @@ __global__ void k_nn_input(const double* __restrict__ b, const double* __restric
 }
 
 // ---------------------------------------------------------------------------
+// The first layer has 3 input channels (the rest of the 32 are zero): its 27
+// in-plane products of a plane kz, (ky, kx, ci), are packed into one K = 32
+// operand, k = 3 (3 ky + kx) + ci for k < 27; k = 27 .. 31 read input
+// channel 3 of the centre pixel (zero) against zero weights. Three matrix
+// products per output instead of 27. pack_tap gives k's offsets.
+__device__ __forceinline__ void pack_tap(int k, int& ky, int& kx, int& ci) {
+    if (k < 27) {
+        ky = k / 9;
+        kx = (k / 3) % 3;
+        ci = k % 3;
+    } else {
+        ky = 1;
+        kx = 1;
+        ci = 3;
+    }
+}
+
+// weight fragment of the packed first layer for plane kz, output channels
+// cb 16 .. cb 16 + 15: lane (n, kg) holds W[cb 16 + n][9 kz + 3 ky + kx][ci]
+// for the eight k of kg
+__device__ __forceinline__ bf16x8 pack_weights(const u16* __restrict__ Wl, int kz, int cb, int n, int kg) {
+    bf16x8 b;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        int ky, kx, ci;
+        const int k = kg * 8 + e;
+        pack_tap(k, ky, kx, ci);
+        const u16 v = k < 27 ? Wl[((cb * 16 + n) * 27 + 9 * kz + 3 * ky + kx) * kC + ci] : (u16)0;
+        b[e] = __builtin_bit_cast(__bf16, v);
+    }
+    return b;
+}
+
+// ---------------------------------------------------------------------------
 // convolution on the matrix cores
 // MODE 0: + bias, ReLU, bfloat16 out; MODE 1: + bias, float32 out of channel 0;
 // MODE 2: bfloat16 out times (act > 0) (input gradient through the ReLU below)
-template <int MODE, int DIM>
+template <int MODE, int DIM, bool PACK = false>
 __global__ __launch_bounds__(kBlock) void k_nn_conv(const u16* __restrict__ X, const u16* __restrict__ Wl,
                                                     const float* __restrict__ bias,
                                                     const u16* __restrict__ act, u16* __restrict__ Y,
                                                     float* __restrict__ Yf, int D, int H, int W) {
+    static_assert(!PACK || (DIM == 3 && MODE == 0), "the packed first layer is 3D, bias + ReLU");
     constexpr int TAPS = DIM == 3 ? 27 : 9;
     __shared__ u16 tile[4][16][kC];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -144,8 +179,24 @@ __global__ __launch_bounds__(kBlock) void k_nn_conv(const u16* __restrict__ X, c
     // first pixel of this wave's 16 (row y of plane z)
     const long row0 = ((long)z * H + y) * W + x0;
     f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (PACK) {
 #pragma unroll
-    for (int tap = 0; tap < TAPS; ++tap) {
+        for (int kz = 0; kz < 3; ++kz) {
+            const int zz = wrap_near(z + kz - 1, D);
+            bf16x8 a;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                int ky, kx, ci;
+                pack_tap(kg * 8 + e, ky, kx, ci);
+                const int yy = wrap_near(y + ky - 1, H), xx = wrap_near(x0 + m + kx - 1, W);
+                a[e] = __builtin_bit_cast(__bf16, X[(((long)zz * H + yy) * W + xx) * kC + ci]);
+            }
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, pack_weights(Wl, kz, 0, m, kg), acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, pack_weights(Wl, kz, 1, m, kg), acc1, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int tap = 0; tap < (PACK ? 0 : TAPS); ++tap) {
         // tap = 9 kz + 3 ky + kx (kz = 1 in 2D): offsets k - 1 along each axis
         const int kz = DIM == 3 ? tap / 9 : 1, ky = (tap % 9) / 3, kx = tap % 3;
         const int zz = DIM == 3 ? wrap_near(z + kz - 1, D) : 0;
@@ -285,6 +336,39 @@ __device__ __forceinline__ void conv3_plane(const bf16x8* __restrict__ P, const 
     }
 }
 
+// the packed first layer on one staged plane: one input fragment per pixel
+// block gathered from channel chunk 0 (off: the lane's eight element
+// offsets, in 16-bit units), one product per (kz, output block)
+template <int R, bool FULL>
+__device__ __forceinline__ void conv3_plane_pack(const bf16x8* __restrict__ P, const bf16x8* __restrict__ Ws,
+                                                 f32x4 (&acc)[3][4][2], int w, int m, int lane,
+                                                 const int (&off)[8], int mask) {
+    const u16* Pu = reinterpret_cast<const u16*>(P);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc[R][j][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 a[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int base = ((w * 4) * kTPxs + 16 * j + m) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a[j][e] = __builtin_bit_cast(__bf16, Pu[base + off[e]]);
+    }
+#pragma unroll
+    for (int kz = 0; kz < 3; ++kz) {
+        if (!FULL && !((mask >> kz) & 1)) continue;
+        const int S = (R - kz + 3) % 3;
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            const bf16x8 b = Ws[(kz * 2 + cb) * 64 + lane];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[S][j][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j], b, acc[S][j][cb], 0, 0, 0);
+        }
+    }
+}
+
 // bias / ReLU (MODE 0), channel 0 in float32 (MODE 1) or the ReLU mask of
 // act (MODE 2) for the 64 pixels of one output row starting at pixel row0
 template <int MODE>
@@ -333,7 +417,7 @@ __device__ __forceinline__ void conv3_store(const f32x4 (&a)[4][2], long row0, c
     }
 }
 
-template <int MODE>
+template <int MODE, bool PACK = false>
 __global__ __launch_bounds__(kTThreads) void k_nn_conv3_tiled(const u16* __restrict__ X,
                                                               const u16* __restrict__ Wl,
                                                               const float* __restrict__ bias,
@@ -355,15 +439,33 @@ __global__ __launch_bounds__(kTThreads) void k_nn_conv3_tiled(const u16* __restr
     const int nz = min(ZR, D - z0), nt = nz + 2;  // input planes z0 - 1 .. z0 + nz
     const long HW = (long)H * W;
 
-    // weights: LDS fragment (tap, cb, lane) = Wl[cb 16 + m][tap][8 kg .. 8 kg + 7]
-#pragma unroll
-    for (int s = 0; s < kTWLoads; ++s) {
-        const int q = tid + s * kTThreads;
-        if (q < kTW) {
-            const int l = q & 63, tc = q >> 6;
-            const int tap = tc >> 1, cb = tc & 1, mm = l & 15, kk = l >> 4;
-            Ws[q] = *reinterpret_cast<const bf16x8*>(Wl + ((cb * 16 + mm) * 27 + tap) * kC + kk * 8);
+    static_assert(!PACK || MODE == 0, "the packed first layer is bias + ReLU");
+    // weights: LDS fragment (tap, cb, lane) = Wl[cb 16 + m][tap][8 kg .. 8 kg + 7];
+    // packed first layer: fragment (kz, cb, lane) of pack_weights
+    if constexpr (PACK) {
+        if (tid < 6 * 64) {
+            const int l = tid & 63, tc = tid >> 6;
+            Ws[tid] = pack_weights(Wl, tc >> 1, tc & 1, l & 15, l >> 4);
         }
+    } else {
+#pragma unroll
+        for (int s = 0; s < kTWLoads; ++s) {
+            const int q = tid + s * kTThreads;
+            if (q < kTW) {
+                const int l = q & 63, tc = q >> 6;
+                const int tap = tc >> 1, cb = tc & 1, mm = l & 15, kk = l >> 4;
+                Ws[q] = *reinterpret_cast<const bf16x8*>(Wl + ((cb * 16 + mm) * 27 + tap) * kC + kk * 8);
+            }
+        }
+    }
+    // packed first layer: the lane's eight input offsets (16-bit units) from
+    // its pixel's chunk 0 in the staged plane
+    int poff[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        int ky, kx, ci;
+        pack_tap(kg * 8 + e, ky, kx, ci);
+        poff[e] = (ky * 4 * kTPxs + kx) * 8 + ci;
     }
     // plane staging: slot q = 16 bytes (chunk c of pixel px in halo row r);
     // slots past the plane re-read slot 0 and are not stored
@@ -401,10 +503,16 @@ __global__ __launch_bounds__(kTThreads) void k_nn_conv3_tiled(const u16* __restr
         const bool more = t + 1 < nt;
         if (more) fetch(t + 1);
         const int mask = (t < nz ? 1 : 0) | (t >= 1 && t <= nz ? 2 : 0) | (t >= 2 ? 4 : 0);
-        if (mask == 7)
+        if constexpr (PACK) {
+            if (mask == 7)
+                conv3_plane_pack<R, true>(Ps[t & 1], Ws, acc, wave, m, lane, poff, 7);
+            else
+                conv3_plane_pack<R, false>(Ps[t & 1], Ws, acc, wave, m, lane, poff, mask);
+        } else if (mask == 7) {
             conv3_plane<MODE, R, true>(Ps[t & 1], Ws, acc, wave, m, kg, lane, 7);
-        else
+        } else {
             conv3_plane<MODE, R, false>(Ps[t & 1], Ws, acc, wave, m, kg, lane, mask);
+        }
         // input plane t completes output plane t - 2 (set (R + 1) mod 3)
         if (t >= 2)
             conv3_store<MODE>(acc[(R + 1) % 3], rowz + (long)(t - 2) * HW, bias, act, Y, Yf, Ep[wave], m, kg,
@@ -625,20 +733,21 @@ static bool conv3_tiled(const ib_nn* n) {
 
 // one convolution layer: MODE 0 (bias, ReLU), 1 (float32 channel 0) or 2
 // (input gradient through the ReLU mask of act)
-template <int MODE>
+// PACK: the first layer (3 input channels) with its in-plane products packed (3D)
+template <int MODE, bool PACK = false>
 static void nn_conv(const ib_nn* n, const u16* X, const u16* Wl, const float* bias, const u16* act, u16* Y,
                     float* Yf, hipStream_t st) {
     if (conv3_tiled(n)) {
         const int zr = conv3_range(n);
         const int nb = (n->W / kTX) * (n->H / kTY) * ((n->D + zr - 1) / zr);
-        hipLaunchKernelGGL((k_nn_conv3_tiled<MODE>), dim3(nb), dim3(kTThreads), 0, st, X, Wl, bias, act, Y, Yf,
-                           n->D, n->H, n->W, zr);
+        hipLaunchKernelGGL((k_nn_conv3_tiled<MODE, PACK>), dim3(nb), dim3(kTThreads), 0, st, X, Wl, bias, act, Y,
+                           Yf, n->D, n->H, n->W, zr);
         return;
     }
     dim3 grid(n->W / 64, n->H, n->D);
     if (n->dim == 3)
-        hipLaunchKernelGGL((k_nn_conv<MODE, 3>), grid, dim3(kBlock), 0, st, X, Wl, bias, act, Y, Yf, n->D, n->H,
-                           n->W);
+        hipLaunchKernelGGL((k_nn_conv<MODE, 3, PACK>), grid, dim3(kBlock), 0, st, X, Wl, bias, act, Y, Yf, n->D,
+                           n->H, n->W);
     else
         hipLaunchKernelGGL((k_nn_conv<MODE, 2>), grid, dim3(kBlock), 0, st, X, Wl, bias, act, Y, Yf, n->D, n->H,
                            n->W);
@@ -658,6 +767,8 @@ static int nn_forward(ib_nn* n, const double* b, const double* H, const double* 
         const float* bias = n->bias + l * kC;
         if (l == kLayers - 1)
             nn_conv<1>(n, n->act[l], Wl, bias, nullptr, nullptr, n->yf, st);
+        else if (l == 0 && n->dim == 3)
+            nn_conv<0, true>(n, n->act[l], Wl, bias, nullptr, n->act[l + 1], nullptr, st);
         else
             nn_conv<0>(n, n->act[l], Wl, bias, nullptr, n->act[l + 1], nullptr, st);
     }
