@@ -251,8 +251,6 @@ constexpr int kTX = 64, kTY = 8, kTThreads = 512;
 constexpr int kTRows = kTY + 2, kTPx = kTX + 2;
 constexpr int kTPxs = 68;                         // LDS pixel stride (bank spread)
 constexpr int kTPlane = kTRows * 4 * kTPxs;       // 16-byte units per staged plane
-constexpr int kTSlots = kTRows * kTPx * 4;        // 16-byte loads per plane
-constexpr int kTLoads = (kTSlots + kTThreads - 1) / kTThreads;
 constexpr int kTW = 27 * 2 * 64;                  // 16-byte weight fragments
 constexpr int kTWLoads = (kTW + kTThreads - 1) / kTThreads;
 
@@ -467,28 +465,31 @@ __global__ __launch_bounds__(kTThreads) void k_nn_conv3_tiled(const u16* __restr
         pack_tap(kg * 8 + e, ky, kx, ci);
         poff[e] = (ky * 4 * kTPxs + kx) * 8 + ci;
     }
-    // plane staging: slot q = 16 bytes (chunk c of pixel px in halo row r);
-    // slots past the plane re-read slot 0 and are not stored
-    int goff[kTLoads], loff[kTLoads];
+    // plane staging: slot q = 16 bytes (chunk c of pixel px in halo row r;
+    // the packed first layer reads chunk 0, channels 0 .. 7, only); slots
+    // past the plane re-read slot 0 and are not stored
+    constexpr int NCH = PACK ? 1 : 4, NSLOT = kTRows * kTPx * NCH;
+    constexpr int NLD = (NSLOT + kTThreads - 1) / kTThreads;
+    int goff[NLD], loff[NLD];
 #pragma unroll
-    for (int s = 0; s < kTLoads; ++s) {
+    for (int s = 0; s < NLD; ++s) {
         int q = tid + s * kTThreads;
-        const bool v = q < kTSlots;
+        const bool v = q < NSLOT;
         if (!v) q = 0;
-        const int c = q & 3, px = (q >> 2) % kTPx, r = (q >> 2) / kTPx;
+        const int c = q % NCH, px = (q / NCH) % kTPx, r = (q / NCH) / kTPx;
         goff[s] = (wrap_near(y0 - 1 + r, H) * W + wrap_near(x0 - 1 + px, W)) * kC + c * 8;
         loff[s] = v ? (r * 4 + c) * kTPxs + px : -1;
     }
-    bf16x8 pre[kTLoads];
+    bf16x8 pre[NLD];
     auto fetch = [&](int t) {
         const u16* base = X + (long)wrap_near(z0 - 1 + t, D) * HW * kC;
 #pragma unroll
-        for (int s = 0; s < kTLoads; ++s) pre[s] = *reinterpret_cast<const bf16x8*>(base + goff[s]);
+        for (int s = 0; s < NLD; ++s) pre[s] = *reinterpret_cast<const bf16x8*>(base + goff[s]);
     };
     auto commit = [&](int t) {
         bf16x8* P = Ps[t & 1];
 #pragma unroll
-        for (int s = 0; s < kTLoads; ++s)
+        for (int s = 0; s < NLD; ++s)
             if (loff[s] >= 0) P[loff[s]] = pre[s];
     };
     fetch(0);
