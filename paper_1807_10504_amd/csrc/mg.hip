@@ -270,8 +270,11 @@ __device__ __forceinline__ T apply_row(const T* __restrict__ p, const K& co, con
 }
 
 // ---------------------------------------------------------------------------
-// smoother: one colour of red-black Gauss-Seidel, one thread per cell of the colour
-template <typename T, int DIM>
+// smoother: one colour of red-black Gauss-Seidel, one thread per cell of the colour.
+// ZERO: the red pass of a sweep that starts from p = 0 (p is neither filled nor
+// read: every neighbour term is +0, the value the filled array gives, so the
+// result is the same bit for bit; the black pass then reads only red cells)
+template <typename T, int DIM, bool ZERO = false>
 __global__ void k_rbgs(T* __restrict__ p, const T* __restrict__ b, const T* __restrict__ b0,
                        const T* __restrict__ b1, const T* __restrict__ b2, Dims d, T h2, int color) {
     long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -285,16 +288,16 @@ __global__ void k_rbgs(T* __restrict__ p, const T* __restrict__ b, const T* __re
     int i = 2 * i2 + ((j + k + color) & 1);
     Nb n = neighbours(d, i, j, k, DIM);
     T br = b0[n.xp], bl = b0[n.c];
-    T num = br * p[n.xp] + bl * p[n.xm];
+    T num = ZERO ? T(0) : br * p[n.xp] + bl * p[n.xm];
     T diag = br + bl;
     br = b1[n.yp];
     bl = b1[n.c];
-    num += br * p[n.yp] + bl * p[n.ym];
+    if (!ZERO) num += br * p[n.yp] + bl * p[n.ym];
     diag += br + bl;
     if (DIM == 3) {
         br = b2[n.zp];
         bl = b2[n.c];
-        num += br * p[n.zp] + bl * p[n.zm];
+        if (!ZERO) num += br * p[n.zp] + bl * p[n.zm];
         diag += br + bl;
     }
     p[n.c] = (num - h2 * b[n.c]) / diag;
@@ -1188,6 +1191,7 @@ struct PersistLevels {
     int n;  // levels first .. coarsest
     int nu1, nu2;
     int nc;  // coarsest cells
+    int zero;  // the first level starts from p = 0 (its p is not read)
     const double* minv;
     Dims d[kPersistMaxLevels];
     T* p[kPersistMaxLevels];
@@ -1197,7 +1201,8 @@ struct PersistLevels {
     const T* b2[kPersistMaxLevels];
 };
 
-template <typename T, int DIM>
+// ZERO: the red pass from p = 0, which reads no p (as k_rbgs<..., true>)
+template <typename T, int DIM, bool ZERO = false>
 __device__ void pv_rbgs(const PersistLevels<T>& L, int l, int color) {
     const Dims d = L.d[l];
     T* __restrict__ p = L.p[l];
@@ -1216,16 +1221,16 @@ __device__ void pv_rbgs(const PersistLevels<T>& L, int l, int color) {
         int i = 2 * i2 + ((j + k + color) & 1);
         Nb n = neighbours(d, i, j, k, DIM);
         T br = b0[n.xp], bl = b0[n.c];
-        T num = br * p[n.xp] + bl * p[n.xm];
+        T num = ZERO ? T(0) : br * p[n.xp] + bl * p[n.xm];
         T diag = br + bl;
         br = b1[n.yp];
         bl = b1[n.c];
-        num += br * p[n.yp] + bl * p[n.ym];
+        if (!ZERO) num += br * p[n.yp] + bl * p[n.ym];
         diag += br + bl;
         if (DIM == 3) {
             br = b2[n.zp];
             bl = b2[n.c];
-            num += br * p[n.zp] + bl * p[n.zm];
+            if (!ZERO) num += br * p[n.zp] + bl * p[n.zm];
             diag += br + bl;
         }
         p[n.c] = (num - h2 * b[n.c]) / diag;
@@ -1301,9 +1306,18 @@ template <typename T, int DIM>
 __global__ __launch_bounds__(kPersistThreads) void k_coarse_vcycle(PersistLevels<T> L) {
     __shared__ double sb[kMaxCoarse];
     const int last = L.n - 1;
+    // a first level from p = 0: its first red pass reads no p; without
+    // pre-smoothing the restriction reads p, which is cleared here
+    if (L.zero && L.nu1 == 0 && last > 0) {
+        for (long t = threadIdx.x; t < L.d[0].cells(); t += blockDim.x) L.p[0][t] = T(0);
+        __syncthreads();
+    }
     for (int l = 0; l < last; ++l) {
         for (int s = 0; s < L.nu1; ++s) {
-            pv_rbgs<T, DIM>(L, l, 0);
+            if (l == 0 && s == 0 && L.zero)
+                pv_rbgs<T, DIM, true>(L, l, 0);
+            else
+                pv_rbgs<T, DIM>(L, l, 0);
             __syncthreads();
             pv_rbgs<T, DIM>(L, l, 1);
             __syncthreads();
@@ -1404,7 +1418,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_coarse_vcycle_lds(PersistLevels
                 bzr[c][s] = L.b2[0][n.zp];
                 bzl[c][s] = L.b2[0][n.c];
                 B0[n.c] = L.b[0][n.c];
-                P0[n.c] = L.p[0][n.c];
+                P0[n.c] = L.zero ? T(0) : L.p[0][n.c];
             }
         }
     __syncthreads();
@@ -2312,18 +2326,23 @@ template <typename T> LevelT<T>& lvl(Level& L);
 template <> LevelT<double>& lvl<double>(Level& L) { return L.f64; }
 template <> LevelT<float>& lvl<float>(Level& L) { return L.f32; }
 
+// zero: the red pass of a sweep from p = 0 (p is not read)
 template <typename T>
-static void launch_rbgs(Level& L, int color, hipStream_t st, bool finest) {
+static void launch_rbgs(Level& L, int color, hipStream_t st, bool finest, bool zero = false) {
     ProfScope ps(sizeof(T) == 8 ? IB_PROF_SMOOTH64 : IB_PROF_SMOOTH32, st, finest);
     LevelT<T>& A = lvl<T>(L);
     T h2 = (T)(L.d.h * L.d.h);
     long half = L.d.cells() / 2;
-    if (L.d.dim == 2)
-        hipLaunchKernelGGL((k_rbgs<T, 2>), dim3(grid_for(half)), dim3(kBlock), 0, st, A.p, A.b,
-                           A.beta[0], A.beta[1], A.beta[1], L.d, h2, color);
+    const dim3 g(grid_for(half)), blk(kBlock);
+    const T* b2 = L.d.dim == 2 ? A.beta[1] : A.beta[2];
+    if (L.d.dim == 2 && zero)
+        hipLaunchKernelGGL((k_rbgs<T, 2, true>), g, blk, 0, st, A.p, A.b, A.beta[0], A.beta[1], b2, L.d, h2, 0);
+    else if (L.d.dim == 2)
+        hipLaunchKernelGGL((k_rbgs<T, 2>), g, blk, 0, st, A.p, A.b, A.beta[0], A.beta[1], b2, L.d, h2, color);
+    else if (zero)
+        hipLaunchKernelGGL((k_rbgs<T, 3, true>), g, blk, 0, st, A.p, A.b, A.beta[0], A.beta[1], b2, L.d, h2, 0);
     else
-        hipLaunchKernelGGL((k_rbgs<T, 3>), dim3(grid_for(half)), dim3(kBlock), 0, st, A.p, A.b,
-                           A.beta[0], A.beta[1], A.beta[2], L.d, h2, color);
+        hipLaunchKernelGGL((k_rbgs<T, 3>), g, blk, 0, st, A.p, A.b, A.beta[0], A.beta[1], b2, L.d, h2, color);
 }
 
 // zero: the sweep starts from p = 0 (pin is not read); pe (density levels
@@ -2399,8 +2418,8 @@ static void launch_fused(Level& L, T* pin, T* pout, hipStream_t st, bool finest,
 }
 
 // nu red-black sweeps on level L; returns the buffer holding the result.
-// zero_first: the level starts from p = 0, which a single-pass first sweep
-// takes without reading (the caller then need not fill p)
+// zero_first: the level starts from p = 0, which the first sweep takes
+// without reading p (p need not be filled)
 // dots_last: the last sweep leaves the inner products of Level::dots_*
 template <typename T>
 static T* smooth(Level& L, T* cur, int nu, hipStream_t st, bool finest, bool zero_first,
@@ -2415,7 +2434,7 @@ static T* smooth(Level& L, T* cur, int nu, hipStream_t st, bool finest, bool zer
         } else {
             T* save = A.p;
             A.p = cur;
-            launch_rbgs<T>(L, 0, st, finest);
+            launch_rbgs<T>(L, 0, st, finest, zero_first && s == 0);
             launch_rbgs<T>(L, 1, st, finest);
             A.p = save;
         }
@@ -2488,6 +2507,7 @@ static void vcycle(mg_handle* m, int l, hipStream_t st, bool zero_start) {
         P.nu1 = m->o.nu1;
         P.nu2 = m->o.nu2;
         P.nc = m->nc;
+        P.zero = zero_start ? 1 : 0;
         P.minv = m->cinv;
         for (int i = 0; i < P.n; ++i) {
             Level& Li = m->lv[l + i];
@@ -2517,11 +2537,14 @@ static void vcycle(mg_handle* m, int l, hipStream_t st, bool zero_start) {
     Level& C = m->lv[l + 1];
     LevelT<T>& B = lvl<T>(C);
     bool fin = l == 0;
+    // from p = 0 the first sweep reads no p; without pre-smoothing the
+    // restriction reads it, so it is cleared
+    if (zero_start && m->o.nu1 == 0)
+        hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(L.d.cells())), dim3(kBlock), 0, st, A.p, L.d.cells(),
+                           (T)0);
     T* cur = smooth<T>(L, A.p, m->o.nu1, st, fin, zero_start);
-    const long nc = C.d.cells();
     restrict_residual<T>(L, C, cur, st, fin);
-    if (l + 1 != last && !C.fused)
-        hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(nc)), dim3(kBlock), 0, st, B.p, nc, (T)0);
+    // every coarser level starts from p = 0 without a fill
     vcycle<T>(m, l + 1, st, true);
     // on a 3D density level with at least two post-smoothing sweeps the first
     // (a plain sweep) adds the prolongated correction as it stages p
@@ -3037,12 +3060,10 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
         if (mixed) {
             if (!r32_ready) hipLaunchKernelGGL(k_cast_f32, g1, blk, 0, st, m->kr, L0.f32.b, N);
             r32_ready = false;
-            if (!L0.fused) hipLaunchKernelGGL((k_fill<float>), g1, blk, 0, st, L0.f32.p, N, 0.0f);
             vcycle<float>(m, 0, st, true);
         } else {
             L0.f64.b = m->kr;
             L0.f64.p = m->kz;
-            if (!L0.fused) hipLaunchKernelGGL((k_fill<double>), g1, blk, 0, st, m->kz, N, 0.0);
             vcycle<double>(m, 0, st, true);
         }
     };
@@ -3271,8 +3292,6 @@ extern "C" int mg_solve(mg_handle* m, const double* b, double* p, double rtol, i
         // A annihilates constants and every step of a cycle commutes with adding
         // one, so the mean is removed once, after the last cycle
         if (mixed) {
-            if (!L0.fused)
-                hipLaunchKernelGGL((k_fill<float>), dim3(grid_for(N)), dim3(kBlock), 0, st, L0.f32.p, N, 0.0f);
             vcycle<float>(m, 0, st, true);
             int nb = red_blocks(N);
             hipLaunchKernelGGL(k_correct_f32, dim3(nb), dim3(kBlock), 0, st, p, L0.f32.p, N,

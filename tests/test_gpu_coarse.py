@@ -32,7 +32,8 @@ CASES = [((512, 512), "fp64", 0, (2, 2)), ((128, 128, 128), "fp64", 0, (2, 2)),
          ((128, 128, 128), "mixed", 1, (2, 2)), ((32, 32, 32), "fp64", 1, (1, 1)),
          ((64, 64, 64), "mixed", 0, (2, 1)), ((256, 256), "mixed", 1, (2, 2)),
          ((128, 128, 128), "fp64", 1, (1, 3)), ((128, 128, 128), "mixed", 0, (2, 2)),
-         ((256, 256, 256), "fp64", 1, (2, 2))]
+         ((256, 256, 256), "fp64", 1, (2, 2)), ((128, 128, 128), "fp64", 1, (0, 2)),
+         ((256, 256), "mixed", 0, (0, 2))]
 
 
 @pytest.mark.parametrize("shape,prec,krylov,nu", CASES)

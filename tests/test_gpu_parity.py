@@ -287,6 +287,29 @@ def test_mg_fixed_cycles_parity(ib, shape):
     assert abs(st["rel_res"] - hist[-1]) <= 1e-6 * hist[-1]
 
 
+@pytest.mark.parametrize("shape,nu", [((64, 64), (0, 2)), ((32, 32, 32), (0, 2)), ((32, 32, 32), (1, 1)),
+                                      ((64, 64, 64), (0, 2)), ((64, 64, 64), (1, 2))])
+def test_mg_fixed_cycles_parity_sweep_counts(ib, shape, nu):
+    """Other smoothing counts: every coarse level starts from p = 0 without a
+    fill (the first red pass reads no p; without pre-smoothing p is cleared
+    before the restriction reads it)."""
+    dim = len(shape)
+    n = tuple(reversed(shape))
+    h = 1.0 / shape[-1]
+    beta = _drop_beta(shape)
+    b = W.random_cells(n, dim, 1.0, seed=53)
+    b -= b.mean()
+    mg = ib.Multigrid(dim, n, h, nu1=nu[0], nu2=nu[1])
+    mg.update_coeffs([dev(x) for x in beta])
+    p = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    ncyc = 4
+    st = mg.solve(dev(b), p, fixed_cycles=ncyc)
+    po, _, hist = poisson.mg_solve(b, beta, h, fixed_cycles=ncyc, nu1=nu[0], nu2=nu[1])
+    assert st["cycles"] == ncyc
+    assert rel_l2(host(p), po) <= 1e-11
+    assert abs(st["rel_res"] - hist[-1]) <= 1e-6 * hist[-1]
+
+
 def test_mg_converged_vs_dense(ib):
     shape = (16, 16)
     beta = _drop_beta(shape)
