@@ -3198,7 +3198,8 @@ static int solve_krylov(mg_handle* m, const double* b, double* x, double rtol, i
                                mixed ? L0.f32.b : nullptr);
         }
         r32_ready = mixed;
-        IB_TRY(device_sum(pa, nb, m->ks + KS_RR, st));
+        // (r, r) is read only by the host's checks
+        if (check) IB_TRY(device_sum(pa, nb, m->ks + KS_RR, st));
         ++it;
         S->cycles = it;
         if (!check) {

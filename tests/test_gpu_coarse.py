@@ -1,6 +1,6 @@
 """The fused phases of the cycle against the launch-per-phase cycle: the
 persistent coarse-level kernel (one workgroup runs the sub-V-cycle of the
-levels with at most 32768 cells) and, on 3D density levels (128^3 and up),
+levels with at most 4096 cells) and, on 3D density levels (128^3 and up),
 the prolongation folded into the first post-smoothing sweep. p and the
 residual history bitwise equal, on 2D and 3D hierarchies, FP64 and mixed,
 plain cycles and flexible CG, other smoothing counts, and the 256^3 flexible
