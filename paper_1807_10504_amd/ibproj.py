@@ -138,12 +138,22 @@ _lib = None
 
 
 def load(path: str = LIB_PATH):
-    """Load the library (no GPU call is made here)."""
+    """Load the library (no GPU call is made here).
+
+    torch is imported first: its HIP runtime is then the one the library binds
+    to. Loaded the other way round, the process would hold two HIP runtimes
+    (torch asks for its own copy by another file name) and the library's
+    device allocations fail.
+    """
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"HIP library not built: {path} (run python -m paper_1807_10504_amd.build)")
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     vp, i32, f64 = C.c_void_p, C.c_int, C.c_double
     P = C.POINTER

@@ -31,6 +31,20 @@ def test_library_exports_every_declared_symbol():
     assert set(ibproj.EXPORTS) == decl
 
 
+def test_library_shares_torch_hip_runtime():
+    """Loaded through the binding, the library binds to the HIP runtime torch
+    brings: one runtime is mapped in a fresh process (loaded before torch, the
+    library would pull in a second runtime, and its allocations fail)."""
+    import subprocess
+    import sys
+    code = ("from paper_1807_10504_amd import ibproj; ibproj.load(); import torch; "
+            "m = open('/proc/self/maps').read(); "
+            "print(len({l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().splitlines()[-1] == "1"
+
+
 def test_invalid_arguments_rejected_without_device():
     import ctypes as C
     lib = ibproj.load()
