@@ -45,7 +45,7 @@ SWEEP_BYTES_F32 = 24.0
 # (FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000, the factors an elementwise copy of
 # known size reads), recorded with the kernel they were taken on; any other
 # kernel reports null
-TRAFFIC = {"k_rbgs_fused_rho<32,16,512>": (703.8e6, "profiles/rbgs_fused_rho_256cube_hbm_counters.txt")}
+TRAFFIC = {"k_rbgs_fused_rho<32,16,512>": (707.4e6, "profiles/rbgs_fused_rho_256cube_hbm_counters.txt")}
 
 
 def log(msg):
