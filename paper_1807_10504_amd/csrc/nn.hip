@@ -23,7 +23,10 @@
 // pixels of one row and all 32 output channels and, for each tap, multiply a
 // 16 x 32 (pixel x channel) slab of the shifted input by the 32 x 16 weight
 // block of each half of the output channels (two MFMA per tap); the two give
-// identical results. The weight gradient is a GEMM
+// identical results. The 3D first layer, whose input has 3 channels, packs
+// the 27 (ky, kx, channel) products of each kz into one 32-wide operand
+// (PACK): 3 products per output block instead of 27, in both kernels, which
+// again agree bit for bit. The weight gradient is a GEMM
 // over pixels: a workgroup stages 64 pixels of the gradient and the input
 // rows they touch in LDS and accumulates the (tap, co-block, ci-block)
 // 16 x 16 tiles; per-workgroup partials are summed in a fixed order.
