@@ -114,8 +114,8 @@ int ib_interp(ib_ctx* ctx, const double* const u[3], const ib_surface* s, double
  *   2D, along nrm in 3D) with region values H(q) = 1/2 + q/4 +
  *   sin(pi q/2)/(2 pi) at q = -2..2 (Section 3.2); F_d = f (H_c - H_{c-e_d})/h
  *   with f = fs at the foot point on the nearest element (linear/barycentric).
- *   The offset surfaces must stay strictly inside the box (no wrap): else
- *   IB_EGEOM (syncs).
+ *   The offset surfaces must stay more than 4h from every box face (they are
+ *   not wrapped across the periodic seam): else IB_EGEOM (syncs).
  * IB_SPREAD_DELTA: F_d(x_f) = sum_s fs_s ds_s n_s,d delta_h(x_f - X_s)
  *   (eq delta_vec); H may be NULL (then not computed) or is filled as above.
  * F: dim device face arrays, fully overwritten. Deterministic: repeated calls
