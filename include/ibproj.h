@@ -650,8 +650,10 @@ int  ib_nn_get_params(ib_nn* nn, float* params, int count);
  * LDS and marches a 64 x 8 tile along z, staging each input plane once for
  * the three output planes it touches); otherwise, and with
  * IB_NN_CONV_DIRECT, the direct kernel (a wave reads its input slab from
- * memory for every tap). Both add the 27 taps of an output in the same order
- * and give identical results. IB_EINVAL for another kind. */
+ * memory for every tap). Both form every output from the same products in
+ * the same order (the 3-channel first layer, in 3D, with its 27 in-plane
+ * products of each kz packed into one operand in both) and give identical
+ * results. IB_EINVAL for another kind. */
 enum { IB_NN_CONV_AUTO = 0, IB_NN_CONV_DIRECT = 1 };
 int  ib_nn_set_conv(ib_nn* nn, int kind);
 /* p0 (device cells) from b, H (device cells; rho from H as in ib_coefficients),

@@ -722,7 +722,7 @@ struct ib_nn {
     int conv = IB_NN_CONV_AUTO;
 };
 
-// planes per workgroup of the tiled kernel: 16, halved while the grid has
+// planes per workgroup of the tiled kernel: 32, halved while the grid has
 // fewer than 1024 workgroups (at least 4)
 static int conv3_range(const ib_nn* n) {
     const long xy = (long)(n->W / kTX) * (n->H / kTY);
