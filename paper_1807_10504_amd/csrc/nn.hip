@@ -163,6 +163,63 @@ __device__ __forceinline__ bf16x8 pack_weights(const u16* __restrict__ Wl, int k
     return b;
 }
 
+// Epilogue of a 16-pixel block whose products took the weights as the left
+// operand: this lane holds channels c0 .. c0 + 3 (a0) and 16 + c0 .. 16 + c0
+// + 3 (a1) of pixel r, bv their biases. MODE 0: + bias, ReLU, bfloat16;
+// MODE 1: channel 0 + bias in float32 (the lanes with c0 = 0); MODE 2:
+// bfloat16 times (act > 0). Four channels of a pixel are 8 contiguous bytes,
+// stored by the lane itself.
+template <int MODE>
+__device__ __forceinline__ void conv_out(const f32x4& a0, const f32x4& a1, long r, int c0, const float (&bv)[2][4],
+                                         const u16* __restrict__ act, u16* __restrict__ Y,
+                                         float* __restrict__ Yf) {
+    if constexpr (MODE == 1) {
+        if (c0 == 0) Yf[r] = a0[0] + bv[0][0];
+        return;
+    }
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const f32x4& a = cb ? a1 : a0;
+        const int c = 16 * cb + c0;
+        unsigned h[4];
+        if constexpr (MODE == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) h[i] = f2bf(fmaxf(a[i] + bv[cb][i], 0.f));
+        } else {
+            const uint2 av = *reinterpret_cast<const uint2*>(act + r * kC + c);
+            const u16 g[4] = {(u16)(av.x & 0xFFFFu), (u16)(av.x >> 16), (u16)(av.y & 0xFFFFu), (u16)(av.y >> 16)};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) h[i] = bf2f(g[i]) > 0.f ? f2bf(a[i]) : 0u;
+        }
+        uint2 o;
+        o.x = h[0] | (h[1] << 16);
+        o.y = h[2] | (h[3] << 16);
+        *reinterpret_cast<uint2*>(Y + r * kC + c) = o;
+    }
+}
+
+// the biases of channels c0 .. c0 + 3 and 16 + c0 .. 16 + c0 + 3 (MODE 1:
+// channel 0's only; MODE 2: none)
+template <int MODE>
+__device__ __forceinline__ void conv_bias(const float* __restrict__ bias, int c0, float (&bv)[2][4]) {
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bv[cb][i] = 0.f;
+    if constexpr (MODE == 1) {
+        bv[0][0] = bias[0];
+    } else if constexpr (MODE == 0) {
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            const float4 q = *reinterpret_cast<const float4*>(bias + 16 * cb + c0);
+            bv[cb][0] = q.x;
+            bv[cb][1] = q.y;
+            bv[cb][2] = q.z;
+            bv[cb][3] = q.w;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // convolution on the matrix cores
 // MODE 0: + bias, ReLU, bfloat16 out; MODE 1: + bias, float32 out of channel 0;
@@ -174,7 +231,6 @@ __global__ __launch_bounds__(kBlock) void k_nn_conv(const u16* __restrict__ X, c
                                                     float* __restrict__ Yf, int D, int H, int W) {
     static_assert(!PACK || (DIM == 3 && MODE == 0), "the packed first layer is 3D, bias + ReLU");
     constexpr int TAPS = DIM == 3 ? 27 : 9;
-    __shared__ u16 tile[4][16][kC];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int y = blockIdx.y, z = blockIdx.z;
     const int x0 = blockIdx.x * 64 + wave * 16;
@@ -194,8 +250,8 @@ __global__ __launch_bounds__(kBlock) void k_nn_conv(const u16* __restrict__ X, c
                 const int yy = wrap_near(y + ky - 1, H), xx = wrap_near(x0 + m + kx - 1, W);
                 a[e] = __builtin_bit_cast(__bf16, X[(((long)zz * H + yy) * W + xx) * kC + ci]);
             }
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, pack_weights(Wl, kz, 0, m, kg), acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, pack_weights(Wl, kz, 1, m, kg), acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pack_weights(Wl, kz, 0, m, kg), a, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pack_weights(Wl, kz, 1, m, kg), a, acc1, 0, 0, 0);
         }
     }
 #pragma unroll
@@ -207,37 +263,14 @@ __global__ __launch_bounds__(kBlock) void k_nn_conv(const u16* __restrict__ X, c
         bf16x8 a = *reinterpret_cast<const bf16x8*>(X + (((long)zz * H + yy) * W + xx) * kC + kg * 8);
         bf16x8 b0 = *reinterpret_cast<const bf16x8*>(Wl + ((m)*TAPS + tap) * kC + kg * 8);
         bf16x8 b1 = *reinterpret_cast<const bf16x8*>(Wl + ((16 + m) * TAPS + tap) * kC + kg * 8);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b0, a, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b1, a, acc1, 0, 0, 0);
     }
-    // accumulator element i of lane (m, kg): pixel 4 kg + i, channel m (acc0) / 16 + m (acc1)
-    if (MODE == 1) {
-        if (m == 0) {
-            float b0v = bias[0];
-            for (int i = 0; i < 4; ++i) Yf[row0 + 4 * kg + i] = acc0[i] + b0v;
-        }
-        return;
-    }
-    for (int i = 0; i < 4; ++i) {
-        int px = 4 * kg + i;
-        float v0 = acc0[i], v1 = acc1[i];
-        if (MODE == 0) {
-            v0 = fmaxf(v0 + bias[m], 0.f);
-            v1 = fmaxf(v1 + bias[16 + m], 0.f);
-            tile[wave][px][m] = f2bf(v0);
-            tile[wave][px][16 + m] = f2bf(v1);
-        } else {
-            const u16* ar = act + (row0 + px) * kC;
-            u16 h0 = f2bf(v0), h1 = f2bf(v1);
-            tile[wave][px][m] = bf2f(ar[m]) > 0.f ? h0 : (u16)0;
-            tile[wave][px][16 + m] = bf2f(ar[16 + m]) > 0.f ? h1 : (u16)0;
-        }
-    }
-    __syncthreads();
-    // lane l stores 8 channels of pixel l / 4
-    const int px = lane >> 2, ch = (lane & 3) * 8;
-    uint4 v = *reinterpret_cast<const uint4*>(&tile[wave][px][ch]);
-    *reinterpret_cast<uint4*>(Y + (row0 + px) * kC + ch) = v;
+    // the weights are the left operand: accumulator element i of lane (m, kg)
+    // is channel 4 kg + i (acc0) / 16 + 4 kg + i (acc1) of pixel m
+    float bv[2][4];
+    conv_bias<MODE>(bias, 4 * kg, bv);
+    conv_out<MODE>(acc0, acc1, row0 + m, 4 * kg, bv, act, Y, Yf);
 }
 
 // ---------------------------------------------------------------------------
@@ -307,7 +340,7 @@ __device__ __forceinline__ void conv3_plane(const bf16x8* __restrict__ P, const 
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
                         acc[S][j][cb] =
-                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(c.a[j], c.b[kz][cb], acc[S][j][cb], 0, 0, 0);
+                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(c.b[kz][cb], c.a[j], acc[S][j][cb], 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -330,7 +363,7 @@ __device__ __forceinline__ void conv3_plane(const bf16x8* __restrict__ P, const 
                     const bf16x8 b = Ws[(tap * 2 + cb) * 64 + lane];
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
-                        acc[S][j][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j], b, acc[S][j][cb], 0, 0, 0);
+                        acc[S][j][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, a[j], acc[S][j][cb], 0, 0, 0);
                 }
             }
         }
@@ -365,57 +398,21 @@ __device__ __forceinline__ void conv3_plane_pack(const bf16x8* __restrict__ P, c
             const bf16x8 b = Ws[(kz * 2 + cb) * 64 + lane];
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                acc[S][j][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j], b, acc[S][j][cb], 0, 0, 0);
+                acc[S][j][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, a[j], acc[S][j][cb], 0, 0, 0);
         }
     }
 }
 
-// bias / ReLU (MODE 0), channel 0 in float32 (MODE 1) or the ReLU mask of
-// act (MODE 2) for the 64 pixels of one output row starting at pixel row0
+// the 64 pixels of one output row starting at pixel row0 (conv_out per
+// block of 16; the biases are read here, where few registers are live)
 template <int MODE>
 __device__ __forceinline__ void conv3_store(const f32x4 (&a)[4][2], long row0, const float* __restrict__ bias,
                                             const u16* __restrict__ act, u16* __restrict__ Y,
-                                            float* __restrict__ Yf, u16 (*ep)[kC], int m, int kg, int lane) {
+                                            float* __restrict__ Yf, int m, int kg) {
+    float bv[2][4];
+    conv_bias<MODE>(bias, 4 * kg, bv);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const long r = row0 + 16 * j;
-        if (MODE == 1) {
-            if (m == 0) {
-                const float b0 = bias[0];
-                float4 o;
-                o.x = a[j][0][0] + b0;
-                o.y = a[j][0][1] + b0;
-                o.z = a[j][0][2] + b0;
-                o.w = a[j][0][3] + b0;
-                *reinterpret_cast<float4*>(Yf + r + 4 * kg) = o;
-            }
-            continue;
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int px = 4 * kg + i;
-            float v0 = a[j][0][i], v1 = a[j][1][i];
-            if (MODE == 0) {
-                ep[px][m] = f2bf(fmaxf(v0 + bias[m], 0.f));
-                ep[px][16 + m] = f2bf(fmaxf(v1 + bias[16 + m], 0.f));
-            } else {
-                const u16* ar = act + (r + px) * kC;
-                const u16 h0 = f2bf(v0), h1 = f2bf(v1);
-                ep[px][m] = bf2f(ar[m]) > 0.f ? h0 : (u16)0;
-                ep[px][16 + m] = bf2f(ar[16 + m]) > 0.f ? h1 : (u16)0;
-            }
-        }
-        // the tile is private to the wave, whose LDS accesses complete in order
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int px = lane >> 2, ch = (lane & 3) * 8;
-        const uint4 v = *reinterpret_cast<const uint4*>(&ep[px][ch]);
-        *reinterpret_cast<uint4*>(Y + (r + px) * kC + ch) = v;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
+    for (int j = 0; j < 4; ++j) conv_out<MODE>(a[j][0], a[j][1], row0 + 16 * j + m, 4 * kg, bv, act, Y, Yf);
 }
 
 template <int MODE, bool PACK = false>
@@ -427,7 +424,6 @@ __global__ __launch_bounds__(kTThreads) void k_nn_conv3_tiled(const u16* __restr
                                                               int D, int H, int W, int ZR) {
     __shared__ bf16x8 Ws[kTW];
     __shared__ bf16x8 Ps[2][kTPlane];
-    __shared__ u16 Ep[kTThreads / 64][16][kC];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int m = lane & 15, kg = lane >> 4;
     const int ntx = W / kTX, nty = H / kTY, nzr = (D + ZR - 1) / ZR;
@@ -519,8 +515,7 @@ __global__ __launch_bounds__(kTThreads) void k_nn_conv3_tiled(const u16* __restr
         }
         // input plane t completes output plane t - 2 (set (R + 1) mod 3)
         if (t >= 2)
-            conv3_store<MODE>(acc[(R + 1) % 3], rowz + (long)(t - 2) * HW, bias, act, Y, Yf, Ep[wave], m, kg,
-                              lane);
+            conv3_store<MODE>(acc[(R + 1) % 3], rowz + (long)(t - 2) * HW, bias, act, Y, Yf, m, kg);
         if (more) commit(t + 1);
         __syncthreads();
     };
