@@ -26,7 +26,8 @@
 // identical results. The 3D first layer, whose input has 3 channels, packs
 // the 27 (ky, kx, channel) products of each kz into one 32-wide operand
 // (PACK): 3 products per output block instead of 27, in both kernels, which
-// again agree bit for bit. The weight gradient is a GEMM
+// again agree bit for bit; it reads the input in 8 channels (16 bytes a
+// pixel) instead of 32. The weight gradient is a GEMM
 // over pixels: a workgroup stages 64 pixels of the gradient and the input
 // rows they touch in LDS and accumulates the (tap, co-block, ci-block)
 // 16 x 16 tiles; per-workgroup partials are summed in a fixed order.
@@ -109,17 +110,19 @@ __global__ void k_nn_scales(const double* __restrict__ part, int nb, long N, dou
     }
 }
 
-// one lane per 16-byte chunk of a pixel's 32 bfloat16 channels (a wave
-// writes 16 whole pixels, 1 KB, with one store): chunk 0 holds channels
-// 0 .. 2, the rest are zero padding
+// one lane per 16-byte chunk of a pixel's NCH chunks (NCH = 4: the 32
+// bfloat16 channels of the layer layout, a wave writing 16 whole pixels, 1 KB,
+// with one store; NCH = 1: the 8-channel form the packed 3D first layer
+// reads): chunk 0 holds channels 0 .. 2, the rest are zero padding
+template <int NCH>
 __global__ void k_nn_input(const double* __restrict__ b, const double* __restrict__ H,
                            const double* __restrict__ pp, long N, double h2, double rin, double rout,
                            const double* __restrict__ scale, u16* __restrict__ X) {
     const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= 4 * N) return;
-    const long c = q >> 2;
+    if (q >= NCH * N) return;
+    const long c = q / NCH;
     uint4 v = {0u, 0u, 0u, 0u};
-    if ((q & 3) == 0) {
+    if (q % NCH == 0) {
         float v0 = (float)(b[c] * h2 / scale[0]);
         float v1 = (float)((1.0 / (rout + (rin - rout) * H[c])) / scale[2]);
         float v2 = (float)((pp ? pp[c] : 0.0) / scale[1]);
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_conv(const u16* __restrict__ X, c
                 int ky, kx, ci;
                 pack_tap(kg * 8 + e, ky, kx, ci);
                 const int yy = wrap_near(y + ky - 1, H), xx = wrap_near(x0 + m + kx - 1, W);
-                a[e] = __builtin_bit_cast(__bf16, X[(((long)zz * H + yy) * W + xx) * kC + ci]);
+                a[e] = __builtin_bit_cast(__bf16, X[(((long)zz * H + yy) * W + xx) * 8 + ci]);
             }
             acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pack_weights(Wl, kz, 0, m, kg), a, acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pack_weights(Wl, kz, 1, m, kg), a, acc1, 0, 0, 0);
@@ -468,6 +471,9 @@ __global__ __launch_bounds__(kTThreads) void k_nn_conv3_tiled(const u16* __restr
     // the packed first layer reads chunk 0, channels 0 .. 7, only); slots
     // past the plane re-read slot 0 and are not stored
     constexpr int NCH = PACK ? 1 : 4, NSLOT = kTRows * kTPx * NCH;
+    // 16-bit elements per input pixel: the packed first layer reads the
+    // 8-channel form of the input
+    constexpr int XS = PACK ? 8 : kC;
     constexpr int NLD = (NSLOT + kTThreads - 1) / kTThreads;
     int goff[NLD], loff[NLD];
 #pragma unroll
@@ -476,12 +482,12 @@ __global__ __launch_bounds__(kTThreads) void k_nn_conv3_tiled(const u16* __restr
         const bool v = q < NSLOT;
         if (!v) q = 0;
         const int c = q % NCH, px = (q / NCH) % kTPx, r = (q / NCH) / kTPx;
-        goff[s] = (wrap_near(y0 - 1 + r, H) * W + wrap_near(x0 - 1 + px, W)) * kC + c * 8;
+        goff[s] = (wrap_near(y0 - 1 + r, H) * W + wrap_near(x0 - 1 + px, W)) * XS + c * 8;
         loff[s] = v ? (r * 4 + c) * kTPxs + px : -1;
     }
     bf16x8 pre[NLD];
     auto fetch = [&](int t) {
-        const u16* base = X + (long)wrap_near(z0 - 1 + t, D) * HW * kC;
+        const u16* base = X + (long)wrap_near(z0 - 1 + t, D) * HW * XS;
 #pragma unroll
         for (int s = 0; s < NLD; ++s) pre[s] = *reinterpret_cast<const bf16x8*>(base + goff[s]);
     };
@@ -700,6 +706,7 @@ struct ib_nn {
     double h = 0.0;
     long N = 0;
     u16* act[kLayers] = {};   // layer inputs (act[0] = normalised input)
+    u16* act0c = nullptr;     // 3D: the normalised input in 8 channels (the packed first layer)
     float* yf = nullptr;      // network output
     u16* g[2] = {};           // gradient ping-pong
     u16* Wl = nullptr;        // kLayers * wsize(taps)
@@ -752,14 +759,20 @@ static void nn_conv(const ib_nn* n, const u16* X, const u16* Wl, const float* bi
                            n->W);
 }
 
+// train: the 32-channel input is written as well (the first layer's weight
+// gradient reads it; in 3D the forward reads the 8-channel form only)
 static int nn_forward(ib_nn* n, const double* b, const double* H, const double* pp, double rin,
-                      double rout, hipStream_t st) {
+                      double rout, bool train, hipStream_t st) {
     const int nb = 1024;
     double h2 = n->h * n->h;
     hipLaunchKernelGGL(k_nn_stats, dim3(nb), dim3(kBlock), 0, st, b, H, pp, n->N, h2, rin, rout, n->red);
     hipLaunchKernelGGL(k_nn_scales, dim3(1), dim3(kBlock), 0, st, n->red, nb, n->N, n->scale);
-    hipLaunchKernelGGL(k_nn_input, dim3(grid_for(4 * n->N)), dim3(kBlock), 0, st, b, H, pp, n->N, h2, rin,
-                       rout, n->scale, n->act[0]);
+    if (n->dim == 3)
+        hipLaunchKernelGGL(k_nn_input<1>, dim3(grid_for(n->N)), dim3(kBlock), 0, st, b, H, pp, n->N, h2, rin,
+                           rout, n->scale, n->act0c);
+    if (n->dim == 2 || train)
+        hipLaunchKernelGGL(k_nn_input<4>, dim3(grid_for(4 * n->N)), dim3(kBlock), 0, st, b, H, pp, n->N, h2,
+                           rin, rout, n->scale, n->act[0]);
     const long ws = wsize(n->taps);
     for (int l = 0; l < kLayers; ++l) {
         const u16* Wl = n->Wl + (long)l * ws;
@@ -767,7 +780,7 @@ static int nn_forward(ib_nn* n, const double* b, const double* H, const double* 
         if (l == kLayers - 1)
             nn_conv<1>(n, n->act[l], Wl, bias, nullptr, nullptr, n->yf, st);
         else if (l == 0 && n->dim == 3)
-            nn_conv<0, true>(n, n->act[l], Wl, bias, nullptr, n->act[l + 1], nullptr, st);
+            nn_conv<0, true>(n, n->act0c, Wl, bias, nullptr, n->act[l + 1], nullptr, st);
         else
             nn_conv<0>(n, n->act[l], Wl, bias, nullptr, n->act[l + 1], nullptr, st);
     }
@@ -779,7 +792,7 @@ static int nn_forward(ib_nn* n, const double* b, const double* H, const double* 
 // summed into *loss (syncs)
 static int nn_backward(ib_nn* n, const double* b, const double* H, const double* pp, const double* p,
                        double rin, double rout, double* loss, hipStream_t st) {
-    IB_TRY(nn_forward(n, b, H, pp, rin, rout, st));
+    IB_TRY(nn_forward(n, b, H, pp, rin, rout, true, st));
     const int nb = 1024;
     hipLaunchKernelGGL(k_nn_loss, dim3(nb), dim3(kBlock), 0, st, n->yf, p, pp, n->scale, n->N, n->g[0],
                        n->red);
@@ -811,7 +824,7 @@ static int nn_backward(ib_nn* n, const double* b, const double* H, const double*
 static void nn_free(ib_nn* n) {
     if (!n) return;
     for (int l = 0; l < kLayers; ++l) (void)hipFree(n->act[l]);
-    void* ptrs[] = {n->yf, n->g[0], n->g[1], n->Wl, n->Wt, n->bias, n->master, n->mom,
+    void* ptrs[] = {n->act0c, n->yf, n->g[0], n->g[1], n->Wl, n->Wt, n->bias, n->master, n->mom,
                     n->vel, n->grad, n->part, n->red, n->scale};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -845,6 +858,7 @@ extern "C" int ib_nn_create(const ib_grid* g, ib_nn** out) {
         if (ok && hipMalloc(p, bytes) != hipSuccess) ok = false;
     };
     for (int l = 0; l < kLayers; ++l) alloc((void**)&n->act[l], n->N * kC * sizeof(u16));
+    if (n->dim == 3) alloc((void**)&n->act0c, n->N * 8 * sizeof(u16));
     alloc((void**)&n->yf, n->N * sizeof(float));
     alloc((void**)&n->g[0], n->N * kC * sizeof(u16));
     alloc((void**)&n->g[1], n->N * kC * sizeof(u16));
@@ -943,7 +957,7 @@ extern "C" int ib_nn_predict(ib_nn* n, const double* b, const double* H, const d
                              double rho_in, double rho_out, double* p0, void* stream) {
     IB_CHECK(n && b && H && p0, IB_EINVAL, "ib_nn_predict: null argument");
     hipStream_t st = (hipStream_t)stream;
-    IB_TRY(nn_forward(n, b, H, p_prev, rho_in, rho_out, st));
+    IB_TRY(nn_forward(n, b, H, p_prev, rho_in, rho_out, false, st));
     hipLaunchKernelGGL(k_nn_guess, dim3(grid_for(n->N)), dim3(kBlock), 0, st, n->yf, p_prev, n->scale,
                        n->N, p0);
     IB_HIP(hipGetLastError());
