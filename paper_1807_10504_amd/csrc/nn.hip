@@ -223,6 +223,21 @@ __device__ __forceinline__ void conv_bias(const float* __restrict__ bias, int c0
     }
 }
 
+// The last layer has one output channel: its weight fragment for in-plane
+// tap i = 3 ky + kx carries, as rows 0, 1, 2 of the left operand, the
+// weights of taps (kz, ky, kx) for kz = 0, 1, 2 (rows 3 .. 15 zero). One
+// product with an input plane then gives that plane's contributions to the
+// three output planes it feeds, in rows 0 .. 2 (lane (pixel, 0), elements
+// 0 .. 2). Each output is the sum, in order kz = 0, 1, 2, of its three
+// in-plane chains, plus the bias.
+__device__ __forceinline__ bf16x8 last_weights(const u16* __restrict__ Wl, int i, int mm, int kk) {
+    if (mm < 3) return *reinterpret_cast<const bf16x8*>(Wl + (9 * mm + i) * kC + kk * 8);
+    bf16x8 z;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) z[e] = __builtin_bit_cast(__bf16, (u16)0);
+    return z;
+}
+
 // ---------------------------------------------------------------------------
 // convolution on the matrix cores
 // MODE 0: + bias, ReLU, bfloat16 out; MODE 1: + bias, float32 out of channel 0;
@@ -241,6 +256,26 @@ __global__ __launch_bounds__(kBlock) void k_nn_conv(const u16* __restrict__ X, c
     // first pixel of this wave's 16 (row y of plane z)
     const long row0 = ((long)z * H + y) * W + x0;
     f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (MODE == 1 && DIM == 3) {
+        // one output channel: per input plane z + kz - 1 the chain over the
+        // nine in-plane taps, row kz of the packed product (last_weights)
+        float run = 0.f;
+#pragma unroll
+        for (int kz = 0; kz < 3; ++kz) {
+            const int zz = wrap_near(z + kz - 1, D);
+            f32x4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const int ky = i / 3, kx = i % 3;
+                const int yy = wrap_near(y + ky - 1, H), xx = wrap_near(x0 + m + kx - 1, W);
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(X + (((long)zz * H + yy) * W + xx) * kC + kg * 8);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(last_weights(Wl, i, m, kg), a, c, 0, 0, 0);
+            }
+            run = kz == 0 ? c[0] : run + c[kz];
+        }
+        if (kg == 0) Yf[row0 + m] = run + bias[0];
+        return;
+    }
     if constexpr (PACK) {
 #pragma unroll
         for (int kz = 0; kz < 3; ++kz) {
@@ -447,6 +482,9 @@ __global__ __launch_bounds__(kTThreads) void k_nn_conv3_tiled(const u16* __restr
             const int l = tid & 63, tc = tid >> 6;
             Ws[tid] = pack_weights(Wl, tc >> 1, tc & 1, l & 15, l >> 4);
         }
+    } else if constexpr (MODE == 1) {
+        // last layer: fragment (i, lane) of last_weights
+        for (int q = tid; q < 9 * 64; q += kTThreads) Ws[q] = last_weights(Wl, q >> 6, q & 15, (q & 63) >> 4);
     } else {
 #pragma unroll
         for (int s = 0; s < kTWLoads; ++s) {
@@ -502,6 +540,8 @@ __global__ __launch_bounds__(kTThreads) void k_nn_conv3_tiled(const u16* __restr
     __syncthreads();
 
     f32x4 acc[3][4][2];
+    // last layer: running sums of output planes t, t - 1, t - 2 (sets as acc)
+    float run[3][4];
     // output row of this wave; pixel index of (z0 + u, y0 + wave, x0) is rowz + u H W
     const long rowz = ((long)z0 * H + y0 + wave) * W + x0;
     auto step = [&](auto rc, int t) {
@@ -509,7 +549,33 @@ __global__ __launch_bounds__(kTThreads) void k_nn_conv3_tiled(const u16* __restr
         const bool more = t + 1 < nt;
         if (more) fetch(t + 1);
         const int mask = (t < nz ? 1 : 0) | (t >= 1 && t <= nz ? 2 : 0) | (t >= 2 ? 4 : 0);
-        if constexpr (PACK) {
+        if constexpr (MODE == 1) {
+            f32x4 c[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) c[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            const bf16x8* P = Ps[t & 1];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const int ky = i / 3, kx = i % 3;
+                const bf16x8 b = Ws[i * 64 + lane];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    c[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        b, P[((wave + ky) * 4 + kg) * kTPxs + 16 * j + m + kx], c[j], 0, 0, 0);
+            }
+            // this plane is input plane kz of the output plane in set (R - kz) mod 3
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (mask & 1) run[R][j] = c[j][0];
+                if (mask & 2) run[(R + 2) % 3][j] += c[j][1];
+                if (mask & 4) run[(R + 1) % 3][j] += c[j][2];
+            }
+            if (t >= 2 && kg == 0) {
+                const float b0 = bias[0];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) Yf[rowz + (long)(t - 2) * HW + 16 * j + m] = run[(R + 1) % 3][j] + b0;
+            }
+        } else if constexpr (PACK) {
             if (mask == 7)
                 conv3_plane_pack<R, true>(Ps[t & 1], Ws, acc, wave, m, lane, poff, 7);
             else
@@ -520,7 +586,7 @@ __global__ __launch_bounds__(kTThreads) void k_nn_conv3_tiled(const u16* __restr
             conv3_plane<MODE, R, false>(Ps[t & 1], Ws, acc, wave, m, kg, lane, mask);
         }
         // input plane t completes output plane t - 2 (set (R + 1) mod 3)
-        if (t >= 2)
+        if (MODE != 1 && t >= 2)
             conv3_store<MODE>(acc[(R + 1) % 3], rowz + (long)(t - 2) * HW, bias, act, Y, Yf, m, kg);
         if (more) commit(t + 1);
         __syncthreads();
