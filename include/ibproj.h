@@ -651,8 +651,9 @@ int  ib_nn_get_params(ib_nn* nn, float* params, int count);
  * the three output planes it touches); otherwise, and with
  * IB_NN_CONV_DIRECT, the direct kernel (a wave reads its input slab from
  * memory for every tap). Both form every output from the same products in
- * the same order (the 3-channel first layer, in 3D, with its 27 in-plane
- * products of each kz packed into one operand in both) and give identical
+ * the same order (in 3D the 3-channel first layer with its 27 in-plane
+ * products of each kz packed into one operand, and the 1-channel last layer
+ * with its three kz taps as rows of one product, in both) and give identical
  * results. IB_EINVAL for another kind. */
 enum { IB_NN_CONV_AUTO = 0, IB_NN_CONV_DIRECT = 1 };
 int  ib_nn_set_conv(ib_nn* nn, int kind);

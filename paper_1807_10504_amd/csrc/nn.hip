@@ -320,7 +320,9 @@ __global__ __launch_bounds__(kBlock) void k_nn_conv(const u16* __restrict__ X, c
 // per (ky, kx). Wave w owns output row w of the tile: 4 blocks of 16 pixels x
 // 2 blocks of 16 output channels, for 3 output planes in flight. Every
 // accumulator receives its 27 taps in increasing tap order with the same
-// operands as k_nn_conv, so the two kernels give identical results.
+// operands as k_nn_conv (the packed first layer its three kz products; the
+// one-channel last layer its three in-plane chains, added in kz order), so
+// the two kernels give identical results.
 constexpr int kTX = 64, kTY = 8, kTThreads = 512;
 constexpr int kTRows = kTY + 2, kTPx = kTX + 2;
 constexpr int kTPxs = 68;                         // LDS pixel stride (bank spread)
