@@ -792,12 +792,12 @@ struct ib_nn {
     int conv = IB_NN_CONV_AUTO;
 };
 
-// planes per workgroup of the tiled kernel: 32, halved while the grid has
-// fewer than 1024 workgroups (at least 4)
+// planes per workgroup of the tiled kernel: 64 (two planes of halo per 64),
+// halved while the grid has fewer than 512 workgroups (two per CU; at least 4)
 static int conv3_range(const ib_nn* n) {
     const long xy = (long)(n->W / kTX) * (n->H / kTY);
-    int zr = 32;
-    while (zr > 4 && xy * ((n->D + zr - 1) / zr) < 1024) zr /= 2;
+    int zr = 64;
+    while (zr > 4 && xy * ((n->D + zr - 1) / zr) < 512) zr /= 2;
     return zr;
 }
 
