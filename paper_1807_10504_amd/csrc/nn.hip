@@ -793,7 +793,8 @@ struct ib_nn {
 };
 
 // planes per workgroup of the tiled kernel: 64 (two planes of halo per 64),
-// halved while the grid has fewer than 512 workgroups (two per CU; at least 4)
+// halved while the grid has fewer than 512 workgroups (two rounds of one
+// workgroup per CU on 256 CUs; at least 4)
 static int conv3_range(const ib_nn* n) {
     const long xy = (long)(n->W / kTX) * (n->H / kTY);
     int zr = 64;
