@@ -337,7 +337,6 @@ struct Conv3Ops {
     bf16x8 b[3][2];
 };
 
-template <int NCB>
 __device__ __forceinline__ void conv3_load(Conv3Ops& o, const bf16x8* __restrict__ P,
                                            const bf16x8* __restrict__ Ws, int i, int w, int m, int kg,
                                            int lane) {
@@ -347,7 +346,7 @@ __device__ __forceinline__ void conv3_load(Conv3Ops& o, const bf16x8* __restrict
 #pragma unroll
     for (int kz = 0; kz < 3; ++kz)
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) o.b[kz][cb] = Ws[((9 * kz + i) * 2 + cb) * 64 + lane];
+        for (int cb = 0; cb < 2; ++cb) o.b[kz][cb] = Ws[((9 * kz + i) * 2 + cb) * 64 + lane];
 }
 
 // bit kz of mask: the output plane this input plane feeds as tap plane kz
@@ -357,7 +356,7 @@ __device__ __forceinline__ void conv3_load(Conv3Ops& o, const bf16x8* __restrict
 template <int MODE, int R, bool FULL>
 __device__ __forceinline__ void conv3_plane(const bf16x8* __restrict__ P, const bf16x8* __restrict__ Ws,
                                             f32x4 (&acc)[3][4][2], int w, int m, int kg, int lane, int mask) {
-    constexpr int NCB = MODE == 1 ? 1 : 2;  // MODE 1 stores channel 0 only
+    static_assert(MODE != 1, "the one-channel last layer has its own plane step");
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -366,17 +365,17 @@ __device__ __forceinline__ void conv3_plane(const bf16x8* __restrict__ P, const 
     // no registers for a second operand set)
     if (FULL && MODE != 2) {
         Conv3Ops o[2];
-        conv3_load<NCB>(o[0], P, Ws, 0, w, m, kg, lane);
+        conv3_load(o[0], P, Ws, 0, w, m, kg, lane);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            if (i + 1 < 9) conv3_load<NCB>(o[(i + 1) & 1], P, Ws, i + 1, w, m, kg, lane);
+            if (i + 1 < 9) conv3_load(o[(i + 1) & 1], P, Ws, i + 1, w, m, kg, lane);
             __builtin_amdgcn_sched_barrier(0);
             const Conv3Ops& c = o[i & 1];
 #pragma unroll
             for (int kz = 0; kz < 3; ++kz) {
                 const int S = (R - kz + 3) % 3;
 #pragma unroll
-                for (int cb = 0; cb < NCB; ++cb)
+                for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
                         acc[S][j][cb] =
@@ -399,7 +398,7 @@ __device__ __forceinline__ void conv3_plane(const bf16x8* __restrict__ P, const 
                 const int S = (R - kz + 3) % 3, tap = 9 * kz + 3 * ky + kx;
                 if (!((mask >> kz) & 1)) continue;
 #pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) {
+                for (int cb = 0; cb < 2; ++cb) {
                     const bf16x8 b = Ws[(tap * 2 + cb) * 64 + lane];
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
